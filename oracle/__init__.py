@@ -1,0 +1,251 @@
+"""FP64 CPU oracle for the Barnes-Hut hot path (arXiv:2203.08966).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path.  It shares no code
+with the GPU library; the heavy loops live in ``oracle.c`` (plain C, FP64,
+built with ``build()``), the glue here is plain numpy.
+
+Pins (see ``tests/test_oracle_*.py``) tie every function to something other
+than itself: the paper's worked Morton example and its 21-point quadtree
+figure, closed forms (two-body force, two-mass quadrupole field, Plummer
+energies, circular orbits), brute force on tiny inputs, invariants
+(momentum conservation, coverage, time reversal) and theta = 0 equal to
+direct summation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+_P = np.ctypeslib.ndpointer
+_f64 = _P(np.float64, flags="C_CONTIGUOUS")
+_i64 = _P(np.int64, flags="C_CONTIGUOUS")
+_i32 = _P(np.int32, flags="C_CONTIGUOUS")
+_u64 = _P(np.uint64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (gcc, FP64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = C.CDLL(_LIB)
+    lib.orc_num_threads.restype = C.c_int
+    lib.orc_direct.argtypes = [C.c_int64, _f64, _f64, C.c_double, C.c_int64, _i64, _f64, _f64]
+    lib.orc_root_cube.argtypes = [C.c_int64, _f64, _f64, C.POINTER(C.c_double)]
+    lib.orc_interleave.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
+    lib.orc_interleave.restype = C.c_uint64
+    lib.orc_keys.argtypes = [C.c_int64, _f64, _f64, C.c_double, _u64]
+    lib.orc_sort.argtypes = [C.c_int64, _u64, _i64]
+    opt_u64 = C.c_void_p
+    lib.orc_build.argtypes = [C.c_int64, _u64, C.c_int] + [opt_u64] * 7
+    lib.orc_build.restype = C.c_int64
+    lib.orc_moments.argtypes = [C.c_int64, _i32, _u64, _i32, _i32, _f64, _f64, _f64,
+                                C.c_double, _f64, _f64, _f64]
+    lib.orc_walk.argtypes = [C.c_int64, _i32, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
+                             C.c_double, C.c_double, C.c_double, C.c_int, C.c_int64, _i64,
+                             _f64, _f64, _i64, _i64, _i64, _i32]
+    _lib = lib
+    return lib
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def _pos64(pos):
+    return np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
+
+
+def direct(pos, mass, eps: float, targets=None):
+    """FP64 direct sum: (acc[t], phi[t]) for each body index in ``targets``
+    (all bodies by default), original order."""
+    lib = _load()
+    p = _pos64(pos)
+    m = np.ascontiguousarray(mass, dtype=np.float64)
+    n = m.shape[0]
+    t = np.arange(n, dtype=np.int64) if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    acc = np.zeros((t.shape[0], 3))
+    phi = np.zeros(t.shape[0])
+    lib.orc_direct(n, p.ravel(), m, float(eps), t.shape[0], t, acc.ravel(), phi)
+    return acc, phi
+
+
+def root_cube(pos):
+    lib = _load()
+    p = _pos64(pos)
+    lo = np.zeros(3)
+    L = C.c_double()
+    lib.orc_root_cube(p.shape[0], p.ravel(), lo, C.byref(L))
+    return lo, L.value
+
+
+def interleave(qx: int, qy: int, qz: int) -> int:
+    return int(_load().orc_interleave(qx, qy, qz))
+
+
+def keys(pos, lo, L):
+    lib = _load()
+    p = _pos64(pos)
+    k = np.zeros(p.shape[0], dtype=np.uint64)
+    lib.orc_keys(p.shape[0], p.ravel(), np.ascontiguousarray(lo, dtype=np.float64), float(L), k)
+    return k
+
+
+def sort(k):
+    lib = _load()
+    k = np.ascontiguousarray(k, dtype=np.uint64)
+    perm = np.zeros(k.shape[0], dtype=np.int64)
+    lib.orc_sort(k.shape[0], k, perm)
+    return perm
+
+
+def build_tree(sorted_keys, leaf_size: int) -> dict:
+    """Pre-order node arrays of the canonical octree over key-sorted bodies."""
+    lib = _load()
+    k = np.ascontiguousarray(sorted_keys, dtype=np.uint64)
+    n = k.shape[0]
+    m = lib.orc_build(n, k, int(leaf_size), None, None, None, None, None, None, None)
+    t = {
+        "hkey": np.zeros(m, dtype=np.uint64),
+        "level": np.zeros(m, dtype=np.int32),
+        "begin": np.zeros(m, dtype=np.int32),
+        "count": np.zeros(m, dtype=np.int32),
+        "next": np.zeros(m, dtype=np.int32),
+        "parent": np.zeros(m, dtype=np.int32),
+        "cmask": np.zeros(m, dtype=np.int32),
+    }
+    m2 = lib.orc_build(n, k, int(leaf_size), *(t[f].ctypes.data for f in
+                       ("hkey", "level", "begin", "count", "next", "parent", "cmask")))
+    assert m2 == m
+    return t
+
+
+def moments(tree: dict, spos, smass, lo, L):
+    lib = _load()
+    m = tree["hkey"].shape[0]
+    p = _pos64(spos)
+    ms = np.ascontiguousarray(smass, dtype=np.float64)
+    M = np.zeros(m)
+    com = np.zeros((m, 3))
+    Q = np.zeros((m, 6))
+    lib.orc_moments(m, tree["level"], tree["hkey"], tree["begin"], tree["count"], p.ravel(), ms,
+                    np.ascontiguousarray(lo, dtype=np.float64), float(L), M, com.ravel(), Q.ravel())
+    return M, com, Q
+
+
+class WalkResult(tuple):
+    """(acc, phi, npp, npc, ncov, flag) of a tree walk; fields by name too."""
+    _fields = ("acc", "phi", "npp", "npc", "ncov", "flag")
+
+    def __new__(cls, *vals):
+        return super().__new__(cls, vals)
+
+    def __getattr__(self, name):
+        try:
+            return self[self._fields.index(name)]
+        except ValueError:
+            raise AttributeError(name) from None
+
+
+def walk(tree, mom, spos, smass, L, theta, eps, order=2, targets=None):
+    """Per-body tree walk over sorted bodies; ``targets`` are sorted ranks."""
+    lib = _load()
+    M, com, Q = mom
+    p = _pos64(spos)
+    ms = np.ascontiguousarray(smass, dtype=np.float64)
+    n = ms.shape[0]
+    t = np.arange(n, dtype=np.int64) if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = t.shape[0]
+    acc = np.zeros((nt, 3))
+    phi = np.zeros(nt)
+    npp = np.zeros(nt, dtype=np.int64)
+    npc = np.zeros(nt, dtype=np.int64)
+    ncov = np.zeros(nt, dtype=np.int64)
+    flag = np.zeros(nt, dtype=np.int32)
+    lib.orc_walk(M.shape[0], tree["level"], tree["begin"], tree["count"], tree["next"],
+                 M, com.ravel(), Q.ravel(), p.ravel(), ms, float(L), float(theta), float(eps),
+                 int(order), nt, t, acc.ravel(), phi, npp, npc, ncov, flag)
+    return WalkResult(acc, phi, npp, npc, ncov, flag)
+
+
+def build_all(pos, mass, leaf_size: int):
+    """Root cube, keys, stable sort, tree and moments for bodies in any order."""
+    p = _pos64(pos)
+    m = np.ascontiguousarray(mass, dtype=np.float64)
+    lo, L = root_cube(p)
+    k = keys(p, lo, L)
+    perm = sort(k)
+    sk = k[perm]
+    tree = build_tree(sk, leaf_size)
+    spos = p[perm]
+    smass = m[perm]
+    mom = moments(tree, spos, smass, lo, L)
+    return dict(lo=lo, L=L, keys=sk, perm=perm, tree=tree, mom=mom, spos=spos, smass=smass)
+
+
+def barnes_hut(pos, mass, theta, eps, leaf_size, order=2, targets=None, built=None):
+    """Barnes-Hut forces on bodies ``targets`` (original indices; all by default).
+    Returns a WalkResult (acc, phi, npp, npc, ncov, flag) in the order of
+    ``targets``."""
+    b = built if built is not None else build_all(pos, mass, leaf_size)
+    n = b["perm"].shape[0]
+    rank = np.empty(n, dtype=np.int64)
+    rank[b["perm"]] = np.arange(n, dtype=np.int64)
+    t = np.arange(n, dtype=np.int64) if targets is None else np.asarray(targets, dtype=np.int64)
+    return walk(b["tree"], b["mom"], b["spos"], b["smass"], b["L"], theta, eps, order, rank[t])
+
+
+def energy(pos, vel, mass, eps):
+    """(E_kin, E_pot) with E_pot = 1/2 sum_i m_i phi_i from the direct sum:
+    each pair counted once (the double sum over i != j in the energy formula
+    of Sec. 2.4 counts every pair twice), softened like the force."""
+    m = np.asarray(mass, dtype=np.float64)
+    v = np.asarray(vel, dtype=np.float64)
+    ekin = 0.5 * float(np.sum(m * np.sum(v * v, axis=1)))
+    _, phi = direct(pos, m, eps)
+    epot = 0.5 * float(np.sum(m * phi))
+    return ekin, epot
+
+
+def kdk(pos, vel, mass, dt, steps, force):
+    """Kick-drift-kick leapfrog (Sec. 2.3) with a fixed step: the acceleration
+    at the start is computed once, then each step is half kick, drift, new
+    acceleration, half kick.  ``force(pos) -> acc``.  Returns (pos, vel, acc)."""
+    x = np.array(pos, dtype=np.float64)
+    v = np.array(vel, dtype=np.float64)
+    a = force(x)
+    for _ in range(int(steps)):
+        v = v + a * (0.5 * dt)
+        x = x + v * dt
+        a = force(x)
+        v = v + a * (0.5 * dt)
+    return x, v, a
+
+
+def rms_rel(acc, ref):
+    """sqrt(mean_i |a_i - a_i^ref|^2 / |a_i^ref|^2) with the median, p99, max."""
+    e = np.linalg.norm(np.asarray(acc) - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    return dict(rms=float(np.sqrt(np.mean(e * e))), median=float(np.median(e)),
+                p99=float(np.quantile(e, 0.99)), max=float(e.max()))

@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark: Barnes-Hut force evaluation on one MI355X.
+
+Metric: bodies/s (and body-cell interactions/s) of the force evaluation at an
+rms relative force error of 1e-3 against FP64 direct summation.
+
+Workload (default): Plummer sphere, N = 2^20 equal masses (G = M = a = 1),
+eps 0.005, leaf 16, FP32 walk with FP64 cell moments, quadrupole order, KDK
+leapfrog dt 5e-4.  Before timing, theta is swept on the initial state and the
+theta at which the rms error over a seeded 4096-body subsample equals 1e-3
+is interpolated (log-log); the timed steps run at that theta.
+
+A timed step is one kick-drift-kick leapfrog step: kick + drift, tree
+rebuild (bbox, keys, radix sort, topology, FP64 upward pass, pack), the
+wavefront tree walk, the second kick, and the FP64 energy diagnostic.
+value = N / (time per step): one force evaluation per step, tree build
+included.  Inputs are resident on the GPU before timing starts.
+
+Prints ONE JSON line.  --gpus N with N > 1 is refused: this build targets
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "body-cell interactions/s and bodies/s force eval at rms rel force err 1e-3"
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+# algorithmic FLOPs per interaction: particle-particle 20;
+# particle-cell 20 (monopole) or 60 (monopole + quadrupole)
+FLOP_PP = 20
+FLOP_PC = {0: 20, 2: 60}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--n", type=int, default=None, help="override N")
+    ap.add_argument("--theta", type=float, default=None, help="skip the sweep; use this theta")
+    ap.add_argument("--target-err", type=float, default=1e-3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 20,
+                    help="bodies the CPU oracle walks (the tree is built in full)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        log("bench.py: only --gpus 1 is supported (single-GPU build)")
+        sys.exit(2)
+
+    import torch
+
+    from paper_2203_08966_amd import binding as B
+    from paper_2203_08966_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        log("bench.py needs a GPU")
+        sys.exit(1)
+    B.load()
+    bodies, cfg = W.config(args.config, n=args.n)
+    n = bodies.n
+    eps, leaf, dt, order = cfg["eps"], cfg["leaf"], cfg["dt"], 2
+    dtype = torch.float32 if cfg["dtype"] == "f32" else torch.float64
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(np.ascontiguousarray(bodies.pos)).to(dev)
+    vel = torch.from_numpy(np.ascontiguousarray(bodies.vel)).to(dev)
+    mass = torch.from_numpy(np.ascontiguousarray(bodies.mass)).to(dev)
+    ctx = B.bh_ctx_create(0)
+    log(f"workload {cfg['workload']} N={n} eps={eps} leaf={leaf} dtype={cfg['dtype']}")
+
+    # ---- error reference: FP64 direct sum on a seeded subsample (GPU)
+    sample = W.subsample(n, 4096, cfg.get("sub_seed", 100))
+    tg = torch.from_numpy(sample).to(dev)
+    acc_dir = torch.empty((len(sample), 3), dtype=torch.float64, device=dev)
+    B.bh_direct(ctx, pos, mass, tg, eps, acc_dir)
+    torch.cuda.synchronize()
+    ref = acc_dir.cpu().numpy()
+
+    tree = B.bh_build(ctx, pos, mass, leaf)
+    acc = torch.empty_like(pos)
+    npp = torch.zeros(n, dtype=torch.int32, device=dev)
+    npc = torch.zeros(n, dtype=torch.int32, device=dev)
+
+    def walk(theta, counters=False):
+        o = B.force_opts(order=order, n_pp=npp if counters else None,
+                         n_pc=npc if counters else None)
+        B.bh_forces(tree, theta, eps, acc, o)
+
+    def rms_at(theta):
+        walk(theta)
+        torch.cuda.synchronize()
+        a = acc.cpu().numpy()[sample].astype(np.float64)
+        e = np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        return float(np.sqrt(np.mean(e * e)))
+
+    # ---- theta at the target error
+    sweep = []
+    if args.theta is None:
+        for th in (0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0):
+            sweep.append((th, rms_at(th)))
+        log("theta sweep:", ", ".join(f"{t:.2f}:{e:.2e}" for t, e in sweep))
+        ths = np.array([s[0] for s in sweep])
+        es = np.array([s[1] for s in sweep])
+        lt, le = np.log(ths), np.log(es)
+        target = np.log(args.target_err)
+        k = int(np.searchsorted(le, target))
+        k = min(max(k, 1), len(ths) - 1)
+        w = (target - le[k - 1]) / (le[k] - le[k - 1])
+        theta = float(np.exp(lt[k - 1] + w * (lt[k] - lt[k - 1])))
+    else:
+        theta = args.theta
+    err_theta = rms_at(theta)
+    log(f"theta* = {theta:.4f}  rms rel err = {err_theta:.3e}")
+
+    # ---- interactions per force evaluation, walk-only time
+    walk(theta, counters=True)
+    torch.cuda.synchronize()
+    s_pp = int(npp.to(torch.int64).sum().item())
+    s_pc = int(npc.to(torch.int64).sum().item())
+    for _ in range(3):
+        walk(theta)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        walk(theta)
+    e1.record()
+    torch.cuda.synchronize()
+    walk_ms = e0.elapsed_time(e1) / reps
+    B.bh_tree_free(tree)
+
+    # ---- timed simulation steps
+    B.bh_sim_init(ctx, pos, vel, mass, leaf, theta, eps)
+    ek0, ep0 = B.bh_energy(ctx)
+    for _ in range(args.warmup):
+        B.bh_leapfrog_step(ctx, dt)
+        B.bh_energy(ctx)
+    torch.cuda.synchronize()
+    B.bh_sim_timing(ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B.bh_leapfrog_step(ctx, dt)
+        ek, ep = B.bh_energy(ctx)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phase_ms, nsteps = B.bh_sim_timing_get(ctx)
+    B.bh_sim_timing(ctx, False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = n / (ms_step * 1e-3)
+    phases = {k: v / max(nsteps, 1) for k, v in
+              zip(["kick_drift", "build", "walk", "kick"], phase_ms)}
+    walk_step_ms = phases["walk"]
+    inter = s_pp + s_pc
+    flops = FLOP_PP * s_pp + FLOP_PC[order] * s_pc
+    achieved_tf = flops / (walk_step_ms * 1e-3) / 1e12
+    log(f"step {ms_step:.3f} ms  phases {phases}  walk(bh_forces) {walk_ms:.3f} ms")
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "bodies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if dtype == torch.float32 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{cfg['workload']} N={n} (equal masses, G=M=a=1, seed {cfg['seed']})",
+            "n": n, "theta": round(theta, 4), "eps": eps, "leaf": leaf, "order": order,
+            "dt": dt, "step": "KDK leapfrog step: kick+drift, rebuild, walk, kick, energy",
+        },
+        "rms_rel_err": err_theta,
+        "interactions_per_s": inter / (walk_step_ms * 1e-3),
+        "interactions_per_eval": {"pp": s_pp, "pc": s_pc},
+        "walk_bodies_per_s": n / (walk_step_ms * 1e-3),
+        "phases_ms": phases,
+        "energy_rel_change": abs((ek + ep) - (ek0 + ep0)) / abs(ek0 + ep0),
+        "theta_sweep": [[t, e] for t, e in sweep],
+        "roofline": {
+            "bound": "alu", "kernel": "k_walk (FP32, quadrupole)",
+            "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": None,
+            "flop_per_launch": flops, "launch_ms": walk_step_ms,
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(bodies, cfg, theta, order, args.cpu_sample)
+    B.bh_ctx_destroy(ctx)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(bodies, cfg, theta, order, k):
+    """The FP64 C oracle on the host cores: full tree build over all N bodies
+    plus the walk of a seeded sample of k bodies; bodies/s extrapolated as
+    N / (t_build + t_walk * N / k)."""
+    import oracle
+    from paper_2203_08966_amd import workloads as W
+    oracle.build(force=False)
+    p64 = bodies.pos.astype(np.float64)
+    m64 = bodies.mass.astype(np.float64)
+    n = len(m64)
+    t0 = time.perf_counter()
+    built = oracle.build_all(p64, m64, cfg["leaf"])
+    t1 = time.perf_counter()
+    sample = W.subsample(n, k, 4242)
+    r = oracle.barnes_hut(None, None, theta, cfg["eps"], cfg["leaf"], order=order,
+                          targets=sample, built=built)
+    t2 = time.perf_counter()
+    t_eval = (t1 - t0) + (t2 - t1) * n / len(sample)
+    log(f"cpu oracle: build {t1 - t0:.2f} s, walk of {len(sample)} bodies {t2 - t1:.2f} s")
+    return {
+        "value": n / t_eval, "unit": "bodies/s", "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"full FP64 tree build of all {n} bodies ({t1 - t0:.2f} s) + walk of "
+                  f"{len(sample)} sampled bodies ({t2 - t1:.2f} s), extrapolated to N",
+        "interactions_per_s": float((r.npp.sum() + r.npc.sum()) / (t2 - t1)),
+    }
+
+
+if __name__ == "__main__":
+    main()

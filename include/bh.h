@@ -1,0 +1,195 @@
+/*
+ * bh.h -- C ABI of the MI355X (gfx950) Barnes-Hut library.
+ *
+ * The operations follow the Barnes-Hut loop body of Brandt, "On Distributed
+ * Gravitational N-Body Simulations" (arXiv:2203.08966), Sec. 3: build the
+ * octree over the bodies, compute each cell's mass distribution bottom-up,
+ * walk the tree per body with the opening-angle test side/distance < theta,
+ * then integrate with the kick-drift-kick leapfrog of Sec. 2.3.
+ *
+ * Conventions shared by every entry point:
+ *  - Units: G = 1 (Sec. 2.2).
+ *  - Pointers named "device" are device memory on the context's GPU; "host"
+ *    pointers are ordinary CPU memory.  Positions, velocities and
+ *    accelerations are N x 3, row-major, contiguous (x0 y0 z0 x1 ...);
+ *    masses are N.  Element type is given by a dtype argument (BH_F32 or
+ *    BH_F64); accelerations and potentials come back in the tree's dtype.
+ *  - The caller owns every pointer it passes.  The library never keeps a
+ *    caller pointer after a call returns; trees and simulation state live in
+ *    library-owned device memory freed by bh_tree_free / bh_ctx_destroy.
+ *  - All GPU work is enqueued on the context's stream; calls return without
+ *    waiting unless stated.  bh_build waits once for the node count.
+ *  - Every call returns BH_OK (0) or a negative status.  Argument checks run
+ *    on the host before any GPU work, so a rejected call has no effect.
+ *    Asynchronous device failures surface from bh_sync or the next call.
+ *    bh_last_error() gives a message for the calling thread's last failure.
+ *  - Results are deterministic: identical inputs and options give bitwise
+ *    identical outputs on every run.
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef BH_H
+#define BH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BH_OK = 0,
+    BH_E_INVALID = -1,   /* bad argument (null pointer, size, parameter, dtype) */
+    BH_E_NOMEM = -2,     /* device allocation failed */
+    BH_E_DEVICE = -3,    /* HIP runtime / kernel failure, or no usable GPU */
+    BH_E_STATE = -4,     /* call out of order (e.g. step before bh_sim_init) */
+    BH_E_NONFINITE = -5  /* a position is NaN or infinite */
+};
+
+enum { BH_F32 = 0, BH_F64 = 1 };
+
+/* Acceptance criterion used by the walk. */
+enum {
+    BH_MAC_THETA = 0, /* side/distance < theta (Sec. 3) */
+    BH_MAC_MLP = 1    /* learned criterion inside a theta band, theta outside it */
+};
+
+typedef struct bh_ctx bh_ctx;
+typedef struct bh_tree bh_tree;
+
+/* Options of a force evaluation.  Fill with bh_force_opts_default first. */
+typedef struct {
+    int order;        /* 0: monopole only; 2: monopole + quadrupole (default) */
+    int mac;          /* BH_MAC_THETA (default) or BH_MAC_MLP */
+    void *phi;        /* optional device out, N values in caller order: the
+                         potential at each body from the same walk */
+    uint32_t *n_pp;   /* optional device out, N: particle-particle count */
+    uint32_t *n_pc;   /* optional device out, N: particle-cell count */
+    int64_t target_begin; /* walk only bodies of sorted rank [begin, end); */
+    int64_t target_end;   /* end <= 0 means all.  Outputs of other bodies are
+                             left untouched. */
+    double mlp_theta_lo;  /* learned criterion: side/d below -> accept */
+    double mlp_theta_hi;  /* above -> open; in between ask the network */
+    double mlp_log10_tau; /* accept when predicted log10 error < this */
+} bh_force_opts;
+
+/* Library version string. */
+const char *bh_version(void);
+
+/* Message for the calling thread's most recent failed call ("" if none). */
+const char *bh_last_error(void);
+
+void bh_force_opts_default(bh_force_opts *opts);
+
+/* Create a context on HIP device `device`, enqueuing on `stream` (a
+ * hipStream_t; NULL = the null stream).  *out receives the context.
+ * BH_E_DEVICE when the device cannot be used. */
+int bh_ctx_create(int device, void *stream, bh_ctx **out);
+int bh_ctx_set_stream(bh_ctx *ctx, void *stream);
+/* Frees the context, its simulation state and its learned-criterion
+ * weights.  Trees built with it must be freed first. */
+int bh_ctx_destroy(bh_ctx *ctx);
+/* Waits for the context's stream; reports asynchronous device errors. */
+int bh_sync(bh_ctx *ctx);
+
+/* ---------------------------------------------------------------------
+ * bh_build -- octree construction (Sec. 3 build step; Sec. 4.4 Morton keys,
+ * Sec. 4.2 pre-order serialisation, Sec. 4.7 hashed keys).
+ *
+ * pos: device, n x 3 of dtype; mass: device, n of dtype (>= 0).
+ * leaf_size B in [1, 256]: a cell holding more than B bodies is split in
+ * half in each dimension, down to key level 21; only non-empty children
+ * exist (B = 1 is the paper's tree).  The root is the smallest power-of-two
+ * cube holding every body with its corner on a multiple of half its side;
+ * keys are 21 bits per dimension, x more significant than y than z.
+ * Bodies are sorted by key, ties in input order.  Nodes are stored in
+ * pre-order.  Cell moments (mass, centre of mass, quadrupole about it) are
+ * computed in FP64 whatever the dtype.
+ *
+ * *tree: NULL to allocate a new tree, or an existing tree of this context
+ * to rebuild into (its memory is reused and grown as needed).
+ * Errors: BH_E_INVALID (null pointer, n < 1, n >= 2^31, leaf_size out of
+ * range, bad dtype), BH_E_NONFINITE, BH_E_NOMEM, BH_E_DEVICE.  Waits for the
+ * device once (to size the node arrays).
+ * ------------------------------------------------------------------- */
+int bh_build(bh_ctx *ctx, const void *pos, const void *mass, int dtype, int64_t n,
+             int leaf_size, bh_tree **tree);
+int bh_tree_free(bh_tree *tree);
+
+/* ---------------------------------------------------------------------
+ * bh_forces -- per-body tree walk (Sec. 3, "Compute Cell Force").
+ *
+ * For every body: starting below the root, each child cell C in octant
+ * order contributes particle-particle if it holds one body; a particle-cell
+ * term with its multipole expansion if side^2 < theta^2 * d^2 (d from the
+ * body to C's centre of mass); particle-particle with each of its bodies if
+ * it is a leaf; otherwise C is opened.  Softening eps applies to every term
+ * (s^2 = r^2 + eps^2).  The self pair is skipped.  Arithmetic is the tree's
+ * dtype; the FP32 walk takes every position relative to a cell centre.
+ *
+ * acc: device out, n x 3 of the tree's dtype, caller order.
+ * theta >= 0, eps >= 0, finite.  opts NULL = defaults.
+ * Errors: BH_E_INVALID, BH_E_STATE (BH_MAC_MLP without loaded weights),
+ * BH_E_DEVICE.
+ * ------------------------------------------------------------------- */
+int bh_forces(bh_tree *tree, double theta, double eps, void *acc, const bh_force_opts *opts);
+
+/* Tree shape: n bodies, m nodes, depth, root cube (lo, side), dtype, leaf size. */
+typedef struct {
+    int64_t n, m;
+    int32_t depth, dtype, leaf_size, reserved;
+    double lo[3], side;
+} bh_tree_info;
+int bh_tree_info_get(const bh_tree *tree, bh_tree_info *info);
+
+/* Copies the tree to host buffers (any may be NULL): sorted keys[n],
+ * perm[n] (caller index of each sorted rank), and per node in pre-order:
+ * hkey[m] (1 << 3k | key prefix), level[m], begin[m] (first sorted rank),
+ * count[m], next[m] (first node after the subtree), parent[m] (-1 root),
+ * cmask[m] (bit d set iff child octant d exists), mass[m], com[m x 3]
+ * (absolute), quad[m x 6] (xx xy xz yy yz zz, sum m(3 y_a y_b - |y|^2 d_ab)
+ * about the COM).  Synchronous. */
+int bh_tree_export(const bh_tree *tree, uint64_t *keys, uint32_t *perm, uint64_t *hkey,
+                   int32_t *level, int32_t *begin, int32_t *count, int32_t *next,
+                   int32_t *parent, int32_t *cmask, double *mass, double *com, double *quad);
+
+/* ---------------------------------------------------------------------
+ * Simulation: kick-drift-kick leapfrog with a fixed step (Sec. 2.3).
+ * bh_sim_init copies pos/vel/mass (device, dtype) into context-owned state,
+ * builds the tree and computes the initial accelerations.  Each
+ * bh_leapfrog_step(dt) does v += a dt/2; x += v dt; rebuild; walk;
+ * v += a dt/2.  State is kept in key order between steps.
+ * ------------------------------------------------------------------- */
+int bh_sim_init(bh_ctx *ctx, const void *pos, const void *vel, const void *mass, int dtype,
+                int64_t n, int leaf_size, double theta, double eps, const bh_force_opts *opts);
+int bh_leapfrog_step(bh_ctx *ctx, double dt);
+/* Copies state to device buffers in caller order (any may be NULL). */
+int bh_sim_get(bh_ctx *ctx, void *pos, void *vel, void *acc);
+/* Kinetic energy sum m v^2 / 2 and potential energy sum m phi / 2 (each
+ * pair once, softened; Sec. 2.4), phi from the last walk, accumulated in
+ * FP64.  Synchronous. */
+int bh_energy(bh_ctx *ctx, double *ekin, double *epot);
+/* The simulation's current tree (owned by the context; do not free). */
+int bh_sim_tree(bh_ctx *ctx, bh_tree **tree);
+
+/* Per-phase timing of bh_leapfrog_step with HIP events recorded on the
+ * context's stream.  enable = 1 clears the totals and starts recording (at
+ * most 65536 steps); 0 stops.  bh_sim_timing_get waits for the stream and
+ * returns, summed over the recorded steps, the milliseconds spent in
+ * ms[0] kick + drift, ms[1] tree build, ms[2] walk, ms[3] final kick, and
+ * the number of steps. */
+int bh_sim_timing(bh_ctx *ctx, int enable);
+int bh_sim_timing_get(bh_ctx *ctx, double *ms, int64_t *steps);
+
+/* ---------------------------------------------------------------------
+ * bh_direct -- FP64 direct summation (Sec. 2.1) for a subset of targets,
+ * the judge of the tree's error.  pos/mass: device, dtype; targets: device
+ * int64[nt] caller indices; acc: device f64 nt x 3; phi: device f64 nt or
+ * NULL.  Self pair skipped.
+ * ------------------------------------------------------------------- */
+int bh_direct(bh_ctx *ctx, const void *pos, const void *mass, int dtype, int64_t n,
+              const int64_t *targets, int64_t nt, double eps, double *acc, double *phi);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BH_H */

@@ -1,0 +1,299 @@
+"""ctypes binding of libbh.so: argument marshalling only.
+
+Every function carries the name of the C entry point it calls (see
+include/bh.h) and takes torch tensors on the GPU; all work runs in the HIP
+library on the current torch stream.  There is no fallback: if the library
+is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbh.so")
+
+BH_OK, BH_E_INVALID, BH_E_NOMEM, BH_E_DEVICE, BH_E_STATE, BH_E_NONFINITE = 0, -1, -2, -3, -4, -5
+BH_F32, BH_F64 = 0, 1
+BH_MAC_THETA, BH_MAC_MLP = 0, 1
+
+EXPORTED = [
+    "bh_version", "bh_last_error", "bh_force_opts_default", "bh_ctx_create", "bh_ctx_set_stream",
+    "bh_ctx_destroy", "bh_sync", "bh_build", "bh_tree_free", "bh_forces", "bh_tree_info_get",
+    "bh_tree_export", "bh_sim_init", "bh_leapfrog_step", "bh_sim_get", "bh_energy",
+    "bh_sim_tree", "bh_direct", "bh_sim_timing", "bh_sim_timing_get",
+]
+
+
+__all__ = EXPORTED + [
+    "BHError", "ForceOpts", "TreeInfo", "force_opts", "load", "BH_OK", "BH_E_INVALID",
+    "BH_E_NOMEM", "BH_E_DEVICE", "BH_E_STATE", "BH_E_NONFINITE", "BH_F32", "BH_F64",
+    "BH_MAC_THETA", "BH_MAC_MLP",
+]
+
+
+class BHError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class ForceOpts(C.Structure):
+    _fields_ = [
+        ("order", C.c_int), ("mac", C.c_int), ("phi", C.c_void_p), ("n_pp", C.c_void_p),
+        ("n_pc", C.c_void_p), ("target_begin", C.c_int64), ("target_end", C.c_int64),
+        ("mlp_theta_lo", C.c_double), ("mlp_theta_hi", C.c_double),
+        ("mlp_log10_tau", C.c_double),
+    ]
+
+
+class TreeInfo(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("m", C.c_int64), ("depth", C.c_int32), ("dtype", C.c_int32),
+        ("leaf_size", C.c_int32), ("reserved", C.c_int32), ("lo", C.c_double * 3),
+        ("side", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libbh.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not built: run __graft_entry__.build() or "
+                          "python paper_2203_08966_amd/build_lib.py")
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    pp = C.POINTER(C.c_void_p)
+    sig = {
+        "bh_version": ([], C.c_char_p),
+        "bh_last_error": ([], C.c_char_p),
+        "bh_force_opts_default": ([C.POINTER(ForceOpts)], None),
+        "bh_ctx_create": ([i32, vp, pp], i32),
+        "bh_ctx_set_stream": ([vp, vp], i32),
+        "bh_ctx_destroy": ([vp], i32),
+        "bh_sync": ([vp], i32),
+        "bh_build": ([vp, vp, vp, i32, i64, i32, pp], i32),
+        "bh_tree_free": ([vp], i32),
+        "bh_forces": ([vp, dbl, dbl, vp, C.POINTER(ForceOpts)], i32),
+        "bh_tree_info_get": ([vp, C.POINTER(TreeInfo)], i32),
+        "bh_tree_export": ([vp] + [vp] * 12, i32),
+        "bh_sim_init": ([vp, vp, vp, vp, i32, i64, i32, dbl, dbl, C.POINTER(ForceOpts)], i32),
+        "bh_leapfrog_step": ([vp, dbl], i32),
+        "bh_sim_get": ([vp, vp, vp, vp], i32),
+        "bh_energy": ([vp, C.POINTER(dbl), C.POINTER(dbl)], i32),
+        "bh_sim_tree": ([vp, pp], i32),
+        "bh_direct": ([vp, vp, vp, i32, i64, vp, i64, dbl, vp, vp], i32),
+        "bh_sim_timing": ([vp, i32], i32),
+        "bh_sim_timing_get": ([vp, C.POINTER(dbl), C.POINTER(i64)], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != BH_OK:
+        raise BHError(rc, load().bh_last_error().decode())
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return BH_F32
+    if t.dtype == torch.float64:
+        return BH_F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _dev(t, name):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _bodies(pos, mass, vel=None):
+    """Shape/dtype checks shared by the entry points that take bodies."""
+    n = int(mass.shape[0])
+    if mass.dim() != 1 or tuple(pos.shape) != (n, 3):
+        raise ValueError(f"pos must be (n, 3) and mass (n,); got {tuple(pos.shape)}, {tuple(mass.shape)}")
+    if vel is not None and tuple(vel.shape) != (n, 3):
+        raise ValueError("vel must be (n, 3)")
+    for t in (mass, vel):
+        if t is not None and t.dtype != pos.dtype:
+            raise TypeError("pos, vel and mass must share a dtype")
+    return n
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def force_opts(order=2, mac=BH_MAC_THETA, phi=None, n_pp=None, n_pc=None, target_range=None,
+               mlp_theta_lo=None, mlp_theta_hi=None, mlp_log10_tau=None) -> ForceOpts:
+    o = ForceOpts()
+    load().bh_force_opts_default(C.byref(o))
+    o.order = order
+    o.mac = mac
+    o.phi = _dev(phi, "phi")
+    o.n_pp = _dev(n_pp, "n_pp")
+    o.n_pc = _dev(n_pc, "n_pc")
+    if target_range is not None:
+        o.target_begin, o.target_end = int(target_range[0]), int(target_range[1])
+    if mlp_theta_lo is not None:
+        o.mlp_theta_lo = mlp_theta_lo
+    if mlp_theta_hi is not None:
+        o.mlp_theta_hi = mlp_theta_hi
+    if mlp_log10_tau is not None:
+        o.mlp_log10_tau = mlp_log10_tau
+    return o
+
+
+# ----------------------------------------------------------------- entry points
+def bh_version() -> str:
+    return load().bh_version().decode()
+
+
+def bh_last_error() -> str:
+    return load().bh_last_error().decode()
+
+
+def bh_force_opts_default() -> ForceOpts:
+    o = ForceOpts()
+    load().bh_force_opts_default(C.byref(o))
+    return o
+
+
+def bh_ctx_create(device: int = 0, stream=None) -> C.c_void_p:
+    h = C.c_void_p()
+    s = _stream() if stream is None else C.c_void_p(stream)
+    _check(load().bh_ctx_create(device, s, C.byref(h)))
+    return h
+
+
+def bh_ctx_set_stream(ctx, stream=None):
+    _check(load().bh_ctx_set_stream(ctx, _stream() if stream is None else C.c_void_p(stream)))
+
+
+def bh_ctx_destroy(ctx):
+    _check(load().bh_ctx_destroy(ctx))
+
+
+def bh_sync(ctx):
+    _check(load().bh_sync(ctx))
+
+
+def bh_build(ctx, pos, mass, leaf_size: int, tree=None) -> C.c_void_p:
+    n = _bodies(pos, mass)
+    h = C.c_void_p(tree.value if tree is not None else None)
+    _check(load().bh_build(ctx, _dev(pos, "pos"), _dev(mass, "mass"), _dtype_code(pos),
+                           n, int(leaf_size), C.byref(h)))
+    return h
+
+
+def bh_tree_free(tree):
+    _check(load().bh_tree_free(tree))
+
+
+def bh_forces(tree, theta: float, eps: float, acc, opts: ForceOpts | None = None):
+    info = TreeInfo()
+    _check(load().bh_tree_info_get(tree, C.byref(info)))
+    if tuple(acc.shape) != (info.n, 3) or _dtype_code(acc) != info.dtype:
+        raise ValueError("acc must be (n, 3) in the tree's dtype")
+    _check(load().bh_forces(tree, float(theta), float(eps), _dev(acc, "acc"),
+                            C.byref(opts) if opts is not None else None))
+
+
+def bh_tree_info_get(tree) -> dict:
+    info = TreeInfo()
+    _check(load().bh_tree_info_get(tree, C.byref(info)))
+    return dict(n=info.n, m=info.m, depth=info.depth, dtype=info.dtype,
+                leaf_size=info.leaf_size, lo=np.array(info.lo[:]), side=info.side)
+
+
+def bh_tree_export(tree) -> dict:
+    info = bh_tree_info_get(tree)
+    n, m = info["n"], info["m"]
+    out = dict(
+        keys=np.zeros(n, np.uint64), perm=np.zeros(n, np.uint32), hkey=np.zeros(m, np.uint64),
+        level=np.zeros(m, np.int32), begin=np.zeros(m, np.int32), count=np.zeros(m, np.int32),
+        next=np.zeros(m, np.int32), parent=np.zeros(m, np.int32), cmask=np.zeros(m, np.int32),
+        mass=np.zeros(m), com=np.zeros((m, 3)), quad=np.zeros((m, 6)),
+    )
+    order = ["keys", "perm", "hkey", "level", "begin", "count", "next", "parent", "cmask",
+             "mass", "com", "quad"]
+    _check(load().bh_tree_export(tree, *[C.c_void_p(out[k].ctypes.data) for k in order]))
+    out.update(info)
+    return out
+
+
+def bh_sim_init(ctx, pos, vel, mass, leaf_size: int, theta: float, eps: float,
+                opts: ForceOpts | None = None):
+    n = _bodies(pos, mass, vel)
+    _check(load().bh_sim_init(ctx, _dev(pos, "pos"), _dev(vel, "vel"), _dev(mass, "mass"),
+                              _dtype_code(pos), n, int(leaf_size),
+                              float(theta), float(eps), C.byref(opts) if opts else None))
+
+
+def bh_leapfrog_step(ctx, dt: float):
+    _check(load().bh_leapfrog_step(ctx, float(dt)))
+
+
+def bh_sim_get(ctx, pos=None, vel=None, acc=None):
+    info = bh_tree_info_get(bh_sim_tree(ctx))
+    for t, name in ((pos, "pos"), (vel, "vel"), (acc, "acc")):
+        if t is not None and (tuple(t.shape) != (info["n"], 3) or _dtype_code(t) != info["dtype"]):
+            raise ValueError(f"{name} must be (n, 3) in the simulation's dtype")
+    _check(load().bh_sim_get(ctx, _dev(pos, "pos"), _dev(vel, "vel"), _dev(acc, "acc")))
+
+
+def bh_energy(ctx) -> tuple[float, float]:
+    ek, ep = C.c_double(), C.c_double()
+    _check(load().bh_energy(ctx, C.byref(ek), C.byref(ep)))
+    return ek.value, ep.value
+
+
+def bh_sim_tree(ctx) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(load().bh_sim_tree(ctx, C.byref(h)))
+    return h
+
+
+def bh_direct(ctx, pos, mass, targets, eps: float, acc, phi=None):
+    import torch
+    if targets.dtype != torch.int64:
+        raise TypeError("targets must be int64")
+    _bodies(pos, mass)
+    nt = int(targets.shape[0])
+    if tuple(acc.shape) != (nt, 3) or acc.dtype != torch.float64:
+        raise ValueError("acc must be (len(targets), 3) float64")
+    if phi is not None and (tuple(phi.shape) != (nt,) or phi.dtype != torch.float64):
+        raise ValueError("phi must be (len(targets),) float64")
+    _check(load().bh_direct(ctx, _dev(pos, "pos"), _dev(mass, "mass"), _dtype_code(pos),
+                            int(mass.shape[0]), _dev(targets, "targets"), int(targets.shape[0]),
+                            float(eps), _dev(acc, "acc"), _dev(phi, "phi")))
+
+
+def bh_sim_timing(ctx, enable: bool = True):
+    _check(load().bh_sim_timing(ctx, 1 if enable else 0))
+
+
+def bh_sim_timing_get(ctx) -> tuple[list, int]:
+    ms = (C.c_double * 4)()
+    steps = C.c_int64()
+    _check(load().bh_sim_timing_get(ctx, ms, C.byref(steps)))
+    return list(ms), steps.value

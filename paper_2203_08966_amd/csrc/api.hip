@@ -1,0 +1,504 @@
+// C ABI of the gfx950 Barnes-Hut library: argument checks (host, before any
+// GPU work), object lifetimes, and dispatch to the kernels.
+#include <math.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "bh_internal.h"
+
+namespace bh {
+
+static thread_local std::string g_err;
+
+int set_error(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int grow(DevBuf &b, size_t bytes) {
+    if (bytes == 0) bytes = 64;
+    if (b.cap >= bytes) return BH_OK;
+    if (b.p) {
+        hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    const size_t want = bytes + bytes / 8 + 256;
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess || !p) {
+        hipGetLastError();
+        return set_error(BH_E_NOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+    }
+    b.p = p;
+    b.cap = want;
+    return BH_OK;
+}
+
+void free_buf(DevBuf &b) {
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+int check_launch(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(BH_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return BH_OK;
+}
+
+static int use_device(bh_ctx *c) {
+    if (hipSetDevice(c->device) != hipSuccess) {
+        hipGetLastError();
+        return set_error(BH_E_DEVICE, "hipSetDevice failed");
+    }
+    return BH_OK;
+}
+
+static void free_tree_bufs(bh_tree *t) {
+    DevBuf *all[] = {&t->keys_a, &t->keys_b, &t->idx_a, &t->idx_b, &t->spos, &t->smass,
+                     &t->bodies, &t->anchors, &t->delta, &t->nstart, &t->offs, &t->hkey,
+                     &t->level, &t->begin, &t->count, &t->next, &t->parent, &t->cmask,
+                     &t->nchild, &t->arrive, &t->cx, &t->cy, &t->cz, &t->mom, &t->recs,
+                     &t->cube, &t->part, &t->hist, &t->status, &t->misc, &t->cnt_scratch};
+    for (DevBuf *b : all) free_buf(*b);
+}
+
+static void free_sim(SimState *s) {
+    DevBuf *all[] = {&s->pos, &s->vel, &s->mass, &s->acc, &s->phi, &s->id,
+                     &s->pos2, &s->vel2, &s->mass2, &s->id2, &s->red};
+    for (DevBuf *b : all) free_buf(*b);
+}
+
+static bool bad_dtype(int d) { return d != BH_F32 && d != BH_F64; }
+static size_t dsize(int d) { return d == BH_F32 ? 4 : 8; }
+
+static int check_opts(const bh_force_opts &o, int64_t n) {
+    if (o.order != 0 && o.order != 2) return set_error(BH_E_INVALID, "opts.order must be 0 or 2");
+    if (o.mac != BH_MAC_THETA && o.mac != BH_MAC_MLP)
+        return set_error(BH_E_INVALID, "opts.mac must be BH_MAC_THETA or BH_MAC_MLP");
+    if (o.target_end > 0 &&
+        (o.target_begin < 0 || o.target_begin > o.target_end || o.target_end > n))
+        return set_error(BH_E_INVALID, "opts target range outside [0, n]");
+    if (o.mac == BH_MAC_MLP &&
+        !(o.mlp_theta_lo >= 0 && o.mlp_theta_hi >= o.mlp_theta_lo && isfinite(o.mlp_theta_hi) &&
+          isfinite(o.mlp_log10_tau)))
+        return set_error(BH_E_INVALID, "opts learned-criterion band invalid");
+    return BH_OK;
+}
+
+static int check_params(double theta, double eps) {
+    if (!(theta >= 0) || !isfinite(theta)) return set_error(BH_E_INVALID, "theta must be finite and >= 0");
+    if (!(eps >= 0) || !isfinite(eps)) return set_error(BH_E_INVALID, "eps must be finite and >= 0");
+    return BH_OK;
+}
+
+static int check_build_args(const void *pos, const void *mass, int dtype, int64_t n, int leaf) {
+    if (!pos || !mass) return set_error(BH_E_INVALID, "null pos or mass");
+    if (bad_dtype(dtype)) return set_error(BH_E_INVALID, "dtype must be BH_F32 or BH_F64");
+    if (n < 1 || n > (int64_t)0x7fff0000) return set_error(BH_E_INVALID, "n must be in [1, 2^31 - 2^16]");
+    if (leaf < 1 || leaf > kMaxLeaf) return set_error(BH_E_INVALID, "leaf_size must be in [1, 256]");
+    return BH_OK;
+}
+
+}  // namespace bh
+
+using namespace bh;
+
+extern "C" {
+
+const char *bh_version(void) { return "bh-gfx950 0.1"; }
+
+const char *bh_last_error(void) { return g_err.c_str(); }
+
+void bh_force_opts_default(bh_force_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->order = 2;
+    o->mac = BH_MAC_THETA;
+    o->mlp_theta_lo = 0.3;
+    o->mlp_theta_hi = 1.0;
+    o->mlp_log10_tau = -3.0;
+}
+
+int bh_ctx_create(int device, void *stream, bh_ctx **out) {
+    if (!out) return set_error(BH_E_INVALID, "null out");
+    *out = nullptr;
+    if (device < 0) return set_error(BH_E_INVALID, "device must be >= 0");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        hipGetLastError();
+        return set_error(BH_E_DEVICE, "no HIP device available");
+    }
+    if (device >= count) return set_error(BH_E_INVALID, "device index out of range");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+        return set_error(BH_E_DEVICE, "hipGetDeviceProperties failed");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_error(BH_E_DEVICE, std::string("library is built for gfx950, device is ") +
+                                          prop.gcnArchName);
+    bh_ctx *c = new bh_ctx;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    if (use_device(c) || hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return set_error(BH_E_DEVICE, "pinned staging allocation failed");
+    }
+    *out = c;
+    return BH_OK;
+}
+
+int bh_ctx_set_stream(bh_ctx *c, void *stream) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    c->stream = (hipStream_t)stream;
+    return BH_OK;
+}
+
+int bh_ctx_destroy(bh_ctx *c) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if (c->live_trees > 0) return set_error(BH_E_STATE, "free the context's trees first");
+    use_device(c);
+    hipStreamSynchronize(c->stream);
+    if (c->sim) {
+        free_sim(c->sim);
+        delete c->sim;
+    }
+    if (c->sim_tree) {
+        free_tree_bufs(c->sim_tree);
+        delete c->sim_tree;
+    }
+    free_buf(c->mlp_w);
+    free_buf(c->scratch);
+    for (hipEvent_t e : c->events) hipEventDestroy(e);
+    if (c->pinned) hipHostFree(c->pinned);
+    delete c;
+    return BH_OK;
+}
+
+int bh_sync(bh_ctx *c) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if (use_device(c)) return BH_E_DEVICE;
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return set_error(BH_E_DEVICE, std::string("device error: ") + hipGetErrorString(e));
+    return check_launch("sync");
+}
+
+int bh_build(bh_ctx *c, const void *pos, const void *mass, int dtype, int64_t n, int leaf,
+             bh_tree **tree) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if (!tree) return set_error(BH_E_INVALID, "null tree handle");
+    int rc = check_build_args(pos, mass, dtype, n, leaf);
+    if (rc) return rc;
+    if (*tree && (*tree)->ctx != c) return set_error(BH_E_INVALID, "tree belongs to another context");
+    if (*tree && *tree == c->sim_tree) return set_error(BH_E_INVALID, "cannot rebuild the simulation tree");
+    if (use_device(c)) return BH_E_DEVICE;
+    bh_tree *t = *tree;
+    const bool fresh = t == nullptr;
+    if (fresh) {
+        t = new bh_tree;
+        t->ctx = c;
+    }
+    rc = build_tree(c, t, pos, mass, dtype, n, leaf, nullptr, nullptr, nullptr, nullptr,
+                    nullptr, nullptr);
+    if (rc) {
+        if (fresh) {
+            free_tree_bufs(t);
+            delete t;
+        }
+        return rc;
+    }
+    if (fresh) {
+        c->live_trees++;
+        *tree = t;
+    }
+    return BH_OK;
+}
+
+int bh_tree_free(bh_tree *t) {
+    if (!t) return set_error(BH_E_INVALID, "null tree");
+    if (t->ctx && t == t->ctx->sim_tree) return set_error(BH_E_INVALID, "the simulation tree is owned by its context");
+    if (t->ctx) {
+        use_device(t->ctx);
+        hipStreamSynchronize(t->ctx->stream);
+        t->ctx->live_trees--;
+    }
+    free_tree_bufs(t);
+    delete t;
+    return BH_OK;
+}
+
+int bh_forces(bh_tree *t, double theta, double eps, void *acc, const bh_force_opts *opts) {
+    if (!t) return set_error(BH_E_INVALID, "null tree");
+    if (!acc) return set_error(BH_E_INVALID, "null acc");
+    int rc = check_params(theta, eps);
+    if (rc) return rc;
+    bh_force_opts o;
+    if (opts) o = *opts;
+    else bh_force_opts_default(&o);
+    if ((rc = check_opts(o, t->n))) return rc;
+    if (o.mac == BH_MAC_MLP && !t->ctx->mlp_loaded)
+        return set_error(BH_E_STATE, "learned criterion requested but no weights are loaded");
+    if (use_device(t->ctx)) return BH_E_DEVICE;
+    return run_walk(t, theta, eps, acc, o.phi, o.n_pp, o.n_pc, o, false);
+}
+
+int bh_tree_info_get(const bh_tree *t, bh_tree_info *info) {
+    if (!t || !info) return set_error(BH_E_INVALID, "null tree or info");
+    if (use_device(t->ctx)) return BH_E_DEVICE;
+    uint32_t depth = 0;
+    if (hipStreamSynchronize(t->ctx->stream) != hipSuccess ||
+        hipMemcpy(&depth, (uint32_t *)t->misc.p + 1, 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return set_error(BH_E_DEVICE, "tree info copy failed");
+    memset(info, 0, sizeof(*info));
+    info->n = t->n;
+    info->m = t->m;
+    info->depth = (int32_t)depth;
+    info->dtype = t->dtype;
+    info->leaf_size = t->leaf;
+    for (int d = 0; d < 3; ++d) info->lo[d] = t->lo[d];
+    info->side = t->L;
+    return BH_OK;
+}
+
+int bh_tree_export(const bh_tree *t, uint64_t *keys, uint32_t *perm, uint64_t *hkey,
+                   int32_t *level, int32_t *begin, int32_t *count, int32_t *next,
+                   int32_t *parent, int32_t *cmask, double *mass, double *com, double *quad) {
+    if (!t) return set_error(BH_E_INVALID, "null tree");
+    if (use_device(t->ctx)) return BH_E_DEVICE;
+    if (hipStreamSynchronize(t->ctx->stream) != hipSuccess)
+        return set_error(BH_E_DEVICE, "device error before export");
+    const size_t n = (size_t)t->n, m = (size_t)t->m;
+    bool ok = true;
+    auto cp = [&](void *dst, const void *src, size_t bytes) {
+        if (dst && ok) ok = hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost) == hipSuccess;
+    };
+    cp(keys, t->sorted_keys, 8 * n);
+    cp(perm, t->perm, 4 * n);
+    cp(hkey, t->hkey.p, 8 * m);
+    cp(level, t->level.p, 4 * m);
+    cp(begin, t->begin.p, 4 * m);
+    cp(count, t->count.p, 4 * m);
+    cp(next, t->next.p, 4 * m);
+    cp(parent, t->parent.p, 4 * m);
+    cp(cmask, t->cmask.p, 4 * m);
+    if (ok && (mass || com || quad)) {
+        std::vector<Moments> mom(m);
+        std::vector<int32_t> c3(3 * m);
+        cp(mom.data(), t->mom.p, sizeof(Moments) * m);
+        cp(c3.data(), t->cx.p, 4 * m);
+        cp(c3.data() + m, t->cy.p, 4 * m);
+        cp(c3.data() + 2 * m, t->cz.p, 4 * m);
+        if (ok) {
+            const double h = ldexp(t->L, -(kLevels + 1));
+            for (size_t i = 0; i < m; ++i) {
+                const Moments &q = mom[i];
+                if (mass) mass[i] = q.m;
+                if (com)
+                    for (int d = 0; d < 3; ++d)
+                        com[3 * i + d] = t->lo[d] + c3[d * m + i] * h + q.c[d];
+                if (quad) {
+                    const double tr = q.t[0] + q.t[3] + q.t[5];
+                    quad[6 * i + 0] = 3 * q.t[0] - tr;
+                    quad[6 * i + 1] = 3 * q.t[1];
+                    quad[6 * i + 2] = 3 * q.t[2];
+                    quad[6 * i + 3] = 3 * q.t[3] - tr;
+                    quad[6 * i + 4] = 3 * q.t[4];
+                    quad[6 * i + 5] = 3 * q.t[5] - tr;
+                }
+            }
+        }
+    }
+    if (!ok) {
+        hipGetLastError();
+        return set_error(BH_E_DEVICE, "tree export copy failed");
+    }
+    return BH_OK;
+}
+
+// ---------------------------------------------------------------- simulation
+static int sim_forces(bh_ctx *c) {
+    SimState *s = c->sim;
+    return run_walk(c->sim_tree, s->theta, s->eps, s->acc.p, s->phi.p, nullptr, nullptr, s->opts,
+                    true);
+}
+
+static int sim_rebuild(bh_ctx *c, const void *pos, const void *vel, const void *mass,
+                       const uint32_t *id) {
+    SimState *s = c->sim;
+    int rc = build_tree(c, c->sim_tree, pos, mass, s->dtype, s->n, s->leaf, vel, id, s->pos2.p,
+                        s->vel2.p, s->mass2.p, (uint32_t *)s->id2.p);
+    if (rc) return rc;
+    std::swap(s->pos, s->pos2);
+    std::swap(s->vel, s->vel2);
+    std::swap(s->mass, s->mass2);
+    std::swap(s->id, s->id2);
+    return BH_OK;
+}
+
+int bh_sim_init(bh_ctx *c, const void *pos, const void *vel, const void *mass, int dtype,
+                int64_t n, int leaf, double theta, double eps, const bh_force_opts *opts) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if (!vel) return set_error(BH_E_INVALID, "null vel");
+    int rc = check_build_args(pos, mass, dtype, n, leaf);
+    if (rc) return rc;
+    if ((rc = check_params(theta, eps))) return rc;
+    bh_force_opts o;
+    if (opts) o = *opts;
+    else bh_force_opts_default(&o);
+    o.phi = nullptr;
+    o.n_pp = o.n_pc = nullptr;
+    o.target_begin = o.target_end = 0;
+    if ((rc = check_opts(o, n))) return rc;
+    if (o.mac == BH_MAC_MLP && !c->mlp_loaded)
+        return set_error(BH_E_STATE, "learned criterion requested but no weights are loaded");
+    if (use_device(c)) return BH_E_DEVICE;
+    if (!c->sim) c->sim = new SimState;
+    if (!c->sim_tree) {
+        c->sim_tree = new bh_tree;
+        c->sim_tree->ctx = c;
+    }
+    SimState *s = c->sim;
+    s->dtype = dtype;
+    s->n = n;
+    s->leaf = leaf;
+    s->theta = theta;
+    s->eps = eps;
+    s->opts = o;
+    s->have_acc = false;
+    const size_t e = dsize(dtype);
+    if ((rc = grow(s->pos, 3 * e * n)) || (rc = grow(s->vel, 3 * e * n)) ||
+        (rc = grow(s->mass, e * n)) || (rc = grow(s->acc, 3 * e * n)) ||
+        (rc = grow(s->phi, e * n)) || (rc = grow(s->id, 4ull * n)) ||
+        (rc = grow(s->pos2, 3 * e * n)) || (rc = grow(s->vel2, 3 * e * n)) ||
+        (rc = grow(s->mass2, e * n)) || (rc = grow(s->id2, 4ull * n)) ||
+        (rc = grow(s->red, 8ull * (2 * 1024 + 8))))
+        return rc;
+    // first build gathers straight from the caller's arrays
+    if ((rc = sim_rebuild(c, pos, vel, mass, nullptr))) return rc;
+    if ((rc = sim_forces(c))) return rc;
+    s->have_acc = true;
+    return BH_OK;
+}
+
+static constexpr int64_t kMaxTimedSteps = 65536;
+
+static hipEvent_t *step_events(bh_ctx *c) {
+    if (!c->timing || c->timed_steps >= kMaxTimedSteps) return nullptr;
+    const size_t need = 5 * (size_t)(c->timed_steps + 1);
+    while (c->events.size() < need) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->events.push_back(e);
+    }
+    return &c->events[5 * (size_t)c->timed_steps];
+}
+
+int bh_leapfrog_step(bh_ctx *c, double dt) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if (!c->sim || !c->sim->have_acc) return set_error(BH_E_STATE, "bh_sim_init has not run");
+    if (!isfinite(dt)) return set_error(BH_E_INVALID, "dt must be finite");
+    if (use_device(c)) return BH_E_DEVICE;
+    SimState *s = c->sim;
+    hipEvent_t *ev = step_events(c);
+    auto mark = [&](int k) {
+        if (ev) hipEventRecord(ev[k], c->stream);
+    };
+    int rc;
+    mark(0);
+    // kick (dt/2) and drift (dt)
+    if ((rc = launch_kick_drift(c->stream, s->dtype, s->n, s->pos.p, s->vel.p, s->acc.p,
+                                0.5 * dt, dt)))
+        return rc;
+    mark(1);
+    // new tree and accelerations at the drifted positions
+    if ((rc = sim_rebuild(c, s->pos.p, s->vel.p, s->mass.p, (const uint32_t *)s->id.p))) return rc;
+    mark(2);
+    if ((rc = sim_forces(c))) return rc;
+    mark(3);
+    // second kick (dt/2)
+    rc = launch_kick(c->stream, s->dtype, s->n, s->vel.p, s->acc.p, 0.5 * dt);
+    mark(4);
+    if (ev) c->timed_steps++;
+    return rc;
+}
+
+int bh_sim_timing(bh_ctx *c, int enable) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    c->timing = enable != 0;
+    if (enable) c->timed_steps = 0;
+    return BH_OK;
+}
+
+int bh_sim_timing_get(bh_ctx *c, double *ms, int64_t *steps) {
+    if (!c || !ms || !steps) return set_error(BH_E_INVALID, "null argument");
+    if (use_device(c)) return BH_E_DEVICE;
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return set_error(BH_E_DEVICE, "device error while timing");
+    for (int k = 0; k < 4; ++k) ms[k] = 0.0;
+    for (int64_t s = 0; s < c->timed_steps; ++s) {
+        hipEvent_t *e = &c->events[5 * (size_t)s];
+        for (int k = 0; k < 4; ++k) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, e[k], e[k + 1]) != hipSuccess)
+                return set_error(BH_E_DEVICE, "hipEventElapsedTime failed");
+            ms[k] += t;
+        }
+    }
+    *steps = c->timed_steps;
+    return BH_OK;
+}
+
+int bh_sim_get(bh_ctx *c, void *pos, void *vel, void *acc) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if (!c->sim || !c->sim->have_acc) return set_error(BH_E_STATE, "bh_sim_init has not run");
+    if (use_device(c)) return BH_E_DEVICE;
+    SimState *s = c->sim;
+    int rc = BH_OK;
+    const uint32_t *id = (const uint32_t *)s->id.p;
+    if (pos && (rc = launch_unpermute(c->stream, s->dtype, s->n, id, s->pos.p, pos))) return rc;
+    if (vel && (rc = launch_unpermute(c->stream, s->dtype, s->n, id, s->vel.p, vel))) return rc;
+    if (acc && (rc = launch_unpermute(c->stream, s->dtype, s->n, id, s->acc.p, acc))) return rc;
+    return BH_OK;
+}
+
+int bh_energy(bh_ctx *c, double *ekin, double *epot) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if (!ekin || !epot) return set_error(BH_E_INVALID, "null output");
+    if (!c->sim || !c->sim->have_acc) return set_error(BH_E_STATE, "bh_sim_init has not run");
+    if (use_device(c)) return BH_E_DEVICE;
+    SimState *s = c->sim;
+    double *red = (double *)s->red.p;
+    int rc = launch_energy(c->stream, s->dtype, s->n, s->vel.p, s->mass.p, s->phi.p, red,
+                           red + 2 * 1024);
+    if (rc) return rc;
+    double *hp = (double *)c->pinned + 64;
+    if (hipMemcpyAsync(hp, red + 2 * 1024, 16, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return set_error(BH_E_DEVICE, "energy copy failed");
+    *ekin = hp[0];
+    *epot = hp[1];
+    return BH_OK;
+}
+
+int bh_sim_tree(bh_ctx *c, bh_tree **tree) {
+    if (!c || !tree) return set_error(BH_E_INVALID, "null argument");
+    if (!c->sim || !c->sim->have_acc) return set_error(BH_E_STATE, "bh_sim_init has not run");
+    *tree = c->sim_tree;
+    return BH_OK;
+}
+
+int bh_direct(bh_ctx *c, const void *pos, const void *mass, int dtype, int64_t n,
+              const int64_t *targets, int64_t nt, double eps, double *acc, double *phi) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if (!pos || !mass || !targets || !acc) return set_error(BH_E_INVALID, "null pointer");
+    if (bad_dtype(dtype)) return set_error(BH_E_INVALID, "dtype must be BH_F32 or BH_F64");
+    if (n < 1 || n > (int64_t)0x7fff0000) return set_error(BH_E_INVALID, "n out of range");
+    if (nt < 1 || nt > (int64_t)0x7fff0000) return set_error(BH_E_INVALID, "nt out of range");
+    if (!(eps >= 0) || !isfinite(eps)) return set_error(BH_E_INVALID, "eps must be finite and >= 0");
+    if (use_device(c)) return BH_E_DEVICE;
+    return launch_direct(c->stream, dtype, n, pos, mass, targets, nt, eps, acc, phi, c->scratch);
+}
+
+}  // extern "C"

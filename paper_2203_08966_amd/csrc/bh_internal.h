@@ -1,0 +1,158 @@
+// Internal declarations of the gfx950 Barnes-Hut library (HIP, wave64).
+// Device data layouts, launch helpers and the host-side objects behind the
+// opaque handles of bh.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "bh.h"
+
+namespace bh {
+
+constexpr int kLevels = 21;        // key bits per dimension (Sec. 4.4)
+constexpr int kMaxLeaf = 256;      // largest supported leaf capacity B
+constexpr int kThreads = 256;      // default block size (4 waves)
+
+// Root cube, device resident: lower corner and side (a power of two).
+struct Cube {
+    double lo[3];
+    double L;
+};
+
+// FP64 cell moments from the upward pass: total mass, centre of mass
+// relative to the cell centre, and the raw second moment
+// sum m (y - com)(y - com)^T about the COM (xx xy xz yy yz zz).
+struct Moments {
+    double m;
+    double c[3];
+    double t[6];
+};
+
+// Walk record of one cell, FP32: 64 bytes, read with uniform (scalar) loads.
+// Integer centre in units of L * 2^-22 (exact for every level); COM and
+// quadrupole relative to that centre; traceless quadrupole as 5 components.
+struct alignas(64) NodeRec32 {
+    int cx, cy, cz;
+    float mx, my, mz;
+    float m;
+    float qxx, qxy, qxz, qyy, qyz;
+    int begin, count, next, level;
+};
+
+// FP64 walk record (128 bytes).
+struct alignas(128) NodeRec64 {
+    int cx, cy, cz, level;
+    int begin, count, next, pad0;
+    double mx, my, mz, m;
+    double qxx, qxy, qxz, qyy, qyz, pad1;
+};
+
+template <typename R> struct NodeRecT;
+template <> struct NodeRecT<float> { using type = NodeRec32; };
+template <> struct NodeRecT<double> { using type = NodeRec64; };
+
+// Body record for the walk: offset from its leaf's centre and mass.
+template <typename R> struct alignas(4 * sizeof(R)) BodyRec {
+    R x, y, z, m;
+};
+
+// Grow-only device buffer.
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct SimState;
+
+}  // namespace bh
+
+// Opaque handles.
+struct bh_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint32_t epoch = 0;              // look-back epoch of the radix sort
+    void *pinned = nullptr;          // small pinned host staging area
+    bh::SimState *sim = nullptr;
+    bh_tree *sim_tree = nullptr;
+    int live_trees = 0;
+    // learned acceptance criterion
+    bh::DevBuf mlp_w;                // packed weights on the device
+    int mlp_loaded = 0;
+    bh::DevBuf scratch;              // direct-sum partials
+    // phase timing of simulation steps
+    bool timing = false;
+    std::vector<hipEvent_t> events;  // 5 per recorded step
+    int64_t timed_steps = 0;
+};
+
+struct bh_tree {
+    bh_ctx *ctx = nullptr;
+    int dtype = BH_F32;
+    int64_t n = 0, m = 0;
+    int leaf = 1;
+    int depth = 0;
+    double lo[3] = {0, 0, 0}, L = 1.0;
+    // body-indexed
+    bh::DevBuf keys_a, keys_b, idx_a, idx_b;  // radix-sort ping-pong
+    bh::DevBuf spos, smass;                    // sorted positions and masses (dtype)
+    bh::DevBuf bodies, anchors;                // walk body records, leaf centres
+    bh::DevBuf delta, nstart, offs;            // topology scratch
+    // node-indexed
+    bh::DevBuf hkey, level, begin, count, next, parent, cmask, nchild, arrive;
+    bh::DevBuf cx, cy, cz;
+    bh::DevBuf mom, recs;
+    // small scratch
+    bh::DevBuf cube, part, hist, status, misc, cnt_scratch;
+    uint64_t *sorted_keys = nullptr;           // result buffers after the sort
+    uint32_t *perm = nullptr;
+};
+
+namespace bh {
+
+struct SimState {
+    int dtype = BH_F32;
+    int64_t n = 0;
+    int leaf = 16;
+    double theta = 0.5, eps = 0.0;
+    bh_force_opts opts{};
+    DevBuf pos, vel, mass, acc, phi, id;       // key order (current)
+    DevBuf pos2, vel2, mass2, id2;             // gather targets
+    DevBuf red;                                // energy reduction scratch
+    bool have_acc = false;
+};
+
+// ---- host helpers (api.hip)
+int set_error(int code, const std::string &msg);
+int grow(DevBuf &b, size_t bytes);
+void free_buf(DevBuf &b);
+int check_launch(const char *what);
+
+// ---- tree construction (build.hip)
+// Builds the tree from device pos/mass of `dtype`.  If `vel`/`id` are given
+// (simulation), they are permuted alongside into vel_out/id_out.
+int build_tree(bh_ctx *ctx, bh_tree *t, const void *pos, const void *mass, int dtype,
+               int64_t n, int leaf, const void *vel, const uint32_t *id, void *pos_out,
+               void *vel_out, void *mass_out, uint32_t *id_out);
+
+// ---- walk (walk.hip)
+int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_t *npp,
+             uint32_t *npc, const bh_force_opts &o, bool sorted_out);
+
+// ---- simulation helpers (sim.hip)
+int launch_kick(hipStream_t s, int dtype, int64_t n, void *vel, const void *acc, double h);
+int launch_kick_drift(hipStream_t s, int dtype, int64_t n, void *pos, void *vel,
+                      const void *acc, double h, double dt);
+int launch_energy(hipStream_t s, int dtype, int64_t n, const void *vel, const void *mass,
+                  const void *phi, double *red, double *host_out2);
+int launch_unpermute(hipStream_t s, int dtype, int64_t n, const uint32_t *id, const void *src,
+                     void *dst);
+int launch_direct(hipStream_t s, int dtype, int64_t n, const void *pos, const void *mass,
+                  const int64_t *targets, int64_t nt, double eps, double *acc, double *phi,
+                  DevBuf &scratch);
+
+inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace bh

@@ -1,0 +1,896 @@
+// Octree construction on gfx950 (Barnes-Hut loop body, Sec. 3, build step).
+//
+//  1. bbox + root cube     per-block FP64 min/max, then one block snaps the
+//                          root cube (power-of-two side, corner on L/2 grid)
+//  2. keys + histograms    21-bit quantisation per axis in FP64, bit-spread
+//                          interleave x > y > z (Sec. 4.4); the same pass
+//                          counts all eight 8-bit digits of every key
+//  3. LDS radix sort       eight stable passes; each pass ranks a 4096-key
+//                          tile in LDS (wave-level match via ballots),
+//                          finds its global offsets by decoupled look-back,
+//                          reorders the tile in LDS and writes runs
+//  4. gather               bodies into key order
+//  5. topology             bottom-up from adjacent-key common prefixes: each
+//                          sorted rank s starts the chain of cells whose
+//                          first body it is; a scan of the chain lengths
+//                          places every cell in pre-order (Sec. 4.2)
+//  6. upward pass (FP64)   leaves from their bodies, parents from children
+//                          with the parallel-axis shift; the last child to
+//                          finish (atomic arrival count) climbs on
+//  7. pack                 FP32/FP64 walk records and leaf-relative bodies
+#include <float.h>
+#include <math.h>
+
+#include "bh_internal.h"
+
+namespace bh {
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys
+constexpr int kWaveTile = 64 * kSortItems;            // 1024 keys per wave
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kThreads * kScanItems;      // 2048
+
+__device__ __forceinline__ unsigned lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+// popcount(mask & lanes-below-me)
+__device__ __forceinline__ unsigned rank_in(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// ------------------------------------------------------------------ zero fill
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------------ 1. bbox
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bbox(const T *__restrict__ pos, int n,
+                                                   double *__restrict__ part,
+                                                   uint32_t *__restrict__ flags) {
+    double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    bool bad = false;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double v = (double)pos[3 * (int64_t)i + d];
+            bad |= !isfinite(v);
+            mn[d] = fmin(mn[d], v);
+            mx[d] = fmax(mx[d], v);
+        }
+    }
+    __shared__ double sh[6][kThreads / 64];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        for (int o = 32; o > 0; o >>= 1) {
+            mn[d] = fmin(mn[d], __shfl_xor(mn[d], o));
+            mx[d] = fmax(mx[d], __shfl_xor(mx[d], o));
+        }
+    }
+    const int w = threadIdx.x / 64;
+    if (lane_id() == 0) {
+        for (int d = 0; d < 3; ++d) {
+            sh[d][w] = mn[d];
+            sh[3 + d][w] = mx[d];
+        }
+    }
+    if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flags, 1u);
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int d = threadIdx.x;
+        double v = sh[d][0];
+        for (int k = 1; k < kThreads / 64; ++k) v = d < 3 ? fmin(v, sh[d][k]) : fmax(v, sh[d][k]);
+        part[6 * blockIdx.x + d] = v;
+    }
+}
+
+// One block: reduce the partials and snap the root cube.  Same rule as the
+// method's definition: smallest power-of-two side L such that, with the
+// corner at floor(min / (L/2)) * (L/2), max < corner + L in every axis.
+__global__ __launch_bounds__(kThreads) void k_cube(const double *__restrict__ part, int np,
+                                                   Cube *__restrict__ cube) {
+    double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    for (int b = threadIdx.x; b < np; b += blockDim.x)
+        for (int d = 0; d < 3; ++d) {
+            mn[d] = fmin(mn[d], part[6 * b + d]);
+            mx[d] = fmax(mx[d], part[6 * b + 3 + d]);
+        }
+    for (int d = 0; d < 3; ++d)
+        for (int o = 32; o > 0; o >>= 1) {
+            mn[d] = fmin(mn[d], __shfl_xor(mn[d], o));
+            mx[d] = fmax(mx[d], __shfl_xor(mx[d], o));
+        }
+    __shared__ double sh[6][kThreads / 64];
+    const int w = threadIdx.x / 64;
+    if (lane_id() == 0)
+        for (int d = 0; d < 3; ++d) {
+            sh[d][w] = mn[d];
+            sh[3 + d][w] = mx[d];
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int d = 0; d < 3; ++d) {
+            for (int k = 1; k < kThreads / 64; ++k) {
+                sh[d][0] = fmin(sh[d][0], sh[d][k]);
+                sh[3 + d][0] = fmax(sh[3 + d][0], sh[3 + d][k]);
+            }
+            mn[d] = sh[d][0];
+            mx[d] = sh[3 + d][0];
+        }
+        double ext = 0.0;
+        for (int d = 0; d < 3; ++d) ext = fmax(ext, mx[d] - mn[d]);
+        double L = 1.0;
+        if (ext > 0.0) {
+            int e;
+            frexp(ext, &e);
+            L = ldexp(1.0, e - 1);
+        }
+        double lo[3];
+        for (;;) {
+            const double half = 0.5 * L;
+            bool ok = true;
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = floor(mn[d] / half) * half;
+                ok = ok && (mx[d] < lo[d] + L);
+            }
+            if (ok) break;
+            L *= 2.0;
+        }
+        for (int d = 0; d < 3; ++d) cube->lo[d] = lo[d];
+        cube->L = L;
+    }
+}
+
+// ------------------------------------------------------------------ 2. keys
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1fffffu;
+    x = (x | x << 32) & 0x001f00000000ffffull;
+    x = (x | x << 16) & 0x001f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+__device__ __forceinline__ uint32_t compact3(uint64_t x) {
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x ^ (x >> 8)) & 0x001f0000ff0000ffull;
+    x = (x ^ (x >> 16)) & 0x001f00000000ffffull;
+    x = (x ^ (x >> 32)) & 0x00000000001fffffull;
+    return (uint32_t)x;
+}
+__device__ __forceinline__ uint32_t quantise(double x, double lo, double scale) {
+    double t = __dmul_rn(__dsub_rn(x, lo), scale);
+    double f = floor(t);
+    f = f < 0.0 ? 0.0 : f;
+    f = f > 2097151.0 ? 2097151.0 : f;
+    return (uint32_t)f;
+}
+
+// Keys, and the counts of every 8-bit digit of every key (8 x 256 bins).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_keys(const T *__restrict__ pos, int n,
+                                                   const Cube *__restrict__ cube,
+                                                   uint64_t *__restrict__ keys,
+                                                   uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[8][256];
+    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const double lx = cube->lo[0], ly = cube->lo[1], lz = cube->lo[2];
+    const double scale = ldexp(1.0, kLevels) / cube->L;
+    const int stride = gridDim.x * blockDim.x;
+    const int iters = (n + stride - 1) / stride;
+    for (int it = 0; it < iters; ++it) {
+        const int i = it * stride + blockIdx.x * blockDim.x + threadIdx.x;
+        const bool valid = i < n;
+        uint64_t k = 0;
+        if (valid) {
+            const int64_t b = 3 * (int64_t)i;
+            k = (spread3(quantise((double)pos[b + 0], lx, scale)) << 2) |
+                (spread3(quantise((double)pos[b + 1], ly, scale)) << 1) |
+                spread3(quantise((double)pos[b + 2], lz, scale));
+            keys[i] = k;
+        }
+        const uint64_t live = ballot(valid);
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const uint32_t d = (uint32_t)(k >> (8 * p)) & 255u;
+            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+            const uint64_t same = ballot(valid && d == d0);
+            if (same == live) {  // whole wave on one bin: one add
+                if (rank_in(live) == 0 && valid) atomicAdd(&h[p][d0], (uint32_t)__popcll(live));
+            } else if (valid) {
+                atomicAdd(&h[p][d], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) {
+        const uint32_t v = (&h[0][0])[i];
+        if (v) atomicAdd(&hist[i], v);
+    }
+}
+
+// Exclusive scan of each pass's 256-bin histogram (8 blocks x 256 threads);
+// also clears the per-pass tile counters.
+__global__ __launch_bounds__(256) void k_hist_scan(const uint32_t *__restrict__ hist,
+                                                   uint32_t *__restrict__ off,
+                                                   uint32_t *__restrict__ tile_ctr) {
+    __shared__ uint32_t s[256];
+    const int p = blockIdx.x, t = threadIdx.x;
+    s[t] = hist[256 * p + t];
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        uint32_t v = t >= o ? s[t - o] : 0u;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    off[256 * p + t] = s[t] - hist[256 * p + t];
+    if (t == 0) tile_ctr[p] = 0;
+}
+
+// ------------------------------------------------------------------ 3. one radix pass
+// Status word per (tile, digit): epoch << 34 | flag << 32 | count,
+// flag 1 = tile aggregate only, 2 = inclusive prefix through this tile.
+__device__ __forceinline__ void st_status(unsigned long long *p, uint32_t epoch, uint32_t flag,
+                                          uint32_t cnt) {
+    unsigned long long v = ((unsigned long long)epoch << 34) |
+                           ((unsigned long long)flag << 32) | cnt;
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_pass(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, int n, int shift,
+    const uint32_t *__restrict__ digit_off, unsigned long long *__restrict__ status,
+    uint32_t *__restrict__ tile_ctr, uint32_t epoch) {
+    __shared__ uint32_t hist[kSortThreads / 64][256];
+    __shared__ uint32_t tstart[256];
+    __shared__ int32_t gbase[256];
+    __shared__ uint32_t wsum[kSortThreads / 64];
+    __shared__ uint64_t sk[kSortTile];
+    __shared__ uint32_t sv[kSortTile];
+    __shared__ uint32_t tile_s;
+
+    const int t = threadIdx.x;
+    if (t == 0) tile_s = atomicAdd(tile_ctr, 1u);
+    for (int i = t; i < (kSortThreads / 64) * 256; i += kSortThreads) (&hist[0][0])[i] = 0;
+    __syncthreads();
+    const int tile = (int)tile_s;
+    const int wave = t / 64;
+    const unsigned lane = lane_id();
+    const int64_t base = (int64_t)tile * kSortTile + wave * kWaveTile;
+
+    uint64_t key[kSortItems];
+    uint32_t val[kSortItems];
+    uint32_t rnk[kSortItems];
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t i = base + k * 64 + lane;
+        const bool valid = i < n;
+        key[k] = valid ? kin[i] : 0ull;
+        val[k] = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t i = base + k * 64 + lane;
+        const bool valid = i < n;
+        const uint32_t d = (uint32_t)(key[k] >> shift) & 255u;
+        uint64_t m = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = ballot(valid && bit);
+            m &= bit ? bal : ~bal;
+        }
+        const uint32_t r = rank_in(m);
+        uint32_t c = 0;
+        if (valid) c = hist[wave][d];
+        rnk[k] = c + r;
+        if (valid && r == 0) hist[wave][d] = c + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    // per digit: prefix over waves, tile total
+    uint32_t tot = 0;
+    for (int w = 0; w < kSortThreads / 64; ++w) {
+        const uint32_t c = hist[w][t];
+        hist[w][t] = tot;
+        tot += c;
+    }
+    // exclusive scan of tile totals over digits
+    uint32_t incl = tot;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o);
+        if ((int)lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    // look-back for digit t
+    unsigned long long *my = status + (size_t)tile * 256 + t;
+    st_status(my, epoch, tile == 0 ? 2u : 1u, tot);
+    uint32_t excl = 0;
+    if (tile > 0) {
+        int j = tile - 1;
+        for (;;) {
+            const unsigned long long v = __hip_atomic_load(status + (size_t)j * 256 + t,
+                                                           __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t ep = (uint32_t)(v >> 34), fl = (uint32_t)(v >> 32) & 3u;
+            if (ep != epoch || fl == 0) {
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            excl += (uint32_t)v;
+            if (fl == 2) break;
+            --j;
+        }
+        st_status(my, epoch, 2u, excl + tot);
+    }
+    __syncthreads();
+    uint32_t wpre = 0;
+    for (int w = 0; w < wave; ++w) wpre += wsum[w];
+    const uint32_t ts = wpre + incl - tot;
+    tstart[t] = ts;
+    gbase[t] = (int32_t)(digit_off[t] + excl) - (int32_t)ts;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t i = base + k * 64 + lane;
+        if (i < n) {
+            const uint32_t d = (uint32_t)(key[k] >> shift) & 255u;
+            const uint32_t p = tstart[d] + hist[wave][d] + rnk[k];
+            sk[p] = key[k];
+            sv[p] = val[k];
+        }
+    }
+    __syncthreads();
+    const int64_t t0 = (int64_t)tile * kSortTile;
+    const int tn = (int)(n - t0 < kSortTile ? n - t0 : kSortTile);
+    for (int p = t; p < tn; p += kSortThreads) {
+        const uint64_t kk = sk[p];
+        const uint32_t d = (uint32_t)(kk >> shift) & 255u;
+        const int o = gbase[d] + p;
+        kout[o] = kk;
+        vout[o] = sv[p];
+    }
+}
+
+// ------------------------------------------------------------------ 4. gather
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather(int n, uint32_t *__restrict__ flags,
+                                                     const uint32_t *__restrict__ perm,
+                                                     const T *__restrict__ pos,
+                                                     const T *__restrict__ mass,
+                                                     const T *__restrict__ vel,
+                                                     const uint32_t *__restrict__ id,
+                                                     T *__restrict__ spos, T *__restrict__ smass,
+                                                     T *__restrict__ svel,
+                                                     uint32_t *__restrict__ sid) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int64_t j = perm[r];
+    if (j >= n) {  // guard: a broken permutation is reported, not followed
+        atomicOr(flags, 2u);
+        j = 0;
+    }
+    spos[3 * (int64_t)r + 0] = pos[3 * j + 0];
+    spos[3 * (int64_t)r + 1] = pos[3 * j + 1];
+    spos[3 * (int64_t)r + 2] = pos[3 * j + 2];
+    smass[r] = mass[j];
+    if (svel) {
+        svel[3 * (int64_t)r + 0] = vel[3 * j + 0];
+        svel[3 * (int64_t)r + 1] = vel[3 * j + 1];
+        svel[3 * (int64_t)r + 2] = vel[3 * j + 2];
+    }
+    if (sid) sid[r] = id ? id[j] : (uint32_t)j;
+}
+
+// ------------------------------------------------------------------ 5. topology
+// delta[i] = number of leading octal digits shared by keys i-1 and i
+// (21 when equal); delta[0] = delta[n] = -1.
+__global__ __launch_bounds__(kThreads) void k_delta(const uint64_t *__restrict__ keys, int n,
+                                                    int8_t *__restrict__ delta) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    int d = -1;
+    if (i > 0 && i < n) {
+        const uint64_t x = keys[i - 1] ^ keys[i];
+        d = x ? (__clzll(x) - 1) / 3 : kLevels;
+    }
+    delta[i] = (int8_t)d;
+}
+
+// Chain length of every sorted rank s: the cells whose first body is s.
+// They are the levels delta[s]+1 .. k_leaf(s), present only if the
+// level-delta[s] cell around s holds more than B bodies (its parent is
+// split); k_leaf is the first level at which the cell starting at s holds
+// at most B bodies (or 21).  Also per-block sums for the scan.
+__global__ __launch_bounds__(kThreads) void k_chain(const int8_t *__restrict__ delta, int n,
+                                                    int B, uint8_t *__restrict__ ns,
+                                                    uint32_t *__restrict__ bsum) {
+    __shared__ int8_t sd[kThreads + 2 * (kMaxLeaf + 1) + 1];
+    __shared__ uint32_t ws[kThreads / 64];
+    const int H = B + 1;
+    const int b0 = blockIdx.x * kThreads;
+    // sd[k] = delta[b0 - H + k]
+    for (int k = threadIdx.x; k < kThreads + 2 * H + 1; k += kThreads) {
+        const int g = b0 - H + k;
+        sd[k] = (g >= 0 && g <= n) ? delta[g] : (int8_t)-1;
+    }
+    __syncthreads();
+    const int s = b0 + threadIdx.x;
+    uint32_t cnt_s = 0;
+    if (s < n) {
+        const int L = threadIdx.x + H;  // local index of s
+        const int ds = sd[L];
+        if (ds < kLevels) {
+            bool exists = (s == 0);
+            if (!exists) {
+                int cnt = 1;
+                int j = L;
+                while (cnt <= B && sd[j] >= ds) {  // delta[j] >= ds: rank j-1 inside
+                    ++cnt;
+                    --j;
+                }
+                j = L + 1;
+                while (cnt <= B && sd[j] >= ds) {  // delta[j] >= ds: rank j inside
+                    ++cnt;
+                    ++j;
+                }
+                exists = cnt > B;
+            }
+            if (exists) {
+                int mu = kLevels;
+                for (int j = 1; j <= B; ++j) {
+                    const int v = sd[L + j];
+                    mu = v < mu ? v : mu;
+                    if (s + j >= n) break;
+                }
+                int kl = ds + 1 > mu + 1 ? ds + 1 : mu + 1;
+                kl = kl > kLevels ? kLevels : kl;
+                cnt_s = (uint32_t)(kl - ds);
+            }
+        }
+        ns[s] = (uint8_t)cnt_s;
+    }
+    uint32_t v = cnt_s;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane_id() == 0) ws[threadIdx.x / 64] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tsum = 0;
+        for (int w = 0; w < kThreads / 64; ++w) tsum += ws[w];
+        bsum[blockIdx.x] = tsum;
+    }
+}
+
+// Exclusive scan of the per-block sums, in place (one block, any length).
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *__restrict__ s, int nb) {
+    __shared__ uint32_t carry;
+    __shared__ uint32_t ws[16];
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < nb; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const uint32_t x = i < nb ? s[i] : 0u;
+        uint32_t incl = x;
+        const unsigned lane = lane_id();
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o);
+            if ((int)lane >= o) incl += v;
+        }
+        const int w = threadIdx.x / 64;
+        if (lane == 63) ws[w] = incl;
+        __syncthreads();
+        uint32_t pre = carry;
+        for (int k = 0; k < w; ++k) pre += ws[k];
+        if (i < nb) s[i] = pre + incl - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = pre + incl;
+        __syncthreads();
+    }
+}
+
+// offs[s] = exclusive prefix of ns over ranks; offs[n] = node count.
+__global__ __launch_bounds__(kThreads) void k_scan_down(const uint8_t *__restrict__ ns, int n,
+                                                        const uint32_t *__restrict__ bpre,
+                                                        int32_t *__restrict__ offs) {
+    __shared__ uint32_t ws[kThreads / 64];
+    const int s = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t x = s < n ? ns[s] : 0u;
+    uint32_t incl = x;
+    const unsigned lane = lane_id();
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o);
+        if ((int)lane >= o) incl += v;
+    }
+    const int w = threadIdx.x / 64;
+    if (lane == 63) ws[w] = incl;
+    __syncthreads();
+    uint32_t pre = bpre[blockIdx.x];
+    for (int k = 0; k < w; ++k) pre += ws[k];
+    if (s < n) offs[s] = (int32_t)(pre + incl - x);
+    if (s == n - 1) offs[n] = (int32_t)(pre + incl);
+}
+
+// First rank in (s, hi) whose key prefix (key >> shift) differs from pre;
+// hi if none.  Galloping, then bisection.
+__device__ int seg_end(const uint64_t *__restrict__ keys, int s, int hi, int shift, uint64_t pre) {
+    int lo = s, step = 1, probe = s + 1;
+    while (probe < hi && (keys[probe] >> shift) == pre) {
+        lo = probe;
+        step <<= 1;
+        probe = s + step;
+    }
+    int r = probe < hi ? probe : hi;
+    while (r - lo > 1) {
+        const int mid = lo + ((r - lo) >> 1);
+        if ((keys[mid] >> shift) == pre) lo = mid;
+        else r = mid;
+    }
+    return r;
+}
+// First rank a <= s whose key prefix equals that of s.
+__device__ int seg_begin(const uint64_t *__restrict__ keys, int s, int shift, uint64_t pre) {
+    int hi = s, step = 1, probe = s - 1;
+    while (probe >= 0 && (keys[probe] >> shift) == pre) {
+        hi = probe;
+        step <<= 1;
+        probe = s - step;
+    }
+    int l = probe >= 0 ? probe : -1;  // keys[l] differs (or l = -1)
+    while (hi - l > 1) {
+        const int mid = l + ((hi - l) >> 1);
+        if ((keys[mid] >> shift) == pre) hi = mid;
+        else l = mid;
+    }
+    return hi;
+}
+
+// Writes every cell in pre-order: hashed key, level, body range, skip
+// pointer, parent, integer centre; counts children and their octants.
+__global__ __launch_bounds__(kThreads) void k_emit(
+    const uint64_t *__restrict__ keys, const int8_t *__restrict__ delta,
+    const uint8_t *__restrict__ ns, const int32_t *__restrict__ offs, int n, int m,
+    uint64_t *__restrict__ hkey, int32_t *__restrict__ level, int32_t *__restrict__ begin,
+    int32_t *__restrict__ count, int32_t *__restrict__ next, int32_t *__restrict__ parent,
+    int32_t *__restrict__ cx, int32_t *__restrict__ cy, int32_t *__restrict__ cz,
+    uint32_t *__restrict__ cmask, uint32_t *__restrict__ nchild, uint32_t *__restrict__ depth) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int cnt = ns[s];
+    if (cnt == 0) return;
+    const int ds = delta[s];
+    const uint64_t key = keys[s];
+    const uint32_t qx = compact3(key >> 2), qy = compact3(key >> 1), qz = compact3(key);
+    const int o = offs[s];
+    int par = -1;
+    if (s > 0) {
+        const int sh = 3 * (kLevels - ds);
+        const uint64_t pre = ds > 0 ? key >> sh : 0ull;
+        const int a = ds > 0 ? seg_begin(keys, s, sh, pre) : 0;
+        const int da = delta[a];
+        par = offs[a] + (ds - (da + 1));
+    }
+    int hi = n;
+    for (int t = 0; t < cnt; ++t) {
+        const int k = ds + 1 + t;
+        const int node = o + t;
+        const int sh = 3 * (kLevels - k);
+        const uint64_t pre = k > 0 ? key >> sh : 0ull;
+        const int e = k > 0 ? seg_end(keys, s, hi, sh, pre) : n;
+        hi = e;
+        hkey[node] = (1ull << (3 * k)) | pre;
+        level[node] = k;
+        begin[node] = s;
+        count[node] = e - s;
+        next[node] = offs[e];
+        const int p = t > 0 ? node - 1 : par;
+        parent[node] = p < m ? p : -1;  // guard
+        const int cs = kLevels - k;
+        cx[node] = (int32_t)(((qx >> cs) * 2u + 1u) << cs);
+        cy[node] = (int32_t)(((qy >> cs) * 2u + 1u) << cs);
+        cz[node] = (int32_t)(((qz >> cs) * 2u + 1u) << cs);
+        if (p >= 0 && p < m) {
+            atomicOr(&cmask[p], 1u << (uint32_t)(pre & 7u));
+            atomicAdd(&nchild[p], 1u);
+        }
+        if (t == cnt - 1) atomicMax(depth, (uint32_t)k);
+    }
+}
+
+// ------------------------------------------------------------------ 6. upward pass
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_upward(
+    int m, const int32_t *__restrict__ begin, const int32_t *__restrict__ count,
+    const int32_t *__restrict__ next, const int32_t *__restrict__ parent,
+    const uint32_t *__restrict__ nchild, uint32_t *arrive, const int32_t *__restrict__ cx,
+    const int32_t *__restrict__ cy, const int32_t *__restrict__ cz, const T *__restrict__ spos,
+    const T *__restrict__ smass, const Cube *__restrict__ cube, Moments *mom) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m || next[i] != i + 1) return;  // leaves start
+    const double h = ldexp(cube->L, -(kLevels + 1));
+    {
+        const double c0 = cube->lo[0] + cx[i] * h, c1 = cube->lo[1] + cy[i] * h,
+                     c2 = cube->lo[2] + cz[i] * h;
+        const int b = begin[i], e = b + count[i];
+        double mt = 0, s0 = 0, s1 = 0, s2 = 0;
+        for (int j = b; j < e; ++j) {
+            const double mj = (double)smass[j];
+            mt += mj;
+            s0 += mj * ((double)spos[3 * (int64_t)j + 0] - c0);
+            s1 += mj * ((double)spos[3 * (int64_t)j + 1] - c1);
+            s2 += mj * ((double)spos[3 * (int64_t)j + 2] - c2);
+        }
+        Moments r;
+        r.m = mt;
+        r.c[0] = mt > 0 ? s0 / mt : 0.0;
+        r.c[1] = mt > 0 ? s1 / mt : 0.0;
+        r.c[2] = mt > 0 ? s2 / mt : 0.0;
+        for (int a = 0; a < 6; ++a) r.t[a] = 0.0;
+        for (int j = b; j < e; ++j) {
+            const double mj = (double)smass[j];
+            const double y0 = (double)spos[3 * (int64_t)j + 0] - c0 - r.c[0];
+            const double y1 = (double)spos[3 * (int64_t)j + 1] - c1 - r.c[1];
+            const double y2 = (double)spos[3 * (int64_t)j + 2] - c2 - r.c[2];
+            r.t[0] += mj * y0 * y0;
+            r.t[1] += mj * y0 * y1;
+            r.t[2] += mj * y0 * y2;
+            r.t[3] += mj * y1 * y1;
+            r.t[4] += mj * y1 * y2;
+            r.t[5] += mj * y2 * y2;
+        }
+        mom[i] = r;
+    }
+    int node = i;
+    for (;;) {
+        const int p = parent[node];
+        if (p < 0 || p >= node) break;  // parents precede children in pre-order
+        const uint32_t old = __hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 != nchild[p]) break;  // a sibling finishes the parent
+        // all children done: combine them about the parent's centre
+        const int pcx = cx[p], pcy = cy[p], pcz = cz[p];
+        double mt = 0, s0 = 0, s1 = 0, s2 = 0;
+        const int pend = min(next[p], m);
+        for (int c = p + 1; c < pend; c = max(next[c], c + 1)) {
+            const Moments q = mom[c];
+            const double g0 = q.c[0] + (double)(cx[c] - pcx) * h;
+            const double g1 = q.c[1] + (double)(cy[c] - pcy) * h;
+            const double g2 = q.c[2] + (double)(cz[c] - pcz) * h;
+            mt += q.m;
+            s0 += q.m * g0;
+            s1 += q.m * g1;
+            s2 += q.m * g2;
+        }
+        Moments r;
+        r.m = mt;
+        r.c[0] = mt > 0 ? s0 / mt : 0.0;
+        r.c[1] = mt > 0 ? s1 / mt : 0.0;
+        r.c[2] = mt > 0 ? s2 / mt : 0.0;
+        for (int a = 0; a < 6; ++a) r.t[a] = 0.0;
+        for (int c = p + 1; c < pend; c = max(next[c], c + 1)) {
+            const Moments q = mom[c];
+            const double y0 = q.c[0] + (double)(cx[c] - pcx) * h - r.c[0];
+            const double y1 = q.c[1] + (double)(cy[c] - pcy) * h - r.c[1];
+            const double y2 = q.c[2] + (double)(cz[c] - pcz) * h - r.c[2];
+            r.t[0] += q.t[0] + q.m * y0 * y0;
+            r.t[1] += q.t[1] + q.m * y0 * y1;
+            r.t[2] += q.t[2] + q.m * y0 * y2;
+            r.t[3] += q.t[3] + q.m * y1 * y1;
+            r.t[4] += q.t[4] + q.m * y1 * y2;
+            r.t[5] += q.t[5] + q.m * y2 * y2;
+        }
+        mom[p] = r;
+        node = p;
+    }
+}
+
+// ------------------------------------------------------------------ 7. pack
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_pack_nodes(
+    int m, const int32_t *__restrict__ level, const int32_t *__restrict__ begin,
+    const int32_t *__restrict__ count, const int32_t *__restrict__ next,
+    const int32_t *__restrict__ cx, const int32_t *__restrict__ cy,
+    const int32_t *__restrict__ cz, const Moments *__restrict__ mom,
+    typename NodeRecT<R>::type *__restrict__ recs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const Moments q = mom[i];
+    const double tr = q.t[0] + q.t[3] + q.t[5];
+    typename NodeRecT<R>::type r{};
+    r.cx = cx[i];
+    r.cy = cy[i];
+    r.cz = cz[i];
+    r.mx = (R)q.c[0];
+    r.my = (R)q.c[1];
+    r.mz = (R)q.c[2];
+    r.m = (R)q.m;
+    r.qxx = (R)(3.0 * q.t[0] - tr);
+    r.qxy = (R)(3.0 * q.t[1]);
+    r.qxz = (R)(3.0 * q.t[2]);
+    r.qyy = (R)(3.0 * q.t[3] - tr);
+    r.qyz = (R)(3.0 * q.t[4]);
+    r.begin = begin[i];
+    r.count = count[i];
+    r.next = next[i];
+    r.level = level[i];
+    recs[i] = r;
+}
+
+// Bodies of every leaf: offset from the leaf centre (computed in FP64) and
+// mass; and the leaf centre as each body's integer anchor.
+template <typename T, typename R>
+__global__ __launch_bounds__(kThreads) void k_pack_bodies(
+    int m, const int32_t *__restrict__ begin, const int32_t *__restrict__ count,
+    const int32_t *__restrict__ next, const int32_t *__restrict__ cx,
+    const int32_t *__restrict__ cy, const int32_t *__restrict__ cz,
+    const T *__restrict__ spos, const T *__restrict__ smass, const Cube *__restrict__ cube,
+    BodyRec<R> *__restrict__ bodies, int4 *__restrict__ anchors) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m || next[i] != i + 1) return;
+    const double h = ldexp(cube->L, -(kLevels + 1));
+    const double c0 = cube->lo[0] + cx[i] * h, c1 = cube->lo[1] + cy[i] * h,
+                 c2 = cube->lo[2] + cz[i] * h;
+    const int b = begin[i], e = b + count[i];
+    const int4 an = make_int4(cx[i], cy[i], cz[i], i);
+    for (int j = b; j < e; ++j) {
+        BodyRec<R> br;
+        br.x = (R)((double)spos[3 * (int64_t)j + 0] - c0);
+        br.y = (R)((double)spos[3 * (int64_t)j + 1] - c1);
+        br.z = (R)((double)spos[3 * (int64_t)j + 2] - c2);
+        br.m = (R)smass[j];
+        bodies[j] = br;
+        anchors[j] = an;
+    }
+}
+
+template <typename T>
+int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int B,
+                const T *vel, const uint32_t *id, T *pos_out, T *vel_out, T *mass_out,
+                uint32_t *id_out) {
+    hipStream_t st = ctx->stream;
+    const int ntiles = div_up(n, kSortTile);
+    const int nb = div_up(n, kThreads);
+    const int nbbox = nb < 1024 ? nb : 1024;
+    const int nkeys = nb < 2048 ? nb : 2048;
+    int rc;
+    // ---- allocations sized by n
+    if ((rc = grow(t->keys_a, 8ull * n)) || (rc = grow(t->keys_b, 8ull * n)) ||
+        (rc = grow(t->idx_a, 4ull * n)) || (rc = grow(t->idx_b, 4ull * n)) ||
+        (rc = grow(t->delta, (size_t)n + 1)) || (rc = grow(t->nstart, (size_t)n)) ||
+        (rc = grow(t->offs, 4ull * (n + 1))) || (rc = grow(t->cube, sizeof(Cube))) ||
+        (rc = grow(t->part, 6ull * 8 * nbbox)) || (rc = grow(t->hist, 4ull * 256 * 8 * 2)) ||
+        (rc = grow(t->misc, 64 + 4ull * (nb + 1))) ||
+        (rc = grow(t->status, 8ull * 256 * ntiles)) ||
+        (rc = grow(t->bodies, sizeof(BodyRec<T>) * (size_t)n)) ||
+        (rc = grow(t->anchors, 16ull * n)))
+        return rc;
+    if (!pos_out) {
+        if ((rc = grow(t->spos, 3 * sizeof(T) * (size_t)n)) ||
+            (rc = grow(t->smass, sizeof(T) * (size_t)n)))
+            return rc;
+        pos_out = (T *)t->spos.p;
+        mass_out = (T *)t->smass.p;
+    }
+    Cube *cube = (Cube *)t->cube.p;
+    uint32_t *misc = (uint32_t *)t->misc.p;  // [0] flags, [1] depth, [8..15] tile ctr
+    uint32_t *flags = misc, *depth = misc + 1, *tile_ctr = misc + 8;
+    uint32_t *bsum = misc + 16;
+    uint32_t *hist = (uint32_t *)t->hist.p, *doff = hist + 2048;
+
+    k_fill_u32<<<1, 64, 0, st>>>(misc, 16, 0u);
+    k_fill_u32<<<8, 256, 0, st>>>(hist, 2048, 0u);
+    k_bbox<T><<<nbbox, kThreads, 0, st>>>(pos, n, (double *)t->part.p, flags);
+    k_cube<<<1, kThreads, 0, st>>>((const double *)t->part.p, nbbox, cube);
+    k_keys<T><<<nkeys, kThreads, 0, st>>>(pos, n, cube, (uint64_t *)t->keys_a.p, hist);
+    k_hist_scan<<<8, 256, 0, st>>>(hist, doff, tile_ctr);
+    uint64_t *ka = (uint64_t *)t->keys_a.p, *kb = (uint64_t *)t->keys_b.p;
+    uint32_t *va = nullptr, *vb = (uint32_t *)t->idx_b.p, *vspare = (uint32_t *)t->idx_a.p;
+    for (int p = 0; p < 8; ++p) {
+        const uint32_t ep = ++ctx->epoch;
+        k_sort_pass<<<ntiles, kSortThreads, 0, st>>>(ka, va, kb, vb, n, 8 * p, doff + 256 * p,
+                                                     (unsigned long long *)t->status.p,
+                                                     tile_ctr + p, ep & 0x3fffffffu);
+        uint64_t *tk = ka;
+        ka = kb;
+        kb = tk;
+        uint32_t *tv = va ? va : vspare;
+        va = vb;
+        vb = tv;
+    }
+    t->sorted_keys = ka;
+    t->perm = va;
+    if ((rc = check_launch("sort"))) return rc;
+    k_gather<T><<<nb, kThreads, 0, st>>>(n, flags, va, pos, mass, vel, id, pos_out, mass_out, vel_out,
+                                         id_out);
+    // ---- topology
+    int8_t *delta = (int8_t *)t->delta.p;
+    uint8_t *ns = (uint8_t *)t->nstart.p;
+    int32_t *offs = (int32_t *)t->offs.p;
+    k_delta<<<div_up(n + 1, kThreads), kThreads, 0, st>>>(ka, n, delta);
+    k_chain<<<nb, kThreads, 0, st>>>(delta, n, B, ns, bsum);
+    k_scan_sums<<<1, 1024, 0, st>>>(bsum, nb);
+    k_scan_down<<<nb, kThreads, 0, st>>>(ns, n, bsum, offs);
+    if ((rc = check_launch("topology"))) return rc;
+    uint32_t *hp = (uint32_t *)ctx->pinned;
+    if (hipMemcpyAsync(hp, offs + n, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(hp + 1, flags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(hp + 16, cube, sizeof(Cube), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return set_error(BH_E_DEVICE, "build: device failure while sizing the tree");
+    if (hp[1] & 1u) return set_error(BH_E_NONFINITE, "bh_build: non-finite position");
+    if (hp[1] & 2u) return set_error(BH_E_DEVICE, "bh_build: internal error (sort permutation)");
+    const Cube hc = *(const Cube *)(hp + 16);
+    for (int d = 0; d < 3; ++d) t->lo[d] = hc.lo[d];
+    t->L = hc.L;
+    const int m = (int)hp[0];
+    t->m = m;
+    // ---- node allocations
+    if ((rc = grow(t->hkey, 8ull * m)) || (rc = grow(t->level, 4ull * m)) ||
+        (rc = grow(t->begin, 4ull * m)) || (rc = grow(t->count, 4ull * m)) ||
+        (rc = grow(t->next, 4ull * m)) || (rc = grow(t->parent, 4ull * m)) ||
+        (rc = grow(t->cmask, 4ull * m)) || (rc = grow(t->nchild, 4ull * m)) ||
+        (rc = grow(t->arrive, 4ull * m)) || (rc = grow(t->cx, 4ull * m)) ||
+        (rc = grow(t->cy, 4ull * m)) || (rc = grow(t->cz, 4ull * m)) ||
+        (rc = grow(t->mom, sizeof(Moments) * (size_t)m)) ||
+        (rc = grow(t->recs, sizeof(typename NodeRecT<T>::type) * (size_t)m)))
+        return rc;
+    const int nbm = div_up(m, kThreads);
+    const int nfill = nbm < 4096 ? nbm : 4096;
+    k_fill_u32<<<nfill, kThreads, 0, st>>>((uint32_t *)t->cmask.p, m, 0u);
+    k_fill_u32<<<nfill, kThreads, 0, st>>>((uint32_t *)t->nchild.p, m, 0u);
+    k_fill_u32<<<nfill, kThreads, 0, st>>>((uint32_t *)t->arrive.p, m, 0u);
+    k_emit<<<nb, kThreads, 0, st>>>(ka, delta, ns, offs, n, m, (uint64_t *)t->hkey.p,
+                                    (int32_t *)t->level.p, (int32_t *)t->begin.p,
+                                    (int32_t *)t->count.p, (int32_t *)t->next.p,
+                                    (int32_t *)t->parent.p, (int32_t *)t->cx.p,
+                                    (int32_t *)t->cy.p, (int32_t *)t->cz.p,
+                                    (uint32_t *)t->cmask.p, (uint32_t *)t->nchild.p, depth);
+    k_upward<T><<<nbm, kThreads, 0, st>>>(
+        m, (const int32_t *)t->begin.p, (const int32_t *)t->count.p, (const int32_t *)t->next.p,
+        (const int32_t *)t->parent.p, (const uint32_t *)t->nchild.p, (uint32_t *)t->arrive.p,
+        (const int32_t *)t->cx.p, (const int32_t *)t->cy.p, (const int32_t *)t->cz.p, pos_out,
+        mass_out, cube, (Moments *)t->mom.p);
+    k_pack_nodes<T><<<nbm, kThreads, 0, st>>>(
+        m, (const int32_t *)t->level.p, (const int32_t *)t->begin.p,
+        (const int32_t *)t->count.p, (const int32_t *)t->next.p, (const int32_t *)t->cx.p,
+        (const int32_t *)t->cy.p, (const int32_t *)t->cz.p, (const Moments *)t->mom.p,
+        (typename NodeRecT<T>::type *)t->recs.p);
+    k_pack_bodies<T, T><<<nbm, kThreads, 0, st>>>(
+        m, (const int32_t *)t->begin.p, (const int32_t *)t->count.p,
+        (const int32_t *)t->next.p, (const int32_t *)t->cx.p, (const int32_t *)t->cy.p,
+        (const int32_t *)t->cz.p, pos_out, mass_out, cube, (BodyRec<T> *)t->bodies.p,
+        (int4 *)t->anchors.p);
+    return check_launch("tree");
+}
+
+}  // namespace
+
+int build_tree(bh_ctx *ctx, bh_tree *t, const void *pos, const void *mass, int dtype,
+               int64_t n, int leaf, const void *vel, const uint32_t *id, void *pos_out,
+               void *vel_out, void *mass_out, uint32_t *id_out) {
+    t->dtype = dtype;
+    t->n = n;
+    t->leaf = leaf;
+    int rc;
+    if (dtype == BH_F32)
+        rc = build_typed<float>(ctx, t, (const float *)pos, (const float *)mass, (int)n, leaf,
+                                (const float *)vel, id, (float *)pos_out, (float *)vel_out,
+                                (float *)mass_out, id_out);
+    else
+        rc = build_typed<double>(ctx, t, (const double *)pos, (const double *)mass, (int)n,
+                                 leaf, (const double *)vel, id, (double *)pos_out,
+                                 (double *)vel_out, (double *)mass_out, id_out);
+    return rc;
+}
+
+}  // namespace bh

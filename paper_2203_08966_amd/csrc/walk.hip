@@ -1,0 +1,233 @@
+// Per-body tree walk on gfx950 (Sec. 3, "Compute Cell Force").
+//
+// One wavefront walks 64 consecutive bodies in key order.  The nodes are in
+// pre-order with a skip pointer `next` (first node after the subtree), so the
+// union of the 64 recursive walks is one forward sweep over the node array:
+//
+//   every lane keeps `resume`, the next node index it needs; a lane is
+//   active at node idx when resume <= idx.  An active lane takes its own
+//   decision for the node exactly as the recursive walk would (one-body cell
+//   -> particle-particle; side^2 < theta^2 d^2 -> particle-cell; leaf ->
+//   particle-particle with its bodies; else open).  A lane that opens the
+//   node resumes at idx + 1 (its first child); any other active lane resumes
+//   at next[idx].  The wave moves to idx + 1 if any lane opened, else to
+//   next[idx]; that is always the smallest resume point of the wave.
+//
+// Each lane therefore sees exactly its own accepted cells and bodies, in
+// pre-order, with no stack, and its arithmetic does not depend on which
+// other bodies share its wave.  The node index is wave-uniform, so node
+// records and leaf bodies are read with scalar loads and broadcast.
+//
+// Positions are relative to cell centres: a body is stored as the integer
+// centre of its leaf (units of L 2^-22) plus a small offset; its position
+// relative to any cell centre is an exact integer difference, scaled by a
+// power of two, plus that offset.
+#include "bh_internal.h"
+
+namespace bh {
+namespace {
+
+__device__ __forceinline__ unsigned lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
+template <typename R> __device__ __forceinline__ R ldexp_r(R x, int e);
+template <> __device__ __forceinline__ float ldexp_r<float>(float x, int e) { return ldexpf(x, e); }
+template <> __device__ __forceinline__ double ldexp_r<double>(double x, int e) { return ldexp(x, e); }
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+enum : int { kNone = 0, kPP = 1, kPC = 2, kOpen = 3 };
+
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT>
+__global__ __launch_bounds__(256) void k_walk(
+    const typename NodeRecT<R>::type *__restrict__ nodes, int m,
+    const BodyRec<R> *__restrict__ bodies, const int4 *__restrict__ anchors,
+    const uint32_t *__restrict__ perm, int nbodies, int t0, int t1, int nwaves_padded, R h,
+    R mac_l2,
+    R eps2, R *__restrict__ acc, R *__restrict__ phi_out, uint32_t *__restrict__ npp_out,
+    uint32_t *__restrict__ npc_out) {
+    using Rec = typename NodeRecT<R>::type;
+    // XCD-aware placement: consecutive workgroups land on different XCDs,
+    // so hand each XCD a contiguous run of 8 logical blocks (spatially
+    // close waves then share that XCD's L2).
+    const int nblk = nwaves_padded / 4;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, r = b >> 3;
+    const int lb = (r >> 3) * 64 + xcd * 8 + (r & 7);
+    if (lb >= nblk) return;
+    const int wave = lb * 4 + (int)(threadIdx.x >> 6);
+    const int base = t0 + wave * 64;
+    if (base >= t1) return;
+    const int i = base + (int)lane_id();
+    const bool live = i < t1;
+
+    R ox = 0, oy = 0, oz = 0;
+    int ax = 0, ay = 0, az = 0;
+    if (live) {
+        const BodyRec<R> me = bodies[i];
+        ox = me.x;
+        oy = me.y;
+        oz = me.z;
+        const int4 an = anchors[i];
+        ax = an.x;
+        ay = an.y;
+        az = an.z;
+    }
+    R sx = 0, sy = 0, sz = 0, sp = 0;
+    uint32_t cpp = 0, cpc = 0;
+
+    const bool root_leaf = nodes[0].next == 1;
+    int idx = root_leaf ? 0 : 1;
+    int resume = live ? idx : 0x7fffffff;
+
+    while (idx < m) {
+        idx = uniform(idx);
+        const Rec nd = nodes[idx];
+        const bool act = resume <= idx;
+        // position relative to the cell centre
+        const R X = (R)(ax - nd.cx) * h + ox;
+        const R Y = (R)(ay - nd.cy) * h + oy;
+        const R Z = (R)(az - nd.cz) * h + oz;
+        const R x = X - nd.mx, y = Y - nd.my, z = Z - nd.mz;
+        const R d2 = x * x + y * y + z * z;
+        const bool leaf = nd.next == idx + 1;
+        int kind = kNone;
+        if (act) {
+            if (nd.count == 1 || idx == 0) kind = kPP;
+            else if (ldexp_r<R>(mac_l2, -2 * nd.level) < d2) kind = kPC;
+            else if (leaf) kind = kPP;
+            else kind = kOpen;
+        }
+        const uint64_t any_open = __ballot(kind == kOpen);
+        if (__ballot(kind == kPC)) {
+            if (kind == kPC) {
+                const R r2 = d2 + eps2;
+                const R inv = rsq(r2);
+                const R inv2 = inv * inv;
+                const R inv3 = inv * inv2;
+                const R mi3 = nd.m * inv3;
+                R fx = -mi3 * x, fy = -mi3 * y, fz = -mi3 * z;
+                R fp = -nd.m * inv;
+                if (ORDER2) {
+                    const R qzz = -nd.qxx - nd.qyy;
+                    const R qx = nd.qxx * x + nd.qxy * y + nd.qxz * z;
+                    const R qy = nd.qxy * x + nd.qyy * y + nd.qyz * z;
+                    const R qz = nd.qxz * x + nd.qyz * y + qzz * z;
+                    const R xqx = x * qx + y * qy + z * qz;
+                    const R inv5 = inv3 * inv2;
+                    const R c7 = (R)2.5 * xqx * inv5 * inv2;
+                    fx += qx * inv5 - c7 * x;
+                    fy += qy * inv5 - c7 * y;
+                    fz += qz * inv5 - c7 * z;
+                    fp -= (R)0.5 * xqx * inv5;
+                }
+                sx += fx;
+                sy += fy;
+                sz += fz;
+                if (PHI) sp += fp;
+                if (CNT) ++cpc;
+            }
+        }
+        if (__ballot(kind == kPP)) {
+            const int jb = uniform(nd.begin);
+            const int je = min(jb + uniform(nd.count), nbodies);  // guard
+            R px = 0, py = 0, pz = 0, pp = 0;
+            uint32_t np = 0;
+            for (int j = jb; j < je; ++j) {
+                const BodyRec<R> s = bodies[j];
+                if (kind == kPP && j != i) {
+                    const R dx = s.x - X, dy = s.y - Y, dz = s.z - Z;
+                    const R r2 = dx * dx + dy * dy + dz * dz + eps2;
+                    const R inv = rsq(r2);
+                    const R mi3 = s.m * inv * inv * inv;
+                    px += mi3 * dx;
+                    py += mi3 * dy;
+                    pz += mi3 * dz;
+                    if (PHI) pp -= s.m * inv;
+                    if (CNT) ++np;
+                }
+            }
+            sx += px;
+            sy += py;
+            sz += pz;
+            if (PHI) sp += pp;
+            if (CNT) cpp += np;
+        }
+        if (kind == kOpen) resume = idx + 1;
+        else if (act) resume = nd.next;
+        const int nx = any_open ? idx + 1 : nd.next;
+        idx = nx > idx ? nx : idx + 1;  // always moves forward
+    }
+    if (live) {
+        const int o = SORTED_OUT ? i : (int)perm[i];
+        acc[3 * (int64_t)o + 0] = sx;
+        acc[3 * (int64_t)o + 1] = sy;
+        acc[3 * (int64_t)o + 2] = sz;
+        if (PHI) phi_out[o] = sp;
+        if (CNT) {
+            npp_out[o] = cpp;
+            npc_out[o] = cpc;
+        }
+    }
+}
+
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED>
+void launch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
+            uint32_t *npp, uint32_t *npc) {
+    const int nw = div_up(t1 - t0, 64);
+    const int nblk = div_up(nw, 4);
+    const int nblk_pad = div_up(nblk, 64) * 64;
+    const R h = (R)ldexp(t->L, -(kLevels + 1));
+    const double l2 = theta > 0 ? (t->L * t->L) / (theta * theta) : HUGE_VAL;
+    k_walk<R, ORDER2, PHI, CNT, SORTED><<<nblk_pad, 256, 0, t->ctx->stream>>>(
+        (const typename NodeRecT<R>::type *)t->recs.p, (int)t->m,
+        (const BodyRec<R> *)t->bodies.p, (const int4 *)t->anchors.p, t->perm, (int)t->n, t0, t1,
+        nblk_pad * 4, h, (R)l2, (R)(eps * eps), (R *)acc, (R *)phi, npp, npc);
+}
+
+template <typename R, bool ORDER2>
+void dispatch2(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
+               uint32_t *npp, uint32_t *npc, bool sorted) {
+    const bool P = phi != nullptr, C = npp != nullptr;
+#define BH_W(p, c, s) launch<R, ORDER2, p, c, s>(t, t0, t1, theta, eps, acc, phi, npp, npc)
+    if (sorted) {
+        if (P) BH_W(true, false, true);
+        else BH_W(false, false, true);
+    } else if (P && C) BH_W(true, true, false);
+    else if (P) BH_W(true, false, false);
+    else if (C) BH_W(false, true, false);
+    else BH_W(false, false, false);
+#undef BH_W
+}
+
+}  // namespace
+
+int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_t *npp,
+             uint32_t *npc, const bh_force_opts &o, bool sorted_out) {
+    int t0 = 0, t1 = (int)t->n;
+    if (o.target_end > 0) {
+        t0 = (int)o.target_begin;
+        t1 = (int)o.target_end;
+    }
+    if (t1 <= t0) return BH_OK;
+    if ((npp != nullptr) != (npc != nullptr)) {  // the kernel writes both or neither
+        int rc = grow(t->cnt_scratch, 4ull * t->n);
+        if (rc) return rc;
+        if (!npp) npp = (uint32_t *)t->cnt_scratch.p;
+        else npc = (uint32_t *)t->cnt_scratch.p;
+    }
+    if (t->dtype == BH_F32) {
+        if (o.order == 0) dispatch2<float, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out);
+        else dispatch2<float, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out);
+    } else {
+        if (o.order == 0) dispatch2<double, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out);
+        else dispatch2<double, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out);
+    }
+    return check_launch("walk");
+}
+
+}  // namespace bh

@@ -19,3 +19,47 @@ def _oracle_built():
     import oracle
     oracle.build(force=False)
     yield
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    """One library context on cuda:0 for the GPU tests (the default stream)."""
+    import torch
+    from paper_2203_08966_amd import binding as B
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.load()
+    c = B.bh_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+    B.bh_ctx_destroy(c)
+
+
+def case_bodies(kind, n, seed, dtype):
+    """Seeded bodies as numpy arrays of `dtype` (the same values feed both the
+    GPU and, promoted exactly to float64, the oracle)."""
+    import numpy as np
+    from paper_2203_08966_amd import workloads as W
+    if kind == "plummer":
+        b = W.plummer(n, seed)
+    elif kind == "two_spheres":
+        b = W.two_spheres(n, seed)
+    elif kind == "clumpy":
+        b = W.clumpy(n, seed, n_clumps=max(1, n // 1000))
+    elif kind == "coincident":
+        rng = np.random.default_rng(seed)
+        base = rng.normal(size=(-(-n // 7), 3))
+        pos = np.repeat(base, 7, axis=0)[:n]
+        b = W.Bodies(pos, np.zeros_like(pos), rng.random(n) + 0.1)
+    elif kind == "tiny_cluster":
+        rng = np.random.default_rng(seed)
+        pos = rng.normal(size=(n, 3)) * 1e-5 + np.array([3.0, -1.0, 0.5])
+        b = W.Bodies(pos, np.zeros_like(pos), np.full(n, 1.0 / n))
+    else:
+        raise ValueError(kind)
+    return (np.ascontiguousarray(b.pos, dtype=dtype), np.ascontiguousarray(b.vel, dtype=dtype),
+            np.ascontiguousarray(b.mass, dtype=dtype))
+
+
+def say(*a):
+    print(*a, flush=True)

@@ -1,0 +1,118 @@
+"""GPU tree construction against the oracle: keys, permutation and every
+node array bit for bit; FP64 moments to rounding (Sec. 3 build step,
+Sec. 4.4 keys, Sec. 4.2 pre-order, Sec. 4.7 hashed keys)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2203_08966_amd import binding as B
+from tests.conftest import GOLDEN, case_bodies, say
+
+pytestmark = pytest.mark.gpu
+
+NODE_FIELDS = ["hkey", "level", "begin", "count", "next", "parent", "cmask"]
+
+
+def gpu_tree(ctx, pos, mass, leaf):
+    p = torch.from_numpy(pos).cuda()
+    m = torch.from_numpy(mass).cuda()
+    t = B.bh_build(ctx, p, m, leaf)
+    ex = B.bh_tree_export(t)
+    return t, ex
+
+
+def check_tree(ex, ref, leaf):
+    assert ex["side"] == ref["L"]
+    np.testing.assert_array_equal(ex["lo"], ref["lo"])
+    np.testing.assert_array_equal(ex["keys"], ref["keys"])
+    np.testing.assert_array_equal(ex["perm"].astype(np.int64), ref["perm"])
+    t = ref["tree"]
+    assert ex["m"] == len(t["hkey"])
+    for f in NODE_FIELDS:
+        np.testing.assert_array_equal(ex[f].astype(t[f].dtype), t[f], err_msg=f)
+    M, com, Q = ref["mom"]
+    side = ref["L"] * 2.0 ** -t["level"].astype(float)
+    np.testing.assert_allclose(ex["mass"], M, rtol=1e-12, atol=0)
+    scale = np.maximum(side, 1e-300)
+    # the oracle averages absolute coordinates: its own FP64 rounding is a
+    # few ulp of |com|, independent of the cell size
+    assert np.all(np.abs(ex["com"] - com) <= 1e-12 * scale[:, None] + 1e-13 * np.abs(com))
+    qs = np.maximum(M * side * side, 1e-300)
+    assert np.all(np.abs(ex["quad"] - Q) <= 1e-10 * qs[:, None])
+
+
+CASES = [
+    ("plummer", 4096, 1, 8, np.float64),
+    ("plummer", 4096, 1, 8, np.float32),
+    ("plummer", 4097, 11, 1, np.float32),
+    ("plummer", 12345, 12, 256, np.float64),
+    ("two_spheres", 30000, 3, 16, np.float32),
+    ("clumpy", 50000, 5, 16, np.float32),
+    ("coincident", 3000, 6, 4, np.float64),
+    ("tiny_cluster", 5000, 7, 16, np.float32),
+    ("plummer", 1, 1, 8, np.float32),
+    ("plummer", 2, 1, 1, np.float64),
+    ("plummer", 63, 2, 8, np.float32),
+    ("plummer", 8191, 3, 16, np.float32),
+]
+
+
+@pytest.mark.parametrize("kind,n,seed,leaf,dtype", CASES)
+def test_build_matches_oracle(ctx, kind, n, seed, leaf, dtype):
+    say(f"build parity: {kind} n={n} seed={seed} leaf={leaf} dtype={dtype.__name__}")
+    pos, _, mass = case_bodies(kind, n, seed, dtype)
+    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), leaf)
+    t, ex = gpu_tree(ctx, pos, mass, leaf)
+    try:
+        check_tree(ex, ref, leaf)
+    finally:
+        B.bh_tree_free(t)
+
+
+def test_quadtree_figure(ctx):
+    with open(os.path.join(GOLDEN, "quadtree21.json")) as f:
+        g = json.load(f)
+    pts = np.array(g["points_in_morton_order"])
+    pos = np.column_stack([pts, np.full(len(pts), 0.5)])[::-1].copy()
+    say("build parity: 21-point quadtree figure, leaf 1")
+    t, ex = gpu_tree(ctx, pos, np.ones(len(pts)), 1)
+    try:
+        assert list(np.bincount(ex["level"])) == g["nodes_per_level"]
+        np.testing.assert_array_equal(ex["perm"], np.arange(len(pts))[::-1])
+        ref = oracle.build_all(pos, np.ones(len(pts)), 1)
+        check_tree(ex, ref, 1)
+    finally:
+        B.bh_tree_free(t)
+
+
+def test_rebuild_reuses_tree_and_is_deterministic(ctx):
+    pos, _, mass = case_bodies("plummer", 20000, 4, np.float32)
+    p = torch.from_numpy(pos).cuda()
+    m = torch.from_numpy(mass).cuda()
+    say("rebuild into the same tree twice, then a smaller input")
+    t = B.bh_build(ctx, p, m, 16)
+    a = B.bh_tree_export(t)
+    t2 = B.bh_build(ctx, p, m, 16, tree=t)
+    assert t2.value == t.value
+    b = B.bh_tree_export(t)
+    for f in ["keys", "perm"] + NODE_FIELDS + ["mass", "com", "quad"]:
+        np.testing.assert_array_equal(a[f], b[f])
+    small_pos, _, small_mass = case_bodies("plummer", 3000, 9, np.float32)
+    B.bh_build(ctx, torch.from_numpy(small_pos).cuda(), torch.from_numpy(small_mass).cuda(), 8, tree=t)
+    c = B.bh_tree_export(t)
+    ref = oracle.build_all(small_pos.astype(np.float64), small_mass.astype(np.float64), 8)
+    check_tree(c, ref, 8)
+    B.bh_tree_free(t)
+
+
+def test_nonfinite_position_rejected(ctx):
+    pos, _, mass = case_bodies("plummer", 1000, 1, np.float32)
+    pos[123, 1] = np.nan
+    say("non-finite input -> BH_E_NONFINITE")
+    with pytest.raises(B.BHError) as e:
+        B.bh_build(ctx, torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda(), 8)
+    assert e.value.code == B.BH_E_NONFINITE

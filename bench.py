@@ -57,7 +57,21 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="bodies the CPU oracle walks (the tree is built in full)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (to scale "
+                         "the profiler's FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib: int):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "reps": 3}))
 
 
 def main():
@@ -73,6 +87,9 @@ def main():
     from paper_2203_08966_amd import binding as B
     from paper_2203_08966_amd import workloads as W
 
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if not torch.cuda.is_available():
         log("bench.py needs a GPU")
         sys.exit(1)

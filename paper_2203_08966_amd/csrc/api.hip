@@ -61,7 +61,7 @@ static void free_tree_bufs(bh_tree *t) {
     DevBuf *all[] = {&t->keys_a, &t->keys_b, &t->idx_a, &t->idx_b, &t->spos, &t->smass,
                      &t->bodies, &t->anchors, &t->delta, &t->nstart, &t->offs, &t->hkey,
                      &t->level, &t->begin, &t->count, &t->next, &t->parent, &t->cmask,
-                     &t->nchild, &t->arrive, &t->cx, &t->cy, &t->cz, &t->mom, &t->recs,
+                     &t->lvl_list, &t->cx, &t->cy, &t->cz, &t->mom, &t->recs,
                      &t->cube, &t->part, &t->hist, &t->status, &t->misc, &t->cnt_scratch};
     for (DevBuf *b : all) free_buf(*b);
 }
@@ -247,14 +247,10 @@ int bh_forces(bh_tree *t, double theta, double eps, void *acc, const bh_force_op
 int bh_tree_info_get(const bh_tree *t, bh_tree_info *info) {
     if (!t || !info) return set_error(BH_E_INVALID, "null tree or info");
     if (use_device(t->ctx)) return BH_E_DEVICE;
-    uint32_t depth = 0;
-    if (hipStreamSynchronize(t->ctx->stream) != hipSuccess ||
-        hipMemcpy(&depth, (uint32_t *)t->misc.p + 1, 4, hipMemcpyDeviceToHost) != hipSuccess)
-        return set_error(BH_E_DEVICE, "tree info copy failed");
     memset(info, 0, sizeof(*info));
     info->n = t->n;
     info->m = t->m;
-    info->depth = (int32_t)depth;
+    info->depth = (int32_t)t->depth;
     info->dtype = t->dtype;
     info->leaf_size = t->leaf;
     for (int d = 0; d < 3; ++d) info->lo[d] = t->lo[d];

@@ -32,22 +32,27 @@ struct Moments {
 };
 
 // Walk record of one cell, FP32: 64 bytes, read with uniform (scalar) loads.
-// Integer centre in units of L * 2^-22 (exact for every level); COM and
-// quadrupole relative to that centre; traceless quadrupole as 5 components.
+// Centre as (integer centre in units of h = L 2^-22) * h, relative to the
+// root corner: an integer below 2^23 times a power of two, so exact in FP32,
+// and the difference of two such centres is exact too.  COM and quadrupole
+// relative to that centre; traceless quadrupole as 5 components.
 struct alignas(64) NodeRec32 {
-    int cx, cy, cz;
+    float cx, cy, cz;
     float mx, my, mz;
     float m;
     float qxx, qxy, qxz, qyy, qyz;
-    int begin, count, next, level;
+    int begin, count, next;
+    float l2;  // side^2
 };
 
 // FP64 walk record (128 bytes).
 struct alignas(128) NodeRec64 {
-    int cx, cy, cz, level;
+    double cx, cy, cz;
+    int level, pad2;
     int begin, count, next, pad0;
     double mx, my, mz, m;
-    double qxx, qxy, qxz, qyy, qyz, pad1;
+    double qxx, qxy, qxz, qyy, qyz;
+    double l2;  // side^2
 };
 
 template <typename R> struct NodeRecT;
@@ -57,6 +62,13 @@ template <> struct NodeRecT<double> { using type = NodeRec64; };
 // Body record for the walk: offset from its leaf's centre and mass.
 template <typename R> struct alignas(4 * sizeof(R)) BodyRec {
     R x, y, z, m;
+};
+
+// A body's anchor: its leaf's centre, scaled like NodeRec centres, and the
+// leaf's node index.
+template <typename R> struct alignas(4 * sizeof(R)) Anchor {
+    R x, y, z;
+    int leaf;
 };
 
 // Grow-only device buffer.
@@ -101,7 +113,7 @@ struct bh_tree {
     bh::DevBuf bodies, anchors;                // walk body records, leaf centres
     bh::DevBuf delta, nstart, offs;            // topology scratch
     // node-indexed
-    bh::DevBuf hkey, level, begin, count, next, parent, cmask, nchild, arrive;
+    bh::DevBuf hkey, level, begin, count, next, parent, cmask, lvl_list;
     bh::DevBuf cx, cy, cz;
     bh::DevBuf mom, recs;
     // small scratch

@@ -412,13 +412,16 @@ __global__ __launch_bounds__(kThreads) void k_delta(const uint64_t *__restrict__
 // They are the levels delta[s]+1 .. k_leaf(s), present only if the
 // level-delta[s] cell around s holds more than B bodies (its parent is
 // split); k_leaf is the first level at which the cell starting at s holds
-// at most B bodies (or 21).  Also per-block sums for the scan.
+// at most B bodies (or 21).  Also, per block, the sum of chain lengths and
+// the number of cells at every level: bsum[b] and bsum[(1 + k) * nb + b].
 __global__ __launch_bounds__(kThreads) void k_chain(const int8_t *__restrict__ delta, int n,
                                                     int B, uint8_t *__restrict__ ns,
                                                     uint32_t *__restrict__ bsum) {
     __shared__ int8_t sd[kThreads + 2 * (kMaxLeaf + 1) + 1];
     __shared__ uint32_t ws[kThreads / 64];
+    __shared__ uint32_t lh[kLevels + 1];
     const int H = B + 1;
+    if (threadIdx.x <= kLevels) lh[threadIdx.x] = 0;
     const int b0 = blockIdx.x * kThreads;
     // sd[k] = delta[b0 - H + k]
     for (int k = threadIdx.x; k < kThreads + 2 * H + 1; k += kThreads) {
@@ -457,6 +460,7 @@ __global__ __launch_bounds__(kThreads) void k_chain(const int8_t *__restrict__ d
                 int kl = ds + 1 > mu + 1 ? ds + 1 : mu + 1;
                 kl = kl > kLevels ? kLevels : kl;
                 cnt_s = (uint32_t)(kl - ds);
+                for (int k = ds + 1; k <= kl; ++k) atomicAdd(&lh[k], 1u);
             }
         }
         ns[s] = (uint8_t)cnt_s;
@@ -470,12 +474,16 @@ __global__ __launch_bounds__(kThreads) void k_chain(const int8_t *__restrict__ d
         for (int w = 0; w < kThreads / 64; ++w) tsum += ws[w];
         bsum[blockIdx.x] = tsum;
     }
+    if (threadIdx.x <= kLevels) bsum[(size_t)(1 + threadIdx.x) * gridDim.x + blockIdx.x] = lh[threadIdx.x];
 }
 
-// Exclusive scan of the per-block sums, in place (one block, any length).
-__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *__restrict__ s, int nb) {
+// Exclusive scan, in place, of each of gridDim.x segments of nb per-block
+// sums (one block per segment); the segment total goes to tot[segment].
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *__restrict__ sums, int nb,
+                                                    uint32_t *__restrict__ tot) {
     __shared__ uint32_t carry;
     __shared__ uint32_t ws[16];
+    uint32_t *s = sums + (size_t)blockIdx.x * nb;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int c0 = 0; c0 < nb; c0 += 1024) {
@@ -497,6 +505,7 @@ __global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *__restrict__ s, in
         if (threadIdx.x == 1023) carry = pre + incl;
         __syncthreads();
     }
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
 // offs[s] = exclusive prefix of ns over ranks; offs[n] = node count.
@@ -555,15 +564,31 @@ __device__ int seg_begin(const uint64_t *__restrict__ keys, int s, int shift, ui
     return hi;
 }
 
+// Per-level placement of the cells: base[k] is the first slot of level k in
+// the level list (an exclusive scan of the level totals, host computed).
+struct LevelBase {
+    int32_t base[kLevels + 1];
+};
+
 // Writes every cell in pre-order: hashed key, level, body range, skip
-// pointer, parent, integer centre; counts children and their octants.
+// pointer, parent and integer centre, and lists it under its level.
+// Block b places its level-k cells after those of blocks < b (scanned
+// per-block level counts in lvl_pre[(1 + k) * nb + b]).
 __global__ __launch_bounds__(kThreads) void k_emit(
     const uint64_t *__restrict__ keys, const int8_t *__restrict__ delta,
     const uint8_t *__restrict__ ns, const int32_t *__restrict__ offs, int n, int m,
-    uint64_t *__restrict__ hkey, int32_t *__restrict__ level, int32_t *__restrict__ begin,
-    int32_t *__restrict__ count, int32_t *__restrict__ next, int32_t *__restrict__ parent,
-    int32_t *__restrict__ cx, int32_t *__restrict__ cy, int32_t *__restrict__ cz,
-    uint32_t *__restrict__ cmask, uint32_t *__restrict__ nchild, uint32_t *__restrict__ depth) {
+    const uint32_t *__restrict__ lvl_pre, LevelBase lb, uint64_t *__restrict__ hkey,
+    int32_t *__restrict__ level, int32_t *__restrict__ begin, int32_t *__restrict__ count,
+    int32_t *__restrict__ next, int32_t *__restrict__ parent, int32_t *__restrict__ cx,
+    int32_t *__restrict__ cy, int32_t *__restrict__ cz, int32_t *__restrict__ lvl_list) {
+    __shared__ uint32_t lcnt[kLevels + 1];
+    __shared__ int32_t lbase[kLevels + 1];
+    if (threadIdx.x <= kLevels) {
+        lcnt[threadIdx.x] = 0;
+        lbase[threadIdx.x] = lb.base[threadIdx.x] +
+                             (int32_t)lvl_pre[(size_t)(1 + threadIdx.x) * gridDim.x + blockIdx.x];
+    }
+    __syncthreads();
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int cnt = ns[s];
@@ -584,6 +609,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(
     for (int t = 0; t < cnt; ++t) {
         const int k = ds + 1 + t;
         const int node = o + t;
+        if (node >= m) break;  // guard
         const int sh = 3 * (kLevels - k);
         const uint64_t pre = k > 0 ? key >> sh : 0ull;
         const int e = k > 0 ? seg_end(keys, s, hi, sh, pre) : n;
@@ -594,122 +620,131 @@ __global__ __launch_bounds__(kThreads) void k_emit(
         count[node] = e - s;
         next[node] = offs[e];
         const int p = t > 0 ? node - 1 : par;
-        parent[node] = p < m ? p : -1;  // guard
+        parent[node] = p < m ? p : -1;
         const int cs = kLevels - k;
         cx[node] = (int32_t)(((qx >> cs) * 2u + 1u) << cs);
         cy[node] = (int32_t)(((qy >> cs) * 2u + 1u) << cs);
         cz[node] = (int32_t)(((qz >> cs) * 2u + 1u) << cs);
-        if (p >= 0 && p < m) {
-            atomicOr(&cmask[p], 1u << (uint32_t)(pre & 7u));
-            atomicAdd(&nchild[p], 1u);
-        }
-        if (t == cnt - 1) atomicMax(depth, (uint32_t)k);
+        const int slot = lbase[k] + (int)atomicAdd(&lcnt[k], 1u);
+        if (slot < m) lvl_list[slot] = node;
     }
 }
 
 // ------------------------------------------------------------------ 6. upward pass
+// Leaves: moments straight from their bodies, about the leaf centre.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_upward(
+__global__ __launch_bounds__(kThreads) void k_up_leaves(
     int m, const int32_t *__restrict__ begin, const int32_t *__restrict__ count,
-    const int32_t *__restrict__ next, const int32_t *__restrict__ parent,
-    const uint32_t *__restrict__ nchild, uint32_t *arrive, const int32_t *__restrict__ cx,
+    const int32_t *__restrict__ next, const int32_t *__restrict__ cx,
     const int32_t *__restrict__ cy, const int32_t *__restrict__ cz, const T *__restrict__ spos,
-    const T *__restrict__ smass, const Cube *__restrict__ cube, Moments *mom) {
+    const T *__restrict__ smass, const Cube *__restrict__ cube, Moments *__restrict__ mom,
+    uint32_t *__restrict__ cmask) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m || next[i] != i + 1) return;  // leaves start
+    if (i >= m || next[i] != i + 1) return;
     const double h = ldexp(cube->L, -(kLevels + 1));
-    {
-        const double c0 = cube->lo[0] + cx[i] * h, c1 = cube->lo[1] + cy[i] * h,
-                     c2 = cube->lo[2] + cz[i] * h;
-        const int b = begin[i], e = b + count[i];
-        double mt = 0, s0 = 0, s1 = 0, s2 = 0;
-        for (int j = b; j < e; ++j) {
-            const double mj = (double)smass[j];
-            mt += mj;
-            s0 += mj * ((double)spos[3 * (int64_t)j + 0] - c0);
-            s1 += mj * ((double)spos[3 * (int64_t)j + 1] - c1);
-            s2 += mj * ((double)spos[3 * (int64_t)j + 2] - c2);
-        }
-        Moments r;
-        r.m = mt;
-        r.c[0] = mt > 0 ? s0 / mt : 0.0;
-        r.c[1] = mt > 0 ? s1 / mt : 0.0;
-        r.c[2] = mt > 0 ? s2 / mt : 0.0;
-        for (int a = 0; a < 6; ++a) r.t[a] = 0.0;
-        for (int j = b; j < e; ++j) {
-            const double mj = (double)smass[j];
-            const double y0 = (double)spos[3 * (int64_t)j + 0] - c0 - r.c[0];
-            const double y1 = (double)spos[3 * (int64_t)j + 1] - c1 - r.c[1];
-            const double y2 = (double)spos[3 * (int64_t)j + 2] - c2 - r.c[2];
-            r.t[0] += mj * y0 * y0;
-            r.t[1] += mj * y0 * y1;
-            r.t[2] += mj * y0 * y2;
-            r.t[3] += mj * y1 * y1;
-            r.t[4] += mj * y1 * y2;
-            r.t[5] += mj * y2 * y2;
-        }
-        mom[i] = r;
+    const double c0 = cube->lo[0] + cx[i] * h, c1 = cube->lo[1] + cy[i] * h,
+                 c2 = cube->lo[2] + cz[i] * h;
+    const int b = begin[i], e = b + count[i];
+    double mt = 0, s0 = 0, s1 = 0, s2 = 0;
+    for (int j = b; j < e; ++j) {
+        const double mj = (double)smass[j];
+        mt += mj;
+        s0 += mj * ((double)spos[3 * (int64_t)j + 0] - c0);
+        s1 += mj * ((double)spos[3 * (int64_t)j + 1] - c1);
+        s2 += mj * ((double)spos[3 * (int64_t)j + 2] - c2);
     }
-    int node = i;
-    for (;;) {
-        const int p = parent[node];
-        if (p < 0 || p >= node) break;  // parents precede children in pre-order
-        const uint32_t old = __hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1 != nchild[p]) break;  // a sibling finishes the parent
-        // all children done: combine them about the parent's centre
-        const int pcx = cx[p], pcy = cy[p], pcz = cz[p];
-        double mt = 0, s0 = 0, s1 = 0, s2 = 0;
-        const int pend = min(next[p], m);
-        for (int c = p + 1; c < pend; c = max(next[c], c + 1)) {
-            const Moments q = mom[c];
-            const double g0 = q.c[0] + (double)(cx[c] - pcx) * h;
-            const double g1 = q.c[1] + (double)(cy[c] - pcy) * h;
-            const double g2 = q.c[2] + (double)(cz[c] - pcz) * h;
-            mt += q.m;
-            s0 += q.m * g0;
-            s1 += q.m * g1;
-            s2 += q.m * g2;
-        }
-        Moments r;
-        r.m = mt;
-        r.c[0] = mt > 0 ? s0 / mt : 0.0;
-        r.c[1] = mt > 0 ? s1 / mt : 0.0;
-        r.c[2] = mt > 0 ? s2 / mt : 0.0;
-        for (int a = 0; a < 6; ++a) r.t[a] = 0.0;
-        for (int c = p + 1; c < pend; c = max(next[c], c + 1)) {
-            const Moments q = mom[c];
-            const double y0 = q.c[0] + (double)(cx[c] - pcx) * h - r.c[0];
-            const double y1 = q.c[1] + (double)(cy[c] - pcy) * h - r.c[1];
-            const double y2 = q.c[2] + (double)(cz[c] - pcz) * h - r.c[2];
-            r.t[0] += q.t[0] + q.m * y0 * y0;
-            r.t[1] += q.t[1] + q.m * y0 * y1;
-            r.t[2] += q.t[2] + q.m * y0 * y2;
-            r.t[3] += q.t[3] + q.m * y1 * y1;
-            r.t[4] += q.t[4] + q.m * y1 * y2;
-            r.t[5] += q.t[5] + q.m * y2 * y2;
-        }
-        mom[p] = r;
-        node = p;
+    Moments r;
+    r.m = mt;
+    r.c[0] = mt > 0 ? s0 / mt : 0.0;
+    r.c[1] = mt > 0 ? s1 / mt : 0.0;
+    r.c[2] = mt > 0 ? s2 / mt : 0.0;
+    for (int a = 0; a < 6; ++a) r.t[a] = 0.0;
+    for (int j = b; j < e; ++j) {
+        const double mj = (double)smass[j];
+        const double y0 = (double)spos[3 * (int64_t)j + 0] - c0 - r.c[0];
+        const double y1 = (double)spos[3 * (int64_t)j + 1] - c1 - r.c[1];
+        const double y2 = (double)spos[3 * (int64_t)j + 2] - c2 - r.c[2];
+        r.t[0] += mj * y0 * y0;
+        r.t[1] += mj * y0 * y1;
+        r.t[2] += mj * y0 * y2;
+        r.t[3] += mj * y1 * y1;
+        r.t[4] += mj * y1 * y2;
+        r.t[5] += mj * y2 * y2;
     }
+    mom[i] = r;
+    cmask[i] = 0u;
+}
+
+// Internal cells of one level: combine the children (already done, one
+// level deeper) about this cell's centre with the parallel-axis shift;
+// children in octant order.  Also the 8-bit child mask.
+__global__ __launch_bounds__(kThreads) void k_up_level(
+    const int32_t *__restrict__ list, int cnt, int m, const uint64_t *__restrict__ hkey,
+    const int32_t *__restrict__ next, const int32_t *__restrict__ cx,
+    const int32_t *__restrict__ cy, const int32_t *__restrict__ cz, const Cube *__restrict__ cube,
+    Moments *__restrict__ mom, uint32_t *__restrict__ cmask) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const int p = list[t];
+    if (p < 0 || p >= m || next[p] == p + 1) return;  // leaves are done
+    const double h = ldexp(cube->L, -(kLevels + 1));
+    const int pcx = cx[p], pcy = cy[p], pcz = cz[p];
+    const int pend = min(next[p], m);
+    double mt = 0, s0 = 0, s1 = 0, s2 = 0;
+    uint32_t mask = 0;
+    for (int c = p + 1; c < pend; c = max(next[c], c + 1)) {
+        const Moments q = mom[c];
+        const double g0 = q.c[0] + (double)(cx[c] - pcx) * h;
+        const double g1 = q.c[1] + (double)(cy[c] - pcy) * h;
+        const double g2 = q.c[2] + (double)(cz[c] - pcz) * h;
+        mt += q.m;
+        s0 += q.m * g0;
+        s1 += q.m * g1;
+        s2 += q.m * g2;
+        mask |= 1u << (uint32_t)(hkey[c] & 7u);
+    }
+    Moments r;
+    r.m = mt;
+    r.c[0] = mt > 0 ? s0 / mt : 0.0;
+    r.c[1] = mt > 0 ? s1 / mt : 0.0;
+    r.c[2] = mt > 0 ? s2 / mt : 0.0;
+    for (int a = 0; a < 6; ++a) r.t[a] = 0.0;
+    for (int c = p + 1; c < pend; c = max(next[c], c + 1)) {
+        const Moments q = mom[c];
+        const double y0 = q.c[0] + (double)(cx[c] - pcx) * h - r.c[0];
+        const double y1 = q.c[1] + (double)(cy[c] - pcy) * h - r.c[1];
+        const double y2 = q.c[2] + (double)(cz[c] - pcz) * h - r.c[2];
+        r.t[0] += q.t[0] + q.m * y0 * y0;
+        r.t[1] += q.t[1] + q.m * y0 * y1;
+        r.t[2] += q.t[2] + q.m * y0 * y2;
+        r.t[3] += q.t[3] + q.m * y1 * y1;
+        r.t[4] += q.t[4] + q.m * y1 * y2;
+        r.t[5] += q.t[5] + q.m * y2 * y2;
+    }
+    mom[p] = r;
+    cmask[p] = mask;
 }
 
 // ------------------------------------------------------------------ 7. pack
+__device__ __forceinline__ void set_level(NodeRec32 &, int) {}
+__device__ __forceinline__ void set_level(NodeRec64 &r, int k) { r.level = k; }
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_pack_nodes(
     int m, const int32_t *__restrict__ level, const int32_t *__restrict__ begin,
     const int32_t *__restrict__ count, const int32_t *__restrict__ next,
     const int32_t *__restrict__ cx, const int32_t *__restrict__ cy,
     const int32_t *__restrict__ cz, const Moments *__restrict__ mom,
-    typename NodeRecT<R>::type *__restrict__ recs) {
+    const Cube *__restrict__ cube, typename NodeRecT<R>::type *__restrict__ recs) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     const Moments q = mom[i];
     const double tr = q.t[0] + q.t[3] + q.t[5];
+    const double h = ldexp(cube->L, -(kLevels + 1));
     typename NodeRecT<R>::type r{};
-    r.cx = cx[i];
-    r.cy = cy[i];
-    r.cz = cz[i];
+    r.cx = (R)(cx[i] * h);  // exact
+    r.cy = (R)(cy[i] * h);
+    r.cz = (R)(cz[i] * h);
     r.mx = (R)q.c[0];
     r.my = (R)q.c[1];
     r.mz = (R)q.c[2];
@@ -722,7 +757,9 @@ __global__ __launch_bounds__(kThreads) void k_pack_nodes(
     r.begin = begin[i];
     r.count = count[i];
     r.next = next[i];
-    r.level = level[i];
+    const double side = ldexp(cube->L, -level[i]);
+    r.l2 = (R)(side * side);
+    set_level(r, level[i]);
     recs[i] = r;
 }
 
@@ -734,14 +771,18 @@ __global__ __launch_bounds__(kThreads) void k_pack_bodies(
     const int32_t *__restrict__ next, const int32_t *__restrict__ cx,
     const int32_t *__restrict__ cy, const int32_t *__restrict__ cz,
     const T *__restrict__ spos, const T *__restrict__ smass, const Cube *__restrict__ cube,
-    BodyRec<R> *__restrict__ bodies, int4 *__restrict__ anchors) {
+    BodyRec<R> *__restrict__ bodies, Anchor<R> *__restrict__ anchors) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m || next[i] != i + 1) return;
     const double h = ldexp(cube->L, -(kLevels + 1));
     const double c0 = cube->lo[0] + cx[i] * h, c1 = cube->lo[1] + cy[i] * h,
                  c2 = cube->lo[2] + cz[i] * h;
     const int b = begin[i], e = b + count[i];
-    const int4 an = make_int4(cx[i], cy[i], cz[i], i);
+    Anchor<R> an;
+    an.x = (R)(cx[i] * h);  // exact
+    an.y = (R)(cy[i] * h);
+    an.z = (R)(cz[i] * h);
+    an.leaf = i;
     for (int j = b; j < e; ++j) {
         BodyRec<R> br;
         br.x = (R)((double)spos[3 * (int64_t)j + 0] - c0);
@@ -769,10 +810,10 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
         (rc = grow(t->delta, (size_t)n + 1)) || (rc = grow(t->nstart, (size_t)n)) ||
         (rc = grow(t->offs, 4ull * (n + 1))) || (rc = grow(t->cube, sizeof(Cube))) ||
         (rc = grow(t->part, 6ull * 8 * nbbox)) || (rc = grow(t->hist, 4ull * 256 * 8 * 2)) ||
-        (rc = grow(t->misc, 64 + 4ull * (nb + 1))) ||
+        (rc = grow(t->misc, 256 + 4ull * (kLevels + 2) * (nb + 1))) ||
         (rc = grow(t->status, 8ull * 256 * ntiles)) ||
         (rc = grow(t->bodies, sizeof(BodyRec<T>) * (size_t)n)) ||
-        (rc = grow(t->anchors, 16ull * n)))
+        (rc = grow(t->anchors, sizeof(Anchor<T>) * (size_t)n)))
         return rc;
     if (!pos_out) {
         if ((rc = grow(t->spos, 3 * sizeof(T) * (size_t)n)) ||
@@ -782,9 +823,11 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
         mass_out = (T *)t->smass.p;
     }
     Cube *cube = (Cube *)t->cube.p;
-    uint32_t *misc = (uint32_t *)t->misc.p;  // [0] flags, [1] depth, [8..15] tile ctr
-    uint32_t *flags = misc, *depth = misc + 1, *tile_ctr = misc + 8;
-    uint32_t *bsum = misc + 16;
+    // misc: [0] flags, [8..15] sort tile counters, [16..38] segment totals
+    // (chain-length sum, then cells per level), [64..] per-block sums
+    uint32_t *misc = (uint32_t *)t->misc.p;
+    uint32_t *flags = misc, *tile_ctr = misc + 8, *seg_tot = misc + 16;
+    uint32_t *bsum = misc + 64;
     uint32_t *hist = (uint32_t *)t->hist.p, *doff = hist + 2048;
 
     k_fill_u32<<<1, 64, 0, st>>>(misc, 16, 0u);
@@ -818,12 +861,13 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     int32_t *offs = (int32_t *)t->offs.p;
     k_delta<<<div_up(n + 1, kThreads), kThreads, 0, st>>>(ka, n, delta);
     k_chain<<<nb, kThreads, 0, st>>>(delta, n, B, ns, bsum);
-    k_scan_sums<<<1, 1024, 0, st>>>(bsum, nb);
+    k_scan_sums<<<kLevels + 2, 1024, 0, st>>>(bsum, nb, seg_tot);
     k_scan_down<<<nb, kThreads, 0, st>>>(ns, n, bsum, offs);
     if ((rc = check_launch("topology"))) return rc;
     uint32_t *hp = (uint32_t *)ctx->pinned;
     if (hipMemcpyAsync(hp, offs + n, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(hp + 1, flags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(hp + 32, seg_tot, 4 * (kLevels + 2), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(hp + 16, cube, sizeof(Cube), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return set_error(BH_E_DEVICE, "build: device failure while sizing the tree");
@@ -834,42 +878,57 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     t->L = hc.L;
     const int m = (int)hp[0];
     t->m = m;
+    // cells per level -> level-list bases, depth
+    LevelBase lb;
+    int lcount[kLevels + 1];
+    int acc = 0;
+    t->depth = 0;
+    for (int k = 0; k <= kLevels; ++k) {
+        lcount[k] = (int)hp[32 + 1 + k];
+        lb.base[k] = acc;
+        acc += lcount[k];
+        if (lcount[k] > 0) t->depth = k;
+    }
+    if (acc != m || hp[32] != (uint32_t)m)
+        return set_error(BH_E_DEVICE, "bh_build: internal error (level counts)");
     // ---- node allocations
     if ((rc = grow(t->hkey, 8ull * m)) || (rc = grow(t->level, 4ull * m)) ||
         (rc = grow(t->begin, 4ull * m)) || (rc = grow(t->count, 4ull * m)) ||
         (rc = grow(t->next, 4ull * m)) || (rc = grow(t->parent, 4ull * m)) ||
-        (rc = grow(t->cmask, 4ull * m)) || (rc = grow(t->nchild, 4ull * m)) ||
-        (rc = grow(t->arrive, 4ull * m)) || (rc = grow(t->cx, 4ull * m)) ||
+        (rc = grow(t->cmask, 4ull * m)) || (rc = grow(t->lvl_list, 4ull * m)) ||
+        (rc = grow(t->cx, 4ull * m)) ||
         (rc = grow(t->cy, 4ull * m)) || (rc = grow(t->cz, 4ull * m)) ||
         (rc = grow(t->mom, sizeof(Moments) * (size_t)m)) ||
         (rc = grow(t->recs, sizeof(typename NodeRecT<T>::type) * (size_t)m)))
         return rc;
     const int nbm = div_up(m, kThreads);
-    const int nfill = nbm < 4096 ? nbm : 4096;
-    k_fill_u32<<<nfill, kThreads, 0, st>>>((uint32_t *)t->cmask.p, m, 0u);
-    k_fill_u32<<<nfill, kThreads, 0, st>>>((uint32_t *)t->nchild.p, m, 0u);
-    k_fill_u32<<<nfill, kThreads, 0, st>>>((uint32_t *)t->arrive.p, m, 0u);
-    k_emit<<<nb, kThreads, 0, st>>>(ka, delta, ns, offs, n, m, (uint64_t *)t->hkey.p,
+    int32_t *lvl_list = (int32_t *)t->lvl_list.p;
+    k_emit<<<nb, kThreads, 0, st>>>(ka, delta, ns, offs, n, m, bsum, lb, (uint64_t *)t->hkey.p,
                                     (int32_t *)t->level.p, (int32_t *)t->begin.p,
                                     (int32_t *)t->count.p, (int32_t *)t->next.p,
                                     (int32_t *)t->parent.p, (int32_t *)t->cx.p,
-                                    (int32_t *)t->cy.p, (int32_t *)t->cz.p,
-                                    (uint32_t *)t->cmask.p, (uint32_t *)t->nchild.p, depth);
-    k_upward<T><<<nbm, kThreads, 0, st>>>(
+                                    (int32_t *)t->cy.p, (int32_t *)t->cz.p, lvl_list);
+    k_up_leaves<T><<<nbm, kThreads, 0, st>>>(
         m, (const int32_t *)t->begin.p, (const int32_t *)t->count.p, (const int32_t *)t->next.p,
-        (const int32_t *)t->parent.p, (const uint32_t *)t->nchild.p, (uint32_t *)t->arrive.p,
         (const int32_t *)t->cx.p, (const int32_t *)t->cy.p, (const int32_t *)t->cz.p, pos_out,
-        mass_out, cube, (Moments *)t->mom.p);
+        mass_out, cube, (Moments *)t->mom.p, (uint32_t *)t->cmask.p);
+    for (int k = t->depth - 1; k >= 0; --k) {  // deepest internal level first
+        if (lcount[k] == 0) continue;
+        k_up_level<<<div_up(lcount[k], kThreads), kThreads, 0, st>>>(
+            lvl_list + lb.base[k], lcount[k], m, (const uint64_t *)t->hkey.p,
+            (const int32_t *)t->next.p, (const int32_t *)t->cx.p, (const int32_t *)t->cy.p,
+            (const int32_t *)t->cz.p, cube, (Moments *)t->mom.p, (uint32_t *)t->cmask.p);
+    }
     k_pack_nodes<T><<<nbm, kThreads, 0, st>>>(
         m, (const int32_t *)t->level.p, (const int32_t *)t->begin.p,
         (const int32_t *)t->count.p, (const int32_t *)t->next.p, (const int32_t *)t->cx.p,
-        (const int32_t *)t->cy.p, (const int32_t *)t->cz.p, (const Moments *)t->mom.p,
+        (const int32_t *)t->cy.p, (const int32_t *)t->cz.p, (const Moments *)t->mom.p, cube,
         (typename NodeRecT<T>::type *)t->recs.p);
     k_pack_bodies<T, T><<<nbm, kThreads, 0, st>>>(
         m, (const int32_t *)t->begin.p, (const int32_t *)t->count.p,
         (const int32_t *)t->next.p, (const int32_t *)t->cx.p, (const int32_t *)t->cy.p,
         (const int32_t *)t->cz.p, pos_out, mass_out, cube, (BodyRec<T> *)t->bodies.p,
-        (int4 *)t->anchors.p);
+        (Anchor<T> *)t->anchors.p);
     return check_launch("tree");
 }
 

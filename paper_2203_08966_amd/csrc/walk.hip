@@ -7,8 +7,9 @@
 //   every lane keeps `resume`, the next node index it needs; a lane is
 //   active at node idx when resume <= idx.  An active lane takes its own
 //   decision for the node exactly as the recursive walk would (one-body cell
-//   -> particle-particle; side^2 < theta^2 d^2 -> particle-cell; leaf ->
-//   particle-particle with its bodies; else open).  A lane that opens the
+//   -> particle-particle; side^2 < theta^2 d^2 -> particle-cell, with the
+//   test in the walk's precision; leaf -> particle-particle with its bodies;
+//   else open).  A lane that opens the
 //   node resumes at idx + 1 (its first child); any other active lane resumes
 //   at next[idx].  The wave moves to idx + 1 if any lane opened, else to
 //   next[idx]; that is always the smallest resume point of the wave.
@@ -18,10 +19,10 @@
 // other bodies share its wave.  The node index is wave-uniform, so node
 // records and leaf bodies are read with scalar loads and broadcast.
 //
-// Positions are relative to cell centres: a body is stored as the integer
-// centre of its leaf (units of L 2^-22) plus a small offset; its position
-// relative to any cell centre is an exact integer difference, scaled by a
-// power of two, plus that offset.
+// Positions are relative to cell centres: a body is stored as the centre of
+// its leaf plus a small offset.  Centres are integers (units h = L 2^-22,
+// below 2^23) times h, so the difference of the body's leaf centre and any
+// cell centre is exact in FP32; adding the offset is the only rounding.
 #include "bh_internal.h"
 
 namespace bh {
@@ -34,22 +35,49 @@ __device__ __forceinline__ unsigned lane_id() {
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
 
-template <typename R> __device__ __forceinline__ R ldexp_r(R x, int e);
-template <> __device__ __forceinline__ float ldexp_r<float>(float x, int e) { return ldexpf(x, e); }
-template <> __device__ __forceinline__ double ldexp_r<double>(double x, int e) { return ldexp(x, e); }
-
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 enum : int { kNone = 0, kPP = 1, kPC = 2, kOpen = 3 };
 
+// Particle-particle terms of the bodies [jb, je) on the lanes in `pp`;
+// SELF: some lane's own body may be among them (skipped by index).
+// Runs on the lanes that take the particle-particle branch (exec mask).
+template <typename R, bool PHI, bool CNT, bool SELF>
+__device__ __forceinline__ void leaf_pp(const BodyRec<R> *__restrict__ bodies, int jb, int je,
+                                        int i, R X, R Y, R Z, R eps2, R &sx, R &sy, R &sz,
+                                        R &sp, uint32_t &cpp) {
+    R px = 0, py = 0, pz = 0, pq = 0;
+    for (int j = jb; j < je; ++j) {
+        const BodyRec<R> s = bodies[j];
+        if (!SELF || j != i) {
+            const R dx = s.x - X, dy = s.y - Y, dz = s.z - Z;
+            R r2 = dx * dx + eps2;
+            r2 = dy * dy + r2;
+            r2 = dz * dz + r2;
+            const R inv = rsq(r2);
+            const R minv = s.m * inv;
+            const R mi3 = minv * (inv * inv);
+            px += mi3 * dx;
+            py += mi3 * dy;
+            pz += mi3 * dz;
+            if (PHI) pq -= minv;
+            if (CNT && SELF) ++cpp;
+        }
+    }
+    if (CNT && !SELF) cpp += (uint32_t)(je - jb);
+    sx += px;
+    sy += py;
+    sz += pz;
+    if (PHI) sp += pq;
+}
+
 template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT>
 __global__ __launch_bounds__(256) void k_walk(
     const typename NodeRecT<R>::type *__restrict__ nodes, int m,
-    const BodyRec<R> *__restrict__ bodies, const int4 *__restrict__ anchors,
-    const uint32_t *__restrict__ perm, int nbodies, int t0, int t1, int nwaves_padded, R h,
-    R mac_l2,
-    R eps2, R *__restrict__ acc, R *__restrict__ phi_out, uint32_t *__restrict__ npp_out,
-    uint32_t *__restrict__ npc_out) {
+    const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
+    const uint32_t *__restrict__ perm, int nbodies, int t0, int t1, int nwaves_padded,
+    R theta2, R eps2, R *__restrict__ acc, R *__restrict__ phi_out,
+    uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out) {
     using Rec = typename NodeRecT<R>::type;
     // XCD-aware placement: consecutive workgroups land on different XCDs,
     // so hand each XCD a contiguous run of 8 logical blocks (spatially
@@ -66,16 +94,18 @@ __global__ __launch_bounds__(256) void k_walk(
     const bool live = i < t1;
 
     R ox = 0, oy = 0, oz = 0;
-    int ax = 0, ay = 0, az = 0;
+    R ax = 0, ay = 0, az = 0;
+    int myleaf = -1;
     if (live) {
         const BodyRec<R> me = bodies[i];
         ox = me.x;
         oy = me.y;
         oz = me.z;
-        const int4 an = anchors[i];
+        const Anchor<R> an = anchors[i];
         ax = an.x;
         ay = an.y;
         az = an.z;
+        myleaf = an.leaf;
     }
     R sx = 0, sy = 0, sz = 0, sp = 0;
     uint32_t cpp = 0, cpc = 0;
@@ -88,79 +118,64 @@ __global__ __launch_bounds__(256) void k_walk(
         idx = uniform(idx);
         const Rec nd = nodes[idx];
         const bool act = resume <= idx;
-        // position relative to the cell centre
-        const R X = (R)(ax - nd.cx) * h + ox;
-        const R Y = (R)(ay - nd.cy) * h + oy;
-        const R Z = (R)(az - nd.cz) * h + oz;
-        const R x = X - nd.mx, y = Y - nd.my, z = Z - nd.mz;
-        const R d2 = x * x + y * y + z * z;
-        const bool leaf = nd.next == idx + 1;
-        int kind = kNone;
-        if (act) {
-            if (nd.count == 1 || idx == 0) kind = kPP;
-            else if (ldexp_r<R>(mac_l2, -2 * nd.level) < d2) kind = kPC;
-            else if (leaf) kind = kPP;
-            else kind = kOpen;
-        }
-        const uint64_t any_open = __ballot(kind == kOpen);
-        if (__ballot(kind == kPC)) {
-            if (kind == kPC) {
-                const R r2 = d2 + eps2;
-                const R inv = rsq(r2);
-                const R inv2 = inv * inv;
-                const R inv3 = inv * inv2;
-                const R mi3 = nd.m * inv3;
-                R fx = -mi3 * x, fy = -mi3 * y, fz = -mi3 * z;
-                R fp = -nd.m * inv;
-                if (ORDER2) {
-                    const R qzz = -nd.qxx - nd.qyy;
-                    const R qx = nd.qxx * x + nd.qxy * y + nd.qxz * z;
-                    const R qy = nd.qxy * x + nd.qyy * y + nd.qyz * z;
-                    const R qz = nd.qxz * x + nd.qyz * y + qzz * z;
-                    const R xqx = x * qx + y * qy + z * qz;
-                    const R inv5 = inv3 * inv2;
-                    const R c7 = (R)2.5 * xqx * inv5 * inv2;
-                    fx += qx * inv5 - c7 * x;
-                    fy += qy * inv5 - c7 * y;
-                    fz += qz * inv5 - c7 * z;
-                    fp -= (R)0.5 * xqx * inv5;
+        const int nxt = uniform(nd.next);
+        const int cnt = uniform(nd.count);
+        // position relative to the cell centre (the centre difference is exact)
+        const R X = (ax - nd.cx) + ox;
+        const R Y = (ay - nd.cy) + oy;
+        const R Z = (az - nd.cz) + oz;
+        bool pp = false, open = false;
+        if (cnt == 1 || idx == 0) {
+            pp = act;  // one body (or the root leaf): particle-particle
+        } else {
+            const R x = X - nd.mx, y = Y - nd.my, z = Z - nd.mz;
+            const R d2 = x * x + y * y + z * z;
+            const bool accept = act && nd.l2 < theta2 * d2;
+            {
+                if (accept) {  // skipped as a whole when no lane accepts
+                    const R inv = rsq(d2 + eps2);
+                    const R inv2 = inv * inv;
+                    const R inv3 = inv * inv2;
+                    if (ORDER2) {
+                        const R qzz = -nd.qxx - nd.qyy;
+                        const R qx = nd.qxx * x + nd.qxy * y + nd.qxz * z;
+                        const R qy = nd.qxy * x + nd.qyy * y + nd.qyz * z;
+                        const R qz = nd.qxz * x + nd.qyz * y + qzz * z;
+                        const R xqx = x * qx + y * qy + z * qz;
+                        const R inv5 = inv3 * inv2;
+                        const R t5 = xqx * inv5;
+                        const R g = nd.m * inv3 + (R)2.5 * t5 * inv2;
+                        sx = inv5 * qx + sx;
+                        sy = inv5 * qy + sy;
+                        sz = inv5 * qz + sz;
+                        sx = -g * x + sx;
+                        sy = -g * y + sy;
+                        sz = -g * z + sz;
+                        if (PHI) sp = sp - nd.m * inv - (R)0.5 * t5;
+                    } else {
+                        const R g = nd.m * inv3;
+                        sx = -g * x + sx;
+                        sy = -g * y + sy;
+                        sz = -g * z + sz;
+                        if (PHI) sp = sp - nd.m * inv;
+                    }
+                    if (CNT) ++cpc;
                 }
-                sx += fx;
-                sy += fy;
-                sz += fz;
-                if (PHI) sp += fp;
-                if (CNT) ++cpc;
             }
+            if (nxt == idx + 1) pp = act && !accept;  // leaf
+            else open = act && !accept;
         }
-        if (__ballot(kind == kPP)) {
+        if (pp) {
             const int jb = uniform(nd.begin);
-            const int je = min(jb + uniform(nd.count), nbodies);  // guard
-            R px = 0, py = 0, pz = 0, pp = 0;
-            uint32_t np = 0;
-            for (int j = jb; j < je; ++j) {
-                const BodyRec<R> s = bodies[j];
-                if (kind == kPP && j != i) {
-                    const R dx = s.x - X, dy = s.y - Y, dz = s.z - Z;
-                    const R r2 = dx * dx + dy * dy + dz * dz + eps2;
-                    const R inv = rsq(r2);
-                    const R mi3 = s.m * inv * inv * inv;
-                    px += mi3 * dx;
-                    py += mi3 * dy;
-                    pz += mi3 * dz;
-                    if (PHI) pp -= s.m * inv;
-                    if (CNT) ++np;
-                }
-            }
-            sx += px;
-            sy += py;
-            sz += pz;
-            if (PHI) sp += pp;
-            if (CNT) cpp += np;
+            const int je = min(jb + cnt, nbodies);  // guard
+            if (myleaf == idx)  // the lane's own leaf: skip itself
+                leaf_pp<R, PHI, CNT, true>(bodies, jb, je, i, X, Y, Z, eps2, sx, sy, sz, sp, cpp);
+            else
+                leaf_pp<R, PHI, CNT, false>(bodies, jb, je, i, X, Y, Z, eps2, sx, sy, sz, sp, cpp);
         }
-        if (kind == kOpen) resume = idx + 1;
-        else if (act) resume = nd.next;
-        const int nx = any_open ? idx + 1 : nd.next;
-        idx = nx > idx ? nx : idx + 1;  // always moves forward
+        const uint64_t any_open = __ballot(open);
+        if (act) resume = open ? idx + 1 : nxt;
+        idx = any_open ? idx + 1 : (nxt > idx ? nxt : idx + 1);  // always moves forward
     }
     if (live) {
         const int o = SORTED_OUT ? i : (int)perm[i];
@@ -181,12 +196,10 @@ void launch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, voi
     const int nw = div_up(t1 - t0, 64);
     const int nblk = div_up(nw, 4);
     const int nblk_pad = div_up(nblk, 64) * 64;
-    const R h = (R)ldexp(t->L, -(kLevels + 1));
-    const double l2 = theta > 0 ? (t->L * t->L) / (theta * theta) : HUGE_VAL;
     k_walk<R, ORDER2, PHI, CNT, SORTED><<<nblk_pad, 256, 0, t->ctx->stream>>>(
         (const typename NodeRecT<R>::type *)t->recs.p, (int)t->m,
-        (const BodyRec<R> *)t->bodies.p, (const int4 *)t->anchors.p, t->perm, (int)t->n, t0, t1,
-        nblk_pad * 4, h, (R)l2, (R)(eps * eps), (R *)acc, (R *)phi, npp, npc);
+        (const BodyRec<R> *)t->bodies.p, (const Anchor<R> *)t->anchors.p, t->perm, (int)t->n, t0,
+        t1, nblk_pad * 4, (R)(theta * theta), (R)(eps * eps), (R *)acc, (R *)phi, npp, npc);
 }
 
 template <typename R, bool ORDER2>

@@ -66,6 +66,19 @@ def _load():
     lib.orc_walk.argtypes = [C.c_int64, _i32, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
                              C.c_double, C.c_double, C.c_double, C.c_int, C.c_int64, _i64,
                              _f64, _f64, _i64, _i64, _i64, _i32]
+    lib.orc_mac_features.argtypes = [_f64, _f64, C.c_double, _f64, C.c_double, _f64, C.c_int,
+                                     C.c_int, C.c_double, _f64]
+    lib.orc_splitmix64.argtypes = [C.c_uint64]
+    lib.orc_splitmix64.restype = C.c_uint64
+    lib.orc_mlp_bf16.argtypes = [_f64, _f64]
+    lib.orc_mlp_bf16.restype = C.c_double
+    lib.orc_mac_samples.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
+                                    _f64, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, C.c_uint64, C.c_int64, _i64, C.c_int64, _f64,
+                                    _f64, _i32, _i64]
+    lib.orc_walk_mlp.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
+                                 _f64, C.c_double, C.c_double, C.c_double, C.c_double,
+                                 C.c_double, _f64, C.c_int64, _i64, _f64, _f64, _i64, _i64, _i32]
     _lib = lib
     return lib
 
@@ -249,3 +262,66 @@ def rms_rel(acc, ref):
     e = np.linalg.norm(np.asarray(acc) - ref, axis=1) / np.linalg.norm(ref, axis=1)
     return dict(rms=float(np.sqrt(np.mean(e * e))), median=float(np.median(e)),
                 p99=float(np.quantile(e, 0.99)), max=float(e.max()))
+
+
+# ------------------------------------------------------------------ learned criterion
+def mac_features(r, centre, side, com, M, Q, count, is_leaf, eps):
+    f = np.zeros(10)
+    _load().orc_mac_features(np.ascontiguousarray(r, dtype=np.float64),
+                             np.ascontiguousarray(centre, dtype=np.float64), float(side),
+                             np.ascontiguousarray(com, dtype=np.float64), float(M),
+                             np.ascontiguousarray(Q, dtype=np.float64), int(count), int(is_leaf),
+                             float(eps), f)
+    return f
+
+
+def splitmix64(x: int) -> int:
+    return int(_load().orc_splitmix64(x))
+
+
+def mlp_bf16(params, f) -> float:
+    return float(_load().orc_mlp_bf16(np.ascontiguousarray(params, dtype=np.float64),
+                                      np.ascontiguousarray(f, dtype=np.float64)))
+
+
+def mac_samples(b, eps, theta_lo, theta_hi, keep, seed, targets=None, cap=4096):
+    """Learned-criterion training pairs of the bodies ``targets`` (sorted
+    ranks; all by default) over a tree from build_all: per target up to
+    ``cap`` kept candidates in pre-order.  Returns (feat, label, node, count)
+    with feat (nt, cap, 10)."""
+    lib = _load()
+    t = b["tree"]
+    M, com, Q = b["mom"]
+    n = b["smass"].shape[0]
+    tg = np.arange(n, dtype=np.int64) if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = tg.shape[0]
+    feat = np.zeros((nt, cap, 10))
+    label = np.zeros((nt, cap))
+    node = np.full((nt, cap), -1, dtype=np.int32)
+    cnt = np.zeros(nt, dtype=np.int64)
+    lib.orc_mac_samples(t["level"], t["hkey"], t["begin"], t["count"], t["next"], M, com.ravel(),
+                        Q.ravel(), b["spos"].ravel(), b["smass"], np.ascontiguousarray(b["lo"]),
+                        float(b["L"]), float(eps), float(theta_lo), float(theta_hi), float(keep),
+                        int(seed), nt, tg, int(cap), feat.ravel(), label.ravel(), node.ravel(), cnt)
+    return feat, label, node, cnt
+
+
+def walk_mlp(b, eps, theta_lo, theta_hi, log10tau, params, targets=None):
+    """Tree walk with the learned criterion (bf16 view of the network)."""
+    lib = _load()
+    t = b["tree"]
+    M, com, Q = b["mom"]
+    n = b["smass"].shape[0]
+    tg = np.arange(n, dtype=np.int64) if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = tg.shape[0]
+    acc = np.zeros((nt, 3))
+    phi = np.zeros(nt)
+    npp = np.zeros(nt, dtype=np.int64)
+    npc = np.zeros(nt, dtype=np.int64)
+    flag = np.zeros(nt, dtype=np.int32)
+    lib.orc_walk_mlp(t["level"], t["hkey"], t["begin"], t["count"], t["next"], M, com.ravel(),
+                     Q.ravel(), b["spos"].ravel(), b["smass"], np.ascontiguousarray(b["lo"]),
+                     float(b["L"]), float(eps), float(theta_lo), float(theta_hi), float(log10tau),
+                     np.ascontiguousarray(params, dtype=np.float64), nt, tg, acc.ravel(), phi,
+                     npp, npc, flag)
+    return WalkResult(acc, phi, npp, npc, np.zeros(nt, dtype=np.int64), flag)

@@ -447,3 +447,334 @@ void orc_walk(int64_t m, const int32_t *level, const int32_t *begin, const int32
         if (flag) flag[t] = r.flag;
     }
 }
+
+/* ========================================================================
+ * Learned acceptance criterion.
+ *
+ * Features of a (body, cell) pair, all scale-free (x = body - COM, d = |x|,
+ * n = x/d, g = COM - cell centre, l = cell side, Q the traceless quadrupole):
+ *   f0 l/d            f1 (l/d)^2          f2 |g|/l        f3 n.g/l
+ *   f4 distance from the body to the cell's cube / d (0 inside)
+ *   f5 n.Q.n/(M l^2)  f6 |Q|_F/(M l^2)    f7 log2(count)/21
+ *   f8 eps/d          f9 1 if the cell is a leaf
+ * Label: log10 of |a_pc - a_exact| / |a_exact|, the error of the cell's
+ * particle-cell term (order 2) relative to the cell's exact contribution
+ * (direct sum over its bodies), floored at 1e-12.
+ * ====================================================================== */
+
+/* cell centre from the hashed key */
+static void cell_centre(uint64_t hkey, int k, const double *lo, double L, double c[3])
+{
+    const uint64_t prefix = hkey ^ ((uint64_t)1 << (3 * k));
+    uint32_t ix = 0, iy = 0, iz = 0;
+    for (int l = 0; l < k; ++l) {
+        unsigned d = (unsigned)((prefix >> (3 * (k - 1 - l))) & 7u);
+        ix = (ix << 1) | ((d >> 2) & 1u);
+        iy = (iy << 1) | ((d >> 1) & 1u);
+        iz = (iz << 1) | (d & 1u);
+    }
+    const double side = ldexp(L, -k);
+    c[0] = lo[0] + (ix + 0.5) * side;
+    c[1] = lo[1] + (iy + 0.5) * side;
+    c[2] = lo[2] + (iz + 0.5) * side;
+}
+
+void orc_mac_features(const double *r, const double *centre, double side, const double *com,
+                      double M, const double *Q, int count, int is_leaf, double eps, double *f)
+{
+    double x[3], g[3], n[3];
+    for (int a = 0; a < 3; ++a) {
+        x[a] = r[a] - com[a];
+        g[a] = com[a] - centre[a];
+    }
+    const double d = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    for (int a = 0; a < 3; ++a)
+        n[a] = x[a] / d;
+    f[0] = side / d;
+    f[1] = f[0] * f[0];
+    f[2] = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / side;
+    f[3] = (n[0] * g[0] + n[1] * g[1] + n[2] * g[2]) / side;
+    double db2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double t = fabs(r[a] - centre[a]) - 0.5 * side;
+        if (t > 0.0)
+            db2 += t * t;
+    }
+    f[4] = sqrt(db2) / d;
+    /* full symmetric Q from xx xy xz yy yz zz */
+    const double q[3][3] = {{Q[0], Q[1], Q[2]}, {Q[1], Q[3], Q[4]}, {Q[2], Q[4], Q[5]}};
+    double nqn = 0.0, qf = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            nqn += n[a] * q[a][b] * n[b];
+            qf += q[a][b] * q[a][b];
+        }
+    const double ml2 = M * side * side;
+    f[5] = ml2 > 0.0 ? nqn / ml2 : 0.0;
+    f[6] = ml2 > 0.0 ? sqrt(qf) / ml2 : 0.0;
+    f[7] = log2((double)count) / 21.0;
+    f[8] = eps / d;
+    f[9] = is_leaf ? 1.0 : 0.0;
+}
+
+/* SplitMix64 (Steele, Lea & Flood 2014): the finaliser applied to x. */
+uint64_t orc_splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* keep a candidate (body rank i, node c) with probability p */
+static int keep_pair(uint64_t seed, int64_t i, int64_t c, double p)
+{
+    const uint64_t h = orc_splitmix64(seed ^ (((uint64_t)i << 32) | (uint64_t)(uint32_t)c));
+    return (double)(h >> 11) * (1.0 / 9007199254740992.0) < p;
+}
+
+static int inside_cell(const double *r, const double *centre, double side)
+{
+    for (int a = 0; a < 3; ++a)
+        if (fabs(r[a] - centre[a]) > 0.5 * side)
+            return 0;
+    return 1;
+}
+
+/* round to bfloat16, nearest even */
+static double bf16r(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/* The network as the bf16 inference evaluates it (see oracle/mlp.py):
+ * parameters W1[32][10] b1[32] W2[32][32] b2[32] w3[32] b3. */
+double orc_mlp_bf16(const double *p, const double *f)
+{
+    const double *W1 = p, *b1 = p + 320, *W2 = p + 352, *b2 = p + 1376, *w3 = p + 1408;
+    const double b3 = (double)(float)p[1440];
+    double h1[32], out = 0.0;
+    for (int u = 0; u < 32; ++u) {
+        double s = bf16r(b1[u]);
+        for (int k = 0; k < 10; ++k)
+            s += bf16r(W1[u * 10 + k]) * bf16r(f[k]);
+        h1[u] = bf16r(s > 0.0 ? s : 0.0);
+    }
+    for (int u = 0; u < 32; ++u) {
+        double s = (double)(float)b2[u];
+        for (int k = 0; k < 32; ++k)
+            s += bf16r(W2[u * 32 + k]) * h1[k];
+        if (s > 0.0)
+            out += (double)(float)w3[u] * s;
+    }
+    return out + b3;
+}
+
+typedef struct {
+    walk_ctx w;
+    const uint64_t *hkey;
+    const double *lo;
+    double tlo2, thi2, eps;
+    /* samples */
+    uint64_t seed;
+    double keep;
+    int64_t cap, slot0, n_cand;
+    double *feat, *label;
+    int32_t *node;
+    /* learned decision */
+    const double *mlp;
+    double log10tau;
+} mac_ctx;
+
+static void cell_label(const mac_ctx *m, int64_t i, int64_t c, double *lab)
+{
+    const walk_ctx *w = &m->w;
+    walk_acc ex, ap;
+    memset(&ex, 0, sizeof(ex));
+    memset(&ap, 0, sizeof(ap));
+    leaf_pp(w, i, c, &ex);
+    double x[3];
+    for (int d = 0; d < 3; ++d)
+        x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
+    pc(w, i, c, x, x[0] * x[0] + x[1] * x[1] + x[2] * x[2], &ap);
+    const double e0 = ap.a[0] - ex.a[0], e1 = ap.a[1] - ex.a[1], e2 = ap.a[2] - ex.a[2];
+    const double ne = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    const double na = sqrt(ex.a[0] * ex.a[0] + ex.a[1] * ex.a[1] + ex.a[2] * ex.a[2]);
+    double rel = na > 0.0 ? ne / na : 1e-12;
+    if (rel < 1e-12)
+        rel = 1e-12;
+    *lab = log10(rel);
+}
+
+static void pair_features(const mac_ctx *m, int64_t i, int64_t c, double *f)
+{
+    const walk_ctx *w = &m->w;
+    double centre[3];
+    cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
+    orc_mac_features(&w->spos[3 * i], centre, ldexp(w->L, -w->level[c]), &w->com[3 * c],
+                     w->M[c], &w->Q[6 * c], w->count[c], w->next[c] == c + 1, m->eps, f);
+}
+
+/* Candidates of body i: walk at theta_lo (everything at or above theta_lo
+ * is opened); every multi-body cell with theta_lo <= l/d < theta_hi that
+ * does not contain the body is a candidate; candidates kept by the hash. */
+static void sample_walk(mac_ctx *m, int64_t node, int64_t i, int64_t *k)
+{
+    const walk_ctx *w = &m->w;
+    for (int64_t c = node + 1; c < w->next[node]; c = w->next[c]) {
+        if (w->count[c] == 1)
+            continue;
+        const double side = ldexp(w->L, -w->level[c]);
+        double x[3];
+        for (int d = 0; d < 3; ++d)
+            x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
+        const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+        const double s2 = side * side;
+        if (s2 < m->tlo2 * d2)
+            continue; /* accepted below the band */
+        if (s2 < m->thi2 * d2) {
+            double centre[3];
+            cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
+            if (!inside_cell(&w->spos[3 * i], centre, side)) {
+                m->n_cand++;
+                if (keep_pair(m->seed, i, c, m->keep) && *k < m->cap) {
+                    const int64_t o = m->slot0 + *k;
+                    pair_features(m, i, c, &m->feat[10 * o]);
+                    cell_label(m, i, c, &m->label[o]);
+                    m->node[o] = (int32_t)c;
+                    ++*k;
+                }
+            }
+        }
+        if (w->next[c] != c + 1)
+            sample_walk(m, c, i, k);
+    }
+}
+
+/* Per target rank t (targets are sorted ranks): up to cap kept candidates in
+ * pre-order at slot t*cap.. of feat (10 each), label, node; count[t]. */
+void orc_mac_samples(const int32_t *level, const uint64_t *hkey, const int32_t *begin,
+                     const int32_t *count, const int32_t *next, const double *M,
+                     const double *com, const double *Q, const double *spos,
+                     const double *smass, const double *lo, double L, double eps,
+                     double theta_lo, double theta_hi, double keep, uint64_t seed, int64_t nt,
+                     const int64_t *targets, int64_t cap, double *feat, double *label,
+                     int32_t *node, int64_t *cnt)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < nt; ++t) {
+        mac_ctx m;
+        memset(&m, 0, sizeof(m));
+        m.w = (walk_ctx){level, begin, count, next, M, com, Q, spos, smass, L, 0.0, eps * eps, 2};
+        m.hkey = hkey;
+        m.lo = lo;
+        m.tlo2 = theta_lo * theta_lo;
+        m.thi2 = theta_hi * theta_hi;
+        m.eps = eps;
+        m.seed = seed;
+        m.keep = keep;
+        m.cap = cap;
+        m.slot0 = cap * t;
+        m.feat = feat;
+        m.label = label;
+        m.node = node;
+        int64_t k = 0;
+        if (next[0] != 1)
+            sample_walk(&m, 0, targets[t], &k);
+        cnt[t] = k;
+    }
+}
+
+/* Tree walk with the learned criterion: below theta_lo accept, at or above
+ * theta_hi or with the body inside the cell open, otherwise accept iff the
+ * network's predicted log10 relative error is below log10tau.  The flag also
+ * marks decisions within 1e-3 of log10tau and bodies within 1e-6 side of a
+ * cell face, where a reduced-precision evaluation may decide the other way. */
+static void cell_force_mlp(mac_ctx *m, int64_t node, int64_t i, walk_acc *r)
+{
+    const walk_ctx *w = &m->w;
+    for (int64_t c = node + 1; c < w->next[node]; c = w->next[c]) {
+        if (w->count[c] == 1) {
+            if (w->begin[c] != i)
+                pp(w, i, w->begin[c], r);
+            continue;
+        }
+        const double side = ldexp(w->L, -w->level[c]);
+        double x[3];
+        for (int d = 0; d < 3; ++d)
+            x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
+        const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+        const double s2 = side * side;
+        int accept;
+        if (fabs(s2 - m->tlo2 * d2) < 1e-5 * s2 || fabs(s2 - m->thi2 * d2) < 1e-5 * s2)
+            r->flag = 1;
+        if (s2 < m->tlo2 * d2) {
+            accept = 1;
+        } else if (s2 >= m->thi2 * d2) {
+            accept = 0;
+        } else {
+            double centre[3];
+            cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
+            int in = inside_cell(&w->spos[3 * i], centre, side);
+            for (int a = 0; a < 3; ++a)
+                if (fabs(fabs(w->spos[3 * i + a] - centre[a]) - 0.5 * side) < 1e-6 * side)
+                    r->flag = 1;
+            if (in) {
+                accept = 0;
+            } else {
+                double f[10];
+                pair_features(m, i, c, f);
+                const double pred = orc_mlp_bf16(m->mlp, f);
+                if (fabs(pred - m->log10tau) < 1e-3)
+                    r->flag = 1;
+                accept = pred < m->log10tau;
+            }
+        }
+        if (accept)
+            pc(w, i, c, x, d2, r);
+        else if (w->next[c] == c + 1)
+            leaf_pp(w, i, c, r);
+        else
+            cell_force_mlp(m, c, i, r);
+    }
+}
+
+void orc_walk_mlp(const int32_t *level, const uint64_t *hkey, const int32_t *begin,
+                  const int32_t *count, const int32_t *next, const double *M, const double *com,
+                  const double *Q, const double *spos, const double *smass, const double *lo,
+                  double L, double eps, double theta_lo, double theta_hi, double log10tau,
+                  const double *mlp, int64_t nt, const int64_t *targets, double *acc,
+                  double *phi, int64_t *npp, int64_t *npc, int32_t *flag)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        mac_ctx m;
+        memset(&m, 0, sizeof(m));
+        m.w = (walk_ctx){level, begin, count, next, M, com, Q, spos, smass, L, 0.0, eps * eps, 2};
+        m.hkey = hkey;
+        m.lo = lo;
+        m.tlo2 = theta_lo * theta_lo;
+        m.thi2 = theta_hi * theta_hi;
+        m.eps = eps;
+        m.mlp = mlp;
+        m.log10tau = log10tau;
+        const int64_t i = targets[t];
+        walk_acc r;
+        memset(&r, 0, sizeof(r));
+        if (next[0] == 1)
+            leaf_pp(&m.w, i, 0, &r);
+        else
+            cell_force_mlp(&m, 0, i, &r);
+        for (int d = 0; d < 3; ++d)
+            acc[3 * t + d] = r.a[d];
+        if (phi) phi[t] = r.phi;
+        if (npp) npp[t] = r.npp;
+        if (npc) npc[t] = r.npc;
+        if (flag) flag[t] = r.flag;
+    }
+}

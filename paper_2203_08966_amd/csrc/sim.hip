@@ -65,15 +65,28 @@ __global__ __launch_bounds__(kThreads) void k_energy(int n, const T *__restrict_
     }
 }
 
-__global__ void k_energy_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double a = 0, b = 0;
-        for (int k = 0; k < nb; ++k) {
-            a += part[2 * k];
-            b += part[2 * k + 1];
+// One block of 256: fixed-order tree reduction of the partials.
+__global__ __launch_bounds__(256) void k_energy_final(const double *__restrict__ part, int nb,
+                                                      double *__restrict__ out) {
+    __shared__ double s[2][256];
+    double a = 0, b = 0;
+    for (int k = threadIdx.x; k < nb; k += 256) {
+        a += part[2 * k];
+        b += part[2 * k + 1];
+    }
+    s[0][threadIdx.x] = a;
+    s[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + o];
+            s[1][threadIdx.x] += s[1][threadIdx.x + o];
         }
-        out[0] = a;
-        out[1] = b;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = s[0][0];
+        out[1] = s[1][0];
     }
 }
 
@@ -190,7 +203,7 @@ int launch_energy(hipStream_t s, int dtype, int64_t n, const void *vel, const vo
     else
         k_energy<double><<<nb, kThreads, 0, s>>>((int)n, (const double *)vel,
                                                  (const double *)mass, (const double *)phi, red);
-    k_energy_final<<<1, 64, 0, s>>>(red, nb, out2);
+    k_energy_final<<<1, 256, 0, s>>>(red, nb, out2);
     return check_launch("energy");
 }
 

@@ -1,0 +1,145 @@
+"""Pins for the oracle's learned acceptance criterion: network gradients,
+Adam, the bf16 view, the hash, features, labels, candidate sampling and the
+learned-criterion walk."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_2203_08966_amd import workloads as W
+
+
+def test_gradient_matches_central_differences():
+    rng = np.random.default_rng(0)
+    X = rng.normal(size=(64, 10))
+    y = rng.normal(size=64)
+    th = mlp.init(1) + rng.normal(size=mlp.NPARAM) * 0.05
+    g = mlp.grad(th, X, y)
+    h = 1e-6
+    idx = rng.choice(mlp.NPARAM, size=120, replace=False)
+    for k in idx:
+        e = np.zeros(mlp.NPARAM)
+        e[k] = h
+        fd = (mlp.loss(th + e, X, y) - mlp.loss(th - e, X, y)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, k
+
+
+def test_adam_first_step_closed_form():
+    """First Adam step: m_hat = g, v_hat = g^2, so the update is
+    lr * g / (|g| + eps)."""
+    th = np.array([0.5, -1.0, 2.0])
+    g = np.array([0.3, -2e-3, 0.0])
+    opt = mlp.Adam(3, lr=1e-2, eps=1e-8)
+    th1 = opt.step(th, g)
+    np.testing.assert_allclose(th1, th - 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_training_reduces_loss():
+    rng = np.random.default_rng(2)
+    X = rng.uniform(-1, 1, size=(2048, 10))
+    y = np.sin(2 * X[:, 0]) + X[:, 1] * X[:, 2]
+    th = mlp.init(5)
+    opt = mlp.Adam(mlp.NPARAM, lr=3e-3)
+    l0 = mlp.loss(th, X, y)
+    for ep in range(300):
+        b = rng.choice(2048, 256, replace=False)
+        th = opt.step(th, mlp.grad(th, X[b], y[b]))
+    assert mlp.loss(th, X, y) < 0.2 * l0
+
+
+def test_bf16_views_agree():
+    """The numpy and C writings of the bf16 network agree; bf16 rounding is
+    round-to-nearest-even on the top 16 bits."""
+    assert mlp.bf16(1.0) == 1.0
+    assert mlp.bf16(1.0 + 2 ** -8) == 1.0           # tie -> even
+    assert mlp.bf16(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6
+    rng = np.random.default_rng(3)
+    th = mlp.init(9) + rng.normal(size=mlp.NPARAM) * 0.1
+    X = rng.normal(size=(50, 10))
+    a = mlp.forward_bf16(th, X)
+    b = np.array([oracle.mlp_bf16(th, x) for x in X])
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-12)
+    full, _ = mlp.forward(th, X)
+    assert np.max(np.abs(a - full)) < 0.05 * np.max(np.abs(full)) + 0.05
+
+
+def test_splitmix64_reference_outputs():
+    """SplitMix64 with state 0: the first three outputs of the published
+    generator (state advances by the golden gamma before each mix)."""
+    gamma = 0x9E3779B97F4A7C15
+    outs = [oracle.splitmix64((k * gamma) % 2 ** 64) for k in range(3)]
+    assert outs == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_features_closed_form():
+    """Body on the x axis at distance 2 from a unit cell centred at the
+    origin holding masses m at +-s z (COM at the centre)."""
+    m, s = 0.25, 0.2
+    Q = np.array([-2 * m * s * s, 0, 0, -2 * m * s * s, 0, 4 * m * s * s])
+    f = oracle.mac_features([2.0, 0, 0], [0, 0, 0], 1.0, [0, 0, 0], 2 * m, Q, 2, 1, 0.1)
+    expect = [0.5, 0.25, 0.0, 0.0, 1.5 / 2.0, -2 * m * s * s / (2 * m),
+              np.sqrt(16 + 4 + 4) * m * s * s / (2 * m), 1 / 21, 0.05, 1.0]
+    np.testing.assert_allclose(f, expect, rtol=1e-14, atol=1e-15)
+
+
+def _pair_tree(z, s, m=0.4):
+    c = 0.25
+    pos = np.array([[c, c, c + s], [c, c, c - s], [c, c, c + z]])
+    mass = np.array([m, m, 0.0])
+    return oracle.build_all(pos, mass, 2)
+
+
+def test_label_two_mass_closed_form():
+    """Label of the on-axis pair cell: the quadrupole's remaining error is
+    the next term, relative size 5 s^4/z^4 / (1 + 3 s^2/z^2 + ...)."""
+    s = 0.01
+    for z in (0.3, 0.4, 0.6):
+        bb = _pair_tree(z, s)
+        rank = int(np.nonzero(bb["perm"] == 2)[0][0])
+        f, lab, node, cnt = oracle.mac_samples(bb, 0.0, 0.0, 100.0, 1.0, 1, targets=[rank], cap=8)
+        assert cnt[0] == 1
+        exact_rel = (5 * s ** 4 / z ** 4) / (1 + 3 * s * s / z ** 2)
+        assert abs(lab[0, 0] - np.log10(exact_rel)) < 0.02
+
+
+def test_samples_invariants_and_keep_rate():
+    b = W.plummer(2048, 41)
+    bb = oracle.build_all(b.pos, b.mass, 8)
+    f, lab, node, cnt = oracle.mac_samples(bb, 0.01, 0.3, 1.0, 1.0, 7, cap=4096)
+    assert cnt.max() < 4096
+    f2, lab2, node2, cnt2 = oracle.mac_samples(bb, 0.01, 0.3, 1.0, 0.25, 7, cap=4096)
+    assert 0.23 < cnt2.sum() / cnt.sum() < 0.27
+    t = bb["tree"]
+    for i in range(0, 2048, 97):
+        k = cnt[i]
+        ratio = f[i, :k, 0]
+        assert np.all(ratio >= 0.3 - 1e-12) and np.all(ratio < 1.0 + 1e-12)
+        assert np.all(t["count"][node[i, :k]] > 1)
+        assert np.all(np.diff(node[i, :k]) > 0)  # pre-order
+        assert np.all(np.isfinite(lab[i, :k])) and np.all(lab[i, :k] <= 1.0)
+        # kept subset is exactly the hashed selection of the full list
+        keep = [oracle.splitmix64(7 ^ ((i << 32) | int(c))) >> 11 for c in node[i, :k]]
+        sel = [c for c, h in zip(node[i, :k], keep) if h * 2.0 ** -53 < 0.25]
+        assert sel == list(node2[i, :cnt2[i]])
+
+
+def _const_net(value):
+    th = np.zeros(mlp.NPARAM)
+    th[-1] = value
+    return th
+
+
+def test_walk_mlp_limits_equal_theta_walks():
+    """A network that never accepts in the band gives the theta walk at
+    theta_lo; one that always accepts (outside the body's own cell) gives
+    the theta walk at theta_hi when theta_hi < 1/sqrt(3)."""
+    b = W.plummer(3000, 5)
+    bb = oracle.build_all(b.pos, b.mass, 8)
+    never = oracle.walk_mlp(bb, 0.01, 0.35, 0.55, -3.0, _const_net(100.0))
+    lo = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], 0.35, 0.01)
+    np.testing.assert_allclose(never.acc, lo.acc, rtol=1e-13, atol=0)
+    assert np.array_equal(never.npc, lo.npc)
+    always = oracle.walk_mlp(bb, 0.01, 0.35, 0.55, -3.0, _const_net(-100.0))
+    hi = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], 0.55, 0.01)
+    np.testing.assert_allclose(always.acc, hi.acc, rtol=1e-13, atol=0)
+    assert np.array_equal(always.npc, hi.npc)

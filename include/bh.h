@@ -189,6 +189,62 @@ int bh_sim_timing_get(bh_ctx *ctx, double *ms, int64_t *steps);
 int bh_direct(bh_ctx *ctx, const void *pos, const void *mass, int dtype, int64_t n,
               const int64_t *targets, int64_t nt, double eps, double *acc, double *phi);
 
+/* ---------------------------------------------------------------------
+ * Learned acceptance criterion (not in the paper; it stands in for the
+ * opening-angle test of Sec. 3 inside a theta band).
+ *
+ * Network: 10 features -> 32 (ReLU) -> 32 (ReLU) -> 1, predicting log10 of
+ * a cell's particle-cell error relative to the cell's exact contribution.
+ * Parameters (BH_MLP_PARAMS doubles, host): W1[32][10] b1[32] W2[32][32]
+ * b2[32] w3[32] b3, held on the device as FP32 master weights with Adam
+ * state, and packed to bf16 MFMA operands for inference.
+ * Features of a (body, cell) pair, x = body - COM, d = |x|, n = x/d,
+ * g = COM - cell centre, l = side: l/d, (l/d)^2, |g|/l, n.g/l, distance
+ * from the body to the cell's cube / d, n.Q.n/(M l^2), |Q|_F/(M l^2),
+ * log2(count)/21, eps/d, leaf (0/1).
+ * ------------------------------------------------------------------- */
+#define BH_MLP_PARAMS 1441
+
+/* Load parameters (host, FP64 values rounded to FP32); resets Adam. */
+int bh_mlp_set(bh_ctx *ctx, const double *params);
+/* Copy the current FP32 parameters to host doubles. */
+int bh_mlp_get(bh_ctx *ctx, double *params);
+
+/* Training pairs from a BH_F64 tree: for every body a walk at theta_lo;
+ * every multi-body cell with theta_lo <= side/d < theta_hi that does not
+ * contain the body is a candidate, kept iff the SplitMix64 hash of
+ * (seed ^ (rank << 32 | node)) >> 11 is below keep * 2^53.  Kept pairs are
+ * written densely, by body rank then pre-order: feat (device f32, 10 per
+ * pair), label (device f32: log10 of the relative error of the cell's
+ * quadrupole term against the direct sum over its bodies, computed in
+ * FP64, floored at -12), node and body rank (device i32).  *total gets the
+ * number of kept pairs; with feat == NULL only *total is computed.
+ * BH_E_INVALID if capacity < *total.  Synchronous. */
+int bh_mlp_samples(bh_tree *tree, double eps, double theta_lo, double theta_hi, double keep,
+                   uint64_t seed, int64_t capacity, float *feat, float *label, int32_t *node,
+                   int32_t *body, int64_t *total);
+
+typedef struct {
+    int epochs;        /* passes over the set */
+    int batch;         /* minibatch size (>= 1) */
+    double lr, beta1, beta2, eps;  /* Adam */
+    uint64_t seed;     /* per-epoch order: sample (a j + c) mod n, a coprime to n */
+} bh_mlp_train_cfg;
+
+/* Trains the loaded parameters on n pairs (device feat f32 n x 10, label
+ * f32 n) with mean-squared error and Adam, then packs them for inference.
+ * loss (host, optional): mean squared error of each epoch.  Synchronous. */
+int bh_mlp_train(bh_ctx *ctx, const float *feat, const float *label, int64_t n,
+                 const bh_mlp_train_cfg *cfg, double *loss);
+
+/* Gradient (device f32 BH_MLP_PARAMS) and mean-squared error (host) of the
+ * loaded parameters over n pairs as one batch; parameters unchanged. */
+int bh_mlp_grad(bh_ctx *ctx, const float *feat, const float *label, int64_t n, float *grad,
+                double *loss);
+
+/* bf16 MFMA inference: pred (device f32 n) for feat (device f32 n x 10). */
+int bh_mlp_infer(bh_ctx *ctx, const float *feat, int64_t n, float *pred);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,8 +23,10 @@ EXPORTED = [
     "bh_version", "bh_last_error", "bh_force_opts_default", "bh_ctx_create", "bh_ctx_set_stream",
     "bh_ctx_destroy", "bh_sync", "bh_build", "bh_tree_free", "bh_forces", "bh_tree_info_get",
     "bh_tree_export", "bh_sim_init", "bh_leapfrog_step", "bh_sim_get", "bh_energy",
-    "bh_sim_tree", "bh_direct", "bh_sim_timing", "bh_sim_timing_get",
+    "bh_sim_tree", "bh_direct", "bh_sim_timing", "bh_sim_timing_get", "bh_mlp_set",
+    "bh_mlp_get", "bh_mlp_samples", "bh_mlp_train", "bh_mlp_grad", "bh_mlp_infer",
 ]
+BH_MLP_PARAMS = 1441
 
 
 __all__ = EXPORTED + [
@@ -47,6 +49,12 @@ class ForceOpts(C.Structure):
         ("mlp_theta_lo", C.c_double), ("mlp_theta_hi", C.c_double),
         ("mlp_log10_tau", C.c_double),
     ]
+
+
+class MlpTrainCfg(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("seed", C.c_uint64)]
 
 
 class TreeInfo(C.Structure):
@@ -92,6 +100,13 @@ def load(path: str = LIB_PATH):
         "bh_direct": ([vp, vp, vp, i32, i64, vp, i64, dbl, vp, vp], i32),
         "bh_sim_timing": ([vp, i32], i32),
         "bh_sim_timing_get": ([vp, C.POINTER(dbl), C.POINTER(i64)], i32),
+        "bh_mlp_set": ([vp, vp], i32),
+        "bh_mlp_get": ([vp, vp], i32),
+        "bh_mlp_samples": ([vp, dbl, dbl, dbl, dbl, C.c_uint64, i64, vp, vp, vp, vp,
+                            C.POINTER(i64)], i32),
+        "bh_mlp_train": ([vp, vp, vp, i64, C.POINTER(MlpTrainCfg), vp], i32),
+        "bh_mlp_grad": ([vp, vp, vp, i64, vp, C.POINTER(dbl)], i32),
+        "bh_mlp_infer": ([vp, vp, i64, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -297,3 +312,77 @@ def bh_sim_timing_get(ctx) -> tuple[list, int]:
     steps = C.c_int64()
     _check(load().bh_sim_timing_get(ctx, ms, C.byref(steps)))
     return list(ms), steps.value
+
+
+# ----------------------------------------------------------------- learned criterion
+def bh_mlp_set(ctx, params):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    if p.shape != (BH_MLP_PARAMS,):
+        raise ValueError(f"params must have {BH_MLP_PARAMS} values")
+    _check(load().bh_mlp_set(ctx, C.c_void_p(p.ctypes.data)))
+
+
+def bh_mlp_get(ctx) -> np.ndarray:
+    p = np.zeros(BH_MLP_PARAMS)
+    _check(load().bh_mlp_get(ctx, C.c_void_p(p.ctypes.data)))
+    return p
+
+
+def bh_mlp_samples(tree, eps, theta_lo, theta_hi, keep, seed):
+    """Training pairs of an FP64 tree: (feat, label, node, body) GPU tensors."""
+    import torch
+    tot = C.c_int64()
+    lib = load()
+    _check(lib.bh_mlp_samples(tree, float(eps), float(theta_lo), float(theta_hi), float(keep),
+                              int(seed), 0, None, None, None, None, C.byref(tot)))
+    n = tot.value
+    dev = torch.device("cuda")
+    feat = torch.empty((max(n, 1), 10), dtype=torch.float32, device=dev)
+    label = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+    node = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    body = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    _check(lib.bh_mlp_samples(tree, float(eps), float(theta_lo), float(theta_hi), float(keep),
+                              int(seed), n, _dev(feat, "feat"), _dev(label, "label"),
+                              _dev(node, "node"), _dev(body, "body"), C.byref(tot)))
+    return feat[:n], label[:n], node[:n], body[:n]
+
+
+def _pairs(feat, label):
+    import torch
+    if feat.dtype != torch.float32 or label.dtype != torch.float32:
+        raise TypeError("feat and label must be float32")
+    n = int(label.shape[0])
+    if tuple(feat.shape) != (n, 10):
+        raise ValueError("feat must be (n, 10)")
+    return n
+
+
+def bh_mlp_train(ctx, feat, label, epochs=10, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999,
+                 eps=1e-8, seed=7) -> np.ndarray:
+    n = _pairs(feat, label)
+    cfg = MlpTrainCfg(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps),
+                      int(seed))
+    loss = np.zeros(max(int(epochs), 1))
+    _check(load().bh_mlp_train(ctx, _dev(feat, "feat"), _dev(label, "label"), n, C.byref(cfg),
+                               C.c_void_p(loss.ctypes.data)))
+    return loss[:int(epochs)]
+
+
+def bh_mlp_grad(ctx, feat, label):
+    import torch
+    n = _pairs(feat, label)
+    g = torch.empty(BH_MLP_PARAMS, dtype=torch.float32, device="cuda")
+    lv = C.c_double()
+    _check(load().bh_mlp_grad(ctx, _dev(feat, "feat"), _dev(label, "label"), n, _dev(g, "grad"),
+                              C.byref(lv)))
+    return g, lv.value
+
+
+def bh_mlp_infer(ctx, feat):
+    import torch
+    if feat.dtype != torch.float32 or feat.dim() != 2 or feat.shape[1] != 10:
+        raise ValueError("feat must be (n, 10) float32")
+    n = int(feat.shape[0])
+    pred = torch.empty(n, dtype=torch.float32, device="cuda")
+    _check(load().bh_mlp_infer(ctx, _dev(feat, "feat"), n, _dev(pred, "pred")))
+    return pred

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "bh_internal.h"
+#include "mlp.h"
 
 namespace bh {
 
@@ -170,6 +171,9 @@ int bh_ctx_destroy(bh_ctx *c) {
         delete c->sim_tree;
     }
     free_buf(c->mlp_w);
+    free_buf(c->mlp_master);
+    free_buf(c->mlp_scratch);
+    free_buf(c->mlp_gpart);
     free_buf(c->scratch);
     for (hipEvent_t e : c->events) hipEventDestroy(e);
     if (c->pinned) hipHostFree(c->pinned);
@@ -495,6 +499,127 @@ int bh_direct(bh_ctx *c, const void *pos, const void *mass, int dtype, int64_t n
     if (!(eps >= 0) || !isfinite(eps)) return set_error(BH_E_INVALID, "eps must be finite and >= 0");
     if (use_device(c)) return BH_E_DEVICE;
     return launch_direct(c->stream, dtype, n, pos, mass, targets, nt, eps, acc, phi, c->scratch);
+}
+
+// ---------------------------------------------------------------- learned criterion
+int bh_mlp_set(bh_ctx *c, const double *params) {
+    if (!c || !params) return set_error(BH_E_INVALID, "null argument");
+    for (int k = 0; k < kMlpParams; ++k)
+        if (!isfinite(params[k])) return set_error(BH_E_INVALID, "non-finite parameter");
+    if (use_device(c)) return BH_E_DEVICE;
+    int rc = grow(c->mlp_master, 3ull * 4 * kMlpParams);
+    if (rc) return rc;
+    std::vector<float> h(3 * kMlpParams, 0.f);
+    for (int k = 0; k < kMlpParams; ++k) h[k] = (float)params[k];
+    if (hipMemcpyAsync(c->mlp_master.p, h.data(), h.size() * 4, hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return set_error(BH_E_DEVICE, "parameter upload failed");
+    c->mlp_step = 0;
+    return mlp_pack(c);
+}
+
+int bh_mlp_get(bh_ctx *c, double *params) {
+    if (!c || !params) return set_error(BH_E_INVALID, "null argument");
+    if (!c->mlp_loaded) return set_error(BH_E_STATE, "no parameters loaded");
+    if (use_device(c)) return BH_E_DEVICE;
+    std::vector<float> h(kMlpParams);
+    if (hipStreamSynchronize(c->stream) != hipSuccess ||
+        hipMemcpy(h.data(), c->mlp_master.p, 4 * kMlpParams, hipMemcpyDeviceToHost) != hipSuccess)
+        return set_error(BH_E_DEVICE, "parameter copy failed");
+    for (int k = 0; k < kMlpParams; ++k) params[k] = h[k];
+    return BH_OK;
+}
+
+int bh_mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_hi, double keep,
+                   uint64_t seed, int64_t capacity, float *feat, float *label, int32_t *node,
+                   int32_t *body, int64_t *total) {
+    if (!t || !total) return set_error(BH_E_INVALID, "null argument");
+    if (t->dtype != BH_F64) return set_error(BH_E_INVALID, "training pairs need a BH_F64 tree");
+    if (!(theta_lo >= 0) || !(theta_hi > theta_lo) || !isfinite(theta_hi) || !(eps >= 0) ||
+        !isfinite(eps) || !(keep >= 0 && keep <= 1))
+        return set_error(BH_E_INVALID, "bad band, eps or keep");
+    if (feat && (!label || !node || !body || capacity < 0))
+        return set_error(BH_E_INVALID, "null output");
+    if (use_device(t->ctx)) return BH_E_DEVICE;
+    return mlp_samples(t, eps, theta_lo, theta_hi, keep, seed, capacity, feat, label, node, body,
+                       total);
+}
+
+static uint64_t gcd_u64(uint64_t a, uint64_t b) {
+    while (b) {
+        const uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+int bh_mlp_train(bh_ctx *c, const float *feat, const float *label, int64_t n,
+                 const bh_mlp_train_cfg *cfg, double *loss) {
+    if (!c || !feat || !label || !cfg) return set_error(BH_E_INVALID, "null argument");
+    if (n < 1 || n > (int64_t)0x7fffffff) return set_error(BH_E_INVALID, "n out of range");
+    if (cfg->epochs < 0 || cfg->batch < 1 || !(cfg->lr > 0) || !(cfg->beta1 >= 0 && cfg->beta1 < 1) ||
+        !(cfg->beta2 >= 0 && cfg->beta2 < 1) || !(cfg->eps > 0))
+        return set_error(BH_E_INVALID, "bad training configuration");
+    if (!c->mlp_loaded) return set_error(BH_E_STATE, "set initial parameters first");
+    if (use_device(c)) return BH_E_DEVICE;
+    const MlpTrainCfg tc{(float)cfg->lr, (float)cfg->beta1, (float)cfg->beta2, (float)cfg->eps};
+    int rc = grow(c->mlp_scratch, 64);
+    if (rc) return rc;
+    float *lacc = (float *)c->mlp_scratch.p;
+    const int bs_max = (int)(cfg->batch < n ? cfg->batch : n);
+    for (int e = 0; e < cfg->epochs; ++e) {
+        // this epoch's order: j -> (a j + b) mod n with gcd(a, n) = 1
+        uint64_t h = cfg->seed * 0x9E3779B97F4A7C15ull + (uint64_t)e * 0xD1B54A32D192ED03ull;
+        uint64_t a = (h % (uint64_t)n) | 1u;
+        while (gcd_u64(a, (uint64_t)n) != 1) a = (a + 2) % (uint64_t)n | 1u;
+        const uint64_t b = (h >> 17) % (uint64_t)n;
+        hipMemsetAsync(lacc, 0, 4, c->stream);
+        for (int64_t base = 0; base < n; base += bs_max) {
+            const int bs = (int)(n - base < bs_max ? n - base : bs_max);
+            if ((rc = mlp_grad_step(c, feat, label, n, base, bs, a, b, nullptr, lacc, true,
+                                    ++c->mlp_step, tc)))
+                return rc;
+        }
+        if (loss) {
+            float lv = 0.f;
+            if (hipMemcpyAsync(&lv, lacc, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+                hipStreamSynchronize(c->stream) != hipSuccess)
+                return set_error(BH_E_DEVICE, "loss copy failed");
+            loss[e] = (double)lv / (double)n;
+        }
+    }
+    return mlp_pack(c);
+}
+
+int bh_mlp_grad(bh_ctx *c, const float *feat, const float *label, int64_t n, float *grad,
+                double *loss) {
+    if (!c || !feat || !label || !grad) return set_error(BH_E_INVALID, "null argument");
+    if (n < 1 || n > (1 << 24)) return set_error(BH_E_INVALID, "n out of range");
+    if (!c->mlp_loaded) return set_error(BH_E_STATE, "no parameters loaded");
+    if (use_device(c)) return BH_E_DEVICE;
+    int rc = grow(c->mlp_scratch, 64);
+    if (rc) return rc;
+    float *lacc = (float *)c->mlp_scratch.p;
+    hipMemsetAsync(lacc, 0, 4, c->stream);
+    const MlpTrainCfg tc{1.f, 0.9f, 0.999f, 1e-8f};
+    if ((rc = mlp_grad_step(c, feat, label, n, 0, (int)n, 1, 0, grad, lacc, false, 1, tc)))
+        return rc;
+    float lv = 0.f;
+    if (hipMemcpyAsync(&lv, lacc, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return set_error(BH_E_DEVICE, "loss copy failed");
+    if (loss) *loss = (double)lv / (double)n;
+    return BH_OK;
+}
+
+int bh_mlp_infer(bh_ctx *c, const float *feat, int64_t n, float *pred) {
+    if (!c || !feat || !pred) return set_error(BH_E_INVALID, "null argument");
+    if (n < 1 || n > (int64_t)0x7fff0000) return set_error(BH_E_INVALID, "n out of range");
+    if (!c->mlp_loaded) return set_error(BH_E_STATE, "no parameters loaded");
+    if (use_device(c)) return BH_E_DEVICE;
+    return mlp_infer(c, feat, n, pred);
 }
 
 }  // extern "C"

@@ -91,8 +91,11 @@ struct bh_ctx {
     bh_tree *sim_tree = nullptr;
     int live_trees = 0;
     // learned acceptance criterion
-    bh::DevBuf mlp_w;                // packed weights on the device
+    bh::DevBuf mlp_w;                // packed inference weights (MlpPacked)
+    bh::DevBuf mlp_master;           // FP32 parameters, Adam m, Adam v
+    bh::DevBuf mlp_scratch, mlp_gpart;
     int mlp_loaded = 0;
+    int mlp_step = 0;                // Adam steps taken
     bh::DevBuf scratch;              // direct-sum partials
     // phase timing of simulation steps
     bool timing = false;

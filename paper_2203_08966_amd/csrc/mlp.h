@@ -1,0 +1,145 @@
+// Learned acceptance criterion: packed inference weights and the wave-level
+// bf16 MFMA evaluation (gfx950, v_mfma_f32_32x32x16_bf16).
+#pragma once
+
+#include "bh_internal.h"
+
+namespace bh {
+
+constexpr int kMlpIn = 10;
+constexpr int kMlpHidden = 32;
+constexpr int kMlpParams = 1441;  // W1 320, b1 32, W2 1024, b2 32, w3 32, b3 1
+
+struct MlpTrainCfg {
+    float lr, beta1, beta2, eps;
+};
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Per-lane operands, lane l of the wave:
+//  a1[l]    row l%32 of W1e = [W1 | b1 | 0] (hidden unit), feature slots
+//           8(l/32) .. +7 (A operand of H1^T = W1e X^T)
+//  a2[c][l] row l%32 of W2, K slots 16c + 8(l/32) + q mapped to hidden unit
+//           16c + 4(l/32) + q (q < 4) or 16c + 8 + 4(l/32) + q - 4 (q >= 4),
+//           which is where the first product leaves those units
+//  b2d/w3d  b2 and w3 of the units lane l holds in an accumulator:
+//           unit 8(v/4) + 4(l/32) + v%4 for register v
+struct MlpPacked {
+    u32x4 a1[64];
+    u32x4 a2[2][64];
+    float b2d[64][16];
+    float w3d[64][16];
+    float b3;
+};
+
+struct MlpRegs {
+    bf16x8 a1;
+    bf16x8 a2[2];
+    float b2d[16];
+    float w3d[16];
+    float b3;
+};
+
+__device__ __forceinline__ void mlp_load(const MlpPacked *__restrict__ p, int l, MlpRegs &r) {
+    r.a1 = __builtin_bit_cast(bf16x8, p->a1[l]);
+    r.a2[0] = __builtin_bit_cast(bf16x8, p->a2[0][l]);
+    r.a2[1] = __builtin_bit_cast(bf16x8, p->a2[1][l]);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        r.b2d[v] = p->b2d[l][v];
+        r.w3d[v] = p->w3d[l][v];
+    }
+    r.b3 = p->b3;
+}
+
+// Prediction for this lane's feature row.  Must be called by all 64 lanes
+// of the wave (uniform control flow).
+__device__ __forceinline__ float mlp_eval(const MlpRegs &r, const float *f, int l) {
+    bf16x8 lo, hi;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) lo[q] = (__bf16)f[q];
+    hi[0] = (__bf16)f[8];
+    hi[1] = (__bf16)f[9];
+    hi[2] = (__bf16)1.0f;
+#pragma unroll
+    for (int q = 3; q < 8; ++q) hi[q] = (__bf16)0.0f;
+    const bool upper = l >= 32;
+    // samples 0..31 are lanes 0..31, samples 32..63 lanes 32..63; the B
+    // operand wants slots 0..7 of a sample in the lower half-wave and slots
+    // 8..15 in the upper half: exchange across the halves
+    const u32x4 send = __builtin_bit_cast(u32x4, upper ? lo : hi);
+    u32x4 recv;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) recv[w] = __shfl_xor(send[w], 32);
+    const bf16x8 B0 = upper ? __builtin_bit_cast(bf16x8, recv) : lo;
+    const bf16x8 B1 = upper ? hi : __builtin_bit_cast(bf16x8, recv);
+    const f32x16 zero = {};
+    const f32x16 d0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a1, B0, zero, 0, 0, 0);
+    const f32x16 d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a1, B1, zero, 0, 0, 0);
+    bf16x8 h00, h01, h10, h11;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        h00[q] = (__bf16)fmaxf(d0[q], 0.f);
+        h01[q] = (__bf16)fmaxf(d0[8 + q], 0.f);
+        h10[q] = (__bf16)fmaxf(d1[q], 0.f);
+        h11[q] = (__bf16)fmaxf(d1[8 + q], 0.f);
+    }
+    f32x16 c2;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) c2[v] = r.b2d[v];
+    f32x16 e0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a2[0], h00, c2, 0, 0, 0);
+    e0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a2[1], h01, e0, 0, 0, 0);
+    f32x16 e1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a2[0], h10, c2, 0, 0, 0);
+    e1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a2[1], h11, e1, 0, 0, 0);
+    float p0 = 0.f, p1 = 0.f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        p0 += r.w3d[v] * fmaxf(e0[v], 0.f);
+        p1 += r.w3d[v] * fmaxf(e1[v], 0.f);
+    }
+    p0 += __shfl_xor(p0, 32);
+    p1 += __shfl_xor(p1, 32);
+    return (upper ? p1 : p0) + r.b3;
+}
+
+// Features of a (body, cell) pair in the walk's precision: X is the body
+// relative to the cell centre, x relative to the COM, d2 = |x|^2.
+template <typename R>
+__device__ __forceinline__ void mac_features(R X, R Y, R Z, R x, R y, R z, R d2, R side, R gx, R gy,
+                                         R gz, R M, R qxx, R qxy, R qxz, R qyy, R qyz, int cnt,
+                                         bool leaf, R eps, R *f) {
+    const R qzz = -qxx - qyy;
+    const R d = sqrt(d2);
+    const R id = (R)1 / d;
+    const R is = (R)1 / side;
+    f[0] = side * id;
+    f[1] = f[0] * f[0];
+    f[2] = sqrt(gx * gx + gy * gy + gz * gz) * is;
+    f[3] = (x * gx + y * gy + z * gz) * id * is;
+    const R h = (R)0.5 * side;
+    const R tx = fmax(fabs(X) - h, (R)0), ty = fmax(fabs(Y) - h, (R)0), tz = fmax(fabs(Z) - h, (R)0);
+    f[4] = sqrt(tx * tx + ty * ty + tz * tz) * id;
+    const R xqx = x * (qxx * x + qxy * y + qxz * z) + y * (qxy * x + qyy * y + qyz * z) +
+                  z * (qxz * x + qyz * y + qzz * z);
+    const R ml2 = M * side * side;
+    const R qf = sqrt(qxx * qxx + qyy * qyy + qzz * qzz + 2 * (qxy * qxy + qxz * qxz + qyz * qyz));
+    f[5] = ml2 > 0 ? xqx / (d2 * ml2) : (R)0;
+    f[6] = ml2 > 0 ? qf / ml2 : (R)0;
+    f[7] = log2((R)cnt) * (R)(1.0 / 21.0);
+    f[8] = eps * id;
+    f[9] = leaf ? (R)1 : (R)0;
+}
+
+// host entry points (mlp.hip)
+int mlp_pack(bh_ctx *c);
+int mlp_infer(bh_ctx *c, const float *X, int64_t n, float *pred);
+int mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_hi, double keep,
+                uint64_t seed, int64_t cap, float *feat, float *label, int32_t *node,
+                int32_t *body, int64_t *total);
+int mlp_grad_step(bh_ctx *c, const float *X, const float *y, int64_t ns, int64_t base, int bs,
+                  uint64_t a, uint64_t cc, float *g_out, float *loss_acc, bool apply, int step,
+                  const MlpTrainCfg &cfg);
+
+}  // namespace bh

@@ -1,0 +1,395 @@
+// Learned acceptance criterion on gfx950: training pairs, training kernels
+// and bf16 MFMA inference.
+//
+// Network 10 -> 32 (ReLU) -> 32 (ReLU) -> 1.  FP32 master parameters, flat:
+// W1[32][10] b1[32] W2[32][32] b2[32] w3[32] b3 (1441 values).
+//
+// Inference is batched per wavefront: the 64 lanes' feature rows are one
+// 64 x 16 operand (10 features, a constant 1 that carries b1, zero padding),
+// split in two 32-sample blocks.  With v_mfma_f32_32x32x16_bf16,
+//   H1^T (32 x 32) = W1e (32 x 16) . X^T (16 x 32)        1 MFMA per block
+//   H2^T (32 x 32) = W2 (32 x 32) . H1^T + b2             2 MFMAs per block
+// and the output layer is a per-lane dot product plus one cross-half add.
+// The accumulator layout of the first product (lane l holds sample l%32,
+// units 8(v/4) + 4(l/32) + v%4) is used directly as the B operand of the
+// second by permuting W2's columns when packing (no data movement).
+#include <math.h>
+
+#include "bh_internal.h"
+#include "mlp.h"
+
+namespace bh {
+namespace {
+
+__device__ __forceinline__ unsigned lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// SplitMix64 finaliser (Steele, Lea & Flood 2014) of x + golden gamma.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ------------------------------------------------------------------ training pairs
+// Walk of one wavefront over the FP64 tree at theta_lo: every multi-body
+// cell with theta_lo <= side/d < theta_hi that does not contain the body is
+// a candidate, kept when the hash of (rank, node) falls below `keep`.
+// Pass 1 (out == nullptr) counts per body; pass 2 writes at offs[rank].
+__global__ __launch_bounds__(256) void k_mac_samples(
+    const NodeRec64 *__restrict__ nodes, int m, const BodyRec<double> *__restrict__ bodies,
+    const Anchor<double> *__restrict__ anchors, int n, double tlo2, double thi2, double eps,
+    double keep, uint64_t seed, int32_t *__restrict__ cnt_out, const int64_t *__restrict__ offs,
+    int64_t cap_total, float *__restrict__ feat, float *__restrict__ label,
+    int32_t *__restrict__ node_out, int32_t *__restrict__ body_out) {
+    const int wave = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int i = wave * 64 + (int)lane_id();
+    const bool live = i < n;
+    if (wave * 64 >= n) return;
+    double ox = 0, oy = 0, oz = 0, ax = 0, ay = 0, az = 0;
+    if (live) {
+        const BodyRec<double> me = bodies[i];
+        ox = me.x;
+        oy = me.y;
+        oz = me.z;
+        const Anchor<double> an = anchors[i];
+        ax = an.x;
+        ay = an.y;
+        az = an.z;
+    }
+    const double e2 = eps * eps;
+    const uint64_t keep_lim = (uint64_t)(keep * 9007199254740992.0);  // 2^53
+    int64_t o = (live && offs) ? offs[i] : 0;
+    int k = 0;
+    int idx = nodes[0].next == 1 ? m : 1;  // a root leaf has no candidates
+    int resume = live ? idx : 0x7fffffff;
+    while (idx < m) {
+        idx = uniform(idx);
+        const NodeRec64 nd = nodes[idx];
+        const bool act = resume <= idx;
+        const int nxt = uniform(nd.next);
+        bool open = false;
+        if (nd.count > 1 && act) {
+            const double X = (ax - nd.cx) + ox, Y = (ay - nd.cy) + oy, Z = (az - nd.cz) + oz;
+            const double x = X - nd.mx, y = Y - nd.my, z = Z - nd.mz;
+            const double d2 = x * x + y * y + z * z;
+            const double s2 = nd.l2;
+            const bool below = s2 < tlo2 * d2;
+            if (!below) {
+                const double side = sqrt(s2);
+                const bool inside = fabs(X) <= 0.5 * side && fabs(Y) <= 0.5 * side &&
+                                    fabs(Z) <= 0.5 * side;
+                if (s2 < thi2 * d2 && !inside) {
+                    const uint64_t hkey = seed ^ (((uint64_t)i << 32) | (uint64_t)(uint32_t)idx);
+                    if ((splitmix64(hkey) >> 11) < keep_lim) {
+                        if (feat && o + k < cap_total) {
+                            double f[10];
+                            mac_features<double>(X, Y, Z, x, y, z, d2, side, nd.mx, nd.my, nd.mz, nd.m,
+                                             nd.qxx, nd.qxy, nd.qxz, nd.qyy, nd.qyz, nd.count,
+                                             nxt == idx + 1, eps, f);
+                            // exact contribution of the cell's bodies
+                            double ex = 0, ey = 0, ez = 0;
+                            for (int j = nd.begin; j < nd.begin + nd.count && j < n; ++j) {
+                                const BodyRec<double> s = bodies[j];
+                                const double dx = s.x + (anchors[j].x - nd.cx) - X;
+                                const double dy = s.y + (anchors[j].y - nd.cy) - Y;
+                                const double dz = s.z + (anchors[j].z - nd.cz) - Z;
+                                const double r2 = dx * dx + dy * dy + dz * dz + e2;
+                                const double ir = 1.0 / sqrt(r2);
+                                const double w = s.m * ir * ir * ir;
+                                ex += w * dx;
+                                ey += w * dy;
+                                ez += w * dz;
+                            }
+                            // the cell's quadrupole particle-cell term
+                            const double inv = 1.0 / sqrt(d2 + e2);
+                            const double inv2 = inv * inv, inv3 = inv * inv2, inv5 = inv3 * inv2;
+                            const double qzz = -nd.qxx - nd.qyy;
+                            const double qx = nd.qxx * x + nd.qxy * y + nd.qxz * z;
+                            const double qy = nd.qxy * x + nd.qyy * y + nd.qyz * z;
+                            const double qz = nd.qxz * x + nd.qyz * y + qzz * z;
+                            const double xqx = x * qx + y * qy + z * qz;
+                            const double g = nd.m * inv3 + 2.5 * xqx * inv5 * inv2;
+                            const double px = inv5 * qx - g * x, py = inv5 * qy - g * y,
+                                         pz = inv5 * qz - g * z;
+                            const double dd = sqrt((px - ex) * (px - ex) + (py - ey) * (py - ey) +
+                                                   (pz - ez) * (pz - ez));
+                            const double na = sqrt(ex * ex + ey * ey + ez * ez);
+                            double rel = na > 0 ? dd / na : 1e-12;
+                            rel = rel < 1e-12 ? 1e-12 : rel;
+                            const int64_t s = o + k;
+                            for (int q = 0; q < 10; ++q) feat[10 * s + q] = (float)f[q];
+                            label[s] = (float)log10(rel);
+                            node_out[s] = idx;
+                            body_out[s] = i;
+                        }
+                        ++k;
+                    }
+                }
+            }
+            open = !below && nxt != idx + 1;
+        }
+        const uint64_t any_open = __ballot(open);
+        if (act) resume = open ? idx + 1 : nxt;
+        idx = any_open ? idx + 1 : (nxt > idx ? nxt : idx + 1);
+    }
+    if (live && cnt_out) cnt_out[i] = k;
+}
+
+// exclusive scan of n counts (one block, any n), total at out[n]
+__global__ __launch_bounds__(1024) void k_scan_counts(const int32_t *__restrict__ c, int n,
+                                                      int64_t *__restrict__ out) {
+    __shared__ int64_t carry;
+    __shared__ int64_t ws[16];
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < n; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const int64_t x = i < n ? c[i] : 0;
+        int64_t incl = x;
+        const unsigned lane = lane_id();
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t v = __shfl_up(incl, o);
+            if ((int)lane >= o) incl += v;
+        }
+        const int w = threadIdx.x / 64;
+        if (lane == 63) ws[w] = incl;
+        __syncthreads();
+        int64_t pre = carry;
+        for (int k = 0; k < w; ++k) pre += ws[k];
+        if (i < n) out[i] = pre + incl - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = pre + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+// ------------------------------------------------------------------ training
+constexpr int kTrainBlock = 128;  // samples per block
+
+// Gradient of the mean-squared error over one minibatch.  Sample j of the
+// batch is sample (a * (base + j) + c) mod ns of the set (a permutation of
+// the set per epoch).  Each block writes its partial gradient and loss.
+__global__ __launch_bounds__(kTrainBlock) void k_mlp_grad(
+    const float *__restrict__ w, const float *__restrict__ X, const float *__restrict__ y,
+    int64_t ns, int64_t base, int bs, uint64_t a, uint64_t c, float *__restrict__ gpart) {
+    __shared__ float sw[kMlpParams];
+    __shared__ float sx[kTrainBlock][kMlpIn];
+    __shared__ float sh1[kTrainBlock][kMlpHidden];
+    __shared__ float sd1[kTrainBlock][kMlpHidden];
+    __shared__ float sh2[kTrainBlock][kMlpHidden];
+    __shared__ float sd2[kTrainBlock][kMlpHidden];
+    __shared__ float sdo[kTrainBlock];
+    __shared__ float sl[kTrainBlock];
+    const int t = threadIdx.x;
+    for (int k = t; k < kMlpParams; k += kTrainBlock) sw[k] = w[k];
+    __syncthreads();
+    const float *W1 = sw, *b1 = sw + 320, *W2 = sw + 352, *b2 = sw + 1376, *w3 = sw + 1408;
+    const float b3 = sw[1440];
+    const int j = blockIdx.x * kTrainBlock + t;
+    const bool live = j < bs;
+    float x[kMlpIn], z1[kMlpHidden], z2[kMlpHidden];
+    float yy = 0;
+    if (live) {
+        const uint64_t g = base + (uint64_t)j;
+        const int64_t sidx = (int64_t)((a * (g % (uint64_t)ns) + c) % (uint64_t)ns);
+        for (int q = 0; q < kMlpIn; ++q) x[q] = X[kMlpIn * sidx + q];
+        yy = y[sidx];
+    } else {
+        for (int q = 0; q < kMlpIn; ++q) x[q] = 0.f;
+    }
+    for (int u = 0; u < kMlpHidden; ++u) {
+        float s = b1[u];
+        for (int q = 0; q < kMlpIn; ++q) s += W1[u * kMlpIn + q] * x[q];
+        z1[u] = s;
+    }
+    for (int u = 0; u < kMlpHidden; ++u) {
+        float s = b2[u];
+        for (int q = 0; q < kMlpHidden; ++q) s += W2[u * kMlpHidden + q] * fmaxf(z1[q], 0.f);
+        z2[u] = s;
+    }
+    float out = b3;
+    for (int u = 0; u < kMlpHidden; ++u) out += w3[u] * fmaxf(z2[u], 0.f);
+    const float dout = live ? 2.f * (out - yy) / (float)bs : 0.f;
+    sl[t] = live ? (out - yy) * (out - yy) : 0.f;
+    sdo[t] = dout;
+    for (int q = 0; q < kMlpIn; ++q) sx[t][q] = x[q];
+    float d2v[kMlpHidden];
+    for (int u = 0; u < kMlpHidden; ++u) {
+        d2v[u] = z2[u] > 0.f ? dout * w3[u] : 0.f;
+        sd2[t][u] = d2v[u];
+        sh2[t][u] = fmaxf(z2[u], 0.f);
+        sh1[t][u] = fmaxf(z1[u], 0.f);
+    }
+    for (int q = 0; q < kMlpHidden; ++q) {
+        float s = 0.f;
+        for (int u = 0; u < kMlpHidden; ++u) s += W2[u * kMlpHidden + q] * d2v[u];
+        sd1[t][q] = z1[q] > 0.f ? s : 0.f;
+    }
+    __syncthreads();
+    // reduce over the block's samples, in sample order
+    float *gp = gpart + (size_t)blockIdx.x * (kMlpParams + 1);
+    for (int k = t; k < kMlpParams + 1; k += kTrainBlock) {
+        float s = 0.f;
+        if (k < 320) {  // W1[u][q] = sum d1[u] x[q]
+            const int u = k / kMlpIn, q = k % kMlpIn;
+            for (int r = 0; r < kTrainBlock; ++r) s += sd1[r][u] * sx[r][q];
+        } else if (k < 352) {
+            for (int r = 0; r < kTrainBlock; ++r) s += sd1[r][k - 320];
+        } else if (k < 1376) {  // W2[u][q] = sum d2[u] h1[q]
+            const int u = (k - 352) / kMlpHidden, q = (k - 352) % kMlpHidden;
+            for (int r = 0; r < kTrainBlock; ++r) s += sd2[r][u] * sh1[r][q];
+        } else if (k < 1408) {
+            for (int r = 0; r < kTrainBlock; ++r) s += sd2[r][k - 1376];
+        } else if (k < 1440) {
+            for (int r = 0; r < kTrainBlock; ++r) s += sdo[r] * sh2[r][k - 1408];
+        } else if (k == 1440) {
+            for (int r = 0; r < kTrainBlock; ++r) s += sdo[r];
+        } else {  // loss sum
+            for (int r = 0; r < kTrainBlock; ++r) s += sl[r];
+        }
+        gp[k] = s;
+    }
+}
+
+// Sum the partial gradients in block order; Adam step t (1-based).
+__global__ __launch_bounds__(256) void k_mlp_adam(const float *__restrict__ gpart, int nblk,
+                                                  float *__restrict__ w, float *__restrict__ m1,
+                                                  float *__restrict__ m2, float *__restrict__ g_out,
+                                                  float *__restrict__ loss_acc, float lr, float b1,
+                                                  float b2, float eps, float c1, float c2,
+                                                  int apply) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > kMlpParams) return;
+    float g = 0.f;
+    for (int b = 0; b < nblk; ++b) g += gpart[(size_t)b * (kMlpParams + 1) + k];
+    if (k == kMlpParams) {  // loss
+        if (loss_acc) loss_acc[0] += g;
+        return;
+    }
+    if (g_out) g_out[k] = g;
+    if (!apply) return;
+    const float mm = b1 * m1[k] + (1.f - b1) * g;
+    const float vv = b2 * m2[k] + (1.f - b2) * g * g;
+    m1[k] = mm;
+    m2[k] = vv;
+    w[k] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+// ------------------------------------------------------------------ inference
+// Pack FP32 master parameters into the per-lane MFMA operand layout.
+__global__ __launch_bounds__(64) void k_mlp_pack(const float *__restrict__ w,
+                                                 MlpPacked *__restrict__ p) {
+    const int l = threadIdx.x;
+    const float *W1 = w, *b1 = w + 320, *W2 = w + 352, *b2 = w + 1376, *w3 = w + 1408;
+    const int row = l & 31, h = l >> 5;
+    bf16x8 v1;
+    for (int q = 0; q < 8; ++q) {
+        const int k = 8 * h + q;  // feature slot: 0..9 weights, 10 bias, rest 0
+        const float v = k < kMlpIn ? W1[row * kMlpIn + k] : (k == kMlpIn ? b1[row] : 0.f);
+        v1[q] = (__bf16)v;
+    }
+    p->a1[l] = __builtin_bit_cast(u32x4, v1);
+    for (int c = 0; c < 2; ++c) {
+        bf16x8 v2;
+        for (int q = 0; q < 8; ++q) {
+            const int unit = q < 4 ? 16 * c + 4 * h + q : 16 * c + 8 + 4 * h + (q - 4);
+            v2[q] = (__bf16)W2[row * kMlpHidden + unit];
+        }
+        p->a2[c][l] = __builtin_bit_cast(u32x4, v2);
+    }
+    for (int v = 0; v < 16; ++v) {
+        const int unit = 8 * (v / 4) + 4 * h + (v % 4);
+        p->b2d[l][v] = b2[unit];
+        p->w3d[l][v] = w3[unit];
+    }
+    if (l == 0) p->b3 = w[1440];
+}
+
+__global__ __launch_bounds__(256) void k_mlp_infer(const MlpPacked *__restrict__ p,
+                                                   const float *__restrict__ X, int n,
+                                                   float *__restrict__ pred) {
+    const int wave = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (wave * 64 >= n) return;  // whole wave: the MFMAs need every lane
+    const int l = (int)lane_id();
+    const int i = wave * 64 + l;
+    MlpRegs r;
+    mlp_load(p, l, r);
+    float f[kMlpIn];
+    for (int q = 0; q < kMlpIn; ++q) f[q] = i < n ? X[kMlpIn * i + q] : 0.f;
+    const float y = mlp_eval(r, f, l);
+    if (i < n) pred[i] = y;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host side
+int mlp_pack(bh_ctx *c) {
+    int rc = grow(c->mlp_w, sizeof(MlpPacked));
+    if (rc) return rc;
+    k_mlp_pack<<<1, 64, 0, c->stream>>>((const float *)c->mlp_master.p, (MlpPacked *)c->mlp_w.p);
+    rc = check_launch("mlp pack");
+    if (!rc) c->mlp_loaded = 1;
+    return rc;
+}
+
+int mlp_infer(bh_ctx *c, const float *X, int64_t n, float *pred) {
+    k_mlp_infer<<<div_up(n, 256), 256, 0, c->stream>>>((const MlpPacked *)c->mlp_w.p, X, (int)n,
+                                                       pred);
+    return check_launch("mlp infer");
+}
+
+int mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_hi, double keep,
+                uint64_t seed, int64_t cap, float *feat, float *label, int32_t *node,
+                int32_t *body, int64_t *total) {
+    bh_ctx *c = t->ctx;
+    const int n = (int)t->n;
+    int rc = grow(c->mlp_scratch, 4ull * n + 8ull * (n + 1) + 8);
+    if (rc) return rc;
+    int32_t *cnt = (int32_t *)c->mlp_scratch.p;
+    int64_t *offs = (int64_t *)((char *)c->mlp_scratch.p + 4ull * n + (4ull * n) % 8);
+    const int nblk = div_up(div_up(n, 64), 4);
+    const NodeRec64 *nodes = (const NodeRec64 *)t->recs.p;
+    const auto *bodies = (const BodyRec<double> *)t->bodies.p;
+    const auto *anchors = (const Anchor<double> *)t->anchors.p;
+    k_mac_samples<<<nblk, 256, 0, c->stream>>>(nodes, (int)t->m, bodies, anchors, n,
+                                               theta_lo * theta_lo, theta_hi * theta_hi, eps, keep,
+                                               seed, cnt, nullptr, 0, nullptr, nullptr, nullptr,
+                                               nullptr);
+    k_scan_counts<<<1, 1024, 0, c->stream>>>(cnt, n, offs);
+    int64_t *hp = (int64_t *)((char *)c->pinned + 2048);
+    if ((rc = check_launch("mlp samples")) ||
+        hipMemcpyAsync(hp, offs + n, 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return rc ? rc : set_error(BH_E_DEVICE, "sample count copy failed");
+    *total = hp[0];
+    if (!feat) return BH_OK;
+    if (*total > cap)
+        return set_error(BH_E_INVALID, "sample capacity too small: need " + std::to_string(*total));
+    k_mac_samples<<<nblk, 256, 0, c->stream>>>(nodes, (int)t->m, bodies, anchors, n,
+                                               theta_lo * theta_lo, theta_hi * theta_hi, eps, keep,
+                                               seed, nullptr, offs, cap, feat, label, node, body);
+    return check_launch("mlp samples");
+}
+
+int mlp_grad_step(bh_ctx *c, const float *X, const float *y, int64_t ns, int64_t base, int bs,
+                  uint64_t a, uint64_t cc, float *g_out, float *loss_acc, bool apply, int step,
+                  const MlpTrainCfg &cfg) {
+    const int nblk = div_up(bs, kTrainBlock);
+    int rc = grow(c->mlp_gpart, 4ull * (kMlpParams + 1) * nblk);
+    if (rc) return rc;
+    k_mlp_grad<<<nblk, kTrainBlock, 0, c->stream>>>((const float *)c->mlp_master.p, X, y, ns, base,
+                                                    bs, a, cc, (float *)c->mlp_gpart.p);
+    const float c1 = 1.f - powf(cfg.beta1, (float)step), c2 = 1.f - powf(cfg.beta2, (float)step);
+    float *mst = (float *)c->mlp_master.p;
+    k_mlp_adam<<<div_up(kMlpParams + 1, 256), 256, 0, c->stream>>>(
+        (const float *)c->mlp_gpart.p, nblk, mst, mst + kMlpParams, mst + 2 * kMlpParams, g_out,
+        loss_acc, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, c1, c2, apply ? 1 : 0);
+    return check_launch("mlp train");
+}
+
+}  // namespace bh

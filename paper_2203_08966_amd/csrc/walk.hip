@@ -24,6 +24,7 @@
 // below 2^23) times h, so the difference of the body's leaf centre and any
 // cell centre is exact in FP32; adding the offset is the only rounding.
 #include "bh_internal.h"
+#include "mlp.h"
 
 namespace bh {
 namespace {
@@ -71,13 +72,19 @@ __device__ __forceinline__ void leaf_pp(const BodyRec<R> *__restrict__ bodies, i
     if (PHI) sp += pq;
 }
 
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT>
+// Learned-criterion parameters of a walk (band on side/d, threshold).
+struct MlpMac {
+    const MlpPacked *w;
+    float tlo2, thi2, log10tau;
+};
+
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool MLP>
 __global__ __launch_bounds__(256) void k_walk(
     const typename NodeRecT<R>::type *__restrict__ nodes, int m,
     const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
     const uint32_t *__restrict__ perm, int nbodies, int t0, int t1, int nwaves_padded,
     R theta2, R eps2, R *__restrict__ acc, R *__restrict__ phi_out,
-    uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out) {
+    uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out, MlpMac mac) {
     using Rec = typename NodeRecT<R>::type;
     // XCD-aware placement: consecutive workgroups land on different XCDs,
     // so hand each XCD a contiguous run of 8 logical blocks (spatially
@@ -109,6 +116,8 @@ __global__ __launch_bounds__(256) void k_walk(
     }
     R sx = 0, sy = 0, sz = 0, sp = 0;
     uint32_t cpp = 0, cpc = 0;
+    MlpRegs mr;
+    if (MLP) mlp_load(mac.w, (int)lane_id(), mr);
 
     const bool root_leaf = nodes[0].next == 1;
     int idx = root_leaf ? 0 : 1;
@@ -130,7 +139,29 @@ __global__ __launch_bounds__(256) void k_walk(
         } else {
             const R x = X - nd.mx, y = Y - nd.my, z = Z - nd.mz;
             const R d2 = x * x + y * y + z * z;
-            const bool accept = act && nd.l2 < theta2 * d2;
+            bool accept;
+            if (MLP) {
+                // below the band accept, above it (or inside the cell) open,
+                // inside it ask the network (all lanes evaluate together)
+                const bool lo_acc = act && nd.l2 < (R)mac.tlo2 * d2;
+                const R hs = (R)0.5 * sqrt(nd.l2);
+                const bool inside = fabs(X) <= hs && fabs(Y) <= hs && fabs(Z) <= hs;
+                const bool band = act && !lo_acc && nd.l2 < (R)mac.thi2 * d2 && !inside;
+                bool ml_acc = false;
+                if (__ballot(band)) {
+                    R f[kMlpIn];
+                    mac_features<R>(X, Y, Z, x, y, z, d2, (R)2 * hs, nd.mx, nd.my, nd.mz, nd.m,
+                                    nd.qxx, nd.qxy, nd.qxz, nd.qyy, nd.qyz, cnt, nxt == idx + 1,
+                                    sqrt(eps2), f);
+                    float ff[kMlpIn];
+                    for (int q = 0; q < kMlpIn; ++q) ff[q] = (float)f[q];
+                    const float pred = mlp_eval(mr, ff, (int)lane_id());
+                    ml_acc = band && pred < mac.log10tau;
+                }
+                accept = lo_acc || ml_acc;
+            } else {
+                accept = act && nd.l2 < theta2 * d2;
+            }
             {
                 if (accept) {  // skipped as a whole when no lane accepts
                     const R inv = rsq(d2 + eps2);
@@ -190,23 +221,23 @@ __global__ __launch_bounds__(256) void k_walk(
     }
 }
 
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED>
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED, bool MLP>
 void launch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
-            uint32_t *npp, uint32_t *npc) {
+            uint32_t *npp, uint32_t *npc, const MlpMac &mac) {
     const int nw = div_up(t1 - t0, 64);
     const int nblk = div_up(nw, 4);
     const int nblk_pad = div_up(nblk, 64) * 64;
-    k_walk<R, ORDER2, PHI, CNT, SORTED><<<nblk_pad, 256, 0, t->ctx->stream>>>(
+    k_walk<R, ORDER2, PHI, CNT, SORTED, MLP><<<nblk_pad, 256, 0, t->ctx->stream>>>(
         (const typename NodeRecT<R>::type *)t->recs.p, (int)t->m,
         (const BodyRec<R> *)t->bodies.p, (const Anchor<R> *)t->anchors.p, t->perm, (int)t->n, t0,
-        t1, nblk_pad * 4, (R)(theta * theta), (R)(eps * eps), (R *)acc, (R *)phi, npp, npc);
+        t1, nblk_pad * 4, (R)(theta * theta), (R)(eps * eps), (R *)acc, (R *)phi, npp, npc, mac);
 }
 
-template <typename R, bool ORDER2>
+template <typename R, bool ORDER2, bool MLP>
 void dispatch2(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
-               uint32_t *npp, uint32_t *npc, bool sorted) {
+               uint32_t *npp, uint32_t *npc, bool sorted, const MlpMac &mac) {
     const bool P = phi != nullptr, C = npp != nullptr;
-#define BH_W(p, c, s) launch<R, ORDER2, p, c, s>(t, t0, t1, theta, eps, acc, phi, npp, npc)
+#define BH_W(p, c, s) launch<R, ORDER2, p, c, s, MLP>(t, t0, t1, theta, eps, acc, phi, npp, npc, mac)
     if (sorted) {
         if (P) BH_W(true, false, true);
         else BH_W(false, false, true);
@@ -233,12 +264,21 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
         if (!npp) npp = (uint32_t *)t->cnt_scratch.p;
         else npc = (uint32_t *)t->cnt_scratch.p;
     }
-    if (t->dtype == BH_F32) {
-        if (o.order == 0) dispatch2<float, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out);
-        else dispatch2<float, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out);
+    MlpMac mac{nullptr, 0.f, 0.f, 0.f};
+    if (o.mac == BH_MAC_MLP) {
+        if (t->dtype != BH_F32 || o.order != 2)
+            return set_error(BH_E_INVALID, "the learned criterion runs in the FP32 quadrupole walk");
+        mac.w = (const MlpPacked *)t->ctx->mlp_w.p;
+        mac.tlo2 = (float)(o.mlp_theta_lo * o.mlp_theta_lo);
+        mac.thi2 = (float)(o.mlp_theta_hi * o.mlp_theta_hi);
+        mac.log10tau = (float)o.mlp_log10_tau;
+        dispatch2<float, true, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+    } else if (t->dtype == BH_F32) {
+        if (o.order == 0) dispatch2<float, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+        else dispatch2<float, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
     } else {
-        if (o.order == 0) dispatch2<double, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out);
-        else dispatch2<double, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out);
+        if (o.order == 0) dispatch2<double, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+        else dispatch2<double, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
     }
     return check_launch("walk");
 }

@@ -55,6 +55,13 @@ def test_null_handles_rejected():
     ek, ep = C.c_double(), C.c_double()
     assert lib.bh_energy(None, C.byref(ek), C.byref(ep)) == B.BH_E_INVALID
     assert lib.bh_sim_timing(None, 1) == B.BH_E_INVALID
+    assert lib.bh_mlp_set(None, None) == B.BH_E_INVALID
+    assert lib.bh_mlp_get(None, None) == B.BH_E_INVALID
+    tot = C.c_int64()
+    assert lib.bh_mlp_samples(None, 0.0, 0.3, 1.0, 1.0, 1, 0, None, None, None, None, C.byref(tot)) == B.BH_E_INVALID
+    assert lib.bh_mlp_train(None, None, None, 1, None, None) == B.BH_E_INVALID
+    assert lib.bh_mlp_grad(None, None, None, 1, None, None) == B.BH_E_INVALID
+    assert lib.bh_mlp_infer(None, None, 1, None) == B.BH_E_INVALID
     assert lib.bh_sim_timing_get(None, None, None) == B.BH_E_INVALID
 
 

@@ -62,23 +62,10 @@ def _load():
     lib.orc_build.argtypes = [C.c_int64, _u64, C.c_int] + [opt_u64] * 7
     lib.orc_build.restype = C.c_int64
     lib.orc_moments.argtypes = [C.c_int64, _i32, _u64, _i32, _i32, _f64, _f64, _f64,
-                                C.c_double, _f64, _f64, _f64]
+                                C.c_double, _f64, _f64, _f64, C.c_void_p]
     lib.orc_walk.argtypes = [C.c_int64, _i32, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
                              C.c_double, C.c_double, C.c_double, C.c_int, C.c_int64, _i64,
                              _f64, _f64, _i64, _i64, _i64, _i32]
-    lib.orc_mac_features.argtypes = [_f64, _f64, C.c_double, _f64, C.c_double, _f64, C.c_int,
-                                     C.c_int, C.c_double, _f64]
-    lib.orc_splitmix64.argtypes = [C.c_uint64]
-    lib.orc_splitmix64.restype = C.c_uint64
-    lib.orc_mlp_bf16.argtypes = [_f64, _f64]
-    lib.orc_mlp_bf16.restype = C.c_double
-    lib.orc_mac_samples.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
-                                    _f64, C.c_double, C.c_double, C.c_double, C.c_double,
-                                    C.c_double, C.c_uint64, C.c_int64, _i64, C.c_int64, _f64,
-                                    _f64, _i32, _i64]
-    lib.orc_walk_mlp.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
-                                 _f64, C.c_double, C.c_double, C.c_double, C.c_double,
-                                 C.c_double, _f64, C.c_int64, _i64, _f64, _f64, _i64, _i64, _i32]
     _lib = lib
     return lib
 
@@ -163,8 +150,11 @@ def moments(tree: dict, spos, smass, lo, L):
     M = np.zeros(m)
     com = np.zeros((m, 3))
     Q = np.zeros((m, 6))
+    trT = np.zeros(m)
     lib.orc_moments(m, tree["level"], tree["hkey"], tree["begin"], tree["count"], p.ravel(), ms,
-                    np.ascontiguousarray(lo, dtype=np.float64), float(L), M, com.ravel(), Q.ravel())
+                    np.ascontiguousarray(lo, dtype=np.float64), float(L), M, com.ravel(), Q.ravel(),
+                    trT.ctypes.data)
+    moments.trT = trT  # the last call's trace of the second moment
     return M, com, Q
 
 
@@ -215,7 +205,8 @@ def build_all(pos, mass, leaf_size: int):
     spos = p[perm]
     smass = m[perm]
     mom = moments(tree, spos, smass, lo, L)
-    return dict(lo=lo, L=L, keys=sk, perm=perm, tree=tree, mom=mom, spos=spos, smass=smass)
+    return dict(lo=lo, L=L, keys=sk, perm=perm, tree=tree, mom=mom, trT=moments.trT, spos=spos,
+                smass=smass)
 
 
 def barnes_hut(pos, mass, theta, eps, leaf_size, order=2, targets=None, built=None):
@@ -265,31 +256,57 @@ def rms_rel(acc, ref):
 
 
 # ------------------------------------------------------------------ learned criterion
-def mac_features(r, centre, side, com, M, Q, count, is_leaf, eps):
+def _mac_sigs(lib):
+    lib.orc_cell_features.argtypes = [_f64, C.c_double, _f64, C.c_double, _f64, C.c_double,
+                                      C.c_int, C.c_int, C.c_double, _f64]
+    lib.orc_splitmix64.argtypes = [C.c_uint64]
+    lib.orc_splitmix64.restype = C.c_uint64
+    lib.orc_mlp_bf16.argtypes = [_f64, _f64]
+    lib.orc_mlp_bf16.restype = C.c_double
+    lib.orc_mac_samples.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
+                                    _f64, _f64, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, C.c_uint64, C.c_int64, _i64, C.c_int64, _f64,
+                                    _f64, _i32, _i64]
+    lib.orc_cell_kc.argtypes = [C.c_int64, _i32, _u64, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
+                                C.c_double, C.c_double, C.c_void_p, _f64]
+    lib.orc_walk_kc.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64, _f64,
+                                C.c_double, C.c_double, C.c_double, C.c_double, _f64, _f64,
+                                C.c_int64, _i64, _f64, _f64, _i64, _i64, _i64, _i32]
+    return lib
+
+
+def _mlib():
+    lib = _load()
+    if not getattr(lib, "_mac_ready", False):
+        _mac_sigs(lib)
+        lib._mac_ready = True
+    return lib
+
+
+def cell_features(centre, side, com, M, Q, trT, count, is_leaf, eps):
     f = np.zeros(10)
-    _load().orc_mac_features(np.ascontiguousarray(r, dtype=np.float64),
-                             np.ascontiguousarray(centre, dtype=np.float64), float(side),
-                             np.ascontiguousarray(com, dtype=np.float64), float(M),
-                             np.ascontiguousarray(Q, dtype=np.float64), int(count), int(is_leaf),
-                             float(eps), f)
+    _mlib().orc_cell_features(np.ascontiguousarray(centre, dtype=np.float64), float(side),
+                              np.ascontiguousarray(com, dtype=np.float64), float(M),
+                              np.ascontiguousarray(Q, dtype=np.float64), float(trT), int(count),
+                              int(is_leaf), float(eps), f)
     return f
 
 
 def splitmix64(x: int) -> int:
-    return int(_load().orc_splitmix64(x))
+    return int(_mlib().orc_splitmix64(x))
 
 
 def mlp_bf16(params, f) -> float:
-    return float(_load().orc_mlp_bf16(np.ascontiguousarray(params, dtype=np.float64),
+    return float(_mlib().orc_mlp_bf16(np.ascontiguousarray(params, dtype=np.float64),
                                       np.ascontiguousarray(f, dtype=np.float64)))
 
 
-def mac_samples(b, eps, theta_lo, theta_hi, keep, seed, targets=None, cap=4096):
-    """Learned-criterion training pairs of the bodies ``targets`` (sorted
-    ranks; all by default) over a tree from build_all: per target up to
-    ``cap`` kept candidates in pre-order.  Returns (feat, label, node, count)
-    with feat (nt, cap, 10)."""
-    lib = _load()
+def mac_samples(b, eps, theta_lo, theta_max, keep, seed, targets=None, cap=4096):
+    """Training pairs of the bodies ``targets`` (sorted ranks; all by
+    default) over a tree from build_all: per target up to ``cap`` kept
+    candidates in pre-order.  Returns (feat (nt, cap, 10) cell features,
+    label (nt, cap), node, count)."""
+    lib = _mlib()
     t = b["tree"]
     M, com, Q = b["mom"]
     n = b["smass"].shape[0]
@@ -300,15 +317,31 @@ def mac_samples(b, eps, theta_lo, theta_hi, keep, seed, targets=None, cap=4096):
     node = np.full((nt, cap), -1, dtype=np.int32)
     cnt = np.zeros(nt, dtype=np.int64)
     lib.orc_mac_samples(t["level"], t["hkey"], t["begin"], t["count"], t["next"], M, com.ravel(),
-                        Q.ravel(), b["spos"].ravel(), b["smass"], np.ascontiguousarray(b["lo"]),
-                        float(b["L"]), float(eps), float(theta_lo), float(theta_hi), float(keep),
-                        int(seed), nt, tg, int(cap), feat.ravel(), label.ravel(), node.ravel(), cnt)
+                        Q.ravel(), b["trT"], b["spos"].ravel(), b["smass"],
+                        np.ascontiguousarray(b["lo"]), float(b["L"]), float(eps), float(theta_lo),
+                        float(theta_max), float(keep), int(seed), nt, tg, int(cap), feat.ravel(),
+                        label.ravel(), node.ravel(), cnt)
     return feat, label, node, cnt
 
 
-def walk_mlp(b, eps, theta_lo, theta_hi, log10tau, params, targets=None):
-    """Tree walk with the learned criterion (bf16 view of the network)."""
-    lib = _load()
+def cell_kc(b, eps, params=None):
+    """Per cell k_C M l^3 (k_C = 1 without a network)."""
+    lib = _mlib()
+    t = b["tree"]
+    M, com, Q = b["mom"]
+    m = M.shape[0]
+    kc = np.zeros(m)
+    pp = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+    lib.orc_cell_kc(m, t["level"], t["hkey"], t["count"], t["next"], M, com.ravel(), Q.ravel(),
+                    b["trT"], np.ascontiguousarray(b["lo"]), float(b["L"]), float(eps),
+                    None if pp is None else pp.ctypes.data, kc)
+    return kc
+
+
+def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None):
+    """Walk with the learned (or, k_C = 1, relative) criterion; anorm is
+    |a_i| per sorted rank."""
+    lib = _mlib()
     t = b["tree"]
     M, com, Q = b["mom"]
     n = b["smass"].shape[0]
@@ -318,10 +351,12 @@ def walk_mlp(b, eps, theta_lo, theta_hi, log10tau, params, targets=None):
     phi = np.zeros(nt)
     npp = np.zeros(nt, dtype=np.int64)
     npc = np.zeros(nt, dtype=np.int64)
+    ncov = np.zeros(nt, dtype=np.int64)
     flag = np.zeros(nt, dtype=np.int32)
-    lib.orc_walk_mlp(t["level"], t["hkey"], t["begin"], t["count"], t["next"], M, com.ravel(),
-                     Q.ravel(), b["spos"].ravel(), b["smass"], np.ascontiguousarray(b["lo"]),
-                     float(b["L"]), float(eps), float(theta_lo), float(theta_hi), float(log10tau),
-                     np.ascontiguousarray(params, dtype=np.float64), nt, tg, acc.ravel(), phi,
-                     npp, npc, flag)
-    return WalkResult(acc, phi, npp, npc, np.zeros(nt, dtype=np.int64), flag)
+    lib.orc_walk_kc(t["level"], t["hkey"], t["begin"], t["count"], t["next"], M, com.ravel(),
+                    Q.ravel(), b["spos"].ravel(), b["smass"], np.ascontiguousarray(b["lo"]),
+                    float(b["L"]), float(eps), float(theta_max),
+                    float(tau), np.ascontiguousarray(kc, dtype=np.float64),
+                    np.ascontiguousarray(anorm, dtype=np.float64), nt, tg, acc.ravel(), phi, npp,
+                    npc, ncov, flag)
+    return WalkResult(acc, phi, npp, npc, ncov, flag)

@@ -241,11 +241,12 @@ int64_t orc_build(int64_t n, const uint64_t *sorted_keys, int leaf_size, uint64_
  * mass), and Q_ab = sum m (3 y_a y_b - |y|^2 delta_ab) with y the body's
  * offset from the COM.  Computed per cell directly from its bodies.
  * A massless cell gets its geometric centre as COM and Q = 0.
- * Q layout: xx, xy, xz, yy, yz, zz.
+ * Q layout: xx, xy, xz, yy, yz, zz.  trT (optional): sum m |y|^2, the trace
+ * of the second moment about the COM, which the traceless Q does not carry.
  * ---------------------------------------------------------------------- */
 void orc_moments(int64_t m, const int32_t *level, const uint64_t *hkey, const int32_t *begin,
                  const int32_t *count, const double *spos, const double *smass,
-                 const double *lo, double L, double *M, double *com, double *Q)
+                 const double *lo, double L, double *M, double *com, double *Q, double *trT)
 {
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t c = 0; c < m; ++c) {
@@ -278,7 +279,7 @@ void orc_moments(int64_t m, const int32_t *level, const uint64_t *hkey, const in
             cy = lo[1] + (iy + 0.5) * side;
             cz = lo[2] + (iz + 0.5) * side;
         }
-        double q[6] = {0, 0, 0, 0, 0, 0};
+        double q[6] = {0, 0, 0, 0, 0, 0}, tr = 0.0;
         for (int64_t j = b; j < e; ++j) {
             const double y0 = spos[3 * j + 0] - cx;
             const double y1 = spos[3 * j + 1] - cy;
@@ -291,7 +292,10 @@ void orc_moments(int64_t m, const int32_t *level, const uint64_t *hkey, const in
             q[3] += mj * (3.0 * y1 * y1 - r2);
             q[4] += mj * (3.0 * y1 * y2);
             q[5] += mj * (3.0 * y2 * y2 - r2);
+            tr += mj * r2;
         }
+        if (trT)
+            trT[c] = tr;
         M[c] = mt;
         com[3 * c + 0] = cx;
         com[3 * c + 1] = cy;
@@ -451,15 +455,22 @@ void orc_walk(int64_t m, const int32_t *level, const int32_t *begin, const int32
 /* ========================================================================
  * Learned acceptance criterion.
  *
- * Features of a (body, cell) pair, all scale-free (x = body - COM, d = |x|,
- * n = x/d, g = COM - cell centre, l = cell side, Q the traceless quadrupole):
- *   f0 l/d            f1 (l/d)^2          f2 |g|/l        f3 n.g/l
- *   f4 distance from the body to the cell's cube / d (0 inside)
- *   f5 n.Q.n/(M l^2)  f6 |Q|_F/(M l^2)    f7 log2(count)/21
- *   f8 eps/d          f9 1 if the cell is a leaf
- * Label: log10 of |a_pc - a_exact| / |a_exact|, the error of the cell's
- * particle-cell term (order 2) relative to the cell's exact contribution
- * (direct sum over its bodies), floored at 1e-12.
+ * The error a cell's particle-cell term (order 2) makes on body i is
+ * modelled as |da| = k_C (l/d)^3 M/d^2 with a per-cell coefficient k_C that
+ * a network predicts from the cell alone (log10 k_C); the walk accepts the
+ * cell iff l^2 < theta_max^2 d^2 and k_C M l^3 < tau |a_i| d^5, i.e. iff the
+ * predicted error is below tau times the body's acceleration.  With k_C = 1
+ * this is a relative opening criterion; the network refines k_C from the
+ * cell's mass distribution.
+ *
+ * Cell features (scale-free; l side, g = COM - centre, M mass, n count,
+ * T2 = sum m |y|^2 about the COM, Q traceless quadrupole):
+ *   f0 |g|/l              f1 sqrt(T2/M)/l          f2 |Q|_F/(M l^2)
+ *   f3 cbrt(det Q)/(M l^2)  f4 max_a |g_a|/l      f5 log2(n)/21
+ *   f6 1 if leaf           f7 eps/l                f8 1/sqrt(n)
+ *   f9 T2/(M l^2)
+ * Label of a (body, cell) pair: log10(|a_pc - a_exact| d^5 / (M l^3)),
+ * a_exact the direct sum over the cell's bodies, floored at -12 inside.
  * ====================================================================== */
 
 /* cell centre from the hashed key */
@@ -479,42 +490,34 @@ static void cell_centre(uint64_t hkey, int k, const double *lo, double L, double
     c[2] = lo[2] + (iz + 0.5) * side;
 }
 
-void orc_mac_features(const double *r, const double *centre, double side, const double *com,
-                      double M, const double *Q, int count, int is_leaf, double eps, double *f)
+void orc_cell_features(const double *centre, double side, const double *com, double M,
+                       const double *Q, double trT, int count, int is_leaf, double eps, double *f)
 {
-    double x[3], g[3], n[3];
+    double g[3], gmax = 0.0;
     for (int a = 0; a < 3; ++a) {
-        x[a] = r[a] - com[a];
         g[a] = com[a] - centre[a];
+        if (fabs(g[a]) > gmax)
+            gmax = fabs(g[a]);
     }
-    const double d = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-    for (int a = 0; a < 3; ++a)
-        n[a] = x[a] / d;
-    f[0] = side / d;
-    f[1] = f[0] * f[0];
-    f[2] = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / side;
-    f[3] = (n[0] * g[0] + n[1] * g[1] + n[2] * g[2]) / side;
-    double db2 = 0.0;
-    for (int a = 0; a < 3; ++a) {
-        double t = fabs(r[a] - centre[a]) - 0.5 * side;
-        if (t > 0.0)
-            db2 += t * t;
-    }
-    f[4] = sqrt(db2) / d;
-    /* full symmetric Q from xx xy xz yy yz zz */
-    const double q[3][3] = {{Q[0], Q[1], Q[2]}, {Q[1], Q[3], Q[4]}, {Q[2], Q[4], Q[5]}};
-    double nqn = 0.0, qf = 0.0;
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
-            nqn += n[a] * q[a][b] * n[b];
-            qf += q[a][b] * q[a][b];
-        }
     const double ml2 = M * side * side;
-    f[5] = ml2 > 0.0 ? nqn / ml2 : 0.0;
-    f[6] = ml2 > 0.0 ? sqrt(qf) / ml2 : 0.0;
-    f[7] = log2((double)count) / 21.0;
-    f[8] = eps / d;
-    f[9] = is_leaf ? 1.0 : 0.0;
+    const double q[3][3] = {{Q[0], Q[1], Q[2]}, {Q[1], Q[3], Q[4]}, {Q[2], Q[4], Q[5]}};
+    double qf = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            qf += q[a][b] * q[a][b];
+    const double det = q[0][0] * (q[1][1] * q[2][2] - q[1][2] * q[2][1]) -
+                       q[0][1] * (q[1][0] * q[2][2] - q[1][2] * q[2][0]) +
+                       q[0][2] * (q[1][0] * q[2][1] - q[1][1] * q[2][0]);
+    f[0] = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / side;
+    f[1] = M > 0.0 ? sqrt(trT / M) / side : 0.0;
+    f[2] = ml2 > 0.0 ? sqrt(qf) / ml2 : 0.0;
+    f[3] = ml2 > 0.0 ? cbrt(det) / ml2 : 0.0;
+    f[4] = gmax / side;
+    f[5] = log2((double)count) / 21.0;
+    f[6] = is_leaf ? 1.0 : 0.0;
+    f[7] = eps / side;
+    f[8] = 1.0 / sqrt((double)count);
+    f[9] = ml2 > 0.0 ? trT / ml2 : 0.0;
 }
 
 /* SplitMix64 (Steele, Lea & Flood 2014): the finaliser applied to x. */
@@ -578,51 +581,50 @@ double orc_mlp_bf16(const double *p, const double *f)
 typedef struct {
     walk_ctx w;
     const uint64_t *hkey;
-    const double *lo;
-    double tlo2, thi2, eps;
+    const double *lo, *trT;
+    double tlo2, tmax2, eps;
     /* samples */
     uint64_t seed;
     double keep;
-    int64_t cap, slot0, n_cand;
+    int64_t cap, slot0;
     double *feat, *label;
     int32_t *node;
     /* learned decision */
-    const double *mlp;
-    double log10tau;
+    const double *kc;  /* per cell k_C M l^3 */
+    double tau, anorm; /* tau and |a_i| of the current body */
 } mac_ctx;
 
-static void cell_label(const mac_ctx *m, int64_t i, int64_t c, double *lab)
+static void features_of(const mac_ctx *m, int64_t c, double *f)
+{
+    const walk_ctx *w = &m->w;
+    double centre[3];
+    cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
+    orc_cell_features(centre, ldexp(w->L, -w->level[c]), &w->com[3 * c], w->M[c], &w->Q[6 * c],
+                      m->trT[c], w->count[c], w->next[c] == c + 1, m->eps, f);
+}
+
+static void pair_label(const mac_ctx *m, int64_t i, int64_t c, const double x[3], double d2,
+                       double *lab)
 {
     const walk_ctx *w = &m->w;
     walk_acc ex, ap;
     memset(&ex, 0, sizeof(ex));
     memset(&ap, 0, sizeof(ap));
     leaf_pp(w, i, c, &ex);
-    double x[3];
-    for (int d = 0; d < 3; ++d)
-        x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
-    pc(w, i, c, x, x[0] * x[0] + x[1] * x[1] + x[2] * x[2], &ap);
+    pc(w, i, c, x, d2, &ap);
     const double e0 = ap.a[0] - ex.a[0], e1 = ap.a[1] - ex.a[1], e2 = ap.a[2] - ex.a[2];
-    const double ne = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-    const double na = sqrt(ex.a[0] * ex.a[0] + ex.a[1] * ex.a[1] + ex.a[2] * ex.a[2]);
-    double rel = na > 0.0 ? ne / na : 1e-12;
-    if (rel < 1e-12)
-        rel = 1e-12;
-    *lab = log10(rel);
+    const double side = ldexp(w->L, -w->level[c]);
+    const double d = sqrt(d2);
+    double v = sqrt(e0 * e0 + e1 * e1 + e2 * e2) * d2 * d2 * d / (w->M[c] * side * side * side);
+    if (!(v > 1e-12))
+        v = 1e-12;
+    *lab = log10(v);
 }
 
-static void pair_features(const mac_ctx *m, int64_t i, int64_t c, double *f)
-{
-    const walk_ctx *w = &m->w;
-    double centre[3];
-    cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
-    orc_mac_features(&w->spos[3 * i], centre, ldexp(w->L, -w->level[c]), &w->com[3 * c],
-                     w->M[c], &w->Q[6 * c], w->count[c], w->next[c] == c + 1, m->eps, f);
-}
-
-/* Candidates of body i: walk at theta_lo (everything at or above theta_lo
- * is opened); every multi-body cell with theta_lo <= l/d < theta_hi that
- * does not contain the body is a candidate; candidates kept by the hash. */
+/* Candidates of body i: walk at theta_lo (cells with l/d < theta_lo are
+ * left alone, all others opened); every multi-body cell with
+ * theta_lo <= l/d < theta_max that does not contain the body is a
+ * candidate, kept by the hash. */
 static void sample_walk(mac_ctx *m, int64_t node, int64_t i, int64_t *k)
 {
     const walk_ctx *w = &m->w;
@@ -634,21 +636,18 @@ static void sample_walk(mac_ctx *m, int64_t node, int64_t i, int64_t *k)
         for (int d = 0; d < 3; ++d)
             x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
         const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-        const double s2 = side * side;
-        if (s2 < m->tlo2 * d2)
-            continue; /* accepted below the band */
-        if (s2 < m->thi2 * d2) {
+        if (side * side < m->tlo2 * d2)
+            continue;
+        if (side * side < m->tmax2 * d2) {
             double centre[3];
             cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
-            if (!inside_cell(&w->spos[3 * i], centre, side)) {
-                m->n_cand++;
-                if (keep_pair(m->seed, i, c, m->keep) && *k < m->cap) {
-                    const int64_t o = m->slot0 + *k;
-                    pair_features(m, i, c, &m->feat[10 * o]);
-                    cell_label(m, i, c, &m->label[o]);
-                    m->node[o] = (int32_t)c;
-                    ++*k;
-                }
+            if (!inside_cell(&w->spos[3 * i], centre, side) && keep_pair(m->seed, i, c, m->keep) &&
+                *k < m->cap) {
+                const int64_t o = m->slot0 + *k;
+                features_of(m, c, &m->feat[10 * o]);
+                pair_label(m, i, c, x, d2, &m->label[o]);
+                m->node[o] = (int32_t)c;
+                ++*k;
             }
         }
         if (w->next[c] != c + 1)
@@ -657,12 +656,13 @@ static void sample_walk(mac_ctx *m, int64_t node, int64_t i, int64_t *k)
 }
 
 /* Per target rank t (targets are sorted ranks): up to cap kept candidates in
- * pre-order at slot t*cap.. of feat (10 each), label, node; count[t]. */
+ * pre-order at slot t*cap.. of feat (10 cell features each), label, node;
+ * count[t]. */
 void orc_mac_samples(const int32_t *level, const uint64_t *hkey, const int32_t *begin,
                      const int32_t *count, const int32_t *next, const double *M,
-                     const double *com, const double *Q, const double *spos,
+                     const double *com, const double *Q, const double *trT, const double *spos,
                      const double *smass, const double *lo, double L, double eps,
-                     double theta_lo, double theta_hi, double keep, uint64_t seed, int64_t nt,
+                     double theta_lo, double theta_max, double keep, uint64_t seed, int64_t nt,
                      const int64_t *targets, int64_t cap, double *feat, double *label,
                      int32_t *node, int64_t *cnt)
 {
@@ -673,8 +673,9 @@ void orc_mac_samples(const int32_t *level, const uint64_t *hkey, const int32_t *
         m.w = (walk_ctx){level, begin, count, next, M, com, Q, spos, smass, L, 0.0, eps * eps, 2};
         m.hkey = hkey;
         m.lo = lo;
+        m.trT = trT;
         m.tlo2 = theta_lo * theta_lo;
-        m.thi2 = theta_hi * theta_hi;
+        m.tmax2 = theta_max * theta_max;
         m.eps = eps;
         m.seed = seed;
         m.keep = keep;
@@ -690,12 +691,35 @@ void orc_mac_samples(const int32_t *level, const uint64_t *hkey, const int32_t *
     }
 }
 
-/* Tree walk with the learned criterion: below theta_lo accept, at or above
- * theta_hi or with the body inside the cell open, otherwise accept iff the
- * network's predicted log10 relative error is below log10tau.  The flag also
- * marks decisions within 1e-3 of log10tau and bodies within 1e-6 side of a
- * cell face, where a reduced-precision evaluation may decide the other way. */
-static void cell_force_mlp(mac_ctx *m, int64_t node, int64_t i, walk_acc *r)
+/* Per cell: k_C M l^3 with log10 k_C from the bf16 network (params) or
+ * k_C = 1 (params NULL). */
+void orc_cell_kc(int64_t m, const int32_t *level, const uint64_t *hkey, const int32_t *count,
+                 const int32_t *next, const double *M, const double *com, const double *Q,
+                 const double *trT, const double *lo, double L, double eps, const double *params,
+                 double *kc)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < m; ++c) {
+        const double side = ldexp(L, -level[c]);
+        double lk = 0.0;
+        if (params) {
+            double centre[3], f[10];
+            cell_centre(hkey[c], level[c], lo, L, centre);
+            orc_cell_features(centre, side, &com[3 * c], M[c], &Q[6 * c], trT[c], count[c],
+                              next[c] == c + 1, eps, f);
+            lk = orc_mlp_bf16(params, f);
+        }
+        kc[c] = pow(10.0, lk) * M[c] * side * side * side;
+    }
+}
+
+/* Tree walk with the learned criterion: a multi-body cell is accepted iff
+ * l^2 < theta_max^2 d^2, the body is outside the cell, and
+ * kc_C < tau |a_i| d^5 (one-body cells and rejected leaves
+ * particle-particle, rejected internal cells opened).  The flag marks tests
+ * within a relative 1e-5 of a threshold and bodies within 1e-6 l of a face
+ * of a cell they are tested against. */
+static void cell_force_kc(mac_ctx *m, int64_t node, int64_t i, walk_acc *r)
 {
     const walk_ctx *w = &m->w;
     for (int64_t c = node + 1; c < w->next[node]; c = w->next[c]) {
@@ -710,46 +734,31 @@ static void cell_force_mlp(mac_ctx *m, int64_t node, int64_t i, walk_acc *r)
             x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
         const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
         const double s2 = side * side;
-        int accept;
-        if (fabs(s2 - m->tlo2 * d2) < 1e-5 * s2 || fabs(s2 - m->thi2 * d2) < 1e-5 * s2)
+        const double lhs = m->kc[c], rhs = m->tau * m->anorm * d2 * d2 * sqrt(d2);
+        if (fabs(s2 - m->tmax2 * d2) < 1e-5 * s2 || fabs(lhs - rhs) < 1e-5 * lhs)
             r->flag = 1;
-        if (s2 < m->tlo2 * d2) {
-            accept = 1;
-        } else if (s2 >= m->thi2 * d2) {
-            accept = 0;
-        } else {
-            double centre[3];
-            cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
-            int in = inside_cell(&w->spos[3 * i], centre, side);
-            for (int a = 0; a < 3; ++a)
-                if (fabs(fabs(w->spos[3 * i + a] - centre[a]) - 0.5 * side) < 1e-6 * side)
-                    r->flag = 1;
-            if (in) {
-                accept = 0;
-            } else {
-                double f[10];
-                pair_features(m, i, c, f);
-                const double pred = orc_mlp_bf16(m->mlp, f);
-                if (fabs(pred - m->log10tau) < 1e-3)
-                    r->flag = 1;
-                accept = pred < m->log10tau;
-            }
-        }
-        if (accept)
+        double centre[3];
+        cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
+        for (int a = 0; a < 3; ++a)
+            if (fabs(fabs(w->spos[3 * i + a] - centre[a]) - 0.5 * side) < 1e-6 * side)
+                r->flag = 1;
+        const int in = inside_cell(&w->spos[3 * i], centre, side);
+        if (s2 < m->tmax2 * d2 && !in && lhs < rhs)
             pc(w, i, c, x, d2, r);
         else if (w->next[c] == c + 1)
             leaf_pp(w, i, c, r);
         else
-            cell_force_mlp(m, c, i, r);
+            cell_force_kc(m, c, i, r);
     }
 }
 
-void orc_walk_mlp(const int32_t *level, const uint64_t *hkey, const int32_t *begin,
-                  const int32_t *count, const int32_t *next, const double *M, const double *com,
-                  const double *Q, const double *spos, const double *smass, const double *lo,
-                  double L, double eps, double theta_lo, double theta_hi, double log10tau,
-                  const double *mlp, int64_t nt, const int64_t *targets, double *acc,
-                  double *phi, int64_t *npp, int64_t *npc, int32_t *flag)
+void orc_walk_kc(const int32_t *level, const uint64_t *hkey, const int32_t *begin,
+                 const int32_t *count, const int32_t *next, const double *M, const double *com,
+                 const double *Q, const double *spos, const double *smass, const double *lo,
+                 double L, double eps, double theta_max,
+                 double tau, const double *kc, const double *anorm, int64_t nt,
+                 const int64_t *targets, double *acc, double *phi, int64_t *npp, int64_t *npc,
+                 int64_t *ncov, int32_t *flag)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nt; ++t) {
@@ -758,23 +767,23 @@ void orc_walk_mlp(const int32_t *level, const uint64_t *hkey, const int32_t *beg
         m.w = (walk_ctx){level, begin, count, next, M, com, Q, spos, smass, L, 0.0, eps * eps, 2};
         m.hkey = hkey;
         m.lo = lo;
-        m.tlo2 = theta_lo * theta_lo;
-        m.thi2 = theta_hi * theta_hi;
-        m.eps = eps;
-        m.mlp = mlp;
-        m.log10tau = log10tau;
+        m.tmax2 = theta_max * theta_max;
+        m.kc = kc;
+        m.tau = tau;
         const int64_t i = targets[t];
+        m.anorm = anorm[i];
         walk_acc r;
         memset(&r, 0, sizeof(r));
         if (next[0] == 1)
             leaf_pp(&m.w, i, 0, &r);
         else
-            cell_force_mlp(&m, 0, i, &r);
+            cell_force_kc(&m, 0, i, &r);
         for (int d = 0; d < 3; ++d)
             acc[3 * t + d] = r.a[d];
         if (phi) phi[t] = r.phi;
         if (npp) npp[t] = r.npp;
         if (npc) npc[t] = r.npc;
+        if (ncov) ncov[t] = r.ncov;
         if (flag) flag[t] = r.flag;
     }
 }

@@ -71,14 +71,17 @@ def test_splitmix64_reference_outputs():
     assert outs == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
 
 
-def test_features_closed_form():
-    """Body on the x axis at distance 2 from a unit cell centred at the
-    origin holding masses m at +-s z (COM at the centre)."""
+def test_cell_features_closed_form():
+    """Unit cell centred at the origin holding masses m at +-s z around a COM
+    offset g = (0.1, 0, 0): T2 = 2 m s^2, Q_zz = 4 m s^2, Q_xx = Q_yy = -2 m s^2."""
     m, s = 0.25, 0.2
+    M = 2 * m
     Q = np.array([-2 * m * s * s, 0, 0, -2 * m * s * s, 0, 4 * m * s * s])
-    f = oracle.mac_features([2.0, 0, 0], [0, 0, 0], 1.0, [0, 0, 0], 2 * m, Q, 2, 1, 0.1)
-    expect = [0.5, 0.25, 0.0, 0.0, 1.5 / 2.0, -2 * m * s * s / (2 * m),
-              np.sqrt(16 + 4 + 4) * m * s * s / (2 * m), 1 / 21, 0.05, 1.0]
+    trT = 2 * m * s * s
+    f = oracle.cell_features([0, 0, 0], 1.0, [0.1, 0, 0], M, Q, trT, 2, 1, 0.01)
+    det = (-2 * m * s * s) ** 2 * (4 * m * s * s)
+    expect = [0.1, np.sqrt(trT / M), np.sqrt(16 + 4 + 4) * m * s * s / M, np.cbrt(det) / M,
+              0.1, 1 / 21, 1.0, 0.01, 1 / np.sqrt(2), trT / M]
     np.testing.assert_allclose(f, expect, rtol=1e-14, atol=1e-15)
 
 
@@ -91,15 +94,17 @@ def _pair_tree(z, s, m=0.4):
 
 def test_label_two_mass_closed_form():
     """Label of the on-axis pair cell: the quadrupole's remaining error is
-    the next term, relative size 5 s^4/z^4 / (1 + 3 s^2/z^2 + ...)."""
+    the next term, |da| = (2m/z^2)(5 s^4/z^4) to leading order, so the
+    label log10(|da| d^5/(M l^3)) is log10(5 s^4/(z l^3))."""
     s = 0.01
     for z in (0.3, 0.4, 0.6):
         bb = _pair_tree(z, s)
         rank = int(np.nonzero(bb["perm"] == 2)[0][0])
         f, lab, node, cnt = oracle.mac_samples(bb, 0.0, 0.0, 100.0, 1.0, 1, targets=[rank], cap=8)
         assert cnt[0] == 1
-        exact_rel = (5 * s ** 4 / z ** 4) / (1 + 3 * s * s / z ** 2)
-        assert abs(lab[0, 0] - np.log10(exact_rel)) < 0.02
+        side = bb["L"] * 2.0 ** -bb["tree"]["level"][node[0, 0]]
+        expect = np.log10(5 * s ** 4 / (z * side ** 3)) - np.log10(1 + 3 * s * s / z ** 2)
+        assert abs(lab[0, 0] - expect) < 0.02
 
 
 def test_samples_invariants_and_keep_rate():
@@ -110,36 +115,78 @@ def test_samples_invariants_and_keep_rate():
     f2, lab2, node2, cnt2 = oracle.mac_samples(bb, 0.01, 0.3, 1.0, 0.25, 7, cap=4096)
     assert 0.23 < cnt2.sum() / cnt.sum() < 0.27
     t = bb["tree"]
+    M, com, Q = bb["mom"]
     for i in range(0, 2048, 97):
         k = cnt[i]
-        ratio = f[i, :k, 0]
+        c = node[i, :k]
+        x = bb["spos"][i] - com[c]
+        ratio = bb["L"] * 2.0 ** -t["level"][c] / np.linalg.norm(x, axis=1)
         assert np.all(ratio >= 0.3 - 1e-12) and np.all(ratio < 1.0 + 1e-12)
-        assert np.all(t["count"][node[i, :k]] > 1)
-        assert np.all(np.diff(node[i, :k]) > 0)  # pre-order
-        assert np.all(np.isfinite(lab[i, :k])) and np.all(lab[i, :k] <= 1.0)
+        assert np.all(t["count"][c] > 1)
+        assert np.all(np.diff(c) > 0)  # pre-order
+        assert np.all(np.isfinite(lab[i, :k]))
         # kept subset is exactly the hashed selection of the full list
-        keep = [oracle.splitmix64(7 ^ ((i << 32) | int(c))) >> 11 for c in node[i, :k]]
-        sel = [c for c, h in zip(node[i, :k], keep) if h * 2.0 ** -53 < 0.25]
+        keep = [oracle.splitmix64(7 ^ ((i << 32) | int(q))) >> 11 for q in c]
+        sel = [q for q, h in zip(c, keep) if h * 2.0 ** -53 < 0.25]
         assert sel == list(node2[i, :cnt2[i]])
 
 
-def _const_net(value):
+def test_cell_kc_without_network():
+    b = W.plummer(1000, 2)
+    bb = oracle.build_all(b.pos, b.mass, 8)
+    kc = oracle.cell_kc(bb, 0.01)
+    side = bb["L"] * 2.0 ** -bb["tree"]["level"]
+    np.testing.assert_allclose(kc, bb["mom"][0] * side ** 3, rtol=1e-15)
     th = np.zeros(mlp.NPARAM)
-    th[-1] = value
-    return th
+    th[-1] = -0.5
+    np.testing.assert_allclose(oracle.cell_kc(bb, 0.01, th), kc * 10 ** -0.5, rtol=1e-7)
 
 
-def test_walk_mlp_limits_equal_theta_walks():
-    """A network that never accepts in the band gives the theta walk at
-    theta_lo; one that always accepts (outside the body's own cell) gives
-    the theta walk at theta_hi when theta_hi < 1/sqrt(3)."""
+def test_walk_kc_limits():
+    """tau = 0 never accepts a cell: the direct sum; an unbounded tau accepts
+    whenever l/d < theta_max (the body outside the cell): the theta walk at
+    theta_max."""
     b = W.plummer(3000, 5)
     bb = oracle.build_all(b.pos, b.mass, 8)
-    never = oracle.walk_mlp(bb, 0.01, 0.35, 0.55, -3.0, _const_net(100.0))
-    lo = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], 0.35, 0.01)
-    np.testing.assert_allclose(never.acc, lo.acc, rtol=1e-13, atol=0)
-    assert np.array_equal(never.npc, lo.npc)
-    always = oracle.walk_mlp(bb, 0.01, 0.35, 0.55, -3.0, _const_net(-100.0))
-    hi = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], 0.55, 0.01)
-    np.testing.assert_allclose(always.acc, hi.acc, rtol=1e-13, atol=0)
-    assert np.array_equal(always.npc, hi.npc)
+    kc = oracle.cell_kc(bb, 0.01)
+    anorm = np.ones(3000)
+    none = oracle.walk_kc(bb, 0.01, 0.55, 0.0, kc, anorm)
+    direct = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], 0.0, 0.01)
+    np.testing.assert_allclose(none.acc, direct.acc, rtol=1e-13, atol=0)
+    assert np.all(none.npc == 0)
+    every = oracle.walk_kc(bb, 0.01, 0.55, 1e300, kc, anorm)
+    th = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], 0.55, 0.01)
+    np.testing.assert_allclose(every.acc, th.acc, rtol=1e-13, atol=0)
+    assert np.array_equal(every.npc, th.npc)
+    # above 1/sqrt(3) the guard keeps every accepted cell away from the body:
+    # every other body is accounted for exactly once
+    wide = oracle.walk_kc(bb, 0.01, 0.95, 1e300, kc, anorm)
+    assert np.all(wide.ncov == 2999)
+
+
+def test_relative_criterion_beats_theta():
+    """The error-budget criterion (k_C = 1) reaches a given rms relative
+    error with fewer interactions than the opening angle (quadrupole walk,
+    Plummer sphere)."""
+    b = W.plummer(20000, 8)
+    bb = oracle.build_all(b.pos, b.mass, 16)
+    samp = np.arange(0, 20000, 10)
+    rank = np.empty(20000, dtype=np.int64)
+    rank[bb["perm"]] = np.arange(20000)
+    ad, _ = oracle.direct(b.pos, b.mass, 0.005, samp)
+    full = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], 0.4, 0.005)
+    anorm = np.linalg.norm(full.acc, axis=1)
+
+    def rms(acc):
+        e = np.linalg.norm(acc - ad, axis=1) / np.linalg.norm(ad, axis=1)
+        return np.sqrt(np.mean(e * e))
+    th = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], 0.55, 0.005,
+                     targets=rank[samp])
+    kc = oracle.cell_kc(bb, 0.005)
+    best = None
+    for tau in (3e-4, 1e-3, 3e-3):
+        r = oracle.walk_kc(bb, 0.005, 1.0, tau, kc, anorm, targets=rank[samp])
+        if rms(r.acc) <= rms(th.acc):
+            best = r
+    assert best is not None
+    assert (best.npp + best.npc).mean() < 0.8 * (th.npp + th.npc).mean()

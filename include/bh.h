@@ -49,8 +49,9 @@ enum { BH_F32 = 0, BH_F64 = 1 };
 
 /* Acceptance criterion used by the walk. */
 enum {
-    BH_MAC_THETA = 0, /* side/distance < theta (Sec. 3) */
-    BH_MAC_MLP = 1    /* learned criterion inside a theta band, theta outside it */
+    BH_MAC_THETA = 0,  /* side/distance < theta (Sec. 3) */
+    BH_MAC_MLP = 1,    /* learned: predicted error k_C (l/d)^3 M/d^2 < tau |a_i| */
+    BH_MAC_BUDGET = 2  /* the same error budget with k_C = 1 (no network) */
 };
 
 typedef struct bh_ctx bh_ctx;
@@ -67,9 +68,17 @@ typedef struct {
     int64_t target_begin; /* walk only bodies of sorted rank [begin, end); */
     int64_t target_end;   /* end <= 0 means all.  Outputs of other bodies are
                              left untouched. */
-    double mlp_theta_lo;  /* learned criterion: side/d below -> accept */
-    double mlp_theta_hi;  /* above -> open; in between ask the network */
-    double mlp_log10_tau; /* accept when predicted log10 error < this */
+    /* BH_MAC_MLP / BH_MAC_BUDGET (FP32 quadrupole walk only): accept a
+     * multi-body cell iff side/d < mlp_theta_max, the body is outside it,
+     * and k_C M side^3 < 10^mlp_log10_tau |a_i| d^5 (k_C from the loaded
+     * network per cell, or 1).  |a_i| comes from mlp_acc_norm (device, n
+     * norms in the tree's dtype, caller order) or, if NULL, from a monopole
+     * walk at mlp_theta_est run first (a simulation step uses the previous
+ * step's accelerations instead). */
+    double mlp_theta_max;     /* default 1.0 */
+    double mlp_log10_tau;     /* default -3 */
+    const void *mlp_acc_norm; /* default NULL */
+    double mlp_theta_est;     /* default 0.8 */
 } bh_force_opts;
 
 /* Library version string. */
@@ -157,7 +166,10 @@ int bh_tree_export(const bh_tree *tree, uint64_t *keys, uint32_t *perm, uint64_t
  * bh_sim_init copies pos/vel/mass (device, dtype) into context-owned state,
  * builds the tree and computes the initial accelerations.  Each
  * bh_leapfrog_step(dt) does v += a dt/2; x += v dt; rebuild; walk;
- * v += a dt/2.  State is kept in key order between steps.
+ * v += a dt/2.  State is kept in key order between steps.  With
+ * BH_MAC_MLP / BH_MAC_BUDGET, opts.mlp_acc_norm is ignored: the initial
+ * walk estimates |a_i| by a monopole walk, later steps use the previous
+ * step's accelerations.
  * ------------------------------------------------------------------- */
 int bh_sim_init(bh_ctx *ctx, const void *pos, const void *vel, const void *mass, int dtype,
                 int64_t n, int leaf_size, double theta, double eps, const bh_force_opts *opts);
@@ -191,17 +203,19 @@ int bh_direct(bh_ctx *ctx, const void *pos, const void *mass, int dtype, int64_t
 
 /* ---------------------------------------------------------------------
  * Learned acceptance criterion (not in the paper; it stands in for the
- * opening-angle test of Sec. 3 inside a theta band).
+ * opening-angle test of Sec. 3).
  *
- * Network: 10 features -> 32 (ReLU) -> 32 (ReLU) -> 1, predicting log10 of
- * a cell's particle-cell error relative to the cell's exact contribution.
- * Parameters (BH_MLP_PARAMS doubles, host): W1[32][10] b1[32] W2[32][32]
- * b2[32] w3[32] b3, held on the device as FP32 master weights with Adam
- * state, and packed to bf16 MFMA operands for inference.
- * Features of a (body, cell) pair, x = body - COM, d = |x|, n = x/d,
- * g = COM - cell centre, l = side: l/d, (l/d)^2, |g|/l, n.g/l, distance
- * from the body to the cell's cube / d, n.Q.n/(M l^2), |Q|_F/(M l^2),
- * log2(count)/21, eps/d, leaf (0/1).
+ * The error of a cell's quadrupole particle-cell term on body i is modelled
+ * as k_C (l/d)^3 M/d^2.  A network 10 -> 32 (ReLU) -> 32 (ReLU) -> 1
+ * predicts log10 k_C from the cell alone; it is evaluated once per cell
+ * (bf16 MFMA, 64 cells per wavefront) and the walk accepts as described at
+ * bh_force_opts.  Parameters (BH_MLP_PARAMS doubles, host): W1[32][10]
+ * b1[32] W2[32][32] b2[32] w3[32] b3, held on the device as FP32 master
+ * weights with Adam state and packed to bf16 operands for inference.
+ * Cell features (l side, g = COM - centre, M mass, n count,
+ * T2 = sum m |y|^2 about the COM, Q traceless quadrupole):
+ * |g|/l, sqrt(T2/M)/l, |Q|_F/(M l^2), cbrt(det Q)/(M l^2), max|g_a|/l,
+ * log2(n)/21, leaf (0/1), eps/l, 1/sqrt(n), T2/(M l^2).
  * ------------------------------------------------------------------- */
 #define BH_MLP_PARAMS 1441
 
@@ -211,16 +225,16 @@ int bh_mlp_set(bh_ctx *ctx, const double *params);
 int bh_mlp_get(bh_ctx *ctx, double *params);
 
 /* Training pairs from a BH_F64 tree: for every body a walk at theta_lo;
- * every multi-body cell with theta_lo <= side/d < theta_hi that does not
+ * every multi-body cell with theta_lo <= side/d < theta_max that does not
  * contain the body is a candidate, kept iff the SplitMix64 hash of
  * (seed ^ (rank << 32 | node)) >> 11 is below keep * 2^53.  Kept pairs are
- * written densely, by body rank then pre-order: feat (device f32, 10 per
- * pair), label (device f32: log10 of the relative error of the cell's
- * quadrupole term against the direct sum over its bodies, computed in
- * FP64, floored at -12), node and body rank (device i32).  *total gets the
- * number of kept pairs; with feat == NULL only *total is computed.
+ * written densely, by body rank then pre-order: feat (device f32, the
+ * cell's 10 features), label (device f32: log10(|a_pc - a_exact| d^5 /
+ * (M l^3)) with a_exact the direct sum over the cell's bodies, FP64,
+ * floored at 1e-12 inside), node and body rank (device i32).  *total gets
+ * the number of kept pairs; with feat == NULL only *total is computed.
  * BH_E_INVALID if capacity < *total.  Synchronous. */
-int bh_mlp_samples(bh_tree *tree, double eps, double theta_lo, double theta_hi, double keep,
+int bh_mlp_samples(bh_tree *tree, double eps, double theta_lo, double theta_max, double keep,
                    uint64_t seed, int64_t capacity, float *feat, float *label, int32_t *node,
                    int32_t *body, int64_t *total);
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libbh.so")
 
 BH_OK, BH_E_INVALID, BH_E_NOMEM, BH_E_DEVICE, BH_E_STATE, BH_E_NONFINITE = 0, -1, -2, -3, -4, -5
 BH_F32, BH_F64 = 0, 1
-BH_MAC_THETA, BH_MAC_MLP = 0, 1
+BH_MAC_THETA, BH_MAC_MLP, BH_MAC_BUDGET = 0, 1, 2
 
 EXPORTED = [
     "bh_version", "bh_last_error", "bh_force_opts_default", "bh_ctx_create", "bh_ctx_set_stream",
@@ -32,7 +32,7 @@ BH_MLP_PARAMS = 1441
 __all__ = EXPORTED + [
     "BHError", "ForceOpts", "TreeInfo", "force_opts", "load", "BH_OK", "BH_E_INVALID",
     "BH_E_NOMEM", "BH_E_DEVICE", "BH_E_STATE", "BH_E_NONFINITE", "BH_F32", "BH_F64",
-    "BH_MAC_THETA", "BH_MAC_MLP",
+    "BH_MAC_THETA", "BH_MAC_MLP", "BH_MAC_BUDGET",
 ]
 
 
@@ -46,8 +46,8 @@ class ForceOpts(C.Structure):
     _fields_ = [
         ("order", C.c_int), ("mac", C.c_int), ("phi", C.c_void_p), ("n_pp", C.c_void_p),
         ("n_pc", C.c_void_p), ("target_begin", C.c_int64), ("target_end", C.c_int64),
-        ("mlp_theta_lo", C.c_double), ("mlp_theta_hi", C.c_double),
-        ("mlp_log10_tau", C.c_double),
+        ("mlp_theta_max", C.c_double), ("mlp_log10_tau", C.c_double),
+        ("mlp_acc_norm", C.c_void_p), ("mlp_theta_est", C.c_double),
     ]
 
 
@@ -159,7 +159,10 @@ def _stream():
 
 
 def force_opts(order=2, mac=BH_MAC_THETA, phi=None, n_pp=None, n_pc=None, target_range=None,
-               mlp_theta_lo=None, mlp_theta_hi=None, mlp_log10_tau=None) -> ForceOpts:
+               mlp_theta_max=None, mlp_log10_tau=None, mlp_acc_norm=None,
+               mlp_theta_est=None) -> ForceOpts:
+    """Walk options.  mlp_acc_norm: device tensor of |a_i| in caller order
+    and the tree's dtype (kept alive by the caller until the walk ran)."""
     o = ForceOpts()
     load().bh_force_opts_default(C.byref(o))
     o.order = order
@@ -169,12 +172,13 @@ def force_opts(order=2, mac=BH_MAC_THETA, phi=None, n_pp=None, n_pc=None, target
     o.n_pc = _dev(n_pc, "n_pc")
     if target_range is not None:
         o.target_begin, o.target_end = int(target_range[0]), int(target_range[1])
-    if mlp_theta_lo is not None:
-        o.mlp_theta_lo = mlp_theta_lo
-    if mlp_theta_hi is not None:
-        o.mlp_theta_hi = mlp_theta_hi
+    if mlp_theta_max is not None:
+        o.mlp_theta_max = mlp_theta_max
     if mlp_log10_tau is not None:
         o.mlp_log10_tau = mlp_log10_tau
+    o.mlp_acc_norm = _dev(mlp_acc_norm, "mlp_acc_norm")
+    if mlp_theta_est is not None:
+        o.mlp_theta_est = mlp_theta_est
     return o
 
 
@@ -328,12 +332,12 @@ def bh_mlp_get(ctx) -> np.ndarray:
     return p
 
 
-def bh_mlp_samples(tree, eps, theta_lo, theta_hi, keep, seed):
+def bh_mlp_samples(tree, eps, theta_lo, theta_max, keep, seed):
     """Training pairs of an FP64 tree: (feat, label, node, body) GPU tensors."""
     import torch
     tot = C.c_int64()
     lib = load()
-    _check(lib.bh_mlp_samples(tree, float(eps), float(theta_lo), float(theta_hi), float(keep),
+    _check(lib.bh_mlp_samples(tree, float(eps), float(theta_lo), float(theta_max), float(keep),
                               int(seed), 0, None, None, None, None, C.byref(tot)))
     n = tot.value
     dev = torch.device("cuda")
@@ -341,7 +345,7 @@ def bh_mlp_samples(tree, eps, theta_lo, theta_hi, keep, seed):
     label = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
     node = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
     body = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
-    _check(lib.bh_mlp_samples(tree, float(eps), float(theta_lo), float(theta_hi), float(keep),
+    _check(lib.bh_mlp_samples(tree, float(eps), float(theta_lo), float(theta_max), float(keep),
                               int(seed), n, _dev(feat, "feat"), _dev(label, "label"),
                               _dev(node, "node"), _dev(body, "body"), C.byref(tot)))
     return feat[:n], label[:n], node[:n], body[:n]

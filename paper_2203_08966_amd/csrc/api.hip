@@ -63,7 +63,8 @@ static void free_tree_bufs(bh_tree *t) {
                      &t->bodies, &t->anchors, &t->delta, &t->nstart, &t->offs, &t->hkey,
                      &t->level, &t->begin, &t->count, &t->next, &t->parent, &t->cmask,
                      &t->lvl_list, &t->cx, &t->cy, &t->cz, &t->mom, &t->recs,
-                     &t->cube, &t->part, &t->hist, &t->status, &t->misc, &t->cnt_scratch};
+                     &t->cube, &t->part, &t->hist, &t->status, &t->misc, &t->cnt_scratch,
+                     &t->cellf, &t->kc, &t->anorm, &t->est_acc};
     for (DevBuf *b : all) free_buf(*b);
 }
 
@@ -78,15 +79,15 @@ static size_t dsize(int d) { return d == BH_F32 ? 4 : 8; }
 
 static int check_opts(const bh_force_opts &o, int64_t n) {
     if (o.order != 0 && o.order != 2) return set_error(BH_E_INVALID, "opts.order must be 0 or 2");
-    if (o.mac != BH_MAC_THETA && o.mac != BH_MAC_MLP)
-        return set_error(BH_E_INVALID, "opts.mac must be BH_MAC_THETA or BH_MAC_MLP");
+    if (o.mac != BH_MAC_THETA && o.mac != BH_MAC_MLP && o.mac != BH_MAC_BUDGET)
+        return set_error(BH_E_INVALID, "opts.mac must be BH_MAC_THETA, BH_MAC_MLP or BH_MAC_BUDGET");
     if (o.target_end > 0 &&
         (o.target_begin < 0 || o.target_begin > o.target_end || o.target_end > n))
         return set_error(BH_E_INVALID, "opts target range outside [0, n]");
-    if (o.mac == BH_MAC_MLP &&
-        !(o.mlp_theta_lo >= 0 && o.mlp_theta_hi >= o.mlp_theta_lo && isfinite(o.mlp_theta_hi) &&
-          isfinite(o.mlp_log10_tau)))
-        return set_error(BH_E_INVALID, "opts learned-criterion band invalid");
+    if (o.mac != BH_MAC_THETA &&
+        !(o.mlp_theta_max > 0 && isfinite(o.mlp_theta_max) && isfinite(o.mlp_log10_tau) &&
+          o.mlp_theta_est >= 0 && isfinite(o.mlp_theta_est)))
+        return set_error(BH_E_INVALID, "opts learned-criterion parameters invalid");
     return BH_OK;
 }
 
@@ -119,9 +120,10 @@ void bh_force_opts_default(bh_force_opts *o) {
     memset(o, 0, sizeof(*o));
     o->order = 2;
     o->mac = BH_MAC_THETA;
-    o->mlp_theta_lo = 0.3;
-    o->mlp_theta_hi = 1.0;
+    o->mlp_theta_max = 1.0;
     o->mlp_log10_tau = -3.0;
+    o->mlp_acc_norm = nullptr;
+    o->mlp_theta_est = 0.8;
 }
 
 int bh_ctx_create(int device, void *stream, bh_ctx **out) {
@@ -318,10 +320,13 @@ int bh_tree_export(const bh_tree *t, uint64_t *keys, uint32_t *perm, uint64_t *h
 }
 
 // ---------------------------------------------------------------- simulation
+// Forces of the current (just rebuilt) step.  The accelerations of the
+// previous step are still in s->acc, in the order the tree was built from,
+// and give the learned criterion its |a_i|.
 static int sim_forces(bh_ctx *c) {
     SimState *s = c->sim;
     return run_walk(c->sim_tree, s->theta, s->eps, s->acc.p, s->phi.p, nullptr, nullptr, s->opts,
-                    true);
+                    true, s->have_acc ? s->acc.p : nullptr);
 }
 
 static int sim_rebuild(bh_ctx *c, const void *pos, const void *vel, const void *mass,
@@ -350,6 +355,7 @@ int bh_sim_init(bh_ctx *c, const void *pos, const void *vel, const void *mass, i
     o.phi = nullptr;
     o.n_pp = o.n_pc = nullptr;
     o.target_begin = o.target_end = 0;
+    o.mlp_acc_norm = nullptr;  // the previous step's accelerations serve instead
     if ((rc = check_opts(o, n))) return rc;
     if (o.mac == BH_MAC_MLP && !c->mlp_loaded)
         return set_error(BH_E_STATE, "learned criterion requested but no weights are loaded");
@@ -531,18 +537,18 @@ int bh_mlp_get(bh_ctx *c, double *params) {
     return BH_OK;
 }
 
-int bh_mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_hi, double keep,
+int bh_mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_max, double keep,
                    uint64_t seed, int64_t capacity, float *feat, float *label, int32_t *node,
                    int32_t *body, int64_t *total) {
     if (!t || !total) return set_error(BH_E_INVALID, "null argument");
     if (t->dtype != BH_F64) return set_error(BH_E_INVALID, "training pairs need a BH_F64 tree");
-    if (!(theta_lo >= 0) || !(theta_hi > theta_lo) || !isfinite(theta_hi) || !(eps >= 0) ||
+    if (!(theta_lo >= 0) || !(theta_max > theta_lo) || !isfinite(theta_max) || !(eps >= 0) ||
         !isfinite(eps) || !(keep >= 0 && keep <= 1))
         return set_error(BH_E_INVALID, "bad band, eps or keep");
     if (feat && (!label || !node || !body || capacity < 0))
         return set_error(BH_E_INVALID, "null output");
     if (use_device(t->ctx)) return BH_E_DEVICE;
-    return mlp_samples(t, eps, theta_lo, theta_hi, keep, seed, capacity, feat, label, node, body,
+    return mlp_samples(t, eps, theta_lo, theta_max, keep, seed, capacity, feat, label, node, body,
                        total);
 }
 

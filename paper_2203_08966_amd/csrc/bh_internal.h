@@ -96,6 +96,7 @@ struct bh_ctx {
     bh::DevBuf mlp_scratch, mlp_gpart;
     int mlp_loaded = 0;
     int mlp_step = 0;                // Adam steps taken
+    int mlp_version = 0;             // bumped whenever the parameters change
     bh::DevBuf scratch;              // direct-sum partials
     // phase timing of simulation steps
     bool timing = false;
@@ -121,6 +122,12 @@ struct bh_tree {
     bh::DevBuf mom, recs;
     // small scratch
     bh::DevBuf cube, part, hist, status, misc, cnt_scratch;
+    // learned criterion: cell features, k_C M l^3, |a| per sorted rank,
+    // estimate accelerations; cache keys of cellf/kc
+    bh::DevBuf cellf, kc, anorm, est_acc;
+    int kc_version = -2;
+    double kc_eps = -1.0;
+    int64_t build_id = 0, kc_tree_id = -1;
     uint64_t *sorted_keys = nullptr;           // result buffers after the sort
     uint32_t *perm = nullptr;
 };
@@ -153,8 +160,11 @@ int build_tree(bh_ctx *ctx, bh_tree *t, const void *pos, const void *mass, int d
                void *vel_out, void *mass_out, uint32_t *id_out);
 
 // ---- walk (walk.hip)
+// prev_acc: accelerations in the tree's input order from an earlier step;
+// the learned criterion takes |a_i| from it unless opts give norms.
 int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_t *npp,
-             uint32_t *npc, const bh_force_opts &o, bool sorted_out);
+             uint32_t *npc, const bh_force_opts &o, bool sorted_out,
+             const void *prev_acc = nullptr);
 
 // ---- simulation helpers (sim.hip)
 int launch_kick(hipStream_t s, int dtype, int64_t n, void *vel, const void *acc, double h);

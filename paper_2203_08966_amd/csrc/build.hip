@@ -940,6 +940,7 @@ int build_tree(bh_ctx *ctx, bh_tree *t, const void *pos, const void *mass, int d
     t->dtype = dtype;
     t->n = n;
     t->leaf = leaf;
+    t->build_id++;
     int rc;
     if (dtype == BH_F32)
         rc = build_typed<float>(ctx, t, (const float *)pos, (const float *)mass, (int)n, leaf,

@@ -104,40 +104,19 @@ __device__ __forceinline__ float mlp_eval(const MlpRegs &r, const float *f, int 
     return (upper ? p1 : p0) + r.b3;
 }
 
-// Features of a (body, cell) pair in the walk's precision: X is the body
-// relative to the cell centre, x relative to the COM, d2 = |x|^2.
-template <typename R>
-__device__ __forceinline__ void mac_features(R X, R Y, R Z, R x, R y, R z, R d2, R side, R gx, R gy,
-                                         R gz, R M, R qxx, R qxy, R qxz, R qyy, R qyz, int cnt,
-                                         bool leaf, R eps, R *f) {
-    const R qzz = -qxx - qyy;
-    const R d = sqrt(d2);
-    const R id = (R)1 / d;
-    const R is = (R)1 / side;
-    f[0] = side * id;
-    f[1] = f[0] * f[0];
-    f[2] = sqrt(gx * gx + gy * gy + gz * gz) * is;
-    f[3] = (x * gx + y * gy + z * gz) * id * is;
-    const R h = (R)0.5 * side;
-    const R tx = fmax(fabs(X) - h, (R)0), ty = fmax(fabs(Y) - h, (R)0), tz = fmax(fabs(Z) - h, (R)0);
-    f[4] = sqrt(tx * tx + ty * ty + tz * tz) * id;
-    const R xqx = x * (qxx * x + qxy * y + qxz * z) + y * (qxy * x + qyy * y + qyz * z) +
-                  z * (qxz * x + qyz * y + qzz * z);
-    const R ml2 = M * side * side;
-    const R qf = sqrt(qxx * qxx + qyy * qyy + qzz * qzz + 2 * (qxy * qxy + qxz * qxz + qyz * qyz));
-    f[5] = ml2 > 0 ? xqx / (d2 * ml2) : (R)0;
-    f[6] = ml2 > 0 ? qf / ml2 : (R)0;
-    f[7] = log2((R)cnt) * (R)(1.0 / 21.0);
-    f[8] = eps * id;
-    f[9] = leaf ? (R)1 : (R)0;
-}
-
 // host entry points (mlp.hip)
 int mlp_pack(bh_ctx *c);
 int mlp_infer(bh_ctx *c, const float *X, int64_t n, float *pred);
-int mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_hi, double keep,
+int mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_max, double keep,
                 uint64_t seed, int64_t cap, float *feat, float *label, int32_t *node,
                 int32_t *body, int64_t *total);
+// features and k_C M l^3 of every cell (learned: the network; else k_C = 1),
+// cached per tree build, eps and parameter version
+int mlp_cells(bh_tree *t, double eps, bool learned);
+// |a| per sorted rank into t->anorm from an acceleration array (acc) or an
+// array of norms (norm), of the tree's dtype, in caller order (read through
+// perm) or in sorted order
+int mlp_anorm(bh_tree *t, const void *acc, const void *norm, bool caller_order);
 int mlp_grad_step(bh_ctx *c, const float *X, const float *y, int64_t ns, int64_t base, int bs,
                   uint64_t a, uint64_t cc, float *g_out, float *loss_acc, bool apply, int step,
                   const MlpTrainCfg &cfg);

@@ -1,5 +1,11 @@
-// Learned acceptance criterion on gfx950: training pairs, training kernels
-// and bf16 MFMA inference.
+// Learned acceptance criterion on gfx950: cell features, training pairs,
+// training kernels and bf16 MFMA inference.
+//
+// The error of a cell's quadrupole term on body i is modelled as
+// k_C (l/d)^3 M/d^2; a network predicts log10 k_C from the cell's features
+// once per cell (inference batched 64 cells per wavefront on MFMA), and the
+// walk accepts a cell iff k_C M l^3 < tau |a_i| d^5 (with l/d < theta_max and
+// the body outside the cell).
 //
 // Network 10 -> 32 (ReLU) -> 32 (ReLU) -> 1.  FP32 master parameters, flat:
 // W1[32][10] b1[32] W2[32][32] b2[32] w3[32] b3 (1441 values).
@@ -34,17 +40,113 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
     return z ^ (z >> 31);
 }
 
+// ------------------------------------------------------------------ cell features
+// Scale-free features of every cell, from its FP64 moments (l side, g COM
+// offset from the centre, M mass, n count, T2 = sum m |y|^2 about the COM,
+// Q traceless quadrupole):
+//   |g|/l, sqrt(T2/M)/l, |Q|_F/(M l^2), cbrt(det Q)/(M l^2), max|g_a|/l,
+//   log2(n)/21, leaf, eps/l, 1/sqrt(n), T2/(M l^2)
+__global__ __launch_bounds__(256) void k_cell_features(int m, const Moments *__restrict__ mom,
+                                                       const int32_t *__restrict__ level,
+                                                       const int32_t *__restrict__ count,
+                                                       const int32_t *__restrict__ next,
+                                                       const Cube *__restrict__ cube, double eps,
+                                                       float *__restrict__ cf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const Moments q = mom[i];
+    const double side = ldexp(cube->L, -level[i]);
+    const double tr = q.t[0] + q.t[3] + q.t[5];
+    const double Q[3][3] = {{3 * q.t[0] - tr, 3 * q.t[1], 3 * q.t[2]},
+                            {3 * q.t[1], 3 * q.t[3] - tr, 3 * q.t[4]},
+                            {3 * q.t[2], 3 * q.t[4], 3 * q.t[5] - tr}};
+    double qf = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) qf += Q[a][b] * Q[a][b];
+    const double det = Q[0][0] * (Q[1][1] * Q[2][2] - Q[1][2] * Q[2][1]) -
+                       Q[0][1] * (Q[1][0] * Q[2][2] - Q[1][2] * Q[2][0]) +
+                       Q[0][2] * (Q[1][0] * Q[2][1] - Q[1][1] * Q[2][0]);
+    const double ml2 = q.m * side * side;
+    const double gmax = fmax(fabs(q.c[0]), fmax(fabs(q.c[1]), fabs(q.c[2])));
+    const int n = count[i];
+    float *f = cf + 10 * (size_t)i;
+    f[0] = (float)(sqrt(q.c[0] * q.c[0] + q.c[1] * q.c[1] + q.c[2] * q.c[2]) / side);
+    f[1] = (float)(q.m > 0 ? sqrt(tr / q.m) / side : 0.0);
+    f[2] = (float)(ml2 > 0 ? sqrt(qf) / ml2 : 0.0);
+    f[3] = (float)(ml2 > 0 ? cbrt(det) / ml2 : 0.0);
+    f[4] = (float)(gmax / side);
+    f[5] = (float)(log2((double)n) / 21.0);
+    f[6] = next[i] == i + 1 ? 1.f : 0.f;
+    f[7] = (float)(eps / side);
+    f[8] = (float)(1.0 / sqrt((double)n));
+    f[9] = (float)(ml2 > 0 ? tr / ml2 : 0.0);
+}
+
+// k_C M l^3 per cell with log10 k_C from the network, 64 cells per wave.
+__global__ __launch_bounds__(256) void k_cell_kc(const MlpPacked *__restrict__ p, int m,
+                                                 const float *__restrict__ cf,
+                                                 const Moments *__restrict__ mom,
+                                                 const int32_t *__restrict__ level,
+                                                 const Cube *__restrict__ cube,
+                                                 float *__restrict__ kc) {
+    const int wave = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (wave * 64 >= m) return;  // whole wave: the MFMAs need every lane
+    const int l = (int)lane_id();
+    const int i = wave * 64 + l;
+    MlpRegs r;
+    mlp_load(p, l, r);
+    float f[kMlpIn];
+    for (int q = 0; q < kMlpIn; ++q) f[q] = i < m ? cf[10 * (size_t)i + q] : 0.f;
+    const float lk = mlp_eval(r, f, l);
+    if (i < m) {
+        const double side = ldexp(cube->L, -level[i]);
+        kc[i] = (float)(exp10((double)lk) * mom[i].m * side * side * side);
+    }
+}
+
+// k_C = 1: M l^3 per cell (the error-budget criterion without a network).
+__global__ __launch_bounds__(256) void k_cell_kc_plain(int m, const Moments *__restrict__ mom,
+                                                       const int32_t *__restrict__ level,
+                                                       const Cube *__restrict__ cube,
+                                                       float *__restrict__ kc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const double side = ldexp(cube->L, -level[i]);
+    kc[i] = (float)(mom[i].m * side * side * side);
+}
+
+// |a| per sorted rank i from element j of an acceleration array (or of an
+// array of norms), j = perm[i] for arrays in caller order, else j = i.
+template <typename R>
+__global__ __launch_bounds__(256) void k_anorm(int n, const R *__restrict__ acc,
+                                               const R *__restrict__ norm,
+                                               const uint32_t *__restrict__ perm,
+                                               float *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = perm ? (int64_t)perm[i] : i;
+    if (norm) {
+        out[i] = (float)norm[j];
+    } else {
+        const R x = acc[3 * j], y = acc[3 * j + 1], z = acc[3 * j + 2];
+        out[i] = (float)sqrt(x * x + y * y + z * z);
+    }
+}
+
 // ------------------------------------------------------------------ training pairs
 // Walk of one wavefront over the FP64 tree at theta_lo: every multi-body
-// cell with theta_lo <= side/d < theta_hi that does not contain the body is
-// a candidate, kept when the hash of (rank, node) falls below `keep`.
-// Pass 1 (out == nullptr) counts per body; pass 2 writes at offs[rank].
+// cell with theta_lo <= side/d < theta_max that does not contain the body is
+// a candidate, kept when the hash of (rank, node) falls below `keep`.  A
+// kept pair gets the cell's features and the label
+// log10(|a_pc - a_exact| d^5 / (M l^3)), a_exact the direct sum over the
+// cell's bodies, FP64.  Pass 1 (feat == nullptr) counts per body; pass 2
+// writes at offs[rank].
 __global__ __launch_bounds__(256) void k_mac_samples(
     const NodeRec64 *__restrict__ nodes, int m, const BodyRec<double> *__restrict__ bodies,
-    const Anchor<double> *__restrict__ anchors, int n, double tlo2, double thi2, double eps,
-    double keep, uint64_t seed, int32_t *__restrict__ cnt_out, const int64_t *__restrict__ offs,
-    int64_t cap_total, float *__restrict__ feat, float *__restrict__ label,
-    int32_t *__restrict__ node_out, int32_t *__restrict__ body_out) {
+    const Anchor<double> *__restrict__ anchors, const float *__restrict__ cf, int n, double tlo2,
+    double tmax2, double eps, double keep, uint64_t seed, int32_t *__restrict__ cnt_out,
+    const int64_t *__restrict__ offs, int64_t cap_total, float *__restrict__ feat,
+    float *__restrict__ label, int32_t *__restrict__ node_out, int32_t *__restrict__ body_out) {
     const int wave = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
     const int i = wave * 64 + (int)lane_id();
     const bool live = i < n;
@@ -82,14 +184,10 @@ __global__ __launch_bounds__(256) void k_mac_samples(
                 const double side = sqrt(s2);
                 const bool inside = fabs(X) <= 0.5 * side && fabs(Y) <= 0.5 * side &&
                                     fabs(Z) <= 0.5 * side;
-                if (s2 < thi2 * d2 && !inside) {
+                if (s2 < tmax2 * d2 && !inside) {
                     const uint64_t hkey = seed ^ (((uint64_t)i << 32) | (uint64_t)(uint32_t)idx);
                     if ((splitmix64(hkey) >> 11) < keep_lim) {
                         if (feat && o + k < cap_total) {
-                            double f[10];
-                            mac_features<double>(X, Y, Z, x, y, z, d2, side, nd.mx, nd.my, nd.mz, nd.m,
-                                             nd.qxx, nd.qxy, nd.qxz, nd.qyy, nd.qyz, nd.count,
-                                             nxt == idx + 1, eps, f);
                             // exact contribution of the cell's bodies
                             double ex = 0, ey = 0, ez = 0;
                             for (int j = nd.begin; j < nd.begin + nd.count && j < n; ++j) {
@@ -117,12 +215,12 @@ __global__ __launch_bounds__(256) void k_mac_samples(
                                          pz = inv5 * qz - g * z;
                             const double dd = sqrt((px - ex) * (px - ex) + (py - ey) * (py - ey) +
                                                    (pz - ez) * (pz - ez));
-                            const double na = sqrt(ex * ex + ey * ey + ez * ez);
-                            double rel = na > 0 ? dd / na : 1e-12;
-                            rel = rel < 1e-12 ? 1e-12 : rel;
+                            const double d = sqrt(d2);
+                            double v = dd * d2 * d2 * d / (nd.m * s2 * side);
+                            v = v > 1e-12 ? v : 1e-12;
                             const int64_t s = o + k;
-                            for (int q = 0; q < 10; ++q) feat[10 * s + q] = (float)f[q];
-                            label[s] = (float)log10(rel);
+                            for (int q = 0; q < 10; ++q) feat[10 * s + q] = cf[10 * (size_t)idx + q];
+                            label[s] = (float)log10(v);
                             node_out[s] = idx;
                             body_out[s] = i;
                         }
@@ -333,7 +431,10 @@ int mlp_pack(bh_ctx *c) {
     if (rc) return rc;
     k_mlp_pack<<<1, 64, 0, c->stream>>>((const float *)c->mlp_master.p, (MlpPacked *)c->mlp_w.p);
     rc = check_launch("mlp pack");
-    if (!rc) c->mlp_loaded = 1;
+    if (!rc) {
+        c->mlp_loaded = 1;
+        c->mlp_version++;  // cached per-cell coefficients are stale
+    }
     return rc;
 }
 
@@ -343,21 +444,63 @@ int mlp_infer(bh_ctx *c, const float *X, int64_t n, float *pred) {
     return check_launch("mlp infer");
 }
 
-int mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_hi, double keep,
+int mlp_cells(bh_tree *t, double eps, bool learned) {
+    bh_ctx *c = t->ctx;
+    const int m = (int)t->m;
+    const int version = learned ? c->mlp_version : -1;
+    if (t->kc_version == version && t->kc_eps == eps && t->kc_tree_id == t->build_id) return BH_OK;
+    int rc;
+    if ((rc = grow(t->cellf, 40ull * m)) || (rc = grow(t->kc, 4ull * m))) return rc;
+    const Moments *mom = (const Moments *)t->mom.p;
+    const Cube *cube = (const Cube *)t->cube.p;
+    k_cell_features<<<div_up(m, 256), 256, 0, c->stream>>>(
+        m, mom, (const int32_t *)t->level.p, (const int32_t *)t->count.p,
+        (const int32_t *)t->next.p, cube, eps, (float *)t->cellf.p);
+    if (learned)
+        k_cell_kc<<<div_up(div_up(m, 64), 4), 256, 0, c->stream>>>(
+            (const MlpPacked *)c->mlp_w.p, m, (const float *)t->cellf.p, mom,
+            (const int32_t *)t->level.p, cube, (float *)t->kc.p);
+    else
+        k_cell_kc_plain<<<div_up(m, 256), 256, 0, c->stream>>>(m, mom, (const int32_t *)t->level.p,
+                                                               cube, (float *)t->kc.p);
+    if ((rc = check_launch("mlp cells"))) return rc;
+    t->kc_version = version;
+    t->kc_eps = eps;
+    t->kc_tree_id = t->build_id;
+    return BH_OK;
+}
+
+int mlp_anorm(bh_tree *t, const void *acc, const void *norm, bool caller_order) {
+    const int n = (int)t->n;
+    int rc = grow(t->anorm, 4ull * n);
+    if (rc) return rc;
+    const uint32_t *perm = caller_order ? t->perm : nullptr;
+    if (t->dtype == BH_F32)
+        k_anorm<float><<<div_up(n, 256), 256, 0, t->ctx->stream>>>(
+            n, (const float *)acc, (const float *)norm, perm, (float *)t->anorm.p);
+    else
+        k_anorm<double><<<div_up(n, 256), 256, 0, t->ctx->stream>>>(
+            n, (const double *)acc, (const double *)norm, perm, (float *)t->anorm.p);
+    return check_launch("anorm");
+}
+
+int mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_max, double keep,
                 uint64_t seed, int64_t cap, float *feat, float *label, int32_t *node,
                 int32_t *body, int64_t *total) {
     bh_ctx *c = t->ctx;
     const int n = (int)t->n;
-    int rc = grow(c->mlp_scratch, 4ull * n + 8ull * (n + 1) + 8);
+    int rc = mlp_cells(t, eps, false);  // features only (k_C unused here)
     if (rc) return rc;
+    if ((rc = grow(c->mlp_scratch, 4ull * n + 8ull * (n + 1) + 8))) return rc;
     int32_t *cnt = (int32_t *)c->mlp_scratch.p;
     int64_t *offs = (int64_t *)((char *)c->mlp_scratch.p + 4ull * n + (4ull * n) % 8);
     const int nblk = div_up(div_up(n, 64), 4);
     const NodeRec64 *nodes = (const NodeRec64 *)t->recs.p;
     const auto *bodies = (const BodyRec<double> *)t->bodies.p;
     const auto *anchors = (const Anchor<double> *)t->anchors.p;
-    k_mac_samples<<<nblk, 256, 0, c->stream>>>(nodes, (int)t->m, bodies, anchors, n,
-                                               theta_lo * theta_lo, theta_hi * theta_hi, eps, keep,
+    const float *cf = (const float *)t->cellf.p;
+    k_mac_samples<<<nblk, 256, 0, c->stream>>>(nodes, (int)t->m, bodies, anchors, cf, n,
+                                               theta_lo * theta_lo, theta_max * theta_max, eps, keep,
                                                seed, cnt, nullptr, 0, nullptr, nullptr, nullptr,
                                                nullptr);
     k_scan_counts<<<1, 1024, 0, c->stream>>>(cnt, n, offs);
@@ -370,8 +513,8 @@ int mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_hi, double
     if (!feat) return BH_OK;
     if (*total > cap)
         return set_error(BH_E_INVALID, "sample capacity too small: need " + std::to_string(*total));
-    k_mac_samples<<<nblk, 256, 0, c->stream>>>(nodes, (int)t->m, bodies, anchors, n,
-                                               theta_lo * theta_lo, theta_hi * theta_hi, eps, keep,
+    k_mac_samples<<<nblk, 256, 0, c->stream>>>(nodes, (int)t->m, bodies, anchors, cf, n,
+                                               theta_lo * theta_lo, theta_max * theta_max, eps, keep,
                                                seed, nullptr, offs, cap, feat, label, node, body);
     return check_launch("mlp samples");
 }

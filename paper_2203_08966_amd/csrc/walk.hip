@@ -72,10 +72,12 @@ __device__ __forceinline__ void leaf_pp(const BodyRec<R> *__restrict__ bodies, i
     if (PHI) sp += pq;
 }
 
-// Learned-criterion parameters of a walk (band on side/d, threshold).
+// Learned-criterion parameters of a walk: per cell k_C M l^3, per sorted
+// rank |a_i|, theta_max^2 and tau.
 struct MlpMac {
-    const MlpPacked *w;
-    float tlo2, thi2, log10tau;
+    const float *kc;
+    const float *anorm;
+    float tmax2, tau;
 };
 
 template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool MLP>
@@ -116,8 +118,8 @@ __global__ __launch_bounds__(256) void k_walk(
     }
     R sx = 0, sy = 0, sz = 0, sp = 0;
     uint32_t cpp = 0, cpc = 0;
-    MlpRegs mr;
-    if (MLP) mlp_load(mac.w, (int)lane_id(), mr);
+    float tau_a = 0.f;  // tau |a_i|
+    if (MLP && live) tau_a = mac.tau * mac.anorm[i];
 
     const bool root_leaf = nodes[0].next == 1;
     int idx = root_leaf ? 0 : 1;
@@ -141,24 +143,13 @@ __global__ __launch_bounds__(256) void k_walk(
             const R d2 = x * x + y * y + z * z;
             bool accept;
             if (MLP) {
-                // below the band accept, above it (or inside the cell) open,
-                // inside it ask the network (all lanes evaluate together)
-                const bool lo_acc = act && nd.l2 < (R)mac.tlo2 * d2;
+                // predicted error k_C (l/d)^3 M/d^2 below tau |a_i|, l/d below
+                // theta_max, and the body outside the cell
+                const float kcv = mac.kc[idx];
                 const R hs = (R)0.5 * sqrt(nd.l2);
                 const bool inside = fabs(X) <= hs && fabs(Y) <= hs && fabs(Z) <= hs;
-                const bool band = act && !lo_acc && nd.l2 < (R)mac.thi2 * d2 && !inside;
-                bool ml_acc = false;
-                if (__ballot(band)) {
-                    R f[kMlpIn];
-                    mac_features<R>(X, Y, Z, x, y, z, d2, (R)2 * hs, nd.mx, nd.my, nd.mz, nd.m,
-                                    nd.qxx, nd.qxy, nd.qxz, nd.qyy, nd.qyz, cnt, nxt == idx + 1,
-                                    sqrt(eps2), f);
-                    float ff[kMlpIn];
-                    for (int q = 0; q < kMlpIn; ++q) ff[q] = (float)f[q];
-                    const float pred = mlp_eval(mr, ff, (int)lane_id());
-                    ml_acc = band && pred < mac.log10tau;
-                }
-                accept = lo_acc || ml_acc;
+                accept = act && nd.l2 < (R)mac.tmax2 * d2 && !inside &&
+                         kcv < tau_a * (d2 * d2 * sqrt(d2));
             } else {
                 accept = act && nd.l2 < theta2 * d2;
             }
@@ -251,7 +242,7 @@ void dispatch2(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, 
 }  // namespace
 
 int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_t *npp,
-             uint32_t *npc, const bh_force_opts &o, bool sorted_out) {
+             uint32_t *npc, const bh_force_opts &o, bool sorted_out, const void *prev_acc) {
     int t0 = 0, t1 = (int)t->n;
     if (o.target_end > 0) {
         t0 = (int)o.target_begin;
@@ -264,14 +255,34 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
         if (!npp) npp = (uint32_t *)t->cnt_scratch.p;
         else npc = (uint32_t *)t->cnt_scratch.p;
     }
-    MlpMac mac{nullptr, 0.f, 0.f, 0.f};
-    if (o.mac == BH_MAC_MLP) {
+    MlpMac mac{nullptr, nullptr, 0.f, 0.f};
+    if (o.mac == BH_MAC_MLP || o.mac == BH_MAC_BUDGET) {
         if (t->dtype != BH_F32 || o.order != 2)
             return set_error(BH_E_INVALID, "the learned criterion runs in the FP32 quadrupole walk");
-        mac.w = (const MlpPacked *)t->ctx->mlp_w.p;
-        mac.tlo2 = (float)(o.mlp_theta_lo * o.mlp_theta_lo);
-        mac.thi2 = (float)(o.mlp_theta_hi * o.mlp_theta_hi);
-        mac.log10tau = (float)o.mlp_log10_tau;
+        int rc = mlp_cells(t, eps, o.mac == BH_MAC_MLP);
+        if (rc) return rc;
+        if (o.mlp_acc_norm) {
+            rc = mlp_anorm(t, nullptr, o.mlp_acc_norm, true);
+        } else if (prev_acc) {
+            rc = mlp_anorm(t, prev_acc, nullptr, true);
+        } else {
+            // estimate |a_i| of the targets with a monopole walk at theta_est
+            if ((rc = grow(t->est_acc, 12ull * t->n))) return rc;
+            bh_force_opts eo;
+            bh_force_opts_default(&eo);
+            eo.order = 0;
+            eo.target_begin = t0;
+            eo.target_end = t1;
+            if ((rc = run_walk(t, o.mlp_theta_est, eps, t->est_acc.p, nullptr, nullptr, nullptr, eo,
+                               true)))
+                return rc;
+            rc = mlp_anorm(t, t->est_acc.p, nullptr, false);
+        }
+        if (rc) return rc;
+        mac.kc = (const float *)t->kc.p;
+        mac.anorm = (const float *)t->anorm.p;
+        mac.tmax2 = (float)(o.mlp_theta_max * o.mlp_theta_max);
+        mac.tau = (float)pow(10.0, o.mlp_log10_tau);
         dispatch2<float, true, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
     } else if (t->dtype == BH_F32) {
         if (o.order == 0) dispatch2<float, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);

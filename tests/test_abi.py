@@ -32,7 +32,8 @@ def test_version_and_defaults():
     o = B.bh_force_opts_default()
     assert o.order == 2 and o.mac == B.BH_MAC_THETA
     assert o.target_begin == 0 and o.target_end == 0
-    assert o.mlp_theta_lo == 0.3 and o.mlp_theta_hi == 1.0 and o.mlp_log10_tau == -3.0
+    assert o.mlp_theta_max == 1.0 and o.mlp_log10_tau == -3.0 and o.mlp_theta_est == 0.8
+    assert o.mlp_acc_norm is None
 
 
 def test_null_handles_rejected():

@@ -1,6 +1,6 @@
 """GPU learned acceptance criterion against the oracle: bf16 MFMA inference,
-training gradients, training pairs (features and labels), and the walk with
-the learned decision."""
+training gradients, training pairs (cell features and labels), and the walk
+with the error-budget decision, with and without the network."""
 import numpy as np
 import pytest
 import torch
@@ -19,13 +19,14 @@ def _params(seed, noise=0.2):
 
 
 def _features(n, seed):
-    """Feature rows in the ranges the walk produces."""
+    """Rows in the ranges the cell features take."""
     rng = np.random.default_rng(seed)
-    r = rng.uniform(0.2, 1.2, n)
-    f = np.stack([r, r * r, rng.uniform(0, 0.5, n), rng.uniform(-0.5, 0.5, n),
-                  rng.uniform(0, 0.8, n), rng.normal(0, 0.3, n), rng.uniform(0, 1.5, n),
-                  rng.integers(1, 12, n) / 21.0, rng.uniform(0, 0.05, n),
-                  rng.integers(0, 2, n).astype(float)], axis=1)
+    cnt = rng.integers(2, 4000, n)
+    t2 = rng.uniform(0, 0.6, n)
+    f = np.stack([rng.uniform(0, 0.5, n), np.sqrt(t2), rng.uniform(0, 1.2, n),
+                  rng.uniform(-0.4, 0.4, n), rng.uniform(0, 0.5, n), np.log2(cnt) / 21.0,
+                  rng.integers(0, 2, n).astype(float), rng.uniform(0, 2, n), 1 / np.sqrt(cnt),
+                  t2], axis=1)
     return f.astype(np.float32)
 
 
@@ -93,16 +94,16 @@ def test_training_reduces_loss_like_oracle(ctx):
 
 def test_training_pairs_match_oracle(ctx):
     pos, _, mass = case_bodies("plummer", 2048, 41, np.float64)
-    theta_lo, theta_hi, keep, seed, eps = 0.3, 1.0, 0.25, 7, 0.01
+    theta_lo, theta_max, keep, seed, eps = 0.3, 1.0, 0.25, 7, 0.01
     say("training pairs: FP64 tree of 2048 bodies vs oracle")
     P, M = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
     t = B.bh_build(ctx, P, M, 8)
-    feat, label, node, body = B.bh_mlp_samples(t, eps, theta_lo, theta_hi, keep, seed)
+    feat, label, node, body = B.bh_mlp_samples(t, eps, theta_lo, theta_max, keep, seed)
     feat, label = feat.cpu().numpy(), label.cpu().numpy()
     node, body = node.cpu().numpy(), body.cpu().numpy()
     B.bh_tree_free(t)
     ref = oracle.build_all(pos, mass, 8)
-    f, lab, nd, cnt = oracle.mac_samples(ref, eps, theta_lo, theta_hi, keep, seed, cap=1024)
+    f, lab, nd, cnt = oracle.mac_samples(ref, eps, theta_lo, theta_max, keep, seed, cap=1024)
     assert len(label) == cnt.sum()
     starts = np.concatenate([[0], np.cumsum(cnt)])
     same = 0
@@ -117,47 +118,122 @@ def test_training_pairs_match_oracle(ctx):
     assert same >= 0.999 * len(cnt)
 
 
-def test_learned_walk_matches_oracle(ctx):
-    """The walk with the learned decision, against the oracle's walk with the
-    bf16 view of the same network: identical interaction counts for every
-    body with no near-threshold decision, forces within the FP32 bound."""
-    pos, _, mass = case_bodies("plummer", 20000, 3, np.float32)
-    th = _params(21, 0.3)
-    th[-1] = 0.0
-    B.bh_mlp_set(ctx, th)
-    th32 = B.bh_mlp_get(ctx)
-    pred = mlp.forward_bf16(th32, _features(20000, 1).astype(np.float64))
-    tau = float(np.median(pred))  # a threshold that splits the decisions
-    lo, hi, eps = 0.35, 0.9, 0.005
-    say(f"learned walk: 20000 bodies, band [{lo}, {hi}], log10 tau {tau:.3f}")
+def _gpu_walk(ctx, pos, mass, leaf, eps, **kw):
     P, M = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
-    t = B.bh_build(ctx, P, M, 16)
+    t = B.bh_build(ctx, P, M, leaf)
     n = len(mass)
     acc = torch.empty_like(P)
     npp = torch.zeros(n, dtype=torch.int32, device="cuda")
     npc = torch.zeros(n, dtype=torch.int32, device="cuda")
-    o = B.force_opts(mac=B.BH_MAC_MLP, n_pp=npp, n_pc=npc, mlp_theta_lo=lo, mlp_theta_hi=hi,
-                     mlp_log10_tau=tau)
+    an = kw.pop("acc_norm", None)
+    an_t = None if an is None else torch.from_numpy(an.astype(np.float32)).cuda()
+    o = B.force_opts(n_pp=npp, n_pc=npc, mlp_acc_norm=an_t, **kw)
     B.bh_forces(t, 0.5, eps, acc, o)
     torch.cuda.synchronize()
     B.bh_tree_free(t)
-    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), 16)
-    r = oracle.walk_mlp(ref, eps, lo, hi, tau, th32)
-    rank = np.empty(n, dtype=np.int64)
-    rank[ref["perm"]] = np.arange(n)
-    a = acc.cpu().numpy().astype(np.float64)[ref["perm"]]
-    cp, cc = npp.cpu().numpy()[ref["perm"]], npc.cpu().numpy()[ref["perm"]]
+    return acc.cpu().numpy().astype(np.float64), npp.cpu().numpy(), npc.cpu().numpy()
+
+
+def _compare(ref, r, a, cp, cc, min_unflagged=0.5):
+    """Identical interaction counts for bodies with no near-threshold
+    decision; forces within the FP32 bound there, and overall (a flipped
+    decision moves a force by about the error budget)."""
+    n = len(cp)
+    p = ref["perm"]
+    a, cp, cc = a[p], cp[p], cc[p]
     ok = r.flag == 0
     match = (cp == r.npp) & (cc == r.npc)
-    say(f"  unflagged {ok.sum()}, of those with identical counts {match[ok].sum()}")
-    assert ok.sum() > 0.5 * n
+    say(f"  unflagged {ok.sum()} of {n}, of those with identical counts {match[ok].sum()}")
+    assert ok.sum() > min_unflagged * n
     assert match[ok].mean() >= 0.99
     e = np.linalg.norm(a - r.acc, axis=1) / np.linalg.norm(r.acc, axis=1)
     assert np.sqrt(np.mean(e[ok & match] ** 2)) < 1e-5
     assert np.sqrt(np.mean(e ** 2)) < 1e-3
 
 
-def test_learned_walk_state_and_band_errors(ctx):
+def _oracle_anorm(ref, eps, theta=0.4):
+    """|a_i| in caller order from the oracle's own quadrupole walk."""
+    w = oracle.walk(ref["tree"], ref["mom"], ref["spos"], ref["smass"], ref["L"], theta, eps)
+    out = np.empty(len(ref["perm"]))
+    out[ref["perm"]] = np.linalg.norm(w.acc, axis=1)
+    return out
+
+
+def test_budget_walk_matches_oracle(ctx):
+    """k_C = 1: accept iff side/d < theta_max, body outside the cell and
+    M l^3 < tau |a_i| d^5; |a_i| handed in by the caller."""
+    pos, _, mass = case_bodies("plummer", 20000, 4, np.float32)
+    eps, tau, tmax = 0.005, 1e-3, 1.0
+    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), 16)
+    an = _oracle_anorm(ref, eps).astype(np.float32)
+    say(f"budget walk: 20000 bodies, tau {tau}, theta_max {tmax}")
+    a, cp, cc = _gpu_walk(ctx, pos, mass, 16, eps, mac=B.BH_MAC_BUDGET, mlp_theta_max=tmax,
+                          mlp_log10_tau=np.log10(tau), acc_norm=an)
+    r = oracle.walk_kc(ref, eps, tmax, tau, oracle.cell_kc(ref, eps),
+                       an.astype(np.float64)[ref["perm"]])
+    _compare(ref, r, a, cp, cc)
+
+
+def test_learned_walk_matches_oracle(ctx):
+    """The walk with the network's per-cell k_C against the oracle's walk with
+    the bf16 view of the same network."""
+    pos, _, mass = case_bodies("plummer", 20000, 3, np.float32)
+    th = _params(21, 0.3)
+    th[-1] = 0.0
+    B.bh_mlp_set(ctx, th)
+    th32 = B.bh_mlp_get(ctx)
+    eps, tau, tmax = 0.005, 3e-3, 0.9
+    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), 16)
+    an = _oracle_anorm(ref, eps).astype(np.float32)
+    say(f"learned walk: 20000 bodies, tau {tau}, theta_max {tmax}")
+    a, cp, cc = _gpu_walk(ctx, pos, mass, 16, eps, mac=B.BH_MAC_MLP, mlp_theta_max=tmax,
+                          mlp_log10_tau=np.log10(tau), acc_norm=an)
+    kc = oracle.cell_kc(ref, eps, th32)
+    r = oracle.walk_kc(ref, eps, tmax, tau, kc, an.astype(np.float64)[ref["perm"]])
+    # the network moves decisions away from the k_C = 1 walk
+    r1 = oracle.walk_kc(ref, eps, tmax, tau, oracle.cell_kc(ref, eps),
+                        an.astype(np.float64)[ref["perm"]])
+    assert np.mean((r.npp != r1.npp) | (r.npc != r1.npc)) > 0.1
+    _compare(ref, r, a, cp, cc)
+
+
+def test_budget_walk_estimates_anorm(ctx):
+    """Without caller norms, |a_i| comes from a monopole walk at theta_est;
+    the oracle does the same with its own monopole walk."""
+    pos, _, mass = case_bodies("clumpy", 12000, 5, np.float32)
+    eps, tau, test = 0.005, 1e-3, 0.7
+    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), 16)
+    say("budget walk with estimated |a|: clumpy 12000 bodies")
+    a, cp, cc = _gpu_walk(ctx, pos, mass, 16, eps, mac=B.BH_MAC_BUDGET,
+                          mlp_log10_tau=np.log10(tau), mlp_theta_est=test)
+    w0 = oracle.walk(ref["tree"], ref["mom"], ref["spos"], ref["smass"], ref["L"], test, eps,
+                     order=0)
+    r = oracle.walk_kc(ref, eps, 1.0, tau, oracle.cell_kc(ref, eps),
+                       np.linalg.norm(w0.acc, axis=1))
+    _compare(ref, r, a, cp, cc)
+
+
+def test_budget_walk_target_range(ctx):
+    """A target sub-range gives the same outputs as the full walk there and
+    leaves the rest untouched (with the estimate walk run on the range)."""
+    pos, _, mass = case_bodies("plummer", 10000, 6, np.float32)
+    P, M = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
+    t = B.bh_build(ctx, P, M, 16)
+    full = torch.empty_like(P)
+    B.bh_forces(t, 0.5, 0.005, full, B.force_opts(mac=B.BH_MAC_BUDGET))
+    part = torch.full_like(P, 7.0)
+    B.bh_forces(t, 0.5, 0.005, part, B.force_opts(mac=B.BH_MAC_BUDGET, target_range=(1234, 5678)))
+    torch.cuda.synchronize()
+    perm = B.bh_tree_export(t)["perm"].astype(np.int64)
+    B.bh_tree_free(t)
+    full, part = full.cpu().numpy(), part.cpu().numpy()
+    inr = perm[1234:5678]
+    out = np.setdiff1d(np.arange(10000), inr)
+    assert np.array_equal(part[inr], full[inr])
+    assert np.all(part[out] == 7.0)
+
+
+def test_learned_walk_state_and_args(ctx):
     pos, _, mass = case_bodies("plummer", 1000, 3, np.float64)
     t = B.bh_build(ctx, torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda(), 8)
     acc = torch.empty((1000, 3), dtype=torch.float64, device="cuda")
@@ -165,4 +241,50 @@ def test_learned_walk_state_and_band_errors(ctx):
     with pytest.raises(B.BHError) as e:  # FP64 tree: the learned walk is FP32 only
         B.bh_forces(t, 0.5, 0.01, acc, B.force_opts(mac=B.BH_MAC_MLP))
     assert e.value.code == B.BH_E_INVALID
+    with pytest.raises(B.BHError) as e:
+        B.bh_forces(t, 0.5, 0.01, acc, B.force_opts(mac=B.BH_MAC_BUDGET, mlp_theta_max=-1.0))
+    assert e.value.code == B.BH_E_INVALID
     B.bh_tree_free(t)
+
+
+def test_budget_leapfrog_matches_oracle(ctx):
+    """KDK with the error-budget criterion: the initial forces take |a_i| from
+    a monopole walk at theta_est, every later step from the previous step's
+    accelerations.  The oracle runs the same recipe in FP64."""
+    pos, vel, mass = case_bodies("plummer", 8192, 7, np.float32)
+    eps, tau, test, dt, steps, leaf = 0.005, 1e-3, 0.8, 5e-4, 4, 16
+    p64, v64, m64 = (a.astype(np.float64) for a in (pos, vel, mass))
+    state = {"prev": None}
+
+    def force(x):
+        ref = oracle.build_all(x, m64, leaf)
+        if state["prev"] is None:
+            w0 = oracle.walk(ref["tree"], ref["mom"], ref["spos"], ref["smass"], ref["L"], test,
+                             eps, order=0)
+            an = np.linalg.norm(w0.acc, axis=1)
+        else:
+            an = np.linalg.norm(state["prev"], axis=1)[ref["perm"]]
+        r = oracle.walk_kc(ref, eps, 1.0, tau, oracle.cell_kc(ref, eps), an)
+        acc = np.empty_like(r.acc)
+        acc[ref["perm"]] = r.acc
+        state["prev"] = acc
+        return acc
+
+    say(f"budget leapfrog: 8192 bodies, {steps} steps, vs FP64 oracle")
+    xo, vo, ao = oracle.kdk(p64, v64, m64, dt, steps, force)
+    P, V, M = (torch.from_numpy(a).cuda() for a in (pos, vel, mass))
+    B.bh_sim_init(ctx, P, V, M, leaf, 0.5, eps,
+                  B.force_opts(mac=B.BH_MAC_BUDGET, mlp_log10_tau=np.log10(tau),
+                               mlp_theta_est=test))
+    for _ in range(steps):
+        B.bh_leapfrog_step(ctx, dt)
+    x, v, a = torch.empty_like(P), torch.empty_like(V), torch.empty_like(P)
+    B.bh_sim_get(ctx, x, v, a)
+    torch.cuda.synchronize()
+    x, a = x.cpu().numpy().astype(np.float64), a.cpu().numpy().astype(np.float64)
+    scale = np.abs(xo).max()
+    assert np.abs(x - xo).max() < 1e-5 * scale
+    e = np.linalg.norm(a - ao, axis=1) / np.linalg.norm(ao, axis=1)
+    say(f"  acc rms rel {np.sqrt(np.mean(e * e)):.2e}")
+    assert np.sqrt(np.mean(e * e)) < 1e-3
+    assert np.median(e) < 1e-5

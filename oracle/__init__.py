@@ -272,6 +272,11 @@ def _mac_sigs(lib):
     lib.orc_walk_kc.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64, _f64,
                                 C.c_double, C.c_double, C.c_double, C.c_double, _f64, _f64,
                                 C.c_int64, _i64, _f64, _f64, _i64, _i64, _i64, _i32]
+    lib.orc_walk_group.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
+                                   _f64, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
+                                   C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_int64,
+                                   C.c_int64, C.c_int64, C.c_double, _f64, _f64, _i64, _i64,
+                                   _i64, _i32]
     return lib
 
 
@@ -359,4 +364,38 @@ def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None):
                     float(tau), np.ascontiguousarray(kc, dtype=np.float64),
                     np.ascontiguousarray(anorm, dtype=np.float64), nt, tg, acc.ravel(), phi, npp,
                     npc, ncov, flag)
+    return WalkResult(acc, phi, npp, npc, ncov, flag)
+
+
+# ------------------------------------------------------------------ group walk
+def walk_group(b, eps, group=64, mode=0, theta=0.5, theta_max=1.0, tau=1e-3, kc=None,
+               anorm=None, order=2, target_range=None, tol=1e-5):
+    """Walk with one acceptance decision per group of ``group`` consecutive
+    sorted ranks in ``target_range`` (all bodies by default): mode 0 opening
+    angle, mode 1 error budget (kc per cell, anorm per sorted rank).
+    Results are indexed by rank - t0."""
+    lib = _mlib()
+    t = b["tree"]
+    M, com, Q = b["mom"]
+    n = b["smass"].shape[0]
+    t0, t1 = (0, n) if target_range is None else (int(target_range[0]), int(target_range[1]))
+    nt = max(t1 - t0, 0)
+    acc = np.zeros((nt, 3))
+    phi = np.zeros(nt)
+    npp = np.zeros(nt, dtype=np.int64)
+    npc = np.zeros(nt, dtype=np.int64)
+    ncov = np.zeros(nt, dtype=np.int64)
+    flag = np.zeros(nt, dtype=np.int32)
+    kcv = None if kc is None else np.ascontiguousarray(kc, dtype=np.float64)
+    anv = None if anorm is None else np.ascontiguousarray(anorm, dtype=np.float64)
+    if mode == 1 and (kcv is None or anv is None):
+        raise ValueError("the error-budget mode needs kc and anorm")
+    if nt:
+        lib.orc_walk_group(t["level"], t["hkey"], t["begin"], t["count"], t["next"], M,
+                           com.ravel(), Q.ravel(), b["spos"].ravel(), b["smass"],
+                           np.ascontiguousarray(b["lo"]), float(b["L"]), float(eps), int(order),
+                           int(mode), float(theta), float(theta_max), float(tau),
+                           None if kcv is None else kcv.ctypes.data,
+                           None if anv is None else anv.ctypes.data, int(group), t0, t1,
+                           float(tol), acc.ravel(), phi, npp, npc, ncov, flag)
     return WalkResult(acc, phi, npp, npc, ncov, flag)

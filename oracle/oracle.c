@@ -787,3 +787,155 @@ void orc_walk_kc(const int32_t *level, const uint64_t *hkey, const int32_t *begi
         if (flag) flag[t] = r.flag;
     }
 }
+
+/* ========================================================================
+ * Group walk: one acceptance decision per cell for a whole group of bodies.
+ *
+ * The bodies of sorted ranks [t0, t1) are split into consecutive groups of
+ * G.  A group's box is the axis-aligned bounding box of its bodies (centre
+ * bc, half extent bh).  For a multi-body cell C with side l, centre c and
+ * centre of mass x_C, the group distance is the distance from x_C to the
+ * box, d_g^2 = sum_a max(0, |x_C,a - bc_a| - bh_a)^2, and C overlaps the
+ * group when its closed cube meets the box (|c_a - bc_a| <= l/2 + bh_a on
+ * every axis).  C is accepted for every body of the group iff it does not
+ * overlap and
+ *   mode 0 (opening angle):  l^2 < theta^2 d_g^2;
+ *   mode 1 (error budget):   l^2 < theta_max^2 d_g^2 and
+ *                            kc_C < tau a_min d_g^5,  a_min = min |a_i|
+ *                            over the group.
+ * Accepted cells give every body of the group a particle-cell term with its
+ * own distance; one-body cells and rejected leaves particle-particle terms
+ * (a body skips itself); rejected internal cells are opened; the root is
+ * always opened.  Since d_g <= d for every body of the group, the group
+ * accepts a cell only where each of its bodies would.  With G = 1 the box
+ * is the body itself: d_g = d, the overlap test is "the body lies in the
+ * closed cube", and mode 0 is the per-body walk of Sec. 3 for theta below
+ * 1/sqrt(3) (where no accepted cell can contain the body).
+ *
+ * flag[t] is set for every body of a group that met a test within a
+ * relative tol of a threshold, or a cube face within tol * l of the box.
+ * ====================================================================== */
+typedef struct {
+    walk_ctx w;
+    const uint64_t *hkey;
+    const double *lo, *kc;
+    int mode;
+    double th2, tmax2, tau, amin, tol;
+    double bc[3], bh[3];
+    int64_t g0, g1;
+    walk_acc *r; /* one per body of the group */
+    int flag;
+} group_ctx;
+
+static void group_cell(group_ctx *g, int64_t node)
+{
+    const walk_ctx *w = &g->w;
+    for (int64_t c = node + 1; c < w->next[node]; c = w->next[c]) {
+        if (w->count[c] == 1) {
+            for (int64_t i = g->g0; i < g->g1; ++i)
+                if (w->begin[c] != i)
+                    pp(w, i, w->begin[c], &g->r[i - g->g0]);
+            continue;
+        }
+        const double side = ldexp(w->L, -w->level[c]);
+        double centre[3], dg2 = 0.0;
+        int overlap = 1;
+        cell_centre(g->hkey[c], w->level[c], g->lo, w->L, centre);
+        for (int a = 0; a < 3; ++a) {
+            const double gap = fabs(centre[a] - g->bc[a]) - (0.5 * side + g->bh[a]);
+            if (gap > 0.0)
+                overlap = 0;
+            if (fabs(gap) < g->tol * side)
+                g->flag = 1;
+            const double t = fabs(w->com[3 * c + a] - g->bc[a]) - g->bh[a];
+            if (t > 0.0)
+                dg2 += t * t;
+        }
+        const double s2 = side * side;
+        const double lim2 = (g->mode == 0 ? g->th2 : g->tmax2) * dg2;
+        int accept = !overlap && s2 < lim2;
+        if (!overlap && fabs(s2 - lim2) < g->tol * s2)
+            g->flag = 1;
+        if (g->mode == 1) {
+            const double rhs = g->tau * g->amin * dg2 * dg2 * sqrt(dg2);
+            if (!overlap && fabs(g->kc[c] - rhs) < g->tol * g->kc[c])
+                g->flag = 1;
+            accept = accept && g->kc[c] < rhs;
+        }
+        if (accept) {
+            for (int64_t i = g->g0; i < g->g1; ++i) {
+                double x[3];
+                for (int d = 0; d < 3; ++d)
+                    x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
+                pc(w, i, c, x, x[0] * x[0] + x[1] * x[1] + x[2] * x[2], &g->r[i - g->g0]);
+            }
+        } else if (w->next[c] == c + 1) {
+            for (int64_t i = g->g0; i < g->g1; ++i)
+                leaf_pp(w, i, c, &g->r[i - g->g0]);
+        } else {
+            group_cell(g, c);
+        }
+    }
+}
+
+/* Outputs indexed by t - t0 for t in [t0, t1). */
+void orc_walk_group(const int32_t *level, const uint64_t *hkey, const int32_t *begin,
+                    const int32_t *count, const int32_t *next, const double *M,
+                    const double *com, const double *Q, const double *spos, const double *smass,
+                    const double *lo, double L, double eps, int order, int mode, double theta,
+                    double theta_max, double tau, const double *kc, const double *anorm,
+                    int64_t G, int64_t t0, int64_t t1, double tol, double *acc, double *phi,
+                    int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag)
+{
+    const int64_t ng = (t1 - t0 + G - 1) / G;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t gi = 0; gi < ng; ++gi) {
+        group_ctx g;
+        memset(&g, 0, sizeof(g));
+        g.w = (walk_ctx){level, begin, count, next, M, com, Q, spos, smass, L, 0.0, eps * eps,
+                         order};
+        g.hkey = hkey;
+        g.lo = lo;
+        g.kc = kc;
+        g.mode = mode;
+        g.th2 = theta * theta;
+        g.tmax2 = theta_max * theta_max;
+        g.tau = tau;
+        g.tol = tol;
+        g.g0 = t0 + gi * G;
+        g.g1 = g.g0 + G < t1 ? g.g0 + G : t1;
+        double bl[3] = {INFINITY, INFINITY, INFINITY}, bu[3] = {-INFINITY, -INFINITY, -INFINITY};
+        g.amin = INFINITY;
+        for (int64_t i = g.g0; i < g.g1; ++i) {
+            for (int a = 0; a < 3; ++a) {
+                bl[a] = fmin(bl[a], spos[3 * i + a]);
+                bu[a] = fmax(bu[a], spos[3 * i + a]);
+            }
+            if (anorm)
+                g.amin = fmin(g.amin, anorm[i]);
+        }
+        for (int a = 0; a < 3; ++a) {
+            g.bc[a] = 0.5 * (bl[a] + bu[a]);
+            g.bh[a] = 0.5 * (bu[a] - bl[a]);
+        }
+        g.r = calloc((size_t)(g.g1 - g.g0), sizeof(walk_acc));
+        if (next[0] == 1) {
+            for (int64_t i = g.g0; i < g.g1; ++i)
+                leaf_pp(&g.w, i, 0, &g.r[i - g.g0]);
+        } else {
+            group_cell(&g, 0);
+        }
+        for (int64_t i = g.g0; i < g.g1; ++i) {
+            const walk_acc *r = &g.r[i - g.g0];
+            const int64_t o = i - t0;
+            for (int d = 0; d < 3; ++d)
+                acc[3 * o + d] = r->a[d];
+            if (phi) phi[o] = r->phi;
+            if (npp) npp[o] = r->npp;
+            if (npc) npc[o] = r->npc;
+            if (ncov) ncov[o] = r->ncov;
+            if (flag) flag[o] = g.flag;
+        }
+        free(g.r);
+    }
+}

@@ -1,0 +1,109 @@
+"""Pins for the oracle's group walk (one acceptance decision per group of
+consecutive sorted bodies)."""
+import numpy as np
+
+import oracle
+from paper_2203_08966_amd import workloads as W
+
+
+def _tree(n=6000, seed=3, leaf=8, kind="plummer"):
+    b = W.plummer(n, seed) if kind == "plummer" else W.clumpy(n, seed, n_clumps=6)
+    return b, oracle.build_all(b.pos, b.mass, leaf)
+
+
+def test_group_of_one_is_the_per_body_walk():
+    """G = 1: the box is the body, d_g = d; below theta = 1/sqrt(3) no
+    accepted cell can contain the body, so this is the walk of Sec. 3."""
+    b, bb = _tree()
+    for theta in (0.3, 0.5):
+        g = oracle.walk_group(bb, 0.01, group=1, theta=theta)
+        w = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], theta, 0.01)
+        np.testing.assert_array_equal(g.npp, w.npp)
+        np.testing.assert_array_equal(g.npc, w.npc)
+        np.testing.assert_allclose(g.acc, w.acc, rtol=1e-13, atol=0)
+        np.testing.assert_allclose(g.phi, w.phi, rtol=1e-13, atol=0)
+
+
+def test_group_of_one_budget_is_the_per_body_budget_walk():
+    b, bb = _tree(seed=4)
+    kc = oracle.cell_kc(bb, 0.01)
+    an = np.linalg.norm(oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"],
+                                    0.4, 0.01).acc, axis=1)
+    g = oracle.walk_group(bb, 0.01, group=1, mode=1, theta_max=0.9, tau=1e-3, kc=kc, anorm=an)
+    w = oracle.walk_kc(bb, 0.01, 0.9, 1e-3, kc, an)
+    np.testing.assert_array_equal(g.npp, w.npp)
+    np.testing.assert_array_equal(g.npc, w.npc)
+    np.testing.assert_allclose(g.acc, w.acc, rtol=1e-13, atol=0)
+
+
+def test_every_body_accounted_once_and_groups_only_tighten():
+    """Every other body is covered exactly once by each group walk; a group
+    decision accepts a cell only where each member's own test would, so the
+    error falls and the work rises against the per-body walk."""
+    b, bb = _tree(8000, 5, 8, "clumpy")
+    n = len(b.mass)
+    direct, _ = oracle.direct(bb["spos"], bb["smass"], 0.01)
+    w = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], 0.55, 0.01)
+
+    def rms(a):
+        e = np.linalg.norm(a - direct, axis=1) / np.linalg.norm(direct, axis=1)
+        return np.sqrt(np.mean(e * e))
+    prev = None
+    for G in (1, 8, 64):
+        g = oracle.walk_group(bb, 0.01, group=G, theta=0.55)
+        assert np.all(g.ncov == n - 1)
+        if prev is not None:
+            assert np.all(g.npp + g.npc >= 0)
+            assert rms(g.acc) <= rms(prev.acc) * 1.0001
+            assert (g.npp + g.npc).sum() >= (prev.npp + prev.npc).sum()
+        prev = g
+    assert rms(prev.acc) < rms(w.acc)
+
+
+def test_one_group_holding_everything_is_the_direct_sum():
+    """A single group whose box covers every cell opens everything: the
+    direct sum, particle-particle only."""
+    b, bb = _tree(700, 6)
+    g = oracle.walk_group(bb, 0.02, group=700, theta=0.9)
+    d, phi = oracle.direct(bb["spos"], bb["smass"], 0.02)
+    assert np.all(g.npc == 0) and np.all(g.npp == 699)
+    np.testing.assert_allclose(g.acc, d, rtol=1e-12, atol=1e-14)
+
+
+def test_ragged_target_range_and_box_geometry():
+    """Groups start at t0; the last one is ragged.  Hand check of one
+    decision: a far, light cell against a two-body group box."""
+    b, bb = _tree(3000, 7)
+    g_all = oracle.walk_group(bb, 0.01, group=64, theta=0.7)
+    g_sub = oracle.walk_group(bb, 0.01, group=64, theta=0.7, target_range=(128, 1000))
+    # groups [128, 192) ... [896, 960) coincide; [960, 1000) is ragged
+    np.testing.assert_array_equal(g_sub.npc[:832], g_all.npc[128:960])
+    np.testing.assert_allclose(g_sub.acc[:832], g_all.acc[128:960], rtol=1e-13, atol=0)
+    assert np.all(g_sub.ncov == 2999)
+    rag = oracle.walk_group(bb, 0.01, group=40, theta=0.7, target_range=(960, 1000))
+    np.testing.assert_array_equal(g_sub.npc[832:], rag.npc)
+    # group box: bodies at x = 0.1 and 0.3 (y = z = 0.5).  Bodies at
+    # (0.8, 0.5, 0.5) and (0.8, 0.7, 0.5) share the level-2 cube
+    # [0.75, 1) x [0.5, 0.75) x [0.5, 0.75) (side 0.25) and split below it;
+    # their COM (0.8, 0.6, 0.5) lies at d_g = sqrt(0.26) from the box (the
+    # box centre is farther, sqrt(0.37)).  Above theta = 0.25/d_g the cell is
+    # one particle-cell term for both group bodies, below it two
+    # particle-particle terms.
+    pos = np.array([[0.1, 0.5, 0.5], [0.3, 0.5, 0.5], [0.8, 0.5, 0.5], [0.8, 0.7, 0.5],
+                    [0.0, 0.0, 0.0], [0.99, 0.99, 0.99]])
+    mass = np.array([1.0, 1.0, 0.5, 0.5, 1e-9, 1e-9])
+    tb = oracle.build_all(pos, mass, 1)
+    assert tb["L"] == 1.0 and np.all(tb["lo"] == 0.0)
+    rank = np.empty(6, dtype=np.int64)
+    rank[tb["perm"]] = np.arange(6)
+    r0 = min(rank[0], rank[1])
+    assert abs(rank[0] - rank[1]) == 1
+    lim = 0.25 / np.sqrt(0.26)
+    for theta, accepted in ((lim * 1.001, True), (lim * 0.999, False)):
+        r = oracle.walk_group(tb, 0.0, group=2, theta=theta, target_range=(r0, r0 + 2))
+        assert np.all(r.ncov == 5)
+        assert np.all(r.npc == (1 if accepted else 0))
+        assert np.all(r.npp == (3 if accepted else 5))
+        # the box lies on the plane y = 0.5, a face of cubes it is tested
+        # against: flagged as a decision reduced precision may take otherwise
+        assert np.all(r.flag == 1)

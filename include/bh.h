@@ -47,6 +47,15 @@ enum {
 
 enum { BH_F32 = 0, BH_F64 = 1 };
 
+/* How the walk takes its decisions. */
+enum {
+    BH_WALK_BODY = 0, /* per body, as in Sec. 3 (wavefronts share the sweep) */
+    BH_WALK_GROUP = 1 /* one decision per cell for each wavefront of 64
+                         consecutive sorted bodies, against the distance from
+                         the cell's COM to the group's bounding box; a cell
+                         whose cube meets the box is always opened */
+};
+
 /* Acceptance criterion used by the walk. */
 enum {
     BH_MAC_THETA = 0,  /* side/distance < theta (Sec. 3) */
@@ -79,6 +88,14 @@ typedef struct {
     double mlp_log10_tau;     /* default -3 */
     const void *mlp_acc_norm; /* default NULL */
     double mlp_theta_est;     /* default 0.8 */
+    int walk;                 /* BH_WALK_BODY (default) or BH_WALK_GROUP */
+    int walk_stack;           /* group walk: LDS stack entries per wavefront,
+                                 1..1024, 0 = 1024; subtrees that do not fit
+                                 are walked without the stack (same result) */
+    int walk_cap;             /* group walk: a group whose work (particle-cell
+                                 terms + particle-particle bodies, per body)
+                                 would exceed this is walked per body with the
+                                 same criterion; 0 = 32768 */
 } bh_force_opts;
 
 /* Library version string. */

@@ -275,8 +275,8 @@ def _mac_sigs(lib):
     lib.orc_walk_group.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
                                    _f64, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
                                    C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_int64,
-                                   C.c_int64, C.c_int64, C.c_double, _f64, _f64, _i64, _i64,
-                                   _i64, _i32]
+                                   C.c_int64, C.c_int64, C.c_int64, C.c_double, _f64, _f64, _i64,
+                                   _i64, _i64, _i32]
     return lib
 
 
@@ -368,12 +368,16 @@ def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None):
 
 
 # ------------------------------------------------------------------ group walk
+GROUP_WORK_CAP = 32768
+
+
 def walk_group(b, eps, group=64, mode=0, theta=0.5, theta_max=1.0, tau=1e-3, kc=None,
-               anorm=None, order=2, target_range=None, tol=1e-5):
+               anorm=None, order=2, target_range=None, tol=1e-5, cap=GROUP_WORK_CAP):
     """Walk with one acceptance decision per group of ``group`` consecutive
     sorted ranks in ``target_range`` (all bodies by default): mode 0 opening
-    angle, mode 1 error budget (kc per cell, anorm per sorted rank).
-    Results are indexed by rank - t0."""
+    angle, mode 1 error budget (kc per cell, anorm per sorted rank).  Groups
+    whose work exceeds ``cap`` are walked per body.  Results are indexed by
+    rank - t0."""
     lib = _mlib()
     t = b["tree"]
     M, com, Q = b["mom"]
@@ -397,5 +401,5 @@ def walk_group(b, eps, group=64, mode=0, theta=0.5, theta_max=1.0, tau=1e-3, kc=
                            int(mode), float(theta), float(theta_max), float(tau),
                            None if kcv is None else kcv.ctypes.data,
                            None if anv is None else anv.ctypes.data, int(group), t0, t1,
-                           float(tol), acc.ravel(), phi, npp, npc, ncov, flag)
+                           int(cap), float(tol), acc.ravel(), phi, npp, npc, ncov, flag)
     return WalkResult(acc, phi, npp, npc, ncov, flag)

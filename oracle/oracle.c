@@ -812,6 +812,12 @@ void orc_walk_kc(const int32_t *level, const uint64_t *hkey, const int32_t *begi
  * closed cube", and mode 0 is the per-body walk of Sec. 3 for theta below
  * 1/sqrt(3) (where no accepted cell can contain the body).
  *
+ * The work of a group is the number of particle-cell terms plus the number
+ * of bodies of its particle-particle cells (its own bodies included), the
+ * same for each body of the group.  A group whose work exceeds cap is
+ * walked per body instead, with the same criterion: the walk of Sec. 3 at
+ * theta (mode 0), or the per-body error-budget walk (mode 1).
+ *
  * flag[t] is set for every body of a group that met a test within a
  * relative tol of a threshold, or a cube face within tol * l of the box.
  * ====================================================================== */
@@ -825,6 +831,7 @@ typedef struct {
     int64_t g0, g1;
     walk_acc *r; /* one per body of the group */
     int flag;
+    int64_t work;
 } group_ctx;
 
 static void group_cell(group_ctx *g, int64_t node)
@@ -835,6 +842,7 @@ static void group_cell(group_ctx *g, int64_t node)
             for (int64_t i = g->g0; i < g->g1; ++i)
                 if (w->begin[c] != i)
                     pp(w, i, w->begin[c], &g->r[i - g->g0]);
+            g->work += 1;
             continue;
         }
         const double side = ldexp(w->L, -w->level[c]);
@@ -869,9 +877,11 @@ static void group_cell(group_ctx *g, int64_t node)
                     x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
                 pc(w, i, c, x, x[0] * x[0] + x[1] * x[1] + x[2] * x[2], &g->r[i - g->g0]);
             }
+            g->work += 1;
         } else if (w->next[c] == c + 1) {
             for (int64_t i = g->g0; i < g->g1; ++i)
                 leaf_pp(w, i, c, &g->r[i - g->g0]);
+            g->work += w->count[c];
         } else {
             group_cell(g, c);
         }
@@ -884,8 +894,8 @@ void orc_walk_group(const int32_t *level, const uint64_t *hkey, const int32_t *b
                     const double *com, const double *Q, const double *spos, const double *smass,
                     const double *lo, double L, double eps, int order, int mode, double theta,
                     double theta_max, double tau, const double *kc, const double *anorm,
-                    int64_t G, int64_t t0, int64_t t1, double tol, double *acc, double *phi,
-                    int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag)
+                    int64_t G, int64_t t0, int64_t t1, int64_t cap, double tol, double *acc,
+                    double *phi, int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag)
 {
     const int64_t ng = (t1 - t0 + G - 1) / G;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -922,8 +932,40 @@ void orc_walk_group(const int32_t *level, const uint64_t *hkey, const int32_t *b
         if (next[0] == 1) {
             for (int64_t i = g.g0; i < g.g1; ++i)
                 leaf_pp(&g.w, i, 0, &g.r[i - g.g0]);
+            g.work = count[0];
         } else {
             group_cell(&g, 0);
+        }
+        if (g.work > cap) { /* too spread out for one decision: per body */
+            memset(g.r, 0, (size_t)(g.g1 - g.g0) * sizeof(walk_acc));
+            g.flag = 0;
+            for (int64_t i = g.g0; i < g.g1; ++i) {
+                walk_acc *r = &g.r[i - g.g0];
+                if (mode == 0) {
+                    walk_ctx w1 = g.w;
+                    w1.theta2 = theta * theta;
+                    if (next[0] == 1)
+                        leaf_pp(&w1, i, 0, r);
+                    else
+                        cell_force(&w1, 0, i, r);
+                } else {
+                    mac_ctx mc;
+                    memset(&mc, 0, sizeof(mc));
+                    mc.w = g.w;
+                    mc.hkey = hkey;
+                    mc.lo = lo;
+                    mc.tmax2 = theta_max * theta_max;
+                    mc.kc = kc;
+                    mc.tau = tau;
+                    mc.anorm = anorm[i];
+                    if (next[0] == 1)
+                        leaf_pp(&mc.w, i, 0, r);
+                    else
+                        cell_force_kc(&mc, 0, i, r);
+                }
+                if (r->flag)
+                    g.flag = 1;
+            }
         }
         for (int64_t i = g.g0; i < g.g1; ++i) {
             const walk_acc *r = &g.r[i - g.g0];

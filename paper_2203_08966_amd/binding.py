@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbh.so")
 BH_OK, BH_E_INVALID, BH_E_NOMEM, BH_E_DEVICE, BH_E_STATE, BH_E_NONFINITE = 0, -1, -2, -3, -4, -5
 BH_F32, BH_F64 = 0, 1
 BH_MAC_THETA, BH_MAC_MLP, BH_MAC_BUDGET = 0, 1, 2
+BH_WALK_BODY, BH_WALK_GROUP = 0, 1
 
 EXPORTED = [
     "bh_version", "bh_last_error", "bh_force_opts_default", "bh_ctx_create", "bh_ctx_set_stream",
@@ -32,7 +33,7 @@ BH_MLP_PARAMS = 1441
 __all__ = EXPORTED + [
     "BHError", "ForceOpts", "TreeInfo", "force_opts", "load", "BH_OK", "BH_E_INVALID",
     "BH_E_NOMEM", "BH_E_DEVICE", "BH_E_STATE", "BH_E_NONFINITE", "BH_F32", "BH_F64",
-    "BH_MAC_THETA", "BH_MAC_MLP", "BH_MAC_BUDGET",
+    "BH_MAC_THETA", "BH_MAC_MLP", "BH_MAC_BUDGET", "BH_WALK_BODY", "BH_WALK_GROUP",
 ]
 
 
@@ -48,6 +49,7 @@ class ForceOpts(C.Structure):
         ("n_pc", C.c_void_p), ("target_begin", C.c_int64), ("target_end", C.c_int64),
         ("mlp_theta_max", C.c_double), ("mlp_log10_tau", C.c_double),
         ("mlp_acc_norm", C.c_void_p), ("mlp_theta_est", C.c_double),
+        ("walk", C.c_int), ("walk_stack", C.c_int), ("walk_cap", C.c_int),
     ]
 
 
@@ -160,7 +162,7 @@ def _stream():
 
 def force_opts(order=2, mac=BH_MAC_THETA, phi=None, n_pp=None, n_pc=None, target_range=None,
                mlp_theta_max=None, mlp_log10_tau=None, mlp_acc_norm=None,
-               mlp_theta_est=None) -> ForceOpts:
+               mlp_theta_est=None, walk=BH_WALK_BODY, walk_stack=0, walk_cap=0) -> ForceOpts:
     """Walk options.  mlp_acc_norm: device tensor of |a_i| in caller order
     and the tree's dtype (kept alive by the caller until the walk ran)."""
     o = ForceOpts()
@@ -179,6 +181,9 @@ def force_opts(order=2, mac=BH_MAC_THETA, phi=None, n_pp=None, n_pc=None, target
     o.mlp_acc_norm = _dev(mlp_acc_norm, "mlp_acc_norm")
     if mlp_theta_est is not None:
         o.mlp_theta_est = mlp_theta_est
+    o.walk = walk
+    o.walk_stack = walk_stack
+    o.walk_cap = walk_cap
     return o
 
 

@@ -64,7 +64,7 @@ static void free_tree_bufs(bh_tree *t) {
                      &t->level, &t->begin, &t->count, &t->next, &t->parent, &t->cmask,
                      &t->lvl_list, &t->cx, &t->cy, &t->cz, &t->mom, &t->recs,
                      &t->cube, &t->part, &t->hist, &t->status, &t->misc, &t->cnt_scratch,
-                     &t->cellf, &t->kc, &t->anorm, &t->est_acc};
+                     &t->cellf, &t->kc, &t->anorm, &t->est_acc, &t->kids};
     for (DevBuf *b : all) free_buf(*b);
 }
 
@@ -88,6 +88,11 @@ static int check_opts(const bh_force_opts &o, int64_t n) {
         !(o.mlp_theta_max > 0 && isfinite(o.mlp_theta_max) && isfinite(o.mlp_log10_tau) &&
           o.mlp_theta_est >= 0 && isfinite(o.mlp_theta_est)))
         return set_error(BH_E_INVALID, "opts learned-criterion parameters invalid");
+    if (o.walk != BH_WALK_BODY && o.walk != BH_WALK_GROUP)
+        return set_error(BH_E_INVALID, "opts.walk must be BH_WALK_BODY or BH_WALK_GROUP");
+    if (o.walk_stack < 0 || o.walk_stack > 1024)
+        return set_error(BH_E_INVALID, "opts.walk_stack must be in [0, 1024]");
+    if (o.walk_cap < 0) return set_error(BH_E_INVALID, "opts.walk_cap must be >= 0");
     return BH_OK;
 }
 
@@ -124,6 +129,9 @@ void bh_force_opts_default(bh_force_opts *o) {
     o->mlp_log10_tau = -3.0;
     o->mlp_acc_norm = nullptr;
     o->mlp_theta_est = 0.8;
+    o->walk = BH_WALK_BODY;
+    o->walk_stack = 0;
+    o->walk_cap = 0;
 }
 
 int bh_ctx_create(int device, void *stream, bh_ctx **out) {

@@ -125,6 +125,8 @@ struct bh_tree {
     // learned criterion: cell features, k_C M l^3, |a| per sorted rank,
     // estimate accelerations; cache keys of cellf/kc
     bh::DevBuf cellf, kc, anorm, est_acc;
+    bh::DevBuf kids;                           // group walk: children per node
+    int64_t kids_tree_id = -1;
     int kc_version = -2;
     double kc_eps = -1.0;
     int64_t build_id = 0, kc_tree_id = -1;

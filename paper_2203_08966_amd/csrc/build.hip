@@ -804,6 +804,7 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     const int nbbox = nb < 1024 ? nb : 1024;
     const int nkeys = nb < 2048 ? nb : 2048;
     int rc;
+    const size_t status_cap0 = t->status.cap;
     // ---- allocations sized by n
     if ((rc = grow(t->keys_a, 8ull * n)) || (rc = grow(t->keys_b, 8ull * n)) ||
         (rc = grow(t->idx_a, 4ull * n)) || (rc = grow(t->idx_b, 4ull * n)) ||
@@ -832,6 +833,12 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
 
     k_fill_u32<<<1, 64, 0, st>>>(misc, 16, 0u);
     k_fill_u32<<<8, 256, 0, st>>>(hist, 2048, 0u);
+    if (t->status.cap != status_cap0) {
+        // fresh look-back status memory: clear it, or leftover words of
+        // whatever used the memory before could carry the current epoch
+        const int64_t words = (int64_t)(t->status.cap / 4);
+        k_fill_u32<<<(int)((words + 255) / 256), 256, 0, st>>>((uint32_t *)t->status.p, words, 0u);
+    }
     k_bbox<T><<<nbbox, kThreads, 0, st>>>(pos, n, (double *)t->part.p, flags);
     k_cube<<<1, kThreads, 0, st>>>((const double *)t->part.p, nbbox, cube);
     k_keys<T><<<nkeys, kThreads, 0, st>>>(pos, n, cube, (uint64_t *)t->keys_a.p, hist);

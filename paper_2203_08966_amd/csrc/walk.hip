@@ -48,8 +48,7 @@ __device__ __forceinline__ void leaf_pp(const BodyRec<R> *__restrict__ bodies, i
                                         int i, R X, R Y, R Z, R eps2, R &sx, R &sy, R &sz,
                                         R &sp, uint32_t &cpp) {
     R px = 0, py = 0, pz = 0, pq = 0;
-    for (int j = jb; j < je; ++j) {
-        const BodyRec<R> s = bodies[j];
+    auto term = [&](const BodyRec<R> &s, int j) {
         if (!SELF || j != i) {
             const R dx = s.x - X, dy = s.y - Y, dz = s.z - Z;
             R r2 = dx * dx + eps2;
@@ -64,7 +63,17 @@ __device__ __forceinline__ void leaf_pp(const BodyRec<R> *__restrict__ bodies, i
             if (PHI) pq -= minv;
             if (CNT && SELF) ++cpp;
         }
+    };
+    int j = jb;
+    for (; j + 4 <= je; j += 4) {  // four uniform loads in flight, then the terms in order
+        const BodyRec<R> s0 = bodies[j], s1 = bodies[j + 1], s2 = bodies[j + 2],
+                         s3 = bodies[j + 3];
+        term(s0, j);
+        term(s1, j + 1);
+        term(s2, j + 2);
+        term(s3, j + 3);
     }
+    for (; j < je; ++j) term(bodies[j], j);
     if (CNT && !SELF) cpp += (uint32_t)(je - jb);
     sx += px;
     sy += py;
@@ -80,44 +89,17 @@ struct MlpMac {
     float tmax2, tau;
 };
 
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool MLP>
-__global__ __launch_bounds__(256) void k_walk(
-    const typename NodeRecT<R>::type *__restrict__ nodes, int m,
-    const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
-    const uint32_t *__restrict__ perm, int nbodies, int t0, int t1, int nwaves_padded,
-    R theta2, R eps2, R *__restrict__ acc, R *__restrict__ phi_out,
-    uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out, MlpMac mac) {
+// The per-body walk of one wavefront (see the file header): lane body i
+// (live), its offset (ox, oy, oz) from its leaf centre (ax, ay, az), leaf
+// index myleaf; sums into s*, counts into cpp/cpc.
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool MLP>
+__device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__restrict__ nodes,
+                                           int m, const BodyRec<R> *__restrict__ bodies,
+                                           int nbodies, int i, bool live, R ox, R oy, R oz,
+                                           R ax, R ay, R az, int myleaf, R theta2, R eps2,
+                                           const MlpMac &mac, R &sx, R &sy, R &sz, R &sp,
+                                           uint32_t &cpp, uint32_t &cpc) {
     using Rec = typename NodeRecT<R>::type;
-    // XCD-aware placement: consecutive workgroups land on different XCDs,
-    // so hand each XCD a contiguous run of 8 logical blocks (spatially
-    // close waves then share that XCD's L2).
-    const int nblk = nwaves_padded / 4;
-    const int b = blockIdx.x;
-    const int xcd = b & 7, r = b >> 3;
-    const int lb = (r >> 3) * 64 + xcd * 8 + (r & 7);
-    if (lb >= nblk) return;
-    const int wave = lb * 4 + (int)(threadIdx.x >> 6);
-    const int base = t0 + wave * 64;
-    if (base >= t1) return;
-    const int i = base + (int)lane_id();
-    const bool live = i < t1;
-
-    R ox = 0, oy = 0, oz = 0;
-    R ax = 0, ay = 0, az = 0;
-    int myleaf = -1;
-    if (live) {
-        const BodyRec<R> me = bodies[i];
-        ox = me.x;
-        oy = me.y;
-        oz = me.z;
-        const Anchor<R> an = anchors[i];
-        ax = an.x;
-        ay = an.y;
-        az = an.z;
-        myleaf = an.leaf;
-    }
-    R sx = 0, sy = 0, sz = 0, sp = 0;
-    uint32_t cpp = 0, cpc = 0;
     float tau_a = 0.f;  // tau |a_i|
     if (MLP && live) tau_a = mac.tau * mac.anorm[i];
 
@@ -153,36 +135,34 @@ __global__ __launch_bounds__(256) void k_walk(
             } else {
                 accept = act && nd.l2 < theta2 * d2;
             }
-            {
-                if (accept) {  // skipped as a whole when no lane accepts
-                    const R inv = rsq(d2 + eps2);
-                    const R inv2 = inv * inv;
-                    const R inv3 = inv * inv2;
-                    if (ORDER2) {
-                        const R qzz = -nd.qxx - nd.qyy;
-                        const R qx = nd.qxx * x + nd.qxy * y + nd.qxz * z;
-                        const R qy = nd.qxy * x + nd.qyy * y + nd.qyz * z;
-                        const R qz = nd.qxz * x + nd.qyz * y + qzz * z;
-                        const R xqx = x * qx + y * qy + z * qz;
-                        const R inv5 = inv3 * inv2;
-                        const R t5 = xqx * inv5;
-                        const R g = nd.m * inv3 + (R)2.5 * t5 * inv2;
-                        sx = inv5 * qx + sx;
-                        sy = inv5 * qy + sy;
-                        sz = inv5 * qz + sz;
-                        sx = -g * x + sx;
-                        sy = -g * y + sy;
-                        sz = -g * z + sz;
-                        if (PHI) sp = sp - nd.m * inv - (R)0.5 * t5;
-                    } else {
-                        const R g = nd.m * inv3;
-                        sx = -g * x + sx;
-                        sy = -g * y + sy;
-                        sz = -g * z + sz;
-                        if (PHI) sp = sp - nd.m * inv;
-                    }
-                    if (CNT) ++cpc;
+            if (accept) {  // skipped as a whole when no lane accepts
+                const R inv = rsq(d2 + eps2);
+                const R inv2 = inv * inv;
+                const R inv3 = inv * inv2;
+                if (ORDER2) {
+                    const R qzz = -nd.qxx - nd.qyy;
+                    const R qx = nd.qxx * x + nd.qxy * y + nd.qxz * z;
+                    const R qy = nd.qxy * x + nd.qyy * y + nd.qyz * z;
+                    const R qz = nd.qxz * x + nd.qyz * y + qzz * z;
+                    const R xqx = x * qx + y * qy + z * qz;
+                    const R inv5 = inv3 * inv2;
+                    const R t5 = xqx * inv5;
+                    const R g = nd.m * inv3 + (R)2.5 * t5 * inv2;
+                    sx = inv5 * qx + sx;
+                    sy = inv5 * qy + sy;
+                    sz = inv5 * qz + sz;
+                    sx = -g * x + sx;
+                    sy = -g * y + sy;
+                    sz = -g * z + sz;
+                    if (PHI) sp = sp - nd.m * inv - (R)0.5 * t5;
+                } else {
+                    const R g = nd.m * inv3;
+                    sx = -g * x + sx;
+                    sy = -g * y + sy;
+                    sz = -g * z + sz;
+                    if (PHI) sp = sp - nd.m * inv;
                 }
+                if (CNT) ++cpc;
             }
             if (nxt == idx + 1) pp = act && !accept;  // leaf
             else open = act && !accept;
@@ -199,6 +179,47 @@ __global__ __launch_bounds__(256) void k_walk(
         if (act) resume = open ? idx + 1 : nxt;
         idx = any_open ? idx + 1 : (nxt > idx ? nxt : idx + 1);  // always moves forward
     }
+}
+
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool MLP>
+__global__ __launch_bounds__(256) void k_walk(
+    const typename NodeRecT<R>::type *__restrict__ nodes, int m,
+    const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
+    const uint32_t *__restrict__ perm, int nbodies, int t0, int t1, int nwaves_padded,
+    R theta2, R eps2, R *__restrict__ acc, R *__restrict__ phi_out,
+    uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out, MlpMac mac) {
+    // XCD-aware placement: consecutive workgroups land on different XCDs,
+    // so hand each XCD a contiguous run of 8 logical blocks (spatially
+    // close waves then share that XCD's L2).
+    const int nblk = nwaves_padded / 4;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, r = b >> 3;
+    const int lb = (r >> 3) * 64 + xcd * 8 + (r & 7);
+    if (lb >= nblk) return;
+    const int wave = lb * 4 + (int)(threadIdx.x >> 6);
+    const int base = t0 + wave * 64;
+    if (base >= t1) return;
+    const int i = base + (int)lane_id();
+    const bool live = i < t1;
+
+    R ox = 0, oy = 0, oz = 0;
+    R ax = 0, ay = 0, az = 0;
+    int myleaf = -1;
+    if (live) {
+        const BodyRec<R> me = bodies[i];
+        ox = me.x;
+        oy = me.y;
+        oz = me.z;
+        const Anchor<R> an = anchors[i];
+        ax = an.x;
+        ay = an.y;
+        az = an.z;
+        myleaf = an.leaf;
+    }
+    R sx = 0, sy = 0, sz = 0, sp = 0;
+    uint32_t cpp = 0, cpc = 0;
+    body_sweep<R, ORDER2, PHI, CNT, MLP>(nodes, m, bodies, nbodies, i, live, ox, oy, oz, ax, ay,
+                                         az, myleaf, theta2, eps2, mac, sx, sy, sz, sp, cpp, cpc);
     if (live) {
         const int o = SORTED_OUT ? i : (int)perm[i];
         acc[3 * (int64_t)o + 0] = sx;
@@ -239,6 +260,353 @@ void dispatch2(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, 
 #undef BH_W
 }
 
+
+// ---------------------------------------------------------------- group walk
+// One wavefront = one group of 64 consecutive sorted bodies, one decision
+// per cell for the whole group: the cell is accepted iff its cube does not
+// meet the group's bounding box and side < theta * d_g (opening angle) or,
+// error budget, side < theta_max * d_g and k_C M l^3 < tau a_min d_g^5,
+// with d_g the distance from the cell's COM to the box and a_min the
+// smallest |a_i| of the group.  Since every decision is wave-uniform, no lane
+// idles while others descend, and the tests themselves run lane-parallel:
+// the wave pops up to 64 nodes from a stack in LDS, each lane classifies
+// one, children of opened nodes are pushed (child table, prefix sum over
+// the lanes), then every lane evaluates each accepted cell and each
+// particle-particle leaf of the round with its own body.  If the children
+// would overflow the stack, the opened subtrees are walked one at a time
+// by a sequential pre-order sweep that needs no memory.
+//
+// A group spread over a large region (64 bodies consecutive on the
+// space-filling curve can straddle one of its jumps) would open nearly
+// everything.  The group's work (particle-cell terms plus particle-particle
+// bodies, the same for each of its bodies) is therefore capped: a group
+// that would exceed the cap drops its partial sums and is walked per body
+// with the same criterion instead.
+constexpr int kGroupStack = 1024;      // LDS stack entries per wavefront
+constexpr int kGroupWorkCap = 32768;   // default per-group work cap
+
+struct GroupMac {
+    const float *kc;     // error budget: k_C M l^3 per node
+    const float *anorm;  // |a_i| per sorted rank
+    float tau;
+    int cap;             // stack entries used (<= kGroupStack)
+    int work_cap;        // per-group work above which the group walks per body
+};
+
+// kids[8 c + q], q < #children: the children of internal node c in
+// pre-order, then -1.
+__global__ __launch_bounds__(256) void k_kids(int m, const int32_t *__restrict__ next,
+                                              int32_t *__restrict__ kids) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    int k[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+    const int end = next[c];
+    int q = 0;
+    for (int ch = c + 1; ch < end && q < 8;) {
+        k[q++] = ch;
+        const int nx = next[ch];
+        if (nx <= ch) break;  // malformed skip pointer: stop
+        ch = nx;
+    }
+    int4 *o = (int4 *)(kids + 8 * (int64_t)c);
+    o[0] = make_int4(k[0], k[1], k[2], k[3]);
+    o[1] = make_int4(k[4], k[5], k[6], k[7]);
+}
+
+template <typename R>
+__device__ __forceinline__ R wave_min(R v) {
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) v = fmin(v, __shfl_xor(v, s));
+    return v;
+}
+template <typename R>
+__device__ __forceinline__ R wave_max(R v) {
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) v = fmax(v, __shfl_xor(v, s));
+    return v;
+}
+
+enum : int { kGNone = 0, kGPC = 1, kGPP = 2, kGOpen = 3 };
+
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool BUDGET>
+__global__ __launch_bounds__(256) void k_gwalk(
+    const typename NodeRecT<R>::type *__restrict__ nodes, int m,
+    const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
+    const int4 *__restrict__ kids, const uint32_t *__restrict__ perm, int nbodies, int t0,
+    int t1, int nwaves_padded, R theta2, R eps2, R *__restrict__ acc, R *__restrict__ phi_out,
+    uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out, GroupMac gm) {
+    using Rec = typename NodeRecT<R>::type;
+    __shared__ int stack_all[4][kGroupStack];
+    const int nblk = nwaves_padded / 4;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, r = b >> 3;
+    const int lb = (r >> 3) * 64 + xcd * 8 + (r & 7);
+    if (lb >= nblk) return;
+    const int wave = lb * 4 + (int)(threadIdx.x >> 6);
+    const int base = t0 + wave * 64;
+    if (base >= t1) return;
+    int *stk = stack_all[threadIdx.x >> 6];
+    const int lane = (int)lane_id();
+    const int i = base + lane;
+    const bool live = i < t1;
+    const int g_end = min(base + 64, t1);
+
+    R ox = 0, oy = 0, oz = 0, ax = 0, ay = 0, az = 0;
+    int myleaf = -1;
+    if (live) {
+        const BodyRec<R> me = bodies[i];
+        ox = me.x;
+        oy = me.y;
+        oz = me.z;
+        const Anchor<R> an = anchors[i];
+        ax = an.x;
+        ay = an.y;
+        az = an.z;
+        myleaf = an.leaf;
+    }
+    // the group's bounding box, relative to the leaf centre g of the first
+    // body: grid centres differ exactly, so the box and the cell distances
+    // are accurate to the rounding of the offsets
+    const R gx = __shfl(ax, 0), gy = __shfl(ay, 0), gz = __shfl(az, 0);
+    const R big = (R)3.0e38;
+    const R px = (ax - gx) + ox, py = (ay - gy) + oy, pz = (az - gz) + oz;
+    const R lx = wave_min(live ? px : big), ly = wave_min(live ? py : big),
+            lz = wave_min(live ? pz : big);
+    const R hx = wave_max(live ? px : -big), hy = wave_max(live ? py : -big),
+            hz = wave_max(live ? pz : -big);
+    const R bcx = (R)0.5 * (lx + hx), bcy = (R)0.5 * (ly + hy), bcz = (R)0.5 * (lz + hz);
+    const R bhx = (R)0.5 * (hx - lx), bhy = (R)0.5 * (hy - ly), bhz = (R)0.5 * (hz - lz);
+    float tau_amin = 0.f;
+    if (BUDGET) tau_amin = gm.tau * wave_min(live ? gm.anorm[i] : 3.0e38f);
+
+    R sx = 0, sy = 0, sz = 0, sp = 0;
+    uint32_t cpp = 0, cpc = 0;
+    int work = 0;  // wave-uniform
+
+    // decision for node c (any lane; wave-uniform when the node is)
+    auto classify = [&](const Rec &nd, int c, float kcv) -> int {
+        if (c == 0) return kGOpen;  // the root is always opened
+        if (nd.count == 1) return kGPP;
+        const R hs = (R)0.5 * sqrt(nd.l2);
+        const R ux = (nd.cx - gx) - bcx, uy = (nd.cy - gy) - bcy, uz = (nd.cz - gz) - bcz;
+        const bool overlap = fabs(ux) <= hs + bhx && fabs(uy) <= hs + bhy && fabs(uz) <= hs + bhz;
+        const R tx = fmax(fabs(ux + nd.mx) - bhx, (R)0);
+        const R ty = fmax(fabs(uy + nd.my) - bhy, (R)0);
+        const R tz = fmax(fabs(uz + nd.mz) - bhz, (R)0);
+        const R dg2 = tx * tx + ty * ty + tz * tz;
+        bool accept = !overlap && nd.l2 < theta2 * dg2;
+        if (BUDGET) accept = accept && kcv < tau_amin * (float)(dg2 * dg2 * sqrt(dg2));
+        if (accept) return kGPC;
+        return nd.next == c + 1 ? kGPP : kGOpen;
+    };
+    // particle-cell term of node nd for this lane's body
+    auto cell_term = [&](const Rec &nd) {
+        const R X = (ax - nd.cx) + ox, Y = (ay - nd.cy) + oy, Z = (az - nd.cz) + oz;
+        const R x = X - nd.mx, y = Y - nd.my, z = Z - nd.mz;
+        const R d2 = x * x + y * y + z * z;
+        const R inv = rsq(d2 + eps2);
+        const R inv2 = inv * inv;
+        const R inv3 = inv * inv2;
+        if (ORDER2) {
+            const R qzz = -nd.qxx - nd.qyy;
+            const R qx = nd.qxx * x + nd.qxy * y + nd.qxz * z;
+            const R qy = nd.qxy * x + nd.qyy * y + nd.qyz * z;
+            const R qz = nd.qxz * x + nd.qyz * y + qzz * z;
+            const R xqx = x * qx + y * qy + z * qz;
+            const R inv5 = inv3 * inv2;
+            const R t5 = xqx * inv5;
+            const R g = nd.m * inv3 + (R)2.5 * t5 * inv2;
+            sx = inv5 * qx + sx;
+            sy = inv5 * qy + sy;
+            sz = inv5 * qz + sz;
+            sx = -g * x + sx;
+            sy = -g * y + sy;
+            sz = -g * z + sz;
+            if (PHI) sp = sp - nd.m * inv - (R)0.5 * t5;
+        } else {
+            const R g = nd.m * inv3;
+            sx = -g * x + sx;
+            sy = -g * y + sy;
+            sz = -g * z + sz;
+            if (PHI) sp = sp - nd.m * inv;
+        }
+        if (CNT) ++cpc;
+        ++work;
+    };
+    // particle-particle terms with the bodies of leaf (or one-body cell) nd
+    auto leaf_terms = [&](const Rec &nd) {
+        const int jb = uniform(nd.begin);
+        const int je = min(jb + uniform(nd.count), nbodies);  // guard
+        const R X = (ax - nd.cx) + ox, Y = (ay - nd.cy) + oy, Z = (az - nd.cz) + oz;
+        work += je - jb;
+        if (jb < g_end && je > base)  // holds bodies of the group: skip self
+            leaf_pp<R, PHI, CNT, true>(bodies, jb, je, i, X, Y, Z, eps2, sx, sy, sz, sp, cpp);
+        else
+            leaf_pp<R, PHI, CNT, false>(bodies, jb, je, i, X, Y, Z, eps2, sx, sy, sz, sp, cpp);
+    };
+    // the subtree below node r without the stack (overflow path)
+    auto sweep = [&](int r0) {
+        int idx = uniform(r0) + 1;
+        const int end = uniform(nodes[uniform(r0)].next);
+        while (idx < end && work <= gm.work_cap) {
+            idx = uniform(idx);
+            const Rec nd = nodes[idx];
+            const int cls = uniform(classify(nd, idx, BUDGET ? gm.kc[idx] : 0.f));
+            if (cls == kGPC) cell_term(nd);
+            else if (cls == kGPP) leaf_terms(nd);
+            const int nx = uniform(nd.next);
+            idx = cls == kGOpen || nx <= idx ? idx + 1 : nx;  // always moves forward
+        }
+    };
+
+    if (nodes[0].next == 1) {  // the root is a leaf
+        leaf_terms(nodes[0]);
+    } else {
+        if (lane == 0) stk[0] = 0;
+        int top = 1;  // wave-uniform stack size
+        while (top > 0 && work <= gm.work_cap) {
+            top = uniform(top);
+            const int k = min(top, 64);
+            top -= k;
+            __builtin_amdgcn_wave_barrier();
+            const bool has = lane < k;
+            const int c = has ? stk[top + lane] : 0;
+            int cls = kGNone;
+            int4 k0 = make_int4(-1, -1, -1, -1), k1 = k0;
+            if (has) {
+                k0 = kids[2 * (int64_t)c];  // loaded with the record, used if opened
+                k1 = kids[2 * (int64_t)c + 1];
+                cls = classify(nodes[c], c, BUDGET ? gm.kc[c] : 0.f);
+            }
+            const uint64_t m_pc = __ballot(cls == kGPC);
+            const uint64_t m_pp = __ballot(cls == kGPP);
+            const uint64_t m_op = __ballot(cls == kGOpen);
+            if (m_op) {
+                const int kid[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+                int nk = 0;
+                if (cls == kGOpen) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) nk += kid[q] >= 0 ? 1 : 0;
+                }
+                // exclusive prefix sum of nk (0..8) over the lanes, bit by bit
+                int excl = 0, total = 0;
+#pragma unroll
+                for (int bit = 0; bit < 4; ++bit) {
+                    const uint64_t bm = __ballot((nk >> bit) & 1);
+                    excl += (int)__builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u))
+                            << bit;
+                    total += __builtin_popcountll(bm) << bit;
+                }
+                if (top + total <= gm.cap) {
+                    const int off = top + excl;
+                    for (int q = 0; q < nk; ++q) stk[off + q] = kid[q];
+                    top += total;
+                } else {
+                    uint64_t mm = m_op;
+                    while (mm) {
+                        const int bit = __builtin_ctzll(mm);
+                        mm &= mm - 1;
+                        sweep(__builtin_amdgcn_readlane(c, bit));
+                    }
+                }
+            }
+            // accepted cells, four records in flight at a time
+            uint64_t mm = m_pc;
+            while (mm) {
+                const int n0 = __builtin_amdgcn_readlane(c, __builtin_ctzll(mm));
+                mm &= mm - 1;
+                int n1 = n0, n2 = n0, n3 = n0;
+                const bool h1 = mm != 0;
+                if (h1) {
+                    n1 = __builtin_amdgcn_readlane(c, __builtin_ctzll(mm));
+                    mm &= mm - 1;
+                }
+                const bool h2 = mm != 0;
+                if (h2) {
+                    n2 = __builtin_amdgcn_readlane(c, __builtin_ctzll(mm));
+                    mm &= mm - 1;
+                }
+                const bool h3 = mm != 0;
+                if (h3) {
+                    n3 = __builtin_amdgcn_readlane(c, __builtin_ctzll(mm));
+                    mm &= mm - 1;
+                }
+                const Rec r0 = nodes[n0], r1 = nodes[n1], r2 = nodes[n2], r3 = nodes[n3];
+                cell_term(r0);
+                if (h1) cell_term(r1);
+                if (h2) cell_term(r2);
+                if (h3) cell_term(r3);
+            }
+            mm = m_pp;
+            while (mm) {
+                const int bit = __builtin_ctzll(mm);
+                mm &= mm - 1;
+                leaf_terms(nodes[__builtin_amdgcn_readlane(c, bit)]);
+            }
+        }
+    }
+    if (work > gm.work_cap) {  // too spread out for one decision: walk per body
+        sx = sy = sz = sp = 0;
+        cpp = cpc = 0;
+        const MlpMac pm{gm.kc, gm.anorm, (float)theta2, gm.tau};
+        body_sweep<R, ORDER2, PHI, CNT, BUDGET>(nodes, m, bodies, nbodies, i, live, ox, oy, oz,
+                                                ax, ay, az, myleaf, theta2, eps2, pm, sx, sy, sz,
+                                                sp, cpp, cpc);
+    }
+    if (live) {
+        const int o = SORTED_OUT ? i : (int)perm[i];
+        acc[3 * (int64_t)o + 0] = sx;
+        acc[3 * (int64_t)o + 1] = sy;
+        acc[3 * (int64_t)o + 2] = sz;
+        if (PHI) phi_out[o] = sp;
+        if (CNT) {
+            npp_out[o] = cpp;
+            npc_out[o] = cpc;
+        }
+    }
+}
+
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED, bool BUDGET>
+void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
+             uint32_t *npp, uint32_t *npc, const GroupMac &gm) {
+    const int nw = div_up(t1 - t0, 64);
+    const int nblk = div_up(nw, 4);
+    const int nblk_pad = div_up(nblk, 64) * 64;
+    k_gwalk<R, ORDER2, PHI, CNT, SORTED, BUDGET><<<nblk_pad, 256, 0, t->ctx->stream>>>(
+        (const typename NodeRecT<R>::type *)t->recs.p, (int)t->m,
+        (const BodyRec<R> *)t->bodies.p, (const Anchor<R> *)t->anchors.p,
+        (const int4 *)t->kids.p, t->perm, (int)t->n, t0, t1, nblk_pad * 4,
+        (R)(theta * theta), (R)(eps * eps), (R *)acc, (R *)phi, npp, npc, gm);
+}
+
+template <typename R, bool ORDER2, bool BUDGET>
+void gdispatch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
+               uint32_t *npp, uint32_t *npc, bool sorted, const GroupMac &gm) {
+    const bool P = phi != nullptr, C = npp != nullptr;
+#define BH_G(p, c, s) glaunch<R, ORDER2, p, c, s, BUDGET>(t, t0, t1, theta, eps, acc, phi, npp, npc, gm)
+    if (sorted) {
+        if (P) BH_G(true, false, true);
+        else BH_G(false, false, true);
+    } else if (P && C) BH_G(true, true, false);
+    else if (P) BH_G(true, false, false);
+    else if (C) BH_G(false, true, false);
+    else BH_G(false, false, false);
+#undef BH_G
+}
+
+// child table of the tree, built once per tree build
+int ensure_kids(bh_tree *t) {
+    if (t->kids_tree_id == t->build_id) return BH_OK;
+    int rc = grow(t->kids, 32ull * t->m);
+    if (rc) return rc;
+    k_kids<<<div_up((int)t->m, 256), 256, 0, t->ctx->stream>>>(
+        (int)t->m, (const int32_t *)t->next.p, (int32_t *)t->kids.p);
+    if ((rc = check_launch("child table"))) return rc;
+    t->kids_tree_id = t->build_id;
+    return BH_OK;
+}
+
 }  // namespace
 
 int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_t *npp,
@@ -256,6 +624,13 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
         else npc = (uint32_t *)t->cnt_scratch.p;
     }
     MlpMac mac{nullptr, nullptr, 0.f, 0.f};
+    const bool group = o.walk == BH_WALK_GROUP;
+    if (group) {
+        int rc = ensure_kids(t);
+        if (rc) return rc;
+    }
+    GroupMac gm{nullptr, nullptr, 0.f, o.walk_stack > 0 ? o.walk_stack : kGroupStack,
+                o.walk_cap > 0 ? o.walk_cap : kGroupWorkCap};
     if (o.mac == BH_MAC_MLP || o.mac == BH_MAC_BUDGET) {
         if (t->dtype != BH_F32 || o.order != 2)
             return set_error(BH_E_INVALID, "the learned criterion runs in the FP32 quadrupole walk");
@@ -271,6 +646,9 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
             bh_force_opts eo;
             bh_force_opts_default(&eo);
             eo.order = 0;
+            eo.walk = o.walk;
+            eo.walk_stack = o.walk_stack;
+            eo.walk_cap = o.walk_cap;
             eo.target_begin = t0;
             eo.target_end = t1;
             if ((rc = run_walk(t, o.mlp_theta_est, eps, t->est_acc.p, nullptr, nullptr, nullptr, eo,
@@ -283,7 +661,24 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
         mac.anorm = (const float *)t->anorm.p;
         mac.tmax2 = (float)(o.mlp_theta_max * o.mlp_theta_max);
         mac.tau = (float)pow(10.0, o.mlp_log10_tau);
-        dispatch2<float, true, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+        if (group) {
+            gm.kc = mac.kc;
+            gm.anorm = mac.anorm;
+            gm.tau = mac.tau;
+            gdispatch<float, true, true>(t, t0, t1, o.mlp_theta_max, eps, acc, phi, npp, npc,
+                                         sorted_out, gm);
+        } else {
+            dispatch2<float, true, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out,
+                                         mac);
+        }
+    } else if (group) {
+        if (t->dtype == BH_F32) {
+            if (o.order == 0) gdispatch<float, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm);
+            else gdispatch<float, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm);
+        } else {
+            if (o.order == 0) gdispatch<double, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm);
+            else gdispatch<double, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm);
+        }
     } else if (t->dtype == BH_F32) {
         if (o.order == 0) dispatch2<float, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
         else dispatch2<float, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);

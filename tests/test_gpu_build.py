@@ -116,3 +116,20 @@ def test_nonfinite_position_rejected(ctx):
     with pytest.raises(B.BHError) as e:
         B.bh_build(ctx, torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda(), 8)
     assert e.value.code == B.BH_E_NONFINITE
+
+
+def test_fresh_trees_sort_correctly(ctx):
+    """Trees created and freed in turn get device memory that earlier trees
+    used for node arrays; the radix sort's look-back status must not read
+    those leftovers as its own.  Every tree's keys are sorted and its
+    permutation is a permutation."""
+    say("40 trees of changing sizes built and freed in turn")
+    rng = np.random.default_rng(17)
+    for k in range(40):
+        n = int(rng.integers(3000, 70000))
+        pos, _, mass = case_bodies("plummer" if k % 2 else "clumpy", n, 100 + k, np.float32)
+        t, ex = gpu_tree(ctx, pos, mass, 8 + (k % 3) * 4)
+        B.bh_tree_free(t)
+        keys = ex["keys"]
+        assert np.all(keys[1:] >= keys[:-1])
+        assert np.array_equal(np.sort(ex["perm"].astype(np.int64)), np.arange(n))

@@ -1,0 +1,190 @@
+"""GPU group walk (one decision per wavefront of 64 bodies) against the
+oracle's group walk."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2203_08966_amd import binding as B
+from paper_2203_08966_amd import workloads as W
+from tests.conftest import case_bodies, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(ctx, pos, mass, leaf, theta, eps, **kw):
+    P, M = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
+    t = B.bh_build(ctx, P, M, leaf)
+    n = len(mass)
+    acc = torch.empty_like(P)
+    phi = torch.empty_like(M)
+    npp = torch.zeros(n, dtype=torch.int32, device="cuda")
+    npc = torch.zeros(n, dtype=torch.int32, device="cuda")
+    an = kw.pop("acc_norm", None)
+    an_t = None if an is None else torch.from_numpy(an).cuda()
+    o = B.force_opts(walk=B.BH_WALK_GROUP, phi=phi, n_pp=npp, n_pc=npc, mlp_acc_norm=an_t, **kw)
+    B.bh_forces(t, theta, eps, acc, o)
+    torch.cuda.synchronize()
+    B.bh_tree_free(t)
+    return (acc.cpu().numpy().astype(np.float64), phi.cpu().numpy().astype(np.float64),
+            npp.cpu().numpy(), npc.cpu().numpy())
+
+
+# per-body relative error against the FP64 oracle: rms and max bounds of
+# the FP32 and FP64 walks (as for the per-body walk)
+TOL = {np.float32: (1e-5, 1e-4), np.float64: (1e-12, 1e-10)}
+# relative margin around a decision threshold inside which the walk's
+# arithmetic may decide either way
+FLAG_TOL = {np.float32: 1e-5, np.float64: 1e-9}
+
+
+def _check(ref, r, out, dtype, min_unflagged=0.7):
+    """Counts identical for every body of an unflagged group, forces within
+    the walk's precision there; a flagged group may take a decision the other
+    way, which swaps one approximation for another."""
+    rms_tol, max_tol = TOL[dtype]
+    a, phi, cp, cc = (x[ref["perm"]] for x in out)
+    ok = r.flag == 0
+    same = (cp == r.npp) & (cc == r.npc)
+    say(f"  unflagged {ok.mean():.3f}, identical counts there {same[ok].mean():.4f}")
+    say(f"  flagged groups with other counts {(~same[~ok]).mean() if (~ok).any() else 0:.3f}")
+    assert ok.mean() >= min_unflagged
+    assert np.all(same[ok])
+    e = np.linalg.norm(a - r.acc, axis=1) / np.linalg.norm(r.acc, axis=1)
+    ep = np.abs(phi - r.phi) / np.abs(r.phi)
+    say(f"  rel err (unflagged): rms {np.sqrt(np.mean(e[ok] ** 2)):.3e} max {e[ok].max():.3e}")
+    assert np.sqrt(np.mean(e[ok] ** 2)) <= rms_tol and e[ok].max() <= max_tol
+    assert np.sqrt(np.mean(ep[ok] ** 2)) <= rms_tol
+    if (~ok).any():
+        assert e[~ok].max() <= 1e-2
+
+
+@pytest.mark.parametrize("kind,n,dtype,theta", [
+    ("plummer", 20000, np.float32, 0.75),
+    ("clumpy", 15000, np.float32, 0.6),
+    ("plummer", 6000, np.float64, 0.8),
+    ("two_spheres", 9000, np.float32, 1.0),
+])
+def test_group_walk_matches_oracle(ctx, kind, n, dtype, theta):
+    pos, _, mass = case_bodies(kind, n, 11, dtype)
+    eps, leaf = 0.005, 16
+    say(f"group walk {kind} n={n} {np.dtype(dtype).name} theta {theta}")
+    out = _run(ctx, pos, mass, leaf, theta, eps)
+    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), leaf)
+    r = oracle.walk_group(ref, eps, group=64, theta=theta, tol=FLAG_TOL[dtype])
+    _check(ref, r, out, dtype)
+
+
+def test_group_walk_small_stack_same_result(ctx):
+    """With a tiny LDS stack the opened subtrees take the stackless sweep:
+    the same interactions (only their order differs)."""
+    pos, _, mass = case_bodies("plummer", 12000, 12, np.float64)
+    say("group walk: stack 1024 vs 8 vs 1 (FP64)")
+    a0 = _run(ctx, pos, mass, 8, 0.7, 0.01)
+    for cap in (8, 1):
+        a1 = _run(ctx, pos, mass, 8, 0.7, 0.01, walk_stack=cap)
+        np.testing.assert_array_equal(a0[2], a1[2])
+        np.testing.assert_array_equal(a0[3], a1[3])
+        e = np.linalg.norm(a0[0] - a1[0], axis=1) / np.linalg.norm(a0[0], axis=1)
+        assert e.max() <= TOL[np.float64][1]
+
+
+def test_group_walk_target_range_and_tiny_trees(ctx):
+    pos, _, mass = case_bodies("plummer", 5000, 13, np.float64)
+    P, M = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
+    t = B.bh_build(ctx, P, M, 8)
+    acc = torch.full_like(P, 5.0)
+    B.bh_forces(t, 0.7, 0.01, acc, B.force_opts(walk=B.BH_WALK_GROUP, target_range=(100, 1337)))
+    torch.cuda.synchronize()
+    perm = B.bh_tree_export(t)["perm"].astype(np.int64)
+    B.bh_tree_free(t)
+    ref = oracle.build_all(pos, mass, 8)
+    r = oracle.walk_group(ref, 0.01, group=64, theta=0.7, target_range=(100, 1337), tol=1e-9)
+    a = acc.cpu().numpy()
+    ok = r.flag == 0
+    e = np.linalg.norm(a[perm[100:1337]] - r.acc, axis=1) / np.linalg.norm(r.acc, axis=1)
+    assert ok.mean() > 0.9 and e[ok].max() <= TOL[np.float64][1]
+    rest = np.setdiff1d(np.arange(5000), perm[100:1337])
+    assert np.all(a[rest] == 5.0)
+    # a root that is a leaf, and a single body
+    for n in (10, 1):
+        p, _, m = case_bodies("plummer", max(n, 2), 14, np.float64)
+        p, m = p[:n].copy(), m[:n].copy()
+        out = _run(ctx, p, m, 16, 0.7, 0.01)
+        d, _ = oracle.direct(p, m, 0.01)
+        np.testing.assert_allclose(out[0], d, rtol=1e-12, atol=1e-300)
+        assert np.all(out[2] == n - 1) and np.all(out[3] == 0)
+
+
+def test_group_budget_matches_oracle(ctx):
+    pos, _, mass = case_bodies("plummer", 20000, 15, np.float32)
+    eps, tau, tmax = 0.005, 10 ** -1.5, 1.2
+    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), 16)
+    w = oracle.walk(ref["tree"], ref["mom"], ref["spos"], ref["smass"], ref["L"], 0.4, eps)
+    an = np.empty(20000)
+    an[ref["perm"]] = np.linalg.norm(w.acc, axis=1)
+    an = an.astype(np.float32)
+    say(f"group budget walk: 20000 bodies, tau {tau:.3g}, theta_max {tmax}")
+    out = _run(ctx, pos, mass, 16, 0.5, eps, mac=B.BH_MAC_BUDGET, mlp_theta_max=tmax,
+               mlp_log10_tau=np.log10(tau), acc_norm=an)
+    r = oracle.walk_group(ref, eps, group=64, mode=1, theta_max=tmax, tau=tau,
+                          kc=oracle.cell_kc(ref, eps), anorm=an.astype(np.float64)[ref["perm"]],
+                          tol=FLAG_TOL[np.float32])
+    _check(ref, r, out, np.float32)
+
+
+def test_group_walk_full_size_sampled(ctx):
+    """The Plummer sphere of 2^20 bodies in the launch the benchmark times
+    (FP32, quadrupole, leaf 16, eps 0.005): sampled groups against the
+    oracle's group walk on the same groups."""
+    b, cfg = W.config("c2")
+    n = b.n
+    theta = 0.75
+    say(f"group walk full size: n={n}, theta {theta}, 24 sampled groups")
+    out = _run(ctx, b.pos, b.mass, cfg["leaf"], theta, cfg["eps"])
+    ref = oracle.build_all(b.pos.astype(np.float64), b.mass.astype(np.float64), cfg["leaf"])
+    rng = np.random.default_rng(4)
+    groups = rng.choice(n // 64, 24, replace=False)
+    a, phi, cp, cc = (x[ref["perm"]] for x in out)
+    checked = 0
+    for g in groups:
+        r = oracle.walk_group(ref, cfg["eps"], group=64, theta=theta,
+                              target_range=(64 * g, 64 * g + 64), tol=FLAG_TOL[np.float32])
+        sl = slice(64 * g, 64 * g + 64)
+        if r.flag[0]:
+            continue
+        checked += 1
+        assert np.array_equal(cp[sl], r.npp) and np.array_equal(cc[sl], r.npc)
+        e = np.linalg.norm(a[sl] - r.acc, axis=1) / np.linalg.norm(r.acc, axis=1)
+        assert e.max() <= TOL[np.float32][1]
+    say(f"  unflagged groups checked: {checked}")
+    assert checked >= 12
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_group_walk_work_cap(ctx, mode):
+    """With a low work cap part of the groups fall back to per-body
+    decisions, exactly where the oracle's groups do."""
+    pos, _, mass = case_bodies("clumpy", 20000, 16, np.float32)
+    eps, cap = 0.005, 2500
+    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), 16)
+    say(f"group walk work cap {cap}, mode {mode}")
+    if mode == 0:
+        out = _run(ctx, pos, mass, 16, 0.7, eps, walk_cap=cap)
+        r = oracle.walk_group(ref, eps, group=64, theta=0.7, tol=FLAG_TOL[np.float32], cap=cap)
+        full = oracle.walk_group(ref, eps, group=64, theta=0.7, tol=FLAG_TOL[np.float32])
+    else:
+        w = oracle.walk(ref["tree"], ref["mom"], ref["spos"], ref["smass"], ref["L"], 0.4, eps)
+        an = np.empty(20000)
+        an[ref["perm"]] = np.linalg.norm(w.acc, axis=1)
+        an = an.astype(np.float32)
+        kw = dict(mac=B.BH_MAC_BUDGET, mlp_theta_max=1.0, mlp_log10_tau=-2.0, acc_norm=an)
+        out = _run(ctx, pos, mass, 16, 0.5, eps, walk_cap=cap, **kw)
+        args = dict(group=64, mode=1, theta_max=1.0, tau=1e-2, kc=oracle.cell_kc(ref, eps),
+                    anorm=an.astype(np.float64)[ref["perm"]], tol=FLAG_TOL[np.float32])
+        r = oracle.walk_group(ref, eps, cap=cap, **args)
+        full = oracle.walk_group(ref, eps, **args)
+    fell = np.mean(full.npp + full.npc + 1 > cap)
+    say(f"  fraction of bodies in groups over the cap: {fell:.3f}")
+    assert 0.05 < fell < 0.95
+    _check(ref, r, out, np.float32)

@@ -107,3 +107,38 @@ def test_ragged_target_range_and_box_geometry():
         # the box lies on the plane y = 0.5, a face of cubes it is tested
         # against: flagged as a decision reduced precision may take otherwise
         assert np.all(r.flag == 1)
+
+
+def test_work_cap_falls_back_to_the_per_body_walk():
+    """A cap below every group's work turns the group walk into the per-body
+    walk (both modes); an unreachable cap changes nothing."""
+    b, bb = _tree(5000, 8, 8, "clumpy")
+    theta = 0.5
+    w = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], theta, 0.01)
+    g = oracle.walk_group(bb, 0.01, group=64, theta=theta, cap=1)
+    np.testing.assert_array_equal(g.npc, w.npc)
+    np.testing.assert_allclose(g.acc, w.acc, rtol=1e-13, atol=0)
+    kc = oracle.cell_kc(bb, 0.01)
+    an = np.linalg.norm(w.acc, axis=1)
+    gb = oracle.walk_group(bb, 0.01, group=64, mode=1, theta_max=0.9, tau=1e-2, kc=kc,
+                           anorm=an, cap=1)
+    wb = oracle.walk_kc(bb, 0.01, 0.9, 1e-2, kc, an)
+    np.testing.assert_array_equal(gb.npp, wb.npp)
+    np.testing.assert_allclose(gb.acc, wb.acc, rtol=1e-13, atol=0)
+    big = oracle.walk_group(bb, 0.01, group=64, theta=theta, cap=1 << 62)
+    dflt = oracle.walk_group(bb, 0.01, group=64, theta=theta)
+    np.testing.assert_array_equal(big.npc, dflt.npc)
+    # the cap splits groups by their work: each group either keeps the group
+    # walk or takes the per-body counts
+    mid = oracle.walk_group(bb, 0.01, group=64, theta=theta, cap=3000)
+    # (a group's work is npp + npc + 1 for each of its bodies: the body's
+    # own particle-particle cell counts it too)
+    work = big.npp + big.npc + 1
+    fell = 0
+    for k0 in range(0, 5000, 64):
+        sl = slice(k0, min(k0 + 64, 5000))
+        assert np.all(work[sl] == work[k0])
+        src = w if work[k0] > 3000 else big
+        fell += work[k0] > 3000
+        np.testing.assert_array_equal(mid.npc[sl], src.npc[sl])
+    assert 0 < fell < 5000 // 64

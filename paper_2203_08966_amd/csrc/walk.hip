@@ -23,6 +23,8 @@
 // its leaf plus a small offset.  Centres are integers (units h = L 2^-22,
 // below 2^23) times h, so the difference of the body's leaf centre and any
 // cell centre is exact in FP32; adding the offset is the only rounding.
+#include <algorithm>
+
 #include "bh_internal.h"
 #include "mlp.h"
 
@@ -328,24 +330,16 @@ __device__ __forceinline__ R wave_max(R v) {
 
 enum : int { kGNone = 0, kGPC = 1, kGPP = 2, kGOpen = 3 };
 
+// One group: the 64 bodies of sorted rank [base, min(base + 64, t1)).
 template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool BUDGET>
-__global__ __launch_bounds__(256) void k_gwalk(
+__device__ __forceinline__ void group_walk(
     const typename NodeRecT<R>::type *__restrict__ nodes, int m,
     const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
-    const int4 *__restrict__ kids, const uint32_t *__restrict__ perm, int nbodies, int t0,
-    int t1, int nwaves_padded, R theta2, R eps2, R *__restrict__ acc, R *__restrict__ phi_out,
-    uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out, GroupMac gm) {
+    const int4 *__restrict__ kids, const uint32_t *__restrict__ perm, int nbodies, int base,
+    int t1, R theta2, R eps2, R *__restrict__ acc, R *__restrict__ phi_out,
+    uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out, const GroupMac &gm,
+    int *__restrict__ stk) {
     using Rec = typename NodeRecT<R>::type;
-    __shared__ int stack_all[4][kGroupStack];
-    const int nblk = nwaves_padded / 4;
-    const int b = blockIdx.x;
-    const int xcd = b & 7, r = b >> 3;
-    const int lb = (r >> 3) * 64 + xcd * 8 + (r & 7);
-    if (lb >= nblk) return;
-    const int wave = lb * 4 + (int)(threadIdx.x >> 6);
-    const int base = t0 + wave * 64;
-    if (base >= t1) return;
-    int *stk = stack_all[threadIdx.x >> 6];
     const int lane = (int)lane_id();
     const int i = base + lane;
     const bool live = i < t1;
@@ -567,17 +561,54 @@ __global__ __launch_bounds__(256) void k_gwalk(
     }
 }
 
+// Groups are handed out dynamically: the groups are split into 8
+// contiguous chunks, one per XCD (workgroups are dispatched to the XCDs in
+// turn, so blockIdx % 8 names the XCD and a chunk's nodes stay in one L2),
+// and every resident wavefront takes the next group of its chunk from an
+// atomic counter until the chunk is done.  A heavy group then delays only
+// the wavefront that drew it.
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool BUDGET>
+__global__ __launch_bounds__(256) void k_gwalk(
+    const typename NodeRecT<R>::type *__restrict__ nodes, int m,
+    const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
+    const int4 *__restrict__ kids, const uint32_t *__restrict__ perm, int nbodies, int t0,
+    int t1, uint32_t *__restrict__ queue, R theta2, R eps2, R *__restrict__ acc,
+    R *__restrict__ phi_out, uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out,
+    GroupMac gm) {
+    __shared__ int stack_all[4][kGroupStack];
+    int *stk = stack_all[threadIdx.x >> 6];
+    const int ng = (t1 - t0 + 63) / 64;
+    const int xcd = (int)(blockIdx.x & 7);
+    const int chunk = (ng + 7) / 8;
+    const int g_lo = xcd * chunk, g_hi = min(ng, g_lo + chunk);
+    uint32_t *ctr = queue + 64 * xcd;  // one counter per 256 bytes
+    for (;;) {
+        uint32_t g = 0;
+        if (lane_id() == 0) g = atomicAdd(ctr, 1u);
+        const int gi = g_lo + (int)__builtin_amdgcn_readfirstlane(g);
+        if (gi >= g_hi) break;
+        group_walk<R, ORDER2, PHI, CNT, SORTED_OUT, BUDGET>(
+            nodes, m, bodies, anchors, kids, perm, nbodies, t0 + 64 * gi, t1, theta2, eps2, acc,
+            phi_out, npp_out, npc_out, gm, stk);
+    }
+}
+
+__global__ void k_zero_queue(uint32_t *q) { q[threadIdx.x * 64] = 0u; }
+
 template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED, bool BUDGET>
 void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
              uint32_t *npp, uint32_t *npc, const GroupMac &gm) {
-    const int nw = div_up(t1 - t0, 64);
-    const int nblk = div_up(nw, 4);
-    const int nblk_pad = div_up(nblk, 64) * 64;
-    k_gwalk<R, ORDER2, PHI, CNT, SORTED, BUDGET><<<nblk_pad, 256, 0, t->ctx->stream>>>(
+    // enough workgroups to fill every CU (8 per CU at this kernel's
+    // register and LDS use), or fewer for small target ranges
+    const int ng = div_up(t1 - t0, 64);
+    const int per_xcd = std::min(div_up(div_up(ng, 8), 4), 256);
+    uint32_t *queue = (uint32_t *)t->wq.p;
+    k_zero_queue<<<1, 8, 0, t->ctx->stream>>>(queue);
+    k_gwalk<R, ORDER2, PHI, CNT, SORTED, BUDGET><<<8 * per_xcd, 256, 0, t->ctx->stream>>>(
         (const typename NodeRecT<R>::type *)t->recs.p, (int)t->m,
         (const BodyRec<R> *)t->bodies.p, (const Anchor<R> *)t->anchors.p,
-        (const int4 *)t->kids.p, t->perm, (int)t->n, t0, t1, nblk_pad * 4,
-        (R)(theta * theta), (R)(eps * eps), (R *)acc, (R *)phi, npp, npc, gm);
+        (const int4 *)t->kids.p, t->perm, (int)t->n, t0, t1, queue, (R)(theta * theta),
+        (R)(eps * eps), (R *)acc, (R *)phi, npp, npc, gm);
 }
 
 template <typename R, bool ORDER2, bool BUDGET>
@@ -597,9 +628,10 @@ void gdispatch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, 
 
 // child table of the tree, built once per tree build
 int ensure_kids(bh_tree *t) {
-    if (t->kids_tree_id == t->build_id) return BH_OK;
-    int rc = grow(t->kids, 32ull * t->m);
+    int rc = grow(t->wq, 8 * 256);  // group queue counters
     if (rc) return rc;
+    if (t->kids_tree_id == t->build_id) return BH_OK;
+    if ((rc = grow(t->kids, 32ull * t->m))) return rc;
     k_kids<<<div_up((int)t->m, 256), 256, 0, t->ctx->stream>>>(
         (int)t->m, (const int32_t *)t->next.p, (int32_t *)t->kids.p);
     if ((rc = check_launch("child table"))) return rc;

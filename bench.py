@@ -6,9 +6,17 @@ rms relative force error of 1e-3 against FP64 direct summation.
 
 Workload (default): Plummer sphere, N = 2^20 equal masses (G = M = a = 1),
 eps 0.005, leaf 16, FP32 walk with FP64 cell moments, quadrupole order, KDK
-leapfrog dt 5e-4.  Before timing, theta is swept on the initial state and the
-theta at which the rms error over a seeded 4096-body subsample equals 1e-3
-is interpolated (log-log); the timed steps run at that theta.
+leapfrog dt 5e-4.  Before timing, three force-evaluation methods are
+calibrated on the initial state against the FP64 direct sum over a seeded
+4096-body subsample:
+  body-theta    the per-body walk of Sec. 3 (opening angle theta);
+  group-theta   one opening-angle decision per wavefront of 64 bodies;
+  group-budget  one error-budget decision per wavefront (k_C = 1 error
+                model, tau times the group's smallest |a|).
+Each is swept over its parameter grid from accurate to cheap; the cheapest
+grid value with rms <= 1e-3 is kept, and the method with the fastest walk
+at that value is the one timed.  After the timed steps the rms error is
+measured again at the final state.
 
 A timed step is one kick-drift-kick leapfrog step: kick + drift, tree
 rebuild (bbox, keys, radix sort, topology, FP64 upward pass, pack), the
@@ -35,10 +43,20 @@ sys.path.insert(0, ROOT)
 METRIC = "body-cell interactions/s and bodies/s force eval at rms rel force err 1e-3"
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-# algorithmic FLOPs per interaction: particle-particle 20;
-# particle-cell 20 (monopole) or 60 (monopole + quadrupole)
+# algorithmic FLOPs per interaction: particle-particle 20; particle-cell 20
+# (monopole) or 60 (monopole + quadrupole)
 FLOP_PP = 20
 FLOP_PC = {0: 20, 2: 60}
+
+# force-evaluation methods compared at the target error, with the parameter
+# grid each is swept over (from accurate to cheap)
+METHODS = {
+    "body-theta": [round(0.5 + 0.02 * k, 2) for k in range(16)],      # Sec. 3 walk
+    "group-theta": [round(0.6 + 0.025 * k, 3) for k in range(14)],    # one decision per wave
+    "group-budget": [round(-2.5 + 0.125 * k, 3) for k in range(13)],  # log10 tau
+}
+PARAM_NAME = {"body-theta": "theta", "group-theta": "theta", "group-budget": "log10_tau"}
+BUDGET_THETA_MAX = 1.5
 
 
 def log(*a):
@@ -52,7 +70,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--n", type=int, default=None, help="override N")
-    ap.add_argument("--theta", type=float, default=None, help="skip the sweep; use this theta")
+    ap.add_argument("--theta", type=float, default=None,
+                    help="per-body walk: skip the sweep and use this theta")
+    ap.add_argument("--method", choices=["body-theta", "group-theta", "group-budget"],
+                    default=None, help="time only this method (default: the fastest at the "
+                    "target error)")
     ap.add_argument("--target-err", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
@@ -108,6 +130,7 @@ def main():
     # ---- error reference: FP64 direct sum on a seeded subsample (GPU)
     sample = W.subsample(n, 4096, cfg.get("sub_seed", 100))
     tg = torch.from_numpy(sample).to(dev)
+    tg_long = tg.to(torch.int64)
     acc_dir = torch.empty((len(sample), 3), dtype=torch.float64, device=dev)
     B.bh_direct(ctx, pos, mass, tg, eps, acc_dir)
     torch.cuda.synchronize()
@@ -117,58 +140,77 @@ def main():
     acc = torch.empty_like(pos)
     npp = torch.zeros(n, dtype=torch.int32, device=dev)
     npc = torch.zeros(n, dtype=torch.int32, device=dev)
+    # |a_i| for the error-budget criterion while calibrating (in the timed
+    # steps each step uses the previous step's accelerations)
+    B.bh_forces(tree, 0.5, eps, acc, B.force_opts(order=order))
+    anorm = acc.norm(dim=1).contiguous()
 
-    def walk(theta, counters=False):
-        o = B.force_opts(order=order, n_pp=npp if counters else None,
-                         n_pc=npc if counters else None)
-        B.bh_forces(tree, theta, eps, acc, o)
+    def opts_of(method, p, counters=False, for_sim=False):
+        kw = dict(order=order, n_pp=npp if counters else None, n_pc=npc if counters else None)
+        if method == "group-theta":
+            kw.update(walk=B.BH_WALK_GROUP)
+        elif method == "group-budget":
+            kw.update(walk=B.BH_WALK_GROUP, mac=B.BH_MAC_BUDGET, mlp_log10_tau=p,
+                      mlp_theta_max=BUDGET_THETA_MAX, mlp_acc_norm=None if for_sim else anorm)
+        return B.force_opts(**kw)
 
-    def rms_at(theta):
-        walk(theta)
-        torch.cuda.synchronize()
-        a = acc.cpu().numpy()[sample].astype(np.float64)
+    def walk(method, p, counters=False):
+        theta = p if method != "group-budget" else 0.5
+        B.bh_forces(tree, theta, eps, acc, opts_of(method, p, counters))
+
+    def rms_at(method, p):
+        walk(method, p)
+        a = acc.index_select(0, tg_long).cpu().numpy().astype(np.float64)
         e = np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)
         return float(np.sqrt(np.mean(e * e)))
 
-    # ---- theta at the target error
-    sweep = []
-    if args.theta is None:
-        for th in (0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0):
-            sweep.append((th, rms_at(th)))
-        log("theta sweep:", ", ".join(f"{t:.2f}:{e:.2e}" for t, e in sweep))
-        ths = np.array([s[0] for s in sweep])
-        es = np.array([s[1] for s in sweep])
-        lt, le = np.log(ths), np.log(es)
-        target = np.log(args.target_err)
-        k = int(np.searchsorted(le, target))
-        k = min(max(k, 1), len(ths) - 1)
-        w = (target - le[k - 1]) / (le[k] - le[k - 1])
-        theta = float(np.exp(lt[k - 1] + w * (lt[k] - lt[k - 1])))
-    else:
-        theta = args.theta
-    err_theta = rms_at(theta)
-    log(f"theta* = {theta:.4f}  rms rel err = {err_theta:.3e}")
+    def walk_ms(method, p, reps=10):
+        for _ in range(3):
+            walk(method, p)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            walk(method, p)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
 
-    # ---- interactions per force evaluation, walk-only time
-    walk(theta, counters=True)
-    torch.cuda.synchronize()
-    s_pp = int(npp.to(torch.int64).sum().item())
-    s_pc = int(npc.to(torch.int64).sum().item())
-    for _ in range(3):
-        walk(theta)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 10
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        walk(theta)
-    e1.record()
-    torch.cuda.synchronize()
-    walk_ms = e0.elapsed_time(e1) / reps
+    # ---- per method: the cheapest parameter on its grid with rms <= target
+    methods = {}
+    names = list(METHODS) if args.method is None else [args.method]
+    for name in names:
+        grid = METHODS[name]
+        if name == "body-theta" and args.theta is not None:
+            grid = [args.theta]
+        sweep, best = [], None
+        for p in grid:
+            r = rms_at(name, p)
+            sweep.append([p, r])
+            if r <= args.target_err:
+                best = p
+            elif r > 1.5 * args.target_err:
+                break
+        if best is None:
+            log(f"{name}: no grid value reaches rms {args.target_err}")
+            continue
+        walk(name, best, counters=True)
+        torch.cuda.synchronize()
+        s_pp = int(npp.to(torch.int64).sum().item())
+        s_pc = int(npc.to(torch.int64).sum().item())
+        methods[name] = {"param": best, "rms_rel_err": rms_at(name, best),
+                         "walk_ms": walk_ms(name, best),
+                         "interactions_per_eval": {"pp": s_pp, "pc": s_pc}, "sweep": sweep}
+        log(f"{name}: param {best} rms {methods[name]['rms_rel_err']:.3e} "
+            f"walk {methods[name]['walk_ms']:.3f} ms  pp/body {s_pp / n:.0f} pc/body {s_pc / n:.0f}")
     B.bh_tree_free(tree)
+    chosen = min(methods, key=lambda k: methods[k]["walk_ms"])
+    cp = methods[chosen]["param"]
+    log(f"timed method: {chosen} ({PARAM_NAME[chosen]} = {cp})")
 
     # ---- timed simulation steps
-    B.bh_sim_init(ctx, pos, vel, mass, leaf, theta, eps)
+    sim_theta = cp if chosen != "group-budget" else 0.5
+    B.bh_sim_init(ctx, pos, vel, mass, leaf, sim_theta, eps, opts_of(chosen, cp, for_sim=True))
     ek0, ep0 = B.bh_energy(ctx)
     for _ in range(args.warmup):
         B.bh_leapfrog_step(ctx, dt)
@@ -188,11 +230,23 @@ def main():
     phases = {k: v / max(nsteps, 1) for k, v in
               zip(["kick_drift", "build", "walk", "kick"], phase_ms)}
     walk_step_ms = phases["walk"]
+    # accuracy of the timed method at the final state of the run
+    xf, af = torch.empty_like(pos), torch.empty_like(pos)
+    B.bh_sim_get(ctx, xf, None, af)
+    ref_f = torch.empty((len(sample), 3), dtype=torch.float64, device=dev)
+    B.bh_direct(ctx, xf, mass, tg, eps, ref_f)
+    a_f = af.index_select(0, tg_long).cpu().numpy().astype(np.float64)
+    r_f = ref_f.cpu().numpy()
+    e_f = np.linalg.norm(a_f - r_f, axis=1) / np.linalg.norm(r_f, axis=1)
+    rms_final = float(np.sqrt(np.mean(e_f * e_f)))
+    s_pp = methods[chosen]["interactions_per_eval"]["pp"]
+    s_pc = methods[chosen]["interactions_per_eval"]["pc"]
     inter = s_pp + s_pc
     flops = FLOP_PP * s_pp + FLOP_PC[order] * s_pc
     achieved_tf = flops / (walk_step_ms * 1e-3) / 1e12
-    log(f"step {ms_step:.3f} ms  phases {phases}  walk(bh_forces) {walk_ms:.3f} ms")
+    log(f"step {ms_step:.3f} ms  phases {phases}  rms at the final state {rms_final:.3e}")
 
+    kernel = "k_walk" if chosen == "body-theta" else "k_gwalk"
     result = {
         "metric": METRIC,
         "value": value,
@@ -208,28 +262,49 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{cfg['workload']} N={n} (equal masses, G=M=a=1, seed {cfg['seed']})",
-            "n": n, "theta": round(theta, 4), "eps": eps, "leaf": leaf, "order": order,
-            "dt": dt, "step": "KDK leapfrog step: kick+drift, rebuild, walk, kick, energy",
+            "n": n, "eps": eps, "leaf": leaf, "order": order, "dt": dt,
+            "method": chosen, PARAM_NAME[chosen]: cp,
+            "step": "KDK leapfrog step: kick+drift, rebuild, walk, kick, energy",
         },
-        "rms_rel_err": err_theta,
+        "rms_rel_err": methods[chosen]["rms_rel_err"],
+        "rms_rel_err_final_state": rms_final,
         "interactions_per_s": inter / (walk_step_ms * 1e-3),
         "interactions_per_eval": {"pp": s_pp, "pc": s_pc},
         "walk_bodies_per_s": n / (walk_step_ms * 1e-3),
         "phases_ms": phases,
         "energy_rel_change": abs((ek + ep) - (ek0 + ep0)) / abs(ek0 + ep0),
-        "theta_sweep": [[t, e] for t, e in sweep],
+        "methods": methods,
         "roofline": {
-            "bound": "alu", "kernel": "k_walk (FP32, quadrupole)",
+            "bound": "alu", "kernel": f"{kernel} (FP32, quadrupole)",
             "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": None,
+            "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": traffic_for(kernel, cfg),
             "flop_per_launch": flops, "launch_ms": walk_step_ms,
         },
     }
 
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(bodies, cfg, theta, order, args.cpu_sample)
+        result["cpu_baseline"] = cpu_baseline(bodies, cfg, methods.get("body-theta", {}).get(
+            "param", 0.6), order, args.cpu_sample)
     B.bh_ctx_destroy(ctx)
     print(json.dumps(result), flush=True)
+
+
+def traffic_for(kernel, cfg):
+    """HBM bytes per launch of the timed walk kernel from the committed
+    rocprofv3 counter summary, if it was taken on this workload with the
+    current walk source; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "walk_traffic.json")
+    src = os.path.join(ROOT, "paper_2203_08966_amd", "csrc", "walk.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or rec.get("walk_hip_sha256") != sha or rec.get("workload") != cfg["workload"]:
+        return None
+    return k["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(bodies, cfg, theta, order, k):

@@ -95,7 +95,7 @@ typedef struct {
     int walk_cap;             /* group walk: a group whose work (particle-cell
                                  terms + particle-particle bodies, per body)
                                  would exceed this is walked per body with the
-                                 same criterion; 0 = 32768 */
+                                 same criterion; 0 = 4096 */
 } bh_force_opts;
 
 /* Library version string. */

@@ -368,7 +368,7 @@ def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None):
 
 
 # ------------------------------------------------------------------ group walk
-GROUP_WORK_CAP = 32768
+GROUP_WORK_CAP = 4096
 
 
 def walk_group(b, eps, group=64, mode=0, theta=0.5, theta_max=1.0, tau=1e-3, kc=None,

@@ -130,7 +130,8 @@ struct bh_tree {
     int64_t kids_tree_id = -1;
     int kc_version = -2;
     double kc_eps = -1.0;
-    int64_t build_id = 0, kc_tree_id = -1;
+    int64_t build_id = 0, kc_tree_id = -1, cf_tree_id = -1;
+    double cf_eps = -1.0;
     uint64_t *sorted_keys = nullptr;           // result buffers after the sort
     uint32_t *perm = nullptr;
 };

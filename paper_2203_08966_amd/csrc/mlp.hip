@@ -444,25 +444,39 @@ int mlp_infer(bh_ctx *c, const float *X, int64_t n, float *pred) {
     return check_launch("mlp infer");
 }
 
+// cell features of the tree (cached per build and eps)
+static int mlp_features(bh_tree *t, double eps) {
+    if (t->cf_tree_id == t->build_id && t->cf_eps == eps) return BH_OK;
+    const int m = (int)t->m;
+    int rc = grow(t->cellf, 40ull * m);
+    if (rc) return rc;
+    k_cell_features<<<div_up(m, 256), 256, 0, t->ctx->stream>>>(
+        m, (const Moments *)t->mom.p, (const int32_t *)t->level.p, (const int32_t *)t->count.p,
+        (const int32_t *)t->next.p, (const Cube *)t->cube.p, eps, (float *)t->cellf.p);
+    if ((rc = check_launch("cell features"))) return rc;
+    t->cf_tree_id = t->build_id;
+    t->cf_eps = eps;
+    return BH_OK;
+}
+
 int mlp_cells(bh_tree *t, double eps, bool learned) {
     bh_ctx *c = t->ctx;
     const int m = (int)t->m;
     const int version = learned ? c->mlp_version : -1;
     if (t->kc_version == version && t->kc_eps == eps && t->kc_tree_id == t->build_id) return BH_OK;
-    int rc;
-    if ((rc = grow(t->cellf, 40ull * m)) || (rc = grow(t->kc, 4ull * m))) return rc;
+    int rc = grow(t->kc, 4ull * m);
+    if (rc) return rc;
     const Moments *mom = (const Moments *)t->mom.p;
     const Cube *cube = (const Cube *)t->cube.p;
-    k_cell_features<<<div_up(m, 256), 256, 0, c->stream>>>(
-        m, mom, (const int32_t *)t->level.p, (const int32_t *)t->count.p,
-        (const int32_t *)t->next.p, cube, eps, (float *)t->cellf.p);
-    if (learned)
+    if (learned) {
+        if ((rc = mlp_features(t, eps))) return rc;
         k_cell_kc<<<div_up(div_up(m, 64), 4), 256, 0, c->stream>>>(
             (const MlpPacked *)c->mlp_w.p, m, (const float *)t->cellf.p, mom,
             (const int32_t *)t->level.p, cube, (float *)t->kc.p);
-    else
+    } else {  // k_C = 1 needs no features
         k_cell_kc_plain<<<div_up(m, 256), 256, 0, c->stream>>>(m, mom, (const int32_t *)t->level.p,
                                                                cube, (float *)t->kc.p);
+    }
     if ((rc = check_launch("mlp cells"))) return rc;
     t->kc_version = version;
     t->kc_eps = eps;
@@ -489,7 +503,7 @@ int mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_max, doubl
                 int32_t *body, int64_t *total) {
     bh_ctx *c = t->ctx;
     const int n = (int)t->n;
-    int rc = mlp_cells(t, eps, false);  // features only (k_C unused here)
+    int rc = mlp_features(t, eps);
     if (rc) return rc;
     if ((rc = grow(c->mlp_scratch, 4ull * n + 8ull * (n + 1) + 8))) return rc;
     int32_t *cnt = (int32_t *)c->mlp_scratch.p;

@@ -285,7 +285,7 @@ void dispatch2(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, 
 // that would exceed the cap drops its partial sums and is walked per body
 // with the same criterion instead.
 constexpr int kGroupStack = 1024;      // LDS stack entries per wavefront
-constexpr int kGroupWorkCap = 32768;   // default per-group work cap
+constexpr int kGroupWorkCap = 4096;    // default per-group work cap
 
 struct GroupMac {
     const float *kc;     // error budget: k_C M l^3 per node

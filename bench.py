@@ -12,7 +12,10 @@ calibrated on the initial state against the FP64 direct sum over a seeded
   body-theta    the per-body walk of Sec. 3 (opening angle theta);
   group-theta   one opening-angle decision per wavefront of 64 bodies;
   group-budget  one error-budget decision per wavefront (k_C = 1 error
-                model, tau times the group's smallest |a|).
+                model, tau times the group's smallest |a|);
+  group-learned the same with k_C per cell from the network, trained first
+                on the library's own FP64 simulations of small Plummer
+                spheres.
 Each is swept over its parameter grid from accurate to cheap; the cheapest
 grid value with rms <= 1e-3 is kept, and the method with the fastest walk
 at that value is the one timed.  After the timed steps the rms error is
@@ -54,8 +57,10 @@ METHODS = {
     "body-theta": [round(0.5 + 0.02 * k, 2) for k in range(16)],      # Sec. 3 walk
     "group-theta": [round(0.6 + 0.025 * k, 3) for k in range(14)],    # one decision per wave
     "group-budget": [round(-2.5 + 0.125 * k, 3) for k in range(13)],  # log10 tau
+    "group-learned": [round(-4.0 + 0.125 * k, 3) for k in range(21)],  # log10 tau
 }
-PARAM_NAME = {"body-theta": "theta", "group-theta": "theta", "group-budget": "log10_tau"}
+PARAM_NAME = {"body-theta": "theta", "group-theta": "theta", "group-budget": "log10_tau",
+              "group-learned": "log10_tau"}
 BUDGET_THETA_MAX = 1.5
 
 
@@ -72,7 +77,8 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="override N")
     ap.add_argument("--theta", type=float, default=None,
                     help="per-body walk: skip the sweep and use this theta")
-    ap.add_argument("--method", choices=["body-theta", "group-theta", "group-budget"],
+    ap.add_argument("--method", choices=["body-theta", "group-theta", "group-budget",
+                                         "group-learned"],
                     default=None, help="time only this method (default: the fastest at the "
                     "target error)")
     ap.add_argument("--target-err", type=float, default=1e-3)
@@ -149,13 +155,15 @@ def main():
         kw = dict(order=order, n_pp=npp if counters else None, n_pc=npc if counters else None)
         if method == "group-theta":
             kw.update(walk=B.BH_WALK_GROUP)
-        elif method == "group-budget":
-            kw.update(walk=B.BH_WALK_GROUP, mac=B.BH_MAC_BUDGET, mlp_log10_tau=p,
-                      mlp_theta_max=BUDGET_THETA_MAX, mlp_acc_norm=None if for_sim else anorm)
+        elif method in ("group-budget", "group-learned"):
+            kw.update(walk=B.BH_WALK_GROUP,
+                      mac=B.BH_MAC_BUDGET if method == "group-budget" else B.BH_MAC_MLP,
+                      mlp_log10_tau=p, mlp_theta_max=BUDGET_THETA_MAX,
+                      mlp_acc_norm=None if for_sim else anorm)
         return B.force_opts(**kw)
 
     def walk(method, p, counters=False):
-        theta = p if method != "group-budget" else 0.5
+        theta = p if PARAM_NAME[method] == "theta" else 0.5
         B.bh_forces(tree, theta, eps, acc, opts_of(method, p, counters))
 
     def rms_at(method, p):
@@ -176,9 +184,25 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    # ---- the learned criterion: train the network on the library's own FP64
+    # simulations of small Plummer spheres (bf16 MFMA inference afterwards)
+    names = list(METHODS) if args.method is None else [args.method]
+    learned_info = None
+    if "group-learned" in names:
+        from paper_2203_08966_amd import learned as LM
+        t0 = time.perf_counter()
+        feat, label = LM.training_set(ctx)
+        loss = LM.train(ctx, feat, label)
+        torch.cuda.synchronize()
+        learned_info = {"pairs": int(feat.shape[0]), "epochs": len(loss),
+                        "loss_first_last": [float(loss[0]), float(loss[-1])],
+                        "label_var": float(label.double().var().item()),
+                        "seconds": time.perf_counter() - t0}
+        del feat, label
+        log(f"learned criterion: {learned_info}")
+
     # ---- per method: the cheapest parameter on its grid with rms <= target
     methods = {}
-    names = list(METHODS) if args.method is None else [args.method]
     for name in names:
         grid = METHODS[name]
         if name == "body-theta" and args.theta is not None:
@@ -209,7 +233,7 @@ def main():
     log(f"timed method: {chosen} ({PARAM_NAME[chosen]} = {cp})")
 
     # ---- timed simulation steps
-    sim_theta = cp if chosen != "group-budget" else 0.5
+    sim_theta = cp if PARAM_NAME[chosen] == "theta" else 0.5
     B.bh_sim_init(ctx, pos, vel, mass, leaf, sim_theta, eps, opts_of(chosen, cp, for_sim=True))
     ek0, ep0 = B.bh_energy(ctx)
     for _ in range(args.warmup):
@@ -274,6 +298,7 @@ def main():
         "phases_ms": phases,
         "energy_rel_change": abs((ek + ep) - (ek0 + ep0)) / abs(ek0 + ep0),
         "methods": methods,
+        "learned_training": learned_info,
         "roofline": {
             "bound": "alu", "kernel": f"{kernel} (FP32, quadrupole)",
             "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

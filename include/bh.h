@@ -260,18 +260,22 @@ typedef struct {
     int batch;         /* minibatch size (>= 1) */
     double lr, beta1, beta2, eps;  /* Adam */
     uint64_t seed;     /* per-epoch order: sample (a j + c) mod n, a coprime to n */
+    double quantile;   /* 0: mean-squared error; q in (0, 1): pinball loss
+                          mean(max(q r, (q - 1) r)), r = label - prediction,
+                          whose minimiser is the label's q-quantile */
 } bh_mlp_train_cfg;
 
 /* Trains the loaded parameters on n pairs (device feat f32 n x 10, label
- * f32 n) with mean-squared error and Adam, then packs them for inference.
- * loss (host, optional): mean squared error of each epoch.  Synchronous. */
+ * f32 n) with the configured loss and Adam, then packs them for inference.
+ * loss (host, optional): mean loss of each epoch.  Synchronous. */
 int bh_mlp_train(bh_ctx *ctx, const float *feat, const float *label, int64_t n,
                  const bh_mlp_train_cfg *cfg, double *loss);
 
-/* Gradient (device f32 BH_MLP_PARAMS) and mean-squared error (host) of the
- * loaded parameters over n pairs as one batch; parameters unchanged. */
-int bh_mlp_grad(bh_ctx *ctx, const float *feat, const float *label, int64_t n, float *grad,
-                double *loss);
+/* Gradient (device f32 BH_MLP_PARAMS) and mean loss (host) of the loaded
+ * parameters over n pairs as one batch (quantile as in bh_mlp_train_cfg);
+ * parameters unchanged. */
+int bh_mlp_grad(bh_ctx *ctx, const float *feat, const float *label, int64_t n, double quantile,
+                float *grad, double *loss);
 
 /* bf16 MFMA inference: pred (device f32 n) for feat (device f32 n x 10). */
 int bh_mlp_infer(bh_ctx *ctx, const float *feat, int64_t n, float *pred);

@@ -2,8 +2,10 @@
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
-Network: 10 features -> 32 (ReLU) -> 32 (ReLU) -> 1, mean-squared error on
-the log10 relative particle-cell error, trained with Adam.  Parameters are a
+Network: 10 features -> 32 (ReLU) -> 32 (ReLU) -> 1, trained with Adam on
+either the mean-squared error or, for a quantile q in (0, 1), the pinball
+loss mean(max(q r, (q - 1) r)) with r = label - prediction, whose minimiser
+is the q-quantile of the label (Koenker and Bassett, 1978).  Parameters are a
 flat vector in the order W1 (32x10, row-major), b1 (32), W2 (32x32), b2 (32),
 w3 (32), b3 (1): 1441 values.
 
@@ -59,17 +61,26 @@ def forward(theta, X):
     return out, (z1, h1, z2, h2)
 
 
-def loss(theta, X, y) -> float:
+def loss(theta, X, y, q=None) -> float:
+    """Mean-squared error, or the pinball loss of quantile q."""
     out, _ = forward(theta, X)
-    return float(np.mean((out - y) ** 2))
+    if q is None:
+        return float(np.mean((out - y) ** 2))
+    r = y - out
+    return float(np.mean(np.maximum(q * r, (q - 1.0) * r)))
 
 
-def grad(theta, X, y):
-    """Analytic gradient of the mean-squared error (backpropagation)."""
+def grad(theta, X, y, q=None):
+    """Analytic gradient of the loss (backpropagation); for the pinball loss
+    the derivative in the prediction is 1 - q where it exceeds the label,
+    else -q."""
     p = unpack(theta)
     out, (z1, h1, z2, h2) = forward(theta, X)
     n = X.shape[0]
-    d_out = 2.0 * (out - y) / n                 # (n,)
+    if q is None:
+        d_out = 2.0 * (out - y) / n             # (n,)
+    else:
+        d_out = np.where(out > y, 1.0 - q, -q) / n
     g = {"w3": h2.T @ d_out, "b3": np.array([d_out.sum()])}
     d_h2 = np.outer(d_out, p["w3"]) * (z2 > 0)   # (n, 32)
     g["W2"] = d_h2.T @ h1

@@ -56,7 +56,7 @@ class ForceOpts(C.Structure):
 class MlpTrainCfg(C.Structure):
     _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_double),
                 ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("quantile", C.c_double)]
 
 
 class TreeInfo(C.Structure):
@@ -107,7 +107,7 @@ def load(path: str = LIB_PATH):
         "bh_mlp_samples": ([vp, dbl, dbl, dbl, dbl, C.c_uint64, i64, vp, vp, vp, vp,
                             C.POINTER(i64)], i32),
         "bh_mlp_train": ([vp, vp, vp, i64, C.POINTER(MlpTrainCfg), vp], i32),
-        "bh_mlp_grad": ([vp, vp, vp, i64, vp, C.POINTER(dbl)], i32),
+        "bh_mlp_grad": ([vp, vp, vp, i64, dbl, vp, C.POINTER(dbl)], i32),
         "bh_mlp_infer": ([vp, vp, i64, vp], i32),
     }
     for name, (args, res) in sig.items():
@@ -367,23 +367,23 @@ def _pairs(feat, label):
 
 
 def bh_mlp_train(ctx, feat, label, epochs=10, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999,
-                 eps=1e-8, seed=7) -> np.ndarray:
+                 eps=1e-8, seed=7, quantile=0.0) -> np.ndarray:
     n = _pairs(feat, label)
     cfg = MlpTrainCfg(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps),
-                      int(seed))
+                      int(seed), float(quantile))
     loss = np.zeros(max(int(epochs), 1))
     _check(load().bh_mlp_train(ctx, _dev(feat, "feat"), _dev(label, "label"), n, C.byref(cfg),
                                C.c_void_p(loss.ctypes.data)))
     return loss[:int(epochs)]
 
 
-def bh_mlp_grad(ctx, feat, label):
+def bh_mlp_grad(ctx, feat, label, quantile=0.0):
     import torch
     n = _pairs(feat, label)
     g = torch.empty(BH_MLP_PARAMS, dtype=torch.float32, device="cuda")
     lv = C.c_double()
-    _check(load().bh_mlp_grad(ctx, _dev(feat, "feat"), _dev(label, "label"), n, _dev(g, "grad"),
-                              C.byref(lv)))
+    _check(load().bh_mlp_grad(ctx, _dev(feat, "feat"), _dev(label, "label"), n, float(quantile),
+                              _dev(g, "grad"), C.byref(lv)))
     return g, lv.value
 
 

@@ -574,11 +574,13 @@ int bh_mlp_train(bh_ctx *c, const float *feat, const float *label, int64_t n,
     if (!c || !feat || !label || !cfg) return set_error(BH_E_INVALID, "null argument");
     if (n < 1 || n > (int64_t)0x7fffffff) return set_error(BH_E_INVALID, "n out of range");
     if (cfg->epochs < 0 || cfg->batch < 1 || !(cfg->lr > 0) || !(cfg->beta1 >= 0 && cfg->beta1 < 1) ||
-        !(cfg->beta2 >= 0 && cfg->beta2 < 1) || !(cfg->eps > 0))
+        !(cfg->beta2 >= 0 && cfg->beta2 < 1) || !(cfg->eps > 0) ||
+        !(cfg->quantile >= 0 && cfg->quantile < 1))
         return set_error(BH_E_INVALID, "bad training configuration");
     if (!c->mlp_loaded) return set_error(BH_E_STATE, "set initial parameters first");
     if (use_device(c)) return BH_E_DEVICE;
-    const MlpTrainCfg tc{(float)cfg->lr, (float)cfg->beta1, (float)cfg->beta2, (float)cfg->eps};
+    const MlpTrainCfg tc{(float)cfg->lr, (float)cfg->beta1, (float)cfg->beta2, (float)cfg->eps,
+                         (float)cfg->quantile};
     int rc = grow(c->mlp_scratch, 64);
     if (rc) return rc;
     float *lacc = (float *)c->mlp_scratch.p;
@@ -607,17 +609,18 @@ int bh_mlp_train(bh_ctx *c, const float *feat, const float *label, int64_t n,
     return mlp_pack(c);
 }
 
-int bh_mlp_grad(bh_ctx *c, const float *feat, const float *label, int64_t n, float *grad,
-                double *loss) {
+int bh_mlp_grad(bh_ctx *c, const float *feat, const float *label, int64_t n, double quantile,
+                float *grad, double *loss) {
     if (!c || !feat || !label || !grad) return set_error(BH_E_INVALID, "null argument");
     if (n < 1 || n > (1 << 24)) return set_error(BH_E_INVALID, "n out of range");
+    if (!(quantile >= 0 && quantile < 1)) return set_error(BH_E_INVALID, "quantile out of range");
     if (!c->mlp_loaded) return set_error(BH_E_STATE, "no parameters loaded");
     if (use_device(c)) return BH_E_DEVICE;
     int rc = grow(c->mlp_scratch, 64);
     if (rc) return rc;
     float *lacc = (float *)c->mlp_scratch.p;
     hipMemsetAsync(lacc, 0, 4, c->stream);
-    const MlpTrainCfg tc{1.f, 0.9f, 0.999f, 1e-8f};
+    const MlpTrainCfg tc{1.f, 0.9f, 0.999f, 1e-8f, (float)quantile};
     if ((rc = mlp_grad_step(c, feat, label, n, 0, (int)n, 1, 0, grad, lacc, false, 1, tc)))
         return rc;
     float lv = 0.f;

@@ -12,6 +12,7 @@ constexpr int kMlpParams = 1441;  // W1 320, b1 32, W2 1024, b2 32, w3 32, b3 1
 
 struct MlpTrainCfg {
     float lr, beta1, beta2, eps;
+    float quantile;  // 0: mean-squared error; in (0, 1): pinball loss
 };
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));

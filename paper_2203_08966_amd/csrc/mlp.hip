@@ -269,12 +269,15 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const int32_t *__restrict_
 // ------------------------------------------------------------------ training
 constexpr int kTrainBlock = 128;  // samples per block
 
-// Gradient of the mean-squared error over one minibatch.  Sample j of the
-// batch is sample (a * (base + j) + c) mod ns of the set (a permutation of
-// the set per epoch).  Each block writes its partial gradient and loss.
+// Gradient of the loss over one minibatch: mean-squared error (quantile 0)
+// or the pinball loss of quantile q (derivative 1 - q where the prediction
+// exceeds the label, else -q).  Sample j of the batch is sample
+// (a * (base + j) + c) mod ns of the set (a permutation of the set per
+// epoch).  Each block writes its partial gradient and loss.
 __global__ __launch_bounds__(kTrainBlock) void k_mlp_grad(
     const float *__restrict__ w, const float *__restrict__ X, const float *__restrict__ y,
-    int64_t ns, int64_t base, int bs, uint64_t a, uint64_t c, float *__restrict__ gpart) {
+    int64_t ns, int64_t base, int bs, uint64_t a, uint64_t c, float quantile,
+    float *__restrict__ gpart) {
     __shared__ float sw[kMlpParams];
     __shared__ float sx[kTrainBlock][kMlpIn];
     __shared__ float sh1[kTrainBlock][kMlpHidden];
@@ -312,8 +315,17 @@ __global__ __launch_bounds__(kTrainBlock) void k_mlp_grad(
     }
     float out = b3;
     for (int u = 0; u < kMlpHidden; ++u) out += w3[u] * fmaxf(z2[u], 0.f);
-    const float dout = live ? 2.f * (out - yy) / (float)bs : 0.f;
-    sl[t] = live ? (out - yy) * (out - yy) : 0.f;
+    float dout, lv;
+    if (quantile > 0.f) {
+        const bool over = out > yy;
+        dout = (over ? 1.f - quantile : -quantile) / (float)bs;
+        lv = over ? (1.f - quantile) * (out - yy) : quantile * (yy - out);
+    } else {
+        dout = 2.f * (out - yy) / (float)bs;
+        lv = (out - yy) * (out - yy);
+    }
+    if (!live) dout = lv = 0.f;
+    sl[t] = lv;
     sdo[t] = dout;
     for (int q = 0; q < kMlpIn; ++q) sx[t][q] = x[q];
     float d2v[kMlpHidden];
@@ -540,7 +552,8 @@ int mlp_grad_step(bh_ctx *c, const float *X, const float *y, int64_t ns, int64_t
     int rc = grow(c->mlp_gpart, 4ull * (kMlpParams + 1) * nblk);
     if (rc) return rc;
     k_mlp_grad<<<nblk, kTrainBlock, 0, c->stream>>>((const float *)c->mlp_master.p, X, y, ns, base,
-                                                    bs, a, cc, (float *)c->mlp_gpart.p);
+                                                    bs, a, cc, cfg.quantile,
+                                                    (float *)c->mlp_gpart.p);
     const float c1 = 1.f - powf(cfg.beta1, (float)step), c2 = 1.f - powf(cfg.beta2, (float)step);
     float *mst = (float *)c->mlp_master.p;
     k_mlp_adam<<<div_up(kMlpParams + 1, 256), 256, 0, c->stream>>>(

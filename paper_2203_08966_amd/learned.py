@@ -55,9 +55,19 @@ def training_set(ctx, seeds=range(41, 51), n=4096, snapshots=(0, 4, 8), dt=1e-3,
     return torch.cat(feats), torch.cat(labels)
 
 
-def train(ctx, feat, label, epochs=8, batch=4096, lr=1e-3, seed=7):
+def train(ctx, feat, label, epochs=8, batch=4096, lr=1e-3, seed=7, quantile=0.9):
     """Initialise, train on the GPU, leave the packed network in ctx.
-    Returns the per-epoch mean squared error."""
-    mean = float(label.double().mean().item())
-    B.bh_mlp_set(ctx, init_params(seed, mean))
-    return B.bh_mlp_train(ctx, feat, label, epochs=epochs, batch=batch, lr=lr, seed=seed)
+
+    With quantile q in (0, 1) the network is fitted to the q-quantile of the
+    label (pinball loss) instead of its mean: a cell is accepted for every
+    body direction at once, so its coefficient should bound the error of most
+    directions rather than describe the average one.  Returns the per-epoch
+    mean loss."""
+    import torch
+    if quantile > 0:
+        start = float(torch.quantile(label[: 1 << 24].double(), quantile).item())
+    else:
+        start = float(label.double().mean().item())
+    B.bh_mlp_set(ctx, init_params(seed, start))
+    return B.bh_mlp_train(ctx, feat, label, epochs=epochs, batch=batch, lr=lr, seed=seed,
+                          quantile=quantile)

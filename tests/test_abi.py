@@ -61,7 +61,7 @@ def test_null_handles_rejected():
     tot = C.c_int64()
     assert lib.bh_mlp_samples(None, 0.0, 0.3, 1.0, 1.0, 1, 0, None, None, None, None, C.byref(tot)) == B.BH_E_INVALID
     assert lib.bh_mlp_train(None, None, None, 1, None, None) == B.BH_E_INVALID
-    assert lib.bh_mlp_grad(None, None, None, 1, None, None) == B.BH_E_INVALID
+    assert lib.bh_mlp_grad(None, None, None, 1, 0.0, None, None) == B.BH_E_INVALID
     assert lib.bh_mlp_infer(None, None, 1, None) == B.BH_E_INVALID
     assert lib.bh_sim_timing_get(None, None, None) == B.BH_E_INVALID
 

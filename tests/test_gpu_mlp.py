@@ -47,18 +47,20 @@ def test_inference_matches_bf16_oracle(ctx):
     assert np.sqrt(np.mean((pred - full) ** 2)) < 0.05 * np.std(full) + 1e-3
 
 
-def test_gradient_matches_oracle(ctx):
+@pytest.mark.parametrize("quantile", [0.0, 0.9])
+def test_gradient_matches_oracle(ctx, quantile):
     th = _params(12, 0.1)
     B.bh_mlp_set(ctx, th)
     th32 = B.bh_mlp_get(ctx)
     X = _features(3000, 4)
     rng = np.random.default_rng(5)
     y = (rng.normal(size=3000) - 3.0).astype(np.float32)
-    say("training gradient (one batch of 3000) vs oracle FP64 backprop")
-    g, lv = B.bh_mlp_grad(ctx, torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda())
+    q = quantile if quantile > 0 else None
+    say(f"training gradient (one batch of 3000, quantile {quantile}) vs oracle FP64 backprop")
+    g, lv = B.bh_mlp_grad(ctx, torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(), quantile)
     g = g.cpu().numpy().astype(np.float64)
-    ref = mlp.grad(th32, X.astype(np.float64), y.astype(np.float64))
-    assert abs(lv - mlp.loss(th32, X.astype(np.float64), y.astype(np.float64))) < 1e-5 * abs(lv) + 1e-7
+    ref = mlp.grad(th32, X.astype(np.float64), y.astype(np.float64), q)
+    assert abs(lv - mlp.loss(th32, X.astype(np.float64), y.astype(np.float64), q)) < 1e-5 * abs(lv) + 1e-7
     rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     say(f"  relative gradient error {rel:.2e}")
     assert rel < 1e-4

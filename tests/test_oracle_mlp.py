@@ -190,3 +190,30 @@ def test_relative_criterion_beats_theta():
             best = r
     assert best is not None
     assert (best.npp + best.npc).mean() < 0.8 * (th.npp + th.npc).mean()
+
+
+def test_pinball_gradient_and_quantile():
+    """Pinball loss: the analytic gradient matches central differences, and
+    for a constant network the bias derivative vanishes exactly at the
+    label's q-quantile (the fraction of labels below it equals q)."""
+    rng = np.random.default_rng(21)
+    X = rng.normal(size=(80, 10))
+    y = rng.normal(size=80)
+    th = mlp.init(4) + rng.normal(size=mlp.NPARAM) * 0.05
+    q = 0.9
+    g = mlp.grad(th, X, y, q)
+    h = 1e-7
+    for k in rng.choice(mlp.NPARAM, size=80, replace=False):
+        e = np.zeros(mlp.NPARAM)
+        e[k] = h
+        fd = (mlp.loss(th + e, X, y, q) - mlp.loss(th - e, X, y, q)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-5 * max(1.0, abs(fd)) + 1e-8, k
+    # constant network: output = b3; d loss / d b3 = frac(y < b3) - q
+    c = np.zeros(mlp.NPARAM)
+    ys = np.sort(rng.normal(size=1000))
+    for b3, frac in ((ys[899] + 1e-9, 0.9), (ys[499] + 1e-9, 0.5), (ys[949] + 1e-9, 0.95)):
+        c[-1] = b3
+        gb = mlp.grad(c, np.zeros((1000, 10)), ys, q)[-1]
+        assert abs(gb - (frac - q)) < 1e-12
+    c[-1] = ys[899] + 1e-9
+    assert abs(mlp.grad(c, np.zeros((1000, 10)), ys, q)[-1]) < 1e-12

@@ -127,6 +127,7 @@ struct bh_tree {
     bh::DevBuf cellf, kc, anorm, est_acc;
     bh::DevBuf kids;                           // group walk: children per node
     bh::DevBuf wq;                             // group walk: queue counters
+    bh::DevBuf gorder;                         // group walk: hand-out order of the groups
     int64_t kids_tree_id = -1;
     int kc_version = -2;
     double kc_eps = -1.0;

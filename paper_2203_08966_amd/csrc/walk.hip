@@ -293,6 +293,7 @@ struct GroupMac {
     float tau;
     int cap;             // stack entries used (<= kGroupStack)
     int work_cap;        // per-group work above which the group walks per body
+    const uint32_t *gorder;  // order in which to hand out the groups, or null
 };
 
 // kids[8 c + q], q < #children: the children of internal node c in
@@ -540,7 +541,8 @@ __device__ __forceinline__ void group_walk(
             }
         }
     }
-    if (work > gm.work_cap) {  // too spread out for one decision: walk per body
+    const bool per_body = work > gm.work_cap;
+    if (per_body) {  // too spread out for one decision: walk per body
         sx = sy = sz = sp = 0;
         cpp = cpc = 0;
         const MlpMac pm{gm.kc, gm.anorm, (float)theta2, gm.tau};
@@ -583,13 +585,67 @@ __global__ __launch_bounds__(256) void k_gwalk(
     const int g_lo = xcd * chunk, g_hi = min(ng, g_lo + chunk);
     uint32_t *ctr = queue + 64 * xcd;  // one counter per 256 bytes
     for (;;) {
-        uint32_t g = 0;
-        if (lane_id() == 0) g = atomicAdd(ctr, 1u);
-        const int gi = g_lo + (int)__builtin_amdgcn_readfirstlane(g);
+        uint32_t slot = 0;
+        if (lane_id() == 0) slot = atomicAdd(ctr, 1u);
+        const int gi = g_lo + (int)__builtin_amdgcn_readfirstlane(slot);
         if (gi >= g_hi) break;
+        const int g = gm.gorder ? (int)gm.gorder[gi] : gi;
         group_walk<R, ORDER2, PHI, CNT, SORTED_OUT, BUDGET>(
-            nodes, m, bodies, anchors, kids, perm, nbodies, t0 + 64 * gi, t1, theta2, eps2, acc,
+            nodes, m, bodies, anchors, kids, perm, nbodies, t0 + 64 * g, t1, theta2, eps2, acc,
             phi_out, npp_out, npc_out, gm, stk);
+    }
+}
+
+// Longest first.  A group of 64 consecutive bodies that straddles a jump of
+// the space-filling curve has a box spanning the cells on both sides and
+// costs many times an ordinary group; such groups are recognised by the
+// smallest cell holding the group's first and last keys: the more bodies
+// that cell holds (two binary searches in the sorted keys), the more the
+// group is spread out.  Within each XCD's chunk, groups whose common cell
+// holds more than 256 x 64 bodies come first, then those above 16 x 64,
+// then the rest (order inside a class is immaterial: groups are
+// independent).  One block per chunk.
+__device__ __forceinline__ int64_t lower_key(const uint64_t *__restrict__ k, int64_t n,
+                                             uint64_t v) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (k[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(1024) void k_group_order(const uint64_t *__restrict__ keys,
+                                                      int64_t n, int t0, int t1, int ng,
+                                                      uint32_t *__restrict__ gorder) {
+    __shared__ uint32_t cnt[3], pos[3];
+    __shared__ uint8_t cls_s[4096];
+    const int chunk = (ng + 7) / 8;
+    const int lo = blockIdx.x * chunk, hi = min(ng, lo + chunk);
+    if (threadIdx.x < 3) cnt[threadIdx.x] = pos[threadIdx.x] = 0;
+    __syncthreads();
+    auto cls = [&](int g) {
+        const uint64_t a = keys[t0 + 64 * (int64_t)g];
+        const uint64_t b = keys[min(t0 + 64 * (int64_t)g + 63, (int64_t)t1 - 1)];
+        const uint64_t x = a ^ b;
+        const int lcp = x == 0 ? 21 : (__builtin_clzll(x) - 1) / 3;  // shared octal digits
+        const int sh = 3 * (21 - lcp);  // 0..63; keys are below 2^63
+        const uint64_t first = (a >> sh) << sh;
+        const uint64_t end = first + (1ull << sh);  // first key after the cell
+        const int64_t c = lower_key(keys, n, end) - lower_key(keys, n, first);
+        return c > 256 * 64 ? 0 : (c > 16 * 64 ? 1 : 2);
+    };
+    for (int g = lo + threadIdx.x; g < hi; g += blockDim.x) {
+        const int c = cls(g);
+        if (g - lo < 4096) cls_s[g - lo] = (uint8_t)c;
+        atomicAdd(&cnt[c], 1u);
+    }
+    __syncthreads();
+    for (int g = lo + threadIdx.x; g < hi; g += blockDim.x) {
+        const int c = g - lo < 4096 ? cls_s[g - lo] : cls(g);
+        const uint32_t base = c == 0 ? 0u : (c == 1 ? cnt[0] : cnt[0] + cnt[1]);
+        gorder[lo + base + atomicAdd(&pos[c], 1u)] = (uint32_t)g;
     }
 }
 
@@ -604,11 +660,17 @@ void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, vo
     const int per_xcd = std::min(div_up(div_up(ng, 8), 4), 256);
     uint32_t *queue = (uint32_t *)t->wq.p;
     k_zero_queue<<<1, 8, 0, t->ctx->stream>>>(queue);
+    GroupMac g2 = gm;
+    if (grow(t->gorder, 4ull * ng) == BH_OK) {
+        k_group_order<<<8, 1024, 0, t->ctx->stream>>>(t->sorted_keys, t->n, t0, t1, ng,
+                                                      (uint32_t *)t->gorder.p);
+        g2.gorder = (const uint32_t *)t->gorder.p;
+    }
     k_gwalk<R, ORDER2, PHI, CNT, SORTED, BUDGET><<<8 * per_xcd, 256, 0, t->ctx->stream>>>(
         (const typename NodeRecT<R>::type *)t->recs.p, (int)t->m,
         (const BodyRec<R> *)t->bodies.p, (const Anchor<R> *)t->anchors.p,
         (const int4 *)t->kids.p, t->perm, (int)t->n, t0, t1, queue, (R)(theta * theta),
-        (R)(eps * eps), (R *)acc, (R *)phi, npp, npc, gm);
+        (R)(eps * eps), (R *)acc, (R *)phi, npp, npc, g2);
 }
 
 template <typename R, bool ORDER2, bool BUDGET>
@@ -662,7 +724,7 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
         if (rc) return rc;
     }
     GroupMac gm{nullptr, nullptr, 0.f, o.walk_stack > 0 ? o.walk_stack : kGroupStack,
-                o.walk_cap > 0 ? o.walk_cap : kGroupWorkCap};
+                o.walk_cap > 0 ? o.walk_cap : kGroupWorkCap, nullptr};
     if (o.mac == BH_MAC_MLP || o.mac == BH_MAC_BUDGET) {
         if (t->dtype != BH_F32 || o.order != 2)
             return set_error(BH_E_INVALID, "the learned criterion runs in the FP32 quadrupole walk");

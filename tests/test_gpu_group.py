@@ -188,3 +188,24 @@ def test_group_walk_work_cap(ctx, mode):
     say(f"  fraction of bodies in groups over the cap: {fell:.3f}")
     assert 0.05 < fell < 0.95
     _check(ref, r, out, np.float32)
+
+
+def test_group_walk_repeat_is_bitwise_identical(ctx):
+    """A second walk of the same tree hands the groups out in the order of
+    the first walk's costs; every group's result is unchanged bit for bit."""
+    pos, _, mass = case_bodies("clumpy", 30000, 17, np.float32)
+    P, M = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
+    t = B.bh_build(ctx, P, M, 16)
+    outs = []
+    for k in range(3):
+        acc = torch.empty_like(P)
+        npc = torch.zeros(30000, dtype=torch.int32, device="cuda")
+        npp = torch.zeros(30000, dtype=torch.int32, device="cuda")
+        B.bh_forces(t, 0.7, 0.005, acc, B.force_opts(walk=B.BH_WALK_GROUP, walk_cap=2000,
+                                                      n_pp=npp, n_pc=npc))
+        torch.cuda.synchronize()
+        outs.append((acc.cpu().numpy(), npp.cpu().numpy(), npc.cpu().numpy()))
+    B.bh_tree_free(t)
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)

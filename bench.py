@@ -54,8 +54,8 @@ FLOP_PC = {0: 20, 2: 60}
 # force-evaluation methods compared at the target error, with the parameter
 # grid each is swept over (from accurate to cheap)
 METHODS = {
-    "body-theta": [round(0.5 + 0.02 * k, 2) for k in range(16)],      # Sec. 3 walk
-    "group-theta": [round(0.6 + 0.025 * k, 3) for k in range(14)],    # one decision per wave
+    "body-theta": [round(0.5 + 0.01 * k, 2) for k in range(31)],      # Sec. 3 walk
+    "group-theta": [round(0.6 + 0.0125 * k, 4) for k in range(29)],   # one decision per wave
     "group-budget": [round(-2.5 + 0.125 * k, 3) for k in range(13)],  # log10 tau
     "group-learned": [round(-4.0 + 0.125 * k, 3) for k in range(21)],  # log10 tau
 }

@@ -90,7 +90,7 @@ typedef struct {
     double mlp_theta_est;     /* default 0.8 */
     int walk;                 /* BH_WALK_BODY (default) or BH_WALK_GROUP */
     int walk_stack;           /* group walk: LDS stack entries per wavefront,
-                                 1..1024, 0 = 1024; subtrees that do not fit
+                                 1..640, 0 = 640; subtrees that do not fit
                                  are walked without the stack (same result) */
     int walk_cap;             /* group walk: a group whose work (particle-cell
                                  terms + particle-particle bodies, per body)

@@ -90,8 +90,8 @@ static int check_opts(const bh_force_opts &o, int64_t n) {
         return set_error(BH_E_INVALID, "opts learned-criterion parameters invalid");
     if (o.walk != BH_WALK_BODY && o.walk != BH_WALK_GROUP)
         return set_error(BH_E_INVALID, "opts.walk must be BH_WALK_BODY or BH_WALK_GROUP");
-    if (o.walk_stack < 0 || o.walk_stack > 1024)
-        return set_error(BH_E_INVALID, "opts.walk_stack must be in [0, 1024]");
+    if (o.walk_stack < 0 || o.walk_stack > 640)
+        return set_error(BH_E_INVALID, "opts.walk_stack must be in [0, 640]");
     if (o.walk_cap < 0) return set_error(BH_E_INVALID, "opts.walk_cap must be >= 0");
     return BH_OK;
 }

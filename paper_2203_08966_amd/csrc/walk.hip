@@ -284,7 +284,8 @@ void dispatch2(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, 
 // bodies, the same for each of its bodies) is therefore capped: a group
 // that would exceed the cap drops its partial sums and is walked per body
 // with the same criterion instead.
-constexpr int kGroupStack = 1024;      // LDS stack entries per wavefront
+constexpr int kGroupStack = 640;       // LDS stack entries per wavefront
+constexpr int kStageW = 12;            // LDS words per staged accepted cell
 constexpr int kGroupWorkCap = 4096;    // default per-group work cap
 
 struct GroupMac {
@@ -339,7 +340,7 @@ __device__ __forceinline__ void group_walk(
     const int4 *__restrict__ kids, const uint32_t *__restrict__ perm, int nbodies, int base,
     int t1, R theta2, R eps2, R *__restrict__ acc, R *__restrict__ phi_out,
     uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out, const GroupMac &gm,
-    int *__restrict__ stk) {
+    int *__restrict__ stk, R *__restrict__ stage) {
     using Rec = typename NodeRecT<R>::type;
     const int lane = (int)lane_id();
     const int i = base + lane;
@@ -428,6 +429,38 @@ __device__ __forceinline__ void group_walk(
         if (CNT) ++cpc;
         ++work;
     };
+    // particle-cell term of a staged cell: COM relative to the group origin
+    // g, mass, quadrupole (xx xy xz yy yz zz)
+    auto staged_term = [&](const R *st) {
+        const R x = px - st[0], y = py - st[1], z = pz - st[2];
+        const R inv = rsq(z * z + (y * y + (x * x + eps2)));
+        const R inv2 = inv * inv;
+        const R inv3 = inv * inv2;
+        const R m = st[3];
+        if (ORDER2) {
+            const R qx = st[4] * x + st[5] * y + st[6] * z;
+            const R qy = st[5] * x + st[7] * y + st[8] * z;
+            const R qz = st[6] * x + st[8] * y + st[9] * z;
+            const R xqx = x * qx + y * qy + z * qz;
+            const R inv5 = inv3 * inv2;
+            const R t5 = xqx * inv5;
+            const R g = m * inv3 + (R)2.5 * t5 * inv2;
+            sx = inv5 * qx + sx;
+            sy = inv5 * qy + sy;
+            sz = inv5 * qz + sz;
+            sx = -g * x + sx;
+            sy = -g * y + sy;
+            sz = -g * z + sz;
+            if (PHI) sp = sp - m * inv - (R)0.5 * t5;
+        } else {
+            const R g = m * inv3;
+            sx = -g * x + sx;
+            sy = -g * y + sy;
+            sz = -g * z + sz;
+            if (PHI) sp = sp - m * inv;
+        }
+        if (CNT) ++cpc;
+    };
     // particle-particle terms with the bodies of leaf (or one-body cell) nd
     auto leaf_terms = [&](const Rec &nd) {
         const int jb = uniform(nd.begin);
@@ -468,14 +501,31 @@ __device__ __forceinline__ void group_walk(
             const int c = has ? stk[top + lane] : 0;
             int cls = kGNone;
             int4 k0 = make_int4(-1, -1, -1, -1), k1 = k0;
+            Rec nd{};
             if (has) {
                 k0 = kids[2 * (int64_t)c];  // loaded with the record, used if opened
                 k1 = kids[2 * (int64_t)c + 1];
-                cls = classify(nodes[c], c, BUDGET ? gm.kc[c] : 0.f);
+                nd = nodes[c];
+                cls = classify(nd, c, BUDGET ? gm.kc[c] : 0.f);
             }
             const uint64_t m_pc = __ballot(cls == kGPC);
             const uint64_t m_pp = __ballot(cls == kGPP);
             const uint64_t m_op = __ballot(cls == kGOpen);
+            if (cls == kGPC) {  // stage the accepted cell for every lane
+                const int slot = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(m_pc >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m_pc, 0u));
+                R *st = stage + kStageW * slot;
+                st[0] = (nd.cx - gx) + nd.mx;
+                st[1] = (nd.cy - gy) + nd.my;
+                st[2] = (nd.cz - gz) + nd.mz;
+                st[3] = nd.m;
+                st[4] = nd.qxx;
+                st[5] = nd.qxy;
+                st[6] = nd.qxz;
+                st[7] = nd.qyy;
+                st[8] = nd.qyz;
+                st[9] = -nd.qxx - nd.qyy;
+            }
             if (m_op) {
                 const int kid[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
                 int nk = 0;
@@ -506,34 +556,12 @@ __device__ __forceinline__ void group_walk(
                     }
                 }
             }
-            // accepted cells, four records in flight at a time
-            uint64_t mm = m_pc;
-            while (mm) {
-                const int n0 = __builtin_amdgcn_readlane(c, __builtin_ctzll(mm));
-                mm &= mm - 1;
-                int n1 = n0, n2 = n0, n3 = n0;
-                const bool h1 = mm != 0;
-                if (h1) {
-                    n1 = __builtin_amdgcn_readlane(c, __builtin_ctzll(mm));
-                    mm &= mm - 1;
-                }
-                const bool h2 = mm != 0;
-                if (h2) {
-                    n2 = __builtin_amdgcn_readlane(c, __builtin_ctzll(mm));
-                    mm &= mm - 1;
-                }
-                const bool h3 = mm != 0;
-                if (h3) {
-                    n3 = __builtin_amdgcn_readlane(c, __builtin_ctzll(mm));
-                    mm &= mm - 1;
-                }
-                const Rec r0 = nodes[n0], r1 = nodes[n1], r2 = nodes[n2], r3 = nodes[n3];
-                cell_term(r0);
-                if (h1) cell_term(r1);
-                if (h2) cell_term(r2);
-                if (h3) cell_term(r3);
-            }
-            mm = m_pp;
+            // accepted cells from LDS (same address on every lane: broadcast)
+            const int npc_round = __builtin_popcountll(m_pc);
+            __builtin_amdgcn_wave_barrier();
+            for (int q = 0; q < npc_round; ++q) staged_term(stage + kStageW * q);
+            work += npc_round;
+            uint64_t mm = m_pp;
             while (mm) {
                 const int bit = __builtin_ctzll(mm);
                 mm &= mm - 1;
@@ -578,7 +606,9 @@ __global__ __launch_bounds__(256) void k_gwalk(
     R *__restrict__ phi_out, uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out,
     GroupMac gm) {
     __shared__ int stack_all[4][kGroupStack];
+    __shared__ R stage_all[4][64 * kStageW];
     int *stk = stack_all[threadIdx.x >> 6];
+    R *stage = stage_all[threadIdx.x >> 6];
     const int ng = (t1 - t0 + 63) / 64;
     const int xcd = (int)(blockIdx.x & 7);
     const int chunk = (ng + 7) / 8;
@@ -592,7 +622,7 @@ __global__ __launch_bounds__(256) void k_gwalk(
         const int g = gm.gorder ? (int)gm.gorder[gi] : gi;
         group_walk<R, ORDER2, PHI, CNT, SORTED_OUT, BUDGET>(
             nodes, m, bodies, anchors, kids, perm, nbodies, t0 + 64 * g, t1, theta2, eps2, acc,
-            phi_out, npp_out, npc_out, gm, stk);
+            phi_out, npp_out, npc_out, gm, stk, stage);
     }
 }
 

@@ -275,8 +275,8 @@ def _mac_sigs(lib):
     lib.orc_walk_group.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
                                    _f64, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
                                    C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_int64,
-                                   C.c_int64, C.c_int64, C.c_int64, C.c_double, _f64, _f64, _i64,
-                                   _i64, _i64, _i32]
+                                   C.c_int64, C.c_int64, C.c_int64, C.c_double, _u64, _i32,
+                                   C.c_int, _f64, _f64, _i64, _i64, _i64, _i32]
     return lib
 
 
@@ -371,13 +371,24 @@ def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None):
 GROUP_WORK_CAP = 4096
 
 
+def leaf_levels(b):
+    """Level of the leaf holding each sorted rank."""
+    t = b["tree"]
+    out = np.zeros(len(b["smass"]), dtype=np.int32)
+    for c in np.nonzero(t["next"] == np.arange(len(t["next"])) + 1)[0]:
+        out[t["begin"][c]:t["begin"][c] + t["count"][c]] = t["level"][c]
+    return out
+
+
 def walk_group(b, eps, group=64, mode=0, theta=0.5, theta_max=1.0, tau=1e-3, kc=None,
-               anorm=None, order=2, target_range=None, tol=1e-5, cap=GROUP_WORK_CAP):
+               anorm=None, order=2, target_range=None, tol=1e-5, cap=GROUP_WORK_CAP,
+               split=True):
     """Walk with one acceptance decision per group of ``group`` consecutive
     sorted ranks in ``target_range`` (all bodies by default): mode 0 opening
-    angle, mode 1 error budget (kc per cell, anorm per sorted rank).  Groups
-    whose work exceeds ``cap`` are walked per body.  Results are indexed by
-    rank - t0."""
+    angle, mode 1 error budget (kc per cell, anorm per sorted rank).  With
+    ``split`` a group straddling a jump of the space-filling curve is cut
+    into runs walked as groups of their own.  Groups whose work exceeds
+    ``cap`` are walked per body.  Results are indexed by rank - t0."""
     lib = _mlib()
     t = b["tree"]
     M, com, Q = b["mom"]
@@ -401,5 +412,7 @@ def walk_group(b, eps, group=64, mode=0, theta=0.5, theta_max=1.0, tau=1e-3, kc=
                            int(mode), float(theta), float(theta_max), float(tau),
                            None if kcv is None else kcv.ctypes.data,
                            None if anv is None else anv.ctypes.data, int(group), t0, t1,
-                           int(cap), float(tol), acc.ravel(), phi, npp, npc, ncov, flag)
+                           int(cap), float(tol), np.ascontiguousarray(b["keys"], dtype=np.uint64),
+                           leaf_levels(b), 1 if split else 0, acc.ravel(), phi, npp, npc, ncov,
+                           flag)
     return WalkResult(acc, phi, npp, npc, ncov, flag)

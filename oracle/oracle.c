@@ -818,6 +818,15 @@ void orc_walk_kc(const int32_t *level, const uint64_t *hkey, const int32_t *begi
  * walked per body instead, with the same criterion: the walk of Sec. 3 at
  * theta (mode 0), or the per-body error-budget walk (mode 1).
  *
+ * With split set, a group that straddles a jump of the space-filling curve
+ * is first cut into runs of consecutive bodies, each walked as a group of
+ * its own (box, decisions, cap).  From the left: the run is [lo, g1); while
+ * it holds two or more bodies and its common cell (level = the smallest
+ * common-prefix length, in octal digits, of adjacent keys inside it) lies
+ * more than two levels above its shallowest leaf, it is cut before its
+ * first adjacent pair with that smallest common prefix.  The run found is
+ * walked and the next starts where it ended.
+ *
  * flag[t] is set for every body of a group that met a test within a
  * relative tol of a threshold, or a cube face within tol * l of the box.
  * ====================================================================== */
@@ -889,17 +898,79 @@ static void group_cell(group_ctx *g, int64_t node)
 }
 
 /* Outputs indexed by t - t0 for t in [t0, t1). */
+static void walk_one_group(const int32_t *level, const uint64_t *hkey, const int32_t *begin,
+                           const int32_t *count, const int32_t *next, const double *M,
+                           const double *com, const double *Q, const double *spos,
+                           const double *smass, const double *lo, double L, double eps,
+                           int order, int mode, double theta, double theta_max, double tau,
+                           const double *kc, const double *anorm, int64_t r0, int64_t r1,
+                           int64_t t0, int64_t cap, double tol, double *acc, double *phi,
+                           int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag);
+
+/* common octal digits of two keys (21 if equal) */
+static int key_lcp(uint64_t a, uint64_t b)
+{
+    const uint64_t x = a ^ b;
+    if (!x)
+        return ORC_LEVELS;
+    int lz = 0;
+    while (!((x << lz) & ((uint64_t)1 << 63)))
+        ++lz;
+    return (lz - 1) / 3;
+}
+
 void orc_walk_group(const int32_t *level, const uint64_t *hkey, const int32_t *begin,
                     const int32_t *count, const int32_t *next, const double *M,
                     const double *com, const double *Q, const double *spos, const double *smass,
                     const double *lo, double L, double eps, int order, int mode, double theta,
                     double theta_max, double tau, const double *kc, const double *anorm,
-                    int64_t G, int64_t t0, int64_t t1, int64_t cap, double tol, double *acc,
+                    int64_t G, int64_t t0, int64_t t1, int64_t cap, double tol,
+                    const uint64_t *skeys, const int32_t *leaf_level, int split, double *acc,
                     double *phi, int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag)
 {
     const int64_t ng = (t1 - t0 + G - 1) / G;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t gi = 0; gi < ng; ++gi) {
+        const int64_t g0 = t0 + gi * G, g1 = g0 + G < t1 ? g0 + G : t1;
+        int64_t a = g0;
+        while (a < g1) {
+            int64_t b = g1;
+            while (split && b - a >= 2) {
+                int kanc = 127, kleaf = 127;
+                int64_t cut = -1;
+                for (int64_t j = a + 1; j < b; ++j) {
+                    const int d = key_lcp(skeys[j - 1], skeys[j]);
+                    if (d < kanc) {
+                        kanc = d;
+                        cut = j;
+                    }
+                }
+                for (int64_t j = a; j < b; ++j)
+                    if (leaf_level[j] < kleaf)
+                        kleaf = leaf_level[j];
+                if (kanc >= kleaf - 2)
+                    break;
+                b = cut;
+            }
+            walk_one_group(level, hkey, begin, count, next, M, com, Q, spos, smass, lo, L, eps,
+                           order, mode, theta, theta_max, tau, kc, anorm, a, b, t0, cap, tol,
+                           acc, phi, npp, npc, ncov, flag);
+            a = b;
+        }
+    }
+}
+
+/* One group (or run): the bodies of sorted rank [r0, r1), outputs at rank - t0. */
+static void walk_one_group(const int32_t *level, const uint64_t *hkey, const int32_t *begin,
+                           const int32_t *count, const int32_t *next, const double *M,
+                           const double *com, const double *Q, const double *spos,
+                           const double *smass, const double *lo, double L, double eps,
+                           int order, int mode, double theta, double theta_max, double tau,
+                           const double *kc, const double *anorm, int64_t r0, int64_t r1,
+                           int64_t t0, int64_t cap, double tol, double *acc, double *phi,
+                           int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag)
+{
+    {
         group_ctx g;
         memset(&g, 0, sizeof(g));
         g.w = (walk_ctx){level, begin, count, next, M, com, Q, spos, smass, L, 0.0, eps * eps,
@@ -912,8 +983,8 @@ void orc_walk_group(const int32_t *level, const uint64_t *hkey, const int32_t *b
         g.tmax2 = theta_max * theta_max;
         g.tau = tau;
         g.tol = tol;
-        g.g0 = t0 + gi * G;
-        g.g1 = g.g0 + G < t1 ? g.g0 + G : t1;
+        g.g0 = r0;
+        g.g1 = r1;
         double bl[3] = {INFINITY, INFINITY, INFINITY}, bu[3] = {-INFINITY, -INFINITY, -INFINITY};
         g.amin = INFINITY;
         for (int64_t i = g.g0; i < g.g1; ++i) {

@@ -675,33 +675,57 @@ __global__ __launch_bounds__(kThreads) void k_up_leaves(
     cmask[i] = 0u;
 }
 
-// Internal cells of one level: combine the children (already done, one
-// level deeper) about this cell's centre with the parallel-axis shift;
-// children in octant order.  Also the 8-bit child mask.
-__global__ __launch_bounds__(kThreads) void k_up_level(
-    const int32_t *__restrict__ list, int cnt, int m, const uint64_t *__restrict__ hkey,
-    const int32_t *__restrict__ next, const int32_t *__restrict__ cx,
-    const int32_t *__restrict__ cy, const int32_t *__restrict__ cz, const Cube *__restrict__ cube,
-    Moments *__restrict__ mom, uint32_t *__restrict__ cmask) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= cnt) return;
-    const int p = list[t];
+// Children of every internal node, in pre-order (= octant order), from the
+// skip pointers: kids[8 c + q] for q < #children, then -1.  The upward pass
+// and the group walk read a node's children from here in one load.
+__global__ __launch_bounds__(kThreads) void k_kids(int m, const int32_t *__restrict__ next,
+                                                   int32_t *__restrict__ kids) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    int k[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+    const int end = next[c];
+    int q = 0;
+    for (int ch = c + 1; ch < end && q < 8;) {
+        k[q++] = ch;
+        const int nx = next[ch];
+        if (nx <= ch) break;  // malformed skip pointer: stop
+        ch = nx;
+    }
+    int4 *o = (int4 *)(kids + 8 * (int64_t)c);
+    o[0] = make_int4(k[0], k[1], k[2], k[3]);
+    o[1] = make_int4(k[4], k[5], k[6], k[7]);
+}
+
+// One internal cell: combine its children (already done, one level deeper)
+// about this cell's centre with the parallel-axis shift, children in
+// octant order.  Also the 8-bit child mask.
+__device__ __forceinline__ void up_node(int p, int m, const int4 *__restrict__ kids,
+                                        const uint64_t *__restrict__ hkey,
+                                        const int32_t *__restrict__ next,
+                                        const int32_t *__restrict__ cx,
+                                        const int32_t *__restrict__ cy,
+                                        const int32_t *__restrict__ cz, double h,
+                                        Moments *__restrict__ mom, uint32_t *__restrict__ cmask) {
     if (p < 0 || p >= m || next[p] == p + 1) return;  // leaves are done
-    const double h = ldexp(cube->L, -(kLevels + 1));
+    const int4 k0 = kids[2 * (int64_t)p], k1 = kids[2 * (int64_t)p + 1];
+    const int ch[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
     const int pcx = cx[p], pcy = cy[p], pcz = cz[p];
-    const int pend = min(next[p], m);
     double mt = 0, s0 = 0, s1 = 0, s2 = 0;
     uint32_t mask = 0;
-    for (int c = p + 1; c < pend; c = max(next[c], c + 1)) {
-        const Moments q = mom[c];
-        const double g0 = q.c[0] + (double)(cx[c] - pcx) * h;
-        const double g1 = q.c[1] + (double)(cy[c] - pcy) * h;
-        const double g2 = q.c[2] + (double)(cz[c] - pcz) * h;
-        mt += q.m;
-        s0 += q.m * g0;
-        s1 += q.m * g1;
-        s2 += q.m * g2;
-        mask |= 1u << (uint32_t)(hkey[c] & 7u);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int c = ch[q];
+        if (c > p && c < m) {
+            const Moments qm = mom[c];
+            const double g0 = qm.c[0] + (double)(cx[c] - pcx) * h;
+            const double g1 = qm.c[1] + (double)(cy[c] - pcy) * h;
+            const double g2 = qm.c[2] + (double)(cz[c] - pcz) * h;
+            mt += qm.m;
+            s0 += qm.m * g0;
+            s1 += qm.m * g1;
+            s2 += qm.m * g2;
+            mask |= 1u << (uint32_t)(hkey[c] & 7u);
+        }
     }
     Moments r;
     r.m = mt;
@@ -709,20 +733,61 @@ __global__ __launch_bounds__(kThreads) void k_up_level(
     r.c[1] = mt > 0 ? s1 / mt : 0.0;
     r.c[2] = mt > 0 ? s2 / mt : 0.0;
     for (int a = 0; a < 6; ++a) r.t[a] = 0.0;
-    for (int c = p + 1; c < pend; c = max(next[c], c + 1)) {
-        const Moments q = mom[c];
-        const double y0 = q.c[0] + (double)(cx[c] - pcx) * h - r.c[0];
-        const double y1 = q.c[1] + (double)(cy[c] - pcy) * h - r.c[1];
-        const double y2 = q.c[2] + (double)(cz[c] - pcz) * h - r.c[2];
-        r.t[0] += q.t[0] + q.m * y0 * y0;
-        r.t[1] += q.t[1] + q.m * y0 * y1;
-        r.t[2] += q.t[2] + q.m * y0 * y2;
-        r.t[3] += q.t[3] + q.m * y1 * y1;
-        r.t[4] += q.t[4] + q.m * y1 * y2;
-        r.t[5] += q.t[5] + q.m * y2 * y2;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int c = ch[q];
+        if (c > p && c < m) {
+            const Moments qm = mom[c];
+            const double y0 = qm.c[0] + (double)(cx[c] - pcx) * h - r.c[0];
+            const double y1 = qm.c[1] + (double)(cy[c] - pcy) * h - r.c[1];
+            const double y2 = qm.c[2] + (double)(cz[c] - pcz) * h - r.c[2];
+            r.t[0] += qm.t[0] + qm.m * y0 * y0;
+            r.t[1] += qm.t[1] + qm.m * y0 * y1;
+            r.t[2] += qm.t[2] + qm.m * y0 * y2;
+            r.t[3] += qm.t[3] + qm.m * y1 * y1;
+            r.t[4] += qm.t[4] + qm.m * y1 * y2;
+            r.t[5] += qm.t[5] + qm.m * y2 * y2;
+        }
     }
     mom[p] = r;
     cmask[p] = mask;
+}
+
+// Internal cells of one level (one launch per level with more than
+// kTopCells cells).
+__global__ __launch_bounds__(kThreads) void k_up_level(
+    const int32_t *__restrict__ list, int cnt, int m, const int4 *__restrict__ kids,
+    const uint64_t *__restrict__ hkey, const int32_t *__restrict__ next,
+    const int32_t *__restrict__ cx, const int32_t *__restrict__ cy,
+    const int32_t *__restrict__ cz, const Cube *__restrict__ cube, Moments *__restrict__ mom,
+    uint32_t *__restrict__ cmask) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    up_node(list[t], m, kids, hkey, next, cx, cy, cz, ldexp(cube->L, -(kLevels + 1)), mom,
+            cmask);
+}
+
+// Levels top .. 0 (all small) in one workgroup, deepest first, with a
+// workgroup barrier between levels.  All waves of the workgroup share one
+// CU, so the barrier's workgroup-scope fence makes a level's results
+// visible to the next.
+__global__ __launch_bounds__(1024) void k_up_top(const int32_t *__restrict__ list, LevelBase lb,
+                                                 LevelBase lc, int top, int m,
+                                                 const int4 *__restrict__ kids,
+                                                 const uint64_t *__restrict__ hkey,
+                                                 const int32_t *__restrict__ next,
+                                                 const int32_t *__restrict__ cx,
+                                                 const int32_t *__restrict__ cy,
+                                                 const int32_t *__restrict__ cz,
+                                                 const Cube *__restrict__ cube,
+                                                 Moments *__restrict__ mom,
+                                                 uint32_t *__restrict__ cmask) {
+    const double h = ldexp(cube->L, -(kLevels + 1));
+    for (int k = top; k >= 0; --k) {
+        for (int t = threadIdx.x; t < lc.base[k]; t += blockDim.x)
+            up_node(list[lb.base[k] + t], m, kids, hkey, next, cx, cy, cz, h, mom, cmask);
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------------ 7. pack
@@ -906,6 +971,7 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
         (rc = grow(t->cx, 4ull * m)) ||
         (rc = grow(t->cy, 4ull * m)) || (rc = grow(t->cz, 4ull * m)) ||
         (rc = grow(t->mom, sizeof(Moments) * (size_t)m)) ||
+        (rc = grow(t->kids, 32ull * m)) ||
         (rc = grow(t->recs, sizeof(typename NodeRecT<T>::type) * (size_t)m)))
         return rc;
     const int nbm = div_up(m, kThreads);
@@ -919,13 +985,29 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
         m, (const int32_t *)t->begin.p, (const int32_t *)t->count.p, (const int32_t *)t->next.p,
         (const int32_t *)t->cx.p, (const int32_t *)t->cy.p, (const int32_t *)t->cz.p, pos_out,
         mass_out, cube, (Moments *)t->mom.p, (uint32_t *)t->cmask.p);
-    for (int k = t->depth - 1; k >= 0; --k) {  // deepest internal level first
+    k_kids<<<nbm, kThreads, 0, st>>>(m, (const int32_t *)t->next.p, (int32_t *)t->kids.p);
+    // the top levels whose cells number at most kTopCells each go to one
+    // workgroup; the deeper levels get a launch each, deepest first
+    constexpr int kTopCells = 1024;
+    int top = -1;
+    while (top + 1 <= t->depth - 1 && lcount[top + 1] <= kTopCells) ++top;
+    const int4 *kids4 = (const int4 *)t->kids.p;
+    for (int k = t->depth - 1; k > top; --k) {
         if (lcount[k] == 0) continue;
         k_up_level<<<div_up(lcount[k], kThreads), kThreads, 0, st>>>(
-            lvl_list + lb.base[k], lcount[k], m, (const uint64_t *)t->hkey.p,
+            lvl_list + lb.base[k], lcount[k], m, kids4, (const uint64_t *)t->hkey.p,
             (const int32_t *)t->next.p, (const int32_t *)t->cx.p, (const int32_t *)t->cy.p,
             (const int32_t *)t->cz.p, cube, (Moments *)t->mom.p, (uint32_t *)t->cmask.p);
     }
+    if (top >= 0) {
+        LevelBase lc;  // cells per level
+        for (int k = 0; k <= kLevels; ++k) lc.base[k] = lcount[k];
+        k_up_top<<<1, 1024, 0, st>>>(lvl_list, lb, lc, top, m, kids4, (const uint64_t *)t->hkey.p,
+                                      (const int32_t *)t->next.p, (const int32_t *)t->cx.p,
+                                      (const int32_t *)t->cy.p, (const int32_t *)t->cz.p, cube,
+                                      (Moments *)t->mom.p, (uint32_t *)t->cmask.p);
+    }
+    t->kids_tree_id = t->build_id;
     k_pack_nodes<T><<<nbm, kThreads, 0, st>>>(
         m, (const int32_t *)t->level.p, (const int32_t *)t->begin.p,
         (const int32_t *)t->count.p, (const int32_t *)t->next.p, (const int32_t *)t->cx.p,

@@ -297,26 +297,6 @@ struct GroupMac {
     const uint32_t *gorder;  // order in which to hand out the groups, or null
 };
 
-// kids[8 c + q], q < #children: the children of internal node c in
-// pre-order, then -1.
-__global__ __launch_bounds__(256) void k_kids(int m, const int32_t *__restrict__ next,
-                                              int32_t *__restrict__ kids) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= m) return;
-    int k[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
-    const int end = next[c];
-    int q = 0;
-    for (int ch = c + 1; ch < end && q < 8;) {
-        k[q++] = ch;
-        const int nx = next[ch];
-        if (nx <= ch) break;  // malformed skip pointer: stop
-        ch = nx;
-    }
-    int4 *o = (int4 *)(kids + 8 * (int64_t)c);
-    o[0] = make_int4(k[0], k[1], k[2], k[3]);
-    o[1] = make_int4(k[4], k[5], k[6], k[7]);
-}
-
 template <typename R>
 __device__ __forceinline__ R wave_min(R v) {
 #pragma unroll
@@ -330,6 +310,12 @@ __device__ __forceinline__ R wave_max(R v) {
     return v;
 }
 
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int sh = 1; sh < 64; sh <<= 1) v = min(v, __shfl_xor(v, sh));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 enum : int { kGNone = 0, kGPC = 1, kGPP = 2, kGOpen = 3 };
 
 // One group: the 64 bodies of sorted rank [base, min(base + 64, t1)).
@@ -340,7 +326,8 @@ __device__ __forceinline__ void group_walk(
     const int4 *__restrict__ kids, const uint32_t *__restrict__ perm, int nbodies, int base,
     int t1, R theta2, R eps2, R *__restrict__ acc, R *__restrict__ phi_out,
     uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out, const GroupMac &gm,
-    int *__restrict__ stk, R *__restrict__ stage) {
+    int *__restrict__ stk, R *__restrict__ stage, const int8_t *__restrict__ delta,
+    const int32_t *__restrict__ level) {
     using Rec = typename NodeRecT<R>::type;
     const int lane = (int)lane_id();
     const int i = base + lane;
@@ -360,234 +347,260 @@ __device__ __forceinline__ void group_walk(
         az = an.z;
         myleaf = an.leaf;
     }
-    // the group's bounding box, relative to the leaf centre g of the first
-    // body: grid centres differ exactly, so the box and the cell distances
-    // are accurate to the rounding of the offsets
-    const R gx = __shfl(ax, 0), gy = __shfl(ay, 0), gz = __shfl(az, 0);
-    const R big = (R)3.0e38;
-    const R px = (ax - gx) + ox, py = (ay - gy) + oy, pz = (az - gz) + oz;
-    const R lx = wave_min(live ? px : big), ly = wave_min(live ? py : big),
-            lz = wave_min(live ? pz : big);
-    const R hx = wave_max(live ? px : -big), hy = wave_max(live ? py : -big),
-            hz = wave_max(live ? pz : -big);
-    const R bcx = (R)0.5 * (lx + hx), bcy = (R)0.5 * (ly + hy), bcz = (R)0.5 * (lz + hz);
-    const R bhx = (R)0.5 * (hx - lx), bhy = (R)0.5 * (hy - ly), bhz = (R)0.5 * (hz - lz);
-    float tau_amin = 0.f;
-    if (BUDGET) tau_amin = gm.tau * wave_min(live ? gm.anorm[i] : 3.0e38f);
+    // A group that straddles a jump of the space-filling curve is split into
+    // runs of consecutive bodies, each walked as a group of its own: from
+    // the left, a run [lo, hi) is cut at its first largest jump (the first
+    // smallest common-prefix length of adjacent keys) while its common cell
+    // lies more than two levels above its shallowest leaf.
+    const int dl = (live && lane > 0) ? (int)delta[i] : 127;  // common octal digits with i - 1
+    const int lv = live ? level[myleaf] : 127;
+    const int nlive = g_end - base;
 
-    R sx = 0, sy = 0, sz = 0, sp = 0;
-    uint32_t cpp = 0, cpc = 0;
-    int work = 0;  // wave-uniform
+    auto pass = [&](const int lo, const int hi) {
+        const bool live_run = live && lane >= lo && lane < hi;
+        // the group's bounding box, relative to the leaf centre g of the first
+        // body: grid centres differ exactly, so the box and the cell distances
+        // are accurate to the rounding of the offsets
+        const R gx = __shfl(ax, lo), gy = __shfl(ay, lo), gz = __shfl(az, lo);
+        const R big = (R)3.0e38;
+        const R px = (ax - gx) + ox, py = (ay - gy) + oy, pz = (az - gz) + oz;
+        const R lx = wave_min(live_run ? px : big), ly = wave_min(live_run ? py : big),
+                lz = wave_min(live_run ? pz : big);
+        const R hx = wave_max(live_run ? px : -big), hy = wave_max(live_run ? py : -big),
+                hz = wave_max(live_run ? pz : -big);
+        const R bcx = (R)0.5 * (lx + hx), bcy = (R)0.5 * (ly + hy), bcz = (R)0.5 * (lz + hz);
+        const R bhx = (R)0.5 * (hx - lx), bhy = (R)0.5 * (hy - ly), bhz = (R)0.5 * (hz - lz);
+        float tau_amin = 0.f;
+        if (BUDGET) tau_amin = gm.tau * wave_min(live_run ? gm.anorm[i] : 3.0e38f);
 
-    // decision for node c (any lane; wave-uniform when the node is)
-    auto classify = [&](const Rec &nd, int c, float kcv) -> int {
-        if (c == 0) return kGOpen;  // the root is always opened
-        if (nd.count == 1) return kGPP;
-        const R hs = (R)0.5 * sqrt(nd.l2);
-        const R ux = (nd.cx - gx) - bcx, uy = (nd.cy - gy) - bcy, uz = (nd.cz - gz) - bcz;
-        const bool overlap = fabs(ux) <= hs + bhx && fabs(uy) <= hs + bhy && fabs(uz) <= hs + bhz;
-        const R tx = fmax(fabs(ux + nd.mx) - bhx, (R)0);
-        const R ty = fmax(fabs(uy + nd.my) - bhy, (R)0);
-        const R tz = fmax(fabs(uz + nd.mz) - bhz, (R)0);
-        const R dg2 = tx * tx + ty * ty + tz * tz;
-        bool accept = !overlap && nd.l2 < theta2 * dg2;
-        if (BUDGET) accept = accept && kcv < tau_amin * (float)(dg2 * dg2 * sqrt(dg2));
-        if (accept) return kGPC;
-        return nd.next == c + 1 ? kGPP : kGOpen;
-    };
-    // particle-cell term of node nd for this lane's body
-    auto cell_term = [&](const Rec &nd) {
-        const R X = (ax - nd.cx) + ox, Y = (ay - nd.cy) + oy, Z = (az - nd.cz) + oz;
-        const R x = X - nd.mx, y = Y - nd.my, z = Z - nd.mz;
-        const R d2 = x * x + y * y + z * z;
-        const R inv = rsq(d2 + eps2);
-        const R inv2 = inv * inv;
-        const R inv3 = inv * inv2;
-        if (ORDER2) {
-            const R qzz = -nd.qxx - nd.qyy;
-            const R qx = nd.qxx * x + nd.qxy * y + nd.qxz * z;
-            const R qy = nd.qxy * x + nd.qyy * y + nd.qyz * z;
-            const R qz = nd.qxz * x + nd.qyz * y + qzz * z;
-            const R xqx = x * qx + y * qy + z * qz;
-            const R inv5 = inv3 * inv2;
-            const R t5 = xqx * inv5;
-            const R g = nd.m * inv3 + (R)2.5 * t5 * inv2;
-            sx = inv5 * qx + sx;
-            sy = inv5 * qy + sy;
-            sz = inv5 * qz + sz;
-            sx = -g * x + sx;
-            sy = -g * y + sy;
-            sz = -g * z + sz;
-            if (PHI) sp = sp - nd.m * inv - (R)0.5 * t5;
-        } else {
-            const R g = nd.m * inv3;
-            sx = -g * x + sx;
-            sy = -g * y + sy;
-            sz = -g * z + sz;
-            if (PHI) sp = sp - nd.m * inv;
-        }
-        if (CNT) ++cpc;
-        ++work;
-    };
-    // particle-cell term of a staged cell: COM relative to the group origin
-    // g, mass, quadrupole (xx xy xz yy yz zz)
-    auto staged_term = [&](const R *st) {
-        const R x = px - st[0], y = py - st[1], z = pz - st[2];
-        const R inv = rsq(z * z + (y * y + (x * x + eps2)));
-        const R inv2 = inv * inv;
-        const R inv3 = inv * inv2;
-        const R m = st[3];
-        if (ORDER2) {
-            const R qx = st[4] * x + st[5] * y + st[6] * z;
-            const R qy = st[5] * x + st[7] * y + st[8] * z;
-            const R qz = st[6] * x + st[8] * y + st[9] * z;
-            const R xqx = x * qx + y * qy + z * qz;
-            const R inv5 = inv3 * inv2;
-            const R t5 = xqx * inv5;
-            const R g = m * inv3 + (R)2.5 * t5 * inv2;
-            sx = inv5 * qx + sx;
-            sy = inv5 * qy + sy;
-            sz = inv5 * qz + sz;
-            sx = -g * x + sx;
-            sy = -g * y + sy;
-            sz = -g * z + sz;
-            if (PHI) sp = sp - m * inv - (R)0.5 * t5;
-        } else {
-            const R g = m * inv3;
-            sx = -g * x + sx;
-            sy = -g * y + sy;
-            sz = -g * z + sz;
-            if (PHI) sp = sp - m * inv;
-        }
-        if (CNT) ++cpc;
-    };
-    // particle-particle terms with the bodies of leaf (or one-body cell) nd
-    auto leaf_terms = [&](const Rec &nd) {
-        const int jb = uniform(nd.begin);
-        const int je = min(jb + uniform(nd.count), nbodies);  // guard
-        const R X = (ax - nd.cx) + ox, Y = (ay - nd.cy) + oy, Z = (az - nd.cz) + oz;
-        work += je - jb;
-        if (jb < g_end && je > base)  // holds bodies of the group: skip self
-            leaf_pp<R, PHI, CNT, true>(bodies, jb, je, i, X, Y, Z, eps2, sx, sy, sz, sp, cpp);
-        else
-            leaf_pp<R, PHI, CNT, false>(bodies, jb, je, i, X, Y, Z, eps2, sx, sy, sz, sp, cpp);
-    };
-    // the subtree below node r without the stack (overflow path)
-    auto sweep = [&](int r0) {
-        int idx = uniform(r0) + 1;
-        const int end = uniform(nodes[uniform(r0)].next);
-        while (idx < end && work <= gm.work_cap) {
-            idx = uniform(idx);
-            const Rec nd = nodes[idx];
-            const int cls = uniform(classify(nd, idx, BUDGET ? gm.kc[idx] : 0.f));
-            if (cls == kGPC) cell_term(nd);
-            else if (cls == kGPP) leaf_terms(nd);
-            const int nx = uniform(nd.next);
-            idx = cls == kGOpen || nx <= idx ? idx + 1 : nx;  // always moves forward
-        }
-    };
+        R sx = 0, sy = 0, sz = 0, sp = 0;
+        uint32_t cpp = 0, cpc = 0;
+        int work = 0;  // wave-uniform
 
-    if (nodes[0].next == 1) {  // the root is a leaf
-        leaf_terms(nodes[0]);
-    } else {
-        if (lane == 0) stk[0] = 0;
-        int top = 1;  // wave-uniform stack size
-        while (top > 0 && work <= gm.work_cap) {
-            top = uniform(top);
-            const int k = min(top, 64);
-            top -= k;
-            __builtin_amdgcn_wave_barrier();
-            const bool has = lane < k;
-            const int c = has ? stk[top + lane] : 0;
-            int cls = kGNone;
-            int4 k0 = make_int4(-1, -1, -1, -1), k1 = k0;
-            Rec nd{};
-            if (has) {
-                k0 = kids[2 * (int64_t)c];  // loaded with the record, used if opened
-                k1 = kids[2 * (int64_t)c + 1];
-                nd = nodes[c];
-                cls = classify(nd, c, BUDGET ? gm.kc[c] : 0.f);
+        // decision for node c (any lane; wave-uniform when the node is)
+        auto classify = [&](const Rec &nd, int c, float kcv) -> int {
+            if (c == 0) return kGOpen;  // the root is always opened
+            if (nd.count == 1) return kGPP;
+            const R hs = (R)0.5 * sqrt(nd.l2);
+            const R ux = (nd.cx - gx) - bcx, uy = (nd.cy - gy) - bcy, uz = (nd.cz - gz) - bcz;
+            const bool overlap = fabs(ux) <= hs + bhx && fabs(uy) <= hs + bhy && fabs(uz) <= hs + bhz;
+            const R tx = fmax(fabs(ux + nd.mx) - bhx, (R)0);
+            const R ty = fmax(fabs(uy + nd.my) - bhy, (R)0);
+            const R tz = fmax(fabs(uz + nd.mz) - bhz, (R)0);
+            const R dg2 = tx * tx + ty * ty + tz * tz;
+            bool accept = !overlap && nd.l2 < theta2 * dg2;
+            if (BUDGET) accept = accept && kcv < tau_amin * (float)(dg2 * dg2 * sqrt(dg2));
+            if (accept) return kGPC;
+            return nd.next == c + 1 ? kGPP : kGOpen;
+        };
+        // particle-cell term of node nd for this lane's body
+        auto cell_term = [&](const Rec &nd) {
+            const R X = (ax - nd.cx) + ox, Y = (ay - nd.cy) + oy, Z = (az - nd.cz) + oz;
+            const R x = X - nd.mx, y = Y - nd.my, z = Z - nd.mz;
+            const R d2 = x * x + y * y + z * z;
+            const R inv = rsq(d2 + eps2);
+            const R inv2 = inv * inv;
+            const R inv3 = inv * inv2;
+            if (ORDER2) {
+                const R qzz = -nd.qxx - nd.qyy;
+                const R qx = nd.qxx * x + nd.qxy * y + nd.qxz * z;
+                const R qy = nd.qxy * x + nd.qyy * y + nd.qyz * z;
+                const R qz = nd.qxz * x + nd.qyz * y + qzz * z;
+                const R xqx = x * qx + y * qy + z * qz;
+                const R inv5 = inv3 * inv2;
+                const R t5 = xqx * inv5;
+                const R g = nd.m * inv3 + (R)2.5 * t5 * inv2;
+                sx = inv5 * qx + sx;
+                sy = inv5 * qy + sy;
+                sz = inv5 * qz + sz;
+                sx = -g * x + sx;
+                sy = -g * y + sy;
+                sz = -g * z + sz;
+                if (PHI) sp = sp - nd.m * inv - (R)0.5 * t5;
+            } else {
+                const R g = nd.m * inv3;
+                sx = -g * x + sx;
+                sy = -g * y + sy;
+                sz = -g * z + sz;
+                if (PHI) sp = sp - nd.m * inv;
             }
-            const uint64_t m_pc = __ballot(cls == kGPC);
-            const uint64_t m_pp = __ballot(cls == kGPP);
-            const uint64_t m_op = __ballot(cls == kGOpen);
-            if (cls == kGPC) {  // stage the accepted cell for every lane
-                const int slot = (int)__builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(m_pc >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m_pc, 0u));
-                R *st = stage + kStageW * slot;
-                st[0] = (nd.cx - gx) + nd.mx;
-                st[1] = (nd.cy - gy) + nd.my;
-                st[2] = (nd.cz - gz) + nd.mz;
-                st[3] = nd.m;
-                st[4] = nd.qxx;
-                st[5] = nd.qxy;
-                st[6] = nd.qxz;
-                st[7] = nd.qyy;
-                st[8] = nd.qyz;
-                st[9] = -nd.qxx - nd.qyy;
+            if (CNT) ++cpc;
+            ++work;
+        };
+        // particle-cell term of a staged cell: COM relative to the group origin
+        // g, mass, quadrupole (xx xy xz yy yz zz)
+        auto staged_term = [&](const R *st) {
+            const R x = px - st[0], y = py - st[1], z = pz - st[2];
+            const R inv = rsq(z * z + (y * y + (x * x + eps2)));
+            const R inv2 = inv * inv;
+            const R inv3 = inv * inv2;
+            const R m = st[3];
+            if (ORDER2) {
+                const R qx = st[4] * x + st[5] * y + st[6] * z;
+                const R qy = st[5] * x + st[7] * y + st[8] * z;
+                const R qz = st[6] * x + st[8] * y + st[9] * z;
+                const R xqx = x * qx + y * qy + z * qz;
+                const R inv5 = inv3 * inv2;
+                const R t5 = xqx * inv5;
+                const R g = m * inv3 + (R)2.5 * t5 * inv2;
+                sx = inv5 * qx + sx;
+                sy = inv5 * qy + sy;
+                sz = inv5 * qz + sz;
+                sx = -g * x + sx;
+                sy = -g * y + sy;
+                sz = -g * z + sz;
+                if (PHI) sp = sp - m * inv - (R)0.5 * t5;
+            } else {
+                const R g = m * inv3;
+                sx = -g * x + sx;
+                sy = -g * y + sy;
+                sz = -g * z + sz;
+                if (PHI) sp = sp - m * inv;
             }
-            if (m_op) {
-                const int kid[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
-                int nk = 0;
-                if (cls == kGOpen) {
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) nk += kid[q] >= 0 ? 1 : 0;
+            if (CNT) ++cpc;
+        };
+        // particle-particle terms with the bodies of leaf (or one-body cell) nd
+        auto leaf_terms = [&](const Rec &nd) {
+            const int jb = uniform(nd.begin);
+            const int je = min(jb + uniform(nd.count), nbodies);  // guard
+            const R X = (ax - nd.cx) + ox, Y = (ay - nd.cy) + oy, Z = (az - nd.cz) + oz;
+            work += je - jb;
+            if (jb < g_end && je > base)  // holds bodies of the group: skip self
+                leaf_pp<R, PHI, CNT, true>(bodies, jb, je, i, X, Y, Z, eps2, sx, sy, sz, sp, cpp);
+            else
+                leaf_pp<R, PHI, CNT, false>(bodies, jb, je, i, X, Y, Z, eps2, sx, sy, sz, sp, cpp);
+        };
+        // the subtree below node r without the stack (overflow path)
+        auto sweep = [&](int r0) {
+            int idx = uniform(r0) + 1;
+            const int end = uniform(nodes[uniform(r0)].next);
+            while (idx < end && work <= gm.work_cap) {
+                idx = uniform(idx);
+                const Rec nd = nodes[idx];
+                const int cls = uniform(classify(nd, idx, BUDGET ? gm.kc[idx] : 0.f));
+                if (cls == kGPC) cell_term(nd);
+                else if (cls == kGPP) leaf_terms(nd);
+                const int nx = uniform(nd.next);
+                idx = cls == kGOpen || nx <= idx ? idx + 1 : nx;  // always moves forward
+            }
+        };
+
+        if (nodes[0].next == 1) {  // the root is a leaf
+            leaf_terms(nodes[0]);
+        } else {
+            if (lane == 0) stk[0] = 0;
+            int top = 1;  // wave-uniform stack size
+            while (top > 0 && work <= gm.work_cap) {
+                top = uniform(top);
+                const int k = min(top, 64);
+                top -= k;
+                __builtin_amdgcn_wave_barrier();
+                const bool has = lane < k;
+                const int c = has ? stk[top + lane] : 0;
+                int cls = kGNone;
+                int4 k0 = make_int4(-1, -1, -1, -1), k1 = k0;
+                Rec nd{};
+                if (has) {
+                    k0 = kids[2 * (int64_t)c];  // loaded with the record, used if opened
+                    k1 = kids[2 * (int64_t)c + 1];
+                    nd = nodes[c];
+                    cls = classify(nd, c, BUDGET ? gm.kc[c] : 0.f);
                 }
-                // exclusive prefix sum of nk (0..8) over the lanes, bit by bit
-                int excl = 0, total = 0;
-#pragma unroll
-                for (int bit = 0; bit < 4; ++bit) {
-                    const uint64_t bm = __ballot((nk >> bit) & 1);
-                    excl += (int)__builtin_amdgcn_mbcnt_hi(
-                                (uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u))
-                            << bit;
-                    total += __builtin_popcountll(bm) << bit;
+                const uint64_t m_pc = __ballot(cls == kGPC);
+                const uint64_t m_pp = __ballot(cls == kGPP);
+                const uint64_t m_op = __ballot(cls == kGOpen);
+                if (cls == kGPC) {  // stage the accepted cell for every lane
+                    const int slot = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(m_pc >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m_pc, 0u));
+                    R *st = stage + kStageW * slot;
+                    st[0] = (nd.cx - gx) + nd.mx;
+                    st[1] = (nd.cy - gy) + nd.my;
+                    st[2] = (nd.cz - gz) + nd.mz;
+                    st[3] = nd.m;
+                    st[4] = nd.qxx;
+                    st[5] = nd.qxy;
+                    st[6] = nd.qxz;
+                    st[7] = nd.qyy;
+                    st[8] = nd.qyz;
+                    st[9] = -nd.qxx - nd.qyy;
                 }
-                if (top + total <= gm.cap) {
-                    const int off = top + excl;
-                    for (int q = 0; q < nk; ++q) stk[off + q] = kid[q];
-                    top += total;
-                } else {
-                    uint64_t mm = m_op;
-                    while (mm) {
-                        const int bit = __builtin_ctzll(mm);
-                        mm &= mm - 1;
-                        sweep(__builtin_amdgcn_readlane(c, bit));
+                if (m_op) {
+                    const int kid[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+                    int nk = 0;
+                    if (cls == kGOpen) {
+    #pragma unroll
+                        for (int q = 0; q < 8; ++q) nk += kid[q] >= 0 ? 1 : 0;
+                    }
+                    // exclusive prefix sum of nk (0..8) over the lanes, bit by bit
+                    int excl = 0, total = 0;
+    #pragma unroll
+                    for (int bit = 0; bit < 4; ++bit) {
+                        const uint64_t bm = __ballot((nk >> bit) & 1);
+                        excl += (int)__builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u))
+                                << bit;
+                        total += __builtin_popcountll(bm) << bit;
+                    }
+                    if (top + total <= gm.cap) {
+                        const int off = top + excl;
+                        for (int q = 0; q < nk; ++q) stk[off + q] = kid[q];
+                        top += total;
+                    } else {
+                        uint64_t mm = m_op;
+                        while (mm) {
+                            const int bit = __builtin_ctzll(mm);
+                            mm &= mm - 1;
+                            sweep(__builtin_amdgcn_readlane(c, bit));
+                        }
                     }
                 }
-            }
-            // accepted cells from LDS (same address on every lane: broadcast)
-            const int npc_round = __builtin_popcountll(m_pc);
-            __builtin_amdgcn_wave_barrier();
-            for (int q = 0; q < npc_round; ++q) staged_term(stage + kStageW * q);
-            work += npc_round;
-            uint64_t mm = m_pp;
-            while (mm) {
-                const int bit = __builtin_ctzll(mm);
-                mm &= mm - 1;
-                leaf_terms(nodes[__builtin_amdgcn_readlane(c, bit)]);
+                // accepted cells from LDS (same address on every lane: broadcast)
+                const int npc_round = __builtin_popcountll(m_pc);
+                __builtin_amdgcn_wave_barrier();
+                for (int q = 0; q < npc_round; ++q) staged_term(stage + kStageW * q);
+                work += npc_round;
+                uint64_t mm = m_pp;
+                while (mm) {
+                    const int bit = __builtin_ctzll(mm);
+                    mm &= mm - 1;
+                    leaf_terms(nodes[__builtin_amdgcn_readlane(c, bit)]);
+                }
             }
         }
-    }
-    const bool per_body = work > gm.work_cap;
-    if (per_body) {  // too spread out for one decision: walk per body
-        sx = sy = sz = sp = 0;
-        cpp = cpc = 0;
-        const MlpMac pm{gm.kc, gm.anorm, (float)theta2, gm.tau};
-        body_sweep<R, ORDER2, PHI, CNT, BUDGET>(nodes, m, bodies, nbodies, i, live, ox, oy, oz,
-                                                ax, ay, az, myleaf, theta2, eps2, pm, sx, sy, sz,
-                                                sp, cpp, cpc);
-    }
-    if (live) {
-        const int o = SORTED_OUT ? i : (int)perm[i];
-        acc[3 * (int64_t)o + 0] = sx;
-        acc[3 * (int64_t)o + 1] = sy;
-        acc[3 * (int64_t)o + 2] = sz;
-        if (PHI) phi_out[o] = sp;
-        if (CNT) {
-            npp_out[o] = cpp;
-            npc_out[o] = cpc;
+        const bool per_body = work > gm.work_cap;
+        if (per_body) {  // too spread out for one decision: walk per body
+            sx = sy = sz = sp = 0;
+            cpp = cpc = 0;
+            const MlpMac pm{gm.kc, gm.anorm, (float)theta2, gm.tau};
+            body_sweep<R, ORDER2, PHI, CNT, BUDGET>(nodes, m, bodies, nbodies, i, live_run, ox, oy, oz,
+                                                    ax, ay, az, myleaf, theta2, eps2, pm, sx, sy, sz,
+                                                    sp, cpp, cpc);
         }
+        if (live_run) {
+            const int o = SORTED_OUT ? i : (int)perm[i];
+            acc[3 * (int64_t)o + 0] = sx;
+            acc[3 * (int64_t)o + 1] = sy;
+            acc[3 * (int64_t)o + 2] = sz;
+            if (PHI) phi_out[o] = sp;
+            if (CNT) {
+                npp_out[o] = cpp;
+                npc_out[o] = cpc;
+            }
+        }
+    };
+
+    int lo = 0;
+    while (lo < nlive) {
+        int hi = nlive;
+        while (hi - lo >= 2) {
+            const int kanc = wave_min_i(lane > lo && lane < hi ? dl : 127);
+            const int kleaf = wave_min_i(lane >= lo && lane < hi ? lv : 127);
+            if (kanc >= kleaf - 2) break;
+            const uint64_t at = __ballot(lane > lo && lane < hi && dl == kanc);
+            hi = __builtin_ctzll(at);
+        }
+        pass(lo, hi);
+        lo = hi;
     }
 }
 
@@ -604,7 +617,7 @@ __global__ __launch_bounds__(256) void k_gwalk(
     const int4 *__restrict__ kids, const uint32_t *__restrict__ perm, int nbodies, int t0,
     int t1, uint32_t *__restrict__ queue, R theta2, R eps2, R *__restrict__ acc,
     R *__restrict__ phi_out, uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out,
-    GroupMac gm) {
+    GroupMac gm, const int8_t *__restrict__ delta, const int32_t *__restrict__ level) {
     __shared__ int stack_all[4][kGroupStack];
     __shared__ R stage_all[4][64 * kStageW];
     int *stk = stack_all[threadIdx.x >> 6];
@@ -622,7 +635,7 @@ __global__ __launch_bounds__(256) void k_gwalk(
         const int g = gm.gorder ? (int)gm.gorder[gi] : gi;
         group_walk<R, ORDER2, PHI, CNT, SORTED_OUT, BUDGET>(
             nodes, m, bodies, anchors, kids, perm, nbodies, t0 + 64 * g, t1, theta2, eps2, acc,
-            phi_out, npp_out, npc_out, gm, stk, stage);
+            phi_out, npp_out, npc_out, gm, stk, stage, delta, level);
     }
 }
 
@@ -700,7 +713,8 @@ void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, vo
         (const typename NodeRecT<R>::type *)t->recs.p, (int)t->m,
         (const BodyRec<R> *)t->bodies.p, (const Anchor<R> *)t->anchors.p,
         (const int4 *)t->kids.p, t->perm, (int)t->n, t0, t1, queue, (R)(theta * theta),
-        (R)(eps * eps), (R *)acc, (R *)phi, npp, npc, g2);
+        (R)(eps * eps), (R *)acc, (R *)phi, npp, npc, g2, (const int8_t *)t->delta.p,
+        (const int32_t *)t->level.p);
 }
 
 template <typename R, bool ORDER2, bool BUDGET>
@@ -718,16 +732,11 @@ void gdispatch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, 
 #undef BH_G
 }
 
-// child table of the tree, built once per tree build
+// group-walk state of the tree (the child table comes with every build)
 int ensure_kids(bh_tree *t) {
     int rc = grow(t->wq, 8 * 256);  // group queue counters
     if (rc) return rc;
-    if (t->kids_tree_id == t->build_id) return BH_OK;
-    if ((rc = grow(t->kids, 32ull * t->m))) return rc;
-    k_kids<<<div_up((int)t->m, 256), 256, 0, t->ctx->stream>>>(
-        (int)t->m, (const int32_t *)t->next.p, (int32_t *)t->kids.p);
-    if ((rc = check_launch("child table"))) return rc;
-    t->kids_tree_id = t->build_id;
+    if (t->kids_tree_id != t->build_id) return set_error(BH_E_STATE, "tree has no child table");
     return BH_OK;
 }
 

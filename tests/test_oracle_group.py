@@ -50,7 +50,7 @@ def test_every_body_accounted_once_and_groups_only_tighten():
         return np.sqrt(np.mean(e * e))
     prev = None
     for G in (1, 8, 64):
-        g = oracle.walk_group(bb, 0.01, group=G, theta=0.55)
+        g = oracle.walk_group(bb, 0.01, group=G, theta=0.55, split=False)
         assert np.all(g.ncov == n - 1)
         if prev is not None:
             assert np.all(g.npp + g.npc >= 0)
@@ -64,7 +64,7 @@ def test_one_group_holding_everything_is_the_direct_sum():
     """A single group whose box covers every cell opens everything: the
     direct sum, particle-particle only."""
     b, bb = _tree(700, 6)
-    g = oracle.walk_group(bb, 0.02, group=700, theta=0.9)
+    g = oracle.walk_group(bb, 0.02, group=700, theta=0.9, split=False)
     d, phi = oracle.direct(bb["spos"], bb["smass"], 0.02)
     assert np.all(g.npc == 0) and np.all(g.npp == 699)
     np.testing.assert_allclose(g.acc, d, rtol=1e-12, atol=1e-14)
@@ -115,23 +115,23 @@ def test_work_cap_falls_back_to_the_per_body_walk():
     b, bb = _tree(5000, 8, 8, "clumpy")
     theta = 0.5
     w = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], theta, 0.01)
-    g = oracle.walk_group(bb, 0.01, group=64, theta=theta, cap=1)
+    g = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False, cap=1)
     np.testing.assert_array_equal(g.npc, w.npc)
     np.testing.assert_allclose(g.acc, w.acc, rtol=1e-13, atol=0)
     kc = oracle.cell_kc(bb, 0.01)
     an = np.linalg.norm(w.acc, axis=1)
     gb = oracle.walk_group(bb, 0.01, group=64, mode=1, theta_max=0.9, tau=1e-2, kc=kc,
-                           anorm=an, cap=1)
+                           anorm=an, cap=1, split=False)
     wb = oracle.walk_kc(bb, 0.01, 0.9, 1e-2, kc, an)
     np.testing.assert_array_equal(gb.npp, wb.npp)
     np.testing.assert_allclose(gb.acc, wb.acc, rtol=1e-13, atol=0)
-    big = oracle.walk_group(bb, 0.01, group=64, theta=theta, cap=1 << 62)
-    dflt = oracle.walk_group(bb, 0.01, group=64, theta=theta)
-    capd = oracle.walk_group(bb, 0.01, group=64, theta=theta, cap=oracle.GROUP_WORK_CAP)
+    big = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False, cap=1 << 62)
+    dflt = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False)
+    capd = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False, cap=oracle.GROUP_WORK_CAP)
     np.testing.assert_array_equal(dflt.npc, capd.npc)
     # the cap splits groups by their work: each group either keeps the group
     # walk or takes the per-body counts
-    mid = oracle.walk_group(bb, 0.01, group=64, theta=theta, cap=3000)
+    mid = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False, cap=3000)
     # (a group's work is npp + npc + 1 for each of its bodies: the body's
     # own particle-particle cell counts it too)
     work = big.npp + big.npc + 1
@@ -143,3 +143,50 @@ def test_work_cap_falls_back_to_the_per_body_walk():
         fell += work[k0] > 3000
         np.testing.assert_array_equal(mid.npc[sl], src.npc[sl])
     assert 0 < fell < 5000 // 64
+
+
+def _fill(rng, lo, hi, hole_lo, hole_hi, n):
+    """n points uniform in the cube [lo, hi)^3 outside [hole_lo, hole_hi)^3."""
+    out = []
+    while len(out) < n:
+        p = lo + (hi - lo) * rng.random(3)
+        if not np.all((p >= hole_lo) & (p < hole_hi)):
+            out.append(p)
+    return np.array(out)
+
+
+def test_split_cuts_a_straddling_group_at_the_jump():
+    """Two clusters of 8 bodies, at the upper corner of the root's first
+    octant and the lower corner of its last, are consecutive on the
+    space-filling curve; filler bodies around them make their leaves deep
+    (level 5 or more).  As one group of 16 their common cell is the root, more than
+    two levels above their leaves, so the group is cut exactly between the
+    clusters and each half is walked as a group of its own.  A cluster
+    alone is not cut."""
+    rng = np.random.default_rng(9)
+    a = 0.497 + 0.0025 * rng.random((8, 3))          # octant 0, upper corner
+    c = 0.5005 + 0.0025 * rng.random((8, 3))         # octant 7, lower corner
+    fa = _fill(rng, 0.375, 0.5, 0.49, 0.5, 300)       # before a on the curve
+    fc = _fill(rng, 0.5, 0.625, 0.5, 0.51, 300)       # after c
+    pos = np.concatenate([a, c, fa, fc, [[0.01, 0.01, 0.01], [0.99, 0.99, 0.99]]])
+    mass = np.full(len(pos), 1.0 / len(pos))
+    bb = oracle.build_all(pos, mass, 8)
+    rank = np.empty(len(pos), dtype=np.int64)
+    rank[bb["perm"]] = np.arange(len(pos))
+    ra, rc = np.sort(rank[:8]), np.sort(rank[8:16])
+    assert ra[-1] + 1 == rc[0]                          # adjacent on the curve
+    lv = oracle.leaf_levels(bb)
+    assert lv[ra].min() >= 5 and lv[rc].min() >= 5           # deep leaves
+    g0 = ra[0]
+    kw = dict(group=16, theta=0.6)
+    sp = oracle.walk_group(bb, 0.0, target_range=(g0, g0 + 16), **kw)
+    nosp = oracle.walk_group(bb, 0.0, target_range=(g0, g0 + 16), split=False, **kw)
+    h1 = oracle.walk_group(bb, 0.0, target_range=(g0, g0 + 8), split=False, **kw)
+    h2 = oracle.walk_group(bb, 0.0, target_range=(g0 + 8, g0 + 16), split=False, **kw)
+    np.testing.assert_array_equal(sp.npc, np.concatenate([h1.npc, h2.npc]))
+    np.testing.assert_array_equal(sp.npp, np.concatenate([h1.npp, h2.npp]))
+    np.testing.assert_allclose(sp.acc, np.concatenate([h1.acc, h2.acc]), rtol=1e-14, atol=0)
+    assert (sp.npp + sp.npc).sum() < (nosp.npp + nosp.npc).sum()
+    # one cluster as its own group: no cut
+    one = oracle.walk_group(bb, 0.0, target_range=(g0, g0 + 8), **kw)
+    np.testing.assert_array_equal(one.npc, h1.npc)

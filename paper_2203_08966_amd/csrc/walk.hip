@@ -51,20 +51,21 @@ __device__ __forceinline__ void leaf_pp(const BodyRec<R> *__restrict__ bodies, i
                                         R &sp, uint32_t &cpp) {
     R px = 0, py = 0, pz = 0, pq = 0;
     auto term = [&](const BodyRec<R> &s, int j) {
-        if (!SELF || j != i) {
-            const R dx = s.x - X, dy = s.y - Y, dz = s.z - Z;
-            R r2 = dx * dx + eps2;
-            r2 = dy * dy + r2;
-            r2 = dz * dz + r2;
-            const R inv = rsq(r2);
-            const R minv = s.m * inv;
-            const R mi3 = minv * (inv * inv);
-            px += mi3 * dx;
-            py += mi3 * dy;
-            pz += mi3 * dz;
-            if (PHI) pq -= minv;
-            if (CNT && SELF) ++cpp;
-        }
+        // the lane's own body (SELF) contributes nothing: a select, not a
+        // branch, so that the wave stays convergent
+        const R dx = s.x - X, dy = s.y - Y, dz = s.z - Z;
+        R r2 = dx * dx + eps2;
+        r2 = dy * dy + r2;
+        r2 = dz * dz + r2;
+        R inv = rsq(r2);
+        if (SELF) inv = j != i ? inv : (R)0;
+        const R minv = s.m * inv;
+        const R mi3 = minv * (inv * inv);
+        px += mi3 * dx;
+        py += mi3 * dy;
+        pz += mi3 * dz;
+        if (PHI) pq -= minv;
+        if (CNT && SELF) cpp += j != i ? 1u : 0u;
     };
     int j = jb;
     for (; j + 4 <= je; j += 4) {  // four uniform loads in flight, then the terms in order
@@ -431,26 +432,24 @@ __device__ __forceinline__ void group_walk(
         // g, mass, quadrupole (xx xy xz yy yz zz)
         auto staged_term = [&](const R *st) {
             const R x = px - st[0], y = py - st[1], z = pz - st[2];
-            const R inv = rsq(z * z + (y * y + (x * x + eps2)));
+            const R s2 = z * z + (y * y + (x * x + eps2));
+            const R inv = rsq(s2);
             const R inv2 = inv * inv;
-            const R inv3 = inv * inv2;
             const R m = st[3];
             if (ORDER2) {
+                // a = inv^5 (Q x - (m s^2 + 5/2 (x.Q.x)/s^2) x)
                 const R qx = st[4] * x + st[5] * y + st[6] * z;
                 const R qy = st[5] * x + st[7] * y + st[8] * z;
                 const R qz = st[6] * x + st[8] * y + st[9] * z;
                 const R xqx = x * qx + y * qy + z * qz;
-                const R inv5 = inv3 * inv2;
-                const R t5 = xqx * inv5;
-                const R g = m * inv3 + (R)2.5 * t5 * inv2;
-                sx = inv5 * qx + sx;
-                sy = inv5 * qy + sy;
-                sz = inv5 * qz + sz;
-                sx = -g * x + sx;
-                sy = -g * y + sy;
-                sz = -g * z + sz;
-                if (PHI) sp = sp - m * inv - (R)0.5 * t5;
+                const R inv5 = inv * (inv2 * inv2);
+                const R c = m * s2 + ((R)2.5 * inv2) * xqx;
+                sx = inv5 * (qx - c * x) + sx;
+                sy = inv5 * (qy - c * y) + sy;
+                sz = inv5 * (qz - c * z) + sz;
+                if (PHI) sp = sp - m * inv - (R)0.5 * (xqx * inv5);
             } else {
+                const R inv3 = inv * inv2;
                 const R g = m * inv3;
                 sx = -g * x + sx;
                 sy = -g * y + sy;

@@ -285,7 +285,7 @@ def main():
         "dtype": "f32" if dtype == torch.float32 else "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{cfg['workload']} N={n} (equal masses, G=M=a=1, seed {cfg['seed']})",
+            "workload": result_workload(cfg, n),
             "n": n, "eps": eps, "leaf": leaf, "order": order, "dt": dt,
             "method": chosen, PARAM_NAME[chosen]: cp,
             "step": "KDK leapfrog step: kick+drift, rebuild, walk, kick, energy",
@@ -302,7 +302,8 @@ def main():
         "roofline": {
             "bound": "alu", "kernel": f"{kernel} (FP32, quadrupole)",
             "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": traffic_for(kernel, cfg),
+            "frac": achieved_tf / PEAK_FP32_TFLOPS,
+            "traffic": traffic_for(kernel, result_workload(cfg, n)),
             "flop_per_launch": flops, "launch_ms": walk_step_ms,
         },
     }
@@ -314,7 +315,11 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def traffic_for(kernel, cfg):
+def result_workload(cfg, n):
+    return f"{cfg['workload']} N={n} (equal masses, G=M=a=1, seed {cfg['seed']})"
+
+
+def traffic_for(kernel, workload):
     """HBM bytes per launch of the timed walk kernel from the committed
     rocprofv3 counter summary, if it was taken on this workload with the
     current walk source; else None."""
@@ -327,7 +332,7 @@ def traffic_for(kernel, cfg):
     except (OSError, ValueError):
         return None
     k = rec.get("kernels", {}).get(kernel)
-    if not k or rec.get("walk_hip_sha256") != sha or rec.get("workload") != cfg["workload"]:
+    if not k or rec.get("walk_hip_sha256") != sha or rec.get("workload") != workload:
         return None
     return k["hbm_bytes_per_launch"]
 

@@ -20,14 +20,15 @@
 //  7. pack                 FP32/FP64 walk records and leaf-relative bodies
 #include <float.h>
 #include <math.h>
+#include <string.h>
 
 #include "bh_internal.h"
 
 namespace bh {
 namespace {
 
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortThreads = 1024;
+constexpr int kSortItems = 4;
 constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys
 constexpr int kWaveTile = 64 * kSortItems;            // 1024 keys per wave
 constexpr int kScanItems = 8;
@@ -53,8 +54,7 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 // ------------------------------------------------------------------ 1. bbox
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_bbox(const T *__restrict__ pos, int n,
-                                                   double *__restrict__ part,
-                                                   uint32_t *__restrict__ flags) {
+                                                   double *__restrict__ part) {
     double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
     bool bad = false;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -81,27 +81,41 @@ __global__ __launch_bounds__(kThreads) void k_bbox(const T *__restrict__ pos, in
             sh[3 + d][w] = mx[d];
         }
     }
-    if (ballot(bad) != 0 && lane_id() == 0) atomicOr(flags, 1u);
+    __shared__ int bad_s;
+    if (threadIdx.x == 0) bad_s = 0;
+    __syncthreads();
+    if (ballot(bad) != 0 && lane_id() == 0) bad_s = 1;
     __syncthreads();
     if (threadIdx.x < 6) {
         const int d = threadIdx.x;
         double v = sh[d][0];
         for (int k = 1; k < kThreads / 64; ++k) v = d < 3 ? fmin(v, sh[d][k]) : fmax(v, sh[d][k]);
-        part[6 * blockIdx.x + d] = v;
+        part[7 * blockIdx.x + d] = v;
     }
+    if (threadIdx.x == 6) part[7 * blockIdx.x + 6] = bad_s ? 1.0 : 0.0;
 }
 
-// One block: reduce the partials and snap the root cube.  Same rule as the
+// One block: reduce the partials and snap the root cube; also starts the
+// build's flags word (bit 0: a non-finite position).  Same rule as the
 // method's definition: smallest power-of-two side L such that, with the
 // corner at floor(min / (L/2)) * (L/2), max < corner + L in every axis.
 __global__ __launch_bounds__(kThreads) void k_cube(const double *__restrict__ part, int np,
-                                                   Cube *__restrict__ cube) {
+                                                   Cube *__restrict__ cube,
+                                                   Cube *__restrict__ mirror,
+                                                   uint32_t *__restrict__ flags) {
     double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
-    for (int b = threadIdx.x; b < np; b += blockDim.x)
+    bool bad = false;
+    for (int b = threadIdx.x; b < np; b += blockDim.x) {
         for (int d = 0; d < 3; ++d) {
-            mn[d] = fmin(mn[d], part[6 * b + d]);
-            mx[d] = fmax(mx[d], part[6 * b + 3 + d]);
+            mn[d] = fmin(mn[d], part[7 * b + d]);
+            mx[d] = fmax(mx[d], part[7 * b + 3 + d]);
         }
+        bad |= part[7 * b + 6] != 0.0;
+    }
+    __shared__ int bad_s;
+    if (threadIdx.x == 0) bad_s = 0;
+    __syncthreads();
+    if (ballot(bad) != 0 && lane_id() == 0) bad_s = 1;
     for (int d = 0; d < 3; ++d)
         for (int o = 32; o > 0; o >>= 1) {
             mn[d] = fmin(mn[d], __shfl_xor(mn[d], o));
@@ -116,6 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_cube(const double *__restrict__ pa
         }
     __syncthreads();
     if (threadIdx.x == 0) {
+        *flags = bad_s ? 1u : 0u;
         for (int d = 0; d < 3; ++d) {
             for (int k = 1; k < kThreads / 64; ++k) {
                 sh[d][0] = fmin(sh[d][0], sh[d][k]);
@@ -143,8 +158,8 @@ __global__ __launch_bounds__(kThreads) void k_cube(const double *__restrict__ pa
             if (ok) break;
             L *= 2.0;
         }
-        for (int d = 0; d < 3; ++d) cube->lo[d] = lo[d];
-        cube->L = L;
+        for (int d = 0; d < 3; ++d) cube->lo[d] = mirror->lo[d] = lo[d];
+        cube->L = mirror->L = L;
     }
 }
 
@@ -175,17 +190,22 @@ __device__ __forceinline__ uint32_t quantise(double x, double lo, double scale) 
     return (uint32_t)f;
 }
 
-// Keys, and the counts of every 8-bit digit of every key (8 x 256 bins).
+// Keys, and the counts of every 8-bit digit of every key (8 x 256 bins):
+// a block histogram in LDS, added to the global one bin by bin.  Few large
+// blocks keep the global adds few.
+constexpr int kKeyThreads = 1024;
+constexpr int kKeyBlocks = 256;
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_keys(const T *__restrict__ pos, int n,
-                                                   const Cube *__restrict__ cube,
-                                                   uint64_t *__restrict__ keys,
-                                                   uint32_t *__restrict__ hist) {
+__global__ __launch_bounds__(kKeyThreads) void k_keys(const T *__restrict__ pos, int n,
+                                                      const Cube *__restrict__ cube,
+                                                      uint64_t *__restrict__ keys,
+                                                      uint32_t *__restrict__ hist) {
     __shared__ uint32_t h[8][256];
     for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
     __syncthreads();
     const double lx = cube->lo[0], ly = cube->lo[1], lz = cube->lo[2];
     const double scale = ldexp(1.0, kLevels) / cube->L;
+    const unsigned lane = lane_id();
     const int stride = gridDim.x * blockDim.x;
     const int iters = (n + stride - 1) / stride;
     for (int it = 0; it < iters; ++it) {
@@ -203,13 +223,17 @@ __global__ __launch_bounds__(kThreads) void k_keys(const T *__restrict__ pos, in
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
             const uint32_t d = (uint32_t)(k >> (8 * p)) & 255u;
-            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-            const uint64_t same = ballot(valid && d == d0);
-            if (same == live) {  // whole wave on one bin: one add
-                if (rank_in(live) == 0 && valid) atomicAdd(&h[p][d0], (uint32_t)__popcll(live));
-            } else if (valid) {
-                atomicAdd(&h[p][d], 1u);
+            // neighbouring bodies (input in curve order) share most digits:
+            // up to two distinct digit values are counted with one add each
+            uint64_t rem = live;
+            for (int r = 0; r < 2 && rem; ++r) {
+                const int l0 = __builtin_ctzll(rem);
+                const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, l0);
+                const uint64_t same = ballot(d == d0) & rem;
+                if ((int)lane == l0) atomicAdd(&h[p][d0], (uint32_t)__popcll(same));
+                rem &= ~same;
             }
+            if ((rem >> lane) & 1ull) atomicAdd(&h[p][d], 1u);
         }
     }
     __syncthreads();
@@ -220,13 +244,16 @@ __global__ __launch_bounds__(kThreads) void k_keys(const T *__restrict__ pos, in
 }
 
 // Exclusive scan of each pass's 256-bin histogram (8 blocks x 256 threads);
-// also clears the per-pass tile counters.
-__global__ __launch_bounds__(256) void k_hist_scan(const uint32_t *__restrict__ hist,
+// also clears the per-pass tile counters, and the histogram for the next
+// build.
+__global__ __launch_bounds__(256) void k_hist_scan(uint32_t *__restrict__ hist,
                                                    uint32_t *__restrict__ off,
                                                    uint32_t *__restrict__ tile_ctr) {
     __shared__ uint32_t s[256];
     const int p = blockIdx.x, t = threadIdx.x;
-    s[t] = hist[256 * p + t];
+    const uint32_t own = hist[256 * p + t];
+    hist[256 * p + t] = 0u;
+    s[t] = own;
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
         uint32_t v = t >= o ? s[t - o] : 0u;
@@ -234,7 +261,7 @@ __global__ __launch_bounds__(256) void k_hist_scan(const uint32_t *__restrict__ 
         s[t] += v;
         __syncthreads();
     }
-    off[256 * p + t] = s[t] - hist[256 * p + t];
+    off[256 * p + t] = s[t] - own;
     if (t == 0) tile_ctr[p] = 0;
 }
 
@@ -299,25 +326,28 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
         if (valid && r == 0) hist[wave][d] = c + (uint32_t)__popcll(m);
     }
     __syncthreads();
-    // per digit: prefix over waves, tile total
-    uint32_t tot = 0;
-    for (int w = 0; w < kSortThreads / 64; ++w) {
-        const uint32_t c = hist[w][t];
-        hist[w][t] = tot;
-        tot += c;
+    // digit phase: thread t < 256 (the first four waves) owns digit t
+    const bool dig = t < 256;
+    uint32_t tot = 0, incl = 0, excl = 0;
+    if (dig) {
+        // per digit: prefix over waves, tile total
+        for (int w = 0; w < kSortThreads / 64; ++w) {
+            const uint32_t c = hist[w][t];
+            hist[w][t] = tot;
+            tot += c;
+        }
+        // exclusive scan of tile totals over digits
+        incl = tot;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o);
+            if ((int)lane >= o) incl += v;
+        }
+        if (lane == 63) wsum[wave] = incl;
     }
-    // exclusive scan of tile totals over digits
-    uint32_t incl = tot;
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t v = __shfl_up(incl, o);
-        if ((int)lane >= o) incl += v;
-    }
-    if (lane == 63) wsum[wave] = incl;
     // look-back for digit t
-    unsigned long long *my = status + (size_t)tile * 256 + t;
-    st_status(my, epoch, tile == 0 ? 2u : 1u, tot);
-    uint32_t excl = 0;
-    if (tile > 0) {
+    unsigned long long *my = status + (size_t)tile * 256 + (dig ? t : 0);
+    if (dig) st_status(my, epoch, tile == 0 ? 2u : 1u, tot);
+    if (dig && tile > 0) {
         int j = tile - 1;
         for (;;) {
             const unsigned long long v = __hip_atomic_load(status + (size_t)j * 256 + t,
@@ -335,11 +365,13 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
         st_status(my, epoch, 2u, excl + tot);
     }
     __syncthreads();
-    uint32_t wpre = 0;
-    for (int w = 0; w < wave; ++w) wpre += wsum[w];
-    const uint32_t ts = wpre + incl - tot;
-    tstart[t] = ts;
-    gbase[t] = (int32_t)(digit_off[t] + excl) - (int32_t)ts;
+    if (dig) {
+        uint32_t wpre = 0;
+        for (int w = 0; w < wave; ++w) wpre += wsum[w];
+        const uint32_t ts = wpre + incl - tot;
+        tstart[t] = ts;
+        gbase[t] = (int32_t)(digit_off[t] + excl) - (int32_t)ts;
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
@@ -394,18 +426,12 @@ __global__ __launch_bounds__(kThreads) void k_gather(int n, uint32_t *__restrict
 }
 
 // ------------------------------------------------------------------ 5. topology
-// delta[i] = number of leading octal digits shared by keys i-1 and i
-// (21 when equal); delta[0] = delta[n] = -1.
-__global__ __launch_bounds__(kThreads) void k_delta(const uint64_t *__restrict__ keys, int n,
-                                                    int8_t *__restrict__ delta) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > n) return;
-    int d = -1;
-    if (i > 0 && i < n) {
-        const uint64_t x = keys[i - 1] ^ keys[i];
-        d = x ? (__clzll(x) - 1) / 3 : kLevels;
-    }
-    delta[i] = (int8_t)d;
+// Number of leading octal digits shared by the keys of ranks i-1 and i
+// (21 when equal); -1 at i = 0 and i = n.
+__device__ __forceinline__ int key_delta(const uint64_t *__restrict__ keys, int n, int i) {
+    if (i <= 0 || i >= n) return -1;
+    const uint64_t x = keys[i - 1] ^ keys[i];
+    return x ? (__clzll(x) - 1) / 3 : kLevels;
 }
 
 // Chain length of every sorted rank s: the cells whose first body is s.
@@ -414,8 +440,11 @@ __global__ __launch_bounds__(kThreads) void k_delta(const uint64_t *__restrict__
 // split); k_leaf is the first level at which the cell starting at s holds
 // at most B bodies (or 21).  Also, per block, the sum of chain lengths and
 // the number of cells at every level: bsum[b] and bsum[(1 + k) * nb + b].
-__global__ __launch_bounds__(kThreads) void k_chain(const int8_t *__restrict__ delta, int n,
-                                                    int B, uint8_t *__restrict__ ns,
+// delta (n + 1 entries) is computed here from the sorted keys and stored
+// for the later steps.
+__global__ __launch_bounds__(kThreads) void k_chain(const uint64_t *__restrict__ keys, int n,
+                                                    int B, int8_t *__restrict__ delta,
+                                                    uint8_t *__restrict__ ns,
                                                     uint32_t *__restrict__ bsum) {
     __shared__ int8_t sd[kThreads + 2 * (kMaxLeaf + 1) + 1];
     __shared__ uint32_t ws[kThreads / 64];
@@ -424,12 +453,12 @@ __global__ __launch_bounds__(kThreads) void k_chain(const int8_t *__restrict__ d
     if (threadIdx.x <= kLevels) lh[threadIdx.x] = 0;
     const int b0 = blockIdx.x * kThreads;
     // sd[k] = delta[b0 - H + k]
-    for (int k = threadIdx.x; k < kThreads + 2 * H + 1; k += kThreads) {
-        const int g = b0 - H + k;
-        sd[k] = (g >= 0 && g <= n) ? delta[g] : (int8_t)-1;
-    }
+    for (int k = threadIdx.x; k < kThreads + 2 * H + 1; k += kThreads)
+        sd[k] = (int8_t)key_delta(keys, n, b0 - H + k);
     __syncthreads();
     const int s = b0 + threadIdx.x;
+    if (s < n) delta[s] = sd[threadIdx.x + H];
+    if (s == n - 1) delta[n] = -1;
     uint32_t cnt_s = 0;
     if (s < n) {
         const int L = threadIdx.x + H;  // local index of s
@@ -511,7 +540,8 @@ __global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *__restrict__ sums,
 // offs[s] = exclusive prefix of ns over ranks; offs[n] = node count.
 __global__ __launch_bounds__(kThreads) void k_scan_down(const uint8_t *__restrict__ ns, int n,
                                                         const uint32_t *__restrict__ bpre,
-                                                        int32_t *__restrict__ offs) {
+                                                        int32_t *__restrict__ offs,
+                                                        uint32_t *__restrict__ total) {
     __shared__ uint32_t ws[kThreads / 64];
     const int s = blockIdx.x * kThreads + threadIdx.x;
     const uint32_t x = s < n ? ns[s] : 0u;
@@ -527,7 +557,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint8_t *__restric
     uint32_t pre = bpre[blockIdx.x];
     for (int k = 0; k < w; ++k) pre += ws[k];
     if (s < n) offs[s] = (int32_t)(pre + incl - x);
-    if (s == n - 1) offs[n] = (int32_t)(pre + incl);
+    if (s == n - 1) {
+        offs[n] = (int32_t)(pre + incl);
+        *total = pre + incl;
+    }
 }
 
 // First rank in (s, hi) whose key prefix (key >> shift) differs from pre;
@@ -572,55 +605,66 @@ struct LevelBase {
 
 // Writes every cell in pre-order: hashed key, level, body range, skip
 // pointer, parent and integer centre, and lists it under its level.
+// Block b covers ranks [256 b, 256 b + 256) and the cells of their chains,
+// one thread per cell (a chain's cells are independent: each finds its own
+// segment end), so a long chain of shallow cells is spread over threads.
 // Block b places its level-k cells after those of blocks < b (scanned
 // per-block level counts in lvl_pre[(1 + k) * nb + b]).
 __global__ __launch_bounds__(kThreads) void k_emit(
     const uint64_t *__restrict__ keys, const int8_t *__restrict__ delta,
-    const uint8_t *__restrict__ ns, const int32_t *__restrict__ offs, int n, int m,
+    const int32_t *__restrict__ offs, int n, int m,
     const uint32_t *__restrict__ lvl_pre, LevelBase lb, uint64_t *__restrict__ hkey,
     int32_t *__restrict__ level, int32_t *__restrict__ begin, int32_t *__restrict__ count,
     int32_t *__restrict__ next, int32_t *__restrict__ parent, int32_t *__restrict__ cx,
     int32_t *__restrict__ cy, int32_t *__restrict__ cz, int32_t *__restrict__ lvl_list) {
     __shared__ uint32_t lcnt[kLevels + 1];
     __shared__ int32_t lbase[kLevels + 1];
+    __shared__ int32_t so[kThreads + 1];  // first cell of each rank's chain
     if (threadIdx.x <= kLevels) {
         lcnt[threadIdx.x] = 0;
         lbase[threadIdx.x] = lb.base[threadIdx.x] +
                              (int32_t)lvl_pre[(size_t)(1 + threadIdx.x) * gridDim.x + blockIdx.x];
     }
-    __syncthreads();
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int cnt = ns[s];
-    if (cnt == 0) return;
-    const int ds = delta[s];
-    const uint64_t key = keys[s];
-    const uint32_t qx = compact3(key >> 2), qy = compact3(key >> 1), qz = compact3(key);
-    const int o = offs[s];
-    int par = -1;
-    if (s > 0) {
-        const int sh = 3 * (kLevels - ds);
-        const uint64_t pre = ds > 0 ? key >> sh : 0ull;
-        const int a = ds > 0 ? seg_begin(keys, s, sh, pre) : 0;
-        const int da = delta[a];
-        par = offs[a] + (ds - (da + 1));
+    const int b0 = blockIdx.x * kThreads;
+    {
+        const int r = b0 + threadIdx.x;
+        so[threadIdx.x] = offs[r < n ? r : n];
+        if (threadIdx.x == 0) so[kThreads] = offs[b0 + kThreads < n ? b0 + kThreads : n];
     }
-    int hi = n;
-    for (int t = 0; t < cnt; ++t) {
+    __syncthreads();
+    const int c1 = so[kThreads] < m ? so[kThreads] : m;
+    for (int node = so[0] + threadIdx.x; node < c1; node += kThreads) {
+        // the rank whose chain holds node: the last local r with so[r] <= node
+        int lo = 0, hi = kThreads;  // so[lo] <= node < so[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (so[mid] <= node) lo = mid;
+            else hi = mid;
+        }
+        const int s = b0 + lo;
+        const int t = node - so[lo];
+        const int ds = delta[s];
+        const uint64_t key = keys[s];
         const int k = ds + 1 + t;
-        const int node = o + t;
-        if (node >= m) break;  // guard
         const int sh = 3 * (kLevels - k);
         const uint64_t pre = k > 0 ? key >> sh : 0ull;
-        const int e = k > 0 ? seg_end(keys, s, hi, sh, pre) : n;
-        hi = e;
+        const int e = k > 0 ? seg_end(keys, s, n, sh, pre) : n;
+        int par = -1;
+        if (t > 0) {
+            par = node - 1;
+        } else if (s > 0) {
+            const int shp = 3 * (kLevels - ds);
+            const uint64_t prep = ds > 0 ? key >> shp : 0ull;
+            const int a = ds > 0 ? seg_begin(keys, s, shp, prep) : 0;
+            par = offs[a] + (ds - (delta[a] + 1));
+        }
+        const uint32_t qx = compact3(key >> 2), qy = compact3(key >> 1), qz = compact3(key);
         hkey[node] = (1ull << (3 * k)) | pre;
         level[node] = k;
         begin[node] = s;
         count[node] = e - s;
         next[node] = offs[e];
-        const int p = t > 0 ? node - 1 : par;
-        parent[node] = p < m ? p : -1;
+        parent[node] = par < m ? par : -1;
         const int cs = kLevels - k;
         cx[node] = (int32_t)(((qx >> cs) * 2u + 1u) << cs);
         cy[node] = (int32_t)(((qy >> cs) * 2u + 1u) << cs);
@@ -631,27 +675,63 @@ __global__ __launch_bounds__(kThreads) void k_emit(
 }
 
 // ------------------------------------------------------------------ 6. upward pass
-// Leaves: moments straight from their bodies, about the leaf centre.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_up_leaves(
+// One thread per node.  Every node: its children, in pre-order (= octant
+// order), from the skip pointers: kids[8 c + q] for q < #children, then -1
+// (the upward pass and the group walk read a node's children from here in
+// one load).  Leaves also: FP64 moments straight from their bodies, about
+// the leaf centre, and the walk's body records (offset from the leaf centre,
+// computed in FP64, and mass) with the leaf centre as each body's anchor.
+template <typename T, typename R>
+__global__ __launch_bounds__(kThreads) void k_leaves(
     int m, const int32_t *__restrict__ begin, const int32_t *__restrict__ count,
     const int32_t *__restrict__ next, const int32_t *__restrict__ cx,
     const int32_t *__restrict__ cy, const int32_t *__restrict__ cz, const T *__restrict__ spos,
-    const T *__restrict__ smass, const Cube *__restrict__ cube, Moments *__restrict__ mom,
-    uint32_t *__restrict__ cmask) {
+    const T *__restrict__ smass, const Cube *__restrict__ cube, int32_t *__restrict__ kids,
+    Moments *__restrict__ mom, uint32_t *__restrict__ cmask, BodyRec<R> *__restrict__ bodies,
+    Anchor<R> *__restrict__ anchors) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m || next[i] != i + 1) return;
+    if (i >= m) return;
+    const int end = next[i];
+    {
+        int k[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+        int q = 0;
+        for (int ch = i + 1; ch < end && q < 8;) {
+            k[q++] = ch;
+            const int nx = next[ch];
+            if (nx <= ch) break;  // malformed skip pointer: stop
+            ch = nx;
+        }
+        int4 *o = (int4 *)(kids + 8 * (int64_t)i);
+        o[0] = make_int4(k[0], k[1], k[2], k[3]);
+        o[1] = make_int4(k[4], k[5], k[6], k[7]);
+    }
+    if (end != i + 1) return;
     const double h = ldexp(cube->L, -(kLevels + 1));
     const double c0 = cube->lo[0] + cx[i] * h, c1 = cube->lo[1] + cy[i] * h,
                  c2 = cube->lo[2] + cz[i] * h;
     const int b = begin[i], e = b + count[i];
+    Anchor<R> an;
+    an.x = (R)(cx[i] * h);  // exact
+    an.y = (R)(cy[i] * h);
+    an.z = (R)(cz[i] * h);
+    an.leaf = i;
     double mt = 0, s0 = 0, s1 = 0, s2 = 0;
     for (int j = b; j < e; ++j) {
         const double mj = (double)smass[j];
+        const double y0 = (double)spos[3 * (int64_t)j + 0] - c0;
+        const double y1 = (double)spos[3 * (int64_t)j + 1] - c1;
+        const double y2 = (double)spos[3 * (int64_t)j + 2] - c2;
         mt += mj;
-        s0 += mj * ((double)spos[3 * (int64_t)j + 0] - c0);
-        s1 += mj * ((double)spos[3 * (int64_t)j + 1] - c1);
-        s2 += mj * ((double)spos[3 * (int64_t)j + 2] - c2);
+        s0 += mj * y0;
+        s1 += mj * y1;
+        s2 += mj * y2;
+        BodyRec<R> br;
+        br.x = (R)y0;
+        br.y = (R)y1;
+        br.z = (R)y2;
+        br.m = (R)smass[j];
+        bodies[j] = br;
+        anchors[j] = an;
     }
     Moments r;
     r.m = mt;
@@ -675,30 +755,10 @@ __global__ __launch_bounds__(kThreads) void k_up_leaves(
     cmask[i] = 0u;
 }
 
-// Children of every internal node, in pre-order (= octant order), from the
-// skip pointers: kids[8 c + q] for q < #children, then -1.  The upward pass
-// and the group walk read a node's children from here in one load.
-__global__ __launch_bounds__(kThreads) void k_kids(int m, const int32_t *__restrict__ next,
-                                                   int32_t *__restrict__ kids) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= m) return;
-    int k[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
-    const int end = next[c];
-    int q = 0;
-    for (int ch = c + 1; ch < end && q < 8;) {
-        k[q++] = ch;
-        const int nx = next[ch];
-        if (nx <= ch) break;  // malformed skip pointer: stop
-        ch = nx;
-    }
-    int4 *o = (int4 *)(kids + 8 * (int64_t)c);
-    o[0] = make_int4(k[0], k[1], k[2], k[3]);
-    o[1] = make_int4(k[4], k[5], k[6], k[7]);
-}
-
 // One internal cell: combine its children (already done, one level deeper)
-// about this cell's centre with the parallel-axis shift, children in
-// octant order.  Also the 8-bit child mask.
+// in octant order, in one pass over them: mass, first and second moments
+// about this cell's centre (the centre offsets are exact), then the shift
+// to the COM, T = S2 - M com com^T.  Also the 8-bit child mask.
 __device__ __forceinline__ void up_node(int p, int m, const int4 *__restrict__ kids,
                                         const uint64_t *__restrict__ hkey,
                                         const int32_t *__restrict__ next,
@@ -711,19 +771,27 @@ __device__ __forceinline__ void up_node(int p, int m, const int4 *__restrict__ k
     const int ch[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
     const int pcx = cx[p], pcy = cy[p], pcz = cz[p];
     double mt = 0, s0 = 0, s1 = 0, s2 = 0;
+    double q[6] = {0, 0, 0, 0, 0, 0};
     uint32_t mask = 0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int c = ch[q];
+    for (int c8 = 0; c8 < 8; ++c8) {
+        const int c = ch[c8];
         if (c > p && c < m) {
             const Moments qm = mom[c];
             const double g0 = qm.c[0] + (double)(cx[c] - pcx) * h;
             const double g1 = qm.c[1] + (double)(cy[c] - pcy) * h;
             const double g2 = qm.c[2] + (double)(cz[c] - pcz) * h;
+            const double w0 = qm.m * g0, w1 = qm.m * g1, w2 = qm.m * g2;
             mt += qm.m;
-            s0 += qm.m * g0;
-            s1 += qm.m * g1;
-            s2 += qm.m * g2;
+            s0 += w0;
+            s1 += w1;
+            s2 += w2;
+            q[0] += qm.t[0] + w0 * g0;
+            q[1] += qm.t[1] + w0 * g1;
+            q[2] += qm.t[2] + w0 * g2;
+            q[3] += qm.t[3] + w1 * g1;
+            q[4] += qm.t[4] + w1 * g2;
+            q[5] += qm.t[5] + w2 * g2;
             mask |= 1u << (uint32_t)(hkey[c] & 7u);
         }
     }
@@ -732,23 +800,12 @@ __device__ __forceinline__ void up_node(int p, int m, const int4 *__restrict__ k
     r.c[0] = mt > 0 ? s0 / mt : 0.0;
     r.c[1] = mt > 0 ? s1 / mt : 0.0;
     r.c[2] = mt > 0 ? s2 / mt : 0.0;
-    for (int a = 0; a < 6; ++a) r.t[a] = 0.0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int c = ch[q];
-        if (c > p && c < m) {
-            const Moments qm = mom[c];
-            const double y0 = qm.c[0] + (double)(cx[c] - pcx) * h - r.c[0];
-            const double y1 = qm.c[1] + (double)(cy[c] - pcy) * h - r.c[1];
-            const double y2 = qm.c[2] + (double)(cz[c] - pcz) * h - r.c[2];
-            r.t[0] += qm.t[0] + qm.m * y0 * y0;
-            r.t[1] += qm.t[1] + qm.m * y0 * y1;
-            r.t[2] += qm.t[2] + qm.m * y0 * y2;
-            r.t[3] += qm.t[3] + qm.m * y1 * y1;
-            r.t[4] += qm.t[4] + qm.m * y1 * y2;
-            r.t[5] += qm.t[5] + qm.m * y2 * y2;
-        }
-    }
+    r.t[0] = q[0] - s0 * r.c[0];
+    r.t[1] = q[1] - s0 * r.c[1];
+    r.t[2] = q[2] - s0 * r.c[2];
+    r.t[3] = q[3] - s1 * r.c[1];
+    r.t[4] = q[4] - s1 * r.c[2];
+    r.t[5] = q[5] - s2 * r.c[2];
     mom[p] = r;
     cmask[p] = mask;
 }
@@ -828,37 +885,6 @@ __global__ __launch_bounds__(kThreads) void k_pack_nodes(
     recs[i] = r;
 }
 
-// Bodies of every leaf: offset from the leaf centre (computed in FP64) and
-// mass; and the leaf centre as each body's integer anchor.
-template <typename T, typename R>
-__global__ __launch_bounds__(kThreads) void k_pack_bodies(
-    int m, const int32_t *__restrict__ begin, const int32_t *__restrict__ count,
-    const int32_t *__restrict__ next, const int32_t *__restrict__ cx,
-    const int32_t *__restrict__ cy, const int32_t *__restrict__ cz,
-    const T *__restrict__ spos, const T *__restrict__ smass, const Cube *__restrict__ cube,
-    BodyRec<R> *__restrict__ bodies, Anchor<R> *__restrict__ anchors) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m || next[i] != i + 1) return;
-    const double h = ldexp(cube->L, -(kLevels + 1));
-    const double c0 = cube->lo[0] + cx[i] * h, c1 = cube->lo[1] + cy[i] * h,
-                 c2 = cube->lo[2] + cz[i] * h;
-    const int b = begin[i], e = b + count[i];
-    Anchor<R> an;
-    an.x = (R)(cx[i] * h);  // exact
-    an.y = (R)(cy[i] * h);
-    an.z = (R)(cz[i] * h);
-    an.leaf = i;
-    for (int j = b; j < e; ++j) {
-        BodyRec<R> br;
-        br.x = (R)((double)spos[3 * (int64_t)j + 0] - c0);
-        br.y = (R)((double)spos[3 * (int64_t)j + 1] - c1);
-        br.z = (R)((double)spos[3 * (int64_t)j + 2] - c2);
-        br.m = (R)smass[j];
-        bodies[j] = br;
-        anchors[j] = an;
-    }
-}
-
 template <typename T>
 int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int B,
                 const T *vel, const uint32_t *id, T *pos_out, T *vel_out, T *mass_out,
@@ -867,15 +893,15 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     const int ntiles = div_up(n, kSortTile);
     const int nb = div_up(n, kThreads);
     const int nbbox = nb < 1024 ? nb : 1024;
-    const int nkeys = nb < 2048 ? nb : 2048;
+    const int nkeys = div_up(n, kKeyThreads) < kKeyBlocks ? div_up(n, kKeyThreads) : kKeyBlocks;
     int rc;
-    const size_t status_cap0 = t->status.cap;
+    const size_t status_cap0 = t->status.cap, hist_cap0 = t->hist.cap;
     // ---- allocations sized by n
     if ((rc = grow(t->keys_a, 8ull * n)) || (rc = grow(t->keys_b, 8ull * n)) ||
         (rc = grow(t->idx_a, 4ull * n)) || (rc = grow(t->idx_b, 4ull * n)) ||
         (rc = grow(t->delta, (size_t)n + 1)) || (rc = grow(t->nstart, (size_t)n)) ||
         (rc = grow(t->offs, 4ull * (n + 1))) || (rc = grow(t->cube, sizeof(Cube))) ||
-        (rc = grow(t->part, 6ull * 8 * nbbox)) || (rc = grow(t->hist, 4ull * 256 * 8 * 2)) ||
+        (rc = grow(t->part, 7ull * 8 * nbbox)) || (rc = grow(t->hist, 4ull * 256 * 8 * 2)) ||
         (rc = grow(t->misc, 256 + 4ull * (kLevels + 2) * (nb + 1))) ||
         (rc = grow(t->status, 8ull * 256 * ntiles)) ||
         (rc = grow(t->bodies, sizeof(BodyRec<T>) * (size_t)n)) ||
@@ -889,24 +915,28 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
         mass_out = (T *)t->smass.p;
     }
     Cube *cube = (Cube *)t->cube.p;
-    // misc: [0] flags, [8..15] sort tile counters, [16..38] segment totals
-    // (chain-length sum, then cells per level), [64..] per-block sums
+    // misc: [0] flags, [1] node count, [8..15] sort tile counters, [16..38]
+    // segment totals (chain-length sum, then cells per level), [40..47] a
+    // copy of the root cube, [64..] per-block sums; [0..48) goes to the host
+    // in one copy
     uint32_t *misc = (uint32_t *)t->misc.p;
     uint32_t *flags = misc, *tile_ctr = misc + 8, *seg_tot = misc + 16;
     uint32_t *bsum = misc + 64;
     uint32_t *hist = (uint32_t *)t->hist.p, *doff = hist + 2048;
 
-    k_fill_u32<<<1, 64, 0, st>>>(misc, 16, 0u);
-    k_fill_u32<<<8, 256, 0, st>>>(hist, 2048, 0u);
+    // the digit histogram is left zeroed by the previous build's scan;
+    // only fresh memory needs clearing
+    if (t->hist.cap != hist_cap0) k_fill_u32<<<8, 256, 0, st>>>(hist, 2048, 0u);
     if (t->status.cap != status_cap0) {
         // fresh look-back status memory: clear it, or leftover words of
         // whatever used the memory before could carry the current epoch
         const int64_t words = (int64_t)(t->status.cap / 4);
         k_fill_u32<<<(int)((words + 255) / 256), 256, 0, st>>>((uint32_t *)t->status.p, words, 0u);
     }
-    k_bbox<T><<<nbbox, kThreads, 0, st>>>(pos, n, (double *)t->part.p, flags);
-    k_cube<<<1, kThreads, 0, st>>>((const double *)t->part.p, nbbox, cube);
-    k_keys<T><<<nkeys, kThreads, 0, st>>>(pos, n, cube, (uint64_t *)t->keys_a.p, hist);
+    k_bbox<T><<<nbbox, kThreads, 0, st>>>(pos, n, (double *)t->part.p);
+    k_cube<<<1, kThreads, 0, st>>>((const double *)t->part.p, nbbox, cube, (Cube *)(misc + 40),
+                                   flags);
+    k_keys<T><<<nkeys, kKeyThreads, 0, st>>>(pos, n, cube, (uint64_t *)t->keys_a.p, hist);
     k_hist_scan<<<8, 256, 0, st>>>(hist, doff, tile_ctr);
     uint64_t *ka = (uint64_t *)t->keys_a.p, *kb = (uint64_t *)t->keys_b.p;
     uint32_t *va = nullptr, *vb = (uint32_t *)t->idx_b.p, *vspare = (uint32_t *)t->idx_a.p;
@@ -931,24 +961,21 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     int8_t *delta = (int8_t *)t->delta.p;
     uint8_t *ns = (uint8_t *)t->nstart.p;
     int32_t *offs = (int32_t *)t->offs.p;
-    k_delta<<<div_up(n + 1, kThreads), kThreads, 0, st>>>(ka, n, delta);
-    k_chain<<<nb, kThreads, 0, st>>>(delta, n, B, ns, bsum);
+    k_chain<<<nb, kThreads, 0, st>>>(ka, n, B, delta, ns, bsum);
     k_scan_sums<<<kLevels + 2, 1024, 0, st>>>(bsum, nb, seg_tot);
-    k_scan_down<<<nb, kThreads, 0, st>>>(ns, n, bsum, offs);
+    k_scan_down<<<nb, kThreads, 0, st>>>(ns, n, bsum, offs, misc + 1);
     if ((rc = check_launch("topology"))) return rc;
     uint32_t *hp = (uint32_t *)ctx->pinned;
-    if (hipMemcpyAsync(hp, offs + n, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipMemcpyAsync(hp + 1, flags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipMemcpyAsync(hp + 32, seg_tot, 4 * (kLevels + 2), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipMemcpyAsync(hp + 16, cube, sizeof(Cube), hipMemcpyDeviceToHost, st) != hipSuccess ||
+    if (hipMemcpyAsync(hp, misc, 4 * 48, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return set_error(BH_E_DEVICE, "build: device failure while sizing the tree");
-    if (hp[1] & 1u) return set_error(BH_E_NONFINITE, "bh_build: non-finite position");
-    if (hp[1] & 2u) return set_error(BH_E_DEVICE, "bh_build: internal error (sort permutation)");
-    const Cube hc = *(const Cube *)(hp + 16);
+    if (hp[0] & 1u) return set_error(BH_E_NONFINITE, "bh_build: non-finite position");
+    if (hp[0] & 2u) return set_error(BH_E_DEVICE, "bh_build: internal error (sort permutation)");
+    Cube hc;
+    memcpy(&hc, hp + 40, sizeof(Cube));
     for (int d = 0; d < 3; ++d) t->lo[d] = hc.lo[d];
     t->L = hc.L;
-    const int m = (int)hp[0];
+    const int m = (int)hp[1];
     t->m = m;
     // cells per level -> level-list bases, depth
     LevelBase lb;
@@ -956,12 +983,12 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     int acc = 0;
     t->depth = 0;
     for (int k = 0; k <= kLevels; ++k) {
-        lcount[k] = (int)hp[32 + 1 + k];
+        lcount[k] = (int)hp[16 + 1 + k];
         lb.base[k] = acc;
         acc += lcount[k];
         if (lcount[k] > 0) t->depth = k;
     }
-    if (acc != m || hp[32] != (uint32_t)m)
+    if (acc != m || hp[16] != (uint32_t)m)
         return set_error(BH_E_DEVICE, "bh_build: internal error (level counts)");
     // ---- node allocations
     if ((rc = grow(t->hkey, 8ull * m)) || (rc = grow(t->level, 4ull * m)) ||
@@ -976,16 +1003,16 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
         return rc;
     const int nbm = div_up(m, kThreads);
     int32_t *lvl_list = (int32_t *)t->lvl_list.p;
-    k_emit<<<nb, kThreads, 0, st>>>(ka, delta, ns, offs, n, m, bsum, lb, (uint64_t *)t->hkey.p,
+    k_emit<<<nb, kThreads, 0, st>>>(ka, delta, offs, n, m, bsum, lb, (uint64_t *)t->hkey.p,
                                     (int32_t *)t->level.p, (int32_t *)t->begin.p,
                                     (int32_t *)t->count.p, (int32_t *)t->next.p,
                                     (int32_t *)t->parent.p, (int32_t *)t->cx.p,
                                     (int32_t *)t->cy.p, (int32_t *)t->cz.p, lvl_list);
-    k_up_leaves<T><<<nbm, kThreads, 0, st>>>(
+    k_leaves<T, T><<<nbm, kThreads, 0, st>>>(
         m, (const int32_t *)t->begin.p, (const int32_t *)t->count.p, (const int32_t *)t->next.p,
         (const int32_t *)t->cx.p, (const int32_t *)t->cy.p, (const int32_t *)t->cz.p, pos_out,
-        mass_out, cube, (Moments *)t->mom.p, (uint32_t *)t->cmask.p);
-    k_kids<<<nbm, kThreads, 0, st>>>(m, (const int32_t *)t->next.p, (int32_t *)t->kids.p);
+        mass_out, cube, (int32_t *)t->kids.p, (Moments *)t->mom.p, (uint32_t *)t->cmask.p,
+        (BodyRec<T> *)t->bodies.p, (Anchor<T> *)t->anchors.p);
     // the top levels whose cells number at most kTopCells each go to one
     // workgroup; the deeper levels get a launch each, deepest first
     constexpr int kTopCells = 1024;
@@ -1013,11 +1040,6 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
         (const int32_t *)t->count.p, (const int32_t *)t->next.p, (const int32_t *)t->cx.p,
         (const int32_t *)t->cy.p, (const int32_t *)t->cz.p, (const Moments *)t->mom.p, cube,
         (typename NodeRecT<T>::type *)t->recs.p);
-    k_pack_bodies<T, T><<<nbm, kThreads, 0, st>>>(
-        m, (const int32_t *)t->begin.p, (const int32_t *)t->count.p,
-        (const int32_t *)t->next.p, (const int32_t *)t->cx.p, (const int32_t *)t->cy.p,
-        (const int32_t *)t->cz.p, pos_out, mass_out, cube, (BodyRec<T> *)t->bodies.p,
-        (Anchor<T> *)t->anchors.p);
     return check_launch("tree");
 }
 

@@ -14,10 +14,12 @@
 //                          sorted rank s starts the chain of cells whose
 //                          first body it is; a scan of the chain lengths
 //                          places every cell in pre-order (Sec. 4.2)
-//  6. upward pass (FP64)   leaves from their bodies, parents from children
-//                          with the parallel-axis shift; the last child to
-//                          finish (atomic arrival count) climbs on
-//  7. pack                 FP32/FP64 walk records and leaf-relative bodies
+//  6. upward pass (FP64)   leaves from their bodies (with the child table
+//                          and the leaf-relative body records), internal
+//                          cells level by level, deepest first, from their
+//                          children's moments about the cell centre; each
+//                          node's FP32/FP64 walk record is written as soon
+//                          as its moments are final
 #include <float.h>
 #include <math.h>
 #include <string.h>
@@ -675,21 +677,72 @@ __global__ __launch_bounds__(kThreads) void k_emit(
 }
 
 // ------------------------------------------------------------------ 6. upward pass
+// The node arrays that the upward pass reads and writes.
+struct UpArgs {
+    int m;
+    const int4 *kids;
+    const uint64_t *hkey;
+    const int32_t *level, *begin, *count, *next, *cx, *cy, *cz;
+    const Cube *cube;
+    Moments *mom;
+    uint32_t *cmask;
+    void *recs;  // NodeRecT<R>::type[m]
+};
+
+__device__ __forceinline__ void set_level(NodeRec32 &, int) {}
+__device__ __forceinline__ void set_level(NodeRec64 &r, int k) { r.level = k; }
+
+// Stores node i's final moments and its walk record (centre, COM offset,
+// mass, traceless quadrupole 3T - tr(T) I, body range, skip pointer, side^2).
+template <typename R>
+__device__ __forceinline__ void finish_node(const UpArgs &a, int i, const Moments &q,
+                                            uint32_t mask, double h) {
+    a.mom[i] = q;
+    a.cmask[i] = mask;
+    const double tr = q.t[0] + q.t[3] + q.t[5];
+    typename NodeRecT<R>::type r{};
+    r.cx = (R)(a.cx[i] * h);  // exact
+    r.cy = (R)(a.cy[i] * h);
+    r.cz = (R)(a.cz[i] * h);
+    r.mx = (R)q.c[0];
+    r.my = (R)q.c[1];
+    r.mz = (R)q.c[2];
+    r.m = (R)q.m;
+    r.qxx = (R)(3.0 * q.t[0] - tr);
+    r.qxy = (R)(3.0 * q.t[1]);
+    r.qxz = (R)(3.0 * q.t[2]);
+    r.qyy = (R)(3.0 * q.t[3] - tr);
+    r.qyz = (R)(3.0 * q.t[4]);
+    r.begin = a.begin[i];
+    r.count = a.count[i];
+    r.next = a.next[i];
+    const int lev = a.level[i];
+    const double side = ldexp(a.cube->L, -lev);
+    r.l2 = (R)(side * side);
+    set_level(r, lev);
+    ((typename NodeRecT<R>::type *)a.recs)[i] = r;
+}
+
 // One thread per node.  Every node: its children, in pre-order (= octant
 // order), from the skip pointers: kids[8 c + q] for q < #children, then -1
 // (the upward pass and the group walk read a node's children from here in
 // one load).  Leaves also: FP64 moments straight from their bodies, about
-// the leaf centre, and the walk's body records (offset from the leaf centre,
-// computed in FP64, and mass) with the leaf centre as each body's anchor.
+// the leaf centre, the node record, and the walk's body records (offset from
+// the leaf centre, computed in FP64, and mass) with the leaf centre as each
+// body's anchor.
 template <typename T, typename R>
-__global__ __launch_bounds__(kThreads) void k_leaves(
-    int m, const int32_t *__restrict__ begin, const int32_t *__restrict__ count,
-    const int32_t *__restrict__ next, const int32_t *__restrict__ cx,
-    const int32_t *__restrict__ cy, const int32_t *__restrict__ cz, const T *__restrict__ spos,
-    const T *__restrict__ smass, const Cube *__restrict__ cube, int32_t *__restrict__ kids,
-    Moments *__restrict__ mom, uint32_t *__restrict__ cmask, BodyRec<R> *__restrict__ bodies,
-    Anchor<R> *__restrict__ anchors) {
+__global__ __launch_bounds__(kThreads) void k_leaves(UpArgs ua, int32_t *__restrict__ kids,
+                                                     const T *__restrict__ spos,
+                                                     const T *__restrict__ smass,
+                                                     BodyRec<R> *__restrict__ bodies,
+                                                     Anchor<R> *__restrict__ anchors) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = ua.m;
+    const int32_t *__restrict__ next = ua.next;
+    const int32_t *__restrict__ cx = ua.cx;
+    const int32_t *__restrict__ cy = ua.cy;
+    const int32_t *__restrict__ cz = ua.cz;
+    const Cube *__restrict__ cube = ua.cube;
     if (i >= m) return;
     const int end = next[i];
     {
@@ -709,7 +762,7 @@ __global__ __launch_bounds__(kThreads) void k_leaves(
     const double h = ldexp(cube->L, -(kLevels + 1));
     const double c0 = cube->lo[0] + cx[i] * h, c1 = cube->lo[1] + cy[i] * h,
                  c2 = cube->lo[2] + cz[i] * h;
-    const int b = begin[i], e = b + count[i];
+    const int b = ua.begin[i], e = b + ua.count[i];
     Anchor<R> an;
     an.x = (R)(cx[i] * h);  // exact
     an.y = (R)(cy[i] * h);
@@ -751,36 +804,31 @@ __global__ __launch_bounds__(kThreads) void k_leaves(
         r.t[4] += mj * y1 * y2;
         r.t[5] += mj * y2 * y2;
     }
-    mom[i] = r;
-    cmask[i] = 0u;
+    finish_node<R>(ua, i, r, 0u, h);
 }
 
 // One internal cell: combine its children (already done, one level deeper)
 // in octant order, in one pass over them: mass, first and second moments
 // about this cell's centre (the centre offsets are exact), then the shift
-// to the COM, T = S2 - M com com^T.  Also the 8-bit child mask.
-__device__ __forceinline__ void up_node(int p, int m, const int4 *__restrict__ kids,
-                                        const uint64_t *__restrict__ hkey,
-                                        const int32_t *__restrict__ next,
-                                        const int32_t *__restrict__ cx,
-                                        const int32_t *__restrict__ cy,
-                                        const int32_t *__restrict__ cz, double h,
-                                        Moments *__restrict__ mom, uint32_t *__restrict__ cmask) {
-    if (p < 0 || p >= m || next[p] == p + 1) return;  // leaves are done
-    const int4 k0 = kids[2 * (int64_t)p], k1 = kids[2 * (int64_t)p + 1];
+// to the COM, T = S2 - M com com^T.  Also the 8-bit child mask and the
+// node record.
+template <typename R>
+__device__ __forceinline__ void up_node(const UpArgs &a, int p, double h) {
+    if (p < 0 || p >= a.m || a.next[p] == p + 1) return;  // leaves are done
+    const int4 k0 = a.kids[2 * (int64_t)p], k1 = a.kids[2 * (int64_t)p + 1];
     const int ch[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
-    const int pcx = cx[p], pcy = cy[p], pcz = cz[p];
+    const int pcx = a.cx[p], pcy = a.cy[p], pcz = a.cz[p];
     double mt = 0, s0 = 0, s1 = 0, s2 = 0;
     double q[6] = {0, 0, 0, 0, 0, 0};
     uint32_t mask = 0;
 #pragma unroll
     for (int c8 = 0; c8 < 8; ++c8) {
         const int c = ch[c8];
-        if (c > p && c < m) {
-            const Moments qm = mom[c];
-            const double g0 = qm.c[0] + (double)(cx[c] - pcx) * h;
-            const double g1 = qm.c[1] + (double)(cy[c] - pcy) * h;
-            const double g2 = qm.c[2] + (double)(cz[c] - pcz) * h;
+        if (c > p && c < a.m) {
+            const Moments qm = a.mom[c];
+            const double g0 = qm.c[0] + (double)(a.cx[c] - pcx) * h;
+            const double g1 = qm.c[1] + (double)(a.cy[c] - pcy) * h;
+            const double g2 = qm.c[2] + (double)(a.cz[c] - pcz) * h;
             const double w0 = qm.m * g0, w1 = qm.m * g1, w2 = qm.m * g2;
             mt += qm.m;
             s0 += w0;
@@ -792,7 +840,7 @@ __device__ __forceinline__ void up_node(int p, int m, const int4 *__restrict__ k
             q[3] += qm.t[3] + w1 * g1;
             q[4] += qm.t[4] + w1 * g2;
             q[5] += qm.t[5] + w2 * g2;
-            mask |= 1u << (uint32_t)(hkey[c] & 7u);
+            mask |= 1u << (uint32_t)(a.hkey[c] & 7u);
         }
     }
     Moments r;
@@ -806,83 +854,32 @@ __device__ __forceinline__ void up_node(int p, int m, const int4 *__restrict__ k
     r.t[3] = q[3] - s1 * r.c[1];
     r.t[4] = q[4] - s1 * r.c[2];
     r.t[5] = q[5] - s2 * r.c[2];
-    mom[p] = r;
-    cmask[p] = mask;
+    finish_node<R>(a, p, r, mask, h);
 }
 
 // Internal cells of one level (one launch per level with more than
 // kTopCells cells).
-__global__ __launch_bounds__(kThreads) void k_up_level(
-    const int32_t *__restrict__ list, int cnt, int m, const int4 *__restrict__ kids,
-    const uint64_t *__restrict__ hkey, const int32_t *__restrict__ next,
-    const int32_t *__restrict__ cx, const int32_t *__restrict__ cy,
-    const int32_t *__restrict__ cz, const Cube *__restrict__ cube, Moments *__restrict__ mom,
-    uint32_t *__restrict__ cmask) {
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_up_level(const int32_t *__restrict__ list, int cnt,
+                                                       UpArgs a) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= cnt) return;
-    up_node(list[t], m, kids, hkey, next, cx, cy, cz, ldexp(cube->L, -(kLevels + 1)), mom,
-            cmask);
+    up_node<R>(a, list[t], ldexp(a.cube->L, -(kLevels + 1)));
 }
 
 // Levels top .. 0 (all small) in one workgroup, deepest first, with a
 // workgroup barrier between levels.  All waves of the workgroup share one
 // CU, so the barrier's workgroup-scope fence makes a level's results
 // visible to the next.
+template <typename R>
 __global__ __launch_bounds__(1024) void k_up_top(const int32_t *__restrict__ list, LevelBase lb,
-                                                 LevelBase lc, int top, int m,
-                                                 const int4 *__restrict__ kids,
-                                                 const uint64_t *__restrict__ hkey,
-                                                 const int32_t *__restrict__ next,
-                                                 const int32_t *__restrict__ cx,
-                                                 const int32_t *__restrict__ cy,
-                                                 const int32_t *__restrict__ cz,
-                                                 const Cube *__restrict__ cube,
-                                                 Moments *__restrict__ mom,
-                                                 uint32_t *__restrict__ cmask) {
-    const double h = ldexp(cube->L, -(kLevels + 1));
+                                                 LevelBase lc, int top, UpArgs a) {
+    const double h = ldexp(a.cube->L, -(kLevels + 1));
     for (int k = top; k >= 0; --k) {
         for (int t = threadIdx.x; t < lc.base[k]; t += blockDim.x)
-            up_node(list[lb.base[k] + t], m, kids, hkey, next, cx, cy, cz, h, mom, cmask);
+            up_node<R>(a, list[lb.base[k] + t], h);
         __syncthreads();
     }
-}
-
-// ------------------------------------------------------------------ 7. pack
-__device__ __forceinline__ void set_level(NodeRec32 &, int) {}
-__device__ __forceinline__ void set_level(NodeRec64 &r, int k) { r.level = k; }
-
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_pack_nodes(
-    int m, const int32_t *__restrict__ level, const int32_t *__restrict__ begin,
-    const int32_t *__restrict__ count, const int32_t *__restrict__ next,
-    const int32_t *__restrict__ cx, const int32_t *__restrict__ cy,
-    const int32_t *__restrict__ cz, const Moments *__restrict__ mom,
-    const Cube *__restrict__ cube, typename NodeRecT<R>::type *__restrict__ recs) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    const Moments q = mom[i];
-    const double tr = q.t[0] + q.t[3] + q.t[5];
-    const double h = ldexp(cube->L, -(kLevels + 1));
-    typename NodeRecT<R>::type r{};
-    r.cx = (R)(cx[i] * h);  // exact
-    r.cy = (R)(cy[i] * h);
-    r.cz = (R)(cz[i] * h);
-    r.mx = (R)q.c[0];
-    r.my = (R)q.c[1];
-    r.mz = (R)q.c[2];
-    r.m = (R)q.m;
-    r.qxx = (R)(3.0 * q.t[0] - tr);
-    r.qxy = (R)(3.0 * q.t[1]);
-    r.qxz = (R)(3.0 * q.t[2]);
-    r.qyy = (R)(3.0 * q.t[3] - tr);
-    r.qyz = (R)(3.0 * q.t[4]);
-    r.begin = begin[i];
-    r.count = count[i];
-    r.next = next[i];
-    const double side = ldexp(cube->L, -level[i]);
-    r.l2 = (R)(side * side);
-    set_level(r, level[i]);
-    recs[i] = r;
 }
 
 template <typename T>
@@ -1008,38 +1005,40 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
                                     (int32_t *)t->count.p, (int32_t *)t->next.p,
                                     (int32_t *)t->parent.p, (int32_t *)t->cx.p,
                                     (int32_t *)t->cy.p, (int32_t *)t->cz.p, lvl_list);
-    k_leaves<T, T><<<nbm, kThreads, 0, st>>>(
-        m, (const int32_t *)t->begin.p, (const int32_t *)t->count.p, (const int32_t *)t->next.p,
-        (const int32_t *)t->cx.p, (const int32_t *)t->cy.p, (const int32_t *)t->cz.p, pos_out,
-        mass_out, cube, (int32_t *)t->kids.p, (Moments *)t->mom.p, (uint32_t *)t->cmask.p,
-        (BodyRec<T> *)t->bodies.p, (Anchor<T> *)t->anchors.p);
+    UpArgs ua;
+    ua.m = m;
+    ua.kids = (const int4 *)t->kids.p;
+    ua.hkey = (const uint64_t *)t->hkey.p;
+    ua.level = (const int32_t *)t->level.p;
+    ua.begin = (const int32_t *)t->begin.p;
+    ua.count = (const int32_t *)t->count.p;
+    ua.next = (const int32_t *)t->next.p;
+    ua.cx = (const int32_t *)t->cx.p;
+    ua.cy = (const int32_t *)t->cy.p;
+    ua.cz = (const int32_t *)t->cz.p;
+    ua.cube = cube;
+    ua.mom = (Moments *)t->mom.p;
+    ua.cmask = (uint32_t *)t->cmask.p;
+    ua.recs = t->recs.p;
+    k_leaves<T, T><<<nbm, kThreads, 0, st>>>(ua, (int32_t *)t->kids.p, pos_out, mass_out,
+                                             (BodyRec<T> *)t->bodies.p,
+                                             (Anchor<T> *)t->anchors.p);
     // the top levels whose cells number at most kTopCells each go to one
     // workgroup; the deeper levels get a launch each, deepest first
     constexpr int kTopCells = 1024;
     int top = -1;
     while (top + 1 <= t->depth - 1 && lcount[top + 1] <= kTopCells) ++top;
-    const int4 *kids4 = (const int4 *)t->kids.p;
     for (int k = t->depth - 1; k > top; --k) {
         if (lcount[k] == 0) continue;
-        k_up_level<<<div_up(lcount[k], kThreads), kThreads, 0, st>>>(
-            lvl_list + lb.base[k], lcount[k], m, kids4, (const uint64_t *)t->hkey.p,
-            (const int32_t *)t->next.p, (const int32_t *)t->cx.p, (const int32_t *)t->cy.p,
-            (const int32_t *)t->cz.p, cube, (Moments *)t->mom.p, (uint32_t *)t->cmask.p);
+        k_up_level<T><<<div_up(lcount[k], kThreads), kThreads, 0, st>>>(lvl_list + lb.base[k],
+                                                                        lcount[k], ua);
     }
     if (top >= 0) {
         LevelBase lc;  // cells per level
         for (int k = 0; k <= kLevels; ++k) lc.base[k] = lcount[k];
-        k_up_top<<<1, 1024, 0, st>>>(lvl_list, lb, lc, top, m, kids4, (const uint64_t *)t->hkey.p,
-                                      (const int32_t *)t->next.p, (const int32_t *)t->cx.p,
-                                      (const int32_t *)t->cy.p, (const int32_t *)t->cz.p, cube,
-                                      (Moments *)t->mom.p, (uint32_t *)t->cmask.p);
+        k_up_top<T><<<1, 1024, 0, st>>>(lvl_list, lb, lc, top, ua);
     }
     t->kids_tree_id = t->build_id;
-    k_pack_nodes<T><<<nbm, kThreads, 0, st>>>(
-        m, (const int32_t *)t->level.p, (const int32_t *)t->begin.p,
-        (const int32_t *)t->count.p, (const int32_t *)t->next.p, (const int32_t *)t->cx.p,
-        (const int32_t *)t->cy.p, (const int32_t *)t->cz.p, (const Moments *)t->mom.p, cube,
-        (typename NodeRecT<T>::type *)t->recs.p);
     return check_launch("tree");
 }
 

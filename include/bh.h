@@ -96,6 +96,14 @@ typedef struct {
                                  terms + particle-particle bodies, per body)
                                  would exceed this is walked per body with the
                                  same criterion; 0 = 4096 */
+    double mlp_acc_floor;     /* BH_MAC_MLP / BH_MAC_BUDGET: |a_i| in the test
+                                 is replaced by max(|a_i|, f <|a|>), f this
+                                 value (>= 0) and <|a|> the mean of the n
+                                 norms, so that bodies where the field nearly
+                                 cancels do not force near-direct sums; the
+                                 budget then bounds the error relative to the
+                                 larger of the body's and f times the mean
+                                 acceleration.  Default 0 (none). */
 } bh_force_opts;
 
 /* Library version string. */

@@ -343,9 +343,21 @@ def cell_kc(b, eps, params=None):
     return kc
 
 
-def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None):
+def floored_norms(anorm, floor):
+    """|a_i| as the error-budget test uses it: max(|a_i|, floor <|a|>), the
+    mean taken over every given norm (the library's reading of the budget:
+    error relative to the larger of the body's acceleration and a fraction
+    of the mean one; floor = 0 leaves the norms as they are)."""
+    a = np.asarray(anorm, dtype=np.float64)
+    if floor <= 0:
+        return a
+    return np.maximum(a, floor * a.mean())
+
+
+def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None, floor=0.0):
     """Walk with the learned (or, k_C = 1, relative) criterion; anorm is
-    |a_i| per sorted rank."""
+    |a_i| per sorted rank, floored by ``floored_norms``."""
+    anorm = floored_norms(anorm, floor)
     lib = _mlib()
     t = b["tree"]
     M, com, Q = b["mom"]
@@ -382,7 +394,7 @@ def leaf_levels(b):
 
 def walk_group(b, eps, group=64, mode=0, theta=0.5, theta_max=1.0, tau=1e-3, kc=None,
                anorm=None, order=2, target_range=None, tol=1e-5, cap=GROUP_WORK_CAP,
-               split=True):
+               split=True, floor=0.0):
     """Walk with one acceptance decision per group of ``group`` consecutive
     sorted ranks in ``target_range`` (all bodies by default): mode 0 opening
     angle, mode 1 error budget (kc per cell, anorm per sorted rank).  With
@@ -402,7 +414,7 @@ def walk_group(b, eps, group=64, mode=0, theta=0.5, theta_max=1.0, tau=1e-3, kc=
     ncov = np.zeros(nt, dtype=np.int64)
     flag = np.zeros(nt, dtype=np.int32)
     kcv = None if kc is None else np.ascontiguousarray(kc, dtype=np.float64)
-    anv = None if anorm is None else np.ascontiguousarray(anorm, dtype=np.float64)
+    anv = None if anorm is None else np.ascontiguousarray(floored_norms(anorm, floor))
     if mode == 1 and (kcv is None or anv is None):
         raise ValueError("the error-budget mode needs kc and anorm")
     if nt:

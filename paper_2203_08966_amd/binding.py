@@ -50,6 +50,7 @@ class ForceOpts(C.Structure):
         ("mlp_theta_max", C.c_double), ("mlp_log10_tau", C.c_double),
         ("mlp_acc_norm", C.c_void_p), ("mlp_theta_est", C.c_double),
         ("walk", C.c_int), ("walk_stack", C.c_int), ("walk_cap", C.c_int),
+        ("mlp_acc_floor", C.c_double),
     ]
 
 
@@ -162,9 +163,11 @@ def _stream():
 
 def force_opts(order=2, mac=BH_MAC_THETA, phi=None, n_pp=None, n_pc=None, target_range=None,
                mlp_theta_max=None, mlp_log10_tau=None, mlp_acc_norm=None,
-               mlp_theta_est=None, walk=BH_WALK_BODY, walk_stack=0, walk_cap=0) -> ForceOpts:
+               mlp_theta_est=None, walk=BH_WALK_BODY, walk_stack=0, walk_cap=0,
+               mlp_acc_floor=None) -> ForceOpts:
     """Walk options.  mlp_acc_norm: device tensor of |a_i| in caller order
-    and the tree's dtype (kept alive by the caller until the walk ran)."""
+    and the tree's dtype (kept alive by the caller until the walk ran);
+    mlp_acc_floor: f in max(|a_i|, f <|a|>)."""
     o = ForceOpts()
     load().bh_force_opts_default(C.byref(o))
     o.order = order
@@ -184,6 +187,8 @@ def force_opts(order=2, mac=BH_MAC_THETA, phi=None, n_pp=None, n_pc=None, target
     o.walk = walk
     o.walk_stack = walk_stack
     o.walk_cap = walk_cap
+    if mlp_acc_floor is not None:
+        o.mlp_acc_floor = mlp_acc_floor
     return o
 
 

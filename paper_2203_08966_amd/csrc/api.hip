@@ -86,7 +86,8 @@ static int check_opts(const bh_force_opts &o, int64_t n) {
         return set_error(BH_E_INVALID, "opts target range outside [0, n]");
     if (o.mac != BH_MAC_THETA &&
         !(o.mlp_theta_max > 0 && isfinite(o.mlp_theta_max) && isfinite(o.mlp_log10_tau) &&
-          o.mlp_theta_est >= 0 && isfinite(o.mlp_theta_est)))
+          o.mlp_theta_est >= 0 && isfinite(o.mlp_theta_est) && o.mlp_acc_floor >= 0 &&
+          isfinite(o.mlp_acc_floor)))
         return set_error(BH_E_INVALID, "opts learned-criterion parameters invalid");
     if (o.walk != BH_WALK_BODY && o.walk != BH_WALK_GROUP)
         return set_error(BH_E_INVALID, "opts.walk must be BH_WALK_BODY or BH_WALK_GROUP");
@@ -129,6 +130,7 @@ void bh_force_opts_default(bh_force_opts *o) {
     o->mlp_log10_tau = -3.0;
     o->mlp_acc_norm = nullptr;
     o->mlp_theta_est = 0.8;
+    o->mlp_acc_floor = 0.0;
     o->walk = BH_WALK_BODY;
     o->walk_stack = 0;
     o->walk_cap = 0;

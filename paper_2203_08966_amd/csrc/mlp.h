@@ -116,8 +116,11 @@ int mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_max, doubl
 int mlp_cells(bh_tree *t, double eps, bool learned);
 // |a| per sorted rank into t->anorm from an acceleration array (acc) or an
 // array of norms (norm), of the tree's dtype, in caller order (read through
-// perm) or in sorted order
-int mlp_anorm(bh_tree *t, const void *acc, const void *norm, bool caller_order);
+// perm) or in sorted order; also the floor floor_frac * mean |a| (device
+// scalar, mlp_anorm_floor)
+int mlp_anorm(bh_tree *t, const void *acc, const void *norm, bool caller_order,
+              double floor_frac);
+const float *mlp_anorm_floor(const bh_tree *t);
 int mlp_grad_step(bh_ctx *c, const float *X, const float *y, int64_t ns, int64_t base, int bs,
                   uint64_t a, uint64_t cc, float *g_out, float *loss_acc, bool apply, int step,
                   const MlpTrainCfg &cfg);

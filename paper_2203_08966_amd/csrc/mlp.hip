@@ -121,16 +121,44 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_anorm(int n, const R *__restrict__ acc,
                                                const R *__restrict__ norm,
                                                const uint32_t *__restrict__ perm,
-                                               float *__restrict__ out) {
+                                               float *__restrict__ out,
+                                               double *__restrict__ part) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t j = perm ? (int64_t)perm[i] : i;
-    if (norm) {
-        out[i] = (float)norm[j];
-    } else {
-        const R x = acc[3 * j], y = acc[3 * j + 1], z = acc[3 * j + 2];
-        out[i] = (float)sqrt(x * x + y * y + z * z);
+    float v = 0.f;
+    if (i < n) {
+        const int64_t j = perm ? (int64_t)perm[i] : i;
+        if (norm) {
+            v = (float)norm[j];
+        } else {
+            const R x = acc[3 * j], y = acc[3 * j + 1], z = acc[3 * j + 2];
+            v = (float)sqrt(x * x + y * y + z * z);
+        }
+        out[i] = v;
     }
+    // block sum of the stored norms, FP64, fixed order
+    __shared__ double s[256];
+    s[threadIdx.x] = (double)v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// floor = f * (sum of the block sums) / n, one block, fixed order.
+__global__ __launch_bounds__(1024) void k_anorm_floor(const double *__restrict__ part, int nblk,
+                                                      int n, double f, float *__restrict__ floor_out) {
+    __shared__ double s[1024];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 1024) v += part[b];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *floor_out = (float)(f * (s[0] / (double)n));
 }
 
 // ------------------------------------------------------------------ training pairs
@@ -496,18 +524,29 @@ int mlp_cells(bh_tree *t, double eps, bool learned) {
     return BH_OK;
 }
 
-int mlp_anorm(bh_tree *t, const void *acc, const void *norm, bool caller_order) {
+int mlp_anorm(bh_tree *t, const void *acc, const void *norm, bool caller_order,
+              double floor_frac) {
     const int n = (int)t->n;
-    int rc = grow(t->anorm, 4ull * n);
+    const int nblk = div_up(n, 256);
+    const size_t npad = 4ull * (size_t)div_up(n, 64) * 64;  // norms, then block sums, floor
+    int rc = grow(t->anorm, npad + 8ull * nblk + 8);
     if (rc) return rc;
     const uint32_t *perm = caller_order ? t->perm : nullptr;
+    double *part = (double *)((char *)t->anorm.p + npad);
     if (t->dtype == BH_F32)
-        k_anorm<float><<<div_up(n, 256), 256, 0, t->ctx->stream>>>(
-            n, (const float *)acc, (const float *)norm, perm, (float *)t->anorm.p);
+        k_anorm<float><<<nblk, 256, 0, t->ctx->stream>>>(
+            n, (const float *)acc, (const float *)norm, perm, (float *)t->anorm.p, part);
     else
-        k_anorm<double><<<div_up(n, 256), 256, 0, t->ctx->stream>>>(
-            n, (const double *)acc, (const double *)norm, perm, (float *)t->anorm.p);
+        k_anorm<double><<<nblk, 256, 0, t->ctx->stream>>>(
+            n, (const double *)acc, (const double *)norm, perm, (float *)t->anorm.p, part);
+    k_anorm_floor<<<1, 1024, 0, t->ctx->stream>>>(part, nblk, n, floor_frac,
+                                                  (float *)(part + nblk));
     return check_launch("anorm");
+}
+
+const float *mlp_anorm_floor(const bh_tree *t) {
+    const size_t npad = 4ull * (size_t)div_up((int)t->n, 64) * 64;
+    return (const float *)((const char *)t->anorm.p + npad + 8ull * div_up((int)t->n, 256));
 }
 
 int mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_max, double keep,

@@ -85,10 +85,11 @@ __device__ __forceinline__ void leaf_pp(const BodyRec<R> *__restrict__ bodies, i
 }
 
 // Learned-criterion parameters of a walk: per cell k_C M l^3, per sorted
-// rank |a_i|, theta_max^2 and tau.
+// rank |a_i|, the floor of |a_i| (device scalar), theta_max^2 and tau.
 struct MlpMac {
     const float *kc;
     const float *anorm;
+    const float *afloor;
     float tmax2, tau;
 };
 
@@ -104,7 +105,7 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
                                            uint32_t &cpp, uint32_t &cpc) {
     using Rec = typename NodeRecT<R>::type;
     float tau_a = 0.f;  // tau |a_i|
-    if (MLP && live) tau_a = mac.tau * mac.anorm[i];
+    if (MLP && live) tau_a = mac.tau * fmaxf(mac.anorm[i], *mac.afloor);
 
     const bool root_leaf = nodes[0].next == 1;
     int idx = root_leaf ? 0 : 1;
@@ -292,6 +293,7 @@ constexpr int kGroupWorkCap = 4096;    // default per-group work cap
 struct GroupMac {
     const float *kc;     // error budget: k_C M l^3 per node
     const float *anorm;  // |a_i| per sorted rank
+    const float *afloor;  // floor of |a_i| (device scalar)
     float tau;
     int cap;             // stack entries used (<= kGroupStack)
     int work_cap;        // per-group work above which the group walks per body
@@ -372,7 +374,8 @@ __device__ __forceinline__ void group_walk(
         const R bcx = (R)0.5 * (lx + hx), bcy = (R)0.5 * (ly + hy), bcz = (R)0.5 * (lz + hz);
         const R bhx = (R)0.5 * (hx - lx), bhy = (R)0.5 * (hy - ly), bhz = (R)0.5 * (hz - lz);
         float tau_amin = 0.f;
-        if (BUDGET) tau_amin = gm.tau * wave_min(live_run ? gm.anorm[i] : 3.0e38f);
+        if (BUDGET)
+            tau_amin = gm.tau * fmaxf(wave_min(live_run ? gm.anorm[i] : 3.0e38f), *gm.afloor);
 
         R sx = 0, sy = 0, sz = 0, sp = 0;
         uint32_t cpp = 0, cpc = 0;
@@ -570,7 +573,7 @@ __device__ __forceinline__ void group_walk(
         if (per_body) {  // too spread out for one decision: walk per body
             sx = sy = sz = sp = 0;
             cpp = cpc = 0;
-            const MlpMac pm{gm.kc, gm.anorm, (float)theta2, gm.tau};
+            const MlpMac pm{gm.kc, gm.anorm, gm.afloor, (float)theta2, gm.tau};
             body_sweep<R, ORDER2, PHI, CNT, BUDGET>(nodes, m, bodies, nbodies, i, live_run, ox, oy, oz,
                                                     ax, ay, az, myleaf, theta2, eps2, pm, sx, sy, sz,
                                                     sp, cpp, cpc);
@@ -755,13 +758,13 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
         if (!npp) npp = (uint32_t *)t->cnt_scratch.p;
         else npc = (uint32_t *)t->cnt_scratch.p;
     }
-    MlpMac mac{nullptr, nullptr, 0.f, 0.f};
+    MlpMac mac{nullptr, nullptr, nullptr, 0.f, 0.f};
     const bool group = o.walk == BH_WALK_GROUP;
     if (group) {
         int rc = ensure_kids(t);
         if (rc) return rc;
     }
-    GroupMac gm{nullptr, nullptr, 0.f, o.walk_stack > 0 ? o.walk_stack : kGroupStack,
+    GroupMac gm{nullptr, nullptr, nullptr, 0.f, o.walk_stack > 0 ? o.walk_stack : kGroupStack,
                 o.walk_cap > 0 ? o.walk_cap : kGroupWorkCap, nullptr};
     if (o.mac == BH_MAC_MLP || o.mac == BH_MAC_BUDGET) {
         if (t->dtype != BH_F32 || o.order != 2)
@@ -769,9 +772,9 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
         int rc = mlp_cells(t, eps, o.mac == BH_MAC_MLP);
         if (rc) return rc;
         if (o.mlp_acc_norm) {
-            rc = mlp_anorm(t, nullptr, o.mlp_acc_norm, true);
+            rc = mlp_anorm(t, nullptr, o.mlp_acc_norm, true, o.mlp_acc_floor);
         } else if (prev_acc) {
-            rc = mlp_anorm(t, prev_acc, nullptr, true);
+            rc = mlp_anorm(t, prev_acc, nullptr, true, o.mlp_acc_floor);
         } else {
             // estimate |a_i| of the targets with a monopole walk at theta_est
             if ((rc = grow(t->est_acc, 12ull * t->n))) return rc;
@@ -786,16 +789,18 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
             if ((rc = run_walk(t, o.mlp_theta_est, eps, t->est_acc.p, nullptr, nullptr, nullptr, eo,
                                true)))
                 return rc;
-            rc = mlp_anorm(t, t->est_acc.p, nullptr, false);
+            rc = mlp_anorm(t, t->est_acc.p, nullptr, false, o.mlp_acc_floor);
         }
         if (rc) return rc;
         mac.kc = (const float *)t->kc.p;
         mac.anorm = (const float *)t->anorm.p;
+        mac.afloor = mlp_anorm_floor(t);
         mac.tmax2 = (float)(o.mlp_theta_max * o.mlp_theta_max);
         mac.tau = (float)pow(10.0, o.mlp_log10_tau);
         if (group) {
             gm.kc = mac.kc;
             gm.anorm = mac.anorm;
+            gm.afloor = mac.afloor;
             gm.tau = mac.tau;
             gdispatch<float, true, true>(t, t0, t1, o.mlp_theta_max, eps, acc, phi, npp, npc,
                                          sorted_out, gm);

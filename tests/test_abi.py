@@ -33,7 +33,7 @@ def test_version_and_defaults():
     assert o.order == 2 and o.mac == B.BH_MAC_THETA
     assert o.target_begin == 0 and o.target_end == 0
     assert o.mlp_theta_max == 1.0 and o.mlp_log10_tau == -3.0 and o.mlp_theta_est == 0.8
-    assert o.mlp_acc_norm is None
+    assert o.mlp_acc_norm is None and o.mlp_acc_floor == 0.0
 
 
 def test_null_handles_rejected():
@@ -100,6 +100,10 @@ def test_force_parameter_checks_precede_device_use():
                        (0.5, float("nan"))]:
         assert lib.bh_forces(t, theta, eps, acc, None) == B.BH_E_INVALID
     assert lib.bh_forces(t, 0.5, 0.0, None, None) == B.BH_E_INVALID
+    for f in (-0.5, float("nan"), float("inf")):
+        o = B.force_opts(mac=B.BH_MAC_BUDGET, mlp_acc_floor=f)
+        assert lib.bh_forces(t, 0.5, 0.0, acc, C.byref(o)) == B.BH_E_INVALID
+        assert "learned-criterion" in B.bh_last_error()
 
 
 def test_sim_argument_checks():

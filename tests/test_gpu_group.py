@@ -133,6 +133,27 @@ def test_group_budget_matches_oracle(ctx):
     _check(ref, r, out, np.float32)
 
 
+def test_group_budget_floor_matches_oracle(ctx):
+    """The group error-budget walk with |a_i| floored at half the mean norm:
+    a group's decision uses max(min |a_i|, floor)."""
+    pos, _, mass = case_bodies("plummer", 20000, 15, np.float32)
+    eps, tau, tmax, fl = 0.005, 10 ** -1.75, 1.5, 0.5
+    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), 16)
+    w = oracle.walk(ref["tree"], ref["mom"], ref["spos"], ref["smass"], ref["L"], 0.4, eps)
+    an = np.empty(20000)
+    an[ref["perm"]] = np.linalg.norm(w.acc, axis=1)
+    an = an.astype(np.float32)
+    say(f"group budget walk, floor {fl}: 20000 bodies, tau {tau:.3g}, theta_max {tmax}")
+    out = _run(ctx, pos, mass, 16, 0.5, eps, mac=B.BH_MAC_BUDGET, mlp_theta_max=tmax,
+               mlp_log10_tau=np.log10(tau), acc_norm=an, mlp_acc_floor=fl)
+    args = dict(group=64, mode=1, theta_max=tmax, tau=tau, kc=oracle.cell_kc(ref, eps),
+                anorm=an.astype(np.float64)[ref["perm"]], tol=FLAG_TOL[np.float32])
+    r = oracle.walk_group(ref, eps, floor=fl, **args)
+    r0 = oracle.walk_group(ref, eps, **args)
+    assert np.mean(r.npp + r.npc < r0.npp + r0.npc) > 0.05  # the floor is in effect
+    _check(ref, r, out, np.float32)
+
+
 def test_group_walk_full_size_sampled(ctx):
     """The Plummer sphere of 2^20 bodies in the launch the benchmark times
     (FP32, quadrupole, leaf 16, eps 0.005): sampled groups against the

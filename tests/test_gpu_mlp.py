@@ -176,6 +176,24 @@ def test_budget_walk_matches_oracle(ctx):
     _compare(ref, r, a, cp, cc)
 
 
+def test_budget_walk_floor_matches_oracle(ctx):
+    """The same test with |a_i| floored at half the mean norm (the library
+    takes the mean over the n norms it is handed)."""
+    pos, _, mass = case_bodies("plummer", 20000, 4, np.float32)
+    eps, tau, tmax, fl = 0.005, 1e-3, 1.0, 0.5
+    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), 16)
+    an = _oracle_anorm(ref, eps).astype(np.float32)
+    say(f"budget walk, floor {fl}: 20000 bodies, tau {tau}, theta_max {tmax}")
+    a, cp, cc = _gpu_walk(ctx, pos, mass, 16, eps, mac=B.BH_MAC_BUDGET, mlp_theta_max=tmax,
+                          mlp_log10_tau=np.log10(tau), acc_norm=an, mlp_acc_floor=fl)
+    r = oracle.walk_kc(ref, eps, tmax, tau, oracle.cell_kc(ref, eps),
+                       an.astype(np.float64)[ref["perm"]], floor=fl)
+    r0 = oracle.walk_kc(ref, eps, tmax, tau, oracle.cell_kc(ref, eps),
+                        an.astype(np.float64)[ref["perm"]])
+    assert np.mean(r.npp + r.npc < r0.npp + r0.npc) > 0.05  # the floor is in effect
+    _compare(ref, r, a, cp, cc)
+
+
 def test_learned_walk_matches_oracle(ctx):
     """The walk with the network's per-cell k_C against the oracle's walk with
     the bf16 view of the same network."""

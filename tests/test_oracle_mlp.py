@@ -217,3 +217,40 @@ def test_pinball_gradient_and_quantile():
         assert abs(gb - (frac - q)) < 1e-12
     c[-1] = ys[899] + 1e-9
     assert abs(mlp.grad(c, np.zeros((1000, 10)), ys, q)[-1]) < 1e-12
+
+
+def test_floored_norms_hand_example():
+    """max(|a_i|, f <|a|>): norms 1, 2, 3, 10 have mean 4."""
+    a = np.array([1.0, 2.0, 3.0, 10.0])
+    np.testing.assert_array_equal(oracle.floored_norms(a, 0.0), a)
+    np.testing.assert_array_equal(oracle.floored_norms(a, 0.5), [2.0, 2.0, 3.0, 10.0])
+    np.testing.assert_array_equal(oracle.floored_norms(a, 3.0), [12.0] * 4)
+
+
+def test_walk_kc_floor_touches_only_bodies_below_it():
+    """Each body's decisions depend on its own |a_i| only: bodies at or above
+    the floor walk exactly as without it; bodies below it walk as with
+    |a_i| = the floor, which accepts at least as much (never more
+    interactions).  A floor above every norm turns the test into an absolute
+    error bound, the same as a constant |a|."""
+    b = W.plummer(3000, 6)
+    bb = oracle.build_all(b.pos, b.mass, 8)
+    kc = oracle.cell_kc(bb, 0.01)
+    full = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], 0.4, 0.01)
+    an = np.linalg.norm(full.acc, axis=1)
+    tau, tm = 1e-3, 1.0
+    r0 = oracle.walk_kc(bb, 0.01, tm, tau, kc, an)
+    rf = oracle.walk_kc(bb, 0.01, tm, tau, kc, an, floor=0.5)
+    fl = 0.5 * an.mean()
+    above = an >= fl
+    assert 0.1 < (~above).mean() < 0.9
+    np.testing.assert_array_equal(rf.acc[above], r0.acc[above])
+    assert np.array_equal(rf.npp[above], r0.npp[above])
+    w0, wf = r0.npp + r0.npc, rf.npp + rf.npc
+    assert np.all(wf[~above] <= w0[~above]) and np.mean(wf[~above] < w0[~above]) > 0.5
+    const = oracle.walk_kc(bb, 0.01, tm, tau, kc, np.full(3000, fl))
+    big = oracle.walk_kc(bb, 0.01, tm, tau, kc, an, floor=an.max() / an.mean())
+    lev = an.max()
+    const_big = oracle.walk_kc(bb, 0.01, tm, tau, kc, np.full(3000, lev))
+    np.testing.assert_array_equal(big.acc, const_big.acc)
+    np.testing.assert_array_equal(rf.acc[~above], const.acc[~above])

@@ -12,7 +12,8 @@ calibrated on the initial state against the FP64 direct sum over a seeded
   body-theta    the per-body walk of Sec. 3 (opening angle theta);
   group-theta   one opening-angle decision per wavefront of 64 bodies;
   group-budget  one error-budget decision per wavefront (k_C = 1 error
-                model, tau times the group's smallest |a|);
+                model, tau times the group's smallest |a|, each |a_i|
+                floored at half the mean |a|);
   group-learned the same with k_C per cell from the network, trained first
                 on the library's own FP64 simulations of small Plummer
                 spheres.
@@ -62,6 +63,8 @@ METHODS = {
 PARAM_NAME = {"body-theta": "theta", "group-theta": "theta", "group-budget": "log10_tau",
               "group-learned": "log10_tau"}
 BUDGET_THETA_MAX = 1.5
+# |a_i| in the budget tests is max(|a_i|, ACC_FLOOR <|a|>)
+ACC_FLOOR = 0.5
 
 
 def log(*a):
@@ -159,7 +162,7 @@ def main():
             kw.update(walk=B.BH_WALK_GROUP,
                       mac=B.BH_MAC_BUDGET if method == "group-budget" else B.BH_MAC_MLP,
                       mlp_log10_tau=p, mlp_theta_max=BUDGET_THETA_MAX,
-                      mlp_acc_norm=None if for_sim else anorm)
+                      mlp_acc_norm=None if for_sim else anorm, mlp_acc_floor=ACC_FLOOR)
         return B.force_opts(**kw)
 
     def walk(method, p, counters=False):
@@ -288,6 +291,8 @@ def main():
             "workload": result_workload(cfg, n),
             "n": n, "eps": eps, "leaf": leaf, "order": order, "dt": dt,
             "method": chosen, PARAM_NAME[chosen]: cp,
+            **({"theta_max": BUDGET_THETA_MAX, "acc_floor": ACC_FLOOR}
+               if PARAM_NAME[chosen] == "log10_tau" else {}),
             "step": "KDK leapfrog step: kick+drift, rebuild, walk, kick, energy",
         },
         "rms_rel_err": methods[chosen]["rms_rel_err"],

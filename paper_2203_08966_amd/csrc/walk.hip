@@ -95,8 +95,11 @@ struct MlpMac {
 
 // The per-body walk of one wavefront (see the file header): lane body i
 // (live), its offset (ox, oy, oz) from its leaf centre (ax, ay, az), leaf
-// index myleaf; sums into s*, counts into cpp/cpc.
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool MLP>
+// index myleaf; sums into s*, counts into cpp/cpc.  With PF both possible
+// successor records are loaded while a node is processed: this shortens the
+// dependent chain of a lone wavefront (the group walk's per-body fallback)
+// but costs the register file the occupancy that hides it in a full launch.
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool MLP, bool PF = false>
 __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__restrict__ nodes,
                                            int m, const BodyRec<R> *__restrict__ bodies,
                                            int nbodies, int i, bool live, R ox, R oy, R oz,
@@ -111,12 +114,20 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
     int idx = root_leaf ? 0 : 1;
     int resume = live ? idx : 0x7fffffff;
 
+    Rec nd_next = nodes[uniform(idx)];
     while (idx < m) {
         idx = uniform(idx);
-        const Rec nd = nodes[idx];
+        const Rec nd = PF ? nd_next : nodes[idx];
         const bool act = resume <= idx;
         const int nxt = uniform(nd.next);
         const int cnt = uniform(nd.count);
+        Rec n1{}, n2{};
+        if (PF) {
+            const int s1 = uniform(idx + 1 < m ? idx + 1 : idx);
+            const int s2 = uniform(nxt > idx && nxt < m ? nxt : s1);
+            n1 = nodes[s1];
+            n2 = nodes[s2];
+        }
         // position relative to the cell centre (the centre difference is exact)
         const R X = (ax - nd.cx) + ox;
         const R Y = (ay - nd.cy) + oy;
@@ -181,7 +192,9 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
         }
         const uint64_t any_open = __ballot(open);
         if (act) resume = open ? idx + 1 : nxt;
-        idx = any_open ? idx + 1 : (nxt > idx ? nxt : idx + 1);  // always moves forward
+        const int nidx = any_open ? idx + 1 : (nxt > idx ? nxt : idx + 1);  // always moves forward
+        if (PF) nd_next = nidx == idx + 1 ? n1 : n2;
+        idx = nidx;
     }
 }
 
@@ -574,7 +587,7 @@ __device__ __forceinline__ void group_walk(
             sx = sy = sz = sp = 0;
             cpp = cpc = 0;
             const MlpMac pm{gm.kc, gm.anorm, gm.afloor, (float)theta2, gm.tau};
-            body_sweep<R, ORDER2, PHI, CNT, BUDGET>(nodes, m, bodies, nbodies, i, live_run, ox, oy, oz,
+            body_sweep<R, ORDER2, PHI, CNT, BUDGET, true>(nodes, m, bodies, nbodies, i, live_run, ox, oy, oz,
                                                     ax, ay, az, myleaf, theta2, eps2, pm, sx, sy, sz,
                                                     sp, cpp, cpc);
         }

@@ -212,8 +212,9 @@ int bh_sim_tree(bh_ctx *ctx, bh_tree **tree);
  * context's stream.  enable = 1 clears the totals and starts recording (at
  * most 65536 steps); 0 stops.  bh_sim_timing_get waits for the stream and
  * returns, summed over the recorded steps, the milliseconds spent in
- * ms[0] kick + drift, ms[1] tree build, ms[2] walk, ms[3] final kick, and
- * the number of steps. */
+ * ms[0] kick + drift, ms[1] tree build, ms[2] walk (with its set-up
+ * kernels), ms[3] final kick, ms[4] the walk kernel alone (ms holds 5
+ * values), and the number of steps. */
 int bh_sim_timing(bh_ctx *ctx, int enable);
 int bh_sim_timing_get(bh_ctx *ctx, double *ms, int64_t *steps);
 

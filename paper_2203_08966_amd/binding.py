@@ -322,7 +322,7 @@ def bh_sim_timing(ctx, enable: bool = True):
 
 
 def bh_sim_timing_get(ctx) -> tuple[list, int]:
-    ms = (C.c_double * 4)()
+    ms = (C.c_double * 5)()
     steps = C.c_int64()
     _check(load().bh_sim_timing_get(ctx, ms, C.byref(steps)))
     return list(ms), steps.value

@@ -402,13 +402,13 @@ static constexpr int64_t kMaxTimedSteps = 65536;
 
 static hipEvent_t *step_events(bh_ctx *c) {
     if (!c->timing || c->timed_steps >= kMaxTimedSteps) return nullptr;
-    const size_t need = 5 * (size_t)(c->timed_steps + 1);
+    const size_t need = 7 * (size_t)(c->timed_steps + 1);
     while (c->events.size() < need) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
         c->events.push_back(e);
     }
-    return &c->events[5 * (size_t)c->timed_steps];
+    return &c->events[7 * (size_t)c->timed_steps];
 }
 
 int bh_leapfrog_step(bh_ctx *c, double dt) {
@@ -431,7 +431,10 @@ int bh_leapfrog_step(bh_ctx *c, double dt) {
     // new tree and accelerations at the drifted positions
     if ((rc = sim_rebuild(c, s->pos.p, s->vel.p, s->mass.p, (const uint32_t *)s->id.p))) return rc;
     mark(2);
-    if ((rc = sim_forces(c))) return rc;
+    c->walk_ev = ev ? ev + 5 : nullptr;  // the walk kernel alone: events 5, 6
+    rc = sim_forces(c);
+    c->walk_ev = nullptr;
+    if (rc) return rc;
     mark(3);
     // second kick (dt/2)
     rc = launch_kick(c->stream, s->dtype, s->n, s->vel.p, s->acc.p, 0.5 * dt);
@@ -452,12 +455,13 @@ int bh_sim_timing_get(bh_ctx *c, double *ms, int64_t *steps) {
     if (use_device(c)) return BH_E_DEVICE;
     if (hipStreamSynchronize(c->stream) != hipSuccess)
         return set_error(BH_E_DEVICE, "device error while timing");
-    for (int k = 0; k < 4; ++k) ms[k] = 0.0;
+    for (int k = 0; k < 5; ++k) ms[k] = 0.0;
     for (int64_t s = 0; s < c->timed_steps; ++s) {
-        hipEvent_t *e = &c->events[5 * (size_t)s];
-        for (int k = 0; k < 4; ++k) {
+        hipEvent_t *e = &c->events[7 * (size_t)s];
+        for (int k = 0; k < 5; ++k) {
             float t = 0.f;
-            if (hipEventElapsedTime(&t, e[k], e[k + 1]) != hipSuccess)
+            const int a = k < 4 ? k : 5;  // ms[4]: events 5 .. 6
+            if (hipEventElapsedTime(&t, e[a], e[a + 1]) != hipSuccess)
                 return set_error(BH_E_DEVICE, "hipEventElapsedTime failed");
             ms[k] += t;
         }

@@ -100,8 +100,9 @@ struct bh_ctx {
     bh::DevBuf scratch;              // direct-sum partials
     // phase timing of simulation steps
     bool timing = false;
-    std::vector<hipEvent_t> events;  // 5 per recorded step
+    std::vector<hipEvent_t> events;  // 7 per recorded step
     int64_t timed_steps = 0;
+    hipEvent_t *walk_ev = nullptr;   // set during a timed step: around the walk kernel
 };
 
 struct bh_tree {

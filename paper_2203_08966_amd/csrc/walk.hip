@@ -256,10 +256,12 @@ void launch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, voi
     const int nw = div_up(t1 - t0, 64);
     const int nblk = div_up(nw, 4);
     const int nblk_pad = div_up(nblk, 64) * 64;
+    if (t->ctx->walk_ev) hipEventRecord(t->ctx->walk_ev[0], t->ctx->stream);
     k_walk<R, ORDER2, PHI, CNT, SORTED, MLP><<<nblk_pad, 256, 0, t->ctx->stream>>>(
         (const typename NodeRecT<R>::type *)t->recs.p, (int)t->m,
         (const BodyRec<R> *)t->bodies.p, (const Anchor<R> *)t->anchors.p, t->perm, (int)t->n, t0,
         t1, nblk_pad * 4, (R)(theta * theta), (R)(eps * eps), (R *)acc, (R *)phi, npp, npc, mac);
+    if (t->ctx->walk_ev) hipEventRecord(t->ctx->walk_ev[1], t->ctx->stream);
 }
 
 template <typename R, bool ORDER2, bool MLP>
@@ -724,12 +726,14 @@ void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, vo
                                                       (uint32_t *)t->gorder.p);
         g2.gorder = (const uint32_t *)t->gorder.p;
     }
+    if (t->ctx->walk_ev) hipEventRecord(t->ctx->walk_ev[0], t->ctx->stream);
     k_gwalk<R, ORDER2, PHI, CNT, SORTED, BUDGET><<<8 * per_xcd, 256, 0, t->ctx->stream>>>(
         (const typename NodeRecT<R>::type *)t->recs.p, (int)t->m,
         (const BodyRec<R> *)t->bodies.p, (const Anchor<R> *)t->anchors.p,
         (const int4 *)t->kids.p, t->perm, (int)t->n, t0, t1, queue, (R)(theta * theta),
         (R)(eps * eps), (R *)acc, (R *)phi, npp, npc, g2, (const int8_t *)t->delta.p,
         (const int32_t *)t->level.p);
+    if (t->ctx->walk_ev) hipEventRecord(t->ctx->walk_ev[1], t->ctx->stream);
 }
 
 template <typename R, bool ORDER2, bool BUDGET>

@@ -55,8 +55,13 @@ def test_leapfrog_fp32_short_run(ctx):
     P, V, M = (torch.from_numpy(a).cuda() for a in (pos, vel, mass))
     B.bh_sim_init(ctx, P, V, M, leaf, theta, eps)
     e0 = sum(B.bh_energy(ctx))
+    B.bh_sim_timing(ctx, True)
     for _ in range(5):
         B.bh_leapfrog_step(ctx, dt)
+    ms, steps = B.bh_sim_timing_get(ctx)
+    B.bh_sim_timing(ctx, False)
+    # phases: kick+drift, build, walk (with set-up), kick, walk kernel alone
+    assert steps == 5 and all(t > 0 for t in ms) and ms[4] <= ms[2]
     x = torch.empty_like(P)
     v = torch.empty_like(V)
     B.bh_sim_get(ctx, x, v)

@@ -128,7 +128,10 @@ struct bh_tree {
     bh::DevBuf cellf, kc, anorm, est_acc;
     bh::DevBuf kids;                           // group walk: children per node
     bh::DevBuf wq;                             // group walk: queue counters
-    bh::DevBuf gorder;                         // group walk: hand-out order of the groups
+    bh::DevBuf gorder;                         // group walk: work items in hand-out order
+    bh::DevBuf gfb;                            // group walk: per-group fallback prediction
+    uint64_t gfb_sig = 0;                      //   parameters it was made with
+    int64_t gfb_ng = -1;                       //   and group count
     int64_t kids_tree_id = -1;
     int kc_version = -2;
     double kc_eps = -1.0;

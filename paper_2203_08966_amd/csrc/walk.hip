@@ -312,8 +312,19 @@ struct GroupMac {
     float tau;
     int cap;             // stack entries used (<= kGroupStack)
     int work_cap;        // per-group work above which the group walks per body
-    const uint32_t *gorder;  // order in which to hand out the groups, or null
+    // work items in hand-out order, per XCD chunk of groups (chunk c's at
+    // 4 * its first group): 8 g + 4 walks group g, 8 g + q (q < 4) walks
+    // lanes 16 q .. 16 q + 15 of group g per body; or null: groups in order
+    const uint32_t *items;
+    // per group: further walks for which the group is predicted to exceed
+    // the work cap (written when a one-run group does), or null
+    uint8_t *gfb;
 };
+
+// Walks for which a group that exceeded the work cap is walked per body
+// straight away (its four quarters as separate items) before the group walk
+// is tried again.
+constexpr int kPredictWalks = 3;
 
 template <typename R>
 __device__ __forceinline__ R wave_min(R v) {
@@ -338,19 +349,20 @@ enum : int { kGNone = 0, kGPC = 1, kGPP = 2, kGOpen = 3 };
 
 // One group: the 64 bodies of sorted rank [base, min(base + 64, t1)).
 template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool BUDGET>
-__device__ __forceinline__ void group_walk(
+__device__ __forceinline__ auto group_walk(
     const typename NodeRecT<R>::type *__restrict__ nodes, int m,
     const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
     const int4 *__restrict__ kids, const uint32_t *__restrict__ perm, int nbodies, int base,
     int t1, R theta2, R eps2, R *__restrict__ acc, R *__restrict__ phi_out,
     uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out, const GroupMac &gm,
     int *__restrict__ stk, R *__restrict__ stage, const int8_t *__restrict__ delta,
-    const int32_t *__restrict__ level) {
+    const int32_t *__restrict__ level) -> bool {
     using Rec = typename NodeRecT<R>::type;
     const int lane = (int)lane_id();
     const int i = base + lane;
     const bool live = i < t1;
     const int g_end = min(base + 64, t1);
+    int runs = 0, over = 0;  // runs walked, runs over the work cap
 
     R ox = 0, oy = 0, oz = 0, ax = 0, ay = 0, az = 0;
     int myleaf = -1;
@@ -585,6 +597,8 @@ __device__ __forceinline__ void group_walk(
             }
         }
         const bool per_body = work > gm.work_cap;
+        ++runs;
+        over += per_body ? 1 : 0;
         if (per_body) {  // too spread out for one decision: walk per body
             sx = sy = sz = sp = 0;
             cpp = cpc = 0;
@@ -619,6 +633,53 @@ __device__ __forceinline__ void group_walk(
         pass(lo, hi);
         lo = hi;
     }
+    return runs == 1 && over == 1;  // one run, walked per body
+}
+
+// Per-body walk of lanes q0 .. q0 + 15 of the group at rank base (one
+// quarter of a group predicted to exceed the work cap); the other lanes
+// idle.  Each body's walk is the per-body walk's, whichever bodies share
+// the wavefront.
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool BUDGET>
+__device__ __forceinline__ void quarter_walk(
+    const typename NodeRecT<R>::type *__restrict__ nodes, int m,
+    const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
+    const uint32_t *__restrict__ perm, int nbodies, int base, int q0, int t1, R theta2, R eps2,
+    R *__restrict__ acc, R *__restrict__ phi_out, uint32_t *__restrict__ npp_out,
+    uint32_t *__restrict__ npc_out, const GroupMac &gm) {
+    const int lane = (int)lane_id();
+    const bool live = lane < 16 && base + q0 + lane < t1;
+    const int i = live ? base + q0 + lane : base;  // idle lanes: any rank of the group
+    R ox = 0, oy = 0, oz = 0, ax = 0, ay = 0, az = 0;
+    int myleaf = -1;
+    if (live) {
+        const BodyRec<R> me = bodies[i];
+        ox = me.x;
+        oy = me.y;
+        oz = me.z;
+        const Anchor<R> an = anchors[i];
+        ax = an.x;
+        ay = an.y;
+        az = an.z;
+        myleaf = an.leaf;
+    }
+    R sx = 0, sy = 0, sz = 0, sp = 0;
+    uint32_t cpp = 0, cpc = 0;
+    const MlpMac pm{gm.kc, gm.anorm, gm.afloor, (float)theta2, gm.tau};
+    body_sweep<R, ORDER2, PHI, CNT, BUDGET, true>(nodes, m, bodies, nbodies, i, live, ox, oy, oz,
+                                                  ax, ay, az, myleaf, theta2, eps2, pm, sx, sy, sz,
+                                                  sp, cpp, cpc);
+    if (live) {
+        const int o = SORTED_OUT ? i : (int)perm[i];
+        acc[3 * (int64_t)o + 0] = sx;
+        acc[3 * (int64_t)o + 1] = sy;
+        acc[3 * (int64_t)o + 2] = sz;
+        if (PHI) phi_out[o] = sp;
+        if (CNT) {
+            npp_out[o] = cpp;
+            npc_out[o] = cpc;
+        }
+    }
 }
 
 // Groups are handed out dynamically: the groups are split into 8
@@ -644,15 +705,29 @@ __global__ __launch_bounds__(256) void k_gwalk(
     const int chunk = (ng + 7) / 8;
     const int g_lo = xcd * chunk, g_hi = min(ng, g_lo + chunk);
     uint32_t *ctr = queue + 64 * xcd;  // one counter per 256 bytes
+    // item count of the chunk (written by the ordering kernel), or groups
+    const int n_items = gm.items ? (int)queue[64 * xcd + 16] : g_hi - g_lo;
     for (;;) {
         uint32_t slot = 0;
         if (lane_id() == 0) slot = atomicAdd(ctr, 1u);
-        const int gi = g_lo + (int)__builtin_amdgcn_readfirstlane(slot);
-        if (gi >= g_hi) break;
-        const int g = gm.gorder ? (int)gm.gorder[gi] : gi;
-        group_walk<R, ORDER2, PHI, CNT, SORTED_OUT, BUDGET>(
+        const int gi = (int)__builtin_amdgcn_readfirstlane(slot);
+        if (gi >= n_items) break;
+        int g = g_lo + gi, code = 4;
+        if (gm.items) {
+            const uint32_t it = gm.items[4 * (size_t)g_lo + gi];
+            g = (int)(it >> 3);
+            code = (int)(it & 7u);
+        }
+        if (code < 4) {
+            quarter_walk<R, ORDER2, PHI, CNT, SORTED_OUT, BUDGET>(
+                nodes, m, bodies, anchors, perm, nbodies, t0 + 64 * g, 16 * code, t1, theta2, eps2,
+                acc, phi_out, npp_out, npc_out, gm);
+            continue;
+        }
+        const bool fell = group_walk<R, ORDER2, PHI, CNT, SORTED_OUT, BUDGET>(
             nodes, m, bodies, anchors, kids, perm, nbodies, t0 + 64 * g, t1, theta2, eps2, acc,
             phi_out, npp_out, npc_out, gm, stk, stage, delta, level);
+        if (fell && gm.gfb && lane_id() == 0) gm.gfb[g] = (uint8_t)kPredictWalks;
     }
 }
 
@@ -678,14 +753,19 @@ __device__ __forceinline__ int64_t lower_key(const uint64_t *__restrict__ k, int
 
 __global__ __launch_bounds__(1024) void k_group_order(const uint64_t *__restrict__ keys,
                                                       int64_t n, int t0, int t1, int ng,
-                                                      uint32_t *__restrict__ gorder) {
-    __shared__ uint32_t cnt[3], pos[3];
+                                                      uint8_t *__restrict__ gfb,
+                                                      uint32_t *__restrict__ items,
+                                                      uint32_t *__restrict__ queue) {
+    // classes: 3 predicted to exceed the work cap (four quarter items, first),
+    // then 0, 1, 2 by spread
+    __shared__ uint32_t cnt[4], pos[4];
     __shared__ uint8_t cls_s[4096];
     const int chunk = (ng + 7) / 8;
     const int lo = blockIdx.x * chunk, hi = min(ng, lo + chunk);
-    if (threadIdx.x < 3) cnt[threadIdx.x] = pos[threadIdx.x] = 0;
+    if (threadIdx.x < 4) cnt[threadIdx.x] = pos[threadIdx.x] = 0;
     __syncthreads();
     auto cls = [&](int g) {
+        if (gfb && gfb[g] > 0) return 3;
         const uint64_t a = keys[t0 + 64 * (int64_t)g];
         const uint64_t b = keys[min(t0 + 64 * (int64_t)g + 63, (int64_t)t1 - 1)];
         const uint64_t x = a ^ b;
@@ -699,21 +779,42 @@ __global__ __launch_bounds__(1024) void k_group_order(const uint64_t *__restrict
     for (int g = lo + threadIdx.x; g < hi; g += blockDim.x) {
         const int c = cls(g);
         if (g - lo < 4096) cls_s[g - lo] = (uint8_t)c;
-        atomicAdd(&cnt[c], 1u);
+        atomicAdd(&cnt[c], c == 3 ? 4u : 1u);
     }
     __syncthreads();
+    if (threadIdx.x == 0) queue[64 * blockIdx.x + 16] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+    uint32_t *out = items + 4 * (size_t)lo;  // at most 4 items per group
     for (int g = lo + threadIdx.x; g < hi; g += blockDim.x) {
         const int c = g - lo < 4096 ? cls_s[g - lo] : cls(g);
-        const uint32_t base = c == 0 ? 0u : (c == 1 ? cnt[0] : cnt[0] + cnt[1]);
-        gorder[lo + base + atomicAdd(&pos[c], 1u)] = (uint32_t)g;
+        const uint32_t base = c == 3 ? 0u
+                            : c == 0 ? cnt[3]
+                            : c == 1 ? cnt[3] + cnt[0]
+                                     : cnt[3] + cnt[0] + cnt[1];
+        if (c == 3) {
+            const uint32_t p = base + atomicAdd(&pos[3], 4u);
+            for (int q = 0; q < 4; ++q) out[p + q] = (uint32_t)g * 8u + (uint32_t)q;
+        } else {
+            out[base + atomicAdd(&pos[c], 1u)] = (uint32_t)g * 8u + 4u;
+        }
     }
+    __syncthreads();
+    // one prediction used up (after every class has been read)
+    if (gfb)
+        for (int g = lo + threadIdx.x; g < hi; g += blockDim.x)
+            if (gfb[g] > 0) gfb[g] = (uint8_t)(gfb[g] - 1);
+}
+
+__global__ void k_zero_bytes(uint8_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
 
 __global__ void k_zero_queue(uint32_t *q) { q[threadIdx.x * 64] = 0u; }
 
 template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED, bool BUDGET>
 void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
-             uint32_t *npp, uint32_t *npc, const GroupMac &gm) {
+             uint32_t *npp, uint32_t *npc, const GroupMac &gm, uint64_t sig) {
     // enough workgroups to fill every CU (8 per CU at this kernel's
     // register and LDS use), or fewer for small target ranges
     const int ng = div_up(t1 - t0, 64);
@@ -721,10 +822,22 @@ void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, vo
     uint32_t *queue = (uint32_t *)t->wq.p;
     k_zero_queue<<<1, 8, 0, t->ctx->stream>>>(queue);
     GroupMac g2 = gm;
-    if (grow(t->gorder, 4ull * ng) == BH_OK) {
-        k_group_order<<<8, 1024, 0, t->ctx->stream>>>(t->sorted_keys, t->n, t0, t1, ng,
-                                                      (uint32_t *)t->gorder.p);
-        g2.gorder = (const uint32_t *)t->gorder.p;
+    // fallback predictions hold for walks of this tree object with the same
+    // parameters and targets
+    uint8_t *gfb = nullptr;
+    if (grow(t->gfb, (size_t)ng) == BH_OK) {
+        gfb = (uint8_t *)t->gfb.p;
+        if (t->gfb_sig != sig || t->gfb_ng != ng) {
+            k_zero_bytes<<<std::min(div_up(ng, 256), 1024), 256, 0, t->ctx->stream>>>(gfb, ng);
+            t->gfb_sig = sig;
+            t->gfb_ng = ng;
+        }
+    }
+    if (grow(t->gorder, 16ull * ng) == BH_OK) {
+        k_group_order<<<8, 1024, 0, t->ctx->stream>>>(t->sorted_keys, t->n, t0, t1, ng, gfb,
+                                                      (uint32_t *)t->gorder.p, queue);
+        g2.items = (const uint32_t *)t->gorder.p;
+        g2.gfb = gfb;
     }
     if (t->ctx->walk_ev) hipEventRecord(t->ctx->walk_ev[0], t->ctx->stream);
     k_gwalk<R, ORDER2, PHI, CNT, SORTED, BUDGET><<<8 * per_xcd, 256, 0, t->ctx->stream>>>(
@@ -738,9 +851,9 @@ void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, vo
 
 template <typename R, bool ORDER2, bool BUDGET>
 void gdispatch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
-               uint32_t *npp, uint32_t *npc, bool sorted, const GroupMac &gm) {
+               uint32_t *npp, uint32_t *npc, bool sorted, const GroupMac &gm, uint64_t sig) {
     const bool P = phi != nullptr, C = npp != nullptr;
-#define BH_G(p, c, s) glaunch<R, ORDER2, p, c, s, BUDGET>(t, t0, t1, theta, eps, acc, phi, npp, npc, gm)
+#define BH_G(p, c, s) glaunch<R, ORDER2, p, c, s, BUDGET>(t, t0, t1, theta, eps, acc, phi, npp, npc, gm, sig)
     if (sorted) {
         if (P) BH_G(true, false, true);
         else BH_G(false, false, true);
@@ -782,7 +895,24 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
         if (rc) return rc;
     }
     GroupMac gm{nullptr, nullptr, nullptr, 0.f, o.walk_stack > 0 ? o.walk_stack : kGroupStack,
-                o.walk_cap > 0 ? o.walk_cap : kGroupWorkCap, nullptr};
+                o.walk_cap > 0 ? o.walk_cap : kGroupWorkCap, nullptr, nullptr};
+    // the parameters that decide which groups exceed the work cap (FNV-1a)
+    uint64_t sig = 1469598103934665603ull;
+    auto mixin = [&](const void *p, size_t len) {
+        for (size_t k = 0; k < len; ++k) {
+            sig ^= ((const unsigned char *)p)[k];
+            sig *= 1099511628211ull;
+        }
+    };
+    {
+        const double dv[6] = {theta, eps, o.mlp_theta_max, o.mlp_log10_tau, o.mlp_acc_floor,
+                              (double)o.walk_cap};
+        const int64_t iv[6] = {o.mac, o.order, t0, t1, t->dtype,
+                               o.mac == BH_MAC_MLP ? t->ctx->mlp_version : 0};
+        mixin(dv, sizeof dv);
+        mixin(iv, sizeof iv);
+        sig |= 1ull << 63;  // never the unset value 0
+    }
     if (o.mac == BH_MAC_MLP || o.mac == BH_MAC_BUDGET) {
         if (t->dtype != BH_F32 || o.order != 2)
             return set_error(BH_E_INVALID, "the learned criterion runs in the FP32 quadrupole walk");
@@ -820,18 +950,18 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
             gm.afloor = mac.afloor;
             gm.tau = mac.tau;
             gdispatch<float, true, true>(t, t0, t1, o.mlp_theta_max, eps, acc, phi, npp, npc,
-                                         sorted_out, gm);
+                                         sorted_out, gm, sig);
         } else {
             dispatch2<float, true, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out,
                                          mac);
         }
     } else if (group) {
         if (t->dtype == BH_F32) {
-            if (o.order == 0) gdispatch<float, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm);
-            else gdispatch<float, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm);
+            if (o.order == 0) gdispatch<float, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
+            else gdispatch<float, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
         } else {
-            if (o.order == 0) gdispatch<double, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm);
-            else gdispatch<double, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm);
+            if (o.order == 0) gdispatch<double, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
+            else gdispatch<double, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
         }
     } else if (t->dtype == BH_F32) {
         if (o.order == 0) dispatch2<float, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);

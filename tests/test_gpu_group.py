@@ -212,8 +212,9 @@ def test_group_walk_work_cap(ctx, mode):
 
 
 def test_group_walk_repeat_is_bitwise_identical(ctx):
-    """A second walk of the same tree hands the groups out in the order of
-    the first walk's costs; every group's result is unchanged bit for bit."""
+    """Later walks of the same tree with the same parameters walk the groups
+    that exceeded the work cap per body straight away (the prediction made
+    by the first walk); every result is unchanged bit for bit."""
     pos, _, mass = case_bodies("clumpy", 30000, 17, np.float32)
     P, M = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
     t = B.bh_build(ctx, P, M, 16)
@@ -230,3 +231,43 @@ def test_group_walk_repeat_is_bitwise_identical(ctx):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
+
+
+def test_group_walk_prediction_after_rebuild(ctx):
+    """After the tree object is rebuilt from moved bodies, a group predicted
+    (by the previous walk) to exceed the work cap is walked per body even if
+    it would now fit: every body's result is either the oracle's group-walk
+    result or its per-body walk result at the same theta, and both occur."""
+    pos, _, mass = case_bodies("clumpy", 20000, 16, np.float32)
+    eps, cap, theta = 0.005, 2500, 0.7
+    P, M = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
+    t = B.bh_build(ctx, P, M, 16)
+    n = len(mass)
+    acc = torch.empty_like(P)
+    npp = torch.zeros(n, dtype=torch.int32, device="cuda")
+    npc = torch.zeros(n, dtype=torch.int32, device="cuda")
+    o = B.force_opts(walk=B.BH_WALK_GROUP, walk_cap=cap, n_pp=npp, n_pc=npc)
+    B.bh_forces(t, theta, eps, acc, o)  # makes the predictions
+    rng = np.random.default_rng(5)
+    pos2 = (pos + rng.normal(0, 1e-2, pos.shape)).astype(np.float32)
+    P2 = torch.from_numpy(pos2).cuda()
+    B.bh_build(ctx, P2, M, 16, tree=t)
+    B.bh_forces(t, theta, eps, acc, o)
+    torch.cuda.synchronize()
+    B.bh_tree_free(t)
+    ref = oracle.build_all(pos2.astype(np.float64), mass.astype(np.float64), 16)
+    p = ref["perm"]
+    a = acc.cpu().numpy().astype(np.float64)[p]
+    cp, cc = npp.cpu().numpy()[p], npc.cpu().numpy()[p]
+    rg = oracle.walk_group(ref, eps, group=64, theta=theta, tol=FLAG_TOL[np.float32], cap=cap)
+    rb = oracle.walk(ref["tree"], ref["mom"], ref["spos"], ref["smass"], ref["L"], theta, eps)
+
+    def same(r):
+        e = np.linalg.norm(a - r.acc, axis=1) / np.linalg.norm(r.acc, axis=1)
+        return (cp == r.npp) & (cc == r.npc) & (e <= TOL[np.float32][1])
+    sg, sb = same(rg), same(rb)
+    only_b = sb & ~sg
+    say(f"  group-walk results {sg.mean():.3f}, per-body only {only_b.mean():.3f}")
+    assert np.mean(sg | sb) >= 0.99
+    assert only_b.mean() > 0.005  # predicted groups walked per body
+    assert sg.mean() > 0.5

@@ -95,7 +95,13 @@ typedef struct {
     int walk_cap;             /* group walk: a group whose work (particle-cell
                                  terms + particle-particle bodies, per body)
                                  would exceed this is walked per body with the
-                                 same criterion; 0 = 4096 */
+                                 same criterion; 0 = 4096.  A group (of one
+                                 run) that did is walked per body straight
+                                 away in the next 15 walks of the same tree
+                                 object with the same parameters and targets,
+                                 also after the tree is rebuilt in place: a
+                                 simulation step may then walk such a group
+                                 per body although it would now fit. */
     double mlp_acc_floor;     /* BH_MAC_MLP / BH_MAC_BUDGET: |a_i| in the test
                                  is replaced by max(|a_i|, f <|a|>), f this
                                  value (>= 0) and <|a|> the mean of the n

@@ -313,8 +313,9 @@ struct GroupMac {
     int cap;             // stack entries used (<= kGroupStack)
     int work_cap;        // per-group work above which the group walks per body
     // work items in hand-out order, per XCD chunk of groups (chunk c's at
-    // 4 * its first group): 8 g + 4 walks group g, 8 g + q (q < 4) walks
-    // lanes 16 q .. 16 q + 15 of group g per body; or null: groups in order
+    // kParts * its first group): 16 g + 15 walks group g, 16 g + q
+    // (q < kParts) walks lanes kPartLanes q .. kPartLanes (q + 1) - 1 of
+    // group g per body; or null: groups in index order
     const uint32_t *items;
     // per group: further walks for which the group is predicted to exceed
     // the work cap (written when a one-run group does), or null
@@ -322,9 +323,12 @@ struct GroupMac {
 };
 
 // Walks for which a group that exceeded the work cap is walked per body
-// straight away (its four quarters as separate items) before the group walk
-// is tried again.
-constexpr int kPredictWalks = 3;
+// straight away (in parts of kPartLanes bodies, separate items) before the
+// group walk is tried again.
+constexpr int kPredictWalks = 15;
+constexpr int kPartLanes = 16;
+constexpr int kParts = 64 / kPartLanes;
+constexpr uint32_t kWholeGroup = 15;
 
 template <typename R>
 __device__ __forceinline__ R wave_min(R v) {
@@ -636,19 +640,19 @@ __device__ __forceinline__ auto group_walk(
     return runs == 1 && over == 1;  // one run, walked per body
 }
 
-// Per-body walk of lanes q0 .. q0 + 15 of the group at rank base (one
-// quarter of a group predicted to exceed the work cap); the other lanes
-// idle.  Each body's walk is the per-body walk's, whichever bodies share
+// Per-body walk of lanes q0 .. q0 + kPartLanes - 1 of the group at rank
+// base (one part of a group predicted to exceed the work cap); the other
+// lanes idle.  Each body's walk is the per-body walk's, whichever bodies share
 // the wavefront.
 template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool BUDGET>
-__device__ __forceinline__ void quarter_walk(
+__device__ __forceinline__ void part_walk(
     const typename NodeRecT<R>::type *__restrict__ nodes, int m,
     const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
     const uint32_t *__restrict__ perm, int nbodies, int base, int q0, int t1, R theta2, R eps2,
     R *__restrict__ acc, R *__restrict__ phi_out, uint32_t *__restrict__ npp_out,
     uint32_t *__restrict__ npc_out, const GroupMac &gm) {
     const int lane = (int)lane_id();
-    const bool live = lane < 16 && base + q0 + lane < t1;
+    const bool live = lane < kPartLanes && base + q0 + lane < t1;
     const int i = live ? base + q0 + lane : base;  // idle lanes: any rank of the group
     R ox = 0, oy = 0, oz = 0, ax = 0, ay = 0, az = 0;
     int myleaf = -1;
@@ -712,16 +716,16 @@ __global__ __launch_bounds__(256) void k_gwalk(
         if (lane_id() == 0) slot = atomicAdd(ctr, 1u);
         const int gi = (int)__builtin_amdgcn_readfirstlane(slot);
         if (gi >= n_items) break;
-        int g = g_lo + gi, code = 4;
+        int g = g_lo + gi, code = (int)kWholeGroup;
         if (gm.items) {
-            const uint32_t it = gm.items[4 * (size_t)g_lo + gi];
-            g = (int)(it >> 3);
-            code = (int)(it & 7u);
+            const uint32_t it = gm.items[kParts * (size_t)g_lo + gi];
+            g = (int)(it >> 4);
+            code = (int)(it & 15u);
         }
-        if (code < 4) {
-            quarter_walk<R, ORDER2, PHI, CNT, SORTED_OUT, BUDGET>(
-                nodes, m, bodies, anchors, perm, nbodies, t0 + 64 * g, 16 * code, t1, theta2, eps2,
-                acc, phi_out, npp_out, npc_out, gm);
+        if (code < kParts) {
+            part_walk<R, ORDER2, PHI, CNT, SORTED_OUT, BUDGET>(
+                nodes, m, bodies, anchors, perm, nbodies, t0 + 64 * g, kPartLanes * code, t1,
+                theta2, eps2, acc, phi_out, npp_out, npc_out, gm);
             continue;
         }
         const bool fell = group_walk<R, ORDER2, PHI, CNT, SORTED_OUT, BUDGET>(
@@ -756,8 +760,8 @@ __global__ __launch_bounds__(1024) void k_group_order(const uint64_t *__restrict
                                                       uint8_t *__restrict__ gfb,
                                                       uint32_t *__restrict__ items,
                                                       uint32_t *__restrict__ queue) {
-    // classes: 3 predicted to exceed the work cap (four quarter items, first),
-    // then 0, 1, 2 by spread
+    // classes: 3 predicted to exceed the work cap (kParts items, first), then
+    // 0, 1, 2 by spread
     __shared__ uint32_t cnt[4], pos[4];
     __shared__ uint8_t cls_s[4096];
     const int chunk = (ng + 7) / 8;
@@ -779,11 +783,11 @@ __global__ __launch_bounds__(1024) void k_group_order(const uint64_t *__restrict
     for (int g = lo + threadIdx.x; g < hi; g += blockDim.x) {
         const int c = cls(g);
         if (g - lo < 4096) cls_s[g - lo] = (uint8_t)c;
-        atomicAdd(&cnt[c], c == 3 ? 4u : 1u);
+        atomicAdd(&cnt[c], c == 3 ? (uint32_t)kParts : 1u);
     }
     __syncthreads();
     if (threadIdx.x == 0) queue[64 * blockIdx.x + 16] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
-    uint32_t *out = items + 4 * (size_t)lo;  // at most 4 items per group
+    uint32_t *out = items + kParts * (size_t)lo;  // at most kParts items per group
     for (int g = lo + threadIdx.x; g < hi; g += blockDim.x) {
         const int c = g - lo < 4096 ? cls_s[g - lo] : cls(g);
         const uint32_t base = c == 3 ? 0u
@@ -791,10 +795,10 @@ __global__ __launch_bounds__(1024) void k_group_order(const uint64_t *__restrict
                             : c == 1 ? cnt[3] + cnt[0]
                                      : cnt[3] + cnt[0] + cnt[1];
         if (c == 3) {
-            const uint32_t p = base + atomicAdd(&pos[3], 4u);
-            for (int q = 0; q < 4; ++q) out[p + q] = (uint32_t)g * 8u + (uint32_t)q;
+            const uint32_t p = base + atomicAdd(&pos[3], (uint32_t)kParts);
+            for (int q = 0; q < kParts; ++q) out[p + q] = (uint32_t)g * 16u + (uint32_t)q;
         } else {
-            out[base + atomicAdd(&pos[c], 1u)] = (uint32_t)g * 8u + 4u;
+            out[base + atomicAdd(&pos[c], 1u)] = (uint32_t)g * 16u + kWholeGroup;
         }
     }
     __syncthreads();
@@ -833,7 +837,7 @@ void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, vo
             t->gfb_ng = ng;
         }
     }
-    if (grow(t->gorder, 16ull * ng) == BH_OK) {
+    if (grow(t->gorder, 4ull * kParts * ng) == BH_OK) {
         k_group_order<<<8, 1024, 0, t->ctx->stream>>>(t->sorted_keys, t->n, t0, t1, ng, gfb,
                                                       (uint32_t *)t->gorder.p, queue);
         g2.items = (const uint32_t *)t->gorder.p;

@@ -739,22 +739,12 @@ __global__ __launch_bounds__(256) void k_gwalk(
 // the space-filling curve has a box spanning the cells on both sides and
 // costs many times an ordinary group; such groups are recognised by the
 // smallest cell holding the group's first and last keys: the more bodies
-// that cell holds (two binary searches in the sorted keys), the more the
+// that cell holds (counted by galloping outwards from the group in the
+// sorted keys, up to the largest threshold), the more the
 // group is spread out.  Within each XCD's chunk, groups whose common cell
 // holds more than 256 x 64 bodies come first, then those above 16 x 64,
 // then the rest (order inside a class is immaterial: groups are
 // independent).  One block per chunk.
-__device__ __forceinline__ int64_t lower_key(const uint64_t *__restrict__ k, int64_t n,
-                                             uint64_t v) {
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (k[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
 __global__ __launch_bounds__(1024) void k_group_order(const uint64_t *__restrict__ keys,
                                                       int64_t n, int t0, int t1, int ng,
                                                       uint8_t *__restrict__ gfb,
@@ -770,15 +760,33 @@ __global__ __launch_bounds__(1024) void k_group_order(const uint64_t *__restrict
     __syncthreads();
     auto cls = [&](int g) {
         if (gfb && gfb[g] > 0) return 3;
-        const uint64_t a = keys[t0 + 64 * (int64_t)g];
-        const uint64_t b = keys[min(t0 + 64 * (int64_t)g + 63, (int64_t)t1 - 1)];
-        const uint64_t x = a ^ b;
+        const int64_t r0 = t0 + 64 * (int64_t)g, r1 = min(r0 + 63, (int64_t)t1 - 1);
+        const uint64_t a = keys[r0];
+        const uint64_t x = a ^ keys[r1];
         const int lcp = x == 0 ? 21 : (__builtin_clzll(x) - 1) / 3;  // shared octal digits
         const int sh = 3 * (21 - lcp);  // 0..63; keys are below 2^63
-        const uint64_t first = (a >> sh) << sh;
-        const uint64_t end = first + (1ull << sh);  // first key after the cell
-        const int64_t c = lower_key(keys, n, end) - lower_key(keys, n, first);
-        return c > 256 * 64 ? 0 : (c > 16 * 64 ? 1 : 2);
+        const uint64_t pre = a >> sh;   // the cell's key prefix
+        // bodies of the cell beyond the group on either side, counted by
+        // galloping outwards up to the largest threshold
+        constexpr int64_t kBig = 256 * 64;
+        auto reach = [&](int64_t from, int dir) -> int64_t {
+            int64_t in = 0, step = 1;
+            for (;;) {  // keys[from + dir * in] is inside the cell
+                const int64_t j = from + dir * (in + step);
+                if (j < 0 || j >= n || (keys[j] >> sh) != pre) break;
+                in += step;
+                if (in > kBig) return in;
+                step <<= 1;
+            }
+            while (step > 1) {  // inside at in, outside (or beyond n) at in + step
+                step >>= 1;
+                const int64_t j = from + dir * (in + step);
+                if (j >= 0 && j < n && (keys[j] >> sh) == pre) in += step;
+            }
+            return in;
+        };
+        const int64_t c = (r1 - r0 + 1) + reach(r0, -1) + reach(r1, 1);
+        return c > kBig ? 0 : (c > 16 * 64 ? 1 : 2);
     };
     for (int g = lo + threadIdx.x; g < hi; g += blockDim.x) {
         const int c = cls(g);

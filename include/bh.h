@@ -63,6 +63,12 @@ enum {
     BH_MAC_BUDGET = 2  /* the same error budget with k_C = 1 (no network) */
 };
 
+/* Arithmetic of the network's inference (MFMA operands; FP32 accumulate). */
+enum {
+    BH_MLP_BF16 = 0,
+    BH_MLP_FP16 = 1
+};
+
 typedef struct bh_ctx bh_ctx;
 typedef struct bh_tree bh_tree;
 
@@ -110,6 +116,8 @@ typedef struct {
                                  budget then bounds the error relative to the
                                  larger of the body's and f times the mean
                                  acceleration.  Default 0 (none). */
+    int mlp_precision;        /* BH_MAC_MLP: BH_MLP_BF16 (default) or
+                                 BH_MLP_FP16 operands of the network */
 } bh_force_opts;
 
 /* Library version string. */
@@ -240,10 +248,11 @@ int bh_direct(bh_ctx *ctx, const void *pos, const void *mass, int dtype, int64_t
  * The error of a cell's quadrupole particle-cell term on body i is modelled
  * as k_C (l/d)^3 M/d^2.  A network 10 -> 32 (ReLU) -> 32 (ReLU) -> 1
  * predicts log10 k_C from the cell alone; it is evaluated once per cell
- * (bf16 MFMA, 64 cells per wavefront) and the walk accepts as described at
- * bh_force_opts.  Parameters (BH_MLP_PARAMS doubles, host): W1[32][10]
- * b1[32] W2[32][32] b2[32] w3[32] b3, held on the device as FP32 master
- * weights with Adam state and packed to bf16 operands for inference.
+ * (bf16 or fp16 MFMA, 64 cells per wavefront) and the walk accepts as
+ * described at bh_force_opts.  Parameters (BH_MLP_PARAMS doubles, host):
+ * W1[32][10] b1[32] W2[32][32] b2[32] w3[32] b3, held on the device as FP32
+ * master weights with Adam state and packed to bf16 and fp16 operands for
+ * inference.
  * Cell features (l side, g = COM - centre, M mass, n count,
  * T2 = sum m |y|^2 about the COM, Q traceless quadrupole):
  * |g|/l, sqrt(T2/M)/l, |Q|_F/(M l^2), cbrt(det Q)/(M l^2), max|g_a|/l,
@@ -292,8 +301,10 @@ int bh_mlp_train(bh_ctx *ctx, const float *feat, const float *label, int64_t n,
 int bh_mlp_grad(bh_ctx *ctx, const float *feat, const float *label, int64_t n, double quantile,
                 float *grad, double *loss);
 
-/* bf16 MFMA inference: pred (device f32 n) for feat (device f32 n x 10). */
-int bh_mlp_infer(bh_ctx *ctx, const float *feat, int64_t n, float *pred);
+/* MFMA inference, 64 rows per wavefront, operands in bf16 or fp16
+ * (precision BH_MLP_BF16 / BH_MLP_FP16), FP32 accumulation: pred (device
+ * f32 n) for feat (device f32 n x 10). */
+int bh_mlp_infer(bh_ctx *ctx, const float *feat, int64_t n, int precision, float *pred);
 
 #ifdef __cplusplus
 }

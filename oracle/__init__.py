@@ -263,12 +263,16 @@ def _mac_sigs(lib):
     lib.orc_splitmix64.restype = C.c_uint64
     lib.orc_mlp_bf16.argtypes = [_f64, _f64]
     lib.orc_mlp_bf16.restype = C.c_double
+    lib.orc_mlp_f16.argtypes = [_f64, _f64]
+    lib.orc_mlp_f16.restype = C.c_double
+    lib.orc_f16r.argtypes = [C.c_double]
+    lib.orc_f16r.restype = C.c_double
     lib.orc_mac_samples.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
                                     _f64, _f64, C.c_double, C.c_double, C.c_double, C.c_double,
                                     C.c_double, C.c_uint64, C.c_int64, _i64, C.c_int64, _f64,
                                     _f64, _i32, _i64]
     lib.orc_cell_kc.argtypes = [C.c_int64, _i32, _u64, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
-                                C.c_double, C.c_double, C.c_void_p, _f64]
+                                C.c_double, C.c_double, C.c_void_p, C.c_int, _f64]
     lib.orc_walk_kc.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64, _f64,
                                 C.c_double, C.c_double, C.c_double, C.c_double, _f64, _f64,
                                 C.c_int64, _i64, _f64, _f64, _i64, _i64, _i64, _i32]
@@ -306,6 +310,17 @@ def mlp_bf16(params, f) -> float:
                                       np.ascontiguousarray(f, dtype=np.float64)))
 
 
+def mlp_f16(params, f) -> float:
+    """The network with fp16 operands (IEEE binary16, nearest even)."""
+    return float(_mlib().orc_mlp_f16(np.ascontiguousarray(params, dtype=np.float64),
+                                     np.ascontiguousarray(f, dtype=np.float64)))
+
+
+def f16r(x: float) -> float:
+    """The C oracle's rounding of an FP32 value to binary16."""
+    return float(_mlib().orc_f16r(float(x)))
+
+
 def mac_samples(b, eps, theta_lo, theta_max, keep, seed, targets=None, cap=4096):
     """Training pairs of the bodies ``targets`` (sorted ranks; all by
     default) over a tree from build_all: per target up to ``cap`` kept
@@ -329,8 +344,9 @@ def mac_samples(b, eps, theta_lo, theta_max, keep, seed, targets=None, cap=4096)
     return feat, label, node, cnt
 
 
-def cell_kc(b, eps, params=None):
-    """Per cell k_C M l^3 (k_C = 1 without a network)."""
+def cell_kc(b, eps, params=None, f16=False):
+    """Per cell k_C M l^3 (k_C = 1 without a network; the network's operands
+    in bf16, or fp16 with ``f16``)."""
     lib = _mlib()
     t = b["tree"]
     M, com, Q = b["mom"]
@@ -339,7 +355,7 @@ def cell_kc(b, eps, params=None):
     pp = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
     lib.orc_cell_kc(m, t["level"], t["hkey"], t["count"], t["next"], M, com.ravel(), Q.ravel(),
                     b["trT"], np.ascontiguousarray(b["lo"]), float(b["L"]), float(eps),
-                    None if pp is None else pp.ctypes.data, kc)
+                    None if pp is None else pp.ctypes.data, 1 if f16 else 0, kc)
     return kc
 
 

@@ -117,17 +117,26 @@ def bf16(x):
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def forward_bf16(theta, X):
-    """The network as the bf16 inference evaluates it: features, W1 (with b1)
-    and W2 rounded to bf16, first hidden layer rounded to bf16 after ReLU,
-    b2, w3, b3 and all accumulation in full precision."""
+def f16(x):
+    """Round FP32 values to IEEE binary16 (numpy's conversion: nearest even,
+    subnormals kept, overflow to infinity), returned as float64."""
+    with np.errstate(over="ignore"):  # overflow to infinity is the format's rule
+        return np.asarray(x, dtype=np.float32).astype(np.float16).astype(np.float64)
+
+
+def forward_bf16(theta, X, rnd=None):
+    """The network as the MFMA inference evaluates it: features, W1 (with b1)
+    and W2 rounded to bf16 (or by ``rnd``, e.g. ``f16``), first hidden layer
+    rounded the same way after ReLU, b2, w3, b3 and all accumulation in full
+    precision."""
+    rnd = bf16 if rnd is None else rnd
     p = unpack(theta)
-    W1 = bf16(p["W1"])
-    b1 = bf16(p["b1"])
-    W2 = bf16(p["W2"])
+    W1 = rnd(p["W1"])
+    b1 = rnd(p["b1"])
+    W2 = rnd(p["W2"])
     b2 = np.asarray(p["b2"], dtype=np.float32).astype(np.float64)
     w3 = np.asarray(p["w3"], dtype=np.float32).astype(np.float64)
     b3 = float(np.float32(p["b3"][0]))
-    h1 = bf16(np.maximum(bf16(X) @ W1.T + b1, 0.0))
+    h1 = rnd(np.maximum(rnd(X) @ W1.T + b1, 0.0))
     h2 = np.maximum(h1 @ W2.T + b2, 0.0)
     return h2 @ w3 + b3

@@ -555,28 +555,53 @@ static double bf16r(double x)
     return (double)f;
 }
 
-/* The network as the bf16 inference evaluates it (see oracle/mlp.py):
- * parameters W1[32][10] b1[32] W2[32][32] b2[32] w3[32] b3. */
-double orc_mlp_bf16(const double *p, const double *f)
+/* round an FP32 value to IEEE binary16, nearest even: 11 significant bits
+ * for normal values (|x| >= 2^-14), a fixed spacing of 2^-24 below, and
+ * infinity from 65520 (the midpoint between 65504 and 2^16) up */
+static double f16r(double x)
+{
+    const float f = (float)x;
+    const double a = fabs((double)f);
+    if (a == 0.0 || a != a)
+        return (double)f;
+    if (a >= 65520.0)
+        return copysign(INFINITY, (double)f);
+    int e;
+    frexp(a, &e); /* a = m 2^e, m in [0.5, 1) */
+    int q = e - 11;
+    if (q < -24)
+        q = -24;
+    const double s = ldexp(1.0, q);
+    return copysign(nearbyint(a / s) * s, (double)f);
+}
+
+/* The network as the MFMA inference evaluates it (see oracle/mlp.py), with
+ * rounding rnd of the operands (bf16 or fp16): parameters W1[32][10] b1[32]
+ * W2[32][32] b2[32] w3[32] b3. */
+static double mlp_rounded(const double *p, const double *f, double (*rnd)(double))
 {
     const double *W1 = p, *b1 = p + 320, *W2 = p + 352, *b2 = p + 1376, *w3 = p + 1408;
     const double b3 = (double)(float)p[1440];
     double h1[32], out = 0.0;
     for (int u = 0; u < 32; ++u) {
-        double s = bf16r(b1[u]);
+        double s = rnd(b1[u]);
         for (int k = 0; k < 10; ++k)
-            s += bf16r(W1[u * 10 + k]) * bf16r(f[k]);
-        h1[u] = bf16r(s > 0.0 ? s : 0.0);
+            s += rnd(W1[u * 10 + k]) * rnd(f[k]);
+        h1[u] = rnd(s > 0.0 ? s : 0.0);
     }
     for (int u = 0; u < 32; ++u) {
         double s = (double)(float)b2[u];
         for (int k = 0; k < 32; ++k)
-            s += bf16r(W2[u * 32 + k]) * h1[k];
+            s += rnd(W2[u * 32 + k]) * h1[k];
         if (s > 0.0)
             out += (double)(float)w3[u] * s;
     }
     return out + b3;
 }
+
+double orc_mlp_bf16(const double *p, const double *f) { return mlp_rounded(p, f, bf16r); }
+double orc_mlp_f16(const double *p, const double *f) { return mlp_rounded(p, f, f16r); }
+double orc_f16r(double x) { return f16r(x); }
 
 typedef struct {
     walk_ctx w;
@@ -691,12 +716,12 @@ void orc_mac_samples(const int32_t *level, const uint64_t *hkey, const int32_t *
     }
 }
 
-/* Per cell: k_C M l^3 with log10 k_C from the bf16 network (params) or
- * k_C = 1 (params NULL). */
+/* Per cell: k_C M l^3 with log10 k_C from the network (params; bf16
+ * operands, or fp16 with f16 != 0) or k_C = 1 (params NULL). */
 void orc_cell_kc(int64_t m, const int32_t *level, const uint64_t *hkey, const int32_t *count,
                  const int32_t *next, const double *M, const double *com, const double *Q,
                  const double *trT, const double *lo, double L, double eps, const double *params,
-                 double *kc)
+                 int f16, double *kc)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < m; ++c) {
@@ -707,7 +732,7 @@ void orc_cell_kc(int64_t m, const int32_t *level, const uint64_t *hkey, const in
             cell_centre(hkey[c], level[c], lo, L, centre);
             orc_cell_features(centre, side, &com[3 * c], M[c], &Q[6 * c], trT[c], count[c],
                               next[c] == c + 1, eps, f);
-            lk = orc_mlp_bf16(params, f);
+            lk = f16 ? orc_mlp_f16(params, f) : orc_mlp_bf16(params, f);
         }
         kc[c] = pow(10.0, lk) * M[c] * side * side * side;
     }

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbh.so")
 BH_OK, BH_E_INVALID, BH_E_NOMEM, BH_E_DEVICE, BH_E_STATE, BH_E_NONFINITE = 0, -1, -2, -3, -4, -5
 BH_F32, BH_F64 = 0, 1
 BH_MAC_THETA, BH_MAC_MLP, BH_MAC_BUDGET = 0, 1, 2
+BH_MLP_BF16, BH_MLP_FP16 = 0, 1
 BH_WALK_BODY, BH_WALK_GROUP = 0, 1
 
 EXPORTED = [
@@ -50,7 +51,7 @@ class ForceOpts(C.Structure):
         ("mlp_theta_max", C.c_double), ("mlp_log10_tau", C.c_double),
         ("mlp_acc_norm", C.c_void_p), ("mlp_theta_est", C.c_double),
         ("walk", C.c_int), ("walk_stack", C.c_int), ("walk_cap", C.c_int),
-        ("mlp_acc_floor", C.c_double),
+        ("mlp_acc_floor", C.c_double), ("mlp_precision", C.c_int),
     ]
 
 
@@ -109,7 +110,7 @@ def load(path: str = LIB_PATH):
                             C.POINTER(i64)], i32),
         "bh_mlp_train": ([vp, vp, vp, i64, C.POINTER(MlpTrainCfg), vp], i32),
         "bh_mlp_grad": ([vp, vp, vp, i64, dbl, vp, C.POINTER(dbl)], i32),
-        "bh_mlp_infer": ([vp, vp, i64, vp], i32),
+        "bh_mlp_infer": ([vp, vp, i64, i32, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -164,7 +165,7 @@ def _stream():
 def force_opts(order=2, mac=BH_MAC_THETA, phi=None, n_pp=None, n_pc=None, target_range=None,
                mlp_theta_max=None, mlp_log10_tau=None, mlp_acc_norm=None,
                mlp_theta_est=None, walk=BH_WALK_BODY, walk_stack=0, walk_cap=0,
-               mlp_acc_floor=None) -> ForceOpts:
+               mlp_acc_floor=None, mlp_precision=None) -> ForceOpts:
     """Walk options.  mlp_acc_norm: device tensor of |a_i| in caller order
     and the tree's dtype (kept alive by the caller until the walk ran);
     mlp_acc_floor: f in max(|a_i|, f <|a|>)."""
@@ -189,6 +190,8 @@ def force_opts(order=2, mac=BH_MAC_THETA, phi=None, n_pp=None, n_pc=None, target
     o.walk_cap = walk_cap
     if mlp_acc_floor is not None:
         o.mlp_acc_floor = mlp_acc_floor
+    if mlp_precision is not None:
+        o.mlp_precision = mlp_precision
     return o
 
 
@@ -392,11 +395,12 @@ def bh_mlp_grad(ctx, feat, label, quantile=0.0):
     return g, lv.value
 
 
-def bh_mlp_infer(ctx, feat):
+def bh_mlp_infer(ctx, feat, precision=None):
     import torch
     if feat.dtype != torch.float32 or feat.dim() != 2 or feat.shape[1] != 10:
         raise ValueError("feat must be (n, 10) float32")
     n = int(feat.shape[0])
     pred = torch.empty(n, dtype=torch.float32, device="cuda")
-    _check(load().bh_mlp_infer(ctx, _dev(feat, "feat"), n, _dev(pred, "pred")))
+    prec = BH_MLP_BF16 if precision is None else precision
+    _check(load().bh_mlp_infer(ctx, _dev(feat, "feat"), n, prec, _dev(pred, "pred")))
     return pred

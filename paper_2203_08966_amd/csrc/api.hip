@@ -88,7 +88,8 @@ static int check_opts(const bh_force_opts &o, int64_t n) {
     if (o.mac != BH_MAC_THETA &&
         !(o.mlp_theta_max > 0 && isfinite(o.mlp_theta_max) && isfinite(o.mlp_log10_tau) &&
           o.mlp_theta_est >= 0 && isfinite(o.mlp_theta_est) && o.mlp_acc_floor >= 0 &&
-          isfinite(o.mlp_acc_floor)))
+          isfinite(o.mlp_acc_floor) &&
+          (o.mlp_precision == BH_MLP_BF16 || o.mlp_precision == BH_MLP_FP16)))
         return set_error(BH_E_INVALID, "opts learned-criterion parameters invalid");
     if (o.walk != BH_WALK_BODY && o.walk != BH_WALK_GROUP)
         return set_error(BH_E_INVALID, "opts.walk must be BH_WALK_BODY or BH_WALK_GROUP");
@@ -132,6 +133,7 @@ void bh_force_opts_default(bh_force_opts *o) {
     o->mlp_acc_norm = nullptr;
     o->mlp_theta_est = 0.8;
     o->mlp_acc_floor = 0.0;
+    o->mlp_precision = BH_MLP_BF16;
     o->walk = BH_WALK_BODY;
     o->walk_stack = 0;
     o->walk_cap = 0;
@@ -638,12 +640,14 @@ int bh_mlp_grad(bh_ctx *c, const float *feat, const float *label, int64_t n, dou
     return BH_OK;
 }
 
-int bh_mlp_infer(bh_ctx *c, const float *feat, int64_t n, float *pred) {
+int bh_mlp_infer(bh_ctx *c, const float *feat, int64_t n, int precision, float *pred) {
     if (!c || !feat || !pred) return set_error(BH_E_INVALID, "null argument");
     if (n < 1 || n > (int64_t)0x7fff0000) return set_error(BH_E_INVALID, "n out of range");
+    if (precision != BH_MLP_BF16 && precision != BH_MLP_FP16)
+        return set_error(BH_E_INVALID, "precision must be BH_MLP_BF16 or BH_MLP_FP16");
     if (!c->mlp_loaded) return set_error(BH_E_STATE, "no parameters loaded");
     if (use_device(c)) return BH_E_DEVICE;
-    return mlp_infer(c, feat, n, pred);
+    return mlp_infer(c, feat, n, precision, pred);
 }
 
 }  // extern "C"

@@ -1,6 +1,9 @@
 // Learned acceptance criterion: packed inference weights and the wave-level
-// bf16 MFMA evaluation (gfx950, v_mfma_f32_32x32x16_bf16).
+// MFMA evaluation in bf16 or fp16 (gfx950, v_mfma_f32_32x32x16_bf16 /
+// v_mfma_f32_32x32x16_f16: the same operand layout).
 #pragma once
+
+#include <type_traits>
 
 #include "bh_internal.h"
 
@@ -16,8 +19,22 @@ struct MlpTrainCfg {
 };
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// element type of an 8-wide MFMA operand
+template <typename V> struct VecElem;
+template <> struct VecElem<bf16x8> { using type = __bf16; };
+template <> struct VecElem<f16x8> { using type = _Float16; };
+
+template <typename V>
+__device__ __forceinline__ f32x16 mfma32(const V &a, const V &b, const f32x16 &c) {
+    if constexpr (std::is_same<V, f16x8>::value)
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
 
 // Per-lane operands, lane l of the wave:
 //  a1[l]    row l%32 of W1e = [W1 | b1 | 0] (hidden unit), feature slots
@@ -35,18 +52,20 @@ struct MlpPacked {
     float b3;
 };
 
+template <typename V>
 struct MlpRegs {
-    bf16x8 a1;
-    bf16x8 a2[2];
+    V a1;
+    V a2[2];
     float b2d[16];
     float w3d[16];
     float b3;
 };
 
-__device__ __forceinline__ void mlp_load(const MlpPacked *__restrict__ p, int l, MlpRegs &r) {
-    r.a1 = __builtin_bit_cast(bf16x8, p->a1[l]);
-    r.a2[0] = __builtin_bit_cast(bf16x8, p->a2[0][l]);
-    r.a2[1] = __builtin_bit_cast(bf16x8, p->a2[1][l]);
+template <typename V>
+__device__ __forceinline__ void mlp_load(const MlpPacked *__restrict__ p, int l, MlpRegs<V> &r) {
+    r.a1 = __builtin_bit_cast(V, p->a1[l]);
+    r.a2[0] = __builtin_bit_cast(V, p->a2[0][l]);
+    r.a2[1] = __builtin_bit_cast(V, p->a2[1][l]);
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         r.b2d[v] = p->b2d[l][v];
@@ -57,15 +76,17 @@ __device__ __forceinline__ void mlp_load(const MlpPacked *__restrict__ p, int l,
 
 // Prediction for this lane's feature row.  Must be called by all 64 lanes
 // of the wave (uniform control flow).
-__device__ __forceinline__ float mlp_eval(const MlpRegs &r, const float *f, int l) {
-    bf16x8 lo, hi;
+template <typename V>
+__device__ __forceinline__ float mlp_eval(const MlpRegs<V> &r, const float *f, int l) {
+    using E = typename VecElem<V>::type;
+    V lo, hi;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) lo[q] = (__bf16)f[q];
-    hi[0] = (__bf16)f[8];
-    hi[1] = (__bf16)f[9];
-    hi[2] = (__bf16)1.0f;
+    for (int q = 0; q < 8; ++q) lo[q] = (E)f[q];
+    hi[0] = (E)f[8];
+    hi[1] = (E)f[9];
+    hi[2] = (E)1.0f;
 #pragma unroll
-    for (int q = 3; q < 8; ++q) hi[q] = (__bf16)0.0f;
+    for (int q = 3; q < 8; ++q) hi[q] = (E)0.0f;
     const bool upper = l >= 32;
     // samples 0..31 are lanes 0..31, samples 32..63 lanes 32..63; the B
     // operand wants slots 0..7 of a sample in the lower half-wave and slots
@@ -74,26 +95,26 @@ __device__ __forceinline__ float mlp_eval(const MlpRegs &r, const float *f, int 
     u32x4 recv;
 #pragma unroll
     for (int w = 0; w < 4; ++w) recv[w] = __shfl_xor(send[w], 32);
-    const bf16x8 B0 = upper ? __builtin_bit_cast(bf16x8, recv) : lo;
-    const bf16x8 B1 = upper ? hi : __builtin_bit_cast(bf16x8, recv);
+    const V B0 = upper ? __builtin_bit_cast(V, recv) : lo;
+    const V B1 = upper ? hi : __builtin_bit_cast(V, recv);
     const f32x16 zero = {};
-    const f32x16 d0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a1, B0, zero, 0, 0, 0);
-    const f32x16 d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a1, B1, zero, 0, 0, 0);
-    bf16x8 h00, h01, h10, h11;
+    const f32x16 d0 = mfma32<V>(r.a1, B0, zero);
+    const f32x16 d1 = mfma32<V>(r.a1, B1, zero);
+    V h00, h01, h10, h11;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        h00[q] = (__bf16)fmaxf(d0[q], 0.f);
-        h01[q] = (__bf16)fmaxf(d0[8 + q], 0.f);
-        h10[q] = (__bf16)fmaxf(d1[q], 0.f);
-        h11[q] = (__bf16)fmaxf(d1[8 + q], 0.f);
+        h00[q] = (E)fmaxf(d0[q], 0.f);
+        h01[q] = (E)fmaxf(d0[8 + q], 0.f);
+        h10[q] = (E)fmaxf(d1[q], 0.f);
+        h11[q] = (E)fmaxf(d1[8 + q], 0.f);
     }
     f32x16 c2;
 #pragma unroll
     for (int v = 0; v < 16; ++v) c2[v] = r.b2d[v];
-    f32x16 e0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a2[0], h00, c2, 0, 0, 0);
-    e0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a2[1], h01, e0, 0, 0, 0);
-    f32x16 e1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a2[0], h10, c2, 0, 0, 0);
-    e1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r.a2[1], h11, e1, 0, 0, 0);
+    f32x16 e0 = mfma32<V>(r.a2[0], h00, c2);
+    e0 = mfma32<V>(r.a2[1], h01, e0);
+    f32x16 e1 = mfma32<V>(r.a2[0], h10, c2);
+    e1 = mfma32<V>(r.a2[1], h11, e1);
     float p0 = 0.f, p1 = 0.f;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -107,13 +128,14 @@ __device__ __forceinline__ float mlp_eval(const MlpRegs &r, const float *f, int 
 
 // host entry points (mlp.hip)
 int mlp_pack(bh_ctx *c);
-int mlp_infer(bh_ctx *c, const float *X, int64_t n, float *pred);
+// precision: BH_MLP_BF16 or BH_MLP_FP16 (both packings live in c->mlp_w)
+int mlp_infer(bh_ctx *c, const float *X, int64_t n, int precision, float *pred);
 int mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_max, double keep,
                 uint64_t seed, int64_t cap, float *feat, float *label, int32_t *node,
                 int32_t *body, int64_t *total);
 // features and k_C M l^3 of every cell (learned: the network; else k_C = 1),
 // cached per tree build, eps and parameter version
-int mlp_cells(bh_tree *t, double eps, bool learned);
+int mlp_cells(bh_tree *t, double eps, bool learned, int precision);
 // |a| per sorted rank into t->anorm from an acceleration array (acc) or an
 // array of norms (norm), of the tree's dtype, in caller order (read through
 // perm) or in sorted order; also the floor floor_frac * mean |a| (device

@@ -83,6 +83,7 @@ __global__ __launch_bounds__(256) void k_cell_features(int m, const Moments *__r
 }
 
 // k_C M l^3 per cell with log10 k_C from the network, 64 cells per wave.
+template <typename V>
 __global__ __launch_bounds__(256) void k_cell_kc(const MlpPacked *__restrict__ p, int m,
                                                  const float *__restrict__ cf,
                                                  const Moments *__restrict__ mom,
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(256) void k_cell_kc(const MlpPacked *__restrict__ p
     if (wave * 64 >= m) return;  // whole wave: the MFMAs need every lane
     const int l = (int)lane_id();
     const int i = wave * 64 + l;
-    MlpRegs r;
+    MlpRegs<V> r;
     mlp_load(p, l, r);
     float f[kMlpIn];
     for (int q = 0; q < kMlpIn; ++q) f[q] = i < m ? cf[10 * (size_t)i + q] : 0.f;
@@ -419,24 +420,26 @@ __global__ __launch_bounds__(256) void k_mlp_adam(const float *__restrict__ gpar
 }
 
 // ------------------------------------------------------------------ inference
-// Pack FP32 master parameters into the per-lane MFMA operand layout.
-__global__ __launch_bounds__(64) void k_mlp_pack(const float *__restrict__ w,
-                                                 MlpPacked *__restrict__ p) {
-    const int l = threadIdx.x;
+// Pack FP32 master parameters into the per-lane MFMA operand layout, in
+// the element type of V.
+template <typename V>
+__device__ __forceinline__ void mlp_pack_as(const float *__restrict__ w, MlpPacked *__restrict__ p,
+                                            int l) {
+    using E = typename VecElem<V>::type;
     const float *W1 = w, *b1 = w + 320, *W2 = w + 352, *b2 = w + 1376, *w3 = w + 1408;
     const int row = l & 31, h = l >> 5;
-    bf16x8 v1;
+    V v1;
     for (int q = 0; q < 8; ++q) {
         const int k = 8 * h + q;  // feature slot: 0..9 weights, 10 bias, rest 0
         const float v = k < kMlpIn ? W1[row * kMlpIn + k] : (k == kMlpIn ? b1[row] : 0.f);
-        v1[q] = (__bf16)v;
+        v1[q] = (E)v;
     }
     p->a1[l] = __builtin_bit_cast(u32x4, v1);
     for (int c = 0; c < 2; ++c) {
-        bf16x8 v2;
+        V v2;
         for (int q = 0; q < 8; ++q) {
             const int unit = q < 4 ? 16 * c + 4 * h + q : 16 * c + 8 + 4 * h + (q - 4);
-            v2[q] = (__bf16)W2[row * kMlpHidden + unit];
+            v2[q] = (E)W2[row * kMlpHidden + unit];
         }
         p->a2[c][l] = __builtin_bit_cast(u32x4, v2);
     }
@@ -448,6 +451,14 @@ __global__ __launch_bounds__(64) void k_mlp_pack(const float *__restrict__ w,
     if (l == 0) p->b3 = w[1440];
 }
 
+// both packings: p[BH_MLP_BF16] and p[BH_MLP_FP16]
+__global__ __launch_bounds__(64) void k_mlp_pack(const float *__restrict__ w,
+                                                 MlpPacked *__restrict__ p) {
+    mlp_pack_as<bf16x8>(w, p + BH_MLP_BF16, threadIdx.x);
+    mlp_pack_as<f16x8>(w, p + BH_MLP_FP16, threadIdx.x);
+}
+
+template <typename V>
 __global__ __launch_bounds__(256) void k_mlp_infer(const MlpPacked *__restrict__ p,
                                                    const float *__restrict__ X, int n,
                                                    float *__restrict__ pred) {
@@ -455,7 +466,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const MlpPacked *__restrict__
     if (wave * 64 >= n) return;  // whole wave: the MFMAs need every lane
     const int l = (int)lane_id();
     const int i = wave * 64 + l;
-    MlpRegs r;
+    MlpRegs<V> r;
     mlp_load(p, l, r);
     float f[kMlpIn];
     for (int q = 0; q < kMlpIn; ++q) f[q] = i < n ? X[kMlpIn * i + q] : 0.f;
@@ -467,7 +478,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const MlpPacked *__restrict__
 
 // ------------------------------------------------------------------ host side
 int mlp_pack(bh_ctx *c) {
-    int rc = grow(c->mlp_w, sizeof(MlpPacked));
+    int rc = grow(c->mlp_w, 2 * sizeof(MlpPacked));
     if (rc) return rc;
     k_mlp_pack<<<1, 64, 0, c->stream>>>((const float *)c->mlp_master.p, (MlpPacked *)c->mlp_w.p);
     rc = check_launch("mlp pack");
@@ -478,9 +489,12 @@ int mlp_pack(bh_ctx *c) {
     return rc;
 }
 
-int mlp_infer(bh_ctx *c, const float *X, int64_t n, float *pred) {
-    k_mlp_infer<<<div_up(n, 256), 256, 0, c->stream>>>((const MlpPacked *)c->mlp_w.p, X, (int)n,
-                                                       pred);
+int mlp_infer(bh_ctx *c, const float *X, int64_t n, int precision, float *pred) {
+    const MlpPacked *p = (const MlpPacked *)c->mlp_w.p + precision;
+    if (precision == BH_MLP_FP16)
+        k_mlp_infer<f16x8><<<div_up(n, 256), 256, 0, c->stream>>>(p, X, (int)n, pred);
+    else
+        k_mlp_infer<bf16x8><<<div_up(n, 256), 256, 0, c->stream>>>(p, X, (int)n, pred);
     return check_launch("mlp infer");
 }
 
@@ -499,10 +513,10 @@ static int mlp_features(bh_tree *t, double eps) {
     return BH_OK;
 }
 
-int mlp_cells(bh_tree *t, double eps, bool learned) {
+int mlp_cells(bh_tree *t, double eps, bool learned, int precision) {
     bh_ctx *c = t->ctx;
     const int m = (int)t->m;
-    const int version = learned ? c->mlp_version : -1;
+    const int version = learned ? 2 * c->mlp_version + precision : -1;
     if (t->kc_version == version && t->kc_eps == eps && t->kc_tree_id == t->build_id) return BH_OK;
     int rc = grow(t->kc, 4ull * m);
     if (rc) return rc;
@@ -510,9 +524,15 @@ int mlp_cells(bh_tree *t, double eps, bool learned) {
     const Cube *cube = (const Cube *)t->cube.p;
     if (learned) {
         if ((rc = mlp_features(t, eps))) return rc;
-        k_cell_kc<<<div_up(div_up(m, 64), 4), 256, 0, c->stream>>>(
-            (const MlpPacked *)c->mlp_w.p, m, (const float *)t->cellf.p, mom,
-            (const int32_t *)t->level.p, cube, (float *)t->kc.p);
+        const MlpPacked *p = (const MlpPacked *)c->mlp_w.p + precision;
+        if (precision == BH_MLP_FP16)
+            k_cell_kc<f16x8><<<div_up(div_up(m, 64), 4), 256, 0, c->stream>>>(
+                p, m, (const float *)t->cellf.p, mom, (const int32_t *)t->level.p, cube,
+                (float *)t->kc.p);
+        else
+            k_cell_kc<bf16x8><<<div_up(div_up(m, 64), 4), 256, 0, c->stream>>>(
+                p, m, (const float *)t->cellf.p, mom, (const int32_t *)t->level.p, cube,
+                (float *)t->kc.p);
     } else {  // k_C = 1 needs no features
         k_cell_kc_plain<<<div_up(m, 256), 256, 0, c->stream>>>(m, mom, (const int32_t *)t->level.p,
                                                                cube, (float *)t->kc.p);

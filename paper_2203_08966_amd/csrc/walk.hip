@@ -919,8 +919,9 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
     {
         const double dv[6] = {theta, eps, o.mlp_theta_max, o.mlp_log10_tau, o.mlp_acc_floor,
                               (double)o.walk_cap};
-        const int64_t iv[6] = {o.mac, o.order, t0, t1, t->dtype,
-                               o.mac == BH_MAC_MLP ? t->ctx->mlp_version : 0};
+        const int64_t iv[7] = {o.mac, o.order, t0, t1, t->dtype,
+                               o.mac == BH_MAC_MLP ? t->ctx->mlp_version : 0,
+                               o.mac == BH_MAC_MLP ? o.mlp_precision : 0};
         mixin(dv, sizeof dv);
         mixin(iv, sizeof iv);
         sig |= 1ull << 63;  // never the unset value 0
@@ -928,7 +929,7 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
     if (o.mac == BH_MAC_MLP || o.mac == BH_MAC_BUDGET) {
         if (t->dtype != BH_F32 || o.order != 2)
             return set_error(BH_E_INVALID, "the learned criterion runs in the FP32 quadrupole walk");
-        int rc = mlp_cells(t, eps, o.mac == BH_MAC_MLP);
+        int rc = mlp_cells(t, eps, o.mac == BH_MAC_MLP, o.mlp_precision);
         if (rc) return rc;
         if (o.mlp_acc_norm) {
             rc = mlp_anorm(t, nullptr, o.mlp_acc_norm, true, o.mlp_acc_floor);

@@ -34,6 +34,7 @@ def test_version_and_defaults():
     assert o.target_begin == 0 and o.target_end == 0
     assert o.mlp_theta_max == 1.0 and o.mlp_log10_tau == -3.0 and o.mlp_theta_est == 0.8
     assert o.mlp_acc_norm is None and o.mlp_acc_floor == 0.0
+    assert o.mlp_precision == B.BH_MLP_BF16
 
 
 def test_null_handles_rejected():
@@ -62,7 +63,7 @@ def test_null_handles_rejected():
     assert lib.bh_mlp_samples(None, 0.0, 0.3, 1.0, 1.0, 1, 0, None, None, None, None, C.byref(tot)) == B.BH_E_INVALID
     assert lib.bh_mlp_train(None, None, None, 1, None, None) == B.BH_E_INVALID
     assert lib.bh_mlp_grad(None, None, None, 1, 0.0, None, None) == B.BH_E_INVALID
-    assert lib.bh_mlp_infer(None, None, 1, None) == B.BH_E_INVALID
+    assert lib.bh_mlp_infer(None, None, 1, B.BH_MLP_BF16, None) == B.BH_E_INVALID
     assert lib.bh_sim_timing_get(None, None, None) == B.BH_E_INVALID
 
 
@@ -104,6 +105,11 @@ def test_force_parameter_checks_precede_device_use():
         o = B.force_opts(mac=B.BH_MAC_BUDGET, mlp_acc_floor=f)
         assert lib.bh_forces(t, 0.5, 0.0, acc, C.byref(o)) == B.BH_E_INVALID
         assert "learned-criterion" in B.bh_last_error()
+    o = B.force_opts(mac=B.BH_MAC_MLP, mlp_precision=2)
+    assert lib.bh_forces(t, 0.5, 0.0, acc, C.byref(o)) == B.BH_E_INVALID
+    ctx = C.c_void_p(C.addressof(dummy))
+    assert lib.bh_mlp_infer(ctx, acc, 1, 2, acc) == B.BH_E_INVALID
+    assert "precision" in B.bh_last_error()
 
 
 def test_sim_argument_checks():

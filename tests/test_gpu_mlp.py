@@ -47,6 +47,24 @@ def test_inference_matches_bf16_oracle(ctx):
     assert np.sqrt(np.mean((pred - full) ** 2)) < 0.05 * np.std(full) + 1e-3
 
 
+def test_inference_matches_f16_oracle(ctx):
+    th = _params(12)
+    B.bh_mlp_set(ctx, th)
+    th32 = B.bh_mlp_get(ctx)
+    X = _features(5000, 4)
+    say("fp16 MFMA inference vs oracle fp16 view, 5000 rows")
+    pred = B.bh_mlp_infer(ctx, torch.from_numpy(X).cuda(), B.BH_MLP_FP16).cpu().numpy()
+    ref = mlp.forward_bf16(th32, X.astype(np.float64), rnd=mlp.f16)
+    err = np.abs(pred - ref)
+    say(f"  max |d| {err.max():.2e}  rms {np.sqrt(np.mean(err ** 2)):.2e}")
+    assert np.sqrt(np.mean(err ** 2)) < 2e-4
+    assert err.max() < 5e-3
+    pb = B.bh_mlp_infer(ctx, torch.from_numpy(X).cuda(), B.BH_MLP_BF16).cpu().numpy()
+    full, _ = mlp.forward(th32, X.astype(np.float64))
+    # 11 significant bits against 8: nearer the full-precision network
+    assert np.sqrt(np.mean((pred - full) ** 2)) < np.sqrt(np.mean((pb - full) ** 2))
+
+
 @pytest.mark.parametrize("quantile", [0.0, 0.9])
 def test_gradient_matches_oracle(ctx, quantile):
     th = _params(12, 0.1)
@@ -214,6 +232,26 @@ def test_learned_walk_matches_oracle(ctx):
     r1 = oracle.walk_kc(ref, eps, tmax, tau, oracle.cell_kc(ref, eps),
                         an.astype(np.float64)[ref["perm"]])
     assert np.mean((r.npp != r1.npp) | (r.npc != r1.npc)) > 0.1
+    _compare(ref, r, a, cp, cc)
+
+
+def test_learned_walk_f16_matches_oracle(ctx):
+    """The learned walk with fp16 network operands against the oracle's walk
+    with the fp16 view of the same network."""
+    pos, _, mass = case_bodies("plummer", 20000, 3, np.float32)
+    th = _params(21, 0.3)
+    th[-1] = 0.0
+    B.bh_mlp_set(ctx, th)
+    th32 = B.bh_mlp_get(ctx)
+    eps, tau, tmax = 0.005, 3e-3, 0.9
+    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), 16)
+    an = _oracle_anorm(ref, eps).astype(np.float32)
+    say(f"learned walk, fp16: 20000 bodies, tau {tau}, theta_max {tmax}")
+    a, cp, cc = _gpu_walk(ctx, pos, mass, 16, eps, mac=B.BH_MAC_MLP, mlp_theta_max=tmax,
+                          mlp_log10_tau=np.log10(tau), acc_norm=an,
+                          mlp_precision=B.BH_MLP_FP16)
+    kc = oracle.cell_kc(ref, eps, th32, f16=True)
+    r = oracle.walk_kc(ref, eps, tmax, tau, kc, an.astype(np.float64)[ref["perm"]])
     _compare(ref, r, a, cp, cc)
 
 

@@ -63,6 +63,33 @@ def test_bf16_views_agree():
     assert np.max(np.abs(a - full)) < 0.05 * np.max(np.abs(full)) + 0.05
 
 
+def test_f16_rounding_and_views_agree():
+    """The C oracle's binary16 rounding (written from the format's
+    definition) equals numpy's float16 conversion, ties to even, subnormals
+    and overflow included; the numpy and C writings of the fp16 network
+    agree."""
+    cases = [1.0, 1.0 + 2 ** -11, 1.0 + 3 * 2 ** -11, -(1.0 + 2 ** -11), 65504.0, 65519.0,
+             65520.0, 1e6, 2 ** -14, 2 ** -24, 2 ** -25, 3 * 2 ** -26, 1e-9, 0.0, -0.0]
+    assert oracle.f16r(1.0 + 2 ** -11) == 1.0                 # tie -> even
+    assert oracle.f16r(1.0 + 3 * 2 ** -11) == 1.0 + 2 ** -9
+    assert oracle.f16r(65519.0) == 65504.0 and np.isinf(oracle.f16r(65520.0))
+    assert oracle.f16r(2 ** -25) == 0.0 and oracle.f16r(3 * 2 ** -26) == 2 ** -24
+    rng = np.random.default_rng(4)
+    xs = np.concatenate([cases, rng.normal(size=2000) * 10.0 ** rng.uniform(-9, 5, 2000)])
+    xs = xs.astype(np.float32).astype(np.float64)
+    want = mlp.f16(xs)
+    got = np.array([oracle.f16r(x) for x in xs])
+    assert np.array_equal(got, want)
+    th = mlp.init(9) + rng.normal(size=mlp.NPARAM) * 0.1
+    X = rng.normal(size=(50, 10))
+    a = mlp.forward_bf16(th, X, rnd=mlp.f16)
+    b = np.array([oracle.mlp_f16(th, x) for x in X])
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-12)
+    full, _ = mlp.forward(th, X)
+    # 11 significant bits: closer to the full network than the bf16 view
+    assert np.max(np.abs(a - full)) < np.max(np.abs(mlp.forward_bf16(th, X) - full))
+
+
 def test_splitmix64_reference_outputs():
     """SplitMix64 with state 0: the first three outputs of the published
     generator (state advances by the golden gamma before each mix)."""

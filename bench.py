@@ -58,7 +58,7 @@ METHODS = {
     "body-theta": [round(0.5 + 0.01 * k, 2) for k in range(31)],      # Sec. 3 walk
     "group-theta": [round(0.6 + 0.0125 * k, 4) for k in range(29)],   # one decision per wave
     "group-budget": [round(-2.5 + 0.125 * k, 3) for k in range(13)],  # log10 tau
-    "group-learned": [round(-4.0 + 0.125 * k, 3) for k in range(21)],  # log10 tau
+    "group-learned": [round(-5.0 + 0.125 * k, 3) for k in range(29)],  # log10 tau
 }
 PARAM_NAME = {"body-theta": "theta", "group-theta": "theta", "group-budget": "log10_tau",
               "group-learned": "log10_tau"}
@@ -154,12 +154,15 @@ def main():
     B.bh_forces(tree, 0.5, eps, acc, B.force_opts(order=order))
     anorm = acc.norm(dim=1).contiguous()
 
+    # network operands of the learned criterion (fp16 where the workload asks)
+    mlp_precision = B.BH_MLP_FP16 if cfg.get("mlp") == "fp16" else B.BH_MLP_BF16
+
     def opts_of(method, p, counters=False, for_sim=False):
         kw = dict(order=order, n_pp=npp if counters else None, n_pc=npc if counters else None)
         if method == "group-theta":
             kw.update(walk=B.BH_WALK_GROUP)
         elif method in ("group-budget", "group-learned"):
-            kw.update(walk=B.BH_WALK_GROUP,
+            kw.update(walk=B.BH_WALK_GROUP, mlp_precision=mlp_precision,
                       mac=B.BH_MAC_BUDGET if method == "group-budget" else B.BH_MAC_MLP,
                       mlp_log10_tau=p, mlp_theta_max=BUDGET_THETA_MAX,
                       mlp_acc_norm=None if for_sim else anorm, mlp_acc_floor=ACC_FLOOR)
@@ -200,7 +203,8 @@ def main():
         learned_info = {"pairs": int(feat.shape[0]), "epochs": len(loss),
                         "loss_first_last": [float(loss[0]), float(loss[-1])],
                         "label_var": float(label.double().var().item()),
-                        "seconds": time.perf_counter() - t0}
+                        "seconds": time.perf_counter() - t0,
+                        "inference": "fp16" if mlp_precision == B.BH_MLP_FP16 else "bf16"}
         del feat, label
         log(f"learned criterion: {learned_info}")
 
@@ -294,6 +298,8 @@ def main():
             "method": chosen, PARAM_NAME[chosen]: cp,
             **({"theta_max": BUDGET_THETA_MAX, "acc_floor": ACC_FLOOR}
                if PARAM_NAME[chosen] == "log10_tau" else {}),
+            **({"mlp": "fp16" if mlp_precision == B.BH_MLP_FP16 else "bf16"}
+               if chosen == "group-learned" else {}),
             "step": "KDK leapfrog step: kick+drift, rebuild, walk, kick, energy",
         },
         "rms_rel_err": methods[chosen]["rms_rel_err"],
@@ -322,7 +328,10 @@ def main():
 
 
 def result_workload(cfg, n):
-    return f"{cfg['workload']} N={n} (equal masses, G=M=a=1, seed {cfg['seed']})"
+    what = {"plummer": "equal masses, G=M=a=1",
+            "two_spheres": "radii 1 and 0.3, lognormal masses, approaching",
+            "clumpy": "4096 Plummer clumps + 10% background, equal masses"}[cfg["workload"]]
+    return f"{cfg['workload']} N={n} ({what}, seed {cfg['seed']})"
 
 
 def traffic_for(kernel, workload):

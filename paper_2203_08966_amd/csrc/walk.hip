@@ -740,80 +740,110 @@ __global__ __launch_bounds__(256) void k_gwalk(
 // costs many times an ordinary group; such groups are recognised by the
 // smallest cell holding the group's first and last keys: the more bodies
 // that cell holds (counted by galloping outwards from the group in the
-// sorted keys, up to the largest threshold), the more the
-// group is spread out.  Within each XCD's chunk, groups whose common cell
-// holds more than 256 x 64 bodies come first, then those above 16 x 64,
-// then the rest (order inside a class is immaterial: groups are
-// independent).  One block per chunk.
-__global__ __launch_bounds__(1024) void k_group_order(const uint64_t *__restrict__ keys,
-                                                      int64_t n, int t0, int t1, int ng,
-                                                      uint8_t *__restrict__ gfb,
-                                                      uint32_t *__restrict__ items,
-                                                      uint32_t *__restrict__ queue) {
-    // classes: 3 predicted to exceed the work cap (kParts items, first), then
-    // 0, 1, 2 by spread
-    __shared__ uint32_t cnt[4], pos[4];
-    __shared__ uint8_t cls_s[4096];
-    const int chunk = (ng + 7) / 8;
-    const int lo = blockIdx.x * chunk, hi = min(ng, lo + chunk);
-    if (threadIdx.x < 4) cnt[threadIdx.x] = pos[threadIdx.x] = 0;
-    __syncthreads();
-    auto cls = [&](int g) {
-        if (gfb && gfb[g] > 0) return 3;
-        const int64_t r0 = t0 + 64 * (int64_t)g, r1 = min(r0 + 63, (int64_t)t1 - 1);
-        const uint64_t a = keys[r0];
-        const uint64_t x = a ^ keys[r1];
-        const int lcp = x == 0 ? 21 : (__builtin_clzll(x) - 1) / 3;  // shared octal digits
-        const int sh = 3 * (21 - lcp);  // 0..63; keys are below 2^63
-        const uint64_t pre = a >> sh;   // the cell's key prefix
-        // bodies of the cell beyond the group on either side, counted by
-        // galloping outwards up to the largest threshold
-        constexpr int64_t kBig = 256 * 64;
-        auto reach = [&](int64_t from, int dir) -> int64_t {
-            int64_t in = 0, step = 1;
-            for (;;) {  // keys[from + dir * in] is inside the cell
-                const int64_t j = from + dir * (in + step);
-                if (j < 0 || j >= n || (keys[j] >> sh) != pre) break;
-                in += step;
-                if (in > kBig) return in;
-                step <<= 1;
-            }
-            while (step > 1) {  // inside at in, outside (or beyond n) at in + step
-                step >>= 1;
-                const int64_t j = from + dir * (in + step);
-                if (j >= 0 && j < n && (keys[j] >> sh) == pre) in += step;
-            }
-            return in;
-        };
-        const int64_t c = (r1 - r0 + 1) + reach(r0, -1) + reach(r1, 1);
-        return c > kBig ? 0 : (c > 16 * 64 ? 1 : 2);
-    };
-    for (int g = lo + threadIdx.x; g < hi; g += blockDim.x) {
-        const int c = cls(g);
-        if (g - lo < 4096) cls_s[g - lo] = (uint8_t)c;
-        atomicAdd(&cnt[c], c == 3 ? (uint32_t)kParts : 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) queue[64 * blockIdx.x + 16] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
-    uint32_t *out = items + kParts * (size_t)lo;  // at most kParts items per group
-    for (int g = lo + threadIdx.x; g < hi; g += blockDim.x) {
-        const int c = g - lo < 4096 ? cls_s[g - lo] : cls(g);
-        const uint32_t base = c == 3 ? 0u
-                            : c == 0 ? cnt[3]
-                            : c == 1 ? cnt[3] + cnt[0]
-                                     : cnt[3] + cnt[0] + cnt[1];
-        if (c == 3) {
-            const uint32_t p = base + atomicAdd(&pos[3], (uint32_t)kParts);
-            for (int q = 0; q < kParts; ++q) out[p + q] = (uint32_t)g * 16u + (uint32_t)q;
-        } else {
-            out[base + atomicAdd(&pos[c], 1u)] = (uint32_t)g * 16u + kWholeGroup;
+// sorted keys, up to the largest threshold), the more the group is spread
+// out.  Within each XCD's chunk, groups predicted to exceed the work cap
+// come first (kParts items each), then groups whose common cell holds more
+// than 256 x 64 bodies, then those above 16 x 64, then the rest (order
+// inside a class is immaterial: groups are independent).  Two launches over
+// all groups: classify and count, then place.
+//
+// Queue memory per XCD chunk x (uint32 words at 64 x): [0] hand-out
+// counter, [16] item count, [20 + c] items of class c, [24 + c] placed.
+// hand-out position of a class: 3 first, then 0, 1, 2
+__device__ __forceinline__ int class_pos(int c) { return c == 3 ? 0 : c + 1; }
+
+__device__ __forceinline__ int group_class(const uint64_t *__restrict__ keys, int64_t n, int t0,
+                                           int t1, int g, const uint8_t *__restrict__ gfb) {
+    if (gfb && gfb[g] > 0) return 3;
+    const int64_t r0 = t0 + 64 * (int64_t)g, r1 = min(r0 + 63, (int64_t)t1 - 1);
+    const uint64_t a = keys[r0];
+    const uint64_t x = a ^ keys[r1];
+    const int lcp = x == 0 ? 21 : (__builtin_clzll(x) - 1) / 3;  // shared octal digits
+    const int sh = 3 * (21 - lcp);  // 0..63; keys are below 2^63
+    const uint64_t pre = a >> sh;   // the cell's key prefix
+    // bodies of the cell beyond the group on either side, counted by
+    // galloping outwards up to the largest threshold
+    constexpr int64_t kBig = 256 * 64;
+    auto reach = [&](int64_t from, int dir) -> int64_t {
+        int64_t in = 0, step = 1;
+        for (;;) {  // keys[from + dir * in] is inside the cell
+            const int64_t j = from + dir * (in + step);
+            if (j < 0 || j >= n || (keys[j] >> sh) != pre) break;
+            in += step;
+            if (in > kBig) return in;
+            step <<= 1;
         }
+        while (step > 1) {  // inside at in, outside (or beyond n) at in + step
+            step >>= 1;
+            const int64_t j = from + dir * (in + step);
+            if (j >= 0 && j < n && (keys[j] >> sh) == pre) in += step;
+        }
+        return in;
+    };
+    const int64_t c = (r1 - r0 + 1) + reach(r0, -1) + reach(r1, 1);
+    return c > kBig ? 0 : (c > 16 * 64 ? 1 : 2);
+}
+
+__global__ __launch_bounds__(256) void k_group_class(const uint64_t *__restrict__ keys, int64_t n,
+                                                     int t0, int t1, int ng,
+                                                     const uint8_t *__restrict__ gfb,
+                                                     uint8_t *__restrict__ cls,
+                                                     uint32_t *__restrict__ queue) {
+    __shared__ uint32_t cnt[8][4];  // per XCD chunk and class, this block's share
+    if (threadIdx.x < 32) (&cnt[0][0])[threadIdx.x] = 0;
+    __syncthreads();
+    const int chunk = (ng + 7) / 8;
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g < ng) {
+        const int c = group_class(keys, n, t0, t1, g, gfb);
+        cls[g] = (uint8_t)c;
+        atomicAdd(&cnt[g / chunk][c], c == 3 ? (uint32_t)kParts : 1u);
     }
     __syncthreads();
-    // one prediction used up (after every class has been read)
-    if (gfb)
-        for (int g = lo + threadIdx.x; g < hi; g += blockDim.x)
-            if (gfb[g] > 0) gfb[g] = (uint8_t)(gfb[g] - 1);
+    if (threadIdx.x < 32) {
+        const uint32_t v = (&cnt[0][0])[threadIdx.x];
+        if (v) atomicAdd(&queue[64 * (threadIdx.x >> 2) + 20 + (threadIdx.x & 3)], v);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_group_place(int ng, const uint8_t *__restrict__ cls,
+                                                     uint8_t *__restrict__ gfb,
+                                                     uint32_t *__restrict__ items,
+                                                     uint32_t *__restrict__ queue) {
+    __shared__ uint32_t cnt[8][4], base[8][4];
+    if (threadIdx.x < 32) (&cnt[0][0])[threadIdx.x] = 0;
+    __syncthreads();
+    const int chunk = (ng + 7) / 8;
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    int c = 0, x = 0;
+    uint32_t rank = 0;
+    if (g < ng) {
+        c = cls[g];
+        x = g / chunk;
+        rank = atomicAdd(&cnt[x][c], c == 3 ? (uint32_t)kParts : 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {  // reserve this block's range of every (chunk, class)
+        const int xx = threadIdx.x >> 2, cc = threadIdx.x & 3;
+        const uint32_t v = cnt[xx][cc];
+        uint32_t b = 0;
+        for (int k = 0; k < 4; ++k)
+            if (class_pos(k) < class_pos(cc)) b += queue[64 * xx + 20 + k];
+        base[xx][cc] = b + (v ? atomicAdd(&queue[64 * xx + 24 + cc], v) : 0u);
+        if (blockIdx.x == 0 && cc == 0)
+            queue[64 * xx + 16] = queue[64 * xx + 20] + queue[64 * xx + 21] +
+                                  queue[64 * xx + 22] + queue[64 * xx + 23];
+    }
+    __syncthreads();
+    if (g >= ng) return;
+    uint32_t *out = items + kParts * (size_t)x * chunk;  // at most kParts items per group
+    const uint32_t p = base[x][c] + rank;
+    if (c == 3) {
+        for (int q = 0; q < kParts; ++q) out[p + q] = (uint32_t)g * 16u + (uint32_t)q;
+        gfb[g] = (uint8_t)(gfb[g] - 1);  // one prediction used up
+    } else {
+        out[p] = (uint32_t)g * 16u + kWholeGroup;
+    }
 }
 
 __global__ void k_zero_bytes(uint8_t *p, int64_t n) {
@@ -822,7 +852,7 @@ __global__ void k_zero_bytes(uint8_t *p, int64_t n) {
         p[i] = 0;
 }
 
-__global__ void k_zero_queue(uint32_t *q) { q[threadIdx.x * 64] = 0u; }
+__global__ void k_zero_queue(uint32_t *q) { q[threadIdx.x] = 0u; }  // 512 threads
 
 template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED, bool BUDGET>
 void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
@@ -832,7 +862,7 @@ void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, vo
     const int ng = div_up(t1 - t0, 64);
     const int per_xcd = std::min(div_up(div_up(ng, 8), 4), 256);
     uint32_t *queue = (uint32_t *)t->wq.p;
-    k_zero_queue<<<1, 8, 0, t->ctx->stream>>>(queue);
+    k_zero_queue<<<1, 512, 0, t->ctx->stream>>>(queue);
     GroupMac g2 = gm;
     // fallback predictions hold for walks of this tree object with the same
     // parameters and targets
@@ -845,10 +875,14 @@ void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, vo
             t->gfb_ng = ng;
         }
     }
-    if (grow(t->gorder, 4ull * kParts * ng) == BH_OK) {
-        k_group_order<<<8, 1024, 0, t->ctx->stream>>>(t->sorted_keys, t->n, t0, t1, ng, gfb,
-                                                      (uint32_t *)t->gorder.p, queue);
-        g2.items = (const uint32_t *)t->gorder.p;
+    // items (kParts slots per group), then one class byte per group
+    if (grow(t->gorder, 4ull * kParts * ng + ng) == BH_OK) {
+        uint32_t *items = (uint32_t *)t->gorder.p;
+        uint8_t *cls = (uint8_t *)(items + (size_t)kParts * ng);
+        k_group_class<<<div_up(ng, 256), 256, 0, t->ctx->stream>>>(t->sorted_keys, t->n, t0, t1,
+                                                                  ng, gfb, cls, queue);
+        k_group_place<<<div_up(ng, 256), 256, 0, t->ctx->stream>>>(ng, cls, gfb, items, queue);
+        g2.items = items;
         g2.gfb = gfb;
     }
     if (t->ctx->walk_ev) hipEventRecord(t->ctx->walk_ev[0], t->ctx->stream);

@@ -180,9 +180,9 @@ CONFIGS = {
     "c3": dict(workload="two_spheres", n=1 << 24, seed=3, theta=0.6, eps=0.002, leaf=16,
                dtype="f32", dt=5e-4, steps=10, sub_seed=103),
     "c4": dict(workload="plummer", n=1 << 22, seed=4, theta=0.5, eps=0.005, leaf=16,
-               dtype="f32", dt=5e-4, steps=10, sub_seed=104),
+               dtype="f32", dt=5e-4, steps=10, sub_seed=104, mlp="bf16"),
     "c5": dict(workload="clumpy", n=1 << 26, seed=5, theta=0.7, eps=1e-4, leaf=16,
-               dtype="f32", dt=1e-3, steps=10, sub_seed=105),
+               dtype="f32", dt=1e-3, steps=10, sub_seed=105, mlp="fp16"),
 }
 
 

@@ -346,3 +346,50 @@ def test_budget_leapfrog_matches_oracle(ctx):
     say(f"  acc rms rel {np.sqrt(np.mean(e * e)):.2e}")
     assert np.sqrt(np.mean(e * e)) < 1e-3
     assert np.median(e) < 1e-5
+
+
+def test_trained_network_beats_theta_at_equal_error(ctx):
+    """What the trained network gains: trained by the library's own pipeline
+    (FP64 simulations of small Plummer spheres, GPU training), the learned
+    criterion reaches rms relative error 1e-3 against FP64 direct summation
+    with fewer interactions per body than the opening angle, both with one
+    decision per wavefront group (Plummer sphere of 2^18 bodies)."""
+    from paper_2203_08966_amd import learned as LM
+    from paper_2203_08966_amd import workloads as W
+    feat, label = LM.training_set(ctx)
+    LM.train(ctx, feat, label)
+    del feat, label
+    b = W.plummer(1 << 18, 9).astype(np.float32)
+    n, eps = b.n, 0.005
+    P = torch.from_numpy(np.ascontiguousarray(b.pos)).cuda()
+    M = torch.from_numpy(np.ascontiguousarray(b.mass)).cuda()
+    tg = torch.from_numpy(W.subsample(n, 2048, 19)).cuda()
+    ref = torch.empty((2048, 3), dtype=torch.float64, device="cuda")
+    B.bh_direct(ctx, P, M, tg, eps, ref)
+    t = B.bh_build(ctx, P, M, 16)
+    acc = torch.empty_like(P)
+    npp = torch.zeros(n, dtype=torch.int32, device="cuda")
+    npc = torch.zeros(n, dtype=torch.int32, device="cuda")
+    B.bh_forces(t, 0.5, eps, acc)
+    anorm = acc.norm(dim=1).contiguous()
+    r = ref.cpu().numpy()
+
+    def run(theta, **kw):
+        B.bh_forces(t, theta, eps, acc, B.force_opts(walk=B.BH_WALK_GROUP, n_pp=npp, n_pc=npc,
+                                                     **kw))
+        a = acc.index_select(0, tg.long()).cpu().numpy().astype(np.float64)
+        e = np.linalg.norm(a - r, axis=1) / np.linalg.norm(r, axis=1)
+        work = (npp.to(torch.int64).sum() + npc.to(torch.int64).sum()).item() / n
+        return float(np.sqrt(np.mean(e * e))), work
+
+    def cheapest(results):
+        ok = [w for rms, w in results if rms <= 1e-3]
+        return min(ok) if ok else None
+    th = [run(x) for x in np.arange(0.5, 0.9, 0.0125)]
+    ln = [run(0.5, mac=B.BH_MAC_MLP, mlp_log10_tau=x, mlp_theta_max=1.5, mlp_acc_norm=anorm,
+              mlp_acc_floor=0.5) for x in np.arange(-4.5, -2.5, 0.125)]
+    B.bh_tree_free(t)
+    w_th, w_ln = cheapest(th), cheapest(ln)
+    say(f"  interactions per body at rms <= 1e-3: theta {w_th:.0f}, learned {w_ln:.0f}")
+    assert w_th is not None and w_ln is not None
+    assert w_ln < 0.9 * w_th

@@ -692,18 +692,28 @@ struct UpArgs {
 __device__ __forceinline__ void set_level(NodeRec32 &, int) {}
 __device__ __forceinline__ void set_level(NodeRec64 &r, int k) { r.level = k; }
 
+// A node's own index data, loaded before its moments are combined (the
+// stores of the moments would otherwise order these loads after them).
+struct NodeGeo {
+    int cx, cy, cz, begin, count, next, level;
+};
+__device__ __forceinline__ NodeGeo node_geo(const UpArgs &a, int i) {
+    return NodeGeo{a.cx[i], a.cy[i], a.cz[i], a.begin[i], a.count[i], a.next[i], a.level[i]};
+}
+
 // Stores node i's final moments and its walk record (centre, COM offset,
 // mass, traceless quadrupole 3T - tr(T) I, body range, skip pointer, side^2).
+// h = L 2^-(kLevels+1): centres and sides are exact multiples of it.
 template <typename R>
-__device__ __forceinline__ void finish_node(const UpArgs &a, int i, const Moments &q,
-                                            uint32_t mask, double h) {
+__device__ __forceinline__ void finish_node(const UpArgs &a, int i, const NodeGeo &gn,
+                                            const Moments &q, uint32_t mask, double h) {
     a.mom[i] = q;
     a.cmask[i] = mask;
     const double tr = q.t[0] + q.t[3] + q.t[5];
     typename NodeRecT<R>::type r{};
-    r.cx = (R)(a.cx[i] * h);  // exact
-    r.cy = (R)(a.cy[i] * h);
-    r.cz = (R)(a.cz[i] * h);
+    r.cx = (R)(gn.cx * h);  // exact
+    r.cy = (R)(gn.cy * h);
+    r.cz = (R)(gn.cz * h);
     r.mx = (R)q.c[0];
     r.my = (R)q.c[1];
     r.mz = (R)q.c[2];
@@ -713,13 +723,12 @@ __device__ __forceinline__ void finish_node(const UpArgs &a, int i, const Moment
     r.qxz = (R)(3.0 * q.t[2]);
     r.qyy = (R)(3.0 * q.t[3] - tr);
     r.qyz = (R)(3.0 * q.t[4]);
-    r.begin = a.begin[i];
-    r.count = a.count[i];
-    r.next = a.next[i];
-    const int lev = a.level[i];
-    const double side = ldexp(a.cube->L, -lev);
+    r.begin = gn.begin;
+    r.count = gn.count;
+    r.next = gn.next;
+    const double side = ldexp(h, kLevels + 1 - gn.level);
     r.l2 = (R)(side * side);
-    set_level(r, lev);
+    set_level(r, gn.level);
     ((typename NodeRecT<R>::type *)a.recs)[i] = r;
 }
 
@@ -759,14 +768,15 @@ __global__ __launch_bounds__(kThreads) void k_leaves(UpArgs ua, int32_t *__restr
         o[1] = make_int4(k[4], k[5], k[6], k[7]);
     }
     if (end != i + 1) return;
+    const NodeGeo gn = node_geo(ua, i);
     const double h = ldexp(cube->L, -(kLevels + 1));
-    const double c0 = cube->lo[0] + cx[i] * h, c1 = cube->lo[1] + cy[i] * h,
-                 c2 = cube->lo[2] + cz[i] * h;
-    const int b = ua.begin[i], e = b + ua.count[i];
+    const double c0 = cube->lo[0] + gn.cx * h, c1 = cube->lo[1] + gn.cy * h,
+                 c2 = cube->lo[2] + gn.cz * h;
+    const int b = gn.begin, e = b + gn.count;
     Anchor<R> an;
-    an.x = (R)(cx[i] * h);  // exact
-    an.y = (R)(cy[i] * h);
-    an.z = (R)(cz[i] * h);
+    an.x = (R)(gn.cx * h);  // exact
+    an.y = (R)(gn.cy * h);
+    an.z = (R)(gn.cz * h);
     an.leaf = i;
     double mt = 0, s0 = 0, s1 = 0, s2 = 0;
     for (int j = b; j < e; ++j) {
@@ -804,7 +814,7 @@ __global__ __launch_bounds__(kThreads) void k_leaves(UpArgs ua, int32_t *__restr
         r.t[4] += mj * y1 * y2;
         r.t[5] += mj * y2 * y2;
     }
-    finish_node<R>(ua, i, r, 0u, h);
+    finish_node<R>(ua, i, gn, r, 0u, h);
 }
 
 // One internal cell: combine its children (already done, one level deeper)
@@ -812,12 +822,31 @@ __global__ __launch_bounds__(kThreads) void k_leaves(UpArgs ua, int32_t *__restr
 // about this cell's centre (the centre offsets are exact), then the shift
 // to the COM, T = S2 - M com com^T.  Also the 8-bit child mask and the
 // node record.
+// The part that does not depend on the children's moments: node data and
+// child table.
+struct UpPre {
+    int p;  // -1: nothing to combine (a leaf, or no node)
+    NodeGeo gn;
+    int4 k0, k1;
+};
+__device__ __forceinline__ UpPre up_pre(const UpArgs &a, int p) {
+    UpPre u;
+    u.p = -1;
+    if (p < 0 || p >= a.m) return u;
+    u.gn = node_geo(a, p);
+    u.k0 = a.kids[2 * (int64_t)p];
+    u.k1 = a.kids[2 * (int64_t)p + 1];
+    if (u.gn.next != p + 1) u.p = p;  // leaves are done
+    return u;
+}
+
 template <typename R>
-__device__ __forceinline__ void up_node(const UpArgs &a, int p, double h) {
-    if (p < 0 || p >= a.m || a.next[p] == p + 1) return;  // leaves are done
-    const int4 k0 = a.kids[2 * (int64_t)p], k1 = a.kids[2 * (int64_t)p + 1];
-    const int ch[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
-    const int pcx = a.cx[p], pcy = a.cy[p], pcz = a.cz[p];
+__device__ __forceinline__ void up_combine(const UpArgs &a, const UpPre &u, double h) {
+    const int p = u.p;
+    if (p < 0) return;
+    const NodeGeo &gn = u.gn;
+    const int ch[8] = {u.k0.x, u.k0.y, u.k0.z, u.k0.w, u.k1.x, u.k1.y, u.k1.z, u.k1.w};
+    const int pcx = gn.cx, pcy = gn.cy, pcz = gn.cz;
     double mt = 0, s0 = 0, s1 = 0, s2 = 0;
     double q[6] = {0, 0, 0, 0, 0, 0};
     uint32_t mask = 0;
@@ -854,7 +883,12 @@ __device__ __forceinline__ void up_node(const UpArgs &a, int p, double h) {
     r.t[3] = q[3] - s1 * r.c[1];
     r.t[4] = q[4] - s1 * r.c[2];
     r.t[5] = q[5] - s2 * r.c[2];
-    finish_node<R>(a, p, r, mask, h);
+    finish_node<R>(a, p, gn, r, mask, h);
+}
+
+template <typename R>
+__device__ __forceinline__ void up_node(const UpArgs &a, int p, double h) {
+    up_combine<R>(a, up_pre(a, p), h);
 }
 
 // Internal cells of one level (one launch per level with more than

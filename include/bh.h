@@ -50,11 +50,15 @@ enum { BH_F32 = 0, BH_F64 = 1 };
 /* How the walk takes its decisions. */
 enum {
     BH_WALK_BODY = 0, /* per body, as in Sec. 3 (wavefronts share the sweep) */
-    BH_WALK_GROUP = 1 /* one decision per cell for each wavefront of 64
-                         consecutive sorted bodies, against the distance from
-                         the cell's COM to the group's bounding box; a cell
-                         whose cube meets the box is always opened */
+    BH_WALK_GROUP = 1 /* one decision per cell for each group of
+                         BH_GROUP_BODIES consecutive sorted bodies (one
+                         wavefront, one lane per body), against the distance
+                         from the cell's COM to the group's bounding box; a
+                         cell whose cube meets the box is always opened */
 };
+
+/* Bodies per group of BH_WALK_GROUP: groups start at target_begin. */
+enum { BH_GROUP_BODIES = 64 };
 
 /* Acceptance criterion used by the walk. */
 enum {

@@ -20,6 +20,7 @@ BH_F32, BH_F64 = 0, 1
 BH_MAC_THETA, BH_MAC_MLP, BH_MAC_BUDGET = 0, 1, 2
 BH_MLP_BF16, BH_MLP_FP16 = 0, 1
 BH_WALK_BODY, BH_WALK_GROUP = 0, 1
+BH_GROUP_BODIES = 64  # bodies per group of BH_WALK_GROUP
 
 EXPORTED = [
     "bh_version", "bh_last_error", "bh_force_opts_default", "bh_ctx_create", "bh_ctx_set_stream",
@@ -34,7 +35,7 @@ BH_MLP_PARAMS = 1441
 __all__ = EXPORTED + [
     "BHError", "ForceOpts", "TreeInfo", "force_opts", "load", "BH_OK", "BH_E_INVALID",
     "BH_E_NOMEM", "BH_E_DEVICE", "BH_E_STATE", "BH_E_NONFINITE", "BH_F32", "BH_F64",
-    "BH_MAC_THETA", "BH_MAC_MLP", "BH_MAC_BUDGET", "BH_WALK_BODY", "BH_WALK_GROUP",
+    "BH_MAC_THETA", "BH_MAC_MLP", "BH_MAC_BUDGET", "BH_WALK_BODY", "BH_WALK_GROUP", "BH_GROUP_BODIES",
 ]
 
 

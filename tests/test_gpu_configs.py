@@ -63,13 +63,13 @@ def test_full_size_sampled_against_oracle(ctx, name):
     ga = gacc.cpu().numpy().astype(np.float64)[ref["perm"]]
     rng = np.random.default_rng(7)
     checked = 0
-    for g in rng.choice(n // 64, 16, replace=False):
-        rg = oracle.walk_group(ref, eps, group=64, theta=0.7, target_range=(64 * g, 64 * g + 64))
+    G = B.BH_GROUP_BODIES
+    for g in rng.choice(n // G, 16, replace=False):
+        rg = oracle.walk_group(ref, eps, group=G, theta=0.7, target_range=(G * g, G * g + G))
         if rg.flag.any():
             continue
         checked += 1
-        eg = np.linalg.norm(ga[64 * g:64 * g + 64] - rg.acc, axis=1) / np.linalg.norm(rg.acc,
-                                                                                         axis=1)
+        eg = np.linalg.norm(ga[G * g:G * g + G] - rg.acc, axis=1) / np.linalg.norm(rg.acc, axis=1)
         assert eg.max() <= TOL32_MAX
     say(f"  group walk: unflagged sampled groups {checked} of 16")
     assert checked >= 8

@@ -1,4 +1,4 @@
-"""GPU group walk (one decision per wavefront of 64 bodies) against the
+"""GPU group walk (one decision per group of BH_GROUP_BODIES bodies) against the
 oracle's group walk."""
 import numpy as np
 import pytest
@@ -71,7 +71,7 @@ def test_group_walk_matches_oracle(ctx, kind, n, dtype, theta):
     say(f"group walk {kind} n={n} {np.dtype(dtype).name} theta {theta}")
     out = _run(ctx, pos, mass, leaf, theta, eps)
     ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), leaf)
-    r = oracle.walk_group(ref, eps, group=64, theta=theta, tol=FLAG_TOL[dtype])
+    r = oracle.walk_group(ref, eps, group=B.BH_GROUP_BODIES, theta=theta, tol=FLAG_TOL[dtype])
     _check(ref, r, out, dtype)
 
 
@@ -99,7 +99,7 @@ def test_group_walk_target_range_and_tiny_trees(ctx):
     perm = B.bh_tree_export(t)["perm"].astype(np.int64)
     B.bh_tree_free(t)
     ref = oracle.build_all(pos, mass, 8)
-    r = oracle.walk_group(ref, 0.01, group=64, theta=0.7, target_range=(100, 1337), tol=1e-9)
+    r = oracle.walk_group(ref, 0.01, group=B.BH_GROUP_BODIES, theta=0.7, target_range=(100, 1337), tol=1e-9)
     a = acc.cpu().numpy()
     ok = r.flag == 0
     e = np.linalg.norm(a[perm[100:1337]] - r.acc, axis=1) / np.linalg.norm(r.acc, axis=1)
@@ -127,7 +127,7 @@ def test_group_budget_matches_oracle(ctx):
     say(f"group budget walk: 20000 bodies, tau {tau:.3g}, theta_max {tmax}")
     out = _run(ctx, pos, mass, 16, 0.5, eps, mac=B.BH_MAC_BUDGET, mlp_theta_max=tmax,
                mlp_log10_tau=np.log10(tau), acc_norm=an)
-    r = oracle.walk_group(ref, eps, group=64, mode=1, theta_max=tmax, tau=tau,
+    r = oracle.walk_group(ref, eps, group=B.BH_GROUP_BODIES, mode=1, theta_max=tmax, tau=tau,
                           kc=oracle.cell_kc(ref, eps), anorm=an.astype(np.float64)[ref["perm"]],
                           tol=FLAG_TOL[np.float32])
     _check(ref, r, out, np.float32)
@@ -146,7 +146,7 @@ def test_group_budget_floor_matches_oracle(ctx):
     say(f"group budget walk, floor {fl}: 20000 bodies, tau {tau:.3g}, theta_max {tmax}")
     out = _run(ctx, pos, mass, 16, 0.5, eps, mac=B.BH_MAC_BUDGET, mlp_theta_max=tmax,
                mlp_log10_tau=np.log10(tau), acc_norm=an, mlp_acc_floor=fl)
-    args = dict(group=64, mode=1, theta_max=tmax, tau=tau, kc=oracle.cell_kc(ref, eps),
+    args = dict(group=B.BH_GROUP_BODIES, mode=1, theta_max=tmax, tau=tau, kc=oracle.cell_kc(ref, eps),
                 anorm=an.astype(np.float64)[ref["perm"]], tol=FLAG_TOL[np.float32])
     r = oracle.walk_group(ref, eps, floor=fl, **args)
     r0 = oracle.walk_group(ref, eps, **args)
@@ -165,13 +165,14 @@ def test_group_walk_full_size_sampled(ctx):
     out = _run(ctx, b.pos, b.mass, cfg["leaf"], theta, cfg["eps"])
     ref = oracle.build_all(b.pos.astype(np.float64), b.mass.astype(np.float64), cfg["leaf"])
     rng = np.random.default_rng(4)
-    groups = rng.choice(n // 64, 24, replace=False)
+    G = B.BH_GROUP_BODIES
+    groups = rng.choice(n // G, 24, replace=False)
     a, phi, cp, cc = (x[ref["perm"]] for x in out)
     checked = 0
     for g in groups:
-        r = oracle.walk_group(ref, cfg["eps"], group=64, theta=theta,
-                              target_range=(64 * g, 64 * g + 64), tol=FLAG_TOL[np.float32])
-        sl = slice(64 * g, 64 * g + 64)
+        r = oracle.walk_group(ref, cfg["eps"], group=B.BH_GROUP_BODIES, theta=theta,
+                              target_range=(G * g, G * g + G), tol=FLAG_TOL[np.float32])
+        sl = slice(G * g, G * g + G)
         if r.flag[0]:
             continue
         checked += 1
@@ -185,26 +186,32 @@ def test_group_walk_full_size_sampled(ctx):
 @pytest.mark.parametrize("mode", [0, 1])
 def test_group_walk_work_cap(ctx, mode):
     """With a low work cap part of the groups fall back to per-body
-    decisions, exactly where the oracle's groups do."""
+    decisions, exactly where the oracle's groups do.  The cap is the 70th
+    percentile of the work of the uncapped oracle walk (a run's work is
+    each of its bodies' npp + npc + 1), so that about 30 % of the bodies
+    fall back."""
     pos, _, mass = case_bodies("clumpy", 20000, 16, np.float32)
-    eps, cap = 0.005, 2500
+    eps = 0.005
     ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), 16)
-    say(f"group walk work cap {cap}, mode {mode}")
+    G = B.BH_GROUP_BODIES
     if mode == 0:
-        out = _run(ctx, pos, mass, 16, 0.7, eps, walk_cap=cap)
-        r = oracle.walk_group(ref, eps, group=64, theta=0.7, tol=FLAG_TOL[np.float32], cap=cap)
-        full = oracle.walk_group(ref, eps, group=64, theta=0.7, tol=FLAG_TOL[np.float32])
+        args = dict(group=G, theta=0.7, tol=FLAG_TOL[np.float32])
+        kw = dict()
+        theta = 0.7
     else:
         w = oracle.walk(ref["tree"], ref["mom"], ref["spos"], ref["smass"], ref["L"], 0.4, eps)
         an = np.empty(20000)
         an[ref["perm"]] = np.linalg.norm(w.acc, axis=1)
         an = an.astype(np.float32)
         kw = dict(mac=B.BH_MAC_BUDGET, mlp_theta_max=1.0, mlp_log10_tau=-2.0, acc_norm=an)
-        out = _run(ctx, pos, mass, 16, 0.5, eps, walk_cap=cap, **kw)
-        args = dict(group=64, mode=1, theta_max=1.0, tau=1e-2, kc=oracle.cell_kc(ref, eps),
+        args = dict(group=G, mode=1, theta_max=1.0, tau=1e-2, kc=oracle.cell_kc(ref, eps),
                     anorm=an.astype(np.float64)[ref["perm"]], tol=FLAG_TOL[np.float32])
-        r = oracle.walk_group(ref, eps, cap=cap, **args)
-        full = oracle.walk_group(ref, eps, **args)
+        theta = 0.5
+    full = oracle.walk_group(ref, eps, **args)
+    cap = int(np.quantile(full.npp + full.npc + 1, 0.7))
+    say(f"group walk work cap {cap}, mode {mode}")
+    out = _run(ctx, pos, mass, 16, theta, eps, walk_cap=cap, **kw)
+    r = oracle.walk_group(ref, eps, cap=cap, **args)
     fell = np.mean(full.npp + full.npc + 1 > cap)
     say(f"  fraction of bodies in groups over the cap: {fell:.3f}")
     assert 0.05 < fell < 0.95
@@ -259,7 +266,7 @@ def test_group_walk_prediction_after_rebuild(ctx):
     p = ref["perm"]
     a = acc.cpu().numpy().astype(np.float64)[p]
     cp, cc = npp.cpu().numpy()[p], npc.cpu().numpy()[p]
-    rg = oracle.walk_group(ref, eps, group=64, theta=theta, tol=FLAG_TOL[np.float32], cap=cap)
+    rg = oracle.walk_group(ref, eps, group=B.BH_GROUP_BODIES, theta=theta, tol=FLAG_TOL[np.float32], cap=cap)
     rb = oracle.walk(ref["tree"], ref["mom"], ref["spos"], ref["smass"], ref["L"], theta, eps)
 
     def same(r):

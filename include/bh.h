@@ -50,11 +50,16 @@ enum { BH_F32 = 0, BH_F64 = 1 };
 /* How the walk takes its decisions. */
 enum {
     BH_WALK_BODY = 0, /* per body, as in Sec. 3 (wavefronts share the sweep) */
-    BH_WALK_GROUP = 1 /* one decision per cell for each group of
+    BH_WALK_GROUP = 1, /* one decision per cell for each group of
                          BH_GROUP_BODIES consecutive sorted bodies (one
                          wavefront, one lane per body), against the distance
                          from the cell's COM to the group's bounding box; a
                          cell whose cube meets the box is always opened */
+    BH_WALK_DIRECT = 2 /* simulation only (bh_sim_init): no tree, every pair
+                          summed directly, the direct method of Sec. 3, in
+                          the simulation's dtype (each tile of 256 sources
+                          summed into FP64); O(N^2).  theta, the criterion and the
+                          order are ignored; bh_forces rejects it. */
 };
 
 /* Bodies per group of BH_WALK_GROUP: groups start at target_begin. */
@@ -98,7 +103,8 @@ typedef struct {
     double mlp_log10_tau;     /* default -3 */
     const void *mlp_acc_norm; /* default NULL */
     double mlp_theta_est;     /* default 0.8 */
-    int walk;                 /* BH_WALK_BODY (default) or BH_WALK_GROUP */
+    int walk;                 /* BH_WALK_BODY (default), BH_WALK_GROUP or
+                                 BH_WALK_DIRECT (simulation only) */
     int walk_stack;           /* group walk: LDS stack entries per wavefront,
                                  1..640, 0 = 640; subtrees that do not fit
                                  are walked without the stack (same result) */
@@ -223,7 +229,8 @@ int bh_sim_get(bh_ctx *ctx, void *pos, void *vel, void *acc);
  * pair once, softened; Sec. 2.4), phi from the last walk, accumulated in
  * FP64.  Synchronous. */
 int bh_energy(bh_ctx *ctx, double *ekin, double *epot);
-/* The simulation's current tree (owned by the context; do not free). */
+/* The simulation's current tree (owned by the context; do not free).  With
+ * BH_WALK_DIRECT, the tree of bh_sim_init: the steps build none. */
 int bh_sim_tree(bh_ctx *ctx, bh_tree **tree);
 
 /* Per-phase timing of bh_leapfrog_step with HIP events recorded on the
@@ -244,6 +251,21 @@ int bh_sim_timing_get(bh_ctx *ctx, double *ms, int64_t *steps);
  * ------------------------------------------------------------------- */
 int bh_direct(bh_ctx *ctx, const void *pos, const void *mass, int dtype, int64_t n,
               const int64_t *targets, int64_t nt, double eps, double *acc, double *phi);
+
+/* ---------------------------------------------------------------------
+ * bh_standard_units -- scale a system in place to the standard units of
+ * Sec. 2.4: masses to total 1, positions and velocities to the
+ * centre-of-mass frame, velocities by one factor so that E_kin = -E_pot/2,
+ * then lengths by b and velocities by 1/sqrt(b) so that the total energy is
+ * -1/4.  E_pot is the unsoftened direct sum (FP64, every pair: O(N^2)).
+ * pos, vel: device n x 3, mass: device n, all of dtype.  stats: optional
+ * host double[3] out: E_kin, E_pot and total mass before the scaling (after
+ * the shift).  Synchronous.  Fails with BH_E_INVALID if the total mass or
+ * the kinetic energy is not positive, BH_E_NONFINITE on non-finite sums
+ * (e.g. two bodies at one point).
+ * ------------------------------------------------------------------- */
+int bh_standard_units(bh_ctx *ctx, void *pos, void *vel, void *mass, int dtype, int64_t n,
+                      double *stats);
 
 /* ---------------------------------------------------------------------
  * Learned acceptance criterion (not in the paper; it stands in for the

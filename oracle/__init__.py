@@ -233,6 +233,28 @@ def energy(pos, vel, mass, eps):
     return ekin, epot
 
 
+def standard_units(pos, vel, mass):
+    """Scale a system to the standard units of Sec. 2.4, in the paper's
+    order: total mass 1; shift to the centre-of-mass frame; one velocity
+    factor so that E_kin = -E_pot / 2 (virial equilibrium); then lengths by
+    b and velocities by 1 / sqrt(b), which divides the total energy by b,
+    with b chosen so that it becomes -1/4.  E_pot is the unsoftened direct
+    sum.  Returns (pos, vel, mass, (E_kin, E_pot, M)) with E_kin and E_pot
+    of the shifted system before the two scalings and M the input's total
+    mass."""
+    m = np.asarray(mass, dtype=np.float64)
+    M = float(m.sum())
+    m = m / M
+    x = _pos64(pos)
+    v = _pos64(vel)
+    x = x - np.sum(m[:, None] * x, axis=0)
+    v = v - np.sum(m[:, None] * v, axis=0)
+    ek, ep = energy(x, v, m, 0.0)
+    v = v * np.sqrt(-ep / (2.0 * ek))  # now E = E_pot / 2
+    b = -2.0 * ep                     # E / b = -1/4
+    return x * b, v / np.sqrt(b), m, (ek, ep, M)
+
+
 def kdk(pos, vel, mass, dt, steps, force):
     """Kick-drift-kick leapfrog (Sec. 2.3) with a fixed step: the acceleration
     at the start is computed once, then each step is half kick, drift, new

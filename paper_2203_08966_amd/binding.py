@@ -19,7 +19,7 @@ BH_OK, BH_E_INVALID, BH_E_NOMEM, BH_E_DEVICE, BH_E_STATE, BH_E_NONFINITE = 0, -1
 BH_F32, BH_F64 = 0, 1
 BH_MAC_THETA, BH_MAC_MLP, BH_MAC_BUDGET = 0, 1, 2
 BH_MLP_BF16, BH_MLP_FP16 = 0, 1
-BH_WALK_BODY, BH_WALK_GROUP = 0, 1
+BH_WALK_BODY, BH_WALK_GROUP, BH_WALK_DIRECT = 0, 1, 2
 BH_GROUP_BODIES = 64  # bodies per group of BH_WALK_GROUP
 
 EXPORTED = [
@@ -28,6 +28,7 @@ EXPORTED = [
     "bh_tree_export", "bh_sim_init", "bh_leapfrog_step", "bh_sim_get", "bh_energy",
     "bh_sim_tree", "bh_direct", "bh_sim_timing", "bh_sim_timing_get", "bh_mlp_set",
     "bh_mlp_get", "bh_mlp_samples", "bh_mlp_train", "bh_mlp_grad", "bh_mlp_infer",
+    "bh_standard_units",
 ]
 BH_MLP_PARAMS = 1441
 
@@ -35,7 +36,8 @@ BH_MLP_PARAMS = 1441
 __all__ = EXPORTED + [
     "BHError", "ForceOpts", "TreeInfo", "force_opts", "load", "BH_OK", "BH_E_INVALID",
     "BH_E_NOMEM", "BH_E_DEVICE", "BH_E_STATE", "BH_E_NONFINITE", "BH_F32", "BH_F64",
-    "BH_MAC_THETA", "BH_MAC_MLP", "BH_MAC_BUDGET", "BH_WALK_BODY", "BH_WALK_GROUP", "BH_GROUP_BODIES",
+    "BH_MAC_THETA", "BH_MAC_MLP", "BH_MAC_BUDGET", "BH_WALK_BODY", "BH_WALK_GROUP", "BH_WALK_DIRECT",
+    "BH_GROUP_BODIES",
 ]
 
 
@@ -103,6 +105,7 @@ def load(path: str = LIB_PATH):
         "bh_energy": ([vp, C.POINTER(dbl), C.POINTER(dbl)], i32),
         "bh_sim_tree": ([vp, pp], i32),
         "bh_direct": ([vp, vp, vp, i32, i64, vp, i64, dbl, vp, vp], i32),
+        "bh_standard_units": ([vp, vp, vp, vp, i32, i64, vp], i32),
         "bh_sim_timing": ([vp, i32], i32),
         "bh_sim_timing_get": ([vp, C.POINTER(dbl), C.POINTER(i64)], i32),
         "bh_mlp_set": ([vp, vp], i32),
@@ -319,6 +322,18 @@ def bh_direct(ctx, pos, mass, targets, eps: float, acc, phi=None):
     _check(load().bh_direct(ctx, _dev(pos, "pos"), _dev(mass, "mass"), _dtype_code(pos),
                             int(mass.shape[0]), _dev(targets, "targets"), int(targets.shape[0]),
                             float(eps), _dev(acc, "acc"), _dev(phi, "phi")))
+
+
+def bh_standard_units(ctx, pos, vel, mass) -> tuple[float, float, float]:
+    """Scale (pos, vel, mass) in place to standard units; returns E_kin,
+    E_pot and the total mass before the scaling."""
+    _bodies(pos, mass)
+    if tuple(vel.shape) != tuple(pos.shape) or vel.dtype != pos.dtype:
+        raise ValueError("vel must match pos in shape and dtype")
+    st = (C.c_double * 3)()
+    _check(load().bh_standard_units(ctx, _dev(pos, "pos"), _dev(vel, "vel"), _dev(mass, "mass"),
+                                    _dtype_code(pos), int(mass.shape[0]), st))
+    return st[0], st[1], st[2]
 
 
 def bh_sim_timing(ctx, enable: bool = True):

@@ -91,8 +91,9 @@ static int check_opts(const bh_force_opts &o, int64_t n) {
           isfinite(o.mlp_acc_floor) &&
           (o.mlp_precision == BH_MLP_BF16 || o.mlp_precision == BH_MLP_FP16)))
         return set_error(BH_E_INVALID, "opts learned-criterion parameters invalid");
-    if (o.walk != BH_WALK_BODY && o.walk != BH_WALK_GROUP)
-        return set_error(BH_E_INVALID, "opts.walk must be BH_WALK_BODY or BH_WALK_GROUP");
+    if (o.walk != BH_WALK_BODY && o.walk != BH_WALK_GROUP && o.walk != BH_WALK_DIRECT)
+        return set_error(BH_E_INVALID,
+                         "opts.walk must be BH_WALK_BODY, BH_WALK_GROUP or BH_WALK_DIRECT");
     if (o.walk_stack < 0 || o.walk_stack > 640)
         return set_error(BH_E_INVALID, "opts.walk_stack must be in [0, 640]");
     if (o.walk_cap < 0) return set_error(BH_E_INVALID, "opts.walk_cap must be >= 0");
@@ -190,6 +191,7 @@ int bh_ctx_destroy(bh_ctx *c) {
     free_buf(c->mlp_scratch);
     free_buf(c->mlp_gpart);
     free_buf(c->scratch);
+    free_buf(c->su_work);
     for (hipEvent_t e : c->events) hipEventDestroy(e);
     if (c->pinned) hipHostFree(c->pinned);
     delete c;
@@ -257,6 +259,10 @@ int bh_forces(bh_tree *t, double theta, double eps, void *acc, const bh_force_op
     if (opts) o = *opts;
     else bh_force_opts_default(&o);
     if ((rc = check_opts(o, t->n))) return rc;
+    if (o.walk == BH_WALK_DIRECT)
+        return set_error(BH_E_INVALID,
+                         "BH_WALK_DIRECT is a simulation mode (bh_sim_init); bh_direct sums "
+                         "for given targets");
     if (o.mac == BH_MAC_MLP && !t->ctx->mlp_loaded)
         return set_error(BH_E_STATE, "learned criterion requested but no weights are loaded");
     if (use_device(t->ctx)) return BH_E_DEVICE;
@@ -338,6 +344,13 @@ int bh_tree_export(const bh_tree *t, uint64_t *keys, uint32_t *perm, uint64_t *h
 // and give the learned criterion its |a_i|.
 static int sim_forces(bh_ctx *c) {
     SimState *s = c->sim;
+    if (s->opts.walk == BH_WALK_DIRECT) {  // every pair, no tree (Sec. 3, direct method)
+        if (c->walk_ev) hipEventRecord(c->walk_ev[0], c->stream);
+        int rc = launch_direct_all(c->stream, s->dtype, s->n, s->pos.p, s->mass.p, s->eps,
+                                   s->acc.p, s->phi.p, c->scratch);
+        if (c->walk_ev) hipEventRecord(c->walk_ev[1], c->stream);
+        return rc;
+    }
     return run_walk(c->sim_tree, s->theta, s->eps, s->acc.p, s->phi.p, nullptr, nullptr, s->opts,
                     true, s->have_acc ? s->acc.p : nullptr);
 }
@@ -370,7 +383,7 @@ int bh_sim_init(bh_ctx *c, const void *pos, const void *vel, const void *mass, i
     o.target_begin = o.target_end = 0;
     o.mlp_acc_norm = nullptr;  // the previous step's accelerations serve instead
     if ((rc = check_opts(o, n))) return rc;
-    if (o.mac == BH_MAC_MLP && !c->mlp_loaded)
+    if (o.mac == BH_MAC_MLP && o.walk != BH_WALK_DIRECT && !c->mlp_loaded)
         return set_error(BH_E_STATE, "learned criterion requested but no weights are loaded");
     if (use_device(c)) return BH_E_DEVICE;
     if (!c->sim) c->sim = new SimState;
@@ -431,8 +444,11 @@ int bh_leapfrog_step(bh_ctx *c, double dt) {
                                 0.5 * dt, dt)))
         return rc;
     mark(1);
-    // new tree and accelerations at the drifted positions
-    if ((rc = sim_rebuild(c, s->pos.p, s->vel.p, s->mass.p, (const uint32_t *)s->id.p))) return rc;
+    // new tree and accelerations at the drifted positions (the direct method
+    // keeps the bodies in the order of the first build and needs no tree)
+    if (s->opts.walk != BH_WALK_DIRECT &&
+        (rc = sim_rebuild(c, s->pos.p, s->vel.p, s->mass.p, (const uint32_t *)s->id.p)))
+        return rc;
     mark(2);
     c->walk_ev = ev ? ev + 5 : nullptr;  // the walk kernel alone: events 5, 6
     rc = sim_forces(c);
@@ -522,6 +538,23 @@ int bh_direct(bh_ctx *c, const void *pos, const void *mass, int dtype, int64_t n
     if (!(eps >= 0) || !isfinite(eps)) return set_error(BH_E_INVALID, "eps must be finite and >= 0");
     if (use_device(c)) return BH_E_DEVICE;
     return launch_direct(c->stream, dtype, n, pos, mass, targets, nt, eps, acc, phi, c->scratch);
+}
+
+int bh_standard_units(bh_ctx *c, void *pos, void *vel, void *mass, int dtype, int64_t n,
+                      double *stats) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if (!pos || !vel || !mass) return set_error(BH_E_INVALID, "null pointer");
+    if (bad_dtype(dtype)) return set_error(BH_E_INVALID, "dtype must be BH_F32 or BH_F64");
+    if (n < 2 || n > (int64_t)0x7fff0000) return set_error(BH_E_INVALID, "n must be in [2, 2^31 - 2^16]");
+    if (use_device(c)) return BH_E_DEVICE;
+    double *hp = (double *)c->pinned + 128;
+    int rc = standard_units(c->stream, dtype, n, pos, vel, mass, c->scratch, c->su_work, hp);
+    if (rc) return rc;
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return set_error(BH_E_DEVICE, "standard units: device error");
+    if (stats)
+        for (int k = 0; k < 3; ++k) stats[k] = hp[k];
+    return BH_OK;
 }
 
 // ---------------------------------------------------------------- learned criterion

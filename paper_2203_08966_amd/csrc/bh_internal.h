@@ -98,6 +98,7 @@ struct bh_ctx {
     int mlp_step = 0;                // Adam steps taken
     int mlp_version = 0;             // bumped whenever the parameters change
     bh::DevBuf scratch;              // direct-sum partials
+    bh::DevBuf su_work;              // standard units: FP64 acc, phi, partials
     // phase timing of simulation steps
     bool timing = false;
     std::vector<hipEvent_t> events;  // 7 per recorded step
@@ -186,6 +187,13 @@ int launch_unpermute(hipStream_t s, int dtype, int64_t n, const uint32_t *id, co
 int launch_direct(hipStream_t s, int dtype, int64_t n, const void *pos, const void *mass,
                   const int64_t *targets, int64_t nt, double eps, double *acc, double *phi,
                   DevBuf &scratch);
+// every body of (pos, mass) as target, arithmetic and outputs in dtype
+int launch_direct_all(hipStream_t s, int dtype, int64_t n, const void *pos, const void *mass,
+                      double eps, void *acc, void *phi, DevBuf &scratch);
+// in place; synchronous.  host (pinned, 8 doubles) returns E_kin, E_pot
+// and the total mass before the scaling.
+int standard_units(hipStream_t s, int dtype, int64_t n, void *pos, void *vel, void *mass,
+                   DevBuf &scratch, DevBuf &work, double *host);
 
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 

@@ -3,8 +3,15 @@
 //  kick / drift   KDK leapfrog with a fixed step (Sec. 2.3)
 //  energy         E_kin = sum m v^2 / 2, E_pot = sum m phi / 2 (Sec. 2.4, each
 //                 pair once), FP64 accumulation in a fixed order
-//  direct         FP64 O(N * targets) direct sum (Sec. 2.1), the judge of the
-//                 tree walk's error; sources staged through LDS
+//  direct         O(N * targets) direct sum (Sec. 2.1): in FP64 as the judge
+//                 of the tree walk's error, and in the simulation's own
+//                 precision as the direct method of Sec. 3 (every pair, no
+//                 tree); sources staged through LDS
+//  standard units the scaling of Sec. 2.4 (total mass 1, centre-of-mass
+//                 frame, virial ratio 1/2, total energy -1/4)
+#include <algorithm>
+#include <cmath>
+
 #include "bh_internal.h"
 
 namespace bh {
@@ -101,47 +108,71 @@ __global__ __launch_bounds__(kThreads) void k_unpermute(int n, int comps,
     for (int c = 0; c < comps; ++c) dst[comps * o + c] = src[comps * (int64_t)r + c];
 }
 
-// Direct sum, FP64: thread per target, grid.y splits the sources; each
-// block stages 256 sources at a time in LDS.  Partial results per split are
-// summed afterwards in split order.
-template <typename T>
+// Direct sum: thread per target, grid.y splits the sources; each block
+// stages 256 sources at a time in LDS.  Arithmetic in R (FP64 for the judge,
+// the simulation's dtype for the direct method); each tile's sums are added
+// into FP64 accumulators, and the partial results per split are summed
+// afterwards in split order.  targets == nullptr: target t is body t.
+template <typename R> struct Src4;
+template <> struct Src4<float> { using type = float4; };
+template <> struct Src4<double> { using type = double4; };
+
+__device__ __forceinline__ float inv_sqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
+
+template <typename T, typename R>
 __global__ __launch_bounds__(kThreads) void k_direct(int n, const T *__restrict__ pos,
                                                      const T *__restrict__ mass,
                                                      const int64_t *__restrict__ targets, int nt,
                                                      double e2, int chunk,
                                                      double *__restrict__ part) {
-    __shared__ double4 src[kThreads];
+    using V4 = typename Src4<R>::type;
+    __shared__ V4 src[kThreads];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t ti = t < nt ? targets[t] : -1;
+    int64_t ti = t < nt ? (targets ? targets[t] : t) : -1;
     const bool live = ti >= 0 && ti < n;  // out-of-range targets get NaN
     if (!live) ti = -1;
-    double xi = 0, yi = 0, zi = 0;
+    R xi = 0, yi = 0, zi = 0;
     if (live) {
-        xi = pos[3 * ti];
-        yi = pos[3 * ti + 1];
-        zi = pos[3 * ti + 2];
+        xi = (R)pos[3 * ti];
+        yi = (R)pos[3 * ti + 1];
+        zi = (R)pos[3 * ti + 2];
     }
+    const R re2 = (R)e2;
     double ax = 0, ay = 0, az = 0, ph = 0;
     const int j0 = blockIdx.y * chunk;
     const int j1 = min(n, j0 + chunk);
     for (int jb = j0; jb < j1; jb += kThreads) {
         const int j = jb + threadIdx.x;
-        if (j < j1) src[threadIdx.x] = make_double4(pos[3 * (int64_t)j], pos[3 * (int64_t)j + 1],
-                                                    pos[3 * (int64_t)j + 2], mass[j]);
+        if (j < j1) {
+            V4 v;
+            v.x = (R)pos[3 * (int64_t)j];
+            v.y = (R)pos[3 * (int64_t)j + 1];
+            v.z = (R)pos[3 * (int64_t)j + 2];
+            v.w = (R)mass[j];
+            src[threadIdx.x] = v;
+        }
         __syncthreads();
         const int cnt = min(kThreads, j1 - jb);
+        const int self = (int)(ti - jb);  // tile slot of the target itself
+        R tx = 0, ty = 0, tz = 0, tp = 0;
+#pragma unroll 4
         for (int k = 0; k < cnt; ++k) {
-            const double4 s = src[k];
-            if (jb + k == ti) continue;
-            const double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-            const double r2 = dx * dx + dy * dy + dz * dz + e2;
-            const double r = sqrt(r2);
-            const double f = s.w / (r2 * r);
-            ax += f * dx;
-            ay += f * dy;
-            az += f * dz;
-            ph -= s.w / r;
+            const V4 s = src[k];
+            const R dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+            const R r2 = dx * dx + dy * dy + dz * dz + re2;
+            const R inv = k == self ? (R)0 : inv_sqrt(r2);
+            const R minv = s.w * inv;
+            const R f = minv * (inv * inv);
+            tx += f * dx;
+            ty += f * dy;
+            tz += f * dz;
+            tp -= minv;
         }
+        ax += (double)tx;
+        ay += (double)ty;
+        az += (double)tz;
+        ph += (double)tp;
         __syncthreads();
     }
     if (t < nt) {
@@ -154,18 +185,112 @@ __global__ __launch_bounds__(kThreads) void k_direct(int n, const T *__restrict_
     }
 }
 
+template <typename T>
 __global__ __launch_bounds__(kThreads) void k_direct_sum(const double *__restrict__ part, int nt,
-                                                         int nsplit, double *__restrict__ acc,
-                                                         double *__restrict__ phi) {
+                                                         int nsplit, T *__restrict__ acc,
+                                                         T *__restrict__ phi) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
     double a[4] = {0, 0, 0, 0};
     for (int s = 0; s < nsplit; ++s)
         for (int c = 0; c < 4; ++c) a[c] += part[4 * ((int64_t)s * nt + t) + c];
-    acc[3 * (int64_t)t] = a[0];
-    acc[3 * (int64_t)t + 1] = a[1];
-    acc[3 * (int64_t)t + 2] = a[2];
-    if (phi) phi[t] = a[3];
+    acc[3 * (int64_t)t] = (T)a[0];
+    acc[3 * (int64_t)t + 1] = (T)a[1];
+    acc[3 * (int64_t)t + 2] = (T)a[2];
+    if (phi) phi[t] = (T)a[3];
+}
+
+// FP64 per-block partial sums of (m, m x, m v) for the standard units.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_moments7(int n, const T *__restrict__ x,
+                                                       const T *__restrict__ v,
+                                                       const T *__restrict__ m,
+                                                       double *__restrict__ part) {
+    double q[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double mi = m[i];
+        q[0] += mi;
+        for (int c = 0; c < 3; ++c) {
+            q[1 + c] += mi * (double)x[3 * (int64_t)i + c];
+            q[4 + c] += mi * (double)v[3 * (int64_t)i + c];
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        for (int c = 0; c < 7; ++c) q[c] += __shfl_xor(q[c], o);
+    __shared__ double s[7][kThreads / 64];
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0)
+        for (int c = 0; c < 7; ++c) s[c][w] = q[c];
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        double a = 0;
+        for (int k = 0; k < kThreads / 64; ++k) a += s[threadIdx.x][k];
+        part[7 * blockIdx.x + threadIdx.x] = a;
+    }
+}
+
+// One block: fixed-order sums of nb partial rows of k values.
+__global__ __launch_bounds__(64) void k_rows_final(const double *__restrict__ part, int nb, int k,
+                                                   double *__restrict__ out) {
+    if ((int)threadIdx.x >= k) return;
+    double a = 0;
+    for (int b = 0; b < nb; ++b) a += part[k * b + threadIdx.x];
+    out[threadIdx.x] = a;
+}
+
+// m /= M; x -= com; v -= vcom (shift and mass scale in FP64, stored in T)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_shift(int n, T *__restrict__ x, T *__restrict__ v,
+                                                    T *__restrict__ m, double minv, double cx,
+                                                    double cy, double cz, double ux, double uy,
+                                                    double uz) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        m[i] = (T)((double)m[i] * minv);
+        x[3 * (int64_t)i] = (T)((double)x[3 * (int64_t)i] - cx);
+        x[3 * (int64_t)i + 1] = (T)((double)x[3 * (int64_t)i + 1] - cy);
+        x[3 * (int64_t)i + 2] = (T)((double)x[3 * (int64_t)i + 2] - cz);
+        v[3 * (int64_t)i] = (T)((double)v[3 * (int64_t)i] - ux);
+        v[3 * (int64_t)i + 1] = (T)((double)v[3 * (int64_t)i + 1] - uy);
+        v[3 * (int64_t)i + 2] = (T)((double)v[3 * (int64_t)i + 2] - uz);
+    }
+}
+
+// Per-block FP64 partial sums of (m v^2 / 2, m phi / 2) with FP64 phi.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_energy64(int n, const T *__restrict__ v,
+                                                       const T *__restrict__ m,
+                                                       const double *__restrict__ phi,
+                                                       double *__restrict__ part) {
+    double q[2] = {0, 0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double vx = v[3 * (int64_t)i], vy = v[3 * (int64_t)i + 1], vz = v[3 * (int64_t)i + 2];
+        const double mi = m[i];
+        q[0] += 0.5 * mi * (vx * vx + vy * vy + vz * vz);
+        q[1] += 0.5 * mi * phi[i];
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        for (int c = 0; c < 2; ++c) q[c] += __shfl_xor(q[c], o);
+    __shared__ double s[2][kThreads / 64];
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0)
+        for (int c = 0; c < 2; ++c) s[c][w] = q[c];
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double a = 0;
+        for (int k = 0; k < kThreads / 64; ++k) a += s[threadIdx.x][k];
+        part[2 * blockIdx.x + threadIdx.x] = a;
+    }
+}
+
+// x *= a; v *= b (in FP64, stored in T)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scale(int64_t n3, T *__restrict__ x,
+                                                    T *__restrict__ v, double a, double b) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n3;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] = (T)((double)x[i] * a);
+        v[i] = (T)((double)v[i] * b);
+    }
 }
 
 int grid_for(int64_t n) {
@@ -218,8 +343,11 @@ int launch_unpermute(hipStream_t s, int dtype, int64_t n, const uint32_t *id, co
     return check_launch("unpermute");
 }
 
-int launch_direct(hipStream_t s, int dtype, int64_t n, const void *pos, const void *mass,
-                  const int64_t *targets, int64_t nt, double eps, double *acc, double *phi,
+namespace {
+// sources split so that about 2048 blocks are in flight
+template <typename T, typename R, typename O>
+int direct_splits(hipStream_t s, int64_t n, const T *pos, const T *mass,
+                  const int64_t *targets, int64_t nt, double eps, O *acc, O *phi,
                   DevBuf &scratch) {
     const int bx = div_up(nt, kThreads);
     int nsplit = 2048 / bx;
@@ -231,16 +359,93 @@ int launch_direct(hipStream_t s, int dtype, int64_t n, const void *pos, const vo
     int rc = grow(scratch, 32ull * nsplit * nt);
     if (rc) return rc;
     dim3 grid(bx, nsplit);
-    if (dtype == BH_F32)
-        k_direct<float><<<grid, kThreads, 0, s>>>((int)n, (const float *)pos, (const float *)mass,
-                                                  targets, (int)nt, eps * eps, chunk,
-                                                  (double *)scratch.p);
-    else
-        k_direct<double><<<grid, kThreads, 0, s>>>((int)n, (const double *)pos,
-                                                   (const double *)mass, targets, (int)nt,
-                                                   eps * eps, chunk, (double *)scratch.p);
-    k_direct_sum<<<bx, kThreads, 0, s>>>((const double *)scratch.p, (int)nt, nsplit, acc, phi);
+    k_direct<T, R><<<grid, kThreads, 0, s>>>((int)n, pos, mass, targets, (int)nt, eps * eps,
+                                             chunk, (double *)scratch.p);
+    k_direct_sum<O><<<bx, kThreads, 0, s>>>((const double *)scratch.p, (int)nt, nsplit, acc, phi);
     return check_launch("direct");
+}
+}  // namespace
+
+int launch_direct(hipStream_t s, int dtype, int64_t n, const void *pos, const void *mass,
+                  const int64_t *targets, int64_t nt, double eps, double *acc, double *phi,
+                  DevBuf &scratch) {
+    if (dtype == BH_F32)
+        return direct_splits<float, double, double>(s, n, (const float *)pos, (const float *)mass,
+                                                    targets, nt, eps, acc, phi, scratch);
+    return direct_splits<double, double, double>(s, n, (const double *)pos, (const double *)mass,
+                                                 targets, nt, eps, acc, phi, scratch);
+}
+
+int launch_direct_all(hipStream_t s, int dtype, int64_t n, const void *pos, const void *mass,
+                      double eps, void *acc, void *phi, DevBuf &scratch) {
+    if (dtype == BH_F32)
+        return direct_splits<float, float, float>(s, n, (const float *)pos, (const float *)mass,
+                                                  nullptr, n, eps, (float *)acc, (float *)phi,
+                                                  scratch);
+    return direct_splits<double, double, double>(s, n, (const double *)pos, (const double *)mass,
+                                                 nullptr, n, eps, (double *)acc, (double *)phi,
+                                                 scratch);
+}
+
+namespace {
+template <typename T>
+int standard_units_t(hipStream_t s, int64_t n, T *pos, T *vel, T *mass, DevBuf &scratch,
+                     DevBuf &work, double *host) {
+    const int nb = 256;
+    // work: direct-sum acc (3 n) and phi (n), then the partial rows
+    int rc = grow(work, 8ull * (4 * n + 7 * nb + 8));
+    if (rc) return rc;
+    double *wacc = (double *)work.p, *wphi = wacc + 3 * n, *part = wphi + n;
+    double *tot = part + 7 * nb;
+    auto fetch = [&](int k) -> int {
+        if (hipMemcpyAsync(host, tot, 8 * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return set_error(BH_E_DEVICE, "standard units: reduction copy failed");
+        for (int c = 0; c < k; ++c)
+            if (!std::isfinite(host[c]))
+                return set_error(BH_E_NONFINITE, "standard units: non-finite input");
+        return BH_OK;
+    };
+    // 1. total mass 1 and the centre-of-mass frame
+    k_moments7<T><<<nb, kThreads, 0, s>>>((int)n, pos, vel, mass, part);
+    k_rows_final<<<1, 64, 0, s>>>(part, nb, 7, tot);
+    if ((rc = fetch(7))) return rc;
+    const double M = host[0];
+    if (!(M > 0)) return set_error(BH_E_INVALID, "standard units: total mass must be > 0");
+    k_shift<T><<<std::min(div_up(n, kThreads), 4096), kThreads, 0, s>>>(
+        (int)n, pos, vel, mass, 1.0 / M, host[1] / M, host[2] / M, host[3] / M, host[4] / M,
+        host[5] / M, host[6] / M);
+    // 2. kinetic and (unsoftened) potential energy
+    if ((rc = direct_splits<T, double, double>(s, n, pos, mass, nullptr, n, 0.0, wacc, wphi,
+                                               scratch)))
+        return rc;
+    k_energy64<T><<<nb, kThreads, 0, s>>>((int)n, vel, mass, wphi, part);
+    k_rows_final<<<1, 64, 0, s>>>(part, nb, 2, tot);
+    if ((rc = fetch(2))) return rc;
+    const double ek = host[0], ep = host[1];
+    if (!(ek > 0)) return set_error(BH_E_INVALID, "standard units: kinetic energy must be > 0");
+    if (!(ep < 0)) return set_error(BH_E_INVALID, "standard units: potential energy must be < 0");
+    // 3. velocities to virial ratio 1/2: E_kin = -E_pot / 2, so E = E_pot / 2
+    const double qv = std::sqrt(-0.5 * ep / ek);
+    // 4. lengths x b, velocities x 1/sqrt(b): E -> E / b = -1/4 for b = -2 E_pot
+    const double b = -2.0 * ep;
+    k_scale<T><<<std::min(div_up(3 * n, kThreads), 4096), kThreads, 0, s>>>(
+        3 * n, pos, vel, b, qv / std::sqrt(b));
+    if ((rc = check_launch("standard units"))) return rc;
+    host[0] = ek;
+    host[1] = ep;
+    host[2] = M;
+    return BH_OK;
+}
+}  // namespace
+
+int standard_units(hipStream_t s, int dtype, int64_t n, void *pos, void *vel, void *mass,
+                   DevBuf &scratch, DevBuf &work, double *host) {
+    if (dtype == BH_F32)
+        return standard_units_t<float>(s, n, (float *)pos, (float *)vel, (float *)mass, scratch,
+                                       work, host);
+    return standard_units_t<double>(s, n, (double *)pos, (double *)vel, (double *)mass, scratch,
+                                    work, host);
 }
 
 }  // namespace bh

@@ -9,6 +9,9 @@ standard units, Sec. 5; the sizes below are the measured configurations):
 
 * ``plummer``   -- one Plummer sphere, equal masses.
 * ``two_spheres`` -- two Plummer spheres on a collision course, lognormal masses.
+* ``two_clusters`` -- the paper's test problem: two equal-mass Plummer
+  clusters of n/2 bodies each, offset in every dimension, at rest relative
+  to each other (to be scaled to standard units before use).
 * ``clumpy``    -- many small Plummer clumps in a unit cube plus a uniform
   background at rest.
 
@@ -27,6 +30,7 @@ __all__ = [
     "Bodies",
     "plummer",
     "two_spheres",
+    "two_clusters",
     "clumpy",
     "subsample",
     "config",
@@ -125,6 +129,30 @@ def two_spheres(n: int, seed: int, a1: float = 1.0, a2: float = 0.3,
     vel = np.concatenate([parts[0][1], parts[1][1]])
     mass = np.concatenate([parts[0][2], parts[1][2]])
     return Bodies(pos, vel, mass, {"kind": "two_spheres", "n": n, "seed": seed})
+
+
+def two_clusters(n: int, seed: int, offset: float = 2.0) -> Bodies:
+    """Two Plummer clusters (scale radius 1, mass 1/2 each, equal-mass
+    bodies) centred at -offset (1, 1, 1) and +offset (1, 1, 1), each in its
+    own equilibrium and at rest relative to the other, so that mutual
+    gravity brings them together (Sec. 5's collision of two globular
+    clusters).  The paper runs it in standard units, which needs the
+    system's potential energy: apply that scaling (with the library or the
+    oracle) before integrating."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n1 = n // 2
+    parts = []
+    for nk, sgn in ((n1, -1.0), (n - n1, 1.0)):
+        p, v = _plummer_unit(rng, nk)
+        m = np.full(nk, 1.0 / n)
+        p, v = _com_shift(p, v, m)
+        v = v * np.sqrt(0.5)  # virialised with the cluster's own mass 1/2
+        parts.append((p + sgn * offset, v, m))
+    pos = np.concatenate([parts[0][0], parts[1][0]])
+    vel = np.concatenate([parts[0][1], parts[1][1]])
+    mass = np.concatenate([parts[0][2], parts[1][2]])
+    return Bodies(pos, vel, mass, {"kind": "two_clusters", "n": n, "seed": seed,
+                                   "offset": offset})
 
 
 def clumpy(n: int, seed: int, n_clumps: int = 4096, mean_radius: float = 0.05,

@@ -28,8 +28,17 @@ wavefront tree walk, the second kick, and the FP64 energy diagnostic.
 value = N / (time per step): one force evaluation per step, tree build
 included.  Inputs are resident on the GPU before timing starts.
 
+After the timed steps the direct method (every pair, FP32, no tree) is
+timed once on the same bodies as the O(N^2) reference point.
+
 Prints ONE JSON line.  --gpus N with N > 1 is refused: this build targets
 one GPU.
+
+--energy-table runs the paper's validation experiment instead (Sec. 5):
+two Plummer clusters colliding, in standard units, theta 0.5, dt 0.01, 500
+steps, FP64, one body per leaf as in the paper's tree, softening 0.003 (the
+paper gives none), for N = 10000 ... 80000, with the tree code and with the
+direct method; it prints one JSON line with |dE/E| in percent per run.
 """
 from __future__ import annotations
 
@@ -88,6 +97,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="bodies the CPU oracle walks (the tree is built in full)")
+    ap.add_argument("--energy-table", action="store_true",
+                    help="run the two-cluster energy-conservation experiment and exit")
+    ap.add_argument("--table-n", default="10000,20000,40000,60000,80000")
+    ap.add_argument("--table-steps", type=int, default=500)
+    ap.add_argument("--table-eps", type=float, default=0.003)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (to scale "
                          "the profiler's FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -125,6 +139,9 @@ def main():
         log("bench.py needs a GPU")
         sys.exit(1)
     B.load()
+    if args.energy_table:
+        energy_table(args)
+        return
     bodies, cfg = W.config(args.config, n=args.n)
     n = bodies.n
     eps, leaf, dt, order = cfg["eps"], cfg["leaf"], cfg["dt"], 2
@@ -320,11 +337,78 @@ def main():
         },
     }
 
+    result["direct_method"] = direct_method(ctx, pos, vel, mass, leaf, eps, tg, ref,
+                                            walk_step_ms)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(bodies, cfg, methods.get("body-theta", {}).get(
             "param", 0.6), order, args.cpu_sample)
     B.bh_ctx_destroy(ctx)
     print(json.dumps(result), flush=True)
+
+
+def direct_method(ctx, pos, vel, mass, leaf, eps, tg, ref, walk_step_ms):
+    """One force evaluation of the direct method (every pair, the
+    simulation's dtype, no tree) on the timed workload's initial bodies:
+    its kernel time, rate and error against the FP64 judge."""
+    import torch
+    from paper_2203_08966_amd import binding as B
+    n = int(mass.shape[0])
+    o = B.force_opts(walk=B.BH_WALK_DIRECT)
+    B.bh_sim_init(ctx, pos, vel, mass, leaf, 0.5, eps, o)
+    B.bh_sim_timing(ctx, True)
+    B.bh_leapfrog_step(ctx, 0.0)  # dt 0: the same positions again
+    ms, _ = B.bh_sim_timing_get(ctx)
+    B.bh_sim_timing(ctx, False)
+    a = torch.empty_like(pos)
+    B.bh_sim_get(ctx, None, None, a)
+    a = a.index_select(0, tg.to(torch.int64)).cpu().numpy().astype(np.float64)
+    e = np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    t = ms[4]
+    log(f"direct method: {t:.1f} ms per force evaluation, rms {np.sqrt(np.mean(e * e)):.2e}")
+    return {"ms": t, "bodies_per_s": n / (t * 1e-3),
+            "interactions_per_s": n * (n - 1) / (t * 1e-3),
+            "rms_rel_err": float(np.sqrt(np.mean(e * e))),
+            "tree_walk_speedup": t / walk_step_ms}
+
+
+def energy_table(args):
+    """Sec. 5's validation: |dE/E| (percent) after the run, per N and method."""
+    import torch
+    from paper_2203_08966_amd import binding as B
+    from paper_2203_08966_amd import workloads as W
+    ctx = B.bh_ctx_create(0)
+    dev = torch.device("cuda:0")
+    theta, dt, eps, steps, seed = 0.5, 0.01, args.table_eps, args.table_steps, 2203
+    rows = []
+    for n in [int(v) for v in args.table_n.split(",")]:
+        b = W.two_clusters(n, seed)
+        P, V, M = (torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+                   for a in (b.pos, b.vel, b.mass))
+        B.bh_standard_units(ctx, P, V, M)
+        for name, opts in (("direct", B.force_opts(walk=B.BH_WALK_DIRECT)),
+                           ("tree", B.force_opts(order=2))):
+            B.bh_sim_init(ctx, P, V, M, 1, theta, eps, opts)
+            e0 = sum(B.bh_energy(ctx))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(steps):
+                B.bh_leapfrog_step(ctx, dt)
+                if (k + 1) % 100 == 0:
+                    B.bh_energy(ctx)  # paces the queue; also a progress point
+                    log(f"  N={n} {name}: step {k + 1}")
+            e1 = sum(B.bh_energy(ctx))
+            t1 = time.perf_counter()
+            rows.append({"n": n, "method": name, "E0": e0, "E_end": e1,
+                         "dE_over_E_percent": 100.0 * abs(e1 - e0) / abs(e0),
+                         "ms_per_step": (t1 - t0) * 1e3 / steps})
+            log(f"N={n} {name}: E0 {e0:.6f} |dE/E| {rows[-1]['dE_over_E_percent']:.4f} % "
+                f"({rows[-1]['ms_per_step']:.2f} ms/step)")
+    B.bh_ctx_destroy(ctx)
+    print(json.dumps({"energy_table": rows, "config": {
+        "workload": f"two Plummer clusters (offset +-2 (1,1,1), at rest), standard units, "
+                    f"seed {seed}",
+        "theta": theta, "dt": dt, "steps": steps, "eps": eps, "leaf": 1, "order": 2,
+        "dtype": "f64"}}), flush=True)
 
 
 def result_workload(cfg, n):

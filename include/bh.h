@@ -213,9 +213,9 @@ int bh_tree_export(const bh_tree *tree, uint64_t *keys, uint32_t *perm, uint64_t
 /* ---------------------------------------------------------------------
  * Simulation: kick-drift-kick leapfrog with a fixed step (Sec. 2.3).
  * bh_sim_init copies pos/vel/mass (device, dtype) into context-owned state,
- * builds the tree and computes the initial accelerations.  Each
- * bh_leapfrog_step(dt) does v += a dt/2; x += v dt; rebuild; walk;
- * v += a dt/2.  State is kept in key order between steps.  With
+ * builds the tree and computes the initial accelerations (and potential).
+ * Each bh_leapfrog_step(dt) does v += a dt/2; x += v dt; rebuild; walk
+ * (accelerations); v += a dt/2.  State is kept in key order between steps.  With
  * BH_MAC_MLP / BH_MAC_BUDGET, opts.mlp_acc_norm is ignored: the initial
  * walk estimates |a_i| by a monopole walk, later steps use the previous
  * step's accelerations.
@@ -226,8 +226,12 @@ int bh_leapfrog_step(bh_ctx *ctx, double dt);
 /* Copies state to device buffers in caller order (any may be NULL). */
 int bh_sim_get(bh_ctx *ctx, void *pos, void *vel, void *acc);
 /* Kinetic energy sum m v^2 / 2 and potential energy sum m phi / 2 (each
- * pair once, softened; Sec. 2.4), phi from the last walk, accumulated in
- * FP64.  Synchronous. */
+ * pair once, softened; Sec. 2.4), accumulated in FP64.  Steps compute
+ * accelerations only; phi comes from the last walk if it computed it (the
+ * initial walk, the direct method, an earlier bh_energy of the same state),
+ * else from one more walk of the current tree with the simulation's
+ * options (a relative criterion takes |a_i| from the current
+ * accelerations), whose accelerations are discarded.  Synchronous. */
 int bh_energy(bh_ctx *ctx, double *ekin, double *epot);
 /* The simulation's current tree (owned by the context; do not free).  With
  * BH_WALK_DIRECT, the tree of bh_sim_init: the steps build none. */

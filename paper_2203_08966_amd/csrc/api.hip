@@ -71,7 +71,7 @@ static void free_tree_bufs(bh_tree *t) {
 
 static void free_sim(SimState *s) {
     DevBuf *all[] = {&s->pos, &s->vel, &s->mass, &s->acc, &s->phi, &s->id,
-                     &s->pos2, &s->vel2, &s->mass2, &s->id2, &s->red};
+                     &s->pos2, &s->vel2, &s->mass2, &s->id2, &s->red, &s->acc_tmp};
     for (DevBuf *b : all) free_buf(*b);
 }
 
@@ -341,18 +341,24 @@ int bh_tree_export(const bh_tree *t, uint64_t *keys, uint32_t *perm, uint64_t *h
 // ---------------------------------------------------------------- simulation
 // Forces of the current (just rebuilt) step.  The accelerations of the
 // previous step are still in s->acc, in the order the tree was built from,
-// and give the learned criterion its |a_i|.
-static int sim_forces(bh_ctx *c) {
+// and give the learned criterion its |a_i|.  The potential is computed when
+// asked for (the initial walk; bh_energy): a step's loop body needs only the
+// accelerations.
+static int sim_forces(bh_ctx *c, bool want_phi) {
     SimState *s = c->sim;
+    int rc;
     if (s->opts.walk == BH_WALK_DIRECT) {  // every pair, no tree (Sec. 3, direct method)
         if (c->walk_ev) hipEventRecord(c->walk_ev[0], c->stream);
-        int rc = launch_direct_all(c->stream, s->dtype, s->n, s->pos.p, s->mass.p, s->eps,
-                                   s->acc.p, s->phi.p, c->scratch);
+        rc = launch_direct_all(c->stream, s->dtype, s->n, s->pos.p, s->mass.p, s->eps,
+                               s->acc.p, s->phi.p, c->scratch);
         if (c->walk_ev) hipEventRecord(c->walk_ev[1], c->stream);
+        s->phi_valid = rc == BH_OK;
         return rc;
     }
-    return run_walk(c->sim_tree, s->theta, s->eps, s->acc.p, s->phi.p, nullptr, nullptr, s->opts,
-                    true, s->have_acc ? s->acc.p : nullptr);
+    rc = run_walk(c->sim_tree, s->theta, s->eps, s->acc.p, want_phi ? s->phi.p : nullptr,
+                  nullptr, nullptr, s->opts, true, s->have_acc ? s->acc.p : nullptr);
+    s->phi_valid = want_phi && rc == BH_OK;
+    return rc;
 }
 
 static int sim_rebuild(bh_ctx *c, const void *pos, const void *vel, const void *mass,
@@ -409,7 +415,7 @@ int bh_sim_init(bh_ctx *c, const void *pos, const void *vel, const void *mass, i
         return rc;
     // first build gathers straight from the caller's arrays
     if ((rc = sim_rebuild(c, pos, vel, mass, nullptr))) return rc;
-    if ((rc = sim_forces(c))) return rc;
+    if ((rc = sim_forces(c, true))) return rc;
     s->have_acc = true;
     return BH_OK;
 }
@@ -451,7 +457,7 @@ int bh_leapfrog_step(bh_ctx *c, double dt) {
         return rc;
     mark(2);
     c->walk_ev = ev ? ev + 5 : nullptr;  // the walk kernel alone: events 5, 6
-    rc = sim_forces(c);
+    rc = sim_forces(c, false);
     c->walk_ev = nullptr;
     if (rc) return rc;
     mark(3);
@@ -508,8 +514,19 @@ int bh_energy(bh_ctx *c, double *ekin, double *epot) {
     if (!c->sim || !c->sim->have_acc) return set_error(BH_E_STATE, "bh_sim_init has not run");
     if (use_device(c)) return BH_E_DEVICE;
     SimState *s = c->sim;
+    int rc;
+    if (!s->phi_valid) {
+        // the potential of the current state: the same walk (tree, theta,
+        // criterion; |a_i| from the current accelerations) with phi, its
+        // accelerations set aside
+        if ((rc = grow(s->acc_tmp, 3 * dsize(s->dtype) * s->n))) return rc;
+        if ((rc = run_walk(c->sim_tree, s->theta, s->eps, s->acc_tmp.p, s->phi.p, nullptr,
+                           nullptr, s->opts, true, s->acc.p)))
+            return rc;
+        s->phi_valid = true;
+    }
     double *red = (double *)s->red.p;
-    int rc = launch_energy(c->stream, s->dtype, s->n, s->vel.p, s->mass.p, s->phi.p, red,
+    rc = launch_energy(c->stream, s->dtype, s->n, s->vel.p, s->mass.p, s->phi.p, red,
                            red + 2 * 1024);
     if (rc) return rc;
     double *hp = (double *)c->pinned + 64;

@@ -153,7 +153,9 @@ struct SimState {
     DevBuf pos, vel, mass, acc, phi, id;       // key order (current)
     DevBuf pos2, vel2, mass2, id2;             // gather targets
     DevBuf red;                                // energy reduction scratch
+    DevBuf acc_tmp;                            // accelerations of an energy walk
     bool have_acc = false;
+    bool phi_valid = false;                    // phi belongs to the current state
 };
 
 // ---- host helpers (api.hip)

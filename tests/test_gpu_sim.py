@@ -74,6 +74,28 @@ def test_leapfrog_fp32_short_run(ctx):
     assert abs(e1 - e0) < 1e-4 * abs(e0)
 
 
+def test_energy_potential_on_demand(ctx):
+    """Steps compute accelerations only; bh_energy then walks the current
+    tree once more for the potential.  It equals the potential of a fresh
+    simulation started from the final state (whose initial walk computes it),
+    and a second call returns the same values."""
+    pos, vel, mass = case_bodies("plummer", 8192, 5, np.float32)
+    theta, eps, leaf, dt = 0.6, 0.01, 16, 1e-3
+    say("energy on demand: 8192 bodies, 4 steps")
+    P, V, M = (torch.from_numpy(a).cuda() for a in (pos, vel, mass))
+    B.bh_sim_init(ctx, P, V, M, leaf, theta, eps)
+    for _ in range(4):
+        B.bh_leapfrog_step(ctx, dt)
+    e1 = B.bh_energy(ctx)
+    assert B.bh_energy(ctx) == e1
+    x, v = torch.empty_like(P), torch.empty_like(V)
+    B.bh_sim_get(ctx, x, v)
+    B.bh_sim_init(ctx, x, v, M, leaf, theta, eps)
+    e2 = B.bh_energy(ctx)
+    assert e1[0] == e2[0]
+    assert abs(e1[1] - e2[1]) <= 1e-6 * abs(e2[1])
+
+
 def test_sim_state_errors(ctx):
     c2 = B.bh_ctx_create(0)
     with pytest.raises(B.BHError) as e:

@@ -739,54 +739,45 @@ __global__ __launch_bounds__(256) void k_gwalk(
 // the space-filling curve has a box spanning the cells on both sides and
 // costs many times an ordinary group; such groups are recognised by the
 // smallest cell holding the group's first and last keys: the more bodies
-// that cell holds (counted by galloping outwards from the group in the
-// sorted keys, up to the largest threshold), the more the group is spread
-// out.  Within each XCD's chunk, groups predicted to exceed the work cap
-// come first (kParts items each), then groups whose common cell holds more
-// than 256 x 64 bodies, then those above 16 x 64, then the rest (order
-// inside a class is immaterial: groups are independent).  Two launches over
-// all groups: classify and count, then place.
+// that cell holds, the more the group is spread out.  The cell is found
+// from the tree, climbing from the first body's leaf to the first ancestor
+// at or above the keys' common level (a cell holding more than a leaf's
+// bodies is a node).  Within each XCD's chunk, groups predicted to exceed
+// the work cap come first (kParts items each), then groups whose common
+// cell holds more than 256 x 64 bodies, then those above 16 x 64, then the
+// rest (order inside a class is immaterial: groups are independent).  Two
+// launches over all groups: classify and count, then place.
 //
 // Queue memory per XCD chunk x (uint32 words at 64 x): [0] hand-out
 // counter, [16] item count, [20 + c] items of class c, [24 + c] placed.
 // hand-out position of a class: 3 first, then 0, 1, 2
 __device__ __forceinline__ int class_pos(int c) { return c == 3 ? 0 : c + 1; }
 
-__device__ __forceinline__ int group_class(const uint64_t *__restrict__ keys, int64_t n, int t0,
-                                           int t1, int g, const uint8_t *__restrict__ gfb) {
+template <typename R>
+__device__ __forceinline__ int group_class(const uint64_t *__restrict__ keys, int t0, int t1,
+                                           int g, const uint8_t *__restrict__ gfb,
+                                           const Anchor<R> *__restrict__ anchors,
+                                           const int32_t *__restrict__ level,
+                                           const int32_t *__restrict__ parent,
+                                           const int32_t *__restrict__ count) {
     if (gfb && gfb[g] > 0) return 3;
-    const int64_t r0 = t0 + 64 * (int64_t)g, r1 = min(r0 + 63, (int64_t)t1 - 1);
-    const uint64_t a = keys[r0];
-    const uint64_t x = a ^ keys[r1];
+    const int r0 = t0 + 64 * g, r1 = min(r0 + 63, t1 - 1);
+    const uint64_t x = keys[r0] ^ keys[r1];
     const int lcp = x == 0 ? 21 : (__builtin_clzll(x) - 1) / 3;  // shared octal digits
-    const int sh = 3 * (21 - lcp);  // 0..63; keys are below 2^63
-    const uint64_t pre = a >> sh;   // the cell's key prefix
-    // bodies of the cell beyond the group on either side, counted by
-    // galloping outwards up to the largest threshold
-    constexpr int64_t kBig = 256 * 64;
-    auto reach = [&](int64_t from, int dir) -> int64_t {
-        int64_t in = 0, step = 1;
-        for (;;) {  // keys[from + dir * in] is inside the cell
-            const int64_t j = from + dir * (in + step);
-            if (j < 0 || j >= n || (keys[j] >> sh) != pre) break;
-            in += step;
-            if (in > kBig) return in;
-            step <<= 1;
-        }
-        while (step > 1) {  // inside at in, outside (or beyond n) at in + step
-            step >>= 1;
-            const int64_t j = from + dir * (in + step);
-            if (j >= 0 && j < n && (keys[j] >> sh) == pre) in += step;
-        }
-        return in;
-    };
-    const int64_t c = (r1 - r0 + 1) + reach(r0, -1) + reach(r1, 1);
-    return c > kBig ? 0 : (c > 16 * 64 ? 1 : 2);
+    int node = anchors[r0].leaf;
+    for (int p; level[node] > lcp && (p = parent[node]) >= 0;) node = p;
+    const int c = count[node];
+    return c > 256 * 64 ? 0 : (c > 16 * 64 ? 1 : 2);
 }
 
-__global__ __launch_bounds__(256) void k_group_class(const uint64_t *__restrict__ keys, int64_t n,
-                                                     int t0, int t1, int ng,
+template <typename R>
+__global__ __launch_bounds__(256) void k_group_class(const uint64_t *__restrict__ keys, int t0,
+                                                     int t1, int ng,
                                                      const uint8_t *__restrict__ gfb,
+                                                     const Anchor<R> *__restrict__ anchors,
+                                                     const int32_t *__restrict__ level,
+                                                     const int32_t *__restrict__ parent,
+                                                     const int32_t *__restrict__ count,
                                                      uint8_t *__restrict__ cls,
                                                      uint32_t *__restrict__ queue) {
     __shared__ uint32_t cnt[8][4];  // per XCD chunk and class, this block's share
@@ -795,7 +786,7 @@ __global__ __launch_bounds__(256) void k_group_class(const uint64_t *__restrict_
     const int chunk = (ng + 7) / 8;
     const int g = blockIdx.x * 256 + threadIdx.x;
     if (g < ng) {
-        const int c = group_class(keys, n, t0, t1, g, gfb);
+        const int c = group_class<R>(keys, t0, t1, g, gfb, anchors, level, parent, count);
         cls[g] = (uint8_t)c;
         atomicAdd(&cnt[g / chunk][c], c == 3 ? (uint32_t)kParts : 1u);
     }
@@ -879,8 +870,10 @@ void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, vo
     if (grow(t->gorder, 4ull * kParts * ng + ng) == BH_OK) {
         uint32_t *items = (uint32_t *)t->gorder.p;
         uint8_t *cls = (uint8_t *)(items + (size_t)kParts * ng);
-        k_group_class<<<div_up(ng, 256), 256, 0, t->ctx->stream>>>(t->sorted_keys, t->n, t0, t1,
-                                                                  ng, gfb, cls, queue);
+        k_group_class<R><<<div_up(ng, 256), 256, 0, t->ctx->stream>>>(
+            t->sorted_keys, t0, t1, ng, gfb, (const Anchor<R> *)t->anchors.p,
+            (const int32_t *)t->level.p, (const int32_t *)t->parent.p,
+            (const int32_t *)t->count.p, cls, queue);
         k_group_place<<<div_up(ng, 256), 256, 0, t->ctx->stream>>>(ng, cls, gfb, items, queue);
         g2.items = items;
         g2.gfb = gfb;

@@ -42,6 +42,36 @@ def test_standard_units_match_oracle(ctx, dtype):
     assert abs(ek + ep + 0.25) <= (1e-12 if dtype == np.float64 else 1e-5)
 
 
+def test_standard_units_two_body_closed_form(ctx):
+    """Masses 1 and 3 two apart along y, relative velocity 4 along -x: in
+    standard units the masses are 1/4 and 3/4, the separation 3/8 (W = -1/2)
+    and the relative speed sqrt(8/3) (E_kin = 1/4), directions kept, centre
+    of mass at rest at the origin."""
+    pos = np.array([[0.3, -1.0, 2.0], [0.3, 1.0, 2.0]])
+    vel = np.array([[5.0, 0.0, 0.0], [1.0, 0.0, 0.0]])
+    x, v, m, st = _units(ctx, pos, vel, np.array([1.0, 3.0]))
+    r, u = 3.0 / 8.0, np.sqrt(8.0 / 3.0)
+    np.testing.assert_allclose(m, [0.25, 0.75], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(x, [[0, -0.75 * r, 0], [0, 0.25 * r, 0]], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(v, [[0.75 * u, 0, 0], [-0.25 * u, 0, 0]], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(st, [1.5, -3.0 / 32.0, 4.0], rtol=1e-14)
+
+
+def test_direct_method_single_body(ctx):
+    """One body: no force, so a step moves it by v dt; its energy is all
+    kinetic."""
+    P = torch.tensor([[0.5, -0.25, 2.0]], dtype=torch.float64, device="cuda")
+    V = torch.tensor([[1.0, 2.0, -3.0]], dtype=torch.float64, device="cuda")
+    M = torch.tensor([2.0], dtype=torch.float64, device="cuda")
+    B.bh_sim_init(ctx, P, V, M, 8, 0.5, 0.0, _direct_opts())
+    B.bh_leapfrog_step(ctx, 0.125)
+    x, a = torch.empty_like(P), torch.empty_like(P)
+    B.bh_sim_get(ctx, x, None, a)
+    assert torch.equal(a.cpu(), torch.zeros(1, 3, dtype=torch.float64))
+    assert torch.equal(x.cpu(), torch.tensor([[0.625, 0.0, 1.625]], dtype=torch.float64))
+    assert B.bh_energy(ctx) == (14.0, 0.0)
+
+
 def test_standard_units_errors(ctx):
     """A system at rest has no kinetic energy to scale (BH_E_INVALID); two
     bodies at one point make the unsoftened potential infinite

@@ -30,6 +30,7 @@
 #ifndef BH_H
 #define BH_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -143,6 +144,21 @@ void bh_force_opts_default(bh_force_opts *opts);
  * BH_E_DEVICE when the device cannot be used. */
 int bh_ctx_create(int device, void *stream, bh_ctx **out);
 int bh_ctx_set_stream(bh_ctx *ctx, void *stream);
+
+/* Device memory from the caller's allocator (e.g. a framework's caching
+ * allocator) instead of hipMalloc.  alloc(bytes, device, stream, user)
+ * returns device memory of at least `bytes` on `device`, usable in the
+ * order of `stream` (the context's stream at the time), or NULL (the call
+ * then fails with BH_E_NOMEM); free_fn(ptr, bytes, device, stream, user)
+ * takes back a block with the arguments of its allocation.  Both or
+ * neither (NULL, NULL: hipMalloc again).  Buffers allocated earlier keep
+ * the allocator they came from.  Every device buffer of the context, its
+ * trees and its simulation state grows through it; the library frees a
+ * buffer only when it grows it or when its owner is freed, so the
+ * functions must stay valid until the context is destroyed. */
+typedef void *(*bh_alloc_fn)(size_t bytes, int device, void *stream, void *user);
+typedef void (*bh_free_fn)(void *ptr, size_t bytes, int device, void *stream, void *user);
+int bh_ctx_set_allocator(bh_ctx *ctx, bh_alloc_fn alloc, bh_free_fn free_fn, void *user);
 /* Frees the context, its simulation state and its learned-criterion
  * weights.  Trees built with it must be freed first. */
 int bh_ctx_destroy(bh_ctx *ctx);

@@ -28,7 +28,7 @@ EXPORTED = [
     "bh_tree_export", "bh_sim_init", "bh_leapfrog_step", "bh_sim_get", "bh_energy",
     "bh_sim_tree", "bh_direct", "bh_sim_timing", "bh_sim_timing_get", "bh_mlp_set",
     "bh_mlp_get", "bh_mlp_samples", "bh_mlp_train", "bh_mlp_grad", "bh_mlp_infer",
-    "bh_standard_units",
+    "bh_standard_units", "bh_ctx_set_allocator",
 ]
 BH_MLP_PARAMS = 1441
 
@@ -36,7 +36,7 @@ BH_MLP_PARAMS = 1441
 __all__ = EXPORTED + [
     "BHError", "ForceOpts", "TreeInfo", "force_opts", "load", "BH_OK", "BH_E_INVALID",
     "BH_E_NOMEM", "BH_E_DEVICE", "BH_E_STATE", "BH_E_NONFINITE", "BH_F32", "BH_F64",
-    "BH_MAC_THETA", "BH_MAC_MLP", "BH_MAC_BUDGET", "BH_WALK_BODY", "BH_WALK_GROUP", "BH_WALK_DIRECT",
+    "use_torch_allocator", "BH_MAC_THETA", "BH_MAC_MLP", "BH_MAC_BUDGET", "BH_WALK_BODY", "BH_WALK_GROUP", "BH_WALK_DIRECT",
     "BH_GROUP_BODIES",
 ]
 
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
         "bh_sim_tree": ([vp, pp], i32),
         "bh_direct": ([vp, vp, vp, i32, i64, vp, i64, dbl, vp, vp], i32),
         "bh_standard_units": ([vp, vp, vp, vp, i32, i64, vp], i32),
+        "bh_ctx_set_allocator": ([vp, ALLOC_FN, FREE_FN, vp], i32),
         "bh_sim_timing": ([vp, i32], i32),
         "bh_sim_timing_get": ([vp, C.POINTER(dbl), C.POINTER(i64)], i32),
         "bh_mlp_set": ([vp, vp], i32),
@@ -227,6 +228,47 @@ def bh_ctx_set_stream(ctx, stream=None):
 
 def bh_ctx_destroy(ctx):
     _check(load().bh_ctx_destroy(ctx))
+    _ALLOCATORS.pop(ctx.value, None)
+
+
+# bh_alloc_fn / bh_free_fn
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p, C.c_void_p)
+_ALLOCATORS = {}  # ctx -> callbacks, kept alive while the context lives
+
+
+def bh_ctx_set_allocator(ctx, alloc=None, free=None):
+    """Route the context's device memory through alloc(bytes, device,
+    stream) -> int and free(ptr, bytes, device, stream) (Python callables;
+    None, None: hipMalloc)."""
+    if (alloc is None) != (free is None):
+        raise ValueError("give both allocator functions or neither")
+    if alloc is None:
+        _check(load().bh_ctx_set_allocator(ctx, ALLOC_FN(), FREE_FN(), None))
+        return
+
+    def _a(nbytes, dev, stream, user):
+        try:
+            return alloc(int(nbytes), int(dev), stream or 0) or None
+        except Exception:  # the library reports BH_E_NOMEM
+            return None
+
+    def _f(ptr, nbytes, dev, stream, user):
+        try:
+            free(int(ptr), int(nbytes), int(dev), stream or 0)
+        except Exception:
+            pass
+    cbs = (ALLOC_FN(_a), FREE_FN(_f))
+    _check(load().bh_ctx_set_allocator(ctx, cbs[0], cbs[1], None))
+    _ALLOCATORS.setdefault(ctx.value, []).append(cbs)
+
+
+def use_torch_allocator(ctx):
+    """Take the context's device memory from torch's caching allocator."""
+    import torch
+    bh_ctx_set_allocator(
+        ctx, lambda n, dev, stream: torch.cuda.caching_allocator_alloc(n, dev, stream),
+        lambda p, n, dev, stream: torch.cuda.caching_allocator_delete(p))
 
 
 def bh_sync(ctx):

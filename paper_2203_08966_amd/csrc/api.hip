@@ -18,29 +18,43 @@ int set_error(int code, const std::string &msg) {
     return code;
 }
 
+// The context of the calling entry point (set by use_device): its
+// allocator serves the buffers that grow during the call.
+static thread_local const bh_ctx *g_cur = nullptr;
+
+void free_buf(DevBuf &b) {
+    if (b.p) {
+        if (b.ffree) b.ffree(b.p, b.cap, b.fdev, b.fstream, b.fuser);
+        else hipFree(b.p);
+    }
+    b.p = nullptr;
+    b.cap = 0;
+    b.ffree = nullptr;
+}
+
 int grow(DevBuf &b, size_t bytes) {
     if (bytes == 0) bytes = 64;
     if (b.cap >= bytes) return BH_OK;
-    if (b.p) {
-        hipFree(b.p);
-        b.p = nullptr;
-        b.cap = 0;
-    }
+    free_buf(b);
     const size_t want = bytes + bytes / 8 + 256;
     void *p = nullptr;
-    if (hipMalloc(&p, want) != hipSuccess || !p) {
+    const bh_ctx *c = g_cur;
+    if (c && c->alloc) {
+        p = c->alloc(want, c->device, (void *)c->stream, c->alloc_user);
+        if (!p)
+            return set_error(BH_E_NOMEM, "caller's allocator refused " + std::to_string(want) +
+                                             " bytes");
+        b.ffree = c->free_fn;
+        b.fuser = c->alloc_user;
+        b.fdev = c->device;
+        b.fstream = (void *)c->stream;
+    } else if (hipMalloc(&p, want) != hipSuccess || !p) {
         hipGetLastError();
         return set_error(BH_E_NOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
     }
     b.p = p;
     b.cap = want;
     return BH_OK;
-}
-
-void free_buf(DevBuf &b) {
-    if (b.p) hipFree(b.p);
-    b.p = nullptr;
-    b.cap = 0;
 }
 
 int check_launch(const char *what) {
@@ -51,6 +65,7 @@ int check_launch(const char *what) {
 }
 
 static int use_device(bh_ctx *c) {
+    g_cur = c;
     if (hipSetDevice(c->device) != hipSuccess) {
         hipGetLastError();
         return set_error(BH_E_DEVICE, "hipSetDevice failed");
@@ -170,6 +185,16 @@ int bh_ctx_create(int device, void *stream, bh_ctx **out) {
 int bh_ctx_set_stream(bh_ctx *c, void *stream) {
     if (!c) return set_error(BH_E_INVALID, "null ctx");
     c->stream = (hipStream_t)stream;
+    return BH_OK;
+}
+
+int bh_ctx_set_allocator(bh_ctx *c, bh_alloc_fn alloc, bh_free_fn free_fn, void *user) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return set_error(BH_E_INVALID, "give both allocator functions or neither");
+    c->alloc = alloc;
+    c->free_fn = free_fn;
+    c->alloc_user = user;
     return BH_OK;
 }
 

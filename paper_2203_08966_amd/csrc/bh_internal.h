@@ -72,9 +72,15 @@ template <typename R> struct alignas(4 * sizeof(R)) Anchor {
 };
 
 // Grow-only device buffer.
+// Its memory comes from the caller's allocator when the owning context has
+// one (the free function and its arguments are kept with the buffer).
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    bh_free_fn ffree = nullptr;
+    void *fuser = nullptr;
+    int fdev = 0;
+    void *fstream = nullptr;
 };
 
 struct SimState;
@@ -97,6 +103,9 @@ struct bh_ctx {
     int mlp_loaded = 0;
     int mlp_step = 0;                // Adam steps taken
     int mlp_version = 0;             // bumped whenever the parameters change
+    bh_alloc_fn alloc = nullptr;     // caller's allocator (NULL: hipMalloc)
+    bh_free_fn free_fn = nullptr;
+    void *alloc_user = nullptr;
     bh::DevBuf scratch;              // direct-sum partials
     bh::DevBuf su_work;              // standard units: FP64 acc, phi, partials
     // phase timing of simulation steps

@@ -327,6 +327,8 @@ def main():
         "rms_rel_err": methods[chosen]["rms_rel_err"],
         "rms_rel_err_final_state": rms_final,
         "interactions_per_s": inter / (walk_step_ms * 1e-3),
+        # particle-cell terms weighted 2 (the paper's cost weights, Sec. 4.5)
+        "weighted_interactions_per_s": (s_pp + 2 * s_pc) / (walk_step_ms * 1e-3),
         "interactions_per_eval": {"pp": s_pp, "pc": s_pc},
         "walk_bodies_per_s": n / (walk_step_ms * 1e-3),
         "phases_ms": phases,

@@ -470,7 +470,8 @@ def cpu_baseline(bodies, cfg, theta, order, k):
         "value": n / t_eval, "unit": "bodies/s", "cores": oracle.num_threads(),
         "kind": "oracle",
         "sample": f"full FP64 tree build of all {n} bodies ({t1 - t0:.2f} s) + walk of "
-                  f"{len(sample)} sampled bodies ({t2 - t1:.2f} s), extrapolated to N",
+                  + (f"all {n} bodies ({t2 - t1:.2f} s)" if len(sample) == n else
+                     f"{len(sample)} sampled bodies ({t2 - t1:.2f} s), extrapolated to N"),
         "interactions_per_s": float((r.npp.sum() + r.npc.sum()) / (t2 - t1)),
     }
 

@@ -292,6 +292,8 @@ def main():
     r_f = ref_f.cpu().numpy()
     e_f = np.linalg.norm(a_f - r_f, axis=1) / np.linalg.norm(r_f, axis=1)
     rms_final = float(np.sqrt(np.mean(e_f * e_f)))
+    err_final = {"rms": rms_final, "median": float(np.median(e_f)),
+                 "p99": float(np.quantile(e_f, 0.99)), "max": float(e_f.max())}
     s_pp = methods[chosen]["interactions_per_eval"]["pp"]
     s_pc = methods[chosen]["interactions_per_eval"]["pc"]
     inter = s_pp + s_pc
@@ -326,6 +328,7 @@ def main():
         },
         "rms_rel_err": methods[chosen]["rms_rel_err"],
         "rms_rel_err_final_state": rms_final,
+        "rel_err_final_state": err_final,
         "interactions_per_s": inter / (walk_step_ms * 1e-3),
         # particle-cell terms weighted 2 (the paper's cost weights, Sec. 4.5)
         "weighted_interactions_per_s": (s_pp + 2 * s_pc) / (walk_step_ms * 1e-3),
@@ -466,6 +469,12 @@ def cpu_baseline(bodies, cfg, theta, order, k):
     t2 = time.perf_counter()
     t_eval = (t1 - t0) + (t2 - t1) * n / len(sample)
     log(f"cpu oracle: build {t1 - t0:.2f} s, walk of {len(sample)} bodies {t2 - t1:.2f} s")
+    # the oracle's FP64 direct sum over all N sources for a few targets
+    dt_targets = W.subsample(n, 256, 4343)
+    t3 = time.perf_counter()
+    oracle.direct(p64, m64, cfg["eps"], dt_targets)
+    t4 = time.perf_counter()
+    log(f"cpu oracle: direct sum for {len(dt_targets)} targets {t4 - t3:.2f} s")
     return {
         "value": n / t_eval, "unit": "bodies/s", "cores": oracle.num_threads(),
         "kind": "oracle",
@@ -473,6 +482,8 @@ def cpu_baseline(bodies, cfg, theta, order, k):
                   + (f"all {n} bodies ({t2 - t1:.2f} s)" if len(sample) == n else
                      f"{len(sample)} sampled bodies ({t2 - t1:.2f} s), extrapolated to N"),
         "interactions_per_s": float((r.npp.sum() + r.npc.sum()) / (t2 - t1)),
+        "direct_sum": {"targets": int(len(dt_targets)), "seconds": t4 - t3,
+                       "interactions_per_s": len(dt_targets) * (n - 1) / (t4 - t3)},
     }
 
 

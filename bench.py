@@ -99,6 +99,8 @@ def parse():
                     default=None, help="time only this method (default: the fastest at the "
                     "target error)")
     ap.add_argument("--target-err", type=float, default=1e-3)
+    ap.add_argument("--walk-cap", type=int, default=0,
+                    help="group walk work cap (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="bodies the CPU oracle walks (the tree is built in full)")
@@ -182,9 +184,9 @@ def main():
     def opts_of(method, p, counters=False, for_sim=False):
         kw = dict(order=order, n_pp=npp if counters else None, n_pc=npc if counters else None)
         if method == "group-theta":
-            kw.update(walk=B.BH_WALK_GROUP)
+            kw.update(walk=B.BH_WALK_GROUP, walk_cap=args.walk_cap)
         elif method in ("group-budget", "group-learned"):
-            kw.update(walk=B.BH_WALK_GROUP, mlp_precision=mlp_precision,
+            kw.update(walk=B.BH_WALK_GROUP, walk_cap=args.walk_cap, mlp_precision=mlp_precision,
                       mac=B.BH_MAC_BUDGET if method == "group-budget" else B.BH_MAC_MLP,
                       mlp_log10_tau=p, mlp_theta_max=BUDGET_THETA_MAX,
                       mlp_acc_norm=None if for_sim else anorm, mlp_acc_floor=ACC_FLOOR)

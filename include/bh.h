@@ -112,7 +112,8 @@ typedef struct {
     int walk_cap;             /* group walk: a group whose work (particle-cell
                                  terms + particle-particle bodies, per body)
                                  would exceed this is walked per body with the
-                                 same criterion; 0 = 4096.  A group (of one
+                                 same criterion; 0 = 6144 (4096 with
+                                 BH_MAC_BUDGET).  A group (of one
                                  run) that did is walked per body straight
                                  away in the next 15 walks of the same tree
                                  object with the same parameters and targets,

@@ -418,7 +418,10 @@ def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None, floor=0.0):
 
 
 # ------------------------------------------------------------------ group walk
-GROUP_WORK_CAP = 4096
+# default work caps of the group walk: opening angle (mode 0) and error
+# budget (mode 1), as the library's defaults for BH_MAC_THETA and
+# BH_MAC_BUDGET
+GROUP_WORK_CAP = {0: 6144, 1: 4096}
 
 
 def leaf_levels(b):
@@ -431,14 +434,17 @@ def leaf_levels(b):
 
 
 def walk_group(b, eps, group=64, mode=0, theta=0.5, theta_max=1.0, tau=1e-3, kc=None,
-               anorm=None, order=2, target_range=None, tol=1e-5, cap=GROUP_WORK_CAP,
+               anorm=None, order=2, target_range=None, tol=1e-5, cap=None,
                split=True, floor=0.0):
     """Walk with one acceptance decision per group of ``group`` consecutive
     sorted ranks in ``target_range`` (all bodies by default): mode 0 opening
     angle, mode 1 error budget (kc per cell, anorm per sorted rank).  With
     ``split`` a group straddling a jump of the space-filling curve is cut
     into runs walked as groups of their own.  Groups whose work exceeds
-    ``cap`` are walked per body.  Results are indexed by rank - t0."""
+    ``cap`` (default ``GROUP_WORK_CAP[mode]``) are walked per body.  Results
+    are indexed by rank - t0."""
+    if cap is None:
+        cap = GROUP_WORK_CAP[mode]
     lib = _mlib()
     t = b["tree"]
     M, com, Q = b["mom"]

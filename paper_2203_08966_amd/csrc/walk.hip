@@ -303,7 +303,12 @@ void dispatch2(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, 
 // with the same criterion instead.
 constexpr int kGroupStack = 640;       // LDS stack entries per wavefront
 constexpr int kStageW = 12;            // LDS words per staged accepted cell
-constexpr int kGroupWorkCap = 4096;    // default per-group work cap
+// Default per-group work caps: a fallback walks the group per body at a
+// quarter of the lanes, so the cap sits near three times a typical group's
+// work (about 1300 per body for the error budget, 1600-2200 for the learned
+// and opening-angle criteria at rms 1e-3).
+constexpr int kGroupWorkCap = 6144;        // opening angle, learned criterion
+constexpr int kGroupWorkCapBudget = 4096;  // error budget with k_C = 1
 
 struct GroupMac {
     const float *kc;     // error budget: k_C M l^3 per node
@@ -934,7 +939,10 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
         if (rc) return rc;
     }
     GroupMac gm{nullptr, nullptr, nullptr, 0.f, o.walk_stack > 0 ? o.walk_stack : kGroupStack,
-                o.walk_cap > 0 ? o.walk_cap : kGroupWorkCap, nullptr, nullptr};
+                o.walk_cap > 0                 ? o.walk_cap
+                : o.mac == BH_MAC_BUDGET       ? kGroupWorkCapBudget
+                                               : kGroupWorkCap,
+                nullptr, nullptr};
     // the parameters that decide which groups exceed the work cap (FNV-1a)
     uint64_t sig = 1469598103934665603ull;
     auto mixin = [&](const void *p, size_t len) {

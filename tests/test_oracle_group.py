@@ -127,7 +127,7 @@ def test_work_cap_falls_back_to_the_per_body_walk():
     np.testing.assert_allclose(gb.acc, wb.acc, rtol=1e-13, atol=0)
     big = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False, cap=1 << 62)
     dflt = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False)
-    capd = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False, cap=oracle.GROUP_WORK_CAP)
+    capd = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False, cap=oracle.GROUP_WORK_CAP[0])
     np.testing.assert_array_equal(dflt.npc, capd.npc)
     # the cap splits groups by their work: each group either keeps the group
     # walk or takes the per-body counts

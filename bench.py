@@ -69,8 +69,8 @@ FLOP_PC = {0: 20, 2: 60}
 METHODS = {
     "body-theta": [round(0.5 + 0.01 * k, 2) for k in range(31)],      # Sec. 3 walk
     "group-theta": [round(0.6 + 0.0125 * k, 4) for k in range(29)],   # one decision per wave
-    "group-budget": [round(-2.5 + 0.125 * k, 3) for k in range(13)],  # log10 tau
-    "group-learned": [round(-5.0 + 0.125 * k, 3) for k in range(29)],  # log10 tau
+    "group-budget": [round(-2.5 + 0.0625 * k, 4) for k in range(25)],  # log10 tau
+    "group-learned": [round(-5.0 + 0.0625 * k, 4) for k in range(57)],  # log10 tau
 }
 PARAM_NAME = {"body-theta": "theta", "group-theta": "theta", "group-budget": "log10_tau",
               "group-learned": "log10_tau"}

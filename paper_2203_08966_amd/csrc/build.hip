@@ -21,6 +21,7 @@
 //                          node's FP32/FP64 walk record is written as soon
 //                          as its moments are final
 #include <float.h>
+#include <limits.h>
 #include <math.h>
 #include <string.h>
 
@@ -745,16 +746,18 @@ __global__ __launch_bounds__(kThreads) void k_leaves(UpArgs ua, int32_t *__restr
                                                      const T *__restrict__ smass,
                                                      BodyRec<R> *__restrict__ bodies,
                                                      Anchor<R> *__restrict__ anchors) {
+    // a wavefront's 64 consecutive nodes in pre-order own one contiguous
+    // range of bodies: it is staged through LDS with coalesced loads (when it
+    // fits), and each leaf's lane then reads its bodies from there
+    constexpr int kStage = 2048 / (int)sizeof(T);  // bodies per wavefront
+    __shared__ T stg[kThreads / 64][4][kStage];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int m = ua.m;
     const int32_t *__restrict__ next = ua.next;
-    const int32_t *__restrict__ cx = ua.cx;
-    const int32_t *__restrict__ cy = ua.cy;
-    const int32_t *__restrict__ cz = ua.cz;
     const Cube *__restrict__ cube = ua.cube;
-    if (i >= m) return;
-    const int end = next[i];
-    {
+    const bool valid = i < m;
+    const int end = valid ? next[i] : 0;
+    if (valid) {
         int k[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
         int q = 0;
         for (int ch = i + 1; ch < end && q < 8;) {
@@ -767,12 +770,36 @@ __global__ __launch_bounds__(kThreads) void k_leaves(UpArgs ua, int32_t *__restr
         o[0] = make_int4(k[0], k[1], k[2], k[3]);
         o[1] = make_int4(k[4], k[5], k[6], k[7]);
     }
-    if (end != i + 1) return;
-    const NodeGeo gn = node_geo(ua, i);
+    const bool leaf = valid && end == i + 1;
+    NodeGeo gn{};
+    if (leaf) gn = node_geo(ua, i);
+    const int b = leaf ? gn.begin : 0, e = leaf ? gn.begin + gn.count : 0;
+    // the wavefront's body range
+    int lo = leaf ? b : INT_MAX, hi = leaf ? e : INT_MIN;
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o));
+        hi = max(hi, __shfl_xor(hi, o));
+    }
+    const int w = (int)threadIdx.x >> 6;
+    const bool staged = hi > lo && hi - lo <= kStage;
+    if (staged) {
+        for (int j = lo + (int)lane_id(); j < hi; j += 64) {
+            stg[w][0][j - lo] = spos[3 * (int64_t)j + 0];
+            stg[w][1][j - lo] = spos[3 * (int64_t)j + 1];
+            stg[w][2][j - lo] = spos[3 * (int64_t)j + 2];
+            stg[w][3][j - lo] = smass[j];
+        }
+    }
+    __syncthreads();
+    if (!leaf) return;
+    // body j's position component d and mass, from LDS or memory
+    auto P = [&](int j, int d) -> double {
+        return (double)(staged ? stg[w][d][j - lo] : spos[3 * (int64_t)j + d]);
+    };
+    auto Mj = [&](int j) -> T { return staged ? stg[w][3][j - lo] : smass[j]; };
     const double h = ldexp(cube->L, -(kLevels + 1));
     const double c0 = cube->lo[0] + gn.cx * h, c1 = cube->lo[1] + gn.cy * h,
                  c2 = cube->lo[2] + gn.cz * h;
-    const int b = gn.begin, e = b + gn.count;
     Anchor<R> an;
     an.x = (R)(gn.cx * h);  // exact
     an.y = (R)(gn.cy * h);
@@ -780,10 +807,11 @@ __global__ __launch_bounds__(kThreads) void k_leaves(UpArgs ua, int32_t *__restr
     an.leaf = i;
     double mt = 0, s0 = 0, s1 = 0, s2 = 0;
     for (int j = b; j < e; ++j) {
-        const double mj = (double)smass[j];
-        const double y0 = (double)spos[3 * (int64_t)j + 0] - c0;
-        const double y1 = (double)spos[3 * (int64_t)j + 1] - c1;
-        const double y2 = (double)spos[3 * (int64_t)j + 2] - c2;
+        const T mm = Mj(j);
+        const double mj = (double)mm;
+        const double y0 = P(j, 0) - c0;
+        const double y1 = P(j, 1) - c1;
+        const double y2 = P(j, 2) - c2;
         mt += mj;
         s0 += mj * y0;
         s1 += mj * y1;
@@ -792,7 +820,7 @@ __global__ __launch_bounds__(kThreads) void k_leaves(UpArgs ua, int32_t *__restr
         br.x = (R)y0;
         br.y = (R)y1;
         br.z = (R)y2;
-        br.m = (R)smass[j];
+        br.m = (R)mm;
         bodies[j] = br;
         anchors[j] = an;
     }
@@ -803,10 +831,10 @@ __global__ __launch_bounds__(kThreads) void k_leaves(UpArgs ua, int32_t *__restr
     r.c[2] = mt > 0 ? s2 / mt : 0.0;
     for (int a = 0; a < 6; ++a) r.t[a] = 0.0;
     for (int j = b; j < e; ++j) {
-        const double mj = (double)smass[j];
-        const double y0 = (double)spos[3 * (int64_t)j + 0] - c0 - r.c[0];
-        const double y1 = (double)spos[3 * (int64_t)j + 1] - c1 - r.c[1];
-        const double y2 = (double)spos[3 * (int64_t)j + 2] - c2 - r.c[2];
+        const double mj = (double)Mj(j);
+        const double y0 = P(j, 0) - c0 - r.c[0];
+        const double y1 = P(j, 1) - c1 - r.c[1];
+        const double y2 = P(j, 2) - c2 - r.c[2];
         r.t[0] += mj * y0 * y0;
         r.t[1] += mj * y0 * y1;
         r.t[2] += mj * y0 * y2;

@@ -135,3 +135,16 @@ def test_no_device_reports_device_error():
     h = C.c_void_p()
     assert B.load().bh_ctx_create(0, None, C.byref(h)) == B.BH_E_DEVICE
     assert "device" in B.bh_last_error().lower()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 exits with status 2 and a JSON
+    line that says so, before touching a device."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]

@@ -278,3 +278,32 @@ def test_group_walk_prediction_after_rebuild(ctx):
     assert np.mean(sg | sb) >= 0.99
     assert only_b.mean() > 0.005  # predicted groups walked per body
     assert sg.mean() > 0.5
+
+
+def test_default_work_cap_by_criterion(ctx):
+    """walk_cap = 0 means 6144 for the opening angle and 4096 for the error
+    budget (the criteria's measured best caps): the defaults reproduce those
+    caps bit for bit, and on the Plummer sphere of 2^20 bodies the other cap
+    changes some results (groups lie between the two)."""
+    b, cfg = W.config("c2")
+    P = torch.from_numpy(np.ascontiguousarray(b.pos)).cuda()
+    M = torch.from_numpy(np.ascontiguousarray(b.mass)).cuda()
+    eps = cfg["eps"]
+    t = B.bh_build(ctx, P, M, cfg["leaf"])
+    acc = torch.empty_like(P)
+    B.bh_forces(t, 0.5, eps, acc)
+    an = acc.norm(dim=1).contiguous()
+    say("default work caps: 2^20 bodies, opening angle and error budget")
+
+    def walk(cap, **kw):
+        out = torch.empty_like(P)
+        B.bh_forces(t, 0.7, eps, out, B.force_opts(walk=B.BH_WALK_GROUP, walk_cap=cap, **kw))
+        torch.cuda.synchronize()
+        return out.cpu()
+    budget = dict(mac=B.BH_MAC_BUDGET, mlp_log10_tau=-1.75, mlp_theta_max=1.5, mlp_acc_norm=an,
+                  mlp_acc_floor=0.5)
+    for kw, default, other in (({}, 6144, 4096), (budget, 4096, 6144)):
+        a0 = walk(0, **kw)
+        assert torch.equal(a0, walk(default, **kw))
+        assert not torch.equal(a0, walk(other, **kw))
+    B.bh_tree_free(t)

@@ -303,6 +303,9 @@ void dispatch2(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, 
 // with the same criterion instead.
 constexpr int kGroupStack = 640;       // LDS stack entries per wavefront
 constexpr int kStageW = 12;            // LDS words per staged accepted cell
+// bodies of particle-particle leaves staged per batch (4 words each, in the
+// same LDS as the accepted cells)
+constexpr int kPPStage = 64 * kStageW / 4;
 // Default per-group work caps: a fallback walks the group per body at a
 // quarter of the lanes, so the cap sits near three times a typical group's
 // work (about 1300 per body for the error budget, 1600-2200 for the learned
@@ -597,7 +600,73 @@ __device__ __forceinline__ auto group_walk(
                 __builtin_amdgcn_wave_barrier();
                 for (int q = 0; q < npc_round; ++q) staged_term(stage + kStageW * q);
                 work += npc_round;
-                uint64_t mm = m_pp;
+                // particle-particle leaves (and one-body cells) of the round.
+                // The bodies of those that hold none of the group's bodies are
+                // written to LDS in the group's frame, each leaf by its own
+                // lane, as many as fit, and summed in one loop with no per-leaf
+                // set-up; a leaf holding group bodies (the self term) or too
+                // large to fit alone takes leaf_terms.
+                int jb_l = 0, nb_l = 0;
+                bool self_l = false;
+                if (cls == kGPP) {
+                    jb_l = nd.begin;
+                    nb_l = max(0, min(nd.count, nbodies - jb_l));  // guard
+                    self_l = jb_l < g_end && jb_l + nb_l > base;
+                }
+                const uint64_t m_self = __ballot(cls == kGPP && self_l);
+                uint64_t pend = m_pp & ~m_self;
+                while (pend) {
+                    const bool mine = (pend >> lane) & 1;
+                    const int nb = mine ? nb_l : 0;
+                    int incl = nb;  // inclusive prefix sum over the lanes
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int v = __shfl_up(incl, o);
+                        if (lane >= o) incl += v;
+                    }
+                    const bool fits = mine && incl <= kPPStage;
+                    const uint64_t put = __ballot(fits);
+                    if (put == 0) {  // the first pending leaf alone does not fit
+                        const int bit = __builtin_ctzll(pend);
+                        pend &= pend - 1;
+                        leaf_terms(nodes[__builtin_amdgcn_readlane(c, bit)]);
+                        continue;
+                    }
+                    pend &= ~put;
+                    __builtin_amdgcn_wave_barrier();
+                    if (fits) {
+                        const R lx = nd.cx - gx, ly = nd.cy - gy, lz = nd.cz - gz;  // exact
+                        R *d = stage + 4 * (incl - nb);
+                        for (int q = 0; q < nb; ++q) {
+                            const BodyRec<R> sb = bodies[jb_l + q];
+                            d[4 * q + 0] = lx + sb.x;
+                            d[4 * q + 1] = ly + sb.y;
+                            d[4 * q + 2] = lz + sb.z;
+                            d[4 * q + 3] = sb.m;
+                        }
+                    }
+                    const int total =
+                        __builtin_amdgcn_readlane(incl, 63 - __builtin_clzll(put));
+                    __builtin_amdgcn_wave_barrier();
+                    work += total;
+                    if (CNT) cpp += (uint32_t)total;
+                    for (int q = 0; q < total; ++q) {  // same address on every lane
+                        const R *sb = stage + 4 * q;
+                        const R dx = sb[0] - px, dy = sb[1] - py, dz = sb[2] - pz;
+                        R r2 = dx * dx + eps2;
+                        r2 = dy * dy + r2;
+                        r2 = dz * dz + r2;
+                        const R inv = rsq(r2);
+                        const R minv = sb[3] * inv;
+                        const R mi3 = minv * (inv * inv);
+                        sx = mi3 * dx + sx;
+                        sy = mi3 * dy + sy;
+                        sz = mi3 * dz + sz;
+                        if (PHI) sp = sp - minv;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+                uint64_t mm = m_self;
                 while (mm) {
                     const int bit = __builtin_ctzll(mm);
                     mm &= mm - 1;

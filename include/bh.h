@@ -115,11 +115,16 @@ typedef struct {
                                  same criterion; 0 = 6144 (4096 with
                                  BH_MAC_BUDGET).  A group (of one
                                  run) that did is walked per body straight
-                                 away in the next 15 walks of the same tree
+                                 away in the next walks of the same tree
                                  object with the same parameters and targets,
-                                 also after the tree is rebuilt in place: a
-                                 simulation step may then walk such a group
-                                 per body although it would now fit. */
+                                 also after the tree is rebuilt in place: 15
+                                 walks, or, when a walk has more than 4 groups
+                                 per wavefront it launches, 1 walk after a
+                                 first excess, doubling with each repeated
+                                 excess up to 15 (a group walk that fits
+                                 starts it over).  A simulation step may then
+                                 walk such a group per body although it would
+                                 now fit. */
     double mlp_acc_floor;     /* BH_MAC_MLP / BH_MAC_BUDGET: |a_i| in the test
                                  is replaced by max(|a_i|, f <|a|>), f this
                                  value (>= 0) and <|a|> the mean of the n

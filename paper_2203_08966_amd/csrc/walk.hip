@@ -326,14 +326,26 @@ struct GroupMac {
     // group g per body; or null: groups in index order
     const uint32_t *items;
     // per group: further walks for which the group is predicted to exceed
-    // the work cap (written when a one-run group does), or null
+    // the work cap (written when a one-run group does), then (at ng + g)
+    // the length of its last prediction; or null
     uint8_t *gfb;
+    int predict_first;   // walks predicted after a first excess
 };
 
-// Walks for which a group that exceeded the work cap is walked per body
-// straight away (in parts of kPartLanes bodies, separate items) before the
-// group walk is tried again.
+// A group that exceeded the work cap is walked per body straight away (in
+// parts of kPartLanes bodies, separate items) in the next walks, then the
+// group walk is tried again.  An excess found during a walk is paid on the
+// wavefront that found it (the group walk up to the cap, then the per-body
+// walk), late in the launch; a wrong prediction costs the per-body walk of
+// a group that would fit.  With few groups per resident wavefront the late
+// excess is a tail on a short launch: the prediction then lasts
+// kPredictWalks walks.  With many, the tail is spread thin, and in a
+// simulation the groups over the cap may turn over within a step or two
+// (bodies near heavy ones): the prediction then lasts one walk after a first
+// excess and doubles with each excess that follows an expired one, up to
+// kPredictWalks.  A group walk that fits resets it.
 constexpr int kPredictWalks = 15;
+constexpr int kLongPredictGroupsPerWave = 4;
 constexpr int kPartLanes = 16;
 constexpr int kParts = 64 / kPartLanes;
 constexpr uint32_t kWholeGroup = 15;
@@ -805,7 +817,17 @@ __global__ __launch_bounds__(256) void k_gwalk(
         const bool fell = group_walk<R, ORDER2, PHI, CNT, SORTED_OUT, BUDGET>(
             nodes, m, bodies, anchors, kids, perm, nbodies, t0 + 64 * g, t1, theta2, eps2, acc,
             phi_out, npp_out, npc_out, gm, stk, stage, delta, level);
-        if (fell && gm.gfb && lane_id() == 0) gm.gfb[g] = (uint8_t)kPredictWalks;
+        if (gm.gfb && lane_id() == 0) {
+            uint8_t *last = gm.gfb + ng;  // length of the group's last prediction
+            if (fell) {
+                const int len =
+                    last[g] ? min(2 * (int)last[g], kPredictWalks) : gm.predict_first;
+                last[g] = (uint8_t)len;
+                gm.gfb[g] = (uint8_t)len;
+            } else if (last[g]) {
+                last[g] = 0;
+            }
+        }
     }
 }
 
@@ -929,13 +951,16 @@ void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, vo
     uint32_t *queue = (uint32_t *)t->wq.p;
     k_zero_queue<<<1, 512, 0, t->ctx->stream>>>(queue);
     GroupMac g2 = gm;
+    const int64_t waves = 8ll * per_xcd * 4;
+    g2.predict_first = ng <= kLongPredictGroupsPerWave * waves ? kPredictWalks : 1;
     // fallback predictions hold for walks of this tree object with the same
-    // parameters and targets
+    // parameters and targets (two bytes per group)
     uint8_t *gfb = nullptr;
-    if (grow(t->gfb, (size_t)ng) == BH_OK) {
+    if (grow(t->gfb, 2ull * ng) == BH_OK) {
         gfb = (uint8_t *)t->gfb.p;
         if (t->gfb_sig != sig || t->gfb_ng != ng) {
-            k_zero_bytes<<<std::min(div_up(ng, 256), 1024), 256, 0, t->ctx->stream>>>(gfb, ng);
+            k_zero_bytes<<<std::min(div_up(2 * ng, 256), 1024), 256, 0, t->ctx->stream>>>(
+                gfb, 2 * (int64_t)ng);
             t->gfb_sig = sig;
             t->gfb_ng = ng;
         }
@@ -1011,7 +1036,7 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
                 o.walk_cap > 0                 ? o.walk_cap
                 : o.mac == BH_MAC_BUDGET       ? kGroupWorkCapBudget
                                                : kGroupWorkCap,
-                nullptr, nullptr};
+                nullptr, nullptr, kPredictWalks};
     // the parameters that decide which groups exceed the work cap (FNV-1a)
     uint64_t sig = 1469598103934665603ull;
     auto mixin = [&](const void *p, size_t len) {

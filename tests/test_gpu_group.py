@@ -240,6 +240,38 @@ def test_group_walk_repeat_is_bitwise_identical(ctx):
             assert np.array_equal(a, b)
 
 
+def test_group_walk_repeat_short_predictions(ctx):
+    """With more than 4 groups per launched wavefront (2^22 bodies) a first
+    excess is predicted for one walk only, then the group walk is tried
+    again and the prediction doubles: walks 1-4 mix excesses found during
+    the walk with predicted per-body walks, and every result is unchanged
+    bit for bit.  A walk without a cap shows that groups did exceed it."""
+    pos, _, mass = case_bodies("plummer", 1 << 22, 23, np.float32)
+    n, cap = len(mass), 4096
+    P, M = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
+    say(f"repeat walks with short predictions: {n} bodies, cap {cap}")
+    t = B.bh_build(ctx, P, M, 16)
+
+    def walk(c):
+        acc = torch.empty_like(P)
+        npc = torch.zeros(n, dtype=torch.int32, device="cuda")
+        npp = torch.zeros(n, dtype=torch.int32, device="cuda")
+        B.bh_forces(t, 0.7, 0.005, acc, B.force_opts(walk=B.BH_WALK_GROUP, walk_cap=c,
+                                                      n_pp=npp, n_pc=npc))
+        torch.cuda.synchronize()
+        return acc.cpu().numpy(), npp.cpu().numpy(), npc.cpu().numpy()
+
+    outs = [walk(cap) for _ in range(4)]
+    free = walk(1 << 30)
+    B.bh_tree_free(t)
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+    fell = (outs[0][1] != free[1]) | (outs[0][2] != free[2])
+    say(f"  bodies in groups over the cap: {fell.mean():.4f}")
+    assert 0.0005 < fell.mean() < 0.5
+
+
 def test_group_walk_prediction_after_rebuild(ctx):
     """After the tree object is rebuilt from moved bodies, a group predicted
     (by the previous walk) to exceed the work cap is walked per body even if

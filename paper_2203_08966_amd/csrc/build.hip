@@ -929,18 +929,29 @@ __global__ __launch_bounds__(kThreads) void k_up_level(const int32_t *__restrict
     up_node<R>(a, list[t], ldexp(a.cube->L, -(kLevels + 1)));
 }
 
-// Levels top .. 0 (all small) in one workgroup, deepest first, with a
-// workgroup barrier between levels.  All waves of the workgroup share one
-// CU, so the barrier's workgroup-scope fence makes a level's results
-// visible to the next.
+// Levels with at most this many cells each go to one workgroup of as many
+// threads (k_up_top).
+constexpr int kTopCells = 1024;
+
+// Levels top .. 0 (all small) in one workgroup, deepest first, one cell per
+// thread, with a workgroup barrier between levels.  All waves of the
+// workgroup share one CU, so the barrier's workgroup-scope fence makes a
+// level's results visible to the next.  A cell's geometry and child table
+// do not depend on the level below, so the next level's are loaded before
+// the barrier: each level then waits on one round of loads (the children's
+// moments) instead of three.
 template <typename R>
-__global__ __launch_bounds__(1024) void k_up_top(const int32_t *__restrict__ list, LevelBase lb,
-                                                 LevelBase lc, int top, UpArgs a) {
+__global__ __launch_bounds__(kTopCells) void k_up_top(const int32_t *__restrict__ list,
+                                                      LevelBase lb, LevelBase lc, int top,
+                                                      UpArgs a) {
     const double h = ldexp(a.cube->L, -(kLevels + 1));
+    const int t = (int)threadIdx.x;
+    UpPre cur = up_pre(a, t < lc.base[top] ? list[lb.base[top] + t] : -1);
     for (int k = top; k >= 0; --k) {
-        for (int t = threadIdx.x; t < lc.base[k]; t += blockDim.x)
-            up_node<R>(a, list[lb.base[k] + t], h);
+        const UpPre nxt = up_pre(a, k > 0 && t < lc.base[k - 1] ? list[lb.base[k - 1] + t] : -1);
+        up_combine<R>(a, cur, h);
         __syncthreads();
+        cur = nxt;
     }
 }
 
@@ -1087,7 +1098,6 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
                                              (Anchor<T> *)t->anchors.p);
     // the top levels whose cells number at most kTopCells each go to one
     // workgroup; the deeper levels get a launch each, deepest first
-    constexpr int kTopCells = 1024;
     int top = -1;
     while (top + 1 <= t->depth - 1 && lcount[top + 1] <= kTopCells) ++top;
     for (int k = t->depth - 1; k > top; --k) {
@@ -1098,7 +1108,7 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     if (top >= 0) {
         LevelBase lc;  // cells per level
         for (int k = 0; k <= kLevels; ++k) lc.base[k] = lcount[k];
-        k_up_top<T><<<1, 1024, 0, st>>>(lvl_list, lb, lc, top, ua);
+        k_up_top<T><<<1, kTopCells, 0, st>>>(lvl_list, lb, lc, top, ua);
     }
     t->kids_tree_id = t->build_id;
     return check_launch("tree");

@@ -35,7 +35,7 @@ After the timed steps the direct method (every pair, FP32, no tree) is
 timed once on the same bodies as the O(N^2) reference point (up to
 N = 2^22).
 
-Prints ONE JSON line.  --gpus N with N > 1 is refused: this build targets
+Prints ONE JSON line.  --gpus N with N > 1 is refused: the library targets
 one GPU.
 
 --energy-table runs the paper's validation experiment instead (Sec. 5):
@@ -132,7 +132,7 @@ def copy_calibration(mib: int):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         log("bench.py: only --gpus 1 is supported (single-GPU build)")
         sys.exit(2)
@@ -373,7 +373,7 @@ def main():
 def direct_method(ctx, pos, vel, mass, leaf, eps, tg, ref, walk_step_ms):
     """One force evaluation of the direct method (every pair, the
     simulation's dtype, no tree) on the timed workload's initial bodies:
-    its kernel time, rate and error against the FP64 judge."""
+    its kernel time, rate and error against the FP64 reference sum."""
     import torch
     from paper_2203_08966_amd import binding as B
     n = int(mass.shape[0])

@@ -271,7 +271,7 @@ int bh_sim_timing_get(bh_ctx *ctx, double *ms, int64_t *steps);
 
 /* ---------------------------------------------------------------------
  * bh_direct -- FP64 direct summation (Sec. 2.1) for a subset of targets,
- * the judge of the tree's error.  pos/mass: device, dtype; targets: device
+ * the reference for the tree's error.  pos/mass: device, dtype; targets: device
  * int64[nt] caller indices; acc: device f64 nt x 3; phi: device f64 nt or
  * NULL.  Self pair skipped.
  * ------------------------------------------------------------------- */

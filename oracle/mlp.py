@@ -9,7 +9,7 @@ is the q-quantile of the label (Koenker and Bassett, 1978).  Parameters are a
 flat vector in the order W1 (32x10, row-major), b1 (32), W2 (32x32), b2 (32),
 w3 (32), b3 (1): 1441 values.
 
-Also the bf16 view used to judge the GPU's MFMA inference: weights of the two
+Also the bf16 view used to check the GPU's MFMA inference: weights of the two
 hidden layers and the layer inputs rounded to bf16 (round to nearest even),
 everything accumulated in FP64, the output layer in full precision.
 """

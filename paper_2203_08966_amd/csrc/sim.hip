@@ -3,8 +3,8 @@
 //  kick / drift   KDK leapfrog with a fixed step (Sec. 2.3)
 //  energy         E_kin = sum m v^2 / 2, E_pot = sum m phi / 2 (Sec. 2.4, each
 //                 pair once), FP64 accumulation in a fixed order
-//  direct         O(N * targets) direct sum (Sec. 2.1): in FP64 as the judge
-//                 of the tree walk's error, and in the simulation's own
+//  direct         O(N * targets) direct sum (Sec. 2.1): in FP64 as the reference
+//                 for the tree walk's error, and in the simulation's own
 //                 precision as the direct method of Sec. 3 (every pair, no
 //                 tree); sources staged through LDS
 //  standard units the scaling of Sec. 2.4 (total mass 1, centre-of-mass
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kThreads) void k_unpermute(int n, int comps,
 }
 
 // Direct sum: thread per target, grid.y splits the sources; each block
-// stages 256 sources at a time in LDS.  Arithmetic in R (FP64 for the judge,
+// stages 256 sources at a time in LDS.  Arithmetic in R (FP64 for the reference sum,
 // the simulation's dtype for the direct method); each tile's sums are added
 // into FP64 accumulators, and the partial results per split are summed
 // afterwards in split order.  targets == nullptr: target t is body t.

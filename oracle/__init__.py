@@ -65,7 +65,8 @@ def _load():
                                 C.c_double, _f64, _f64, _f64, C.c_void_p]
     lib.orc_walk.argtypes = [C.c_int64, _i32, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
                              C.c_double, C.c_double, C.c_double, C.c_int, C.c_int64, _i64,
-                             _f64, _f64, _i64, _i64, _i64, _i32]
+                             _f64, _f64, _i64, _i64, _i64, _i32, C.c_void_p, C.c_void_p,
+                             C.c_int]
     _lib = lib
     return lib
 
@@ -172,8 +173,10 @@ class WalkResult(tuple):
             raise AttributeError(name) from None
 
 
-def walk(tree, mom, spos, smass, L, theta, eps, order=2, targets=None):
-    """Per-body tree walk over sorted bodies; ``targets`` are sorted ranks."""
+def walk(tree, mom, spos, smass, L, theta, eps, order=2, targets=None, guard_lo=None):
+    """Per-body tree walk over sorted bodies; ``targets`` are sorted ranks.
+    ``guard_lo``: the root cube's corner, to open every cell whose cube holds
+    the body (the containment guard, a variant); None: the paper's test."""
     lib = _load()
     M, com, Q = mom
     p = _pos64(spos)
@@ -187,9 +190,13 @@ def walk(tree, mom, spos, smass, L, theta, eps, order=2, targets=None):
     npc = np.zeros(nt, dtype=np.int64)
     ncov = np.zeros(nt, dtype=np.int64)
     flag = np.zeros(nt, dtype=np.int32)
+    hk = np.ascontiguousarray(tree["hkey"], dtype=np.uint64)
+    lo = None if guard_lo is None else np.ascontiguousarray(guard_lo, dtype=np.float64)
     lib.orc_walk(M.shape[0], tree["level"], tree["begin"], tree["count"], tree["next"],
                  M, com.ravel(), Q.ravel(), p.ravel(), ms, float(L), float(theta), float(eps),
-                 int(order), nt, t, acc.ravel(), phi, npp, npc, ncov, flag)
+                 int(order), nt, t, acc.ravel(), phi, npp, npc, ncov, flag,
+                 hk.ctypes.data, None if lo is None else lo.ctypes.data,
+                 0 if lo is None else 1)
     return WalkResult(acc, phi, npp, npc, ncov, flag)
 
 

@@ -330,6 +330,12 @@ void orc_moments(int64_t m, const int32_t *level, const uint64_t *hkey, const in
  * acceptance test of this body was within a relative 1e-5 of its threshold
  * (|side^2 - theta^2 d^2| < 1e-5 side^2), where a reduced-precision evaluation
  * may legitimately decide the other way.
+ *
+ * With the containment guard (a variant, not in the paper) a cell whose
+ * closed cube holds the body is opened whatever its opening angle; the flag
+ * is also set when the body lies within a relative 1e-6 of a face.  Below
+ * theta = 1/sqrt(3) no cell holding the body can pass the test (d is at most
+ * the cube's diagonal), so the guard changes nothing there.
  * ---------------------------------------------------------------------- */
 typedef struct {
     const int32_t *level, *begin, *count, *next;
@@ -337,7 +343,15 @@ typedef struct {
     const double *spos, *smass;
     double L, theta2, e2;
     int order;
+    /* containment guard (opening angle only): hashed keys and the root
+     * cube's corner, or guard = 0 */
+    const uint64_t *hkey;
+    const double *lo;
+    int guard;
 } walk_ctx;
+
+static void cell_centre(uint64_t hkey, int k, const double *lo, double L, double c[3]);
+static int inside_cell(const double *r, const double *centre, double side);
 
 typedef struct {
     double a[3], phi;
@@ -415,7 +429,16 @@ static void cell_force(const walk_ctx *w, int64_t node, int64_t i, walk_acc *r)
         const double lhs = side * side, rhs = w->theta2 * d2;
         if (fabs(lhs - rhs) < 1e-5 * lhs)
             r->flag = 1;
-        if (lhs < rhs)
+        int in = 0;
+        if (w->guard) { /* a cell that holds the body is opened */
+            double centre[3];
+            cell_centre(w->hkey[c], w->level[c], w->lo, w->L, centre);
+            for (int a = 0; a < 3; ++a)
+                if (fabs(fabs(w->spos[3 * i + a] - centre[a]) - 0.5 * side) < 1e-6 * side)
+                    r->flag = 1;
+            in = inside_cell(&w->spos[3 * i], centre, side);
+        }
+        if (lhs < rhs && !in)
             pc(w, i, c, x, d2, r);
         else if (w->next[c] == c + 1)
             leaf_pp(w, i, c, r);
@@ -428,10 +451,11 @@ void orc_walk(int64_t m, const int32_t *level, const int32_t *begin, const int32
               const int32_t *next, const double *M, const double *com, const double *Q,
               const double *spos, const double *smass, double L, double theta, double eps,
               int order, int64_t nt, const int64_t *targets, double *acc, double *phi,
-              int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag)
+              int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag, const uint64_t *hkey,
+              const double *lo, int guard)
 {
     walk_ctx w = {level, begin, count, next, M, com, Q, spos, smass,
-                  L, theta * theta, eps * eps, order};
+                  L, theta * theta, eps * eps, order, hkey, lo, guard};
     (void)m;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nt; ++t) {

@@ -210,3 +210,44 @@ def test_root_leaf_and_tiny():
     np.testing.assert_allclose(r.acc, acc_d, rtol=1e-15)
     r1 = oracle.barnes_hut(pos[:1], mass[:1], 0.5, 0.1, 1)
     assert np.all(r1.acc == 0) and r1.npp[0] == 0
+
+
+def test_guard_changes_nothing_below_inverse_sqrt3():
+    """Below theta = 1/sqrt(3) no cell holding the body passes the opening
+    angle test (its distance to the cell's COM is at most the cube's
+    diagonal), so the containment guard leaves every result unchanged; at
+    theta 1.0 it opens cells and changes counts."""
+    from tests.conftest import case_bodies
+    pos, _, mass = case_bodies("clumpy", 3000, 7, np.float64)
+    ref = oracle.build_all(pos, mass, 8)
+    args = (ref["tree"], ref["mom"], ref["spos"], ref["smass"], ref["L"])
+    for theta in (0.3, 0.5, 0.57):
+        r0 = oracle.walk(*args, theta, 0.01)
+        r1 = oracle.walk(*args, theta, 0.01, guard_lo=ref["lo"])
+        assert np.array_equal(r0.acc, r1.acc) and np.array_equal(r0.phi, r1.phi)
+        assert np.array_equal(r0.npp, r1.npp) and np.array_equal(r0.npc, r1.npc)
+    r0 = oracle.walk(*args, 1.0, 0.01)
+    r1 = oracle.walk(*args, 1.0, 0.01, guard_lo=ref["lo"])
+    assert (r1.npc != r0.npc).any()
+
+
+def test_guard_opens_the_cell_holding_the_body():
+    """Three bodies, leaf size 1, root cube [0, 2)^3: a light body A at 0.05
+    (each coordinate) shares the octant [0, 1)^3 with a heavy body B at 0.95;
+    C at 1.9 is alone in its octant.  At theta 0.9 that octant (side 1, COM
+    about 1.56 from A) passes the opening angle test, so the paper's walk
+    takes A's field from a multipole that holds A itself.  The guard opens
+    it; what remains are two particle-particle terms, so A's acceleration is
+    the direct sum."""
+    pos = np.array([[0.05] * 3, [0.95] * 3, [1.9] * 3])
+    mass = np.array([1e-3, 1.0, 0.5])
+    ref = oracle.build_all(pos, mass, 1)
+    assert ref["L"] == 2.0 and np.array_equal(ref["lo"], np.zeros(3))
+    a_rank = int(np.where(ref["perm"] == 0)[0][0])
+    args = (ref["tree"], ref["mom"], ref["spos"], ref["smass"], ref["L"], 0.9, 0.0)
+    plain = oracle.walk(*args, targets=np.array([a_rank]))
+    guard = oracle.walk(*args, targets=np.array([a_rank]), guard_lo=ref["lo"])
+    direct, _ = oracle.direct(pos, mass, 0.0)
+    assert plain.npc[0] == 1 and guard.npc[0] == 0 and guard.npp[0] == 2
+    np.testing.assert_allclose(guard.acc[0], direct[0], rtol=1e-14, atol=0)
+    assert np.linalg.norm(plain.acc[0] - direct[0]) > 1e-3 * np.linalg.norm(direct[0])

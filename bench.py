@@ -6,10 +6,12 @@ rms relative force error of 1e-3 against FP64 direct summation.
 
 Workload (default): Plummer sphere, N = 2^20 equal masses (G = M = a = 1),
 eps 0.005, leaf 16, FP32 walk with FP64 cell moments, quadrupole order, KDK
-leapfrog dt 5e-4.  Before timing, three force-evaluation methods are
+leapfrog dt 5e-4.  Before timing, the force-evaluation methods are
 calibrated on the initial state against the FP64 direct sum over a seeded
 4096-body subsample:
   body-theta    the per-body walk of Sec. 3 (opening angle theta);
+  body-theta-guard  the same with a containment guard: a cell whose cube
+                holds the body is opened whatever its angle (a variant);
   group-theta   one opening-angle decision per wavefront of 64 bodies;
   group-budget  one error-budget decision per wavefront (k_C = 1 error
                 model, tau times the group's smallest |a|, each |a_i|
@@ -69,11 +71,14 @@ FLOP_PC = {0: 20, 2: 60}
 # grid each is swept over (from accurate to cheap)
 METHODS = {
     "body-theta": [round(0.5 + 0.01 * k, 2) for k in range(31)],      # Sec. 3 walk
+    # the same walk with a containment guard (a cell holding the body is opened)
+    "body-theta-guard": [round(0.5 + 0.01 * k, 2) for k in range(51)],
     "group-theta": [round(0.6 + 0.0125 * k, 4) for k in range(29)],   # one decision per wave
     "group-budget": [round(-2.5 + 0.0625 * k, 4) for k in range(25)],  # log10 tau
     "group-learned": [round(-5.0 + 0.0625 * k, 4) for k in range(57)],  # log10 tau
 }
-PARAM_NAME = {"body-theta": "theta", "group-theta": "theta", "group-budget": "log10_tau",
+PARAM_NAME = {"body-theta": "theta", "body-theta-guard": "theta", "group-theta": "theta",
+              "group-budget": "log10_tau",
               "group-learned": "log10_tau"}
 BUDGET_THETA_MAX = 1.5
 # |a_i| in the budget tests is max(|a_i|, ACC_FLOOR <|a|>)
@@ -97,7 +102,8 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="override N")
     ap.add_argument("--theta", type=float, default=None,
                     help="per-body walk: skip the sweep and use this theta")
-    ap.add_argument("--method", choices=["body-theta", "group-theta", "group-budget",
+    ap.add_argument("--method", choices=["body-theta", "body-theta-guard", "group-theta",
+                                         "group-budget",
                                          "group-learned"],
                     default=None, help="time only this method (default: the fastest at the "
                     "target error)")
@@ -186,7 +192,9 @@ def main():
 
     def opts_of(method, p, counters=False, for_sim=False):
         kw = dict(order=order, n_pp=npp if counters else None, n_pc=npc if counters else None)
-        if method == "group-theta":
+        if method == "body-theta-guard":
+            kw.update(mac=B.BH_MAC_THETA_GUARD)
+        elif method == "group-theta":
             kw.update(walk=B.BH_WALK_GROUP, walk_cap=args.walk_cap)
         elif method in ("group-budget", "group-learned"):
             kw.update(walk=B.BH_WALK_GROUP, walk_cap=args.walk_cap, mlp_precision=mlp_precision,
@@ -310,7 +318,7 @@ def main():
     achieved_tf = flops / (walk_kernel_ms * 1e-3) / 1e12
     log(f"step {ms_step:.3f} ms  phases {phases}  rms at the final state {rms_final:.3e}")
 
-    kernel = "k_walk" if chosen == "body-theta" else "k_gwalk"
+    kernel = "k_walk" if chosen.startswith("body-") else "k_gwalk"
     result = {
         "metric": METRIC,
         "value": value,

@@ -70,7 +70,11 @@ enum { BH_GROUP_BODIES = 64 };
 enum {
     BH_MAC_THETA = 0,  /* side/distance < theta (Sec. 3) */
     BH_MAC_MLP = 1,    /* learned: predicted error k_C (l/d)^3 M/d^2 < tau |a_i| */
-    BH_MAC_BUDGET = 2  /* the same error budget with k_C = 1 (no network) */
+    BH_MAC_BUDGET = 2, /* the same error budget with k_C = 1 (no network) */
+    BH_MAC_THETA_GUARD = 3 /* side/distance < theta and the body outside the
+                              cell's closed cube (a containment guard; not in
+                              the paper; BH_WALK_BODY only).  Below theta =
+                              1/sqrt(3) it equals BH_MAC_THETA. */
 };
 
 /* Arithmetic of the network's inference (MFMA operands; FP32 accumulate). */
@@ -85,7 +89,8 @@ typedef struct bh_tree bh_tree;
 /* Options of a force evaluation.  Fill with bh_force_opts_default first. */
 typedef struct {
     int order;        /* 0: monopole only; 2: monopole + quadrupole (default) */
-    int mac;          /* BH_MAC_THETA (default) or BH_MAC_MLP */
+    int mac;          /* BH_MAC_THETA (default), BH_MAC_MLP, BH_MAC_BUDGET or
+                         BH_MAC_THETA_GUARD */
     void *phi;        /* optional device out, N values in caller order: the
                          potential at each body from the same walk */
     uint32_t *n_pp;   /* optional device out, N: particle-particle count */

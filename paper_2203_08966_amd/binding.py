@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libbh.so")
 
 BH_OK, BH_E_INVALID, BH_E_NOMEM, BH_E_DEVICE, BH_E_STATE, BH_E_NONFINITE = 0, -1, -2, -3, -4, -5
 BH_F32, BH_F64 = 0, 1
-BH_MAC_THETA, BH_MAC_MLP, BH_MAC_BUDGET = 0, 1, 2
+BH_MAC_THETA, BH_MAC_MLP, BH_MAC_BUDGET, BH_MAC_THETA_GUARD = 0, 1, 2, 3
 BH_MLP_BF16, BH_MLP_FP16 = 0, 1
 BH_WALK_BODY, BH_WALK_GROUP, BH_WALK_DIRECT = 0, 1, 2
 BH_GROUP_BODIES = 64  # bodies per group of BH_WALK_GROUP
@@ -36,7 +36,7 @@ BH_MLP_PARAMS = 1441
 __all__ = EXPORTED + [
     "BHError", "ForceOpts", "TreeInfo", "force_opts", "load", "BH_OK", "BH_E_INVALID",
     "BH_E_NOMEM", "BH_E_DEVICE", "BH_E_STATE", "BH_E_NONFINITE", "BH_F32", "BH_F64",
-    "use_torch_allocator", "BH_MAC_THETA", "BH_MAC_MLP", "BH_MAC_BUDGET", "BH_WALK_BODY", "BH_WALK_GROUP", "BH_WALK_DIRECT",
+    "use_torch_allocator", "BH_MAC_THETA", "BH_MAC_MLP", "BH_MAC_BUDGET", "BH_MAC_THETA_GUARD", "BH_WALK_BODY", "BH_WALK_GROUP", "BH_WALK_DIRECT",
     "BH_GROUP_BODIES",
 ]
 

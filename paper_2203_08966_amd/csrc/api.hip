@@ -95,12 +95,17 @@ static size_t dsize(int d) { return d == BH_F32 ? 4 : 8; }
 
 static int check_opts(const bh_force_opts &o, int64_t n) {
     if (o.order != 0 && o.order != 2) return set_error(BH_E_INVALID, "opts.order must be 0 or 2");
-    if (o.mac != BH_MAC_THETA && o.mac != BH_MAC_MLP && o.mac != BH_MAC_BUDGET)
-        return set_error(BH_E_INVALID, "opts.mac must be BH_MAC_THETA, BH_MAC_MLP or BH_MAC_BUDGET");
+    if (o.mac != BH_MAC_THETA && o.mac != BH_MAC_MLP && o.mac != BH_MAC_BUDGET &&
+        o.mac != BH_MAC_THETA_GUARD)
+        return set_error(BH_E_INVALID, "opts.mac must be BH_MAC_THETA, BH_MAC_MLP, BH_MAC_BUDGET "
+                                       "or BH_MAC_THETA_GUARD");
+    if (o.mac == BH_MAC_THETA_GUARD && o.walk != BH_WALK_BODY)
+        return set_error(BH_E_INVALID, "BH_MAC_THETA_GUARD is a per-body walk criterion "
+                                       "(group walks open every cell that meets the group)");
     if (o.target_end > 0 &&
         (o.target_begin < 0 || o.target_begin > o.target_end || o.target_end > n))
         return set_error(BH_E_INVALID, "opts target range outside [0, n]");
-    if (o.mac != BH_MAC_THETA &&
+    if (o.mac != BH_MAC_THETA && o.mac != BH_MAC_THETA_GUARD &&
         !(o.mlp_theta_max > 0 && isfinite(o.mlp_theta_max) && isfinite(o.mlp_log10_tau) &&
           o.mlp_theta_est >= 0 && isfinite(o.mlp_theta_est) && o.mlp_acc_floor >= 0 &&
           isfinite(o.mlp_acc_floor) &&

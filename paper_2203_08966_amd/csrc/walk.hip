@@ -99,7 +99,8 @@ struct MlpMac {
 // successor records are loaded while a node is processed: this shortens the
 // dependent chain of a lone wavefront (the group walk's per-body fallback)
 // but costs the register file the occupancy that hides it in a full launch.
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool MLP, bool PF = false>
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool MLP, bool PF = false,
+          bool GUARD = false>
 __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__restrict__ nodes,
                                            int m, const BodyRec<R> *__restrict__ bodies,
                                            int nbodies, int i, bool live, R ox, R oy, R oz,
@@ -149,6 +150,13 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
                          kcv < tau_a * (d2 * d2 * sqrt(d2));
             } else {
                 accept = act && nd.l2 < theta2 * d2;
+                // containment guard: a cell holding the body is opened.  Below
+                // theta^2 = 1/3 no such cell passes the test (d is at most the
+                // cube's diagonal); the margin covers the rounding of d2.
+                if (GUARD && theta2 > (R)0.33) {
+                    const R q = (R)0.25 * nd.l2;  // (side / 2)^2, exact
+                    accept = accept && !(X * X <= q && Y * Y <= q && Z * Z <= q);
+                }
             }
             if (accept) {  // skipped as a whole when no lane accepts
                 const R inv = rsq(d2 + eps2);
@@ -198,7 +206,8 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
     }
 }
 
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool MLP>
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool MLP,
+          bool GUARD>
 __global__ __launch_bounds__(256) void k_walk(
     const typename NodeRecT<R>::type *__restrict__ nodes, int m,
     const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
@@ -235,8 +244,9 @@ __global__ __launch_bounds__(256) void k_walk(
     }
     R sx = 0, sy = 0, sz = 0, sp = 0;
     uint32_t cpp = 0, cpc = 0;
-    body_sweep<R, ORDER2, PHI, CNT, MLP>(nodes, m, bodies, nbodies, i, live, ox, oy, oz, ax, ay,
-                                         az, myleaf, theta2, eps2, mac, sx, sy, sz, sp, cpp, cpc);
+    body_sweep<R, ORDER2, PHI, CNT, MLP, false, GUARD>(nodes, m, bodies, nbodies, i, live, ox,
+                                                       oy, oz, ax, ay, az, myleaf, theta2, eps2,
+                                                       mac, sx, sy, sz, sp, cpp, cpc);
     if (live) {
         const int o = SORTED_OUT ? i : (int)perm[i];
         acc[3 * (int64_t)o + 0] = sx;
@@ -250,25 +260,25 @@ __global__ __launch_bounds__(256) void k_walk(
     }
 }
 
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED, bool MLP>
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED, bool MLP, bool GUARD>
 void launch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
             uint32_t *npp, uint32_t *npc, const MlpMac &mac) {
     const int nw = div_up(t1 - t0, 64);
     const int nblk = div_up(nw, 4);
     const int nblk_pad = div_up(nblk, 64) * 64;
     if (t->ctx->walk_ev) hipEventRecord(t->ctx->walk_ev[0], t->ctx->stream);
-    k_walk<R, ORDER2, PHI, CNT, SORTED, MLP><<<nblk_pad, 256, 0, t->ctx->stream>>>(
+    k_walk<R, ORDER2, PHI, CNT, SORTED, MLP, GUARD><<<nblk_pad, 256, 0, t->ctx->stream>>>(
         (const typename NodeRecT<R>::type *)t->recs.p, (int)t->m,
         (const BodyRec<R> *)t->bodies.p, (const Anchor<R> *)t->anchors.p, t->perm, (int)t->n, t0,
         t1, nblk_pad * 4, (R)(theta * theta), (R)(eps * eps), (R *)acc, (R *)phi, npp, npc, mac);
     if (t->ctx->walk_ev) hipEventRecord(t->ctx->walk_ev[1], t->ctx->stream);
 }
 
-template <typename R, bool ORDER2, bool MLP>
+template <typename R, bool ORDER2, bool MLP, bool GUARD = false>
 void dispatch2(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
                uint32_t *npp, uint32_t *npc, bool sorted, const MlpMac &mac) {
     const bool P = phi != nullptr, C = npp != nullptr;
-#define BH_W(p, c, s) launch<R, ORDER2, p, c, s, MLP>(t, t0, t1, theta, eps, acc, phi, npp, npc, mac)
+#define BH_W(p, c, s) launch<R, ORDER2, p, c, s, MLP, GUARD>(t, t0, t1, theta, eps, acc, phi, npp, npc, mac)
     if (sorted) {
         if (P) BH_W(true, false, true);
         else BH_W(false, false, true);
@@ -1104,6 +1114,14 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
         } else {
             if (o.order == 0) gdispatch<double, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
             else gdispatch<double, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
+        }
+    } else if (o.mac == BH_MAC_THETA_GUARD) {  // per-body walk only (checked by the caller)
+        if (t->dtype == BH_F32) {
+            if (o.order == 0) dispatch2<float, false, false, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+            else dispatch2<float, true, false, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+        } else {
+            if (o.order == 0) dispatch2<double, false, false, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+            else dispatch2<double, true, false, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
         }
     } else if (t->dtype == BH_F32) {
         if (o.order == 0) dispatch2<float, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);

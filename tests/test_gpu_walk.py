@@ -156,3 +156,71 @@ def test_direct_matches_oracle(ctx):
     torch.cuda.synchronize()
     np.testing.assert_allclose(acc.cpu().numpy(), acc_ref, rtol=1e-10, atol=1e-12 * np.abs(acc_ref).max())
     np.testing.assert_allclose(phi.cpu().numpy(), phi_ref, rtol=1e-12)
+
+
+def _run_guard(ctx, pos, mass, leaf, theta, eps, mac):
+    p, m = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
+    n = len(mass)
+    t = B.bh_build(ctx, p, m, leaf)
+    acc = torch.full((n, 3), float("nan"), dtype=p.dtype, device="cuda")
+    npp = torch.zeros(n, dtype=torch.int32, device="cuda")
+    npc = torch.zeros(n, dtype=torch.int32, device="cuda")
+    B.bh_forces(t, theta, eps, acc, B.force_opts(mac=mac, n_pp=npp, n_pc=npc))
+    torch.cuda.synchronize()
+    B.bh_tree_free(t)
+    return acc.cpu().numpy(), npp.cpu().numpy(), npc.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind,n,seed,leaf,dtype,theta,eps", [
+    ("plummer", 20000, 31, 16, np.float32, 0.9, 0.005),
+    ("clumpy", 20000, 32, 16, np.float32, 1.0, 1e-4),
+    ("plummer", 4096, 33, 8, np.float64, 0.9, 0.01),
+])
+def test_guarded_walk_matches_oracle(ctx, kind, n, seed, leaf, dtype, theta, eps):
+    """The opening angle with the containment guard (a cell whose cube holds
+    the body is opened) against the oracle's guarded walk, element by element;
+    the guard opens cells at these angles (counts differ from the plain
+    walk)."""
+    say(f"guarded walk parity: {kind} n={n} {dtype.__name__} theta={theta}")
+    pos, _, mass = case_bodies(kind, n, seed, dtype)
+    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), leaf)
+    r = oracle.walk(ref["tree"], ref["mom"], ref["spos"], ref["smass"], ref["L"], theta, eps,
+                    guard_lo=ref["lo"])
+    acc, npp, npc = _run_guard(ctx, pos, mass, leaf, theta, eps, B.BH_MAC_THETA_GUARD)
+    _, npp0, npc0 = _run_guard(ctx, pos, mass, leaf, theta, eps, B.BH_MAC_THETA)
+    p = ref["perm"]
+    acc, npp, npc = acc[p].astype(np.float64), npp[p], npc[p]
+    ok = r.flag == 0
+    say(f"  flagged {int((~ok).sum())}; bodies whose counts the guard changed "
+        f"{np.mean((npp != npp0[p]) | (npc != npc0[p])):.3f}")
+    assert (~ok).mean() <= 0.02
+    assert ((npp != npp0[p]) | (npc != npc0[p])).any()
+    np.testing.assert_array_equal(npp[ok], r.npp[ok])
+    np.testing.assert_array_equal(npc[ok], r.npc[ok])
+    e = rel_err(acc, r.acc)
+    rms_tol, max_tol = (TOL32_RMS, TOL32_MAX) if dtype == np.float32 else (TOL64_RMS, TOL64_MAX)
+    assert np.sqrt(np.mean(e[ok] ** 2)) <= rms_tol and e[ok].max() <= max_tol
+    if (~ok).any():
+        assert e[~ok].max() <= 1e-2
+
+
+def test_guard_below_inverse_sqrt3_equals_plain_walk(ctx):
+    """At theta 0.5 no cell holding the body can pass the test, so the
+    guarded walk's results equal the plain walk's bit for bit."""
+    pos, _, mass = case_bodies("clumpy", 20000, 34, np.float32)
+    a = _run_guard(ctx, pos, mass, 16, 0.5, 0.005, B.BH_MAC_THETA_GUARD)
+    b = _run_guard(ctx, pos, mass, 16, 0.5, 0.005, B.BH_MAC_THETA)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_guard_rejects_group_walk(ctx):
+    pos, _, mass = case_bodies("plummer", 1000, 35, np.float32)
+    p, m = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
+    t = B.bh_build(ctx, p, m, 16)
+    acc = torch.empty_like(p)
+    with pytest.raises(B.BHError) as e:
+        B.bh_forces(t, 0.9, 0.01, acc, B.force_opts(mac=B.BH_MAC_THETA_GUARD,
+                                                    walk=B.BH_WALK_GROUP))
+    assert e.value.code == B.BH_E_INVALID
+    B.bh_tree_free(t)

@@ -192,8 +192,9 @@ int bh_sync(bh_ctx *ctx);
  *
  * *tree: NULL to allocate a new tree, or an existing tree of this context
  * to rebuild into (its memory is reused and grown as needed).
- * Errors: BH_E_INVALID (null pointer, n < 1, n >= 2^31, leaf_size out of
- * range, bad dtype), BH_E_NONFINITE, BH_E_NOMEM, BH_E_DEVICE.  Waits for the
+ * Errors: BH_E_INVALID (null pointer, n < 1, n > 2^31 - 2^16, n +
+ * 21 floor(n / (B + 1)) >= 2^31 (the bound on the node count), leaf_size
+ * out of range, bad dtype), BH_E_NONFINITE, BH_E_NOMEM, BH_E_DEVICE.  Waits for the
  * device once (to size the node arrays).
  * ------------------------------------------------------------------- */
 int bh_build(bh_ctx *ctx, const void *pos, const void *mass, int dtype, int64_t n,
@@ -212,16 +213,20 @@ int bh_tree_free(bh_tree *tree);
  * dtype; the FP32 walk takes every position relative to a cell centre.
  *
  * acc: device out, n x 3 of the tree's dtype, caller order.
- * theta >= 0, eps >= 0, finite.  opts NULL = defaults.
- * Errors: BH_E_INVALID, BH_E_STATE (BH_MAC_MLP without loaded weights),
- * BH_E_DEVICE.
+ * theta >= 0, eps >= 0, finite.  opts NULL = defaults.  BH_MAC_MLP with no
+ * network loaded (bh_mlp_set) falls back to the opening angle at theta
+ * (BH_MAC_THETA, same walk kind); bh_tree_info_get reports which criterion
+ * ran.  Errors: BH_E_INVALID, BH_E_DEVICE.
  * ------------------------------------------------------------------- */
 int bh_forces(bh_tree *tree, double theta, double eps, void *acc, const bh_force_opts *opts);
 
-/* Tree shape: n bodies, m nodes, depth, root cube (lo, side), dtype, leaf size. */
+/* Tree shape: n bodies, m nodes, depth, root cube (lo, side), dtype, leaf
+ * size, and the criterion (BH_MAC_*) the tree's last walk used, -1 before
+ * the first: BH_MAC_THETA after a BH_MAC_MLP request with no network
+ * loaded (the fallback to the plain opening angle). */
 typedef struct {
     int64_t n, m;
-    int32_t depth, dtype, leaf_size, reserved;
+    int32_t depth, dtype, leaf_size, last_mac;
     double lo[3], side;
 } bh_tree_info;
 int bh_tree_info_get(const bh_tree *tree, bh_tree_info *info);

@@ -67,7 +67,7 @@ class MlpTrainCfg(C.Structure):
 class TreeInfo(C.Structure):
     _fields_ = [
         ("n", C.c_int64), ("m", C.c_int64), ("depth", C.c_int32), ("dtype", C.c_int32),
-        ("leaf_size", C.c_int32), ("reserved", C.c_int32), ("lo", C.c_double * 3),
+        ("leaf_size", C.c_int32), ("last_mac", C.c_int32), ("lo", C.c_double * 3),
         ("side", C.c_double),
     ]
 
@@ -300,7 +300,8 @@ def bh_tree_info_get(tree) -> dict:
     info = TreeInfo()
     _check(load().bh_tree_info_get(tree, C.byref(info)))
     return dict(n=info.n, m=info.m, depth=info.depth, dtype=info.dtype,
-                leaf_size=info.leaf_size, lo=np.array(info.lo[:]), side=info.side)
+                leaf_size=info.leaf_size, last_mac=info.last_mac, lo=np.array(info.lo[:]),
+                side=info.side)
 
 
 def bh_tree_export(tree) -> dict:
@@ -351,7 +352,7 @@ def bh_sim_tree(ctx) -> C.c_void_p:
     return h
 
 
-def bh_direct(ctx, pos, mass, targets, eps: float, acc, phi=None):
+def _direct_args(pos, mass, targets, acc, phi):
     import torch
     if targets.dtype != torch.int64:
         raise TypeError("targets must be int64")
@@ -361,9 +362,13 @@ def bh_direct(ctx, pos, mass, targets, eps: float, acc, phi=None):
         raise ValueError("acc must be (len(targets), 3) float64")
     if phi is not None and (tuple(phi.shape) != (nt,) or phi.dtype != torch.float64):
         raise ValueError("phi must be (len(targets),) float64")
-    _check(load().bh_direct(ctx, _dev(pos, "pos"), _dev(mass, "mass"), _dtype_code(pos),
-                            int(mass.shape[0]), _dev(targets, "targets"), int(targets.shape[0]),
-                            float(eps), _dev(acc, "acc"), _dev(phi, "phi")))
+    return (_dev(pos, "pos"), _dev(mass, "mass"), _dtype_code(pos), int(mass.shape[0]),
+            _dev(targets, "targets"), nt)
+
+
+def bh_direct(ctx, pos, mass, targets, eps: float, acc, phi=None):
+    _check(load().bh_direct(ctx, *_direct_args(pos, mass, targets, acc, phi), float(eps),
+                            _dev(acc, "acc"), _dev(phi, "phi")))
 
 
 def bh_standard_units(ctx, pos, vel, mass) -> tuple[float, float, float]:

@@ -131,6 +131,12 @@ static int check_build_args(const void *pos, const void *mass, int dtype, int64_
     if (bad_dtype(dtype)) return set_error(BH_E_INVALID, "dtype must be BH_F32 or BH_F64");
     if (n < 1 || n > (int64_t)0x7fff0000) return set_error(BH_E_INVALID, "n must be in [1, 2^31 - 2^16]");
     if (leaf < 1 || leaf > kMaxLeaf) return set_error(BH_E_INVALID, "leaf_size must be in [1, 256]");
+    // node indices are int32: the cells of one level partition the bodies
+    // and at most n / (B + 1) of them are split, so a tree holds at most
+    // n leaves plus kLevels * floor(n / (B + 1)) internal cells
+    if (n + (int64_t)kLevels * (n / (leaf + 1)) > (int64_t)0x7fffffff)
+        return set_error(BH_E_INVALID, "n too large for this leaf_size: the node count could "
+                                       "exceed 2^31 - 1 (need n + 21 floor(n / (B + 1)) < 2^31)");
     return BH_OK;
 }
 
@@ -293,8 +299,8 @@ int bh_forces(bh_tree *t, double theta, double eps, void *acc, const bh_force_op
         return set_error(BH_E_INVALID,
                          "BH_WALK_DIRECT is a simulation mode (bh_sim_init); bh_direct sums "
                          "for given targets");
-    if (o.mac == BH_MAC_MLP && !t->ctx->mlp_loaded)
-        return set_error(BH_E_STATE, "learned criterion requested but no weights are loaded");
+    // the learned criterion without a network: the plain opening angle at theta
+    if (o.mac == BH_MAC_MLP && !t->ctx->mlp_loaded) o.mac = BH_MAC_THETA;
     if (use_device(t->ctx)) return BH_E_DEVICE;
     return run_walk(t, theta, eps, acc, o.phi, o.n_pp, o.n_pc, o, false);
 }
@@ -308,6 +314,7 @@ int bh_tree_info_get(const bh_tree *t, bh_tree_info *info) {
     info->depth = (int32_t)t->depth;
     info->dtype = t->dtype;
     info->leaf_size = t->leaf;
+    info->last_mac = t->last_mac;
     for (int d = 0; d < 3; ++d) info->lo[d] = t->lo[d];
     info->side = t->L;
     return BH_OK;
@@ -419,8 +426,8 @@ int bh_sim_init(bh_ctx *c, const void *pos, const void *vel, const void *mass, i
     o.target_begin = o.target_end = 0;
     o.mlp_acc_norm = nullptr;  // the previous step's accelerations serve instead
     if ((rc = check_opts(o, n))) return rc;
-    if (o.mac == BH_MAC_MLP && o.walk != BH_WALK_DIRECT && !c->mlp_loaded)
-        return set_error(BH_E_STATE, "learned criterion requested but no weights are loaded");
+    // the learned criterion without a network: the plain opening angle at theta
+    if (o.mac == BH_MAC_MLP && !c->mlp_loaded) o.mac = BH_MAC_THETA;
     if (use_device(c)) return BH_E_DEVICE;
     if (!c->sim) c->sim = new SimState;
     if (!c->sim_tree) {

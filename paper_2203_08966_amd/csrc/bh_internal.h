@@ -121,6 +121,7 @@ struct bh_tree {
     int64_t n = 0, m = 0;
     int leaf = 1;
     int depth = 0;
+    int last_mac = -1;  // criterion the last walk of this tree used (-1: none yet)
     double lo[3] = {0, 0, 0}, L = 1.0;
     // body-indexed
     bh::DevBuf keys_a, keys_b, idx_a, idx_b;  // radix-sort ping-pong

@@ -1045,6 +1045,8 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     memcpy(&hc, hp + 40, sizeof(Cube));
     for (int d = 0; d < 3; ++d) t->lo[d] = hc.lo[d];
     t->L = hc.L;
+    if (hp[1] > 0x7fffffffu)  // cannot happen within the host's bound on n
+        return set_error(BH_E_DEVICE, "bh_build: internal error (node count above 2^31 - 1)");
     const int m = (int)hp[1];
     t->m = m;
     // cells per level -> level-list bases, depth

@@ -1030,6 +1030,7 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
         t1 = (int)o.target_end;
     }
     if (t1 <= t0) return BH_OK;
+    t->last_mac = o.mac;
     if ((npp != nullptr) != (npc != nullptr)) {  // the kernel writes both or neither
         int rc = grow(t->cnt_scratch, 4ull * t->n);
         if (rc) return rc;

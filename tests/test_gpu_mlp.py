@@ -393,3 +393,39 @@ def test_trained_network_beats_theta_at_equal_error(ctx):
     say(f"  interactions per body at rms <= 1e-3: theta {w_th:.0f}, learned {w_ln:.0f}")
     assert w_th is not None and w_ln is not None
     assert w_ln < 0.9 * w_th
+
+
+def test_no_network_falls_back_to_theta():
+    """The learned criterion with no network loaded is the plain opening
+    angle at theta (per body and per group, single walks and simulations),
+    and the tree reports which criterion ran."""
+    c = B.bh_ctx_create(0)  # a fresh context: no parameters set
+    try:
+        pos, vel, mass = case_bodies("plummer", 20000, 31, np.float32)
+        P, V, M = (torch.from_numpy(a).cuda() for a in (pos, vel, mass))
+        t = B.bh_build(c, P, M, 16)
+        assert B.bh_tree_info_get(t)["last_mac"] == -1
+        for walk, theta in ((B.BH_WALK_BODY, 0.6), (B.BH_WALK_GROUP, 0.7)):
+            say(f"fallback: walk {walk} theta {theta}")
+            a0, a1 = torch.empty_like(P), torch.empty_like(P)
+            B.bh_forces(t, theta, 0.01, a0, B.force_opts(walk=walk))
+            B.bh_forces(t, theta, 0.01, a1, B.force_opts(walk=walk, mac=B.BH_MAC_MLP,
+                                                         mlp_log10_tau=-3.0))
+            torch.cuda.synchronize()
+            assert B.bh_tree_info_get(t)["last_mac"] == B.BH_MAC_THETA
+            assert torch.equal(a0, a1)
+        B.bh_tree_free(t)
+        xs = []
+        for mac in (B.BH_MAC_THETA, B.BH_MAC_MLP):
+            B.bh_sim_init(c, P, V, M, 16, 0.6, 0.01, B.force_opts(mac=mac))
+            for _ in range(2):
+                B.bh_leapfrog_step(c, 1e-3)
+            x = torch.empty_like(P)
+            B.bh_sim_get(c, x)
+            torch.cuda.synchronize()
+            assert B.bh_tree_info_get(B.bh_sim_tree(c))["last_mac"] == B.BH_MAC_THETA
+            xs.append(x.cpu())
+        assert torch.equal(xs[0], xs[1])
+    finally:
+        torch.cuda.synchronize()
+        B.bh_ctx_destroy(c)

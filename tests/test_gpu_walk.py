@@ -204,12 +204,17 @@ def test_guarded_walk_matches_oracle(ctx, kind, n, seed, leaf, dtype, theta, eps
         assert e[~ok].max() <= 1e-2
 
 
-def test_guard_below_inverse_sqrt3_equals_plain_walk(ctx):
-    """At theta 0.5 no cell holding the body can pass the test, so the
-    guarded walk's results equal the plain walk's bit for bit."""
+@pytest.mark.parametrize("theta", [0.5, 0.576])
+def test_guard_below_inverse_sqrt3_equals_plain_walk(ctx, theta):
+    """Below theta = 1/sqrt(3) no cell holding the body can pass the test
+    (d is at most the cube's diagonal, so side^2 < theta^2 d^2 would need
+    theta^2 > 1/3), so the guarded walk's results equal the plain walk's bit
+    for bit.  At 0.5 the kernel skips the guard (theta^2 <= 0.33); at 0.576
+    (theta^2 = 0.3318, 0.5 % below 1/3) it evaluates it on every accepted
+    cell and must still change nothing."""
     pos, _, mass = case_bodies("clumpy", 20000, 34, np.float32)
-    a = _run_guard(ctx, pos, mass, 16, 0.5, 0.005, B.BH_MAC_THETA_GUARD)
-    b = _run_guard(ctx, pos, mass, 16, 0.5, 0.005, B.BH_MAC_THETA)
+    a = _run_guard(ctx, pos, mass, 16, theta, 0.005, B.BH_MAC_THETA_GUARD)
+    b = _run_guard(ctx, pos, mass, 16, theta, 0.005, B.BH_MAC_THETA)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
 

@@ -4,11 +4,12 @@
 Metric: bodies/s (and body-cell interactions/s) of the force evaluation at an
 rms relative force error of 1e-3 against FP64 direct summation.
 
-Workload (default): Plummer sphere, N = 2^20 equal masses (G = M = a = 1),
-eps 0.005, leaf 16, FP32 walk with FP64 cell moments, quadrupole order, KDK
-leapfrog dt 5e-4.  Before timing, the force-evaluation methods are
-calibrated on the initial state against the FP64 direct sum over a seeded
-4096-body subsample:
+Workload (default): Plummer sphere, N = 2^22 equal masses (G = M = a = 1,
+seed 4), eps 0.005, leaf 16, FP32 walk with FP64 cell moments, quadrupole
+order, KDK leapfrog dt 5e-4: the configuration the learned criterion is
+compared with the opening angle on.  Before timing, the force-evaluation
+methods are calibrated on the initial state against the FP64 direct sum
+over a seeded 4096-body subsample:
   body-theta    the per-body walk of Sec. 3 (opening angle theta);
   body-theta-guard  the same with a containment guard: a cell whose cube
                 holds the body is opened whatever its angle (a variant);
@@ -22,14 +23,18 @@ calibrated on the initial state against the FP64 direct sum over a seeded
 Each is swept over its parameter grid from accurate to cheap; the cheapest
 grid value with rms <= 1e-3 is kept, and the method with the fastest walk
 at that value is the one timed.  After the timed steps the rms error is
-measured again at the final state.
+measured again at the final state.  The per-body walk of Sec. 3 is also
+reported at theta = 0.4, 0.5 and 0.7 and at the theta where its rms error
+is 1e-3 (log-log interpolation of the sweep), each with its walk time.
 
 A timed step is one kick-drift-kick leapfrog step, the paper's loop body:
 kick + drift, tree rebuild (bbox, keys, radix sort, topology, FP64 upward
 pass, pack), the wavefront tree walk (accelerations), the second kick.
 value = N / (time per step): one force evaluation per step, tree build
-included; the per-phase HIP-event breakdown is taken over up to 20 further
-steps.  Inputs are resident on the GPU before timing starts.  The FP64
+included; the per-phase HIP-event breakdown and the interaction counts of
+the simulation's walks are taken over up to 20 further steps, and the
+roofline figure is their counted FLOPs over the walk kernel's event time in
+those same steps.  Inputs are resident on the GPU before timing starts.  The FP64
 energy diagnostic (its potential from one more walk) is taken before and
 after the timed steps, and its relative change reported.
 
@@ -85,6 +90,8 @@ BUDGET_THETA_MAX = 1.5
 ACC_FLOOR = 0.5
 # steps after the timed ones that record the per-phase HIP events
 PHASE_STEPS = 20
+# fixed opening angles the per-body walk is also reported at
+THETA_POINTS = (0.4, 0.5, 0.7)
 # the direct method (every pair) is timed once up to this N
 DIRECT_MAX_N = 1 << 22
 
@@ -98,7 +105,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c4")
     ap.add_argument("--n", type=int, default=None, help="override N")
     ap.add_argument("--theta", type=float, default=None,
                     help="per-body walk: skip the sweep and use this theta")
@@ -269,6 +276,36 @@ def main():
                          "interactions_per_eval": {"pp": s_pp, "pc": s_pc}, "sweep": sweep}
         log(f"{name}: param {best} rms {methods[name]['rms_rel_err']:.3e} "
             f"walk {methods[name]['walk_ms']:.3f} ms  pp/body {s_pp / n:.0f} pc/body {s_pc / n:.0f}")
+    # ---- the paper's per-body walk at fixed angles and at the target error
+    theta_points = {}
+    if "body-theta" in names:
+        for th in THETA_POINTS:
+            walk("body-theta", th, counters=True)
+            torch.cuda.synchronize()
+            t_pp = int(npp.to(torch.int64).sum().item())
+            t_pc = int(npc.to(torch.int64).sum().item())
+            wm = walk_ms("body-theta", th)
+            theta_points[str(th)] = {
+                "rms_rel_err": rms_at("body-theta", th), "walk_ms": wm,
+                "bodies_per_s": n / (wm * 1e-3),
+                "interactions_per_s": (t_pp + t_pc) / (wm * 1e-3),
+                "interactions_per_eval": {"pp": t_pp, "pc": t_pc}}
+            log(f"body-theta at {th}: rms {theta_points[str(th)]['rms_rel_err']:.3e} "
+                f"walk {wm:.3f} ms")
+        th_t = interp_theta(methods.get("body-theta", {}).get("sweep", []), args.target_err)
+        if th_t is not None:
+            walk("body-theta", th_t, counters=True)
+            torch.cuda.synchronize()
+            t_pp = int(npp.to(torch.int64).sum().item())
+            t_pc = int(npc.to(torch.int64).sum().item())
+            wm = walk_ms("body-theta", th_t)
+            theta_points["at_target"] = {
+                "theta": th_t, "rms_rel_err": rms_at("body-theta", th_t), "walk_ms": wm,
+                "bodies_per_s": n / (wm * 1e-3),
+                "interactions_per_s": (t_pp + t_pc) / (wm * 1e-3),
+                "interactions_per_eval": {"pp": t_pp, "pc": t_pc}}
+            log(f"body-theta interpolated to rms {args.target_err}: theta {th_t:.4f} "
+                f"walk {wm:.3f} ms")
     B.bh_tree_free(tree)
     chosen = min(methods, key=lambda k: methods[k]["walk_ms"])
     cp = methods[chosen]["param"]
@@ -292,6 +329,7 @@ def main():
     for _ in range(min(args.steps, PHASE_STEPS)):
         B.bh_leapfrog_step(ctx, dt)
     phase_ms, nsteps = B.bh_sim_timing_get(ctx)
+    sim_pp, sim_pc = B.bh_sim_counts_get(ctx)
     B.bh_sim_timing(ctx, False)
     ek, ep = B.bh_energy(ctx)
     ms_step = (t1 - t0) * 1e3 / args.steps
@@ -311,8 +349,10 @@ def main():
     rms_final = float(np.sqrt(np.mean(e_f * e_f)))
     err_final = {"rms": rms_final, "median": float(np.median(e_f)),
                  "p99": float(np.quantile(e_f, 0.99)), "max": float(e_f.max())}
-    s_pp = methods[chosen]["interactions_per_eval"]["pp"]
-    s_pc = methods[chosen]["interactions_per_eval"]["pc"]
+    # interactions per walk of the recorded simulation steps (the walks the
+    # walk kernel's event time is taken over)
+    s_pp = sim_pp / max(nsteps, 1)
+    s_pc = sim_pc / max(nsteps, 1)
     inter = s_pp + s_pc
     flops = FLOP_PP * s_pp + FLOP_PC[order] * s_pc
     achieved_tf = flops / (walk_kernel_ms * 1e-3) / 1e12
@@ -349,8 +389,10 @@ def main():
         "interactions_per_s": inter / (walk_step_ms * 1e-3),
         # particle-cell terms weighted 2 (the paper's cost weights, Sec. 4.5)
         "weighted_interactions_per_s": (s_pp + 2 * s_pc) / (walk_step_ms * 1e-3),
-        "interactions_per_eval": {"pp": s_pp, "pc": s_pc},
+        "interactions_per_eval": {"pp": s_pp, "pc": s_pc,
+                                  "source": f"mean over the {nsteps} recorded simulation steps"},
         "walk_bodies_per_s": n / (walk_step_ms * 1e-3),
+        "body_theta_points": theta_points,
         "phases_ms": phases,
         "phase_steps": int(nsteps),
         "energy_rel_change": abs((ek + ep) - (ek0 + ep0)) / abs(ek0 + ep0),
@@ -468,6 +510,37 @@ def traffic_for(kernel, workload):
     return k["hbm_bytes_per_launch"]
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def interp_theta(sweep, target):
+    """The theta at which the rms error reaches ``target``: log-log linear
+    interpolation between the two swept angles that bracket it (rms grows
+    with theta); None if no pair brackets it."""
+    pts = sorted((float(t), float(r)) for t, r in sweep if r > 0)
+    for (t0, r0), (t1, r1) in zip(pts, pts[1:]):
+        if r0 <= target <= r1 and r1 > r0:
+            f = (np.log(target) - np.log(r0)) / (np.log(r1) - np.log(r0))
+            return float(np.exp(np.log(t0) + f * (np.log(t1) - np.log(t0))))
+    return None
+
+
 def cpu_baseline(bodies, cfg, theta, order, k):
     """The FP64 C oracle on the host cores: full tree build over all N bodies
     plus the walk of a seeded sample of k bodies; bodies/s extrapolated as
@@ -495,7 +568,7 @@ def cpu_baseline(bodies, cfg, theta, order, k):
     log(f"cpu oracle: direct sum for {len(dt_targets)} targets {t4 - t3:.2f} s")
     return {
         "value": n / t_eval, "unit": "bodies/s", "cores": oracle.num_threads(),
-        "kind": "oracle",
+        "cpu_model": cpu_model(), "kind": "oracle",
         "sample": f"full FP64 tree build of all {n} bodies ({t1 - t0:.2f} s) + walk of "
                   + (f"all {n} bodies ({t2 - t1:.2f} s)" if len(sample) == n else
                      f"{len(sample)} sampled bodies ({t2 - t1:.2f} s), extrapolated to N"),

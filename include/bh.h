@@ -275,9 +275,15 @@ int bh_sim_tree(bh_ctx *ctx, bh_tree **tree);
  * returns, summed over the recorded steps, the milliseconds spent in
  * ms[0] kick + drift, ms[1] tree build, ms[2] walk (with its set-up
  * kernels), ms[3] final kick, ms[4] the walk kernel alone (ms holds 5
- * values), and the number of steps. */
+ * values), and the number of steps.  A recorded tree-walk step also counts
+ * its interactions (the walk kernel then writes per-body counts, 8 bytes a
+ * body more); bh_sim_counts_get waits for the stream and returns the sums
+ * of the particle-particle and particle-cell counts over the walks of the
+ * steps recorded since timing was last enabled (0 for the direct method or
+ * when nothing was recorded). */
 int bh_sim_timing(bh_ctx *ctx, int enable);
 int bh_sim_timing_get(bh_ctx *ctx, double *ms, int64_t *steps);
+int bh_sim_counts_get(bh_ctx *ctx, int64_t *n_pp, int64_t *n_pc);
 
 /* ---------------------------------------------------------------------
  * bh_direct -- FP64 direct summation (Sec. 2.1) for a subset of targets,

@@ -66,7 +66,7 @@ def _load():
     lib.orc_walk.argtypes = [C.c_int64, _i32, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
                              C.c_double, C.c_double, C.c_double, C.c_int, C.c_int64, _i64,
                              _f64, _f64, _i64, _i64, _i64, _i32, C.c_void_p, C.c_void_p,
-                             C.c_int]
+                             C.c_int, C.c_double]
     _lib = lib
     return lib
 
@@ -173,10 +173,13 @@ class WalkResult(tuple):
             raise AttributeError(name) from None
 
 
-def walk(tree, mom, spos, smass, L, theta, eps, order=2, targets=None, guard_lo=None):
+def walk(tree, mom, spos, smass, L, theta, eps, order=2, targets=None, guard_lo=None,
+         tol=1e-5):
     """Per-body tree walk over sorted bodies; ``targets`` are sorted ranks.
     ``guard_lo``: the root cube's corner, to open every cell whose cube holds
-    the body (the containment guard, a variant); None: the paper's test."""
+    the body (the containment guard, a variant); None: the paper's test.
+    ``tol``: a body is flagged when an opening-angle test it takes lies
+    within this relative margin of its threshold."""
     lib = _load()
     M, com, Q = mom
     p = _pos64(spos)
@@ -196,7 +199,7 @@ def walk(tree, mom, spos, smass, L, theta, eps, order=2, targets=None, guard_lo=
                  M, com.ravel(), Q.ravel(), p.ravel(), ms, float(L), float(theta), float(eps),
                  int(order), nt, t, acc.ravel(), phi, npp, npc, ncov, flag,
                  hk.ctypes.data, None if lo is None else lo.ctypes.data,
-                 0 if lo is None else 1)
+                 0 if lo is None else 1, float(tol))
     return WalkResult(acc, phi, npp, npc, ncov, flag)
 
 
@@ -307,9 +310,17 @@ def _mac_sigs(lib):
                                 C.c_int64, _i64, _f64, _f64, _i64, _i64, _i64, _i32]
     lib.orc_walk_group.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
                                    _f64, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
-                                   C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_int64,
-                                   C.c_int64, C.c_int64, C.c_int64, C.c_double, _u64, _i32,
-                                   C.c_int, _f64, _f64, _i64, _i64, _i64, _i32]
+                                   C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_double, _u64,
+                                   _i32, C.c_int, _f64, _f64, _i64, _i64, _i64, _i32]
+    lib.orc_gfeatures.argtypes = [_f64, _f64, _f64, C.c_double, _f64, C.c_double, _f64, C.c_int,
+                                  C.c_int, C.c_double, _f64]
+    lib.orc_gnet_bound.argtypes = [_f64, _f64, C.POINTER(C.c_double)]
+    lib.orc_gnet_bound.restype = C.c_double
+    lib.orc_group_samples.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64,
+                                      _f64, _f64, C.c_double, C.c_int64, C.c_int64, C.c_double,
+                                      C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_int64,
+                                      C.c_int64, _f64, _f64, _i32, _i64]
     return lib
 
 
@@ -425,33 +436,35 @@ def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None, floor=0.0):
 
 
 # ------------------------------------------------------------------ group walk
-# default work caps of the group walk: opening angle (mode 0) and error
-# budget (mode 1), as the library's defaults for BH_MAC_THETA and
-# BH_MAC_BUDGET
-GROUP_WORK_CAP = {0: 6144, 1: 4096}
-
-
 def leaf_levels(b):
-    """Level of the leaf holding each sorted rank."""
+    """Level of the leaf holding each sorted rank (cached in ``b``).  The
+    leaves, in pre-order, cover the sorted bodies left to right."""
+    if "_leaf_levels" in b:
+        return b["_leaf_levels"]
     t = b["tree"]
-    out = np.zeros(len(b["smass"]), dtype=np.int32)
-    for c in np.nonzero(t["next"] == np.arange(len(t["next"])) + 1)[0]:
-        out[t["begin"][c]:t["begin"][c] + t["count"][c]] = t["level"][c]
+    leaves = np.nonzero(t["next"] == np.arange(len(t["next"])) + 1)[0]
+    cnt = t["count"][leaves].astype(np.int64)
+    start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    assert np.array_equal(t["begin"][leaves], start) and cnt.sum() == len(b["smass"])
+    out = np.repeat(t["level"][leaves], cnt).astype(np.int32)
+    b["_leaf_levels"] = out
     return out
 
 
-def walk_group(b, eps, group=64, mode=0, theta=0.5, theta_max=1.0, tau=1e-3, kc=None,
-               anorm=None, order=2, target_range=None, tol=1e-5, cap=None,
-               split=True, floor=0.0):
+def walk_group(b, eps, *, cap, split, group=64, mode=0, theta=0.5, theta_max=1.0, tau=1e-3,
+               kc=None, anorm=None, params=None, order=2, target_range=None, tol=1e-5,
+               floor=0.0):
     """Walk with one acceptance decision per group of ``group`` consecutive
     sorted ranks in ``target_range`` (all bodies by default): mode 0 opening
-    angle, mode 1 error budget (kc per cell, anorm per sorted rank).  With
+    angle, mode 1 error budget (kc per cell, anorm per sorted rank), mode 2
+    the learned criterion (network ``params``, anorm per sorted rank; a run
+    over the cap takes the learned decision with each body as its own
+    group).  With
     ``split`` a group straddling a jump of the space-filling curve is cut
-    into runs walked as groups of their own.  Groups whose work exceeds
-    ``cap`` (default ``GROUP_WORK_CAP[mode]``) are walked per body.  Results
-    are indexed by rank - t0."""
-    if cap is None:
-        cap = GROUP_WORK_CAP[mode]
+    into runs walked as groups of their own.  A run whose work (particle-cell
+    terms plus particle-particle bodies) exceeds ``cap`` is walked per body.
+    Both are part of the walk's definition and have no default: every caller
+    states them.  Results are indexed by rank - t0."""
     lib = _mlib()
     t = b["tree"]
     M, com, Q = b["mom"]
@@ -468,14 +481,64 @@ def walk_group(b, eps, group=64, mode=0, theta=0.5, theta_max=1.0, tau=1e-3, kc=
     anv = None if anorm is None else np.ascontiguousarray(floored_norms(anorm, floor))
     if mode == 1 and (kcv is None or anv is None):
         raise ValueError("the error-budget mode needs kc and anorm")
+    pv = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+    if mode == 2 and (pv is None or anv is None):
+        raise ValueError("the learned mode needs params and anorm")
     if nt:
         lib.orc_walk_group(t["level"], t["hkey"], t["begin"], t["count"], t["next"], M,
                            com.ravel(), Q.ravel(), b["spos"].ravel(), b["smass"],
                            np.ascontiguousarray(b["lo"]), float(b["L"]), float(eps), int(order),
                            int(mode), float(theta), float(theta_max), float(tau),
                            None if kcv is None else kcv.ctypes.data,
-                           None if anv is None else anv.ctypes.data, int(group), t0, t1,
+                           None if anv is None else anv.ctypes.data,
+                           None if pv is None else pv.ctypes.data, int(group), t0, t1,
                            int(cap), float(tol), np.ascontiguousarray(b["keys"], dtype=np.uint64),
                            leaf_levels(b), 1 if split else 0, acc.ravel(), phi, npp, npc, ncov,
                            flag)
     return WalkResult(acc, phi, npp, npc, ncov, flag)
+
+
+# ------------------------------------------------------------------ learned group criterion
+def gfeatures(box_lo, box_hi, centre, side, com, M, Q, count, is_leaf, eps):
+    """The 10 features of a (group box, cell) pair."""
+    f = np.zeros(10)
+    _mlib().orc_gfeatures(np.ascontiguousarray(box_lo, dtype=np.float64),
+                          np.ascontiguousarray(box_hi, dtype=np.float64),
+                          np.ascontiguousarray(centre, dtype=np.float64), float(side),
+                          np.ascontiguousarray(com, dtype=np.float64), float(M),
+                          np.ascontiguousarray(Q, dtype=np.float64), int(count), int(is_leaf),
+                          float(eps), f)
+    return f
+
+
+def gnet_bound(params, f):
+    """(prediction, bound on the move of a reduced-precision evaluation)."""
+    d = C.c_double()
+    out = _mlib().orc_gnet_bound(np.ascontiguousarray(params, dtype=np.float64),
+                                 np.ascontiguousarray(f, dtype=np.float64), C.byref(d))
+    return float(out), d.value
+
+
+def group_samples(b, eps, theta_lo, theta_max, keep, seed, group=64, cap=4096,
+                  target_range=None):
+    """Training pairs of the learned criterion from a tree of build_all:
+    groups of ``group`` consecutive sorted ranks of ``target_range`` (all
+    bodies by default), per group up to ``cap`` kept candidates in
+    pre-order.  Returns (feat (ng, cap, 10), label (ng, cap), node (ng, cap),
+    count (ng,))."""
+    lib = _mlib()
+    t = b["tree"]
+    M, com, Q = b["mom"]
+    n = b["smass"].shape[0]
+    t0, t1 = (0, n) if target_range is None else (int(target_range[0]), int(target_range[1]))
+    ng = (t1 - t0 + group - 1) // group
+    feat = np.zeros((ng, cap, 10))
+    label = np.zeros((ng, cap))
+    node = np.full((ng, cap), -1, dtype=np.int32)
+    cnt = np.zeros(ng, dtype=np.int64)
+    lib.orc_group_samples(t["level"], t["hkey"], t["begin"], t["count"], t["next"], M,
+                          com.ravel(), Q.ravel(), b["spos"].ravel(), b["smass"],
+                          np.ascontiguousarray(b["lo"]), float(b["L"]), t0, t1, float(eps),
+                          float(theta_lo), float(theta_max), float(keep), int(seed), int(group),
+                          int(cap), feat.ravel(), label.ravel(), node.ravel(), cnt)
+    return feat, label, node, cnt

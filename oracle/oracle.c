@@ -348,10 +348,40 @@ typedef struct {
     const uint64_t *hkey;
     const double *lo;
     int guard;
+    /* relative margin of the opening-angle test inside which reduced
+     * precision may decide either way (flags the body); 0 means 1e-5 */
+    double tol;
 } walk_ctx;
 
 static void cell_centre(uint64_t hkey, int k, const double *lo, double L, double c[3]);
 static int inside_cell(const double *r, const double *centre, double side);
+
+/* Three-valued reading of one comparison "a < b" taken in reduced
+ * precision: +1 surely true, -1 surely false, 0 within a relative tol of
+ * the threshold (scale: the magnitude the margin is measured against). */
+static int cmp3(double a, double b, double tol, double scale)
+{
+    if (b - a > tol * scale)
+        return 1;
+    if (a - b > tol * scale)
+        return -1;
+    return 0;
+}
+
+/* A conjunction of three-valued terms: the decision may flip only if no
+ * term is surely false and at least one is uncertain. */
+static int and_uncertain(const int *t, int n)
+{
+    int unc = 0;
+    for (int k = 0; k < n; ++k) {
+        if (t[k] < 0)
+            return 0;
+        if (t[k] == 0)
+            unc = 1;
+    }
+    return unc;
+}
+
 
 typedef struct {
     double a[3], phi;
@@ -427,17 +457,21 @@ static void cell_force(const walk_ctx *w, int64_t node, int64_t i, walk_acc *r)
             x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
         const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
         const double lhs = side * side, rhs = w->theta2 * d2;
-        if (fabs(lhs - rhs) < 1e-5 * lhs)
-            r->flag = 1;
+        int terms[2] = {cmp3(lhs, rhs, w->tol > 0.0 ? w->tol : 1e-5, lhs), 1};
         int in = 0;
         if (w->guard) { /* a cell that holds the body is opened */
             double centre[3];
             cell_centre(w->hkey[c], w->level[c], w->lo, w->L, centre);
-            for (int a = 0; a < 3; ++a)
-                if (fabs(fabs(w->spos[3 * i + a] - centre[a]) - 0.5 * side) < 1e-6 * side)
-                    r->flag = 1;
+            terms[1] = -1;
+            for (int a = 0; a < 3; ++a) {
+                const int o3 = cmp3(0.5 * side, fabs(w->spos[3 * i + a] - centre[a]), 1e-6, side);
+                if (o3 > terms[1])
+                    terms[1] = o3;
+            }
             in = inside_cell(&w->spos[3 * i], centre, side);
         }
+        if (and_uncertain(terms, 2))
+            r->flag = 1;
         if (lhs < rhs && !in)
             pc(w, i, c, x, d2, r);
         else if (w->next[c] == c + 1)
@@ -452,10 +486,10 @@ void orc_walk(int64_t m, const int32_t *level, const int32_t *begin, const int32
               const double *spos, const double *smass, double L, double theta, double eps,
               int order, int64_t nt, const int64_t *targets, double *acc, double *phi,
               int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag, const uint64_t *hkey,
-              const double *lo, int guard)
+              const double *lo, int guard, double tol)
 {
     walk_ctx w = {level, begin, count, next, M, com, Q, spos, smass,
-                  L, theta * theta, eps * eps, order, hkey, lo, guard};
+                  L, theta * theta, eps * eps, order, hkey, lo, guard, tol};
     (void)m;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nt; ++t) {
@@ -784,13 +818,17 @@ static void cell_force_kc(mac_ctx *m, int64_t node, int64_t i, walk_acc *r)
         const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
         const double s2 = side * side;
         const double lhs = m->kc[c], rhs = m->tau * m->anorm * d2 * d2 * sqrt(d2);
-        if (fabs(s2 - m->tmax2 * d2) < 1e-5 * s2 || fabs(lhs - rhs) < 1e-5 * lhs)
-            r->flag = 1;
         double centre[3];
         cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
-        for (int a = 0; a < 3; ++a)
-            if (fabs(fabs(w->spos[3 * i + a] - centre[a]) - 0.5 * side) < 1e-6 * side)
-                r->flag = 1;
+        int out = -1; /* three-valued "the body lies outside the cube" */
+        for (int a = 0; a < 3; ++a) {
+            const int o3 = cmp3(0.5 * side, fabs(w->spos[3 * i + a] - centre[a]), 1e-6, side);
+            if (o3 > out)
+                out = o3;
+        }
+        const int terms[3] = {cmp3(s2, m->tmax2 * d2, 1e-5, s2), out, cmp3(lhs, rhs, 1e-5, lhs)};
+        if (and_uncertain(terms, 3))
+            r->flag = 1;
         const int in = inside_cell(&w->spos[3 * i], centre, side);
         if (s2 < m->tmax2 * d2 && !in && lhs < rhs)
             pc(w, i, c, x, d2, r);
@@ -890,7 +928,12 @@ typedef struct {
     walk_acc *r; /* one per body of the group */
     int flag;
     int64_t work;
+    /* mode 2 (learned): network parameters, softening, log10(tau amin) */
+    const double *params;
+    double eps, lt;
 } group_ctx;
+
+static int learned_term(const group_ctx *g, int64_t c, double side, double dg2, int *accept);
 
 static void group_cell(group_ctx *g, int64_t node)
 {
@@ -905,14 +948,15 @@ static void group_cell(group_ctx *g, int64_t node)
         }
         const double side = ldexp(w->L, -w->level[c]);
         double centre[3], dg2 = 0.0;
-        int overlap = 1;
+        int overlap = 1, sep = -1; /* sep: three-valued "cube misses the box" */
         cell_centre(g->hkey[c], w->level[c], g->lo, w->L, centre);
         for (int a = 0; a < 3; ++a) {
             const double gap = fabs(centre[a] - g->bc[a]) - (0.5 * side + g->bh[a]);
             if (gap > 0.0)
                 overlap = 0;
-            if (fabs(gap) < g->tol * side)
-                g->flag = 1;
+            const int s3 = cmp3(0.0, gap, g->tol, side);
+            if (s3 > sep)
+                sep = s3;
             const double t = fabs(w->com[3 * c + a] - g->bc[a]) - g->bh[a];
             if (t > 0.0)
                 dg2 += t * t;
@@ -920,14 +964,18 @@ static void group_cell(group_ctx *g, int64_t node)
         const double s2 = side * side;
         const double lim2 = (g->mode == 0 ? g->th2 : g->tmax2) * dg2;
         int accept = !overlap && s2 < lim2;
-        if (!overlap && fabs(s2 - lim2) < g->tol * s2)
-            g->flag = 1;
+        int terms[3] = {sep, cmp3(s2, lim2, g->tol, s2), 1};
         if (g->mode == 1) {
             const double rhs = g->tau * g->amin * dg2 * dg2 * sqrt(dg2);
-            if (!overlap && fabs(g->kc[c] - rhs) < g->tol * g->kc[c])
-                g->flag = 1;
+            terms[2] = cmp3(g->kc[c], rhs, g->tol, g->kc[c]);
             accept = accept && g->kc[c] < rhs;
+        } else if (g->mode == 2 && sep >= 0 && terms[1] >= 0) {
+            int acc_l = 0;
+            terms[2] = learned_term(g, c, side, dg2, &acc_l);
+            accept = accept && acc_l;
         }
+        if (and_uncertain(terms, 3))
+            g->flag = 1;
         if (accept) {
             for (int64_t i = g->g0; i < g->g1; ++i) {
                 double x[3];
@@ -952,9 +1000,12 @@ static void walk_one_group(const int32_t *level, const uint64_t *hkey, const int
                            const double *com, const double *Q, const double *spos,
                            const double *smass, const double *lo, double L, double eps,
                            int order, int mode, double theta, double theta_max, double tau,
-                           const double *kc, const double *anorm, int64_t r0, int64_t r1,
-                           int64_t t0, int64_t cap, double tol, double *acc, double *phi,
-                           int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag);
+                           const double *kc, const double *anorm, const double *params,
+                           int64_t r0, int64_t r1, int64_t t0, int64_t cap, double tol,
+                           double *acc, double *phi, int64_t *npp, int64_t *npc, int64_t *ncov,
+                           int32_t *flag);
+
+static void group_run(group_ctx *g, int64_t r0, int64_t r1, const double *anorm, walk_acc *r);
 
 /* common octal digits of two keys (21 if equal) */
 static int key_lcp(uint64_t a, uint64_t b)
@@ -973,7 +1024,8 @@ void orc_walk_group(const int32_t *level, const uint64_t *hkey, const int32_t *b
                     const double *com, const double *Q, const double *spos, const double *smass,
                     const double *lo, double L, double eps, int order, int mode, double theta,
                     double theta_max, double tau, const double *kc, const double *anorm,
-                    int64_t G, int64_t t0, int64_t t1, int64_t cap, double tol,
+                    const double *params, int64_t G, int64_t t0, int64_t t1, int64_t cap,
+                    double tol,
                     const uint64_t *skeys, const int32_t *leaf_level, int split, double *acc,
                     double *phi, int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag)
 {
@@ -1002,8 +1054,8 @@ void orc_walk_group(const int32_t *level, const uint64_t *hkey, const int32_t *b
                 b = cut;
             }
             walk_one_group(level, hkey, begin, count, next, M, com, Q, spos, smass, lo, L, eps,
-                           order, mode, theta, theta_max, tau, kc, anorm, a, b, t0, cap, tol,
-                           acc, phi, npp, npc, ncov, flag);
+                           order, mode, theta, theta_max, tau, kc, anorm, params, a, b, t0, cap,
+                           tol, acc, phi, npp, npc, ncov, flag);
             a = b;
         }
     }
@@ -1015,9 +1067,10 @@ static void walk_one_group(const int32_t *level, const uint64_t *hkey, const int
                            const double *com, const double *Q, const double *spos,
                            const double *smass, const double *lo, double L, double eps,
                            int order, int mode, double theta, double theta_max, double tau,
-                           const double *kc, const double *anorm, int64_t r0, int64_t r1,
-                           int64_t t0, int64_t cap, double tol, double *acc, double *phi,
-                           int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag)
+                           const double *kc, const double *anorm, const double *params,
+                           int64_t r0, int64_t r1, int64_t t0, int64_t cap, double tol,
+                           double *acc, double *phi, int64_t *npp, int64_t *npc, int64_t *ncov,
+                           int32_t *flag)
 {
     {
         group_ctx g;
@@ -1032,38 +1085,28 @@ static void walk_one_group(const int32_t *level, const uint64_t *hkey, const int
         g.tmax2 = theta_max * theta_max;
         g.tau = tau;
         g.tol = tol;
-        g.g0 = r0;
-        g.g1 = r1;
-        double bl[3] = {INFINITY, INFINITY, INFINITY}, bu[3] = {-INFINITY, -INFINITY, -INFINITY};
-        g.amin = INFINITY;
-        for (int64_t i = g.g0; i < g.g1; ++i) {
-            for (int a = 0; a < 3; ++a) {
-                bl[a] = fmin(bl[a], spos[3 * i + a]);
-                bu[a] = fmax(bu[a], spos[3 * i + a]);
-            }
-            if (anorm)
-                g.amin = fmin(g.amin, anorm[i]);
-        }
-        for (int a = 0; a < 3; ++a) {
-            g.bc[a] = 0.5 * (bl[a] + bu[a]);
-            g.bh[a] = 0.5 * (bu[a] - bl[a]);
-        }
-        g.r = calloc((size_t)(g.g1 - g.g0), sizeof(walk_acc));
-        if (next[0] == 1) {
-            for (int64_t i = g.g0; i < g.g1; ++i)
-                leaf_pp(&g.w, i, 0, &g.r[i - g.g0]);
-            g.work = count[0];
-        } else {
-            group_cell(&g, 0);
-        }
-        if (g.work > cap) { /* too spread out for one decision: per body */
-            memset(g.r, 0, (size_t)(g.g1 - g.g0) * sizeof(walk_acc));
-            g.flag = 0;
-            for (int64_t i = g.g0; i < g.g1; ++i) {
-                walk_acc *r = &g.r[i - g.g0];
+        g.params = params;
+        g.eps = eps;
+        g.r = calloc((size_t)(r1 - r0), sizeof(walk_acc));
+        group_run(&g, r0, r1, anorm, g.r);
+        /* with no uncertain group decision the work is exact, and so is the
+         * choice to walk per body: then each body's flag is its own */
+        const int gflag = g.flag;
+        const int per_body = g.work > cap;
+        if (per_body) { /* too spread out for one decision: per body */
+            memset(g.r, 0, (size_t)(r1 - r0) * sizeof(walk_acc));
+            for (int64_t i = r0; i < r1; ++i) {
+                walk_acc *r = &g.r[i - r0];
+                if (mode == 2) { /* the learned decision with the body as the group */
+                    group_ctx g1 = g;
+                    group_run(&g1, i, i + 1, anorm, r);
+                    r->flag = g1.flag;
+                    continue;
+                }
                 if (mode == 0) {
                     walk_ctx w1 = g.w;
                     w1.theta2 = theta * theta;
+                    w1.tol = tol;
                     if (next[0] == 1)
                         leaf_pp(&w1, i, 0, r);
                     else
@@ -1083,8 +1126,6 @@ static void walk_one_group(const int32_t *level, const uint64_t *hkey, const int
                     else
                         cell_force_kc(&mc, 0, i, r);
                 }
-                if (r->flag)
-                    g.flag = 1;
             }
         }
         for (int64_t i = g.g0; i < g.g1; ++i) {
@@ -1096,8 +1137,329 @@ static void walk_one_group(const int32_t *level, const uint64_t *hkey, const int
             if (npp) npp[o] = r->npp;
             if (npc) npc[o] = r->npc;
             if (ncov) ncov[o] = r->ncov;
-            if (flag) flag[o] = g.flag;
+            if (flag) flag[o] = gflag || (per_body && r->flag);
         }
         free(g.r);
+    }
+}
+
+/* Walks the bodies of sorted rank [r0, r1) as one group: box, smallest
+ * norm, decisions; accumulators r[0 .. r1 - r0), work and flag in g. */
+static void group_run(group_ctx *g, int64_t r0, int64_t r1, const double *anorm, walk_acc *r)
+{
+    const walk_ctx *w = &g->w;
+    g->g0 = r0;
+    g->g1 = r1;
+    g->r = r;
+    g->work = 0;
+    g->flag = 0;
+    double bl[3] = {INFINITY, INFINITY, INFINITY}, bu[3] = {-INFINITY, -INFINITY, -INFINITY};
+    g->amin = INFINITY;
+    for (int64_t i = r0; i < r1; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            bl[a] = fmin(bl[a], w->spos[3 * i + a]);
+            bu[a] = fmax(bu[a], w->spos[3 * i + a]);
+        }
+        if (anorm)
+            g->amin = fmin(g->amin, anorm[i]);
+    }
+    for (int a = 0; a < 3; ++a) {
+        g->bc[a] = 0.5 * (bl[a] + bu[a]);
+        g->bh[a] = 0.5 * (bu[a] - bl[a]);
+    }
+    g->lt = anorm ? log10(g->tau * g->amin) : 0.0;
+    if (w->next[0] == 1) {
+        for (int64_t i = r0; i < r1; ++i)
+            leaf_pp(w, i, 0, &r[i - r0]);
+        g->work = w->count[0];
+    } else {
+        group_cell(g, 0);
+    }
+}
+
+/* ========================================================================
+ * Learned acceptance criterion, one decision per (group, cell).
+ *
+ * A network predicts the error a cell's particle-cell term (order 2) makes
+ * on a group of bodies: the largest |a_pc,i - a_exact,i| over the group,
+ * relative to the cell's monopole field M / d_g^2 at the group's box, as
+ * log10.  The cell is accepted for the group iff its cube misses the box,
+ * l^2 < theta_max^2 d_g^2, and
+ *     pred + log10(M) - 2 log10(d_g) < log10(tau a_min),
+ * i.e. iff the predicted error is below tau times the group's smallest
+ * |a_i|.  A group of one body is the per-body criterion.
+ *
+ * Features of (box, cell), all scale-free (l side, d_g distance from the
+ * COM to the box, d_c to the box centre, h the box's half-diagonal,
+ * n the unit vector from the box centre to the COM, g = COM - cell centre,
+ * Q the traceless quadrupole, n_C the body count):
+ *   f0 log2(l/d_g) in [-8, 8]       f1 min(log2(d_c/d_g), 8)
+ *   f2 h / (h + d_g)                f3 n.Q.n / (M l^2)
+ *   f4 |Q|_F / (M l^2)              f5 g.n / l
+ *   f6 |g| / l                      f7 log2(n_C) / 21
+ *   f8 min(eps / d_g, 1)            f9 1 for a leaf, else 0
+ * ====================================================================== */
+
+void orc_gfeatures(const double *bl, const double *bu, const double *centre, double side,
+                   const double *com, double M, const double *Q, int count, int is_leaf,
+                   double eps, double *f)
+{
+    double u[3], g[3], dc2 = 0.0, dg2 = 0.0, h2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double bc = 0.5 * (bl[a] + bu[a]), bh = 0.5 * (bu[a] - bl[a]);
+        u[a] = com[a] - bc;
+        dc2 += u[a] * u[a];
+        const double t = fabs(u[a]) - bh;
+        if (t > 0.0)
+            dg2 += t * t;
+        h2 += bh * bh;
+        g[a] = com[a] - centre[a];
+    }
+    const double dc = sqrt(dc2), dg = sqrt(dg2), h = sqrt(h2);
+    double n[3] = {0.0, 0.0, 0.0};
+    if (dc > 0.0)
+        for (int a = 0; a < 3; ++a)
+            n[a] = u[a] / dc;
+    const double ml2 = M * side * side;
+    const double q[3][3] = {{Q[0], Q[1], Q[2]}, {Q[1], Q[3], Q[4]}, {Q[2], Q[4], Q[5]}};
+    double nqn = 0.0, qf = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            nqn += n[a] * q[a][b] * n[b];
+            qf += q[a][b] * q[a][b];
+        }
+    double f0 = dg > 0.0 ? log2(side / dg) : 8.0;
+    f[0] = f0 < -8.0 ? -8.0 : (f0 > 8.0 ? 8.0 : f0);
+    const double f1 = dg > 0.0 ? log2(dc / dg) : 8.0;
+    f[1] = f1 > 8.0 ? 8.0 : f1;
+    f[2] = h + dg > 0.0 ? h / (h + dg) : 0.0;
+    f[3] = ml2 > 0.0 ? nqn / ml2 : 0.0;
+    f[4] = ml2 > 0.0 ? sqrt(qf) / ml2 : 0.0;
+    f[5] = (g[0] * n[0] + g[1] * n[1] + g[2] * n[2]) / side;
+    f[6] = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / side;
+    f[7] = log2((double)count) / 21.0;
+    f[8] = dg > 0.0 ? (eps / dg < 1.0 ? eps / dg : 1.0) : 1.0;
+    f[9] = is_leaf ? 1.0 : 0.0;
+}
+
+/* The network as the MFMA inference evaluates it (bf16 operands of both
+ * hidden layers, sums in FP32 there, FP64 here), and *delta, a bound on how
+ * far the FP32 evaluation of the same inputs may move the output:
+ *  - a feature computed in FP32 within a relative 1e-5 (plus 1e-6) of a
+ *    bf16 rounding midpoint may round to the other neighbour; the output
+ *    moves by at most that step times the product of the absolute weights
+ *    along every path from the feature (a Lipschitz bound of the ReLU net);
+ *  - a hidden unit's FP32 sum differs from the exact one by at most
+ *    (terms + 1) 2^-24 times the sum of the absolute terms; if that interval
+ *    straddles a bf16 midpoint (or 0) the unit may round the other way;
+ *  - the second layer's and the output's FP32 sums by the same rule. */
+static double gnet_bound(const double *p, const double *f, double *delta)
+{
+    const double *W1 = p, *b1 = p + 320, *W2 = p + 352, *b2 = p + 1376, *w3 = p + 1408;
+    const double b3 = (double)(float)p[1440];
+    const double u24 = ldexp(1.0, -24);
+    double fr[10], lip[10], h1[32], out = 0.0, d = 0.0, sum_out = fabs(b3);
+    double path[32]; /* sum_u |w3_u| |W2_uj| */
+    for (int j = 0; j < 32; ++j) {
+        path[j] = 0.0;
+        for (int u = 0; u < 32; ++u)
+            path[j] += fabs((double)(float)w3[u]) * fabs(bf16r(W2[u * 32 + j]));
+    }
+    for (int k = 0; k < 10; ++k) {
+        fr[k] = bf16r(f[k]);
+        lip[k] = 0.0;
+        for (int j = 0; j < 32; ++j)
+            lip[k] += path[j] * fabs(bf16r(W1[j * 10 + k]));
+        const double m = 1e-5 * fabs(f[k]) + 1e-6;
+        d += lip[k] * fabs(bf16r(f[k] + m) - bf16r(f[k] - m));
+    }
+    for (int j = 0; j < 32; ++j) {
+        double s = bf16r(b1[j]), a = fabs(s);
+        for (int k = 0; k < 10; ++k) {
+            s += bf16r(W1[j * 10 + k]) * fr[k];
+            a += fabs(bf16r(W1[j * 10 + k]) * fr[k]);
+        }
+        const double e = 12.0 * u24 * a;
+        h1[j] = bf16r(s > 0.0 ? s : 0.0);
+        const double hi = bf16r(s + e > 0.0 ? s + e : 0.0), lo = bf16r(s - e > 0.0 ? s - e : 0.0);
+        d += path[j] * (hi - lo);
+    }
+    for (int u = 0; u < 32; ++u) {
+        double s = (double)(float)b2[u], a = fabs(s);
+        for (int j = 0; j < 32; ++j) {
+            s += bf16r(W2[u * 32 + j]) * h1[j];
+            a += fabs(bf16r(W2[u * 32 + j]) * h1[j]);
+        }
+        d += fabs((double)(float)w3[u]) * 34.0 * u24 * a;
+        if (s > 0.0) {
+            out += (double)(float)w3[u] * s;
+            sum_out += fabs((double)(float)w3[u] * s);
+        }
+    }
+    d += 34.0 * u24 * sum_out;
+    *delta = d;
+    return out + b3;
+}
+
+double orc_gnet_bound(const double *p, const double *f, double *delta)
+{
+    return gnet_bound(p, f, delta);
+}
+
+/* Three-valued learned term of cell c for group g (1 surely accepted, -1
+ * surely rejected, 0 uncertain), the decision taken here in *accept. */
+static int learned_term(const group_ctx *g, int64_t c, double side, double dg2, int *accept)
+{
+    const walk_ctx *w = &g->w;
+    *accept = 0;
+    if (!(dg2 > 0.0) || !(w->M[c] > 0.0))
+        return -1;
+    double centre[3], bl[3], bu[3], f[10], delta;
+    cell_centre(g->hkey[c], w->level[c], g->lo, w->L, centre);
+    for (int a = 0; a < 3; ++a) {
+        bl[a] = g->bc[a] - g->bh[a];
+        bu[a] = g->bc[a] + g->bh[a];
+    }
+    orc_gfeatures(bl, bu, centre, side, &w->com[3 * c], w->M[c], &w->Q[6 * c], w->count[c],
+                  w->next[c] == c + 1, g->eps, f);
+    const double pred = gnet_bound(g->params, f, &delta);
+    const double lm = log10(w->M[c]), ld = log10(dg2);
+    const double lhs = pred + lm - ld;
+    *accept = lhs < g->lt;
+    const double margin = delta + g->tol * (fabs(pred) + fabs(lm) + fabs(ld) + fabs(g->lt) + 1.0);
+    if (g->lt - lhs > margin)
+        return 1;
+    if (lhs - g->lt > margin)
+        return -1;
+    return 0;
+}
+
+/* ---- training pairs of the learned criterion */
+
+/* label of cell c for the bodies [g0, g1): log10 of the largest
+ * |a_pc,i - a_exact,i| d_g^2 / M, floored at 1e-12 */
+static double group_label(const walk_ctx *w, int64_t c, int64_t g0, int64_t g1, double dg2)
+{
+    double emax = 0.0;
+    for (int64_t i = g0; i < g1; ++i) {
+        walk_acc ex, ap;
+        memset(&ex, 0, sizeof(ex));
+        memset(&ap, 0, sizeof(ap));
+        leaf_pp(w, i, c, &ex);
+        double x[3];
+        for (int d = 0; d < 3; ++d)
+            x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
+        pc(w, i, c, x, x[0] * x[0] + x[1] * x[1] + x[2] * x[2], &ap);
+        double e = 0.0;
+        for (int d = 0; d < 3; ++d)
+            e += (ap.a[d] - ex.a[d]) * (ap.a[d] - ex.a[d]);
+        if (e > emax)
+            emax = e;
+    }
+    double v = sqrt(emax) * dg2 / w->M[c];
+    if (!(v > 1e-12))
+        v = 1e-12;
+    return log10(v);
+}
+
+typedef struct {
+    walk_ctx w;
+    const uint64_t *hkey;
+    const double *lo;
+    double tlo2, tmax2, eps, keep;
+    uint64_t seed;
+    int64_t g0, g1, cap, slot0, k;
+    double bl[3], bu[3], bc[3], bh[3];
+    double *feat, *label;
+    int32_t *node;
+} gsample_ctx;
+
+/* Candidates of a group: a walk that leaves cells with l < theta_lo d_g
+ * alone and opens every other cell; each multi-body cell whose cube misses
+ * the box with theta_lo d_g <= l < theta_max d_g is a candidate, kept by
+ * the hash of (seed, first rank of the group, node) with probability keep. */
+static void gsample_walk(gsample_ctx *m, int64_t node)
+{
+    const walk_ctx *w = &m->w;
+    for (int64_t c = node + 1; c < w->next[node]; c = w->next[c]) {
+        if (w->count[c] == 1)
+            continue;
+        const double side = ldexp(w->L, -w->level[c]);
+        double centre[3], dg2 = 0.0;
+        int overlap = 1;
+        cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
+        for (int a = 0; a < 3; ++a) {
+            if (fabs(centre[a] - m->bc[a]) - (0.5 * side + m->bh[a]) > 0.0)
+                overlap = 0;
+            const double t = fabs(w->com[3 * c + a] - m->bc[a]) - m->bh[a];
+            if (t > 0.0)
+                dg2 += t * t;
+        }
+        const double s2 = side * side;
+        if (!overlap && s2 < m->tlo2 * dg2)
+            continue;
+        if (!overlap && s2 < m->tmax2 * dg2 && w->M[c] > 0.0 &&
+            keep_pair(m->seed, m->g0, c, m->keep) && m->k < m->cap) {
+            const int64_t o = m->slot0 + m->k;
+            orc_gfeatures(m->bl, m->bu, centre, side, &w->com[3 * c], w->M[c], &w->Q[6 * c],
+                          w->count[c], w->next[c] == c + 1, m->eps, &m->feat[10 * o]);
+            m->label[o] = group_label(w, c, m->g0, m->g1, dg2);
+            m->node[o] = (int32_t)c;
+            ++m->k;
+        }
+        if (w->next[c] != c + 1)
+            gsample_walk(m, c);
+    }
+}
+
+/* Training pairs of the groups of G consecutive sorted ranks of [t0, t1)
+ * (group q holds [t0 + qG, min(t0 + qG + G, t1))): per group up to cap kept
+ * candidates in pre-order at slot q*cap.. of feat (10 features each),
+ * label, node; cnt[q]. */
+void orc_group_samples(const int32_t *level, const uint64_t *hkey, const int32_t *begin,
+                       const int32_t *count, const int32_t *next, const double *M,
+                       const double *com, const double *Q, const double *spos,
+                       const double *smass, const double *lo, double L, int64_t t0, int64_t t1,
+                       double eps, double theta_lo, double theta_max, double keep, uint64_t seed,
+                       int64_t G, int64_t cap, double *feat, double *label, int32_t *node,
+                       int64_t *cnt)
+{
+    const int64_t n = t1;
+    const int64_t ng = (t1 - t0 + G - 1) / G;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < ng; ++q) {
+        gsample_ctx m;
+        memset(&m, 0, sizeof(m));
+        m.w = (walk_ctx){level, begin, count, next, M, com, Q, spos, smass, L, 0.0, eps * eps, 2};
+        m.hkey = hkey;
+        m.lo = lo;
+        m.tlo2 = theta_lo * theta_lo;
+        m.tmax2 = theta_max * theta_max;
+        m.eps = eps;
+        m.keep = keep;
+        m.seed = seed;
+        m.g0 = t0 + q * G;
+        m.g1 = m.g0 + G < n ? m.g0 + G : n;
+        m.cap = cap;
+        m.slot0 = q * cap;
+        m.feat = feat;
+        m.label = label;
+        m.node = node;
+        for (int a = 0; a < 3; ++a) {
+            m.bl[a] = INFINITY;
+            m.bu[a] = -INFINITY;
+        }
+        for (int64_t i = m.g0; i < m.g1; ++i)
+            for (int a = 0; a < 3; ++a) {
+                m.bl[a] = fmin(m.bl[a], spos[3 * i + a]);
+                m.bu[a] = fmax(m.bu[a], spos[3 * i + a]);
+            }
+        for (int a = 0; a < 3; ++a) {
+            m.bc[a] = 0.5 * (m.bl[a] + m.bu[a]);
+            m.bh[a] = 0.5 * (m.bu[a] - m.bl[a]);
+        }
+        if (next[0] != 1)
+            gsample_walk(&m, 0);
+        cnt[q] = m.k;
     }
 }

@@ -26,7 +26,8 @@ EXPORTED = [
     "bh_version", "bh_last_error", "bh_force_opts_default", "bh_ctx_create", "bh_ctx_set_stream",
     "bh_ctx_destroy", "bh_sync", "bh_build", "bh_tree_free", "bh_forces", "bh_tree_info_get",
     "bh_tree_export", "bh_sim_init", "bh_leapfrog_step", "bh_sim_get", "bh_energy",
-    "bh_sim_tree", "bh_direct", "bh_sim_timing", "bh_sim_timing_get", "bh_mlp_set",
+    "bh_sim_tree", "bh_direct", "bh_sim_timing", "bh_sim_timing_get", "bh_sim_counts_get",
+    "bh_mlp_set",
     "bh_mlp_get", "bh_mlp_samples", "bh_mlp_train", "bh_mlp_grad", "bh_mlp_infer",
     "bh_standard_units", "bh_ctx_set_allocator",
 ]
@@ -109,6 +110,7 @@ def load(path: str = LIB_PATH):
         "bh_ctx_set_allocator": ([vp, ALLOC_FN, FREE_FN, vp], i32),
         "bh_sim_timing": ([vp, i32], i32),
         "bh_sim_timing_get": ([vp, C.POINTER(dbl), C.POINTER(i64)], i32),
+        "bh_sim_counts_get": ([vp, C.POINTER(i64), C.POINTER(i64)], i32),
         "bh_mlp_set": ([vp, vp], i32),
         "bh_mlp_get": ([vp, vp], i32),
         "bh_mlp_samples": ([vp, dbl, dbl, dbl, dbl, C.c_uint64, i64, vp, vp, vp, vp,
@@ -392,6 +394,13 @@ def bh_sim_timing_get(ctx) -> tuple[list, int]:
     steps = C.c_int64()
     _check(load().bh_sim_timing_get(ctx, ms, C.byref(steps)))
     return list(ms), steps.value
+
+
+def bh_sim_counts_get(ctx) -> tuple[int, int]:
+    """(sum n_pp, sum n_pc) over the walks of the recorded steps."""
+    pp, pc = C.c_int64(), C.c_int64()
+    _check(load().bh_sim_counts_get(ctx, C.byref(pp), C.byref(pc)))
+    return pp.value, pc.value
 
 
 # ----------------------------------------------------------------- learned criterion

@@ -392,9 +392,14 @@ static int sim_forces(bh_ctx *c, bool want_phi) {
         s->phi_valid = rc == BH_OK;
         return rc;
     }
+    // a recorded step (bh_sim_timing) also counts its interactions
+    const bool count = c->walk_ev != nullptr && s->cnt_sum.p != nullptr;
+    uint32_t *npp = count ? (uint32_t *)s->cnt_pp.p : nullptr;
+    uint32_t *npc = count ? (uint32_t *)s->cnt_pc.p : nullptr;
     rc = run_walk(c->sim_tree, s->theta, s->eps, s->acc.p, want_phi ? s->phi.p : nullptr,
-                  nullptr, nullptr, s->opts, true, s->have_acc ? s->acc.p : nullptr);
+                  npp, npc, s->opts, true, s->have_acc ? s->acc.p : nullptr);
     s->phi_valid = want_phi && rc == BH_OK;
+    s->counted = rc == BH_OK && count;
     return rc;
 }
 
@@ -502,13 +507,45 @@ int bh_leapfrog_step(bh_ctx *c, double dt) {
     rc = launch_kick(c->stream, s->dtype, s->n, s->vel.p, s->acc.p, 0.5 * dt);
     mark(4);
     if (ev) c->timed_steps++;
+    if (rc == BH_OK && s->counted) {  // after the step's last event: not in its phases
+        s->counted = false;
+        rc = launch_count_sum(c->stream, s->n, (const uint32_t *)s->cnt_pp.p,
+                              (const uint32_t *)s->cnt_pc.p, (unsigned long long *)s->cnt_sum.p);
+    }
     return rc;
 }
 
 int bh_sim_timing(bh_ctx *c, int enable) {
     if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if (enable && c->sim && c->sim->opts.walk != BH_WALK_DIRECT) {
+        // per-body counts and their running sums for the recorded steps
+        SimState *s = c->sim;
+        if (use_device(c)) return BH_E_DEVICE;
+        int rc;
+        if ((rc = grow(s->cnt_pp, 4ull * s->n)) || (rc = grow(s->cnt_pc, 4ull * s->n)) ||
+            (rc = grow(s->cnt_sum, 16)))
+            return rc;
+        if (hipMemsetAsync(s->cnt_sum.p, 0, 16, c->stream) != hipSuccess)
+            return set_error(BH_E_DEVICE, "clearing the interaction counters failed");
+    }
     c->timing = enable != 0;
     if (enable) c->timed_steps = 0;
+    return BH_OK;
+}
+
+int bh_sim_counts_get(bh_ctx *c, int64_t *pp, int64_t *pc) {
+    if (!c || !pp || !pc) return set_error(BH_E_INVALID, "null argument");
+    if (!c->sim || !c->sim->have_acc) return set_error(BH_E_STATE, "bh_sim_init has not run");
+    SimState *s = c->sim;
+    *pp = *pc = 0;
+    if (!s->cnt_sum.p) return BH_OK;  // nothing recorded (or the direct method)
+    if (use_device(c)) return BH_E_DEVICE;
+    unsigned long long h[2] = {0, 0};
+    if (hipMemcpyAsync(h, s->cnt_sum.p, 16, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return set_error(BH_E_DEVICE, "reading the interaction counters failed");
+    *pp = (int64_t)h[0];
+    *pc = (int64_t)h[1];
     return BH_OK;
 }
 

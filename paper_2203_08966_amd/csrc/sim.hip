@@ -37,6 +37,27 @@ __global__ __launch_bounds__(kThreads) void k_kick_drift(int64_t n3, T *__restri
     }
 }
 
+// Adds sum(a) and sum(b) (per-body interaction counts) into out[0], out[1]:
+// per-thread 64-bit sums, a wavefront reduction, one atomic per wavefront.
+__global__ __launch_bounds__(kThreads) void k_count_sum(int64_t n, const uint32_t *__restrict__ a,
+                                                        const uint32_t *__restrict__ b,
+                                                        unsigned long long *__restrict__ out) {
+    unsigned long long sa = 0, sb = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        sa += a[i];
+        sb += b[i];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sa += __shfl_down(sa, off);
+        sb += __shfl_down(sb, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&out[0], sa);
+        atomicAdd(&out[1], sb);
+    }
+}
+
 // Per-block FP64 partial sums of (m v^2 / 2, m phi / 2).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_energy(int n, const T *__restrict__ v,
@@ -300,6 +321,12 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
+int launch_count_sum(hipStream_t s, int64_t n, const uint32_t *a, const uint32_t *b,
+                     unsigned long long *out) {
+    k_count_sum<<<std::min(grid_for(n), 1024), kThreads, 0, s>>>(n, a, b, out);
+    return check_launch("count_sum");
+}
+
 int launch_kick(hipStream_t s, int dtype, int64_t n, void *vel, const void *acc, double h) {
     if (dtype == BH_F32)
         k_kick<float><<<grid_for(3 * n), kThreads, 0, s>>>(3 * n, (float *)vel, (const float *)acc, (float)h);
@@ -344,26 +371,46 @@ int launch_unpermute(hipStream_t s, int dtype, int64_t n, const uint32_t *id, co
 }
 
 namespace {
-// sources split so that about 2048 blocks are in flight
+// Sources split so that about 2048 blocks are in flight: the number of
+// splits and the source chunk per split for n sources and nt targets.
+struct DirectSplit {
+    int bx, nsplit, chunk;
+};
+
+DirectSplit direct_split(int64_t n, int64_t nt) {
+    DirectSplit d;
+    d.bx = div_up(nt, kThreads);
+    d.nsplit = 2048 / d.bx;
+    if (d.nsplit < 1) d.nsplit = 1;
+    if (d.nsplit > 256) d.nsplit = 256;
+    d.chunk = div_up(n, d.nsplit);
+    d.chunk = div_up(d.chunk, kThreads) * kThreads;
+    d.nsplit = div_up(n, d.chunk);
+    return d;
+}
+
+// part: 32 * nsplit * nt bytes of device memory (4 doubles per split and target)
+template <typename T, typename R, typename O>
+int direct_launch(hipStream_t s, const DirectSplit &d, int64_t n, const T *pos, const T *mass,
+                  const int64_t *targets, int64_t nt, double eps, O *acc, O *phi, double *part) {
+    dim3 grid(d.bx, d.nsplit);
+    k_direct<T, R><<<grid, kThreads, 0, s>>>((int)n, pos, mass, targets, (int)nt, eps * eps,
+                                             d.chunk, part);
+    k_direct_sum<O><<<d.bx, kThreads, 0, s>>>(part, (int)nt, d.nsplit, acc, phi);
+    return check_launch("direct");
+}
+
 template <typename T, typename R, typename O>
 int direct_splits(hipStream_t s, int64_t n, const T *pos, const T *mass,
                   const int64_t *targets, int64_t nt, double eps, O *acc, O *phi,
                   DevBuf &scratch) {
-    const int bx = div_up(nt, kThreads);
-    int nsplit = 2048 / bx;
-    if (nsplit < 1) nsplit = 1;
-    if (nsplit > 256) nsplit = 256;
-    int chunk = div_up(n, nsplit);
-    chunk = div_up(chunk, kThreads) * kThreads;
-    nsplit = div_up(n, chunk);
-    int rc = grow(scratch, 32ull * nsplit * nt);
+    const DirectSplit d = direct_split(n, nt);
+    int rc = grow(scratch, 32ull * d.nsplit * nt);
     if (rc) return rc;
-    dim3 grid(bx, nsplit);
-    k_direct<T, R><<<grid, kThreads, 0, s>>>((int)n, pos, mass, targets, (int)nt, eps * eps,
-                                             chunk, (double *)scratch.p);
-    k_direct_sum<O><<<bx, kThreads, 0, s>>>((const double *)scratch.p, (int)nt, nsplit, acc, phi);
-    return check_launch("direct");
+    return direct_launch<T, R, O>(s, d, n, pos, mass, targets, nt, eps, acc, phi,
+                                  (double *)scratch.p);
 }
+
 }  // namespace
 
 int launch_direct(hipStream_t s, int dtype, int64_t n, const void *pos, const void *mass,

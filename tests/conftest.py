@@ -63,3 +63,28 @@ def case_bodies(kind, n, seed, dtype):
 
 def say(*a):
     print(*a, flush=True)
+
+
+def check_flagged(ref, orc_acc, gpu_acc, flag, eps, max_frac):
+    """Bodies with a decision near its threshold (``flag``, sorted order):
+    their share is at most ``max_frac``, and each one's GPU force is within
+    the method's own error: its relative error against FP64 direct
+    summation is at most the largest the oracle's walk (same criterion and
+    parameters) makes on any body.  A decision taken the other way swaps one
+    particle-cell term for the exact sum over the cell or back, so it can
+    move a force by no more than the approximation the method accepts."""
+    import numpy as np
+
+    import oracle
+    flag = np.asarray(flag) != 0
+    frac = float(flag.mean())
+    say(f"  flagged {flag.sum()} of {flag.size} ({frac:.4%}), bound {max_frac:.2%}")
+    assert frac <= max_frac
+    if not flag.any():
+        return
+    d, _ = oracle.direct(ref["spos"], ref["smass"], eps)
+    nd = np.linalg.norm(d, axis=1)
+    e_orc = np.linalg.norm(orc_acc - d, axis=1) / nd
+    e_gpu = np.linalg.norm(gpu_acc[flag] - d[flag], axis=1) / nd[flag]
+    say(f"  flagged: max error vs direct {e_gpu.max():.3e}, method's max {e_orc.max():.3e}")
+    assert np.all(e_gpu <= e_orc.max())

@@ -7,7 +7,7 @@ import torch
 import oracle
 from paper_2203_08966_amd import binding as B
 from paper_2203_08966_amd import workloads as W
-from tests.conftest import case_bodies, say
+from tests.conftest import case_bodies, check_flagged, say
 
 pytestmark = pytest.mark.gpu
 
@@ -34,29 +34,37 @@ def _run(ctx, pos, mass, leaf, theta, eps, **kw):
 # the FP32 and FP64 walks (as for the per-body walk)
 TOL = {np.float32: (1e-5, 1e-4), np.float64: (1e-12, 1e-10)}
 # relative margin around a decision threshold inside which the walk's
-# arithmetic may decide either way
+# arithmetic may decide either way.  FP32: the group box, the COM offset and
+# the distance d_g^2 are each a few roundings (2^-24) of quantities up to
+# about ten times d_g (large boxes), so d_g^2 is good to a few 1e-6; FP64 to
+# about 1e-15, with the same factor.
 FLAG_TOL = {np.float32: 1e-5, np.float64: 1e-9}
+# share of bodies that may be flagged: one uncertain decision flags every
+# body of its group (64), and a group takes some thousand decisions; the
+# oracle flags 0-0.7 % of the bodies in these cases
+MAX_FLAGGED = 0.02
+# work caps stated by each test for both the library and the oracle (the
+# method's definition: a run over the cap is walked per body)
+CAP_THETA, CAP_BUDGET = 6144, 4096
 
 
-def _check(ref, r, out, dtype, min_unflagged=0.7):
+def _check(ref, r, out, dtype, eps, max_flagged=MAX_FLAGGED):
     """Counts identical for every body of an unflagged group, forces within
     the walk's precision there; a flagged group may take a decision the other
-    way, which swaps one approximation for another."""
+    way, which swaps one approximation for another: bounded by the method's
+    own error (check_flagged)."""
     rms_tol, max_tol = TOL[dtype]
     a, phi, cp, cc = (x[ref["perm"]] for x in out)
     ok = r.flag == 0
     same = (cp == r.npp) & (cc == r.npc)
-    say(f"  unflagged {ok.mean():.3f}, identical counts there {same[ok].mean():.4f}")
-    say(f"  flagged groups with other counts {(~same[~ok]).mean() if (~ok).any() else 0:.3f}")
-    assert ok.mean() >= min_unflagged
+    say(f"  unflagged {ok.mean():.4f}, identical counts there {same[ok].mean():.4f}")
     assert np.all(same[ok])
     e = np.linalg.norm(a - r.acc, axis=1) / np.linalg.norm(r.acc, axis=1)
     ep = np.abs(phi - r.phi) / np.abs(r.phi)
     say(f"  rel err (unflagged): rms {np.sqrt(np.mean(e[ok] ** 2)):.3e} max {e[ok].max():.3e}")
     assert np.sqrt(np.mean(e[ok] ** 2)) <= rms_tol and e[ok].max() <= max_tol
     assert np.sqrt(np.mean(ep[ok] ** 2)) <= rms_tol
-    if (~ok).any():
-        assert e[~ok].max() <= 1e-2
+    check_flagged(ref, r.acc, a, r.flag, eps, max_flagged)
 
 
 @pytest.mark.parametrize("kind,n,dtype,theta", [
@@ -69,10 +77,11 @@ def test_group_walk_matches_oracle(ctx, kind, n, dtype, theta):
     pos, _, mass = case_bodies(kind, n, 11, dtype)
     eps, leaf = 0.005, 16
     say(f"group walk {kind} n={n} {np.dtype(dtype).name} theta {theta}")
-    out = _run(ctx, pos, mass, leaf, theta, eps)
+    out = _run(ctx, pos, mass, leaf, theta, eps, walk_cap=CAP_THETA)
     ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), leaf)
-    r = oracle.walk_group(ref, eps, group=B.BH_GROUP_BODIES, theta=theta, tol=FLAG_TOL[dtype])
-    _check(ref, r, out, dtype)
+    r = oracle.walk_group(ref, eps, group=B.BH_GROUP_BODIES, theta=theta, tol=FLAG_TOL[dtype],
+                          cap=CAP_THETA, split=True)
+    _check(ref, r, out, dtype, eps)
 
 
 def test_group_walk_small_stack_same_result(ctx):
@@ -94,16 +103,18 @@ def test_group_walk_target_range_and_tiny_trees(ctx):
     P, M = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
     t = B.bh_build(ctx, P, M, 8)
     acc = torch.full_like(P, 5.0)
-    B.bh_forces(t, 0.7, 0.01, acc, B.force_opts(walk=B.BH_WALK_GROUP, target_range=(100, 1337)))
+    B.bh_forces(t, 0.7, 0.01, acc, B.force_opts(walk=B.BH_WALK_GROUP, target_range=(100, 1337),
+                                                 walk_cap=CAP_THETA))
     torch.cuda.synchronize()
     perm = B.bh_tree_export(t)["perm"].astype(np.int64)
     B.bh_tree_free(t)
     ref = oracle.build_all(pos, mass, 8)
-    r = oracle.walk_group(ref, 0.01, group=B.BH_GROUP_BODIES, theta=0.7, target_range=(100, 1337), tol=1e-9)
+    r = oracle.walk_group(ref, 0.01, group=B.BH_GROUP_BODIES, theta=0.7, target_range=(100, 1337),
+                          tol=1e-9, cap=CAP_THETA, split=True)
     a = acc.cpu().numpy()
     ok = r.flag == 0
     e = np.linalg.norm(a[perm[100:1337]] - r.acc, axis=1) / np.linalg.norm(r.acc, axis=1)
-    assert ok.mean() > 0.9 and e[ok].max() <= TOL[np.float64][1]
+    assert ok.mean() >= 1 - MAX_FLAGGED and e[ok].max() <= TOL[np.float64][1]
     rest = np.setdiff1d(np.arange(5000), perm[100:1337])
     assert np.all(a[rest] == 5.0)
     # a root that is a leaf, and a single body
@@ -126,11 +137,11 @@ def test_group_budget_matches_oracle(ctx):
     an = an.astype(np.float32)
     say(f"group budget walk: 20000 bodies, tau {tau:.3g}, theta_max {tmax}")
     out = _run(ctx, pos, mass, 16, 0.5, eps, mac=B.BH_MAC_BUDGET, mlp_theta_max=tmax,
-               mlp_log10_tau=np.log10(tau), acc_norm=an)
+               mlp_log10_tau=np.log10(tau), acc_norm=an, walk_cap=CAP_BUDGET)
     r = oracle.walk_group(ref, eps, group=B.BH_GROUP_BODIES, mode=1, theta_max=tmax, tau=tau,
                           kc=oracle.cell_kc(ref, eps), anorm=an.astype(np.float64)[ref["perm"]],
-                          tol=FLAG_TOL[np.float32])
-    _check(ref, r, out, np.float32)
+                          tol=FLAG_TOL[np.float32], cap=CAP_BUDGET, split=True)
+    _check(ref, r, out, np.float32, eps)
 
 
 def test_group_budget_floor_matches_oracle(ctx):
@@ -145,13 +156,14 @@ def test_group_budget_floor_matches_oracle(ctx):
     an = an.astype(np.float32)
     say(f"group budget walk, floor {fl}: 20000 bodies, tau {tau:.3g}, theta_max {tmax}")
     out = _run(ctx, pos, mass, 16, 0.5, eps, mac=B.BH_MAC_BUDGET, mlp_theta_max=tmax,
-               mlp_log10_tau=np.log10(tau), acc_norm=an, mlp_acc_floor=fl)
+               mlp_log10_tau=np.log10(tau), acc_norm=an, mlp_acc_floor=fl, walk_cap=CAP_BUDGET)
     args = dict(group=B.BH_GROUP_BODIES, mode=1, theta_max=tmax, tau=tau, kc=oracle.cell_kc(ref, eps),
-                anorm=an.astype(np.float64)[ref["perm"]], tol=FLAG_TOL[np.float32])
+                anorm=an.astype(np.float64)[ref["perm"]], tol=FLAG_TOL[np.float32],
+                cap=CAP_BUDGET, split=True)
     r = oracle.walk_group(ref, eps, floor=fl, **args)
     r0 = oracle.walk_group(ref, eps, **args)
     assert np.mean(r.npp + r.npc < r0.npp + r0.npc) > 0.05  # the floor is in effect
-    _check(ref, r, out, np.float32)
+    _check(ref, r, out, np.float32, eps)
 
 
 def test_group_walk_full_size_sampled(ctx):
@@ -162,7 +174,7 @@ def test_group_walk_full_size_sampled(ctx):
     n = b.n
     theta = 0.75
     say(f"group walk full size: n={n}, theta {theta}, 24 sampled groups")
-    out = _run(ctx, b.pos, b.mass, cfg["leaf"], theta, cfg["eps"])
+    out = _run(ctx, b.pos, b.mass, cfg["leaf"], theta, cfg["eps"], walk_cap=CAP_THETA)
     ref = oracle.build_all(b.pos.astype(np.float64), b.mass.astype(np.float64), cfg["leaf"])
     rng = np.random.default_rng(4)
     G = B.BH_GROUP_BODIES
@@ -171,7 +183,8 @@ def test_group_walk_full_size_sampled(ctx):
     checked = 0
     for g in groups:
         r = oracle.walk_group(ref, cfg["eps"], group=B.BH_GROUP_BODIES, theta=theta,
-                              target_range=(G * g, G * g + G), tol=FLAG_TOL[np.float32])
+                              target_range=(G * g, G * g + G), tol=FLAG_TOL[np.float32],
+                              cap=CAP_THETA, split=True)
         sl = slice(G * g, G * g + G)
         if r.flag[0]:
             continue
@@ -195,7 +208,7 @@ def test_group_walk_work_cap(ctx, mode):
     ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), 16)
     G = B.BH_GROUP_BODIES
     if mode == 0:
-        args = dict(group=G, theta=0.7, tol=FLAG_TOL[np.float32])
+        args = dict(group=G, theta=0.7, tol=FLAG_TOL[np.float32], split=True)
         kw = dict()
         theta = 0.7
     else:
@@ -205,9 +218,10 @@ def test_group_walk_work_cap(ctx, mode):
         an = an.astype(np.float32)
         kw = dict(mac=B.BH_MAC_BUDGET, mlp_theta_max=1.0, mlp_log10_tau=-2.0, acc_norm=an)
         args = dict(group=G, mode=1, theta_max=1.0, tau=1e-2, kc=oracle.cell_kc(ref, eps),
-                    anorm=an.astype(np.float64)[ref["perm"]], tol=FLAG_TOL[np.float32])
+                    anorm=an.astype(np.float64)[ref["perm"]], tol=FLAG_TOL[np.float32],
+                    split=True)
         theta = 0.5
-    full = oracle.walk_group(ref, eps, **args)
+    full = oracle.walk_group(ref, eps, cap=1 << 40, **args)
     cap = int(np.quantile(full.npp + full.npc + 1, 0.7))
     say(f"group walk work cap {cap}, mode {mode}")
     out = _run(ctx, pos, mass, 16, theta, eps, walk_cap=cap, **kw)
@@ -215,7 +229,7 @@ def test_group_walk_work_cap(ctx, mode):
     fell = np.mean(full.npp + full.npc + 1 > cap)
     say(f"  fraction of bodies in groups over the cap: {fell:.3f}")
     assert 0.05 < fell < 0.95
-    _check(ref, r, out, np.float32)
+    _check(ref, r, out, np.float32, eps)
 
 
 def test_group_walk_repeat_is_bitwise_identical(ctx):
@@ -298,7 +312,8 @@ def test_group_walk_prediction_after_rebuild(ctx):
     p = ref["perm"]
     a = acc.cpu().numpy().astype(np.float64)[p]
     cp, cc = npp.cpu().numpy()[p], npc.cpu().numpy()[p]
-    rg = oracle.walk_group(ref, eps, group=B.BH_GROUP_BODIES, theta=theta, tol=FLAG_TOL[np.float32], cap=cap)
+    rg = oracle.walk_group(ref, eps, group=B.BH_GROUP_BODIES, theta=theta, tol=FLAG_TOL[np.float32],
+                           cap=cap, split=True)
     rb = oracle.walk(ref["tree"], ref["mom"], ref["spos"], ref["smass"], ref["L"], theta, eps)
 
     def same(r):
@@ -339,3 +354,68 @@ def test_default_work_cap_by_criterion(ctx):
         assert torch.equal(a0, walk(default, **kw))
         assert not torch.equal(a0, walk(other, **kw))
     B.bh_tree_free(t)
+
+
+def test_timed_path_budget_steps_match_oracle(ctx):
+    """The path the benchmark times: leapfrog steps with the group
+    error-budget walk, |a_i| floored at half the mean and taken from the
+    previous step, a work cap, and the per-body predictions the steps carry
+    from walk to walk.  Steps of dt = 0 keep the bodies in place (so every
+    input of the oracle is the host's), while each step still rebuilds the
+    tree in place, walks with the previous accelerations and kicks.  The
+    oracle runs the same chain with its own accelerations: an estimate by a
+    monopole group walk at theta 0.8 first, then one budget walk per step.
+    After every step each body's force and counts equal the oracle's group
+    walk or its per-body budget walk (a group predicted to exceed the cap is
+    walked per body), except the groups that took a decision near a
+    threshold in this step or hold a body that differed in the previous
+    one (a flipped decision changes that body's |a_i|, and with it its
+    group's next decisions)."""
+    n, eps, leaf, cap, steps = 20000, 0.005, 16, 2000, 4
+    tau, tmax, fl, test = 10 ** -1.75, 1.5, 0.5, 0.8
+    pos, vel, mass = case_bodies("plummer", n, 19, np.float32)
+    P, V, M = (torch.from_numpy(a).cuda() for a in (pos, vel, mass))
+    o = B.force_opts(walk=B.BH_WALK_GROUP, mac=B.BH_MAC_BUDGET, walk_cap=cap,
+                     mlp_log10_tau=np.log10(tau), mlp_theta_max=tmax, mlp_acc_floor=fl,
+                     mlp_theta_est=test)
+    say(f"timed path: {n} bodies, group budget walk, cap {cap}, {steps} steps of dt 0")
+    B.bh_sim_init(ctx, P, V, M, leaf, 0.5, eps, o)
+    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), leaf)
+    p = ref["perm"]
+    kc = oracle.cell_kc(ref, eps)
+    G = B.BH_GROUP_BODIES
+    est = oracle.walk_group(ref, eps, group=G, mode=0, order=0, theta=test, cap=cap, split=True,
+                            tol=FLAG_TOL[np.float32])
+    anorm = np.linalg.norm(est.acc, axis=1)
+    exempt = est.flag != 0  # sorted order: bodies whose |a_i| may differ
+    budget = dict(group=G, mode=1, theta_max=tmax, tau=tau, kc=kc, floor=fl, cap=cap,
+                  split=True, tol=FLAG_TOL[np.float32])
+    per_body_seen = 0
+    for k in range(steps + 1):
+        if k:
+            B.bh_leapfrog_step(ctx, 0.0)
+        a = torch.empty_like(P)
+        B.bh_sim_get(ctx, None, None, a)
+        torch.cuda.synchronize()
+        a = a.cpu().numpy().astype(np.float64)[p]
+        rg = oracle.walk_group(ref, eps, anorm=anorm, **budget)
+        rb = oracle.walk_kc(ref, eps, tmax, tau, kc, anorm, floor=fl)
+
+        def close(r):
+            e = np.linalg.norm(a - r.acc, axis=1) / np.linalg.norm(r.acc, axis=1)
+            return e <= TOL[np.float32][1]
+        same_g, same_b = close(rg), close(rb)
+        bad_group = np.repeat(np.add.reduceat(exempt | (rg.flag != 0), np.arange(0, n, G)) > 0,
+                              G)[:n]
+        match = same_g | same_b
+        per_body_seen += int(np.sum(same_b & ~same_g & ~bad_group))
+        say(f"  step {k}: match {match.mean():.4f}, exempt groups hold {bad_group.mean():.4f}, "
+            f"per-body results {np.mean(same_b & ~same_g):.4f}")
+        assert np.all(match | bad_group)
+        assert bad_group.mean() <= 0.05
+        exempt = ~match
+        # the oracle's next |a_i|: its own result where the GPU took the
+        # group walk or the per-body walk, as the GPU did
+        anorm = np.linalg.norm(np.where(same_b[:, None] & ~same_g[:, None], rb.acc, rg.acc),
+                               axis=1)
+    assert per_body_seen > 0  # predicted or over-cap groups were walked per body

@@ -8,7 +8,7 @@ import torch
 import oracle
 from oracle import mlp
 from paper_2203_08966_amd import binding as B
-from tests.conftest import case_bodies, say
+from tests.conftest import case_bodies, check_flagged, say
 
 pytestmark = pytest.mark.gpu
 
@@ -154,10 +154,33 @@ def _gpu_walk(ctx, pos, mass, leaf, eps, **kw):
     return acc.cpu().numpy().astype(np.float64), npp.cpu().numpy(), npc.cpu().numpy()
 
 
-def _compare(ref, r, a, cp, cc, min_unflagged=0.5):
-    """Identical interaction counts for bodies with no near-threshold
-    decision; forces within the FP32 bound there, and overall (a flipped
-    decision moves a force by about the error budget)."""
+def _compare(ref, r, a, cp, cc, eps, max_flagged=0.01):
+    """k_C = 1 (the per-cell coefficient exact in both): identical
+    interaction counts and forces within the FP32 bounds for every body
+    with no near-threshold decision; flagged bodies few and within the
+    method's own error."""
+    n = len(cp)
+    p = ref["perm"]
+    a, cp, cc = a[p], cp[p], cc[p]
+    ok = r.flag == 0
+    match = (cp == r.npp) & (cc == r.npc)
+    say(f"  unflagged {ok.sum()} of {n}, of those with identical counts {match[ok].sum()}")
+    assert np.all(match[ok])
+    e = np.linalg.norm(a - r.acc, axis=1) / np.linalg.norm(r.acc, axis=1)
+    assert np.sqrt(np.mean(e[ok] ** 2)) < 1e-5 and e[ok].max() < 1e-4
+    check_flagged(ref, r.acc, a, r.flag, eps, max_flagged)
+
+
+def _compare_learned(ref, r, a, cp, cc, min_unflagged=0.5):
+    """A criterion input that the two sides compute in different precisions
+    beyond the flag margin: the learned k_C (the network's hidden layer is
+    rounded to bf16 or fp16 after an FP32 sum on the GPU and an FP64 sum in
+    the oracle, so a hidden value at a rounding midpoint can round the other
+    way and move a cell's k_C by up to about 1 %), or |a_i| estimated by
+    each side's own monopole walk (FP32 against FP64).  Identical counts on
+    99 % of the unflagged bodies, forces within the FP32 bound where the
+    counts agree, and overall (a flipped decision moves a force by about the
+    error budget)."""
     n = len(cp)
     p = ref["perm"]
     a, cp, cc = a[p], cp[p], cc[p]
@@ -191,7 +214,7 @@ def test_budget_walk_matches_oracle(ctx):
                           mlp_log10_tau=np.log10(tau), acc_norm=an)
     r = oracle.walk_kc(ref, eps, tmax, tau, oracle.cell_kc(ref, eps),
                        an.astype(np.float64)[ref["perm"]])
-    _compare(ref, r, a, cp, cc)
+    _compare(ref, r, a, cp, cc, eps)
 
 
 def test_budget_walk_floor_matches_oracle(ctx):
@@ -209,7 +232,7 @@ def test_budget_walk_floor_matches_oracle(ctx):
     r0 = oracle.walk_kc(ref, eps, tmax, tau, oracle.cell_kc(ref, eps),
                         an.astype(np.float64)[ref["perm"]])
     assert np.mean(r.npp + r.npc < r0.npp + r0.npc) > 0.05  # the floor is in effect
-    _compare(ref, r, a, cp, cc)
+    _compare(ref, r, a, cp, cc, eps)
 
 
 def test_learned_walk_matches_oracle(ctx):
@@ -232,7 +255,7 @@ def test_learned_walk_matches_oracle(ctx):
     r1 = oracle.walk_kc(ref, eps, tmax, tau, oracle.cell_kc(ref, eps),
                         an.astype(np.float64)[ref["perm"]])
     assert np.mean((r.npp != r1.npp) | (r.npc != r1.npc)) > 0.1
-    _compare(ref, r, a, cp, cc)
+    _compare_learned(ref, r, a, cp, cc)
 
 
 def test_learned_walk_f16_matches_oracle(ctx):
@@ -252,7 +275,7 @@ def test_learned_walk_f16_matches_oracle(ctx):
                           mlp_precision=B.BH_MLP_FP16)
     kc = oracle.cell_kc(ref, eps, th32, f16=True)
     r = oracle.walk_kc(ref, eps, tmax, tau, kc, an.astype(np.float64)[ref["perm"]])
-    _compare(ref, r, a, cp, cc)
+    _compare_learned(ref, r, a, cp, cc)
 
 
 def test_budget_walk_estimates_anorm(ctx):
@@ -268,7 +291,7 @@ def test_budget_walk_estimates_anorm(ctx):
                      order=0)
     r = oracle.walk_kc(ref, eps, 1.0, tau, oracle.cell_kc(ref, eps),
                        np.linalg.norm(w0.acc, axis=1))
-    _compare(ref, r, a, cp, cc)
+    _compare_learned(ref, r, a, cp, cc)
 
 
 def test_budget_walk_target_range(ctx):

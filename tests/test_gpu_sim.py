@@ -105,3 +105,34 @@ def test_sim_state_errors(ctx):
         B.bh_energy(c2)
     assert e.value.code == B.BH_E_STATE
     B.bh_ctx_destroy(c2)
+
+
+@pytest.mark.parametrize("walk", [B.BH_WALK_BODY, B.BH_WALK_GROUP])
+def test_recorded_steps_count_interactions(ctx, walk):
+    """Steps recorded by bh_sim_timing also sum their walks' interaction
+    counts: equal to the counts of the same walk repeated on each step's
+    tree (no work cap, so a repeated group walk takes the same decisions)."""
+    pos, vel, mass = case_bodies("plummer", 30000, 6, np.float32)
+    theta, eps, leaf, dt = 0.6, 0.005, 16, 5e-4
+    say(f"recorded step counts: 30000 bodies, walk {walk}")
+    P, V, M = (torch.from_numpy(a).cuda() for a in (pos, vel, mass))
+    o = B.force_opts(walk=walk, walk_cap=1 << 30)
+    B.bh_sim_init(ctx, P, V, M, leaf, theta, eps, o)
+    B.bh_leapfrog_step(ctx, dt)
+    B.bh_sim_timing(ctx, True)
+    pp = pc = 0
+    for _ in range(3):
+        B.bh_leapfrog_step(ctx, dt)
+        t = B.bh_sim_tree(ctx)
+        acc = torch.empty_like(P)
+        npp = torch.zeros(30000, dtype=torch.int32, device="cuda")
+        npc = torch.zeros(30000, dtype=torch.int32, device="cuda")
+        B.bh_forces(t, theta, eps, acc, B.force_opts(walk=walk, walk_cap=1 << 30, n_pp=npp,
+                                                      n_pc=npc))
+        pp += int(npp.to(torch.int64).sum().item())
+        pc += int(npc.to(torch.int64).sum().item())
+    got = B.bh_sim_counts_get(ctx)
+    _, steps = B.bh_sim_timing_get(ctx)
+    B.bh_sim_timing(ctx, False)
+    say(f"  recorded {got}, repeated walks {(pp, pc)}")
+    assert steps == 3 and got == (pp, pc) and pc > 0

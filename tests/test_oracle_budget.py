@@ -1,0 +1,142 @@
+"""Hand-computed pins of the error-budget acceptance test (the library's
+criterion beside the opening angle of Sec. 3): a multi-body cell C is
+accepted iff l^2 < theta_max^2 d^2, the body lies outside C, and
+k_C M l^3 < tau |a_i| d^5 (k_C = 1 here).  In the group walk d is the
+distance d_g from C's centre of mass to the group's bounding box and |a_i|
+the smallest norm of the group's bodies.
+
+Each pin places a two-mass cell (unequal masses, so the COM is not the
+midpoint) at a distance that is neither 1 nor its side, computes the
+threshold by hand, and checks that the decision flips between a relative
+1e-3 below and above it.  A wrong power of d (d^4 for d^5), of the side
+(l^2 for l^3), the mass squared, the body's own norm in place of the
+group's smallest, or the body distance in place of the box distance all
+move the threshold by far more than 1e-3 and fail here."""
+import numpy as np
+import pytest
+
+import oracle
+
+# Level-1 octant 0 of the root cube [0, 2)^3 holds the corner pin O and the
+# two group bodies A, B; octant 7 holds the far corner pin Z and the cell
+# C = [1.5, 2) x [1, 1.5) x [1, 1.5) (side 0.5, level 2) with C1 and C2.
+O = (0.0, 0.0, 0.0)
+A = (0.2, 0.7, 0.3)
+B = (0.6, 0.4, 0.4)
+C1 = (1.6, 1.1, 1.2)
+C2 = (1.8, 1.4, 1.04)
+Z = (1.98, 1.98, 1.98)
+MC1, MC2 = 0.5, 0.25
+SIDE = 0.5
+
+
+def _system():
+    pos = np.array([O, A, B, C1, C2, Z])
+    mass = np.array([1e-9, 1.0, 1.0, MC1, MC2, 1e-9])
+    tb = oracle.build_all(pos, mass, 1)
+    assert tb["L"] == 2.0 and np.all(tb["lo"] == 0.0)
+    rank = np.empty(6, dtype=np.int64)
+    rank[tb["perm"]] = np.arange(6)
+    # C is one level-2 cell holding exactly C1 and C2
+    t = tb["tree"]
+    c = [k for k in range(len(t["level"])) if t["level"][k] == 2 and t["count"][k] == 2
+         and t["begin"][k] == min(rank[3], rank[4])]
+    assert len(c) == 1
+    return tb, rank, c[0]
+
+
+def _com():
+    return (MC1 * np.array(C1) + MC2 * np.array(C2)) / (MC1 + MC2)
+
+
+def _norms(rank, a_of):
+    """|a_i| per sorted rank (the walk's input), from a map body -> norm."""
+    an = np.ones(6)
+    for body, v in a_of.items():
+        an[rank[body]] = v
+    return an
+
+
+def test_cell_under_test_in_closed_form():
+    tb, rank, c = _system()
+    M, com, Q = tb["mom"]
+    assert M[c] == MC1 + MC2
+    np.testing.assert_allclose(com[c], _com(), rtol=1e-15)
+    kc = oracle.cell_kc(tb, 0.0)
+    assert kc[c] == pytest.approx((MC1 + MC2) * SIDE ** 3, rel=1e-15)
+
+
+def test_per_body_budget_flips_at_hand_threshold():
+    """Body A alone: accept C iff (M l^3) < tau |a_A| d^5, d = |A - COM_C|."""
+    tb, rank, c = _system()
+    kc = oracle.cell_kc(tb, 0.0)
+    a_A = 0.7
+    an = _norms(rank, {1: a_A, 2: 5.0})
+    d = np.linalg.norm(np.array(A) - _com())
+    tau_star = (MC1 + MC2) * SIDE ** 3 / (a_A * d ** 5)
+    # the octant-7 cell (side 1, 8x the coefficient) stays rejected here
+    for f, accepted in ((1 + 1e-3, True), (1 - 1e-3, False)):
+        r = oracle.walk_kc(tb, 0.0, 10.0, tau_star * f, kc, an, targets=[rank[1]])
+        assert r.ncov[0] == 5
+        assert r.npc[0] == (1 if accepted else 0), f
+        assert r.npp[0] == (3 if accepted else 5), f
+        assert r.flag[0] == 0
+
+
+def test_per_body_angle_limit_flips_at_side_over_distance():
+    """With an unbounded budget the test is l^2 < theta_max^2 d^2: C is the
+    first cell to pass as theta_max crosses l/d (octant 7, side 1, is about
+    twice that ratio)."""
+    tb, rank, c = _system()
+    kc = oracle.cell_kc(tb, 0.0)
+    an = _norms(rank, {})
+    d = np.linalg.norm(np.array(A) - _com())
+    lim = SIDE / d
+    for f, accepted in ((1 + 1e-3, True), (1 - 1e-3, False)):
+        r = oracle.walk_kc(tb, 0.0, lim * f, 1e30, kc, an, targets=[rank[1]])
+        assert r.npc[0] == (1 if accepted else 0), f
+
+
+def test_group_budget_flips_at_hand_threshold():
+    """Group {A, B} (consecutive ranks): accept C for both iff
+    M l^3 < tau min(|a_A|, |a_B|) d_g^5, with d_g the distance from C's COM
+    to the box spanned by A and B."""
+    tb, rank, c = _system()
+    assert abs(rank[1] - rank[2]) == 1
+    r0 = min(rank[1], rank[2])
+    kc = oracle.cell_kc(tb, 0.0)
+    a_A, a_B = 1.3, 0.7
+    an = _norms(rank, {1: a_A, 2: a_B})
+    lo = np.minimum(A, B)
+    hi = np.maximum(A, B)
+    gap = np.maximum(0.0, np.maximum(lo - _com(), _com() - hi))
+    dg = np.linalg.norm(gap)
+    # the box's nearest corner is neither body: d_g is well below either
+    # body's own distance
+    assert dg < 0.95 * min(np.linalg.norm(np.array(A) - _com()),
+                          np.linalg.norm(np.array(B) - _com()))
+    tau_star = (MC1 + MC2) * SIDE ** 3 / (min(a_A, a_B) * dg ** 5)
+    for f, accepted in ((1 + 1e-3, True), (1 - 1e-3, False)):
+        r = oracle.walk_group(tb, 0.0, group=2, mode=1, theta_max=10.0, tau=tau_star * f,
+                              kc=kc, anorm=an, target_range=(r0, r0 + 2), cap=1 << 40,
+                              split=False)
+        assert np.all(r.ncov == 5)
+        assert np.all(r.npc == (1 if accepted else 0)), f
+        assert np.all(r.npp == (3 if accepted else 5)), f
+        assert np.all(r.flag == 0)
+
+
+def test_group_angle_limit_uses_the_box_distance():
+    tb, rank, c = _system()
+    r0 = min(rank[1], rank[2])
+    kc = oracle.cell_kc(tb, 0.0)
+    an = _norms(rank, {})
+    lo = np.minimum(A, B)
+    hi = np.maximum(A, B)
+    dg = np.linalg.norm(np.maximum(0.0, np.maximum(lo - _com(), _com() - hi)))
+    for mode, kw in ((0, dict(theta=SIDE / dg)), (1, dict(theta_max=SIDE / dg, tau=1e30))):
+        for f, accepted in ((1 + 1e-3, True), (1 - 1e-3, False)):
+            kw2 = {k: v * f if k in ("theta", "theta_max") else v for k, v in kw.items()}
+            r = oracle.walk_group(tb, 0.0, group=2, mode=mode, kc=kc, anorm=an,
+                                  target_range=(r0, r0 + 2), cap=1 << 40, split=False, **kw2)
+            assert np.all(r.npc == (1 if accepted else 0)), (mode, f)

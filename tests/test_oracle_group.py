@@ -5,6 +5,9 @@ import numpy as np
 import oracle
 from paper_2203_08966_amd import workloads as W
 
+# a work cap no group reaches: every group keeps its group decisions
+NO_CAP = 1 << 40
+
 
 def _tree(n=6000, seed=3, leaf=8, kind="plummer"):
     b = W.plummer(n, seed) if kind == "plummer" else W.clumpy(n, seed, n_clumps=6)
@@ -16,7 +19,7 @@ def test_group_of_one_is_the_per_body_walk():
     accepted cell can contain the body, so this is the walk of Sec. 3."""
     b, bb = _tree()
     for theta in (0.3, 0.5):
-        g = oracle.walk_group(bb, 0.01, group=1, theta=theta)
+        g = oracle.walk_group(bb, 0.01, group=1, theta=theta, cap=NO_CAP, split=False)
         w = oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"], theta, 0.01)
         np.testing.assert_array_equal(g.npp, w.npp)
         np.testing.assert_array_equal(g.npc, w.npc)
@@ -29,7 +32,8 @@ def test_group_of_one_budget_is_the_per_body_budget_walk():
     kc = oracle.cell_kc(bb, 0.01)
     an = np.linalg.norm(oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"],
                                     0.4, 0.01).acc, axis=1)
-    g = oracle.walk_group(bb, 0.01, group=1, mode=1, theta_max=0.9, tau=1e-3, kc=kc, anorm=an)
+    g = oracle.walk_group(bb, 0.01, group=1, mode=1, theta_max=0.9, tau=1e-3, kc=kc, anorm=an,
+                          cap=NO_CAP, split=False)
     w = oracle.walk_kc(bb, 0.01, 0.9, 1e-3, kc, an)
     np.testing.assert_array_equal(g.npp, w.npp)
     np.testing.assert_array_equal(g.npc, w.npc)
@@ -50,7 +54,7 @@ def test_every_body_accounted_once_and_groups_only_tighten():
         return np.sqrt(np.mean(e * e))
     prev = None
     for G in (1, 8, 64):
-        g = oracle.walk_group(bb, 0.01, group=G, theta=0.55, split=False)
+        g = oracle.walk_group(bb, 0.01, group=G, theta=0.55, split=False, cap=NO_CAP)
         assert np.all(g.ncov == n - 1)
         if prev is not None:
             assert np.all(g.npp + g.npc >= 0)
@@ -64,7 +68,7 @@ def test_one_group_holding_everything_is_the_direct_sum():
     """A single group whose box covers every cell opens everything: the
     direct sum, particle-particle only."""
     b, bb = _tree(700, 6)
-    g = oracle.walk_group(bb, 0.02, group=700, theta=0.9, split=False)
+    g = oracle.walk_group(bb, 0.02, group=700, theta=0.9, split=False, cap=NO_CAP)
     d, phi = oracle.direct(bb["spos"], bb["smass"], 0.02)
     assert np.all(g.npc == 0) and np.all(g.npp == 699)
     np.testing.assert_allclose(g.acc, d, rtol=1e-12, atol=1e-14)
@@ -74,13 +78,15 @@ def test_ragged_target_range_and_box_geometry():
     """Groups start at t0; the last one is ragged.  Hand check of one
     decision: a far, light cell against a two-body group box."""
     b, bb = _tree(3000, 7)
-    g_all = oracle.walk_group(bb, 0.01, group=64, theta=0.7)
-    g_sub = oracle.walk_group(bb, 0.01, group=64, theta=0.7, target_range=(128, 1000))
+    g_all = oracle.walk_group(bb, 0.01, group=64, theta=0.7, cap=6144, split=True)
+    g_sub = oracle.walk_group(bb, 0.01, group=64, theta=0.7, target_range=(128, 1000),
+                              cap=6144, split=True)
     # groups [128, 192) ... [896, 960) coincide; [960, 1000) is ragged
     np.testing.assert_array_equal(g_sub.npc[:832], g_all.npc[128:960])
     np.testing.assert_allclose(g_sub.acc[:832], g_all.acc[128:960], rtol=1e-13, atol=0)
     assert np.all(g_sub.ncov == 2999)
-    rag = oracle.walk_group(bb, 0.01, group=40, theta=0.7, target_range=(960, 1000))
+    rag = oracle.walk_group(bb, 0.01, group=40, theta=0.7, target_range=(960, 1000),
+                            cap=6144, split=True)
     np.testing.assert_array_equal(g_sub.npc[832:], rag.npc)
     # group box: bodies at x = 0.1 and 0.3 (y = z = 0.5).  Bodies at
     # (0.8, 0.5, 0.5) and (0.8, 0.7, 0.5) share the level-2 cube
@@ -100,13 +106,18 @@ def test_ragged_target_range_and_box_geometry():
     assert abs(rank[0] - rank[1]) == 1
     lim = 0.25 / np.sqrt(0.26)
     for theta, accepted in ((lim * 1.001, True), (lim * 0.999, False)):
-        r = oracle.walk_group(tb, 0.0, group=2, theta=theta, target_range=(r0, r0 + 2))
+        r = oracle.walk_group(tb, 0.0, group=2, theta=theta, target_range=(r0, r0 + 2),
+                              cap=NO_CAP, split=True)
         assert np.all(r.ncov == 5)
         assert np.all(r.npc == (1 if accepted else 0))
         assert np.all(r.npp == (3 if accepted else 5))
-        # the box lies on the plane y = 0.5, a face of cubes it is tested
-        # against: flagged as a decision reduced precision may take otherwise
-        assert np.all(r.flag == 1)
+        # the box lies on the plane y = 0.5, a face of the cube tested, but
+        # the x axis separates them by far: no decision is near a threshold
+        assert np.all(r.flag == 0)
+    # within a relative 1e-5 of the angle threshold the group is flagged
+    r = oracle.walk_group(tb, 0.0, group=2, theta=lim * (1 + 1e-7), target_range=(r0, r0 + 2),
+                          cap=NO_CAP, split=True)
+    assert np.all(r.flag == 1)
 
 
 def test_work_cap_falls_back_to_the_per_body_walk():
@@ -126,9 +137,6 @@ def test_work_cap_falls_back_to_the_per_body_walk():
     np.testing.assert_array_equal(gb.npp, wb.npp)
     np.testing.assert_allclose(gb.acc, wb.acc, rtol=1e-13, atol=0)
     big = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False, cap=1 << 62)
-    dflt = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False)
-    capd = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False, cap=oracle.GROUP_WORK_CAP[0])
-    np.testing.assert_array_equal(dflt.npc, capd.npc)
     # the cap splits groups by their work: each group either keeps the group
     # walk or takes the per-body counts
     mid = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False, cap=3000)
@@ -178,8 +186,8 @@ def test_split_cuts_a_straddling_group_at_the_jump():
     lv = oracle.leaf_levels(bb)
     assert lv[ra].min() >= 5 and lv[rc].min() >= 5           # deep leaves
     g0 = ra[0]
-    kw = dict(group=16, theta=0.6)
-    sp = oracle.walk_group(bb, 0.0, target_range=(g0, g0 + 16), **kw)
+    kw = dict(group=16, theta=0.6, cap=NO_CAP)
+    sp = oracle.walk_group(bb, 0.0, target_range=(g0, g0 + 16), split=True, **kw)
     nosp = oracle.walk_group(bb, 0.0, target_range=(g0, g0 + 16), split=False, **kw)
     h1 = oracle.walk_group(bb, 0.0, target_range=(g0, g0 + 8), split=False, **kw)
     h2 = oracle.walk_group(bb, 0.0, target_range=(g0 + 8, g0 + 16), split=False, **kw)
@@ -188,5 +196,5 @@ def test_split_cuts_a_straddling_group_at_the_jump():
     np.testing.assert_allclose(sp.acc, np.concatenate([h1.acc, h2.acc]), rtol=1e-14, atol=0)
     assert (sp.npp + sp.npc).sum() < (nosp.npp + nosp.npc).sum()
     # one cluster as its own group: no cut
-    one = oracle.walk_group(bb, 0.0, target_range=(g0, g0 + 8), **kw)
+    one = oracle.walk_group(bb, 0.0, target_range=(g0, g0 + 8), split=True, **kw)
     np.testing.assert_array_equal(one.npc, h1.npc)

@@ -14,12 +14,14 @@ over a seeded 4096-body subsample:
   body-theta-guard  the same with a containment guard: a cell whose cube
                 holds the body is opened whatever its angle (a variant);
   group-theta   one opening-angle decision per wavefront of 64 bodies;
-  group-budget  one error-budget decision per wavefront (k_C = 1 error
-                model, tau times the group's smallest |a|, each |a_i|
-                floored at half the mean |a|);
-  group-learned the same with k_C per cell from the network, trained first
-                on the library's own FP64 simulations of small Plummer
-                spheres.
+  group-budget  one error-budget decision per wavefront (error model
+                M l^3 / d_g^5 against tau times the group's smallest |a|,
+                each |a_i| floored at half the mean |a|);
+  group-learned one learned decision per wavefront and cell: the network's
+                predicted error of the particle-cell term on the group
+                against the same budget (bf16 MFMA inside the walk),
+                trained first on the library's own FP64 simulations of
+                Plummer spheres.
 Each is swept over its parameter grid from accurate to cheap; the cheapest
 grid value with rms <= 1e-3 is kept, and the method with the fastest walk
 at that value is the one timed.  After the timed steps the rms error is

@@ -69,8 +69,10 @@ enum { BH_GROUP_BODIES = 64 };
 /* Acceptance criterion used by the walk. */
 enum {
     BH_MAC_THETA = 0,  /* side/distance < theta (Sec. 3) */
-    BH_MAC_MLP = 1,    /* learned: predicted error k_C (l/d)^3 M/d^2 < tau |a_i| */
-    BH_MAC_BUDGET = 2, /* the same error budget with k_C = 1 (no network) */
+    BH_MAC_MLP = 1,    /* learned: the network's predicted error of the
+                          particle-cell term below tau |a_i| (per group and
+                          cell; see bh_mlp_set) */
+    BH_MAC_BUDGET = 2, /* error budget: M l^3 / d^5 < tau |a_i| (no network) */
     BH_MAC_THETA_GUARD = 3 /* side/distance < theta and the body outside the
                               cell's closed cube (a containment guard; not in
                               the paper; BH_WALK_BODY only).  Below theta =
@@ -88,7 +90,10 @@ typedef struct bh_tree bh_tree;
 
 /* Options of a force evaluation.  Fill with bh_force_opts_default first. */
 typedef struct {
-    int order;        /* 0: monopole only; 2: monopole + quadrupole (default) */
+    int order;        /* 0: monopole only; 2: monopole + quadrupole (default);
+                         3: and the octopole, the l = 3 term of Sec. 2.2
+                         (BH_MAC_THETA only; its moments are computed from
+                         the tree on the first order-3 walk of a build) */
     int mac;          /* BH_MAC_THETA (default), BH_MAC_MLP, BH_MAC_BUDGET or
                          BH_MAC_THETA_GUARD */
     void *phi;        /* optional device out, N values in caller order: the
@@ -98,13 +103,15 @@ typedef struct {
     int64_t target_begin; /* walk only bodies of sorted rank [begin, end); */
     int64_t target_end;   /* end <= 0 means all.  Outputs of other bodies are
                              left untouched. */
-    /* BH_MAC_MLP / BH_MAC_BUDGET (FP32 quadrupole walk only): accept a
-     * multi-body cell iff side/d < mlp_theta_max, the body is outside it,
-     * and k_C M side^3 < 10^mlp_log10_tau |a_i| d^5 (k_C from the loaded
-     * network per cell, or 1).  |a_i| comes from mlp_acc_norm (device, n
-     * norms in the tree's dtype, caller order) or, if NULL, from a monopole
-     * walk at mlp_theta_est run first (a simulation step uses the previous
- * step's accelerations instead). */
+    /* BH_MAC_BUDGET (FP32 quadrupole walk only): accept a multi-body cell
+     * iff side/d < mlp_theta_max, the body is outside it, and
+     * M side^3 < 10^mlp_log10_tau |a_i| d^5 (per group: d_g and the
+     * smallest |a_i|).  BH_MAC_MLP: the learned decision described with
+     * bh_mlp_set, with tau = 10^mlp_log10_tau; with no network loaded the
+     * walk takes the opening-angle test at theta instead.  |a_i| comes from
+     * mlp_acc_norm (device, n norms in the tree's dtype, caller order) or,
+     * if NULL, from a monopole walk at mlp_theta_est run first (a
+     * simulation step uses the previous step's accelerations instead). */
     double mlp_theta_max;     /* default 1.0 */
     double mlp_log10_tau;     /* default -3 */
     const void *mlp_acc_norm; /* default NULL */
@@ -313,18 +320,27 @@ int bh_standard_units(bh_ctx *ctx, void *pos, void *vel, void *mass, int dtype, 
  * Learned acceptance criterion (not in the paper; it stands in for the
  * opening-angle test of Sec. 3).
  *
- * The error of a cell's quadrupole particle-cell term on body i is modelled
- * as k_C (l/d)^3 M/d^2.  A network 10 -> 32 (ReLU) -> 32 (ReLU) -> 1
- * predicts log10 k_C from the cell alone; it is evaluated once per cell
- * (bf16 or fp16 MFMA, 64 cells per wavefront) and the walk accepts as
- * described at bh_force_opts.  Parameters (BH_MLP_PARAMS doubles, host):
+ * One decision per (group, cell): a network 10 -> 32 (ReLU) -> 32 (ReLU)
+ * -> 1 predicts log10 of the largest error the cell's quadrupole
+ * particle-cell term makes on the group's bodies, in units of the error
+ * budget's model M side^3 / d_g^5 (d_g: distance from the cell's COM to the
+ * box): a coefficient k_C per group and cell.  The walk accepts the cell
+ * for the whole group iff its cube misses the box, side < mlp_theta_max d_g,
+ * and
+ *     pred + log10(M side^3 / d_g^5) < log10(tau a_min),
+ * a_min the group's smallest (floored) |a_i|; a group walked per body takes
+ * the same decision with each body as its own group (box of zero extent),
+ * and so does BH_WALK_BODY.  Inside the walk the network runs on MFMA
+ * (bf16, or fp16 with BH_MLP_FP16; FP32 sums), one 64-row batch per round of
+ * candidate cells, one per lane.  Parameters (BH_MLP_PARAMS doubles, host):
  * W1[32][10] b1[32] W2[32][32] b2[32] w3[32] b3, held on the device as FP32
- * master weights with Adam state and packed to bf16 and fp16 operands for
- * inference.
- * Cell features (l side, g = COM - centre, M mass, n count,
- * T2 = sum m |y|^2 about the COM, Q traceless quadrupole):
- * |g|/l, sqrt(T2/M)/l, |Q|_F/(M l^2), cbrt(det Q)/(M l^2), max|g_a|/l,
- * log2(n)/21, leaf (0/1), eps/l, 1/sqrt(n), T2/(M l^2).
+ * master weights with Adam state and packed to bf16 and fp16 operands.
+ * Features (l side, d_c distance from the COM to the box centre, h the
+ * box's half-diagonal, n the unit vector from the box centre to the COM,
+ * g = COM - cell centre, Q the traceless quadrupole):
+ * log2(l/d_g) in [-8, 8], min(log2(d_c/d_g), 8), h/(h + d_g),
+ * n.Q.n/(M l^2), |Q|_F/(M l^2), g.n/l, |g|/l, log2(count)/21,
+ * min(eps/d_g, 1), leaf (0/1).
  * ------------------------------------------------------------------- */
 #define BH_MLP_PARAMS 1441
 
@@ -333,19 +349,22 @@ int bh_mlp_set(bh_ctx *ctx, const double *params);
 /* Copy the current FP32 parameters to host doubles. */
 int bh_mlp_get(bh_ctx *ctx, double *params);
 
-/* Training pairs from a BH_F64 tree: for every body a walk at theta_lo;
- * every multi-body cell with theta_lo <= side/d < theta_max that does not
- * contain the body is a candidate, kept iff the SplitMix64 hash of
- * (seed ^ (rank << 32 | node)) >> 11 is below keep * 2^53.  Kept pairs are
- * written densely, by body rank then pre-order: feat (device f32, the
- * cell's 10 features), label (device f32: log10(|a_pc - a_exact| d^5 /
- * (M l^3)) with a_exact the direct sum over the cell's bodies, FP64,
- * floored at 1e-12 inside), node and body rank (device i32).  *total gets
- * the number of kept pairs; with feat == NULL only *total is computed.
+/* Training pairs from a BH_F64 tree: the bodies in sorted order form
+ * groups of BH_GROUP_BODIES; each group walks the tree leaving alone the
+ * cells whose cube misses its box with side < theta_lo d_g and opening all
+ * others; every multi-body cell whose cube misses the box with
+ * theta_lo d_g <= side < theta_max d_g is a candidate, kept iff the
+ * SplitMix64 hash of (seed ^ (first rank << 32 | node)) >> 11 is below
+ * keep * 2^53.  Kept pairs are written densely, by group then pre-order:
+ * feat (device f32, the pair's 10 features), label (device f32:
+ * log10(max_i |a_pc,i - a_exact,i| d_g^5 / (M side^3)) over the group's bodies with
+ * a_exact the direct sum over the cell's bodies, FP64, floored at 1e-12
+ * inside), node and the group's first sorted rank (device i32).  *total
+ * gets the number of kept pairs; with feat == NULL only *total is computed.
  * BH_E_INVALID if capacity < *total.  Synchronous. */
 int bh_mlp_samples(bh_tree *tree, double eps, double theta_lo, double theta_max, double keep,
                    uint64_t seed, int64_t capacity, float *feat, float *label, int32_t *node,
-                   int32_t *body, int64_t *total);
+                   int32_t *group, int64_t *total);
 
 typedef struct {
     int epochs;        /* passes over the set */

@@ -66,7 +66,8 @@ def _load():
     lib.orc_walk.argtypes = [C.c_int64, _i32, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
                              C.c_double, C.c_double, C.c_double, C.c_int, C.c_int64, _i64,
                              _f64, _f64, _i64, _i64, _i64, _i32, C.c_void_p, C.c_void_p,
-                             C.c_int, C.c_double]
+                             C.c_int, C.c_double, C.c_void_p]
+    lib.orc_octopole.argtypes = [C.c_int64, _i32, _i32, _f64, _f64, _f64, _f64]
     _lib = lib
     return lib
 
@@ -173,13 +174,32 @@ class WalkResult(tuple):
             raise AttributeError(name) from None
 
 
+def octopole(b):
+    """Octopole moments per cell (n_cells x 10: xxx xxy xxz xyy xyz xzz yyy
+    yyz yzz zzz), symmetric and traceless, about the COM; cached in b."""
+    if "oct" not in b:
+        t = b["tree"]
+        com = b["mom"][1]
+        m = com.shape[0]
+        O = np.zeros((m, 10))
+        _load().orc_octopole(m, t["begin"], t["count"], _pos64(b["spos"]).ravel(),
+                             np.ascontiguousarray(b["smass"], dtype=np.float64), com.ravel(),
+                             O.ravel())
+        b["oct"] = O
+    return b["oct"]
+
+
 def walk(tree, mom, spos, smass, L, theta, eps, order=2, targets=None, guard_lo=None,
-         tol=1e-5):
+         tol=1e-5, oct=None):
     """Per-body tree walk over sorted bodies; ``targets`` are sorted ranks.
     ``guard_lo``: the root cube's corner, to open every cell whose cube holds
     the body (the containment guard, a variant); None: the paper's test.
     ``tol``: a body is flagged when an opening-angle test it takes lies
-    within this relative margin of its threshold."""
+    within this relative margin of its threshold.  ``order`` 0 (monopole), 2
+    (with the quadrupole) or 3 (and the octopole: ``oct`` from
+    ``octopole``)."""
+    if order >= 3 and oct is None:
+        raise ValueError("order 3 needs the octopole moments (oct=octopole(b))")
     lib = _load()
     M, com, Q = mom
     p = _pos64(spos)
@@ -199,7 +219,8 @@ def walk(tree, mom, spos, smass, L, theta, eps, order=2, targets=None, guard_lo=
                  M, com.ravel(), Q.ravel(), p.ravel(), ms, float(L), float(theta), float(eps),
                  int(order), nt, t, acc.ravel(), phi, npp, npc, ncov, flag,
                  hk.ctypes.data, None if lo is None else lo.ctypes.data,
-                 0 if lo is None else 1, float(tol))
+                 0 if lo is None else 1, float(tol),
+                 None if oct is None else np.ascontiguousarray(oct).ctypes.data)
     return WalkResult(acc, phi, npp, npc, ncov, flag)
 
 
@@ -228,7 +249,8 @@ def barnes_hut(pos, mass, theta, eps, leaf_size, order=2, targets=None, built=No
     rank = np.empty(n, dtype=np.int64)
     rank[b["perm"]] = np.arange(n, dtype=np.int64)
     t = np.arange(n, dtype=np.int64) if targets is None else np.asarray(targets, dtype=np.int64)
-    return walk(b["tree"], b["mom"], b["spos"], b["smass"], b["L"], theta, eps, order, rank[t])
+    return walk(b["tree"], b["mom"], b["spos"], b["smass"], b["L"], theta, eps, order, rank[t],
+                oct=octopole(b) if order >= 3 else None)
 
 
 def energy(pos, vel, mass, eps):
@@ -289,8 +311,6 @@ def rms_rel(acc, ref):
 
 # ------------------------------------------------------------------ learned criterion
 def _mac_sigs(lib):
-    lib.orc_cell_features.argtypes = [_f64, C.c_double, _f64, C.c_double, _f64, C.c_double,
-                                      C.c_int, C.c_int, C.c_double, _f64]
     lib.orc_splitmix64.argtypes = [C.c_uint64]
     lib.orc_splitmix64.restype = C.c_uint64
     lib.orc_mlp_bf16.argtypes = [_f64, _f64]
@@ -299,23 +319,19 @@ def _mac_sigs(lib):
     lib.orc_mlp_f16.restype = C.c_double
     lib.orc_f16r.argtypes = [C.c_double]
     lib.orc_f16r.restype = C.c_double
-    lib.orc_mac_samples.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
-                                    _f64, _f64, C.c_double, C.c_double, C.c_double, C.c_double,
-                                    C.c_double, C.c_uint64, C.c_int64, _i64, C.c_int64, _f64,
-                                    _f64, _i32, _i64]
-    lib.orc_cell_kc.argtypes = [C.c_int64, _i32, _u64, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
-                                C.c_double, C.c_double, C.c_void_p, C.c_int, _f64]
+    lib.orc_cell_kc.argtypes = [C.c_int64, _i32, _f64, C.c_double, _f64]
     lib.orc_walk_kc.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64, _f64,
                                 C.c_double, C.c_double, C.c_double, C.c_double, _f64, _f64,
                                 C.c_int64, _i64, _f64, _f64, _i64, _i64, _i64, _i32]
     lib.orc_walk_group.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
                                    _f64, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
                                    C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
-                                   C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_double, _u64,
-                                   _i32, C.c_int, _f64, _f64, _i64, _i64, _i64, _i32]
+                                   C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
+                                   C.c_double, _u64,
+                                   _i32, C.c_int, _f64, _f64, _i64, _i64, _i64, _i32, C.c_void_p]
     lib.orc_gfeatures.argtypes = [_f64, _f64, _f64, C.c_double, _f64, C.c_double, _f64, C.c_int,
                                   C.c_int, C.c_double, _f64]
-    lib.orc_gnet_bound.argtypes = [_f64, _f64, C.POINTER(C.c_double)]
+    lib.orc_gnet_bound.argtypes = [_f64, _f64, C.POINTER(C.c_double), C.c_int]
     lib.orc_gnet_bound.restype = C.c_double
     lib.orc_group_samples.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64,
                                       _f64, _f64, C.c_double, C.c_int64, C.c_int64, C.c_double,
@@ -330,15 +346,6 @@ def _mlib():
         _mac_sigs(lib)
         lib._mac_ready = True
     return lib
-
-
-def cell_features(centre, side, com, M, Q, trT, count, is_leaf, eps):
-    f = np.zeros(10)
-    _mlib().orc_cell_features(np.ascontiguousarray(centre, dtype=np.float64), float(side),
-                              np.ascontiguousarray(com, dtype=np.float64), float(M),
-                              np.ascontiguousarray(Q, dtype=np.float64), float(trT), int(count),
-                              int(is_leaf), float(eps), f)
-    return f
 
 
 def splitmix64(x: int) -> int:
@@ -361,41 +368,14 @@ def f16r(x: float) -> float:
     return float(_mlib().orc_f16r(float(x)))
 
 
-def mac_samples(b, eps, theta_lo, theta_max, keep, seed, targets=None, cap=4096):
-    """Training pairs of the bodies ``targets`` (sorted ranks; all by
-    default) over a tree from build_all: per target up to ``cap`` kept
-    candidates in pre-order.  Returns (feat (nt, cap, 10) cell features,
-    label (nt, cap), node, count)."""
+def cell_kc(b):
+    """Per cell M l^3: the error budget's coefficient k_C M l^3 with
+    k_C = 1."""
     lib = _mlib()
     t = b["tree"]
-    M, com, Q = b["mom"]
-    n = b["smass"].shape[0]
-    tg = np.arange(n, dtype=np.int64) if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
-    nt = tg.shape[0]
-    feat = np.zeros((nt, cap, 10))
-    label = np.zeros((nt, cap))
-    node = np.full((nt, cap), -1, dtype=np.int32)
-    cnt = np.zeros(nt, dtype=np.int64)
-    lib.orc_mac_samples(t["level"], t["hkey"], t["begin"], t["count"], t["next"], M, com.ravel(),
-                        Q.ravel(), b["trT"], b["spos"].ravel(), b["smass"],
-                        np.ascontiguousarray(b["lo"]), float(b["L"]), float(eps), float(theta_lo),
-                        float(theta_max), float(keep), int(seed), nt, tg, int(cap), feat.ravel(),
-                        label.ravel(), node.ravel(), cnt)
-    return feat, label, node, cnt
-
-
-def cell_kc(b, eps, params=None, f16=False):
-    """Per cell k_C M l^3 (k_C = 1 without a network; the network's operands
-    in bf16, or fp16 with ``f16``)."""
-    lib = _mlib()
-    t = b["tree"]
-    M, com, Q = b["mom"]
-    m = M.shape[0]
-    kc = np.zeros(m)
-    pp = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
-    lib.orc_cell_kc(m, t["level"], t["hkey"], t["count"], t["next"], M, com.ravel(), Q.ravel(),
-                    b["trT"], np.ascontiguousarray(b["lo"]), float(b["L"]), float(eps),
-                    None if pp is None else pp.ctypes.data, 1 if f16 else 0, kc)
+    M = b["mom"][0]
+    kc = np.zeros(M.shape[0])
+    lib.orc_cell_kc(M.shape[0], t["level"], M, float(b["L"]), kc)
     return kc
 
 
@@ -411,8 +391,8 @@ def floored_norms(anorm, floor):
 
 
 def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None, floor=0.0):
-    """Walk with the learned (or, k_C = 1, relative) criterion; anorm is
-    |a_i| per sorted rank, floored by ``floored_norms``."""
+    """Walk with the error budget (kc from ``cell_kc``); anorm is |a_i| per
+    sorted rank, floored by ``floored_norms``."""
     anorm = floored_norms(anorm, floor)
     lib = _mlib()
     t = b["tree"]
@@ -452,8 +432,8 @@ def leaf_levels(b):
 
 
 def walk_group(b, eps, *, cap, split, group=64, mode=0, theta=0.5, theta_max=1.0, tau=1e-3,
-               kc=None, anorm=None, params=None, order=2, target_range=None, tol=1e-5,
-               floor=0.0):
+               kc=None, anorm=None, params=None, f16=False, order=2, target_range=None,
+               tol=1e-5, floor=0.0):
     """Walk with one acceptance decision per group of ``group`` consecutive
     sorted ranks in ``target_range`` (all bodies by default): mode 0 opening
     angle, mode 1 error budget (kc per cell, anorm per sorted rank), mode 2
@@ -491,10 +471,11 @@ def walk_group(b, eps, *, cap, split, group=64, mode=0, theta=0.5, theta_max=1.0
                            int(mode), float(theta), float(theta_max), float(tau),
                            None if kcv is None else kcv.ctypes.data,
                            None if anv is None else anv.ctypes.data,
-                           None if pv is None else pv.ctypes.data, int(group), t0, t1,
+                           None if pv is None else pv.ctypes.data, 1 if f16 else 0, int(group),
+                           t0, t1,
                            int(cap), float(tol), np.ascontiguousarray(b["keys"], dtype=np.uint64),
                            leaf_levels(b), 1 if split else 0, acc.ravel(), phi, npp, npc, ncov,
-                           flag)
+                           flag, octopole(b).ctypes.data if order >= 3 else None)
     return WalkResult(acc, phi, npp, npc, ncov, flag)
 
 
@@ -511,11 +492,13 @@ def gfeatures(box_lo, box_hi, centre, side, com, M, Q, count, is_leaf, eps):
     return f
 
 
-def gnet_bound(params, f):
-    """(prediction, bound on the move of a reduced-precision evaluation)."""
+def gnet_bound(params, f, f16=False):
+    """(prediction, bound on the move of a reduced-precision evaluation) of
+    the network with bf16 (or fp16) operands."""
     d = C.c_double()
     out = _mlib().orc_gnet_bound(np.ascontiguousarray(params, dtype=np.float64),
-                                 np.ascontiguousarray(f, dtype=np.float64), C.byref(d))
+                                 np.ascontiguousarray(f, dtype=np.float64), C.byref(d),
+                                 1 if f16 else 0)
     return float(out), d.value
 
 

@@ -306,6 +306,39 @@ void orc_moments(int64_t m, const int32_t *level, const uint64_t *hkey, const in
 }
 
 /* ------------------------------------------------------------------------
+ * Octopole moments (Sec. 2.2: the next term of the multipole expansion,
+ * l = 3), per cell directly from its bodies about its COM:
+ *   O_abc = sum m (15 y_a y_b y_c - 3 |y|^2 (y_a d_bc + y_b d_ac + y_c d_ab)),
+ * symmetric and traceless (10 components: xxx xxy xxz xyy xyz xzz yyy yyz
+ * yzz zzz).  Its potential at x (from the COM) is -O:xxx / (6 r^7), the
+ * Legendre term P_3 of 1/|x - y| summed over the bodies.
+ * ---------------------------------------------------------------------- */
+void orc_octopole(int64_t m, const int32_t *begin, const int32_t *count, const double *spos,
+                  const double *smass, const double *com, double *O)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t c = 0; c < m; ++c) {
+        double o[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t j = begin[c]; j < begin[c] + count[c]; ++j) {
+            const double y[3] = {spos[3 * j] - com[3 * c], spos[3 * j + 1] - com[3 * c + 1],
+                                 spos[3 * j + 2] - com[3 * c + 2]};
+            const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+            static const int ia[10] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 2};
+            static const int ib[10] = {0, 0, 0, 1, 1, 2, 1, 1, 2, 2};
+            static const int ic[10] = {0, 1, 2, 1, 2, 2, 1, 2, 2, 2};
+            for (int k = 0; k < 10; ++k) {
+                const int a = ia[k], b = ib[k], cc = ic[k];
+                const double tr = (b == cc ? y[a] : 0.0) + (a == cc ? y[b] : 0.0) +
+                                  (a == b ? y[cc] : 0.0);
+                o[k] += smass[j] * (15.0 * y[a] * y[b] * y[cc] - 3.0 * r2 * tr);
+            }
+        }
+        for (int k = 0; k < 10; ++k)
+            O[10 * c + k] = o[k];
+    }
+}
+
+/* ------------------------------------------------------------------------
  * Tree walk (Sec. 3, "Compute Cell Force" of the Barnes-Hut loop body).
  *
  * For body i, start at the root and, for each child C of the current node in
@@ -351,6 +384,8 @@ typedef struct {
     /* relative margin of the opening-angle test inside which reduced
      * precision may decide either way (flags the body); 0 means 1e-5 */
     double tol;
+    /* order 3: octopole moments per cell (10 each), else NULL */
+    const double *O;
 } walk_ctx;
 
 static void cell_centre(uint64_t hkey, int k, const double *lo, double L, double c[3]);
@@ -430,6 +465,23 @@ static void pc(const walk_ctx *w, int64_t i, int64_t c, const double x[3], doubl
         r->a[2] += qz * inv5 - 2.5 * xqx * x[2] * inv7;
         r->phi -= 0.5 * xqx * inv5;
     }
+    if (w->order >= 3) {
+        /* a = (O:xx) / (2 s^7) - 7 (O:xxx) x / (6 s^9), the gradient of
+         * O:xxx / (6 s^7) */
+        const double *o = &w->O[10 * c];
+        const double xx = x[0] * x[0], yy = x[1] * x[1], zz = x[2] * x[2];
+        const double xy = x[0] * x[1], xz = x[0] * x[2], yz = x[1] * x[2];
+        const double vx = o[0] * xx + o[3] * yy + o[5] * zz + 2.0 * (o[1] * xy + o[2] * xz + o[4] * yz);
+        const double vy = o[1] * xx + o[6] * yy + o[8] * zz + 2.0 * (o[3] * xy + o[4] * xz + o[7] * yz);
+        const double vz = o[2] * xx + o[7] * yy + o[9] * zz + 2.0 * (o[4] * xy + o[5] * xz + o[8] * yz);
+        const double t3 = x[0] * vx + x[1] * vy + x[2] * vz;
+        const double inv7 = inv3 * inv2 * inv2;
+        const double inv9 = inv7 * inv2;
+        r->a[0] += 0.5 * vx * inv7 - (7.0 / 6.0) * t3 * x[0] * inv9;
+        r->a[1] += 0.5 * vy * inv7 - (7.0 / 6.0) * t3 * x[1] * inv9;
+        r->a[2] += 0.5 * vz * inv7 - (7.0 / 6.0) * t3 * x[2] * inv9;
+        r->phi -= t3 * inv7 / 6.0;
+    }
     (void)i;
     r->npc += 1;
     r->ncov += w->count[c];
@@ -486,10 +538,10 @@ void orc_walk(int64_t m, const int32_t *level, const int32_t *begin, const int32
               const double *spos, const double *smass, double L, double theta, double eps,
               int order, int64_t nt, const int64_t *targets, double *acc, double *phi,
               int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag, const uint64_t *hkey,
-              const double *lo, int guard, double tol)
+              const double *lo, int guard, double tol, const double *O)
 {
     walk_ctx w = {level, begin, count, next, M, com, Q, spos, smass,
-                  L, theta * theta, eps * eps, order, hkey, lo, guard, tol};
+                  L, theta * theta, eps * eps, order, hkey, lo, guard, tol, O};
     (void)m;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nt; ++t) {
@@ -511,24 +563,14 @@ void orc_walk(int64_t m, const int32_t *level, const int32_t *begin, const int32
 }
 
 /* ========================================================================
- * Learned acceptance criterion.
+ * Network helpers and the error budget.
  *
- * The error a cell's particle-cell term (order 2) makes on body i is
- * modelled as |da| = k_C (l/d)^3 M/d^2 with a per-cell coefficient k_C that
- * a network predicts from the cell alone (log10 k_C); the walk accepts the
- * cell iff l^2 < theta_max^2 d^2 and k_C M l^3 < tau |a_i| d^5, i.e. iff the
- * predicted error is below tau times the body's acceleration.  With k_C = 1
- * this is a relative opening criterion; the network refines k_C from the
- * cell's mass distribution.
- *
- * Cell features (scale-free; l side, g = COM - centre, M mass, n count,
- * T2 = sum m |y|^2 about the COM, Q traceless quadrupole):
- *   f0 |g|/l              f1 sqrt(T2/M)/l          f2 |Q|_F/(M l^2)
- *   f3 cbrt(det Q)/(M l^2)  f4 max_a |g_a|/l      f5 log2(n)/21
- *   f6 1 if leaf           f7 eps/l                f8 1/sqrt(n)
- *   f9 T2/(M l^2)
- * Label of a (body, cell) pair: log10(|a_pc - a_exact| d^5 / (M l^3)),
- * a_exact the direct sum over the cell's bodies, floored at -12 inside.
+ * The error budget accepts a multi-body cell for body i iff
+ * l^2 < theta_max^2 d^2, the body lies outside the cell, and
+ * M l^3 < tau |a_i| d^5 (the quadrupole term's error taken as
+ * (l/d)^3 M/d^2, the next order of the expansion of Sec. 2.2).  The
+ * network helpers evaluate the learned criterion's network with bf16 or
+ * fp16 operands as the MFMA inference does (see the learned section below).
  * ====================================================================== */
 
 /* cell centre from the hashed key */
@@ -548,36 +590,6 @@ static void cell_centre(uint64_t hkey, int k, const double *lo, double L, double
     c[2] = lo[2] + (iz + 0.5) * side;
 }
 
-void orc_cell_features(const double *centre, double side, const double *com, double M,
-                       const double *Q, double trT, int count, int is_leaf, double eps, double *f)
-{
-    double g[3], gmax = 0.0;
-    for (int a = 0; a < 3; ++a) {
-        g[a] = com[a] - centre[a];
-        if (fabs(g[a]) > gmax)
-            gmax = fabs(g[a]);
-    }
-    const double ml2 = M * side * side;
-    const double q[3][3] = {{Q[0], Q[1], Q[2]}, {Q[1], Q[3], Q[4]}, {Q[2], Q[4], Q[5]}};
-    double qf = 0.0;
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-            qf += q[a][b] * q[a][b];
-    const double det = q[0][0] * (q[1][1] * q[2][2] - q[1][2] * q[2][1]) -
-                       q[0][1] * (q[1][0] * q[2][2] - q[1][2] * q[2][0]) +
-                       q[0][2] * (q[1][0] * q[2][1] - q[1][1] * q[2][0]);
-    f[0] = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / side;
-    f[1] = M > 0.0 ? sqrt(trT / M) / side : 0.0;
-    f[2] = ml2 > 0.0 ? sqrt(qf) / ml2 : 0.0;
-    f[3] = ml2 > 0.0 ? cbrt(det) / ml2 : 0.0;
-    f[4] = gmax / side;
-    f[5] = log2((double)count) / 21.0;
-    f[6] = is_leaf ? 1.0 : 0.0;
-    f[7] = eps / side;
-    f[8] = 1.0 / sqrt((double)count);
-    f[9] = ml2 > 0.0 ? trT / ml2 : 0.0;
-}
-
 /* SplitMix64 (Steele, Lea & Flood 2014): the finaliser applied to x. */
 uint64_t orc_splitmix64(uint64_t x)
 {
@@ -587,7 +599,7 @@ uint64_t orc_splitmix64(uint64_t x)
     return z ^ (z >> 31);
 }
 
-/* keep a candidate (body rank i, node c) with probability p */
+/* keep a candidate (hash key i, node c) with probability p */
 static int keep_pair(uint64_t seed, int64_t i, int64_t c, double p)
 {
     const uint64_t h = orc_splitmix64(seed ^ (((uint64_t)i << 32) | (uint64_t)(uint32_t)c));
@@ -664,135 +676,18 @@ double orc_f16r(double x) { return f16r(x); }
 typedef struct {
     walk_ctx w;
     const uint64_t *hkey;
-    const double *lo, *trT;
-    double tlo2, tmax2, eps;
-    /* samples */
-    uint64_t seed;
-    double keep;
-    int64_t cap, slot0;
-    double *feat, *label;
-    int32_t *node;
-    /* learned decision */
-    const double *kc;  /* per cell k_C M l^3 */
+    const double *lo;
+    double tmax2;
+    const double *kc;  /* per cell M l^3 */
     double tau, anorm; /* tau and |a_i| of the current body */
 } mac_ctx;
 
-static void features_of(const mac_ctx *m, int64_t c, double *f)
+/* Per cell: M l^3, the error budget's k_C M l^3 with k_C = 1. */
+void orc_cell_kc(int64_t m, const int32_t *level, const double *M, double L, double *kc)
 {
-    const walk_ctx *w = &m->w;
-    double centre[3];
-    cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
-    orc_cell_features(centre, ldexp(w->L, -w->level[c]), &w->com[3 * c], w->M[c], &w->Q[6 * c],
-                      m->trT[c], w->count[c], w->next[c] == c + 1, m->eps, f);
-}
-
-static void pair_label(const mac_ctx *m, int64_t i, int64_t c, const double x[3], double d2,
-                       double *lab)
-{
-    const walk_ctx *w = &m->w;
-    walk_acc ex, ap;
-    memset(&ex, 0, sizeof(ex));
-    memset(&ap, 0, sizeof(ap));
-    leaf_pp(w, i, c, &ex);
-    pc(w, i, c, x, d2, &ap);
-    const double e0 = ap.a[0] - ex.a[0], e1 = ap.a[1] - ex.a[1], e2 = ap.a[2] - ex.a[2];
-    const double side = ldexp(w->L, -w->level[c]);
-    const double d = sqrt(d2);
-    double v = sqrt(e0 * e0 + e1 * e1 + e2 * e2) * d2 * d2 * d / (w->M[c] * side * side * side);
-    if (!(v > 1e-12))
-        v = 1e-12;
-    *lab = log10(v);
-}
-
-/* Candidates of body i: walk at theta_lo (cells with l/d < theta_lo are
- * left alone, all others opened); every multi-body cell with
- * theta_lo <= l/d < theta_max that does not contain the body is a
- * candidate, kept by the hash. */
-static void sample_walk(mac_ctx *m, int64_t node, int64_t i, int64_t *k)
-{
-    const walk_ctx *w = &m->w;
-    for (int64_t c = node + 1; c < w->next[node]; c = w->next[c]) {
-        if (w->count[c] == 1)
-            continue;
-        const double side = ldexp(w->L, -w->level[c]);
-        double x[3];
-        for (int d = 0; d < 3; ++d)
-            x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
-        const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-        if (side * side < m->tlo2 * d2)
-            continue;
-        if (side * side < m->tmax2 * d2) {
-            double centre[3];
-            cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
-            if (!inside_cell(&w->spos[3 * i], centre, side) && keep_pair(m->seed, i, c, m->keep) &&
-                *k < m->cap) {
-                const int64_t o = m->slot0 + *k;
-                features_of(m, c, &m->feat[10 * o]);
-                pair_label(m, i, c, x, d2, &m->label[o]);
-                m->node[o] = (int32_t)c;
-                ++*k;
-            }
-        }
-        if (w->next[c] != c + 1)
-            sample_walk(m, c, i, k);
-    }
-}
-
-/* Per target rank t (targets are sorted ranks): up to cap kept candidates in
- * pre-order at slot t*cap.. of feat (10 cell features each), label, node;
- * count[t]. */
-void orc_mac_samples(const int32_t *level, const uint64_t *hkey, const int32_t *begin,
-                     const int32_t *count, const int32_t *next, const double *M,
-                     const double *com, const double *Q, const double *trT, const double *spos,
-                     const double *smass, const double *lo, double L, double eps,
-                     double theta_lo, double theta_max, double keep, uint64_t seed, int64_t nt,
-                     const int64_t *targets, int64_t cap, double *feat, double *label,
-                     int32_t *node, int64_t *cnt)
-{
-#pragma omp parallel for schedule(dynamic, 4)
-    for (int64_t t = 0; t < nt; ++t) {
-        mac_ctx m;
-        memset(&m, 0, sizeof(m));
-        m.w = (walk_ctx){level, begin, count, next, M, com, Q, spos, smass, L, 0.0, eps * eps, 2};
-        m.hkey = hkey;
-        m.lo = lo;
-        m.trT = trT;
-        m.tlo2 = theta_lo * theta_lo;
-        m.tmax2 = theta_max * theta_max;
-        m.eps = eps;
-        m.seed = seed;
-        m.keep = keep;
-        m.cap = cap;
-        m.slot0 = cap * t;
-        m.feat = feat;
-        m.label = label;
-        m.node = node;
-        int64_t k = 0;
-        if (next[0] != 1)
-            sample_walk(&m, 0, targets[t], &k);
-        cnt[t] = k;
-    }
-}
-
-/* Per cell: k_C M l^3 with log10 k_C from the network (params; bf16
- * operands, or fp16 with f16 != 0) or k_C = 1 (params NULL). */
-void orc_cell_kc(int64_t m, const int32_t *level, const uint64_t *hkey, const int32_t *count,
-                 const int32_t *next, const double *M, const double *com, const double *Q,
-                 const double *trT, const double *lo, double L, double eps, const double *params,
-                 int f16, double *kc)
-{
-#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < m; ++c) {
         const double side = ldexp(L, -level[c]);
-        double lk = 0.0;
-        if (params) {
-            double centre[3], f[10];
-            cell_centre(hkey[c], level[c], lo, L, centre);
-            orc_cell_features(centre, side, &com[3 * c], M[c], &Q[6 * c], trT[c], count[c],
-                              next[c] == c + 1, eps, f);
-            lk = f16 ? orc_mlp_f16(params, f) : orc_mlp_bf16(params, f);
-        }
-        kc[c] = pow(10.0, lk) * M[c] * side * side * side;
+        kc[c] = M[c] * side * side * side;
     }
 }
 
@@ -928,8 +823,10 @@ typedef struct {
     walk_acc *r; /* one per body of the group */
     int flag;
     int64_t work;
-    /* mode 2 (learned): network parameters, softening, log10(tau amin) */
+    /* mode 2 (learned): network parameters (fp16 operands if f16, else
+     * bf16), softening, log10(tau amin) */
     const double *params;
+    int f16;
     double eps, lt;
 } group_ctx;
 
@@ -1001,9 +898,9 @@ static void walk_one_group(const int32_t *level, const uint64_t *hkey, const int
                            const double *smass, const double *lo, double L, double eps,
                            int order, int mode, double theta, double theta_max, double tau,
                            const double *kc, const double *anorm, const double *params,
-                           int64_t r0, int64_t r1, int64_t t0, int64_t cap, double tol,
+                           int f16, int64_t r0, int64_t r1, int64_t t0, int64_t cap, double tol,
                            double *acc, double *phi, int64_t *npp, int64_t *npc, int64_t *ncov,
-                           int32_t *flag);
+                           int32_t *flag, const double *O);
 
 static void group_run(group_ctx *g, int64_t r0, int64_t r1, const double *anorm, walk_acc *r);
 
@@ -1024,10 +921,11 @@ void orc_walk_group(const int32_t *level, const uint64_t *hkey, const int32_t *b
                     const double *com, const double *Q, const double *spos, const double *smass,
                     const double *lo, double L, double eps, int order, int mode, double theta,
                     double theta_max, double tau, const double *kc, const double *anorm,
-                    const double *params, int64_t G, int64_t t0, int64_t t1, int64_t cap,
-                    double tol,
+                    const double *params, int f16, int64_t G, int64_t t0, int64_t t1,
+                    int64_t cap, double tol,
                     const uint64_t *skeys, const int32_t *leaf_level, int split, double *acc,
-                    double *phi, int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag)
+                    double *phi, int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag,
+                    const double *O)
 {
     const int64_t ng = (t1 - t0 + G - 1) / G;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -1054,8 +952,8 @@ void orc_walk_group(const int32_t *level, const uint64_t *hkey, const int32_t *b
                 b = cut;
             }
             walk_one_group(level, hkey, begin, count, next, M, com, Q, spos, smass, lo, L, eps,
-                           order, mode, theta, theta_max, tau, kc, anorm, params, a, b, t0, cap,
-                           tol, acc, phi, npp, npc, ncov, flag);
+                           order, mode, theta, theta_max, tau, kc, anorm, params, f16, a, b, t0,
+                           cap, tol, acc, phi, npp, npc, ncov, flag, O);
             a = b;
         }
     }
@@ -1068,15 +966,16 @@ static void walk_one_group(const int32_t *level, const uint64_t *hkey, const int
                            const double *smass, const double *lo, double L, double eps,
                            int order, int mode, double theta, double theta_max, double tau,
                            const double *kc, const double *anorm, const double *params,
-                           int64_t r0, int64_t r1, int64_t t0, int64_t cap, double tol,
+                           int f16, int64_t r0, int64_t r1, int64_t t0, int64_t cap, double tol,
                            double *acc, double *phi, int64_t *npp, int64_t *npc, int64_t *ncov,
-                           int32_t *flag)
+                           int32_t *flag, const double *O)
 {
     {
         group_ctx g;
         memset(&g, 0, sizeof(g));
         g.w = (walk_ctx){level, begin, count, next, M, com, Q, spos, smass, L, 0.0, eps * eps,
                          order};
+        g.w.O = O;
         g.hkey = hkey;
         g.lo = lo;
         g.kc = kc;
@@ -1086,6 +985,7 @@ static void walk_one_group(const int32_t *level, const uint64_t *hkey, const int
         g.tau = tau;
         g.tol = tol;
         g.params = params;
+        g.f16 = f16;
         g.eps = eps;
         g.r = calloc((size_t)(r1 - r0), sizeof(walk_acc));
         group_run(&g, r0, r1, anorm, g.r);
@@ -1181,13 +1081,15 @@ static void group_run(group_ctx *g, int64_t r0, int64_t r1, const double *anorm,
  * Learned acceptance criterion, one decision per (group, cell).
  *
  * A network predicts the error a cell's particle-cell term (order 2) makes
- * on a group of bodies: the largest |a_pc,i - a_exact,i| over the group,
- * relative to the cell's monopole field M / d_g^2 at the group's box, as
- * log10.  The cell is accepted for the group iff its cube misses the box,
+ * on a group of bodies: the largest |a_pc,i - a_exact,i| over the group in
+ * units of the error budget's model M l^3 / d_g^5 (the next order of the
+ * expansion at the group's box), as log10 -- a coefficient k_C per (group,
+ * cell).  The cell is accepted for the group iff its cube misses the box,
  * l^2 < theta_max^2 d_g^2, and
- *     pred + log10(M) - 2 log10(d_g) < log10(tau a_min),
+ *     pred + log10(M l^3 / d_g^5) < log10(tau a_min),
  * i.e. iff the predicted error is below tau times the group's smallest
- * |a_i|.  A group of one body is the per-body criterion.
+ * |a_i|: the error budget with k_C = 10^pred.  A group of one body is the
+ * per-body criterion.
  *
  * Features of (box, cell), all scale-free (l side, d_g distance from the
  * COM to the box, d_c to the box centre, h the box's half-diagonal,
@@ -1242,68 +1144,101 @@ void orc_gfeatures(const double *bl, const double *bu, const double *centre, dou
     f[9] = is_leaf ? 1.0 : 0.0;
 }
 
-/* The network as the MFMA inference evaluates it (bf16 operands of both
- * hidden layers, sums in FP32 there, FP64 here), and *delta, a bound on how
- * far the FP32 evaluation of the same inputs may move the output:
- *  - a feature computed in FP32 within a relative 1e-5 (plus 1e-6) of a
- *    bf16 rounding midpoint may round to the other neighbour; the output
- *    moves by at most that step times the product of the absolute weights
- *    along every path from the feature (a Lipschitz bound of the ReLU net);
- *  - a hidden unit's FP32 sum differs from the exact one by at most
- *    (terms + 1) 2^-24 times the sum of the absolute terms; if that interval
- *    straddles a bf16 midpoint (or 0) the unit may round the other way;
- *  - the second layer's and the output's FP32 sums by the same rule. */
-static double gnet_bound(const double *p, const double *f, double *delta)
+/* The network as the MFMA inference evaluates it (bf16 or fp16 operands of
+ * both hidden layers by rnd, sums in FP32 there, FP64 here) from given
+ * rounded features fr; h1 receives the rounded hidden layer, z1 its sums. */
+static double gnet_fwd(const double *p, const double *fr, double (*rnd)(double), double *h1,
+                       double *z1, double *z2)
 {
     const double *W1 = p, *b1 = p + 320, *W2 = p + 352, *b2 = p + 1376, *w3 = p + 1408;
-    const double b3 = (double)(float)p[1440];
-    const double u24 = ldexp(1.0, -24);
-    double fr[10], lip[10], h1[32], out = 0.0, d = 0.0, sum_out = fabs(b3);
-    double path[32]; /* sum_u |w3_u| |W2_uj| */
+    double out = (double)(float)p[1440];
     for (int j = 0; j < 32; ++j) {
-        path[j] = 0.0;
-        for (int u = 0; u < 32; ++u)
-            path[j] += fabs((double)(float)w3[u]) * fabs(bf16r(W2[u * 32 + j]));
-    }
-    for (int k = 0; k < 10; ++k) {
-        fr[k] = bf16r(f[k]);
-        lip[k] = 0.0;
-        for (int j = 0; j < 32; ++j)
-            lip[k] += path[j] * fabs(bf16r(W1[j * 10 + k]));
-        const double m = 1e-5 * fabs(f[k]) + 1e-6;
-        d += lip[k] * fabs(bf16r(f[k] + m) - bf16r(f[k] - m));
-    }
-    for (int j = 0; j < 32; ++j) {
-        double s = bf16r(b1[j]), a = fabs(s);
-        for (int k = 0; k < 10; ++k) {
-            s += bf16r(W1[j * 10 + k]) * fr[k];
-            a += fabs(bf16r(W1[j * 10 + k]) * fr[k]);
-        }
-        const double e = 12.0 * u24 * a;
-        h1[j] = bf16r(s > 0.0 ? s : 0.0);
-        const double hi = bf16r(s + e > 0.0 ? s + e : 0.0), lo = bf16r(s - e > 0.0 ? s - e : 0.0);
-        d += path[j] * (hi - lo);
+        double s = rnd(b1[j]);
+        for (int k = 0; k < 10; ++k)
+            s += rnd(W1[j * 10 + k]) * fr[k];
+        z1[j] = s;
+        h1[j] = rnd(s > 0.0 ? s : 0.0);
     }
     for (int u = 0; u < 32; ++u) {
-        double s = (double)(float)b2[u], a = fabs(s);
-        for (int j = 0; j < 32; ++j) {
-            s += bf16r(W2[u * 32 + j]) * h1[j];
-            a += fabs(bf16r(W2[u * 32 + j]) * h1[j]);
-        }
-        d += fabs((double)(float)w3[u]) * 34.0 * u24 * a;
-        if (s > 0.0) {
+        double s = (double)(float)b2[u];
+        for (int j = 0; j < 32; ++j)
+            s += rnd(W2[u * 32 + j]) * h1[j];
+        z2[u] = s;
+        if (s > 0.0)
             out += (double)(float)w3[u] * s;
-            sum_out += fabs((double)(float)w3[u] * s);
+    }
+    return out;
+}
+
+/* The network's output from the features f, and *delta, a bound on how far
+ * an evaluation of the same features in FP32 (features computed in FP32,
+ * sums in FP32) may move it:
+ *  - a feature computed in FP32 lies within 4e-6 (|f| + 1) of the exact
+ *    one; if that interval holds a rounding midpoint, the operand may round
+ *    to the other neighbour: the output with that operand is evaluated and
+ *    the difference added;
+ *  - a hidden unit's FP32 sum lies within (terms + 1) 2^-24 times the sum
+ *    of its absolute terms of the exact one; if that interval holds a
+ *    rounding midpoint (or 0), the same;
+ *  - the second layer's and the output's FP32 sums move the output by at
+ *    most their error bound times |w3| (ReLU is 1-Lipschitz).
+ * Flips are taken one at a time (first order; two flips in one evaluation
+ * are rarer still). */
+static double gnet_bound(const double *p, const double *f, double *delta, double (*rnd)(double))
+{
+    const double *W1 = p, *b1 = p + 320, *W2 = p + 352, *w3 = p + 1408;
+    const double u24 = ldexp(1.0, -24);
+    double fr[10], h1[32], z1[32], z2[32], h1x[32], z1x[32], z2x[32];
+    for (int k = 0; k < 10; ++k)
+        fr[k] = rnd(f[k]);
+    const double out = gnet_fwd(p, fr, rnd, h1, z1, z2);
+    double d = 0.0;
+    for (int k = 0; k < 10; ++k) {
+        const double m = 4e-6 * (fabs(f[k]) + 1.0);
+        const double lo = rnd(f[k] - m), hi = rnd(f[k] + m);
+        if (lo == hi)
+            continue;
+        double alt[10];
+        memcpy(alt, fr, sizeof(alt));
+        alt[k] = fr[k] == lo ? hi : lo;
+        d += fabs(gnet_fwd(p, alt, rnd, h1x, z1x, z2x) - out);
+    }
+    for (int j = 0; j < 32; ++j) {
+        double a = fabs(rnd(b1[j]));
+        for (int k = 0; k < 10; ++k)
+            a += fabs(rnd(W1[j * 10 + k]) * fr[k]);
+        const double e = 12.0 * u24 * a;
+        const double lo = rnd(z1[j] - e > 0.0 ? z1[j] - e : 0.0);
+        const double hi = rnd(z1[j] + e > 0.0 ? z1[j] + e : 0.0);
+        if (lo == hi)
+            continue;
+        /* the output with unit j at its other rounding */
+        const double hj = h1[j] == lo ? hi : lo;
+        double alt = (double)(float)p[1440];
+        for (int u = 0; u < 32; ++u) {
+            const double s = z2[u] + rnd(W2[u * 32 + j]) * (hj - h1[j]);
+            if (s > 0.0)
+                alt += (double)(float)w3[u] * s;
         }
+        d += fabs(alt - out);
+    }
+    double sum_out = fabs((double)(float)p[1440]);
+    for (int u = 0; u < 32; ++u) {
+        double a = fabs((double)(float)p[1376 + u]);
+        for (int j = 0; j < 32; ++j)
+            a += fabs(rnd(W2[u * 32 + j]) * h1[j]);
+        d += fabs((double)(float)w3[u]) * 34.0 * u24 * a;
+        if (z2[u] > 0.0)
+            sum_out += fabs((double)(float)w3[u] * z2[u]);
     }
     d += 34.0 * u24 * sum_out;
     *delta = d;
-    return out + b3;
+    return out;
 }
 
-double orc_gnet_bound(const double *p, const double *f, double *delta)
+double orc_gnet_bound(const double *p, const double *f, double *delta, int f16)
 {
-    return gnet_bound(p, f, delta);
+    return gnet_bound(p, f, delta, f16 ? f16r : bf16r);
 }
 
 /* Three-valued learned term of cell c for group g (1 surely accepted, -1
@@ -1322,11 +1257,12 @@ static int learned_term(const group_ctx *g, int64_t c, double side, double dg2, 
     }
     orc_gfeatures(bl, bu, centre, side, &w->com[3 * c], w->M[c], &w->Q[6 * c], w->count[c],
                   w->next[c] == c + 1, g->eps, f);
-    const double pred = gnet_bound(g->params, f, &delta);
-    const double lm = log10(w->M[c]), ld = log10(dg2);
-    const double lhs = pred + lm - ld;
+    const double pred = gnet_bound(g->params, f, &delta, g->f16 ? f16r : bf16r);
+    const double lm = log10(w->M[c]), ls = 1.5 * log10(side * side), ld = 2.5 * log10(dg2);
+    const double lhs = pred + lm + ls - ld;
     *accept = lhs < g->lt;
-    const double margin = delta + g->tol * (fabs(pred) + fabs(lm) + fabs(ld) + fabs(g->lt) + 1.0);
+    const double margin =
+        delta + g->tol * (fabs(pred) + fabs(lm) + fabs(ls) + fabs(ld) + fabs(g->lt) + 1.0);
     if (g->lt - lhs > margin)
         return 1;
     if (lhs - g->lt > margin)
@@ -1337,9 +1273,10 @@ static int learned_term(const group_ctx *g, int64_t c, double side, double dg2, 
 /* ---- training pairs of the learned criterion */
 
 /* label of cell c for the bodies [g0, g1): log10 of the largest
- * |a_pc,i - a_exact,i| d_g^2 / M, floored at 1e-12 */
+ * |a_pc,i - a_exact,i| d_g^5 / (M l^3), floored at 1e-12 */
 static double group_label(const walk_ctx *w, int64_t c, int64_t g0, int64_t g1, double dg2)
 {
+    const double side = ldexp(w->L, -w->level[c]);
     double emax = 0.0;
     for (int64_t i = g0; i < g1; ++i) {
         walk_acc ex, ap;
@@ -1356,7 +1293,7 @@ static double group_label(const walk_ctx *w, int64_t c, int64_t g0, int64_t g1, 
         if (e > emax)
             emax = e;
     }
-    double v = sqrt(emax) * dg2 / w->M[c];
+    double v = sqrt(emax) * dg2 * dg2 * sqrt(dg2) / (w->M[c] * side * side * side);
     if (!(v > 1e-12))
         v = 1e-12;
     return log10(v);

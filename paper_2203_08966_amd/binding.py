@@ -418,7 +418,8 @@ def bh_mlp_get(ctx) -> np.ndarray:
 
 
 def bh_mlp_samples(tree, eps, theta_lo, theta_max, keep, seed):
-    """Training pairs of an FP64 tree: (feat, label, node, body) GPU tensors."""
+    """Training pairs of an FP64 tree: (feat, label, node, group's first
+    sorted rank) GPU tensors."""
     import torch
     tot = C.c_int64()
     lib = load()
@@ -429,11 +430,11 @@ def bh_mlp_samples(tree, eps, theta_lo, theta_max, keep, seed):
     feat = torch.empty((max(n, 1), 10), dtype=torch.float32, device=dev)
     label = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
     node = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
-    body = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    group = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
     _check(lib.bh_mlp_samples(tree, float(eps), float(theta_lo), float(theta_max), float(keep),
                               int(seed), n, _dev(feat, "feat"), _dev(label, "label"),
-                              _dev(node, "node"), _dev(body, "body"), C.byref(tot)))
-    return feat[:n], label[:n], node[:n], body[:n]
+                              _dev(node, "node"), _dev(group, "group"), C.byref(tot)))
+    return feat[:n], label[:n], node[:n], group[:n]
 
 
 def _pairs(feat, label):

@@ -79,7 +79,7 @@ static void free_tree_bufs(bh_tree *t) {
                      &t->level, &t->begin, &t->count, &t->next, &t->parent, &t->cmask,
                      &t->lvl_list, &t->cx, &t->cy, &t->cz, &t->mom, &t->recs,
                      &t->cube, &t->part, &t->hist, &t->status, &t->misc, &t->cnt_scratch,
-                     &t->cellf, &t->kc, &t->anorm, &t->est_acc, &t->kids, &t->wq, &t->gorder,
+                     &t->kc, &t->anorm, &t->est_acc, &t->kids, &t->s3, &t->oct, &t->wq, &t->gorder,
                      &t->gfb};
     for (DevBuf *b : all) free_buf(*b);
 }
@@ -94,7 +94,11 @@ static bool bad_dtype(int d) { return d != BH_F32 && d != BH_F64; }
 static size_t dsize(int d) { return d == BH_F32 ? 4 : 8; }
 
 static int check_opts(const bh_force_opts &o, int64_t n) {
-    if (o.order != 0 && o.order != 2) return set_error(BH_E_INVALID, "opts.order must be 0 or 2");
+    if (o.order != 0 && o.order != 2 && o.order != 3)
+        return set_error(BH_E_INVALID, "opts.order must be 0, 2 or 3");
+    if (o.order == 3 && o.mac != BH_MAC_THETA)
+        return set_error(BH_E_INVALID, "opts.order 3 (octopole) runs with the opening angle "
+                                       "BH_MAC_THETA only");
     if (o.mac != BH_MAC_THETA && o.mac != BH_MAC_MLP && o.mac != BH_MAC_BUDGET &&
         o.mac != BH_MAC_THETA_GUARD)
         return set_error(BH_E_INVALID, "opts.mac must be BH_MAC_THETA, BH_MAC_MLP, BH_MAC_BUDGET "

@@ -121,6 +121,7 @@ struct bh_tree {
     int64_t n = 0, m = 0;
     int leaf = 1;
     int depth = 0;
+    int32_t lvl_cnt[22] = {}, lvl_base[22] = {};  // cells per level, first slot in lvl_list
     int last_mac = -1;  // criterion the last walk of this tree used (-1: none yet)
     double lo[3] = {0, 0, 0}, L = 1.0;
     // body-indexed
@@ -134,20 +135,19 @@ struct bh_tree {
     bh::DevBuf mom, recs;
     // small scratch
     bh::DevBuf cube, part, hist, status, misc, cnt_scratch;
-    // learned criterion: cell features, k_C M l^3, |a| per sorted rank,
-    // estimate accelerations; cache keys of cellf/kc
-    bh::DevBuf cellf, kc, anorm, est_acc;
+    // error budget: M l^3 per cell; |a| per sorted rank; estimate
+    // accelerations
+    bh::DevBuf kc, anorm, est_acc;
     bh::DevBuf kids;                           // group walk: children per node
+    bh::DevBuf s3, oct;                        // order 3: raw third moments, octopole records
+    int64_t oct_tree_id = -1;
     bh::DevBuf wq;                             // group walk: queue counters
     bh::DevBuf gorder;                         // group walk: work items in hand-out order
     bh::DevBuf gfb;                            // group walk: per-group fallback prediction
     uint64_t gfb_sig = 0;                      //   parameters it was made with
     int64_t gfb_ng = -1;                       //   and group count
     int64_t kids_tree_id = -1;
-    int kc_version = -2;
-    double kc_eps = -1.0;
-    int64_t build_id = 0, kc_tree_id = -1, cf_tree_id = -1;
-    double cf_eps = -1.0;
+    int64_t build_id = 0, kc_tree_id = -1;
     uint64_t *sorted_keys = nullptr;           // result buffers after the sort
     uint32_t *perm = nullptr;
 };
@@ -182,6 +182,10 @@ int check_launch(const char *what);
 int build_tree(bh_ctx *ctx, bh_tree *t, const void *pos, const void *mass, int dtype,
                int64_t n, int leaf, const void *vel, const uint32_t *id, void *pos_out,
                void *vel_out, void *mass_out, uint32_t *id_out);
+
+// Octopole records of the tree (order-3 walks), computed on first use per
+// build: 8 values of the tree's dtype per node (see build.hip).
+int ensure_octopole(bh_tree *t);
 
 // ---- walk (walk.hip)
 // prev_acc: accelerations in the tree's input order from an earlier step;

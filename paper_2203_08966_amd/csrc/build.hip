@@ -955,6 +955,120 @@ __global__ __launch_bounds__(kTopCells) void k_up_top(const int32_t *__restrict_
     }
 }
 
+// ---------------------------------------------------------------- octopole
+// Third moments for the order-3 walk (Sec. 2.2, the l = 3 term): raw
+// S3_abc = sum m y_a y_b y_c about each cell's COM, FP64, components xxx
+// xxy xxz xyy xyz xzz yyy yyz yzz zzz.  Leaves from their bodies; internal
+// cells level by level, deepest first, from their children by the shift of
+// origin (the first moment about a child's COM vanishes):
+//   S3_P = sum_k S3_k + (S2_k,ab d_c + S2_k,ac d_b + S2_k,bc d_a) + M_k d_a d_b d_c,
+// d = COM_k - COM_P, S2 the raw second moment about the child's COM.  Then
+// the traceless octopole O_abc = 15 S3_abc - 3 (T_a d_bc + T_b d_ac +
+// T_c d_ab), T_a = S3_axx + S3_ayy + S3_azz, is packed as its seven
+// independent components xxx xxy xxz xyy xyz yyy yyz (the others follow
+// from the zero traces) and a pad.
+__device__ __forceinline__ void com_abs(const Moments &q, int cx, int cy, int cz,
+                                        const Cube *cube, double h, double c[3]) {
+    c[0] = cube->lo[0] + cx * h + q.c[0];
+    c[1] = cube->lo[1] + cy * h + q.c[1];
+    c[2] = cube->lo[2] + cz * h + q.c[2];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_oct_leaves(int m, const int32_t *__restrict__ begin,
+                                                         const int32_t *__restrict__ count,
+                                                         const int32_t *__restrict__ next,
+                                                         const int32_t *__restrict__ cx,
+                                                         const int32_t *__restrict__ cy,
+                                                         const int32_t *__restrict__ cz,
+                                                         const Moments *__restrict__ mom,
+                                                         const Cube *__restrict__ cube,
+                                                         const T *__restrict__ spos,
+                                                         const T *__restrict__ smass,
+                                                         double *__restrict__ s3) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m || next[i] != i + 1) return;
+    const double h = ldexp(cube->L, -(kLevels + 1));
+    double c[3];
+    com_abs(mom[i], cx[i], cy[i], cz[i], cube, h, c);
+    double o[10] = {};
+    for (int j = begin[i]; j < begin[i] + count[i]; ++j) {
+        const double y0 = (double)spos[3 * (int64_t)j] - c[0];
+        const double y1 = (double)spos[3 * (int64_t)j + 1] - c[1];
+        const double y2 = (double)spos[3 * (int64_t)j + 2] - c[2];
+        const double mj = (double)smass[j];
+        o[0] += mj * y0 * y0 * y0;
+        o[1] += mj * y0 * y0 * y1;
+        o[2] += mj * y0 * y0 * y2;
+        o[3] += mj * y0 * y1 * y1;
+        o[4] += mj * y0 * y1 * y2;
+        o[5] += mj * y0 * y2 * y2;
+        o[6] += mj * y1 * y1 * y1;
+        o[7] += mj * y1 * y1 * y2;
+        o[8] += mj * y1 * y2 * y2;
+        o[9] += mj * y2 * y2 * y2;
+    }
+    for (int k = 0; k < 10; ++k) s3[10 * (int64_t)i + k] = o[k];
+}
+
+__global__ __launch_bounds__(kThreads) void k_oct_level(const int32_t *__restrict__ list, int cnt,
+                                                        const int32_t *__restrict__ kids,
+                                                        const int32_t *__restrict__ cx,
+                                                        const int32_t *__restrict__ cy,
+                                                        const int32_t *__restrict__ cz,
+                                                        const Moments *__restrict__ mom,
+                                                        const Cube *__restrict__ cube,
+                                                        double *__restrict__ s3) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const int p = list[t];
+    const int32_t *kp = kids + 8 * (int64_t)p;
+    if (kp[0] < 0) return;  // a leaf (computed from its bodies)
+    const double h = ldexp(cube->L, -(kLevels + 1));
+    double cp[3];
+    com_abs(mom[p], cx[p], cy[p], cz[p], cube, h, cp);
+    double o[10] = {};
+    for (int q = 0; q < 8 && kp[q] >= 0; ++q) {
+        const int k = kp[q];
+        const Moments mk = mom[k];
+        double ck[3];
+        com_abs(mk, cx[k], cy[k], cz[k], cube, h, ck);
+        const double d0 = ck[0] - cp[0], d1 = ck[1] - cp[1], d2 = ck[2] - cp[2];
+        const double *t2 = mk.t;  // xx xy xz yy yz zz about the child's COM
+        const double *sk = s3 + 10 * (int64_t)k;
+        const double M = mk.m;
+        o[0] += sk[0] + 3 * t2[0] * d0 + M * d0 * d0 * d0;
+        o[1] += sk[1] + 2 * t2[1] * d0 + t2[0] * d1 + M * d0 * d0 * d1;
+        o[2] += sk[2] + 2 * t2[2] * d0 + t2[0] * d2 + M * d0 * d0 * d2;
+        o[3] += sk[3] + t2[3] * d0 + 2 * t2[1] * d1 + M * d0 * d1 * d1;
+        o[4] += sk[4] + t2[4] * d0 + t2[2] * d1 + t2[1] * d2 + M * d0 * d1 * d2;
+        o[5] += sk[5] + t2[5] * d0 + 2 * t2[2] * d2 + M * d0 * d2 * d2;
+        o[6] += sk[6] + 3 * t2[3] * d1 + M * d1 * d1 * d1;
+        o[7] += sk[7] + 2 * t2[4] * d1 + t2[3] * d2 + M * d1 * d1 * d2;
+        o[8] += sk[8] + t2[5] * d1 + 2 * t2[4] * d2 + M * d1 * d2 * d2;
+        o[9] += sk[9] + 3 * t2[5] * d2 + M * d2 * d2 * d2;
+    }
+    for (int k = 0; k < 10; ++k) s3[10 * (int64_t)p + k] = o[k];
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_oct_pack(int m, const double *__restrict__ s3,
+                                                       R *__restrict__ oct) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const double *s = s3 + 10 * (int64_t)i;
+    const double tx = s[0] + s[3] + s[5], ty = s[1] + s[6] + s[8], tz = s[2] + s[7] + s[9];
+    R *o = oct + 8 * (int64_t)i;
+    o[0] = (R)(15 * s[0] - 9 * tx);  // xxx
+    o[1] = (R)(15 * s[1] - 3 * ty);  // xxy
+    o[2] = (R)(15 * s[2] - 3 * tz);  // xxz
+    o[3] = (R)(15 * s[3] - 3 * tx);  // xyy
+    o[4] = (R)(15 * s[4]);           // xyz
+    o[5] = (R)(15 * s[6] - 9 * ty);  // yyy
+    o[6] = (R)(15 * s[7] - 3 * tz);  // yyz
+    o[7] = (R)0;
+}
+
 template <typename T>
 int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int B,
                 const T *vel, const uint32_t *id, T *pos_out, T *vel_out, T *mass_out,
@@ -1057,6 +1171,8 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     for (int k = 0; k <= kLevels; ++k) {
         lcount[k] = (int)hp[16 + 1 + k];
         lb.base[k] = acc;
+        t->lvl_cnt[k] = lcount[k];
+        t->lvl_base[k] = acc;
         acc += lcount[k];
         if (lcount[k] > 0) t->depth = k;
     }
@@ -1117,6 +1233,44 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
 }
 
 }  // namespace
+
+int ensure_octopole(bh_tree *t) {
+    if (t->oct_tree_id == t->build_id) return BH_OK;
+    const int m = (int)t->m;
+    const size_t rs = t->dtype == BH_F32 ? 4 : 8;
+    int rc;
+    if ((rc = grow(t->s3, 80ull * m)) || (rc = grow(t->oct, 8 * rs * m))) return rc;
+    hipStream_t st = t->ctx->stream;
+    const int32_t *cx = (const int32_t *)t->cx.p, *cy = (const int32_t *)t->cy.p,
+                  *cz = (const int32_t *)t->cz.p;
+    const Moments *mom = (const Moments *)t->mom.p;
+    const Cube *cube = (const Cube *)t->cube.p;
+    double *s3 = (double *)t->s3.p;
+    if (t->dtype == BH_F32)
+        k_oct_leaves<float><<<div_up(m, kThreads), kThreads, 0, st>>>(
+            m, (const int32_t *)t->begin.p, (const int32_t *)t->count.p,
+            (const int32_t *)t->next.p, cx, cy, cz, mom, cube, (const float *)t->spos.p,
+            (const float *)t->smass.p, s3);
+    else
+        k_oct_leaves<double><<<div_up(m, kThreads), kThreads, 0, st>>>(
+            m, (const int32_t *)t->begin.p, (const int32_t *)t->count.p,
+            (const int32_t *)t->next.p, cx, cy, cz, mom, cube, (const double *)t->spos.p,
+            (const double *)t->smass.p, s3);
+    const int32_t *lvl_list = (const int32_t *)t->lvl_list.p;
+    for (int k = t->depth - 1; k >= 0; --k) {
+        if (t->lvl_cnt[k] == 0) continue;
+        k_oct_level<<<div_up(t->lvl_cnt[k], kThreads), kThreads, 0, st>>>(
+            lvl_list + t->lvl_base[k], t->lvl_cnt[k], (const int32_t *)t->kids.p, cx, cy, cz, mom,
+            cube, s3);
+    }
+    if (t->dtype == BH_F32)
+        k_oct_pack<float><<<div_up(m, kThreads), kThreads, 0, st>>>(m, s3, (float *)t->oct.p);
+    else
+        k_oct_pack<double><<<div_up(m, kThreads), kThreads, 0, st>>>(m, s3, (double *)t->oct.p);
+    if ((rc = check_launch("octopole"))) return rc;
+    t->oct_tree_id = t->build_id;
+    return BH_OK;
+}
 
 int build_tree(bh_ctx *ctx, bh_tree *t, const void *pos, const void *mass, int dtype,
                int64_t n, int leaf, const void *vel, const uint32_t *id, void *pos_out,

@@ -1,11 +1,14 @@
-// Learned acceptance criterion on gfx950: cell features, training pairs,
-// training kernels and bf16 MFMA inference.
+// Learned acceptance criterion on gfx950: training pairs, training kernels
+// and the wave-level MFMA inference used inside the group walk.
 //
-// The error of a cell's quadrupole term on body i is modelled as
-// k_C (l/d)^3 M/d^2; a network predicts log10 k_C from the cell's features
-// once per cell (inference batched 64 cells per wavefront on MFMA), and the
-// walk accepts a cell iff k_C M l^3 < tau |a_i| d^5 (with l/d < theta_max and
-// the body outside the cell).
+// The criterion takes one decision per (group, cell): a network predicts
+// log10 of the largest error the cell's quadrupole particle-cell term makes
+// on the group's bodies in units of the error budget's model M l^3 / d_g^5
+// (a coefficient k_C per group and cell), from 10 scale-free features of
+// the (box, cell) pair; the cell is accepted iff
+// pred + log10(M l^3 / d_g^5) < log10(tau a_min) (and its cube misses the
+// box, and l < theta_max d_g).  The walk evaluates the network
+// for the candidate cells of a round, one per lane, as one 64-row batch.
 //
 // Network 10 -> 32 (ReLU) -> 32 (ReLU) -> 1.  FP32 master parameters, flat:
 // W1[32][10] b1[32] W2[32][32] b2[32] w3[32] b3 (1441 values).
@@ -38,71 +41,6 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
-}
-
-// ------------------------------------------------------------------ cell features
-// Scale-free features of every cell, from its FP64 moments (l side, g COM
-// offset from the centre, M mass, n count, T2 = sum m |y|^2 about the COM,
-// Q traceless quadrupole):
-//   |g|/l, sqrt(T2/M)/l, |Q|_F/(M l^2), cbrt(det Q)/(M l^2), max|g_a|/l,
-//   log2(n)/21, leaf, eps/l, 1/sqrt(n), T2/(M l^2)
-__global__ __launch_bounds__(256) void k_cell_features(int m, const Moments *__restrict__ mom,
-                                                       const int32_t *__restrict__ level,
-                                                       const int32_t *__restrict__ count,
-                                                       const int32_t *__restrict__ next,
-                                                       const Cube *__restrict__ cube, double eps,
-                                                       float *__restrict__ cf) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    const Moments q = mom[i];
-    const double side = ldexp(cube->L, -level[i]);
-    const double tr = q.t[0] + q.t[3] + q.t[5];
-    const double Q[3][3] = {{3 * q.t[0] - tr, 3 * q.t[1], 3 * q.t[2]},
-                            {3 * q.t[1], 3 * q.t[3] - tr, 3 * q.t[4]},
-                            {3 * q.t[2], 3 * q.t[4], 3 * q.t[5] - tr}};
-    double qf = 0;
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) qf += Q[a][b] * Q[a][b];
-    const double det = Q[0][0] * (Q[1][1] * Q[2][2] - Q[1][2] * Q[2][1]) -
-                       Q[0][1] * (Q[1][0] * Q[2][2] - Q[1][2] * Q[2][0]) +
-                       Q[0][2] * (Q[1][0] * Q[2][1] - Q[1][1] * Q[2][0]);
-    const double ml2 = q.m * side * side;
-    const double gmax = fmax(fabs(q.c[0]), fmax(fabs(q.c[1]), fabs(q.c[2])));
-    const int n = count[i];
-    float *f = cf + 10 * (size_t)i;
-    f[0] = (float)(sqrt(q.c[0] * q.c[0] + q.c[1] * q.c[1] + q.c[2] * q.c[2]) / side);
-    f[1] = (float)(q.m > 0 ? sqrt(tr / q.m) / side : 0.0);
-    f[2] = (float)(ml2 > 0 ? sqrt(qf) / ml2 : 0.0);
-    f[3] = (float)(ml2 > 0 ? cbrt(det) / ml2 : 0.0);
-    f[4] = (float)(gmax / side);
-    f[5] = (float)(log2((double)n) / 21.0);
-    f[6] = next[i] == i + 1 ? 1.f : 0.f;
-    f[7] = (float)(eps / side);
-    f[8] = (float)(1.0 / sqrt((double)n));
-    f[9] = (float)(ml2 > 0 ? tr / ml2 : 0.0);
-}
-
-// k_C M l^3 per cell with log10 k_C from the network, 64 cells per wave.
-template <typename V>
-__global__ __launch_bounds__(256) void k_cell_kc(const MlpPacked *__restrict__ p, int m,
-                                                 const float *__restrict__ cf,
-                                                 const Moments *__restrict__ mom,
-                                                 const int32_t *__restrict__ level,
-                                                 const Cube *__restrict__ cube,
-                                                 float *__restrict__ kc) {
-    const int wave = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    if (wave * 64 >= m) return;  // whole wave: the MFMAs need every lane
-    const int l = (int)lane_id();
-    const int i = wave * 64 + l;
-    MlpRegs<V> r;
-    mlp_load(p, l, r);
-    float f[kMlpIn];
-    for (int q = 0; q < kMlpIn; ++q) f[q] = i < m ? cf[10 * (size_t)i + q] : 0.f;
-    const float lk = mlp_eval(r, f, l);
-    if (i < m) {
-        const double side = ldexp(cube->L, -level[i]);
-        kc[i] = (float)(exp10((double)lk) * mom[i].m * side * side * side);
-    }
 }
 
 // k_C = 1: M l^3 per cell (the error-budget criterion without a network).
@@ -163,107 +101,129 @@ __global__ __launch_bounds__(1024) void k_anorm_floor(const double *__restrict__
 }
 
 // ------------------------------------------------------------------ training pairs
-// Walk of one wavefront over the FP64 tree at theta_lo: every multi-body
-// cell with theta_lo <= side/d < theta_max that does not contain the body is
-// a candidate, kept when the hash of (rank, node) falls below `keep`.  A
-// kept pair gets the cell's features and the label
-// log10(|a_pc - a_exact| d^5 / (M l^3)), a_exact the direct sum over the
-// cell's bodies, FP64.  Pass 1 (feat == nullptr) counts per body; pass 2
-// writes at offs[rank].
-__global__ __launch_bounds__(256) void k_mac_samples(
+// One wavefront per group of 64 consecutive sorted ranks [t0 + 64 q, ...),
+// over the FP64 tree.  The group's decisions are wave-uniform, so its walk
+// is a forward sweep with skip pointers: a multi-body cell whose cube
+// misses the box with l < theta_lo d_g is skipped, every other cell opened;
+// a cell whose cube misses the box with theta_lo d_g <= l < theta_max d_g is
+// a candidate, kept when the hash of (seed, first rank, node) falls below
+// `keep`.  A kept pair gets its features and the label
+// log10(max_i |a_pc,i - a_exact,i| d_g^5 / (M l^3)) (each lane one body;
+// a_exact the direct sum over the cell's bodies; floored at 1e-12).  Pass 1 (feat ==
+// nullptr) counts per group; pass 2 writes at offs[q].
+__global__ __launch_bounds__(256) void k_group_samples(
     const NodeRec64 *__restrict__ nodes, int m, const BodyRec<double> *__restrict__ bodies,
-    const Anchor<double> *__restrict__ anchors, const float *__restrict__ cf, int n, double tlo2,
-    double tmax2, double eps, double keep, uint64_t seed, int32_t *__restrict__ cnt_out,
+    const Anchor<double> *__restrict__ anchors, int nbodies, int t0, int t1, double tlo2,
+    double tmax2,
+    double eps, double keep, uint64_t seed, int32_t *__restrict__ cnt_out,
     const int64_t *__restrict__ offs, int64_t cap_total, float *__restrict__ feat,
-    float *__restrict__ label, int32_t *__restrict__ node_out, int32_t *__restrict__ body_out) {
-    const int wave = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    const int i = wave * 64 + (int)lane_id();
-    const bool live = i < n;
-    if (wave * 64 >= n) return;
-    double ox = 0, oy = 0, oz = 0, ax = 0, ay = 0, az = 0;
+    float *__restrict__ label, int32_t *__restrict__ node_out, int32_t *__restrict__ group_out) {
+    const int q = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int ng = (t1 - t0 + 63) / 64;
+    if (q >= ng) return;  // whole wave
+    const int lane = (int)lane_id();
+    const int g0 = t0 + 64 * q, g1 = min(g0 + 64, t1);
+    const int i = g0 + lane;
+    const bool live = i < g1;
+    double px = 0, py = 0, pz = 0;  // body position relative to the root corner
     if (live) {
-        const BodyRec<double> me = bodies[i];
-        ox = me.x;
-        oy = me.y;
-        oz = me.z;
-        const Anchor<double> an = anchors[i];
-        ax = an.x;
-        ay = an.y;
-        az = an.z;
+        const BodyRec<double> b = bodies[i];
+        const Anchor<double> a = anchors[i];
+        px = a.x + b.x;
+        py = a.y + b.y;
+        pz = a.z + b.z;
     }
+    double lo3[3] = {live ? px : 1e300, live ? py : 1e300, live ? pz : 1e300};
+    double hi3[3] = {live ? px : -1e300, live ? py : -1e300, live ? pz : -1e300};
+    for (int o = 32; o > 0; o >>= 1)
+        for (int d = 0; d < 3; ++d) {
+            lo3[d] = fmin(lo3[d], __shfl_xor(lo3[d], o));
+            hi3[d] = fmax(hi3[d], __shfl_xor(hi3[d], o));
+        }
+    const double bcx = 0.5 * (lo3[0] + hi3[0]), bcy = 0.5 * (lo3[1] + hi3[1]),
+                 bcz = 0.5 * (lo3[2] + hi3[2]);
+    const double bhx = 0.5 * (hi3[0] - lo3[0]), bhy = 0.5 * (hi3[1] - lo3[1]),
+                 bhz = 0.5 * (hi3[2] - lo3[2]);
     const double e2 = eps * eps;
     const uint64_t keep_lim = (uint64_t)(keep * 9007199254740992.0);  // 2^53
-    int64_t o = (live && offs) ? offs[i] : 0;
+    const int64_t o0 = offs ? offs[q] : 0;
     int k = 0;
     int idx = nodes[0].next == 1 ? m : 1;  // a root leaf has no candidates
-    int resume = live ? idx : 0x7fffffff;
     while (idx < m) {
         idx = uniform(idx);
         const NodeRec64 nd = nodes[idx];
-        const bool act = resume <= idx;
         const int nxt = uniform(nd.next);
-        bool open = false;
-        if (nd.count > 1 && act) {
-            const double X = (ax - nd.cx) + ox, Y = (ay - nd.cy) + oy, Z = (az - nd.cz) + oz;
-            const double x = X - nd.mx, y = Y - nd.my, z = Z - nd.mz;
-            const double d2 = x * x + y * y + z * z;
-            const double s2 = nd.l2;
-            const bool below = s2 < tlo2 * d2;
-            if (!below) {
-                const double side = sqrt(s2);
-                const bool inside = fabs(X) <= 0.5 * side && fabs(Y) <= 0.5 * side &&
-                                    fabs(Z) <= 0.5 * side;
-                if (s2 < tmax2 * d2 && !inside) {
-                    const uint64_t hkey = seed ^ (((uint64_t)i << 32) | (uint64_t)(uint32_t)idx);
-                    if ((splitmix64(hkey) >> 11) < keep_lim) {
-                        if (feat && o + k < cap_total) {
-                            // exact contribution of the cell's bodies
-                            double ex = 0, ey = 0, ez = 0;
-                            for (int j = nd.begin; j < nd.begin + nd.count && j < n; ++j) {
-                                const BodyRec<double> s = bodies[j];
-                                const double dx = s.x + (anchors[j].x - nd.cx) - X;
-                                const double dy = s.y + (anchors[j].y - nd.cy) - Y;
-                                const double dz = s.z + (anchors[j].z - nd.cz) - Z;
-                                const double r2 = dx * dx + dy * dy + dz * dz + e2;
-                                const double ir = 1.0 / sqrt(r2);
-                                const double w = s.m * ir * ir * ir;
-                                ex += w * dx;
-                                ey += w * dy;
-                                ez += w * dz;
-                            }
-                            // the cell's quadrupole particle-cell term
-                            const double inv = 1.0 / sqrt(d2 + e2);
-                            const double inv2 = inv * inv, inv3 = inv * inv2, inv5 = inv3 * inv2;
-                            const double qzz = -nd.qxx - nd.qyy;
-                            const double qx = nd.qxx * x + nd.qxy * y + nd.qxz * z;
-                            const double qy = nd.qxy * x + nd.qyy * y + nd.qyz * z;
-                            const double qz = nd.qxz * x + nd.qyz * y + qzz * z;
-                            const double xqx = x * qx + y * qy + z * qz;
-                            const double g = nd.m * inv3 + 2.5 * xqx * inv5 * inv2;
-                            const double px = inv5 * qx - g * x, py = inv5 * qy - g * y,
-                                         pz = inv5 * qz - g * z;
-                            const double dd = sqrt((px - ex) * (px - ex) + (py - ey) * (py - ey) +
-                                                   (pz - ez) * (pz - ez));
-                            const double d = sqrt(d2);
-                            double v = dd * d2 * d2 * d / (nd.m * s2 * side);
-                            v = v > 1e-12 ? v : 1e-12;
-                            const int64_t s = o + k;
-                            for (int q = 0; q < 10; ++q) feat[10 * s + q] = cf[10 * (size_t)idx + q];
-                            label[s] = (float)log10(v);
-                            node_out[s] = idx;
-                            body_out[s] = i;
+        if (nd.count == 1) {
+            idx = nxt;
+            continue;
+        }
+        const double hs = 0.5 * sqrt(nd.l2);
+        const bool overlap = fabs(nd.cx - bcx) <= hs + bhx && fabs(nd.cy - bcy) <= hs + bhy &&
+                             fabs(nd.cz - bcz) <= hs + bhz;
+        const double ux = (nd.cx + nd.mx) - bcx, uy = (nd.cy + nd.my) - bcy,
+                     uz = (nd.cz + nd.mz) - bcz;
+        const double tx = fmax(fabs(ux) - bhx, 0.0), ty = fmax(fabs(uy) - bhy, 0.0),
+                     tz = fmax(fabs(uz) - bhz, 0.0);
+        const double dg2 = tx * tx + ty * ty + tz * tz;
+        if (!overlap && nd.l2 < tlo2 * dg2) {
+            idx = nxt;
+            continue;
+        }
+        if (!overlap && nd.l2 < tmax2 * dg2 && nd.m > 0.0) {
+            const uint64_t hkey = seed ^ (((uint64_t)g0 << 32) | (uint64_t)(uint32_t)idx);
+            if ((splitmix64(hkey) >> 11) < keep_lim) {
+                if (feat && o0 + k < cap_total) {
+                    // this lane's body: exact sum over the cell's bodies and
+                    // the cell's quadrupole particle-cell term
+                    double err2 = 0.0;
+                    if (live) {
+                        double ex = 0, ey = 0, ez = 0;
+                        for (int j = nd.begin; j < min(nd.begin + nd.count, nbodies); ++j) {
+                            const BodyRec<double> sb = bodies[j];
+                            const Anchor<double> sa = anchors[j];
+                            const double dx = (sa.x + sb.x) - px, dy = (sa.y + sb.y) - py,
+                                         dz = (sa.z + sb.z) - pz;
+                            const double ir = 1.0 / sqrt(dx * dx + dy * dy + dz * dz + e2);
+                            const double w = sb.m * ir * ir * ir;
+                            ex += w * dx;
+                            ey += w * dy;
+                            ez += w * dz;
                         }
-                        ++k;
+                        const double x = px - (nd.cx + nd.mx), y = py - (nd.cy + nd.my),
+                                     z = pz - (nd.cz + nd.mz);
+                        const double inv = 1.0 / sqrt(x * x + y * y + z * z + e2);
+                        const double inv2 = inv * inv, inv3 = inv * inv2, inv5 = inv3 * inv2;
+                        const double qzz = -nd.qxx - nd.qyy;
+                        const double qx = nd.qxx * x + nd.qxy * y + nd.qxz * z;
+                        const double qy = nd.qxy * x + nd.qyy * y + nd.qyz * z;
+                        const double qz = nd.qxz * x + nd.qyz * y + qzz * z;
+                        const double xqx = x * qx + y * qy + z * qz;
+                        const double g = nd.m * inv3 + 2.5 * xqx * inv5 * inv2;
+                        const double ax = inv5 * qx - g * x - ex, ay = inv5 * qy - g * y - ey,
+                                     az = inv5 * qz - g * z - ez;
+                        err2 = ax * ax + ay * ay + az * az;
+                    }
+                    for (int o = 32; o > 0; o >>= 1) err2 = fmax(err2, __shfl_xor(err2, o));
+                    float f[kMlpIn];
+                    gfeatures<double>(ux, uy, uz, bhx, bhy, bhz, nd.mx, nd.my, nd.mz, nd.m,
+                                      nd.qxx, nd.qxy, nd.qxz, nd.qyy, nd.qyz, nd.l2, nd.count,
+                                      nxt == idx + 1, eps, f);
+                    if (lane == 0) {
+                        const int64_t s = o0 + k;
+                        double v = sqrt(err2) * dg2 * dg2 * sqrt(dg2) / (nd.m * nd.l2 * sqrt(nd.l2));
+                        v = v > 1e-12 ? v : 1e-12;
+                        for (int c = 0; c < kMlpIn; ++c) feat[kMlpIn * s + c] = f[c];
+                        label[s] = (float)log10(v);
+                        node_out[s] = idx;
+                        group_out[s] = g0;
                     }
                 }
+                ++k;
             }
-            open = !below && nxt != idx + 1;
         }
-        const uint64_t any_open = __ballot(open);
-        if (act) resume = open ? idx + 1 : nxt;
-        idx = any_open ? idx + 1 : (nxt > idx ? nxt : idx + 1);
+        idx = nxt == idx + 1 ? nxt : idx + 1;  // a leaf is done; open the rest
     }
-    if (live && cnt_out) cnt_out[i] = k;
+    if (cnt_out && lane == 0) cnt_out[q] = k;
 }
 
 // exclusive scan of n counts (one block, any n), total at out[n]
@@ -484,7 +444,7 @@ int mlp_pack(bh_ctx *c) {
     rc = check_launch("mlp pack");
     if (!rc) {
         c->mlp_loaded = 1;
-        c->mlp_version++;  // cached per-cell coefficients are stale
+        c->mlp_version++;  // group-walk predictions made with the old network are stale
     }
     return rc;
 }
@@ -498,48 +458,15 @@ int mlp_infer(bh_ctx *c, const float *X, int64_t n, int precision, float *pred) 
     return check_launch("mlp infer");
 }
 
-// cell features of the tree (cached per build and eps)
-static int mlp_features(bh_tree *t, double eps) {
-    if (t->cf_tree_id == t->build_id && t->cf_eps == eps) return BH_OK;
+int mlp_cells(bh_tree *t) {
+    if (t->kc_tree_id == t->build_id) return BH_OK;
     const int m = (int)t->m;
-    int rc = grow(t->cellf, 40ull * m);
-    if (rc) return rc;
-    k_cell_features<<<div_up(m, 256), 256, 0, t->ctx->stream>>>(
-        m, (const Moments *)t->mom.p, (const int32_t *)t->level.p, (const int32_t *)t->count.p,
-        (const int32_t *)t->next.p, (const Cube *)t->cube.p, eps, (float *)t->cellf.p);
-    if ((rc = check_launch("cell features"))) return rc;
-    t->cf_tree_id = t->build_id;
-    t->cf_eps = eps;
-    return BH_OK;
-}
-
-int mlp_cells(bh_tree *t, double eps, bool learned, int precision) {
-    bh_ctx *c = t->ctx;
-    const int m = (int)t->m;
-    const int version = learned ? 2 * c->mlp_version + precision : -1;
-    if (t->kc_version == version && t->kc_eps == eps && t->kc_tree_id == t->build_id) return BH_OK;
     int rc = grow(t->kc, 4ull * m);
     if (rc) return rc;
-    const Moments *mom = (const Moments *)t->mom.p;
-    const Cube *cube = (const Cube *)t->cube.p;
-    if (learned) {
-        if ((rc = mlp_features(t, eps))) return rc;
-        const MlpPacked *p = (const MlpPacked *)c->mlp_w.p + precision;
-        if (precision == BH_MLP_FP16)
-            k_cell_kc<f16x8><<<div_up(div_up(m, 64), 4), 256, 0, c->stream>>>(
-                p, m, (const float *)t->cellf.p, mom, (const int32_t *)t->level.p, cube,
-                (float *)t->kc.p);
-        else
-            k_cell_kc<bf16x8><<<div_up(div_up(m, 64), 4), 256, 0, c->stream>>>(
-                p, m, (const float *)t->cellf.p, mom, (const int32_t *)t->level.p, cube,
-                (float *)t->kc.p);
-    } else {  // k_C = 1 needs no features
-        k_cell_kc_plain<<<div_up(m, 256), 256, 0, c->stream>>>(m, mom, (const int32_t *)t->level.p,
-                                                               cube, (float *)t->kc.p);
-    }
+    k_cell_kc_plain<<<div_up(m, 256), 256, 0, t->ctx->stream>>>(
+        m, (const Moments *)t->mom.p, (const int32_t *)t->level.p, (const Cube *)t->cube.p,
+        (float *)t->kc.p);
     if ((rc = check_launch("mlp cells"))) return rc;
-    t->kc_version = version;
-    t->kc_eps = eps;
     t->kc_tree_id = t->build_id;
     return BH_OK;
 }
@@ -571,36 +498,36 @@ const float *mlp_anorm_floor(const bh_tree *t) {
 
 int mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_max, double keep,
                 uint64_t seed, int64_t cap, float *feat, float *label, int32_t *node,
-                int32_t *body, int64_t *total) {
+                int32_t *group, int64_t *total) {
     bh_ctx *c = t->ctx;
     const int n = (int)t->n;
-    int rc = mlp_features(t, eps);
+    const int ng = div_up(n, 64);
+    int rc = grow(c->mlp_scratch, 4ull * ng + 8ull * (ng + 1) + 8);
     if (rc) return rc;
-    if ((rc = grow(c->mlp_scratch, 4ull * n + 8ull * (n + 1) + 8))) return rc;
     int32_t *cnt = (int32_t *)c->mlp_scratch.p;
-    int64_t *offs = (int64_t *)((char *)c->mlp_scratch.p + 4ull * n + (4ull * n) % 8);
-    const int nblk = div_up(div_up(n, 64), 4);
+    int64_t *offs = (int64_t *)((char *)c->mlp_scratch.p + 4ull * ng + (4ull * ng) % 8);
+    const int nblk = div_up(ng, 4);
     const NodeRec64 *nodes = (const NodeRec64 *)t->recs.p;
     const auto *bodies = (const BodyRec<double> *)t->bodies.p;
     const auto *anchors = (const Anchor<double> *)t->anchors.p;
-    const float *cf = (const float *)t->cellf.p;
-    k_mac_samples<<<nblk, 256, 0, c->stream>>>(nodes, (int)t->m, bodies, anchors, cf, n,
-                                               theta_lo * theta_lo, theta_max * theta_max, eps, keep,
-                                               seed, cnt, nullptr, 0, nullptr, nullptr, nullptr,
-                                               nullptr);
-    k_scan_counts<<<1, 1024, 0, c->stream>>>(cnt, n, offs);
+    k_group_samples<<<nblk, 256, 0, c->stream>>>(nodes, (int)t->m, bodies, anchors, n, 0, n,
+                                                 theta_lo * theta_lo, theta_max * theta_max, eps,
+                                                 keep, seed, cnt, nullptr, 0, nullptr, nullptr,
+                                                 nullptr, nullptr);
+    k_scan_counts<<<1, 1024, 0, c->stream>>>(cnt, ng, offs);
     int64_t *hp = (int64_t *)((char *)c->pinned + 2048);
     if ((rc = check_launch("mlp samples")) ||
-        hipMemcpyAsync(hp, offs + n, 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(hp, offs + ng, 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
         return rc ? rc : set_error(BH_E_DEVICE, "sample count copy failed");
     *total = hp[0];
     if (!feat) return BH_OK;
     if (*total > cap)
         return set_error(BH_E_INVALID, "sample capacity too small: need " + std::to_string(*total));
-    k_mac_samples<<<nblk, 256, 0, c->stream>>>(nodes, (int)t->m, bodies, anchors, cf, n,
-                                               theta_lo * theta_lo, theta_max * theta_max, eps, keep,
-                                               seed, nullptr, offs, cap, feat, label, node, body);
+    k_group_samples<<<nblk, 256, 0, c->stream>>>(nodes, (int)t->m, bodies, anchors, n, 0, n,
+                                                 theta_lo * theta_lo, theta_max * theta_max, eps,
+                                                 keep, seed, nullptr, offs, cap, feat, label, node,
+                                                 group);
     return check_launch("mlp samples");
 }
 

@@ -84,14 +84,48 @@ __device__ __forceinline__ void leaf_pp(const BodyRec<R> *__restrict__ bodies, i
     if (PHI) sp += pq;
 }
 
-// Learned-criterion parameters of a walk: per cell k_C M l^3, per sorted
-// rank |a_i|, the floor of |a_i| (device scalar), theta_max^2 and tau.
+// Relative criteria of a walk (MAC: 0 opening angle, 1 error budget with
+// k_C = 1, 2 / 3 the learned criterion with bf16 / fp16 network operands):
+// per cell M l^3 (budget), per sorted rank |a_i|, the floor of |a_i|
+// (device scalar), theta_max^2, tau, the packed network and the softening.
 struct MlpMac {
     const float *kc;
     const float *anorm;
     const float *afloor;
     float tmax2, tau;
+    const MlpPacked *net;
+    float eps;
+    const void *oct;  // order 3: octopole records, 8 values per node
 };
+
+template <int MAC> struct NetVec { using type = bf16x8; };
+
+// The octopole term of a particle-cell interaction (order 3; Sec. 2.2, the
+// l = 3 term): from o = (xxx xxy xxz xyy xyz yyy yyz), the traceless
+// octopole's independent components, and x = body - COM, adds
+// (O:xx) / (2 s^7) - (7/6) (O:xxx) x / s^9 to the acceleration and
+// -(O:xxx) / (6 s^7) to the potential; inv2 = 1/s^2, inv5 = 1/s^5.
+template <typename R, bool PHI>
+__device__ __forceinline__ void oct_term(const R *o, R x, R y, R z, R inv2, R inv5, R &sx,
+                                         R &sy, R &sz, R &sp) {
+    const R xzz = -o[0] - o[3], yzz = -o[1] - o[5], zzz = -o[2] - o[6];
+    const R xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+    const R vx = o[0] * xx + o[3] * yy + xzz * zz + (R)2 * (o[1] * xy + o[2] * xz + o[4] * yz);
+    const R vy = o[1] * xx + o[5] * yy + yzz * zz + (R)2 * (o[3] * xy + o[4] * xz + o[6] * yz);
+    const R vz = o[2] * xx + o[6] * yy + zzz * zz + (R)2 * (o[4] * xy + xzz * xz + yzz * yz);
+    const R t3 = x * vx + y * vy + z * vz;
+    const R inv7 = inv5 * inv2;
+    const R c = (R)(7.0 / 6.0) * t3 * inv2;
+    sx = inv7 * ((R)0.5 * vx - c * x) + sx;
+    sy = inv7 * ((R)0.5 * vy - c * y) + sy;
+    sz = inv7 * ((R)0.5 * vz - c * z) + sz;
+    if (PHI) sp = sp - t3 * inv7 * (R)(1.0 / 6.0);
+}
+template <> struct NetVec<3> { using type = f16x8; };
+
+__device__ __forceinline__ float lg10(float x) {
+    return __builtin_amdgcn_logf(x) * 0.30102999566398120f;
+}
 
 // The per-body walk of one wavefront (see the file header): lane body i
 // (live), its offset (ox, oy, oz) from its leaf centre (ax, ay, az), leaf
@@ -99,8 +133,8 @@ struct MlpMac {
 // successor records are loaded while a node is processed: this shortens the
 // dependent chain of a lone wavefront (the group walk's per-body fallback)
 // but costs the register file the occupancy that hides it in a full launch.
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool MLP, bool PF = false,
-          bool GUARD = false>
+template <typename R, bool ORDER2, bool PHI, bool CNT, int MAC, bool PF = false,
+          bool GUARD = false, bool OCT = false>
 __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__restrict__ nodes,
                                            int m, const BodyRec<R> *__restrict__ bodies,
                                            int nbodies, int i, bool live, R ox, R oy, R oz,
@@ -109,7 +143,9 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
                                            uint32_t &cpp, uint32_t &cpc) {
     using Rec = typename NodeRecT<R>::type;
     float tau_a = 0.f;  // tau |a_i|
-    if (MLP && live) tau_a = mac.tau * fmaxf(mac.anorm[i], *mac.afloor);
+    if (MAC >= 1 && live) tau_a = mac.tau * fmaxf(mac.anorm[i], *mac.afloor);
+    const float lt = MAC >= 2 && live ? lg10(tau_a) : 0.f;
+    const int lane = (int)lane_id();
 
     const bool root_leaf = nodes[0].next == 1;
     int idx = root_leaf ? 0 : 1;
@@ -140,14 +176,33 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
             const R x = X - nd.mx, y = Y - nd.my, z = Z - nd.mz;
             const R d2 = x * x + y * y + z * z;
             bool accept;
-            if (MLP) {
-                // predicted error k_C (l/d)^3 M/d^2 below tau |a_i|, l/d below
+            if (MAC == 1) {
+                // error budget: M l^3 / d^5 below tau |a_i|, l/d below
                 // theta_max, and the body outside the cell
                 const float kcv = mac.kc[idx];
                 const R hs = (R)0.5 * sqrt(nd.l2);
                 const bool inside = fabs(X) <= hs && fabs(Y) <= hs && fabs(Z) <= hs;
                 accept = act && nd.l2 < (R)mac.tmax2 * d2 && !inside &&
                          kcv < tau_a * (d2 * d2 * sqrt(d2));
+            } else if (MAC >= 2) {
+                // learned, the body as its own group: the network's error
+                // for (body, cell) below tau |a_i|, l/d below theta_max, the
+                // body outside the cell; one 64-row batch per node
+                const R hs = (R)0.5 * sqrt(nd.l2);
+                const bool inside = fabs(X) <= hs && fabs(Y) <= hs && fabs(Z) <= hs;
+                const bool cand = act && nd.l2 < (R)mac.tmax2 * d2 && !inside && nd.m > (R)0;
+                accept = false;
+                if (__ballot(cand)) {  // wave-uniform: the MFMAs need every lane
+                    float f[kMlpIn] = {};
+                    if (cand)
+                        gfeatures<R>(-x, -y, -z, (R)0, (R)0, (R)0, nd.mx, nd.my, nd.mz, nd.m,
+                                     nd.qxx, nd.qxy, nd.qxz, nd.qyy, nd.qyz, nd.l2, cnt,
+                                     nxt == idx + 1, (R)mac.eps, f);
+                    const float pred =
+                        mlp_eval_p<typename NetVec<MAC>::type>(mac.net, f, lane);
+                    accept = cand && pred + lg10((float)nd.m) + 1.5f * lg10((float)nd.l2) -
+                                             2.5f * lg10((float)d2) < lt;
+                }
             } else {
                 accept = act && nd.l2 < theta2 * d2;
                 // containment guard: a cell holding the body is opened.  Below
@@ -178,6 +233,9 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
                     sy = -g * y + sy;
                     sz = -g * z + sz;
                     if (PHI) sp = sp - nd.m * inv - (R)0.5 * t5;
+                    if (OCT)
+                        oct_term<R, PHI>((const R *)mac.oct + 8 * (int64_t)idx, x, y, z, inv2,
+                                         inv5, sx, sy, sz, sp);
                 } else {
                     const R g = nd.m * inv3;
                     sx = -g * x + sx;
@@ -206,8 +264,8 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
     }
 }
 
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool MLP,
-          bool GUARD>
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, int MAC,
+          bool GUARD, bool OCT>
 __global__ __launch_bounds__(256) void k_walk(
     const typename NodeRecT<R>::type *__restrict__ nodes, int m,
     const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
@@ -244,7 +302,7 @@ __global__ __launch_bounds__(256) void k_walk(
     }
     R sx = 0, sy = 0, sz = 0, sp = 0;
     uint32_t cpp = 0, cpc = 0;
-    body_sweep<R, ORDER2, PHI, CNT, MLP, false, GUARD>(nodes, m, bodies, nbodies, i, live, ox,
+    body_sweep<R, ORDER2, PHI, CNT, MAC, false, GUARD, OCT>(nodes, m, bodies, nbodies, i, live, ox,
                                                        oy, oz, ax, ay, az, myleaf, theta2, eps2,
                                                        mac, sx, sy, sz, sp, cpp, cpc);
     if (live) {
@@ -260,27 +318,29 @@ __global__ __launch_bounds__(256) void k_walk(
     }
 }
 
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED, bool MLP, bool GUARD>
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED, int MAC, bool GUARD,
+          bool OCT>
 void launch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
             uint32_t *npp, uint32_t *npc, const MlpMac &mac) {
     const int nw = div_up(t1 - t0, 64);
     const int nblk = div_up(nw, 4);
     const int nblk_pad = div_up(nblk, 64) * 64;
     if (t->ctx->walk_ev) hipEventRecord(t->ctx->walk_ev[0], t->ctx->stream);
-    k_walk<R, ORDER2, PHI, CNT, SORTED, MLP, GUARD><<<nblk_pad, 256, 0, t->ctx->stream>>>(
+    k_walk<R, ORDER2, PHI, CNT, SORTED, MAC, GUARD, OCT><<<nblk_pad, 256, 0, t->ctx->stream>>>(
         (const typename NodeRecT<R>::type *)t->recs.p, (int)t->m,
         (const BodyRec<R> *)t->bodies.p, (const Anchor<R> *)t->anchors.p, t->perm, (int)t->n, t0,
         t1, nblk_pad * 4, (R)(theta * theta), (R)(eps * eps), (R *)acc, (R *)phi, npp, npc, mac);
     if (t->ctx->walk_ev) hipEventRecord(t->ctx->walk_ev[1], t->ctx->stream);
 }
 
-template <typename R, bool ORDER2, bool MLP, bool GUARD = false>
+template <typename R, bool ORDER2, int MAC, bool GUARD = false, bool OCT = false>
 void dispatch2(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
                uint32_t *npp, uint32_t *npc, bool sorted, const MlpMac &mac) {
     const bool P = phi != nullptr, C = npp != nullptr;
-#define BH_W(p, c, s) launch<R, ORDER2, p, c, s, MLP, GUARD>(t, t0, t1, theta, eps, acc, phi, npp, npc, mac)
-    if (sorted) {
+#define BH_W(p, c, s) launch<R, ORDER2, p, c, s, MAC, GUARD, OCT>(t, t0, t1, theta, eps, acc, phi, npp, npc, mac)
+    if (sorted) {  // simulation walks: phi for the energy, counts when recorded
         if (P) BH_W(true, false, true);
+        else if (C) BH_W(false, true, true);
         else BH_W(false, false, true);
     } else if (P && C) BH_W(true, true, false);
     else if (P) BH_W(true, false, false);
@@ -315,7 +375,8 @@ constexpr int kGroupStack = 640;       // LDS stack entries per wavefront
 constexpr int kStageW = 12;            // LDS words per staged accepted cell
 // bodies of particle-particle leaves staged per batch (4 words each, in the
 // same LDS as the accepted cells)
-constexpr int kPPStage = 64 * kStageW / 4;
+// with the octopole (order 3) a staged cell also carries its 7 components
+template <bool OCT> struct StageW { static constexpr int value = OCT ? 20 : kStageW; };
 // Default per-group work caps: a fallback walks the group per body at a
 // quarter of the lanes, so the cap sits near three times a typical group's
 // work (about 1300 per body for the error budget, 1600-2200 for the learned
@@ -324,7 +385,7 @@ constexpr int kGroupWorkCap = 6144;        // opening angle, learned criterion
 constexpr int kGroupWorkCapBudget = 4096;  // error budget with k_C = 1
 
 struct GroupMac {
-    const float *kc;     // error budget: k_C M l^3 per node
+    const float *kc;     // error budget: M l^3 per node (k_C = 1)
     const float *anorm;  // |a_i| per sorted rank
     const float *afloor;  // floor of |a_i| (device scalar)
     float tau;
@@ -340,6 +401,9 @@ struct GroupMac {
     // the length of its last prediction; or null
     uint8_t *gfb;
     int predict_first;   // walks predicted after a first excess
+    const MlpPacked *net;  // learned criterion: the packed network
+    float eps;             // and the softening (a feature)
+    const void *oct;       // order 3: octopole records, 8 values per node
 };
 
 // A group that exceeded the work cap is walked per body straight away (in
@@ -379,10 +443,11 @@ __device__ __forceinline__ int wave_min_i(int v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-enum : int { kGNone = 0, kGPC = 1, kGPP = 2, kGOpen = 3 };
+// kGCand: a candidate of the learned criterion, decided by the network
+enum : int { kGNone = 0, kGPC = 1, kGPP = 2, kGOpen = 3, kGCand = 4 };
 
 // One group: the 64 bodies of sorted rank [base, min(base + 64, t1)).
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool BUDGET>
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, int MAC, bool OCT>
 __device__ __forceinline__ auto group_walk(
     const typename NodeRecT<R>::type *__restrict__ nodes, int m,
     const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
@@ -392,6 +457,8 @@ __device__ __forceinline__ auto group_walk(
     int *__restrict__ stk, R *__restrict__ stage, const int8_t *__restrict__ delta,
     const int32_t *__restrict__ level) -> bool {
     using Rec = typename NodeRecT<R>::type;
+    constexpr int SW = StageW<OCT>::value;    // LDS words per staged cell
+    constexpr int PPS = 64 * SW / 4;          // bodies per particle-particle batch
     const int lane = (int)lane_id();
     const int i = base + lane;
     const bool live = i < t1;
@@ -435,8 +502,9 @@ __device__ __forceinline__ auto group_walk(
         const R bcx = (R)0.5 * (lx + hx), bcy = (R)0.5 * (ly + hy), bcz = (R)0.5 * (lz + hz);
         const R bhx = (R)0.5 * (hx - lx), bhy = (R)0.5 * (hy - ly), bhz = (R)0.5 * (hz - lz);
         float tau_amin = 0.f;
-        if (BUDGET)
+        if (MAC >= 1)
             tau_amin = gm.tau * fmaxf(wave_min(live_run ? gm.anorm[i] : 3.0e38f), *gm.afloor);
+        const float lt = MAC >= 2 ? lg10(tau_amin) : 0.f;  // log10(tau a_min)
 
         R sx = 0, sy = 0, sz = 0, sp = 0;
         uint32_t cpp = 0, cpc = 0;
@@ -454,12 +522,34 @@ __device__ __forceinline__ auto group_walk(
             const R tz = fmax(fabs(uz + nd.mz) - bhz, (R)0);
             const R dg2 = tx * tx + ty * ty + tz * tz;
             bool accept = !overlap && nd.l2 < theta2 * dg2;
-            if (BUDGET) accept = accept && kcv < tau_amin * (float)(dg2 * dg2 * sqrt(dg2));
+            if (MAC == 1) accept = accept && kcv < tau_amin * (float)(dg2 * dg2 * sqrt(dg2));
+            if (MAC >= 2 && accept && nd.m > (R)0) return kGCand;  // the network decides
+            if (MAC >= 2) accept = false;
             if (accept) return kGPC;
             return nd.next == c + 1 ? kGPP : kGOpen;
         };
+        // the learned decision for the candidates among the lanes' nodes:
+        // every lane calls (the MFMAs need the whole wave); cls is updated
+        // on the candidate lanes
+        auto learn = [&](const Rec &nd, int c, int &cls) {
+            float f[kMlpIn] = {};
+            R dg2 = (R)1;
+            if (cls == kGCand) {
+                const R ux = ((nd.cx - gx) - bcx) + nd.mx, uy = ((nd.cy - gy) - bcy) + nd.my,
+                        uz = ((nd.cz - gz) - bcz) + nd.mz;
+                dg2 = gfeatures<R>(ux, uy, uz, bhx, bhy, bhz, nd.mx, nd.my, nd.mz, nd.m, nd.qxx,
+                                   nd.qxy, nd.qxz, nd.qyy, nd.qyz, nd.l2, nd.count,
+                                   nd.next == c + 1, (R)gm.eps, f);
+            }
+            const float pred = mlp_eval_p<typename NetVec<MAC>::type>(gm.net, f, lane);
+            if (cls == kGCand)
+                cls = pred + lg10((float)nd.m) + 1.5f * lg10((float)nd.l2) -
+                                  2.5f * lg10((float)dg2) < lt
+                          ? kGPC
+                          : (nd.next == c + 1 ? kGPP : kGOpen);
+        };
         // particle-cell term of node nd for this lane's body
-        auto cell_term = [&](const Rec &nd) {
+        auto cell_term = [&](const Rec &nd, int c) {
             const R X = (ax - nd.cx) + ox, Y = (ay - nd.cy) + oy, Z = (az - nd.cz) + oz;
             const R x = X - nd.mx, y = Y - nd.my, z = Z - nd.mz;
             const R d2 = x * x + y * y + z * z;
@@ -482,6 +572,9 @@ __device__ __forceinline__ auto group_walk(
                 sy = -g * y + sy;
                 sz = -g * z + sz;
                 if (PHI) sp = sp - nd.m * inv - (R)0.5 * t5;
+                if (OCT)
+                    oct_term<R, PHI>((const R *)gm.oct + 8 * (int64_t)c, x, y, z, inv2, inv5, sx,
+                                     sy, sz, sp);
             } else {
                 const R g = nd.m * inv3;
                 sx = -g * x + sx;
@@ -512,6 +605,7 @@ __device__ __forceinline__ auto group_walk(
                 sy = inv5 * (qy - c * y) + sy;
                 sz = inv5 * (qz - c * z) + sz;
                 if (PHI) sp = sp - m * inv - (R)0.5 * (xqx * inv5);
+                if (OCT) oct_term<R, PHI>(st + 10, x, y, z, inv2, inv5, sx, sy, sz, sp);
             } else {
                 const R inv3 = inv * inv2;
                 const R g = m * inv3;
@@ -540,8 +634,12 @@ __device__ __forceinline__ auto group_walk(
             while (idx < end && work <= gm.work_cap) {
                 idx = uniform(idx);
                 const Rec nd = nodes[idx];
-                const int cls = uniform(classify(nd, idx, BUDGET ? gm.kc[idx] : 0.f));
-                if (cls == kGPC) cell_term(nd);
+                int cls = uniform(classify(nd, idx, MAC == 1 ? gm.kc[idx] : 0.f));
+                if (MAC >= 2 && cls == kGCand) {
+                    learn(nd, idx, cls);
+                    cls = uniform(cls);
+                }
+                if (cls == kGPC) cell_term(nd, idx);
                 else if (cls == kGPP) leaf_terms(nd);
                 const int nx = uniform(nd.next);
                 idx = cls == kGOpen || nx <= idx ? idx + 1 : nx;  // always moves forward
@@ -564,10 +662,21 @@ __device__ __forceinline__ auto group_walk(
                 int4 k0 = make_int4(-1, -1, -1, -1), k1 = k0;
                 Rec nd{};
                 if (has) {
-                    k0 = kids[2 * (int64_t)c];  // loaded with the record, used if opened
-                    k1 = kids[2 * (int64_t)c + 1];
+                    if (MAC < 2) {
+                        k0 = kids[2 * (int64_t)c];  // loaded with the record, used if opened
+                        k1 = kids[2 * (int64_t)c + 1];
+                    }
                     nd = nodes[c];
-                    cls = classify(nd, c, BUDGET ? gm.kc[c] : 0.f);
+                    cls = classify(nd, c, MAC == 1 ? gm.kc[c] : 0.f);
+                }
+                if (MAC >= 2) {
+                    // the children after the network (fewer registers live
+                    // across its evaluation)
+                    if (__ballot(cls == kGCand)) learn(nd, c, cls);
+                    if (cls == kGOpen) {
+                        k0 = kids[2 * (int64_t)c];
+                        k1 = kids[2 * (int64_t)c + 1];
+                    }
                 }
                 const uint64_t m_pc = __ballot(cls == kGPC);
                 const uint64_t m_pp = __ballot(cls == kGPP);
@@ -575,7 +684,7 @@ __device__ __forceinline__ auto group_walk(
                 if (cls == kGPC) {  // stage the accepted cell for every lane
                     const int slot = (int)__builtin_amdgcn_mbcnt_hi(
                         (uint32_t)(m_pc >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m_pc, 0u));
-                    R *st = stage + kStageW * slot;
+                    R *st = stage + SW * slot;
                     st[0] = (nd.cx - gx) + nd.mx;
                     st[1] = (nd.cy - gy) + nd.my;
                     st[2] = (nd.cz - gz) + nd.mz;
@@ -586,6 +695,10 @@ __device__ __forceinline__ auto group_walk(
                     st[7] = nd.qyy;
                     st[8] = nd.qyz;
                     st[9] = -nd.qxx - nd.qyy;
+                    if (OCT) {
+                        const R *o = (const R *)gm.oct + 8 * (int64_t)c;
+                        for (int q = 0; q < 7; ++q) st[10 + q] = o[q];
+                    }
                 }
                 if (m_op) {
                     const int kid[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
@@ -620,7 +733,7 @@ __device__ __forceinline__ auto group_walk(
                 // accepted cells from LDS (same address on every lane: broadcast)
                 const int npc_round = __builtin_popcountll(m_pc);
                 __builtin_amdgcn_wave_barrier();
-                for (int q = 0; q < npc_round; ++q) staged_term(stage + kStageW * q);
+                for (int q = 0; q < npc_round; ++q) staged_term(stage + SW * q);
                 work += npc_round;
                 // particle-particle leaves (and one-body cells) of the round.
                 // The bodies of those that hold none of the group's bodies are
@@ -646,7 +759,7 @@ __device__ __forceinline__ auto group_walk(
                         const int v = __shfl_up(incl, o);
                         if (lane >= o) incl += v;
                     }
-                    const bool fits = mine && incl <= kPPStage;
+                    const bool fits = mine && incl <= PPS;
                     const uint64_t put = __ballot(fits);
                     if (put == 0) {  // the first pending leaf alone does not fit
                         const int bit = __builtin_ctzll(pend);
@@ -702,8 +815,8 @@ __device__ __forceinline__ auto group_walk(
         if (per_body) {  // too spread out for one decision: walk per body
             sx = sy = sz = sp = 0;
             cpp = cpc = 0;
-            const MlpMac pm{gm.kc, gm.anorm, gm.afloor, (float)theta2, gm.tau};
-            body_sweep<R, ORDER2, PHI, CNT, BUDGET, true>(nodes, m, bodies, nbodies, i, live_run, ox, oy, oz,
+            const MlpMac pm{gm.kc, gm.anorm, gm.afloor, (float)theta2, gm.tau, gm.net, gm.eps, gm.oct};
+            body_sweep<R, ORDER2, PHI, CNT, MAC, (MAC < 2), false, OCT>(nodes, m, bodies, nbodies, i, live_run, ox, oy, oz,
                                                     ax, ay, az, myleaf, theta2, eps2, pm, sx, sy, sz,
                                                     sp, cpp, cpc);
         }
@@ -740,7 +853,7 @@ __device__ __forceinline__ auto group_walk(
 // base (one part of a group predicted to exceed the work cap); the other
 // lanes idle.  Each body's walk is the per-body walk's, whichever bodies share
 // the wavefront.
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool BUDGET>
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, int MAC, bool OCT>
 __device__ __forceinline__ void part_walk(
     const typename NodeRecT<R>::type *__restrict__ nodes, int m,
     const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
@@ -765,8 +878,8 @@ __device__ __forceinline__ void part_walk(
     }
     R sx = 0, sy = 0, sz = 0, sp = 0;
     uint32_t cpp = 0, cpc = 0;
-    const MlpMac pm{gm.kc, gm.anorm, gm.afloor, (float)theta2, gm.tau};
-    body_sweep<R, ORDER2, PHI, CNT, BUDGET, true>(nodes, m, bodies, nbodies, i, live, ox, oy, oz,
+    const MlpMac pm{gm.kc, gm.anorm, gm.afloor, (float)theta2, gm.tau, gm.net, gm.eps, gm.oct};
+    body_sweep<R, ORDER2, PHI, CNT, MAC, (MAC < 2), false, OCT>(nodes, m, bodies, nbodies, i, live, ox, oy, oz,
                                                   ax, ay, az, myleaf, theta2, eps2, pm, sx, sy, sz,
                                                   sp, cpp, cpc);
     if (live) {
@@ -788,8 +901,8 @@ __device__ __forceinline__ void part_walk(
 // and every resident wavefront takes the next group of its chunk from an
 // atomic counter until the chunk is done.  A heavy group then delays only
 // the wavefront that drew it.
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, bool BUDGET>
-__global__ __launch_bounds__(256) void k_gwalk(
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, int MAC, bool OCT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAC >= 2 ? 4 : 1))) void k_gwalk(
     const typename NodeRecT<R>::type *__restrict__ nodes, int m,
     const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
     const int4 *__restrict__ kids, const uint32_t *__restrict__ perm, int nbodies, int t0,
@@ -797,9 +910,17 @@ __global__ __launch_bounds__(256) void k_gwalk(
     R *__restrict__ phi_out, uint32_t *__restrict__ npp_out, uint32_t *__restrict__ npc_out,
     GroupMac gm, const int8_t *__restrict__ delta, const int32_t *__restrict__ level) {
     __shared__ int stack_all[4][kGroupStack];
-    __shared__ R stage_all[4][64 * kStageW];
+    __shared__ R stage_all[4][64 * StageW<OCT>::value];
+    // the learned criterion's network, staged once per workgroup
+    __shared__ u32x4 net_lds[MAC >= 2 ? sizeof(MlpPacked) / 16 : 1];
     int *stk = stack_all[threadIdx.x >> 6];
     R *stage = stage_all[threadIdx.x >> 6];
+    if (MAC >= 2) {
+        const u32x4 *src = (const u32x4 *)gm.net;
+        for (int k = threadIdx.x; k < (int)(sizeof(MlpPacked) / 16); k += 256) net_lds[k] = src[k];
+        __syncthreads();
+        gm.net = (const MlpPacked *)net_lds;
+    }
     const int ng = (t1 - t0 + 63) / 64;
     const int xcd = (int)(blockIdx.x & 7);
     const int chunk = (ng + 7) / 8;
@@ -819,12 +940,12 @@ __global__ __launch_bounds__(256) void k_gwalk(
             code = (int)(it & 15u);
         }
         if (code < kParts) {
-            part_walk<R, ORDER2, PHI, CNT, SORTED_OUT, BUDGET>(
+            part_walk<R, ORDER2, PHI, CNT, SORTED_OUT, MAC, OCT>(
                 nodes, m, bodies, anchors, perm, nbodies, t0 + 64 * g, kPartLanes * code, t1,
                 theta2, eps2, acc, phi_out, npp_out, npc_out, gm);
             continue;
         }
-        const bool fell = group_walk<R, ORDER2, PHI, CNT, SORTED_OUT, BUDGET>(
+        const bool fell = group_walk<R, ORDER2, PHI, CNT, SORTED_OUT, MAC, OCT>(
             nodes, m, bodies, anchors, kids, perm, nbodies, t0 + 64 * g, t1, theta2, eps2, acc,
             phi_out, npp_out, npc_out, gm, stk, stage, delta, level);
         if (gm.gfb && lane_id() == 0) {
@@ -951,7 +1072,7 @@ __global__ void k_zero_bytes(uint8_t *p, int64_t n) {
 
 __global__ void k_zero_queue(uint32_t *q) { q[threadIdx.x] = 0u; }  // 512 threads
 
-template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED, bool BUDGET>
+template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED, int MAC, bool OCT>
 void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
              uint32_t *npp, uint32_t *npc, const GroupMac &gm, uint64_t sig) {
     // enough workgroups to fill every CU (8 per CU at this kernel's
@@ -988,7 +1109,7 @@ void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, vo
         g2.gfb = gfb;
     }
     if (t->ctx->walk_ev) hipEventRecord(t->ctx->walk_ev[0], t->ctx->stream);
-    k_gwalk<R, ORDER2, PHI, CNT, SORTED, BUDGET><<<8 * per_xcd, 256, 0, t->ctx->stream>>>(
+    k_gwalk<R, ORDER2, PHI, CNT, SORTED, MAC, OCT><<<8 * per_xcd, 256, 0, t->ctx->stream>>>(
         (const typename NodeRecT<R>::type *)t->recs.p, (int)t->m,
         (const BodyRec<R> *)t->bodies.p, (const Anchor<R> *)t->anchors.p,
         (const int4 *)t->kids.p, t->perm, (int)t->n, t0, t1, queue, (R)(theta * theta),
@@ -997,13 +1118,14 @@ void glaunch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, vo
     if (t->ctx->walk_ev) hipEventRecord(t->ctx->walk_ev[1], t->ctx->stream);
 }
 
-template <typename R, bool ORDER2, bool BUDGET>
+template <typename R, bool ORDER2, int MAC, bool OCT = false>
 void gdispatch(bh_tree *t, int t0, int t1, double theta, double eps, void *acc, void *phi,
                uint32_t *npp, uint32_t *npc, bool sorted, const GroupMac &gm, uint64_t sig) {
     const bool P = phi != nullptr, C = npp != nullptr;
-#define BH_G(p, c, s) glaunch<R, ORDER2, p, c, s, BUDGET>(t, t0, t1, theta, eps, acc, phi, npp, npc, gm, sig)
-    if (sorted) {
+#define BH_G(p, c, s) glaunch<R, ORDER2, p, c, s, MAC, OCT>(t, t0, t1, theta, eps, acc, phi, npp, npc, gm, sig)
+    if (sorted) {  // simulation walks: phi for the energy, counts when recorded
         if (P) BH_G(true, false, true);
+        else if (C) BH_G(false, true, true);
         else BH_G(false, false, true);
     } else if (P && C) BH_G(true, true, false);
     else if (P) BH_G(true, false, false);
@@ -1069,7 +1191,8 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
     if (o.mac == BH_MAC_MLP || o.mac == BH_MAC_BUDGET) {
         if (t->dtype != BH_F32 || o.order != 2)
             return set_error(BH_E_INVALID, "the learned criterion runs in the FP32 quadrupole walk");
-        int rc = mlp_cells(t, eps, o.mac == BH_MAC_MLP, o.mlp_precision);
+        const bool learned = o.mac == BH_MAC_MLP;
+        int rc = learned ? BH_OK : mlp_cells(t);
         if (rc) return rc;
         if (o.mlp_acc_norm) {
             rc = mlp_anorm(t, nullptr, o.mlp_acc_norm, true, o.mlp_acc_floor);
@@ -1092,44 +1215,66 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
             rc = mlp_anorm(t, t->est_acc.p, nullptr, false, o.mlp_acc_floor);
         }
         if (rc) return rc;
-        mac.kc = (const float *)t->kc.p;
+        mac.kc = learned ? nullptr : (const float *)t->kc.p;
         mac.anorm = (const float *)t->anorm.p;
         mac.afloor = mlp_anorm_floor(t);
         mac.tmax2 = (float)(o.mlp_theta_max * o.mlp_theta_max);
         mac.tau = (float)pow(10.0, o.mlp_log10_tau);
+        mac.net = learned ? (const MlpPacked *)t->ctx->mlp_w.p + o.mlp_precision : nullptr;
+        mac.eps = (float)eps;
+        const bool f16 = o.mlp_precision == BH_MLP_FP16;
         if (group) {
             gm.kc = mac.kc;
             gm.anorm = mac.anorm;
             gm.afloor = mac.afloor;
             gm.tau = mac.tau;
-            gdispatch<float, true, true>(t, t0, t1, o.mlp_theta_max, eps, acc, phi, npp, npc,
-                                         sorted_out, gm, sig);
+            gm.net = mac.net;
+            gm.eps = mac.eps;
+#define BH_GM(k) gdispatch<float, true, k>(t, t0, t1, o.mlp_theta_max, eps, acc, phi, npp, npc, sorted_out, gm, sig)
+            if (!learned) BH_GM(1);
+            else if (f16) BH_GM(3);
+            else BH_GM(2);
+#undef BH_GM
         } else {
-            dispatch2<float, true, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out,
-                                         mac);
+#define BH_BM(k) dispatch2<float, true, k>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac)
+            if (!learned) BH_BM(1);
+            else if (f16) BH_BM(3);
+            else BH_BM(2);
+#undef BH_BM
+        }
+    } else if (o.order == 3) {  // the opening angle with the octopole term
+        int rc = ensure_octopole(t);
+        if (rc) return rc;
+        gm.oct = mac.oct = t->oct.p;
+        if (group) {
+            if (t->dtype == BH_F32) gdispatch<float, true, 0, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
+            else gdispatch<double, true, 0, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
+        } else {
+            if (t->dtype == BH_F32) dispatch2<float, true, 0, false, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+            else dispatch2<double, true, 0, false, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
         }
     } else if (group) {
         if (t->dtype == BH_F32) {
-            if (o.order == 0) gdispatch<float, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
-            else gdispatch<float, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
+            if (o.order == 0) gdispatch<float, false, 0>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
+            else gdispatch<float, true, 0>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
         } else {
-            if (o.order == 0) gdispatch<double, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
-            else gdispatch<double, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
+            if (o.order == 0) gdispatch<double, false, 0>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
+            else gdispatch<double, true, 0>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, gm, sig);
         }
     } else if (o.mac == BH_MAC_THETA_GUARD) {  // per-body walk only (checked by the caller)
         if (t->dtype == BH_F32) {
-            if (o.order == 0) dispatch2<float, false, false, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
-            else dispatch2<float, true, false, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+            if (o.order == 0) dispatch2<float, false, 0, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+            else dispatch2<float, true, 0, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
         } else {
-            if (o.order == 0) dispatch2<double, false, false, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
-            else dispatch2<double, true, false, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+            if (o.order == 0) dispatch2<double, false, 0, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+            else dispatch2<double, true, 0, true>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
         }
     } else if (t->dtype == BH_F32) {
-        if (o.order == 0) dispatch2<float, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
-        else dispatch2<float, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+        if (o.order == 0) dispatch2<float, false, 0>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+        else dispatch2<float, true, 0>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
     } else {
-        if (o.order == 0) dispatch2<double, false, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
-        else dispatch2<double, true, false>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+        if (o.order == 0) dispatch2<double, false, 0>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+        else dispatch2<double, true, 0>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
     }
     return check_launch("walk");
 }

@@ -117,7 +117,7 @@ def test_full_size_sampled_against_oracle(ctx, name):
             ("theta 0.7", gacc, gpp, gpc, dict(theta=0.7, cap=CAP_THETA)),
             ("budget", bacc, bpp, bpc, dict(
                 mode=1, theta_max=BUDGET["theta_max"], tau=10 ** BUDGET["log10_tau"],
-                kc=oracle.cell_kc(ref, eps), anorm=an_sorted, floor=BUDGET["floor"],
+                kc=oracle.cell_kc(ref), anorm=an_sorted, floor=BUDGET["floor"],
                 cap=CAP_BUDGET))):
         a, cp, cc = a[p], cp[p], cc[p]
         checked = 0

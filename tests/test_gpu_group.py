@@ -9,6 +9,8 @@ from paper_2203_08966_amd import binding as B
 from paper_2203_08966_amd import workloads as W
 from tests.conftest import case_bodies, check_flagged, say
 
+NO_CAP = 1 << 40
+
 pytestmark = pytest.mark.gpu
 
 
@@ -139,7 +141,7 @@ def test_group_budget_matches_oracle(ctx):
     out = _run(ctx, pos, mass, 16, 0.5, eps, mac=B.BH_MAC_BUDGET, mlp_theta_max=tmax,
                mlp_log10_tau=np.log10(tau), acc_norm=an, walk_cap=CAP_BUDGET)
     r = oracle.walk_group(ref, eps, group=B.BH_GROUP_BODIES, mode=1, theta_max=tmax, tau=tau,
-                          kc=oracle.cell_kc(ref, eps), anorm=an.astype(np.float64)[ref["perm"]],
+                          kc=oracle.cell_kc(ref), anorm=an.astype(np.float64)[ref["perm"]],
                           tol=FLAG_TOL[np.float32], cap=CAP_BUDGET, split=True)
     _check(ref, r, out, np.float32, eps)
 
@@ -157,7 +159,7 @@ def test_group_budget_floor_matches_oracle(ctx):
     say(f"group budget walk, floor {fl}: 20000 bodies, tau {tau:.3g}, theta_max {tmax}")
     out = _run(ctx, pos, mass, 16, 0.5, eps, mac=B.BH_MAC_BUDGET, mlp_theta_max=tmax,
                mlp_log10_tau=np.log10(tau), acc_norm=an, mlp_acc_floor=fl, walk_cap=CAP_BUDGET)
-    args = dict(group=B.BH_GROUP_BODIES, mode=1, theta_max=tmax, tau=tau, kc=oracle.cell_kc(ref, eps),
+    args = dict(group=B.BH_GROUP_BODIES, mode=1, theta_max=tmax, tau=tau, kc=oracle.cell_kc(ref),
                 anorm=an.astype(np.float64)[ref["perm"]], tol=FLAG_TOL[np.float32],
                 cap=CAP_BUDGET, split=True)
     r = oracle.walk_group(ref, eps, floor=fl, **args)
@@ -217,7 +219,7 @@ def test_group_walk_work_cap(ctx, mode):
         an[ref["perm"]] = np.linalg.norm(w.acc, axis=1)
         an = an.astype(np.float32)
         kw = dict(mac=B.BH_MAC_BUDGET, mlp_theta_max=1.0, mlp_log10_tau=-2.0, acc_norm=an)
-        args = dict(group=G, mode=1, theta_max=1.0, tau=1e-2, kc=oracle.cell_kc(ref, eps),
+        args = dict(group=G, mode=1, theta_max=1.0, tau=1e-2, kc=oracle.cell_kc(ref),
                     anorm=an.astype(np.float64)[ref["perm"]], tol=FLAG_TOL[np.float32],
                     split=True)
         theta = 0.5
@@ -382,7 +384,7 @@ def test_timed_path_budget_steps_match_oracle(ctx):
     B.bh_sim_init(ctx, P, V, M, leaf, 0.5, eps, o)
     ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), leaf)
     p = ref["perm"]
-    kc = oracle.cell_kc(ref, eps)
+    kc = oracle.cell_kc(ref)
     G = B.BH_GROUP_BODIES
     est = oracle.walk_group(ref, eps, group=G, mode=0, order=0, theta=test, cap=cap, split=True,
                             tol=FLAG_TOL[np.float32])
@@ -390,7 +392,13 @@ def test_timed_path_budget_steps_match_oracle(ctx):
     exempt = est.flag != 0  # sorted order: bodies whose |a_i| may differ
     budget = dict(group=G, mode=1, theta_max=tmax, tau=tau, kc=kc, floor=fl, cap=cap,
                   split=True, tol=FLAG_TOL[np.float32])
-    per_body_seen = 0
+    # groups over the cap (walked per body at once, then predicted for the
+    # next steps) are part of this workload
+    free = oracle.walk_group(ref, eps, anorm=anorm, **dict(budget, cap=NO_CAP))
+    first = oracle.walk_group(ref, eps, anorm=anorm, **budget)
+    over = np.mean((free.npp != first.npp) | (free.npc != first.npc))
+    say(f"  bodies in groups over the cap at the start: {over:.3f}")
+    assert over > 0.01
     for k in range(steps + 1):
         if k:
             B.bh_leapfrog_step(ctx, 0.0)
@@ -408,7 +416,6 @@ def test_timed_path_budget_steps_match_oracle(ctx):
         bad_group = np.repeat(np.add.reduceat(exempt | (rg.flag != 0), np.arange(0, n, G)) > 0,
                               G)[:n]
         match = same_g | same_b
-        per_body_seen += int(np.sum(same_b & ~same_g & ~bad_group))
         say(f"  step {k}: match {match.mean():.4f}, exempt groups hold {bad_group.mean():.4f}, "
             f"per-body results {np.mean(same_b & ~same_g):.4f}")
         assert np.all(match | bad_group)
@@ -418,4 +425,3 @@ def test_timed_path_budget_steps_match_oracle(ctx):
         # group walk or the per-body walk, as the GPU did
         anorm = np.linalg.norm(np.where(same_b[:, None] & ~same_g[:, None], rb.acc, rg.acc),
                                axis=1)
-    assert per_body_seen > 0  # predicted or over-cap groups were walked per body

@@ -62,14 +62,14 @@ def test_cell_under_test_in_closed_form():
     M, com, Q = tb["mom"]
     assert M[c] == MC1 + MC2
     np.testing.assert_allclose(com[c], _com(), rtol=1e-15)
-    kc = oracle.cell_kc(tb, 0.0)
+    kc = oracle.cell_kc(tb)
     assert kc[c] == pytest.approx((MC1 + MC2) * SIDE ** 3, rel=1e-15)
 
 
 def test_per_body_budget_flips_at_hand_threshold():
     """Body A alone: accept C iff (M l^3) < tau |a_A| d^5, d = |A - COM_C|."""
     tb, rank, c = _system()
-    kc = oracle.cell_kc(tb, 0.0)
+    kc = oracle.cell_kc(tb)
     a_A = 0.7
     an = _norms(rank, {1: a_A, 2: 5.0})
     d = np.linalg.norm(np.array(A) - _com())
@@ -88,7 +88,7 @@ def test_per_body_angle_limit_flips_at_side_over_distance():
     first cell to pass as theta_max crosses l/d (octant 7, side 1, is about
     twice that ratio)."""
     tb, rank, c = _system()
-    kc = oracle.cell_kc(tb, 0.0)
+    kc = oracle.cell_kc(tb)
     an = _norms(rank, {})
     d = np.linalg.norm(np.array(A) - _com())
     lim = SIDE / d
@@ -104,7 +104,7 @@ def test_group_budget_flips_at_hand_threshold():
     tb, rank, c = _system()
     assert abs(rank[1] - rank[2]) == 1
     r0 = min(rank[1], rank[2])
-    kc = oracle.cell_kc(tb, 0.0)
+    kc = oracle.cell_kc(tb)
     a_A, a_B = 1.3, 0.7
     an = _norms(rank, {1: a_A, 2: a_B})
     lo = np.minimum(A, B)
@@ -129,7 +129,7 @@ def test_group_budget_flips_at_hand_threshold():
 def test_group_angle_limit_uses_the_box_distance():
     tb, rank, c = _system()
     r0 = min(rank[1], rank[2])
-    kc = oracle.cell_kc(tb, 0.0)
+    kc = oracle.cell_kc(tb)
     an = _norms(rank, {})
     lo = np.minimum(A, B)
     hi = np.maximum(A, B)

@@ -29,7 +29,7 @@ def test_group_of_one_is_the_per_body_walk():
 
 def test_group_of_one_budget_is_the_per_body_budget_walk():
     b, bb = _tree(seed=4)
-    kc = oracle.cell_kc(bb, 0.01)
+    kc = oracle.cell_kc(bb)
     an = np.linalg.norm(oracle.walk(bb["tree"], bb["mom"], bb["spos"], bb["smass"], bb["L"],
                                     0.4, 0.01).acc, axis=1)
     g = oracle.walk_group(bb, 0.01, group=1, mode=1, theta_max=0.9, tau=1e-3, kc=kc, anorm=an,
@@ -129,7 +129,7 @@ def test_work_cap_falls_back_to_the_per_body_walk():
     g = oracle.walk_group(bb, 0.01, group=64, theta=theta, split=False, cap=1)
     np.testing.assert_array_equal(g.npc, w.npc)
     np.testing.assert_allclose(g.acc, w.acc, rtol=1e-13, atol=0)
-    kc = oracle.cell_kc(bb, 0.01)
+    kc = oracle.cell_kc(bb)
     an = np.linalg.norm(w.acc, axis=1)
     gb = oracle.walk_group(bb, 0.01, group=64, mode=1, theta_max=0.9, tau=1e-2, kc=kc,
                            anorm=an, cap=1, split=False)

@@ -82,8 +82,9 @@ def test_label_on_axis_closed_form():
     """Two equal masses at +-s on an axis and group bodies on the axis at
     distances z: the exact field is m/(z - s)^2 + m/(z + s)^2 and monopole
     plus quadrupole give (2m/z^2)(1 + 3 x^2), x = s/z, so the label of the
-    pair cell is log10(((1 - x)^-2 + (1 + x)^-2)/2 - 1 - 3 x^2) at the
-    nearest body (d_g = its distance for a box on the axis)."""
+    pair cell, in units of M l^3 / d_g^5, is
+    log10(((1 - x)^-2 + (1 + x)^-2)/2 - 1 - 3 x^2) + 3 log10(z / l) at the
+    nearest body (d_g = its distance z for a box on the axis)."""
     s = 0.05
     for zs in ([0.31], [0.4, 0.55], [0.6, 0.7, 0.9]):
         bb = _axis_tree(zs, s)
@@ -101,9 +102,11 @@ def test_label_on_axis_closed_form():
         feat, lab, node, cnt = oracle.group_samples(bb, 0.0, 0.0, 100.0, 1.0, 1,
                                                     group=len(zs), cap=64,
                                                     target_range=(r[0], r[-1] + 1))
-        x = s / min(zs)
-        expect = np.log10(((1 - x) ** -2 + (1 + x) ** -2) / 2 - 1 - 3 * x * x)
+        z, x = min(zs), s / min(zs)
         for c in pair:
+            side = bb["L"] * 2.0 ** -t["level"][c]
+            expect = (np.log10(((1 - x) ** -2 + (1 + x) ** -2) / 2 - 1 - 3 * x * x)
+                      + 3 * np.log10(z / side))
             k = list(node[0, :cnt[0]]).index(c)
             assert abs(lab[0, k] - expect) < 1e-9, (lab[0, k], expect)
 
@@ -139,34 +142,37 @@ def _fp32_eval(params, f):
 
 
 def test_network_bound_covers_a_float32_evaluation():
-    """For random networks and inputs, including features placed on bf16
-    rounding midpoints and perturbed by 2e-7 relative (an FP32 feature's
-    error), the FP32 evaluation lies within the bound of the FP64 one."""
+    """For random networks and inputs, with a feature placed on a bf16
+    rounding midpoint and perturbed by 1e-6 relative either way (an FP32
+    feature's error), the FP32 evaluation (sums in another order) lies
+    within the bound of the FP64 one; away from midpoints the bound is
+    tiny."""
     rng = np.random.default_rng(3)
-    worst = 0.0
+    flips, plain = 0, []
     for trial in range(60):
         params = OM.init(100 + trial)
         params[1376:1408] = rng.normal(0, 0.3, 32)   # b2
         params[1440] = rng.normal()
         f = rng.normal(size=10) * 2
         if trial % 2:
-            # put three features on rounding midpoints of bf16
-            for k in rng.choice(10, 3, replace=False):
-                v = np.float32(f[k])
-                u = v.view(np.uint32) & np.uint32(0xFFFF0000)
-                f[k] = float((u | np.uint32(0x8000)).view(np.float32))
+            k = rng.integers(10)  # one feature on a rounding midpoint of bf16
+            v = np.float32(f[k])
+            u = v.view(np.uint32) & np.uint32(0xFFFF0000)
+            f[k] = float((u | np.uint32(0x8000)).view(np.float32))
         pred, delta = oracle.gnet_bound(params, f)
         for sgn in (-1, 1):
-            f32 = f * (1 + sgn * 2e-7)
-            got = _fp32_eval(params, f32)
+            got = _fp32_eval(params, f * (1 + sgn * 1e-6))
             assert abs(got - pred) <= delta + 1e-12, (trial, got, pred, delta)
-            worst = max(worst, abs(got - pred) / max(delta, 1e-30))
-    assert worst > 0.0
+            flips += abs(got - pred) > 1e-4
+        if trial % 2 == 0:
+            plain.append(delta)
+    assert flips > 0  # some midpoint flips did move the output
+    assert np.median(plain) < 1e-4  # no feature on a midpoint: only FP32 sums
 
 
 def test_constant_network_decision_flips_at_hand_threshold():
     """A network that outputs the constant c (all weights 0, output bias c):
-    the cell is accepted for the group iff 10^c M / d_g^2 < tau a_min.  The
+    the cell is accepted for the group iff 10^c M l^3 / d_g^5 < tau a_min.  The
     opening angle 0.5 keeps the octant cell above it (l/d_g 0.72) out, so
     the pair cell C (l/d_g 0.36) is the cell decided."""
     tb, rank, c = _system()
@@ -179,7 +185,7 @@ def test_constant_network_decision_flips_at_hand_threshold():
     params = np.zeros(OM.NPARAM)
     params[-1] = cval
     M = MC1 + MC2
-    tau_star = 10 ** cval * M / (dg * dg * min(a_A, a_B))
+    tau_star = 10 ** cval * M * SIDE ** 3 / (dg ** 5 * min(a_A, a_B))
     for f, accepted in ((1 + 1e-3, True), (1 - 1e-3, False)):
         r = oracle.walk_group(tb, 0.0, group=2, mode=2, theta_max=0.5, tau=tau_star * f,
                               anorm=an, params=params, target_range=(r0, r0 + 2), cap=NO_CAP,

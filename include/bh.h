@@ -302,6 +302,22 @@ int bh_direct(bh_ctx *ctx, const void *pos, const void *mass, int dtype, int64_t
               const int64_t *targets, int64_t nt, double eps, double *acc, double *phi);
 
 /* ---------------------------------------------------------------------
+ * bh_direct_static -- bh_direct for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results bitwise identical to
+ * bh_direct's.  It allocates nothing: the partial sums go to a fixed
+ * 16 MiB array in each GPU's global memory, held from the first
+ * bh_ctx_create on that GPU until the process ends, which limits a call to
+ * nt <= 524288 targets (larger nt: BH_E_INVALID, nothing launched).  Every
+ * call on one GPU shares that array: calls that overlap on one GPU (other
+ * streams, other contexts or threads) race and give wrong results.  The
+ * array needs no clearing between calls: each call writes every partial it
+ * reads.
+ * ------------------------------------------------------------------- */
+int bh_direct_static(bh_ctx *ctx, const void *pos, const void *mass, int dtype, int64_t n,
+                     const int64_t *targets, int64_t nt, double eps, double *acc, double *phi);
+
+/* ---------------------------------------------------------------------
  * bh_standard_units -- scale a system in place to the standard units of
  * Sec. 2.4: masses to total 1, positions and velocities to the
  * centre-of-mass frame, velocities by one factor so that E_kin = -E_pot/2,

@@ -26,7 +26,7 @@ EXPORTED = [
     "bh_version", "bh_last_error", "bh_force_opts_default", "bh_ctx_create", "bh_ctx_set_stream",
     "bh_ctx_destroy", "bh_sync", "bh_build", "bh_tree_free", "bh_forces", "bh_tree_info_get",
     "bh_tree_export", "bh_sim_init", "bh_leapfrog_step", "bh_sim_get", "bh_energy",
-    "bh_sim_tree", "bh_direct", "bh_sim_timing", "bh_sim_timing_get", "bh_sim_counts_get",
+    "bh_sim_tree", "bh_direct", "bh_direct_static", "bh_sim_timing", "bh_sim_timing_get", "bh_sim_counts_get",
     "bh_mlp_set",
     "bh_mlp_get", "bh_mlp_samples", "bh_mlp_train", "bh_mlp_grad", "bh_mlp_infer",
     "bh_standard_units", "bh_ctx_set_allocator",
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
         "bh_energy": ([vp, C.POINTER(dbl), C.POINTER(dbl)], i32),
         "bh_sim_tree": ([vp, pp], i32),
         "bh_direct": ([vp, vp, vp, i32, i64, vp, i64, dbl, vp, vp], i32),
+        "bh_direct_static": ([vp, vp, vp, i32, i64, vp, i64, dbl, vp, vp], i32),
         "bh_standard_units": ([vp, vp, vp, vp, i32, i64, vp], i32),
         "bh_ctx_set_allocator": ([vp, ALLOC_FN, FREE_FN, vp], i32),
         "bh_sim_timing": ([vp, i32], i32),
@@ -371,6 +372,12 @@ def _direct_args(pos, mass, targets, acc, phi):
 def bh_direct(ctx, pos, mass, targets, eps: float, acc, phi=None):
     _check(load().bh_direct(ctx, *_direct_args(pos, mass, targets, acc, phi), float(eps),
                             _dev(acc, "acc"), _dev(phi, "phi")))
+
+
+def bh_direct_static(ctx, pos, mass, targets, eps: float, acc, phi=None):
+    """bh_direct without any device allocation (fixed per-GPU scratch)."""
+    _check(load().bh_direct_static(ctx, *_direct_args(pos, mass, targets, acc, phi), float(eps),
+                                   _dev(acc, "acc"), _dev(phi, "phi")))
 
 
 def bh_standard_units(ctx, pos, vel, mass) -> tuple[float, float, float]:

@@ -193,6 +193,12 @@ int bh_ctx_create(int device, void *stream, bh_ctx **out) {
         delete c;
         return set_error(BH_E_DEVICE, "pinned staging allocation failed");
     }
+    // the device address of the allocation-free entry points' fixed scratch
+    if (int rc = static_scratch_init(device)) {
+        hipHostFree(c->pinned);
+        delete c;
+        return rc;
+    }
     *out = c;
     return BH_OK;
 }
@@ -633,6 +639,20 @@ int bh_direct(bh_ctx *c, const void *pos, const void *mass, int dtype, int64_t n
     if (!(eps >= 0) || !isfinite(eps)) return set_error(BH_E_INVALID, "eps must be finite and >= 0");
     if (use_device(c)) return BH_E_DEVICE;
     return launch_direct(c->stream, dtype, n, pos, mass, targets, nt, eps, acc, phi, c->scratch);
+}
+
+int bh_direct_static(bh_ctx *c, const void *pos, const void *mass, int dtype, int64_t n,
+                     const int64_t *targets, int64_t nt, double eps, double *acc, double *phi) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if (!pos || !mass || !targets || !acc) return set_error(BH_E_INVALID, "null pointer");
+    if (bad_dtype(dtype)) return set_error(BH_E_INVALID, "dtype must be BH_F32 or BH_F64");
+    if (n < 1 || n > (int64_t)0x7fff0000) return set_error(BH_E_INVALID, "n out of range");
+    if (nt < 1 || nt > direct_static_max_targets())
+        return set_error(BH_E_INVALID, "nt out of range: 1 .. 524288 targets per call");
+    if (!(eps >= 0) || !isfinite(eps)) return set_error(BH_E_INVALID, "eps must be finite and >= 0");
+    if (use_device(c)) return BH_E_DEVICE;
+    return launch_direct_static(c->stream, c->device, dtype, n, pos, mass, targets, nt, eps, acc,
+                                phi);
 }
 
 int bh_standard_units(bh_ctx *c, void *pos, void *vel, void *mass, int dtype, int64_t n,

@@ -208,6 +208,16 @@ int launch_count_sum(hipStream_t s, int64_t n, const uint32_t *a, const uint32_t
 int launch_direct(hipStream_t s, int dtype, int64_t n, const void *pos, const void *mass,
                   const int64_t *targets, int64_t nt, double eps, double *acc, double *phi,
                   DevBuf &scratch);
+// The direct sum with its partial sums in a fixed device array of
+// kStaticScratchBytes (no allocation).  static_scratch_init takes the
+// array's address on `device` (the current device) once; calls that
+// overlap on one GPU share the array and race.
+constexpr size_t kStaticScratchBytes = 16ull << 20;
+int static_scratch_init(int device);
+int64_t direct_static_max_targets();
+int launch_direct_static(hipStream_t s, int device, int dtype, int64_t n, const void *pos,
+                         const void *mass, const int64_t *targets, int64_t nt, double eps,
+                         double *acc, double *phi);
 // every body of (pos, mass) as target, arithmetic and outputs in dtype
 int launch_direct_all(hipStream_t s, int dtype, int64_t n, const void *pos, const void *mass,
                       double eps, void *acc, void *phi, DevBuf &scratch);

@@ -411,7 +411,51 @@ int direct_splits(hipStream_t s, int64_t n, const T *pos, const T *mass,
                                   (double *)scratch.p);
 }
 
+// Partial sums of the direct sum for callers that cannot allocate: a fixed
+// array in each GPU's global memory, held until the process ends.  Host
+// code never uses the array's name as an address: its device address is
+// taken once per device (static_scratch_init) and kept in g_static_part.
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / 8];
+double *g_static_part[kMaxDevices] = {};
 }  // namespace
+
+int static_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices)
+        return set_error(BH_E_DEVICE, "device index beyond the static scratch table");
+    if (g_static_part[device]) return BH_OK;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        hipGetLastError();
+        return set_error(BH_E_DEVICE, "hipGetSymbolAddress of the static scratch failed");
+    }
+    g_static_part[device] = (double *)p;
+    return BH_OK;
+}
+
+int64_t direct_static_max_targets() {
+    // direct_split keeps nsplit * nt <= 2048 * kThreads while one split
+    // suffices; beyond that one split of 32 bytes per target
+    return (int64_t)(kStaticScratchBytes / 32);
+}
+
+int launch_direct_static(hipStream_t s, int device, int dtype, int64_t n, const void *pos,
+                         const void *mass, const int64_t *targets, int64_t nt, double eps,
+                         double *acc, double *phi) {
+    if (device < 0 || device >= kMaxDevices || !g_static_part[device])
+        return set_error(BH_E_STATE, "static scratch not set up on this device");
+    const DirectSplit d = direct_split(n, nt);
+    if (32ull * d.nsplit * nt > kStaticScratchBytes)
+        return set_error(BH_E_INVALID, "nt too large for the static scratch");
+    double *part = g_static_part[device];
+    if (dtype == BH_F32)
+        return direct_launch<float, double, double>(s, d, n, (const float *)pos,
+                                                    (const float *)mass, targets, nt, eps, acc,
+                                                    phi, part);
+    return direct_launch<double, double, double>(s, d, n, (const double *)pos,
+                                                 (const double *)mass, targets, nt, eps, acc,
+                                                 phi, part);
+}
 
 int launch_direct(hipStream_t s, int dtype, int64_t n, const void *pos, const void *mass,
                   const int64_t *targets, int64_t nt, double eps, double *acc, double *phi,

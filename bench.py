@@ -21,7 +21,9 @@ over a seeded 4096-body subsample:
                 predicted error of the particle-cell term on the group
                 against the same budget (bf16 MFMA inside the walk),
                 trained first on the library's own FP64 simulations of
-                Plummer spheres.
+                Plummer spheres;
+  body-theta-o3, group-theta-o3  the two opening-angle walks with the
+                octopole term added to each particle-cell interaction.
 Each is swept over its parameter grid from accurate to cheap; the cheapest
 grid value with rms <= 1e-3 is kept, and the method with the fastest walk
 at that value is the one timed.  After the timed steps the rms error is
@@ -70,9 +72,10 @@ METRIC = "body-cell interactions/s and bodies/s force eval at rms rel force err 
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 # algorithmic FLOPs per interaction: particle-particle 20; particle-cell 20
-# (monopole) or 60 (monopole + quadrupole)
+# (monopole), 60 (monopole + quadrupole) or 125 (and octopole: its contraction
+# with x x costs 39, the rest of the term 26)
 FLOP_PP = 20
-FLOP_PC = {0: 20, 2: 60}
+FLOP_PC = {0: 20, 2: 60, 3: 125}
 
 # force-evaluation methods compared at the target error, with the parameter
 # grid each is swept over (from accurate to cheap)
@@ -83,10 +86,18 @@ METHODS = {
     "group-theta": [round(0.6 + 0.0125 * k, 4) for k in range(29)],   # one decision per wave
     "group-budget": [round(-2.5 + 0.0625 * k, 4) for k in range(25)],  # log10 tau
     "group-learned": [round(-5.0 + 0.0625 * k, 4) for k in range(57)],  # log10 tau
+    # the opening angle with the octopole term (l = 3 of the expansion)
+    "body-theta-o3": [round(0.5 + 0.01 * k, 2) for k in range(41)],
+    "group-theta-o3": [round(0.6 + 0.0125 * k, 4) for k in range(37)],
 }
 PARAM_NAME = {"body-theta": "theta", "body-theta-guard": "theta", "group-theta": "theta",
               "group-budget": "log10_tau",
-              "group-learned": "log10_tau"}
+              "group-learned": "log10_tau", "body-theta-o3": "theta", "group-theta-o3": "theta"}
+
+
+def order_of(method):
+    """Expansion order of a method: octopole for the -o3 variants."""
+    return 3 if method.endswith("-o3") else 2
 BUDGET_THETA_MAX = 1.5
 # |a_i| in the budget tests is max(|a_i|, ACC_FLOOR <|a|>)
 ACC_FLOOR = 0.5
@@ -111,9 +122,7 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="override N")
     ap.add_argument("--theta", type=float, default=None,
                     help="per-body walk: skip the sweep and use this theta")
-    ap.add_argument("--method", choices=["body-theta", "body-theta-guard", "group-theta",
-                                         "group-budget",
-                                         "group-learned"],
+    ap.add_argument("--method", choices=list(METHODS),
                     default=None, help="time only this method (default: the fastest at the "
                     "target error)")
     ap.add_argument("--target-err", type=float, default=1e-3)
@@ -200,10 +209,11 @@ def main():
     mlp_precision = B.BH_MLP_FP16 if cfg.get("mlp") == "fp16" else B.BH_MLP_BF16
 
     def opts_of(method, p, counters=False, for_sim=False):
-        kw = dict(order=order, n_pp=npp if counters else None, n_pc=npc if counters else None)
+        kw = dict(order=order_of(method), n_pp=npp if counters else None,
+                  n_pc=npc if counters else None)
         if method == "body-theta-guard":
             kw.update(mac=B.BH_MAC_THETA_GUARD)
-        elif method == "group-theta":
+        elif method in ("group-theta", "group-theta-o3"):
             kw.update(walk=B.BH_WALK_GROUP, walk_cap=args.walk_cap)
         elif method in ("group-budget", "group-learned"):
             kw.update(walk=B.BH_WALK_GROUP, walk_cap=args.walk_cap, mlp_precision=mlp_precision,
@@ -356,7 +366,7 @@ def main():
     s_pp = sim_pp / max(nsteps, 1)
     s_pc = sim_pc / max(nsteps, 1)
     inter = s_pp + s_pc
-    flops = FLOP_PP * s_pp + FLOP_PC[order] * s_pc
+    flops = FLOP_PP * s_pp + FLOP_PC[order_of(chosen)] * s_pc
     achieved_tf = flops / (walk_kernel_ms * 1e-3) / 1e12
     log(f"step {ms_step:.3f} ms  phases {phases}  rms at the final state {rms_final:.3e}")
 
@@ -376,7 +386,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": result_workload(cfg, n),
-            "n": n, "eps": eps, "leaf": leaf, "order": order, "dt": dt,
+            "n": n, "eps": eps, "leaf": leaf, "order": order_of(chosen), "dt": dt,
             "method": chosen, PARAM_NAME[chosen]: cp,
             **({"theta_max": BUDGET_THETA_MAX, "acc_floor": ACC_FLOOR}
                if PARAM_NAME[chosen] == "log10_tau" else {}),
@@ -401,7 +411,8 @@ def main():
         "methods": methods,
         "learned_training": learned_info,
         "roofline": {
-            "bound": "alu", "kernel": f"{kernel} (FP32, quadrupole)",
+            "bound": "alu",
+            "kernel": f"{kernel} (FP32, {'octopole' if order_of(chosen) == 3 else 'quadrupole'})",
             "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved_tf / PEAK_FP32_TFLOPS,
             "traffic": traffic_for(kernel, result_workload(cfg, n)),

@@ -79,7 +79,7 @@ static void free_tree_bufs(bh_tree *t) {
                      &t->level, &t->begin, &t->count, &t->next, &t->parent, &t->cmask,
                      &t->lvl_list, &t->cx, &t->cy, &t->cz, &t->mom, &t->recs,
                      &t->cube, &t->part, &t->hist, &t->status, &t->misc, &t->cnt_scratch,
-                     &t->kc, &t->anorm, &t->est_acc, &t->kids, &t->s3, &t->oct, &t->wq, &t->gorder,
+                     &t->kc, &t->anorm, &t->est_acc, &t->kids, &t->ulist, &t->s3, &t->oct, &t->wq, &t->gorder,
                      &t->gfb};
     for (DevBuf *b : all) free_buf(*b);
 }

@@ -139,6 +139,7 @@ struct bh_tree {
     // accelerations
     bh::DevBuf kc, anorm, est_acc;
     bh::DevBuf kids;                           // group walk: children per node
+    bh::DevBuf ulist;                          // upward pass: subtree roots, upper cells
     bh::DevBuf s3, oct;                        // order 3: raw third moments, octopole records
     int64_t oct_tree_id = -1;
     bh::DevBuf wq;                             // group walk: queue counters

@@ -619,8 +619,11 @@ __global__ __launch_bounds__(kThreads) void k_emit(
     const uint32_t *__restrict__ lvl_pre, LevelBase lb, uint64_t *__restrict__ hkey,
     int32_t *__restrict__ level, int32_t *__restrict__ begin, int32_t *__restrict__ count,
     int32_t *__restrict__ next, int32_t *__restrict__ parent, int32_t *__restrict__ cx,
-    int32_t *__restrict__ cy, int32_t *__restrict__ cz, int32_t *__restrict__ lvl_list) {
+    int32_t *__restrict__ cy, int32_t *__restrict__ cz, int32_t *__restrict__ lvl_list,
+    uint32_t *__restrict__ ucnt, int32_t *__restrict__ kids) {
     __shared__ uint32_t lcnt[kLevels + 1];
+    // the upward pass's list counters start at zero
+    if (blockIdx.x == 0 && threadIdx.x < 3) ucnt[threadIdx.x] = 0u;
     __shared__ int32_t lbase[kLevels + 1];
     __shared__ int32_t so[kThreads + 1];  // first cell of each rank's chain
     if (threadIdx.x <= kLevels) {
@@ -668,6 +671,9 @@ __global__ __launch_bounds__(kThreads) void k_emit(
         count[node] = e - s;
         next[node] = offs[e];
         parent[node] = par < m ? par : -1;
+        // the parent's child table, one slot per key digit (all -1 before
+        // this launch); the upward pass compacts it
+        if (par >= 0 && par < m) kids[8 * (int64_t)par + (int)(pre & 7u)] = node;
         const int cs = kLevels - k;
         cx[node] = (int32_t)(((qx >> cs) * 2u + 1u) << cs);
         cy[node] = (int32_t)(((qy >> cs) * 2u + 1u) << cs);
@@ -682,8 +688,9 @@ __global__ __launch_bounds__(kThreads) void k_emit(
 struct UpArgs {
     int m;
     const int4 *kids;
+    int32_t *kids_out;  // the same table, compacted by the upward pass
     const uint64_t *hkey;
-    const int32_t *level, *begin, *count, *next, *cx, *cy, *cz;
+    const int32_t *level, *begin, *count, *next, *parent, *cx, *cy, *cz;
     const Cube *cube;
     Moments *mom;
     uint32_t *cmask;
@@ -733,19 +740,34 @@ __device__ __forceinline__ void finish_node(const UpArgs &a, int i, const NodeGe
     ((typename NodeRecT<R>::type *)a.recs)[i] = r;
 }
 
-// One thread per node.  Every node: its children, in pre-order (= octant
-// order), from the skip pointers: kids[8 c + q] for q < #children, then -1
-// (the upward pass and the group walk read a node's children from here in
-// one load).  Leaves also: FP64 moments straight from their bodies, about
-// the leaf centre, the node record, and the walk's body records (offset from
-// the leaf centre, computed in FP64, and mass) with the leaf centre as each
-// body's anchor.
+// One thread per node.  Leaves: FP64 moments straight from their bodies,
+// about the leaf centre, the node record, and the walk's body records
+// (offset from the leaf centre, computed in FP64, and mass) with the leaf
+// centre as each body's anchor.  Internal cells are listed for the upward
+// pass.  (The child table kids[8 c + q], the children in pre-order = key
+// digit order for q < #children, then -1, which the upward pass and the
+// group walk read in one load, is written by k_emit one slot per digit and
+// compacted by the upward pass.)
+// The internal cells are combined by the upward pass in two parts: the
+// maximal subtrees of at most kSubNodes nodes (a subtree is the contiguous
+// pre-order range [r, next[r])), one workgroup each, and the cells above
+// them ("upper" cells, whose subtree is larger), in one workgroup.  k_leaves
+// lists both: ulist[0 .. ucnt[0]) the subtree roots (internal cells of at
+// most kSubNodes nodes whose parent's subtree is larger, or the root),
+// ulist[m .. m + ucnt[1]) the upper cells (ucnt[2] is spare).
+// One wavefront per subtree (a subtree has few cells per level), so that
+// the ~N/1400 subtrees of a Plummer sphere are all resident at once.
+constexpr int kSubThreads = 64;
+constexpr int kSubSlots = 16;                         // nodes per thread
+constexpr int kSubNodes = kSubThreads * kSubSlots;    // 1024
+
 template <typename T, typename R>
-__global__ __launch_bounds__(kThreads) void k_leaves(UpArgs ua, int32_t *__restrict__ kids,
-                                                     const T *__restrict__ spos,
+__global__ __launch_bounds__(kThreads) void k_leaves(UpArgs ua, const T *__restrict__ spos,
                                                      const T *__restrict__ smass,
                                                      BodyRec<R> *__restrict__ bodies,
-                                                     Anchor<R> *__restrict__ anchors) {
+                                                     Anchor<R> *__restrict__ anchors,
+                                                     int32_t *__restrict__ ulist,
+                                                     uint32_t *__restrict__ ucnt) {
     // a wavefront's 64 consecutive nodes in pre-order own one contiguous
     // range of bodies: it is staged through LDS with coalesced loads (when it
     // fits), and each leaf's lane then reads its bodies from there
@@ -758,17 +780,14 @@ __global__ __launch_bounds__(kThreads) void k_leaves(UpArgs ua, int32_t *__restr
     const bool valid = i < m;
     const int end = valid ? next[i] : 0;
     if (valid) {
-        int k[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
-        int q = 0;
-        for (int ch = i + 1; ch < end && q < 8;) {
-            k[q++] = ch;
-            const int nx = next[ch];
-            if (nx <= ch) break;  // malformed skip pointer: stop
-            ch = nx;
+        if (end != i + 1) {  // internal: a subtree root, an upper cell, or neither
+            if (end - i > kSubNodes) {
+                ulist[m + (int)atomicAdd(&ucnt[1], 1u)] = i;
+            } else {
+                const int p = ua.parent[i];
+                if (p < 0 || ua.next[p] - p > kSubNodes) ulist[atomicAdd(&ucnt[0], 1u)] = i;
+            }
         }
-        int4 *o = (int4 *)(kids + 8 * (int64_t)i);
-        o[0] = make_int4(k[0], k[1], k[2], k[3]);
-        o[1] = make_int4(k[4], k[5], k[6], k[7]);
     }
     const bool leaf = valid && end == i + 1;
     NodeGeo gn{};
@@ -878,27 +897,64 @@ __device__ __forceinline__ void up_combine(const UpArgs &a, const UpPre &u, doub
     double mt = 0, s0 = 0, s1 = 0, s2 = 0;
     double q[6] = {0, 0, 0, 0, 0, 0};
     uint32_t mask = 0;
+    // the children in two batches of four, each batch's loads issued
+    // together: an absent child loads the cell's own (unused) slot instead,
+    // so no load waits behind a branch
 #pragma unroll
-    for (int c8 = 0; c8 < 8; ++c8) {
-        const int c = ch[c8];
-        if (c > p && c < a.m) {
-            const Moments qm = a.mom[c];
-            const double g0 = qm.c[0] + (double)(a.cx[c] - pcx) * h;
-            const double g1 = qm.c[1] + (double)(a.cy[c] - pcy) * h;
-            const double g2 = qm.c[2] + (double)(a.cz[c] - pcz) * h;
-            const double w0 = qm.m * g0, w1 = qm.m * g1, w2 = qm.m * g2;
-            mt += qm.m;
+    for (int half = 0; half < 2; ++half) {
+        Moments qm[4];
+        int gx[4], gy[4], gz[4];
+        uint32_t oct[4];
+        bool ok[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = ch[4 * half + j];
+            ok[j] = c > p && c < a.m;
+            const int cc = ok[j] ? c : p;
+            qm[j] = a.mom[cc];
+            gx[j] = a.cx[cc];
+            gy[j] = a.cy[cc];
+            gz[j] = a.cz[cc];
+            oct[j] = (uint32_t)(a.hkey[cc] & 7u);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!ok[j]) continue;
+            const double g0 = qm[j].c[0] + (double)(gx[j] - pcx) * h;
+            const double g1 = qm[j].c[1] + (double)(gy[j] - pcy) * h;
+            const double g2 = qm[j].c[2] + (double)(gz[j] - pcz) * h;
+            const double w0 = qm[j].m * g0, w1 = qm[j].m * g1, w2 = qm[j].m * g2;
+            mt += qm[j].m;
             s0 += w0;
             s1 += w1;
             s2 += w2;
-            q[0] += qm.t[0] + w0 * g0;
-            q[1] += qm.t[1] + w0 * g1;
-            q[2] += qm.t[2] + w0 * g2;
-            q[3] += qm.t[3] + w1 * g1;
-            q[4] += qm.t[4] + w1 * g2;
-            q[5] += qm.t[5] + w2 * g2;
-            mask |= 1u << (uint32_t)(a.hkey[c] & 7u);
+            q[0] += qm[j].t[0] + w0 * g0;
+            q[1] += qm[j].t[1] + w0 * g1;
+            q[2] += qm[j].t[2] + w0 * g2;
+            q[3] += qm[j].t[3] + w1 * g1;
+            q[4] += qm[j].t[4] + w1 * g2;
+            q[5] += qm[j].t[5] + w2 * g2;
+            mask |= 1u << oct[j];
         }
+    }
+    // the child table compacted in place: children first, in digit order
+    {
+        // (selects only: no dynamically indexed register array)
+        int kc[8], rank[8], nk = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            rank[j] = ch[j] > p && ch[j] < a.m ? nk : -1;
+            nk += rank[j] >= 0 ? 1 : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            kc[q] = -1;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) kc[q] = rank[j] == q ? ch[j] : kc[q];
+        }
+        int4 *o = (int4 *)a.kids_out + 2 * (int64_t)p;
+        o[0] = make_int4(kc[0], kc[1], kc[2], kc[3]);
+        o[1] = make_int4(kc[4], kc[5], kc[6], kc[7]);
     }
     Moments r;
     r.m = mt;
@@ -919,39 +975,124 @@ __device__ __forceinline__ void up_node(const UpArgs &a, int p, double h) {
     up_combine<R>(a, up_pre(a, p), h);
 }
 
-// Internal cells of one level (one launch per level with more than
-// kTopCells cells).
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_up_level(const int32_t *__restrict__ list, int cnt,
-                                                       UpArgs a) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= cnt) return;
-    up_node<R>(a, list[t], ldexp(a.cube->L, -(kLevels + 1)));
+// Level buckets of a workgroup's cells in LDS: cells are placed by a
+// counting sort over their levels (order within a level is free: the cells
+// of one level are independent), so that each level is then one contiguous
+// run that the workgroup's threads take in turn, from one call site.
+struct LevelBuckets {
+    int cnt[kLevels + 2];
+    int off[kLevels + 2];
+};
+__device__ __forceinline__ void buckets_clear(LevelBuckets &b, int t) {
+    if (t <= kLevels + 1) b.cnt[t] = 0;
+}
+__device__ __forceinline__ void buckets_scan(LevelBuckets &b, int t) {
+    if (t == 0) {
+        int acc = 0;
+        for (int k = 0; k <= kLevels + 1; ++k) {
+            b.off[k] = acc;
+            acc += b.cnt[k];
+            b.cnt[k] = b.off[k];  // becomes the placement cursor
+        }
+    }
 }
 
-// Levels with at most this many cells each go to one workgroup of as many
-// threads (k_up_top).
-constexpr int kTopCells = 1024;
-
-// Levels top .. 0 (all small) in one workgroup, deepest first, one cell per
-// thread, with a workgroup barrier between levels.  All waves of the
-// workgroup share one CU, so the barrier's workgroup-scope fence makes a
-// level's results visible to the next.  A cell's geometry and child table
-// do not depend on the level below, so the next level's are loaded before
-// the barrier: each level then waits on one round of loads (the children's
-// moments) instead of three.
+// The subtrees: workgroup b takes roots b, b + gridDim.x, ... of the list,
+// buckets each subtree's internal cells by level, and combines them level
+// by level, deepest first, with a workgroup barrier between levels (all
+// waves share one CU, so the barrier's fence makes a level's moments visible
+// to the next).  The leaves were done by k_leaves, the launch before.  Any
+// grid size is correct.  (A shared atomic hand-out counter cost more than
+// the uneven sizes of the subtrees: 166 against 88 us at 2^22 bodies.)
 template <typename R>
-__global__ __launch_bounds__(kTopCells) void k_up_top(const int32_t *__restrict__ list,
-                                                      LevelBase lb, LevelBase lc, int top,
-                                                      UpArgs a) {
+__global__ __launch_bounds__(kSubThreads) void k_up_sub(UpArgs a,
+                                                        const int32_t *__restrict__ roots,
+                                                        const uint32_t *__restrict__ ucnt) {
+    __shared__ LevelBuckets bk;
+    __shared__ int32_t cell[kSubNodes];
     const double h = ldexp(a.cube->L, -(kLevels + 1));
     const int t = (int)threadIdx.x;
-    UpPre cur = up_pre(a, t < lc.base[top] ? list[lb.base[top] + t] : -1);
-    for (int k = top; k >= 0; --k) {
-        const UpPre nxt = up_pre(a, k > 0 && t < lc.base[k - 1] ? list[lb.base[k - 1] + t] : -1);
-        up_combine<R>(a, cur, h);
+    const int total = (int)ucnt[0];
+    for (int w = (int)blockIdx.x; w < total; w += (int)gridDim.x) {
+        buckets_clear(bk, t);
         __syncthreads();
-        cur = nxt;
+        const int r = roots[w];
+        const int e = a.next[r];
+        // every slot's loads at once (indices clamped into the subtree)
+        int nx[kSubSlots], lv[kSubSlots];
+#pragma unroll
+        for (int q = 0; q < kSubSlots; ++q) {
+            const int i = min(r + t + q * kSubThreads, e - 1);
+            nx[q] = a.next[i];
+            lv[q] = a.level[i];
+        }
+#pragma unroll
+        for (int q = 0; q < kSubSlots; ++q) {
+            const int i = r + t + q * kSubThreads;
+            if (i >= e || nx[q] == i + 1) lv[q] = -1;  // outside, or a leaf
+            if (lv[q] >= 0) atomicAdd(&bk.cnt[lv[q]], 1);
+        }
+        __syncthreads();
+        buckets_scan(bk, t);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kSubSlots; ++q)
+            if (lv[q] >= 0) cell[atomicAdd(&bk.cnt[lv[q]], 1)] = r + t + q * kSubThreads;
+        __syncthreads();
+        const int kr = a.level[r];
+        for (int k = kLevels; k >= kr; --k) {
+            const int b0 = bk.off[k], b1 = bk.off[k + 1];
+            if (b0 == b1) continue;  // uniform
+            for (int j = b0 + t; j < b1; j += kSubThreads) up_node<R>(a, cell[j], h);
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+}
+
+// The upper cells, in one workgroup, level by level, deepest first: their
+// children are upper cells (done at a deeper level by this workgroup) or
+// subtree roots and leaves (done by the launches before).  Up to kUpLds of
+// them are bucketed by level in LDS; a longer list (only for trees far from
+// balanced) is scanned again at every level.
+constexpr int kUpThreads = 512;
+constexpr int kUpLds = 8192;
+template <typename R>
+__global__ __launch_bounds__(kUpThreads) void k_up_upper(UpArgs a,
+                                                         const int32_t *__restrict__ list,
+                                                         const uint32_t *__restrict__ ucnt) {
+    __shared__ LevelBuckets bk;
+    __shared__ int32_t cell[kUpLds];
+    const double h = ldexp(a.cube->L, -(kLevels + 1));
+    const int t = (int)threadIdx.x;
+    const int u = (int)ucnt[1];
+    if (u == 0) return;
+    if (u <= kUpLds) {
+        buckets_clear(bk, t);
+        __syncthreads();
+        for (int j = t; j < u; j += kUpThreads) atomicAdd(&bk.cnt[a.level[list[j]]], 1);
+        __syncthreads();
+        buckets_scan(bk, t);
+        __syncthreads();
+        for (int j = t; j < u; j += kUpThreads) {
+            const int p = list[j];
+            cell[atomicAdd(&bk.cnt[a.level[p]], 1)] = p;
+        }
+        __syncthreads();
+        for (int k = kLevels; k >= 0; --k) {
+            const int b0 = bk.off[k], b1 = bk.off[k + 1];
+            if (b0 == b1) continue;  // uniform
+            for (int j = b0 + t; j < b1; j += kUpThreads) up_node<R>(a, cell[j], h);
+            __syncthreads();
+        }
+    } else {
+        for (int k = kLevels; k >= 0; --k) {
+            for (int j = t; j < u; j += kUpThreads) {
+                const int p = list[j];
+                if (a.level[p] == k) up_node<R>(a, p, h);
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -1106,6 +1247,7 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     uint32_t *misc = (uint32_t *)t->misc.p;
     uint32_t *flags = misc, *tile_ctr = misc + 8, *seg_tot = misc + 16;
     uint32_t *bsum = misc + 64;
+    uint32_t *ucnt = misc + 48;  // upward pass: roots, upper cells, hand-out
     uint32_t *hist = (uint32_t *)t->hist.p, *doff = hist + 2048;
 
     // the digit histogram is left zeroed by the previous build's scan;
@@ -1186,24 +1328,29 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
         (rc = grow(t->cx, 4ull * m)) ||
         (rc = grow(t->cy, 4ull * m)) || (rc = grow(t->cz, 4ull * m)) ||
         (rc = grow(t->mom, sizeof(Moments) * (size_t)m)) ||
-        (rc = grow(t->kids, 32ull * m)) ||
+        (rc = grow(t->kids, 32ull * m)) || (rc = grow(t->ulist, 8ull * m)) ||
         (rc = grow(t->recs, sizeof(typename NodeRecT<T>::type) * (size_t)m)))
         return rc;
     const int nbm = div_up(m, kThreads);
     int32_t *lvl_list = (int32_t *)t->lvl_list.p;
+    k_fill_u32<<<div_up(8 * (int64_t)m, kThreads), kThreads, 0, st>>>((uint32_t *)t->kids.p,
+                                                                      8 * (int64_t)m, ~0u);
     k_emit<<<nb, kThreads, 0, st>>>(ka, delta, offs, n, m, bsum, lb, (uint64_t *)t->hkey.p,
                                     (int32_t *)t->level.p, (int32_t *)t->begin.p,
                                     (int32_t *)t->count.p, (int32_t *)t->next.p,
                                     (int32_t *)t->parent.p, (int32_t *)t->cx.p,
-                                    (int32_t *)t->cy.p, (int32_t *)t->cz.p, lvl_list);
+                                    (int32_t *)t->cy.p, (int32_t *)t->cz.p, lvl_list, ucnt,
+                                    (int32_t *)t->kids.p);
     UpArgs ua;
     ua.m = m;
     ua.kids = (const int4 *)t->kids.p;
+    ua.kids_out = (int32_t *)t->kids.p;
     ua.hkey = (const uint64_t *)t->hkey.p;
     ua.level = (const int32_t *)t->level.p;
     ua.begin = (const int32_t *)t->begin.p;
     ua.count = (const int32_t *)t->count.p;
     ua.next = (const int32_t *)t->next.p;
+    ua.parent = (const int32_t *)t->parent.p;
     ua.cx = (const int32_t *)t->cx.p;
     ua.cy = (const int32_t *)t->cy.p;
     ua.cz = (const int32_t *)t->cz.p;
@@ -1211,23 +1358,15 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     ua.mom = (Moments *)t->mom.p;
     ua.cmask = (uint32_t *)t->cmask.p;
     ua.recs = t->recs.p;
-    k_leaves<T, T><<<nbm, kThreads, 0, st>>>(ua, (int32_t *)t->kids.p, pos_out, mass_out,
+    int32_t *ulist = (int32_t *)t->ulist.p;
+    k_leaves<T, T><<<nbm, kThreads, 0, st>>>(ua, pos_out, mass_out,
                                              (BodyRec<T> *)t->bodies.p,
-                                             (Anchor<T> *)t->anchors.p);
-    // the top levels whose cells number at most kTopCells each go to one
-    // workgroup; the deeper levels get a launch each, deepest first
-    int top = -1;
-    while (top + 1 <= t->depth - 1 && lcount[top + 1] <= kTopCells) ++top;
-    for (int k = t->depth - 1; k > top; --k) {
-        if (lcount[k] == 0) continue;
-        k_up_level<T><<<div_up(lcount[k], kThreads), kThreads, 0, st>>>(lvl_list + lb.base[k],
-                                                                        lcount[k], ua);
-    }
-    if (top >= 0) {
-        LevelBase lc;  // cells per level
-        for (int k = 0; k <= kLevels; ++k) lc.base[k] = lcount[k];
-        k_up_top<T><<<1, kTopCells, 0, st>>>(lvl_list, lb, lc, top, ua);
-    }
+                                             (Anchor<T> *)t->anchors.p, ulist, ucnt);
+    // subtrees: about one root per 330 nodes in a Plummer sphere, so about
+    // one workgroup each up to 2^22 bodies (a wavefront each: all resident)
+    const int nsub = m / 256 < 1 ? 1 : (m / 256 > 8192 ? 8192 : m / 256);
+    k_up_sub<T><<<nsub, kSubThreads, 0, st>>>(ua, ulist, ucnt);
+    k_up_upper<T><<<1, kUpThreads, 0, st>>>(ua, ulist + m, ucnt);
     t->kids_tree_id = t->build_id;
     return check_launch("tree");
 }

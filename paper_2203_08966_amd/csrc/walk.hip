@@ -733,7 +733,14 @@ __device__ __forceinline__ auto group_walk(
                 // accepted cells from LDS (same address on every lane: broadcast)
                 const int npc_round = __builtin_popcountll(m_pc);
                 __builtin_amdgcn_wave_barrier();
-                for (int q = 0; q < npc_round; ++q) staged_term(stage + SW * q);
+                // two cells per iteration (immediate LDS offsets, two
+                // independent chains; the sums still follow q)
+                int q = 0;
+                for (; q + 1 < npc_round; q += 2) {
+                    staged_term(stage + SW * q);
+                    staged_term(stage + SW * (q + 1));
+                }
+                if (q < npc_round) staged_term(stage + SW * q);
                 work += npc_round;
                 // particle-particle leaves (and one-body cells) of the round.
                 // The bodies of those that hold none of the group's bodies are
@@ -785,8 +792,10 @@ __device__ __forceinline__ auto group_walk(
                     __builtin_amdgcn_wave_barrier();
                     work += total;
                     if (CNT) cpp += (uint32_t)total;
-                    for (int q = 0; q < total; ++q) {  // same address on every lane
-                        const R *sb = stage + 4 * q;
+                    // same address on every lane; two bodies per iteration
+                    // (immediate LDS offsets, two independent chains; the
+                    // sums still follow q)
+                    auto pp_term = [&](const R *sb) {
                         const R dx = sb[0] - px, dy = sb[1] - py, dz = sb[2] - pz;
                         R r2 = dx * dx + eps2;
                         r2 = dy * dy + r2;
@@ -798,7 +807,13 @@ __device__ __forceinline__ auto group_walk(
                         sy = mi3 * dy + sy;
                         sz = mi3 * dz + sz;
                         if (PHI) sp = sp - minv;
+                    };
+                    int q = 0;
+                    for (; q + 1 < total; q += 2) {
+                        pp_term(stage + 4 * q);
+                        pp_term(stage + 4 * (q + 1));
                     }
+                    if (q < total) pp_term(stage + 4 * q);
                     __builtin_amdgcn_wave_barrier();
                 }
                 uint64_t mm = m_self;

@@ -80,15 +80,15 @@ FLOP_PC = {0: 20, 2: 60, 3: 125}
 # force-evaluation methods compared at the target error, with the parameter
 # grid each is swept over (from accurate to cheap)
 METHODS = {
-    "body-theta": [round(0.5 + 0.01 * k, 2) for k in range(31)],      # Sec. 3 walk
+    "body-theta": [round(0.5 + 0.005 * k, 3) for k in range(61)],     # Sec. 3 walk
     # the same walk with a containment guard (a cell holding the body is opened)
-    "body-theta-guard": [round(0.5 + 0.01 * k, 2) for k in range(51)],
-    "group-theta": [round(0.6 + 0.0125 * k, 4) for k in range(29)],   # one decision per wave
-    "group-budget": [round(-2.5 + 0.0625 * k, 4) for k in range(25)],  # log10 tau
-    "group-learned": [round(-5.0 + 0.0625 * k, 4) for k in range(57)],  # log10 tau
+    "body-theta-guard": [round(0.5 + 0.005 * k, 3) for k in range(101)],
+    "group-theta": [round(0.6 + 0.00625 * k, 5) for k in range(57)],  # one decision per wave
+    "group-budget": [round(-2.5 + 0.03125 * k, 5) for k in range(49)],  # log10 tau
+    "group-learned": [round(-5.0 + 0.03125 * k, 5) for k in range(113)],  # log10 tau
     # the opening angle with the octopole term (l = 3 of the expansion)
-    "body-theta-o3": [round(0.5 + 0.01 * k, 2) for k in range(41)],
-    "group-theta-o3": [round(0.6 + 0.0125 * k, 4) for k in range(37)],
+    "body-theta-o3": [round(0.5 + 0.005 * k, 3) for k in range(81)],
+    "group-theta-o3": [round(0.6 + 0.00625 * k, 5) for k in range(73)],
 }
 PARAM_NAME = {"body-theta": "theta", "body-theta-guard": "theta", "group-theta": "theta",
               "group-budget": "log10_tau",

@@ -61,6 +61,11 @@ def _load():
     opt_u64 = C.c_void_p
     lib.orc_build.argtypes = [C.c_int64, _u64, C.c_int] + [opt_u64] * 7
     lib.orc_build.restype = C.c_int64
+    lib.orc_build_curve.argtypes = [C.c_int64, _u64, _u64, C.c_int] + [opt_u64] * 7
+    lib.orc_build_curve.restype = C.c_int64
+    lib.orc_hilbert.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_uint32)]
+    lib.orc_hilbert.restype = C.c_uint64
+    lib.orc_keys_hilbert.argtypes = [C.c_int64, _f64, _f64, C.c_double, _u64]
     lib.orc_moments.argtypes = [C.c_int64, _i32, _u64, _i32, _i32, _f64, _f64, _f64,
                                 C.c_double, _f64, _f64, _f64, C.c_void_p]
     lib.orc_walk.argtypes = [C.c_int64, _i32, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
@@ -107,12 +112,22 @@ def interleave(qx: int, qy: int, qz: int) -> int:
     return int(_load().orc_interleave(qx, qy, qz))
 
 
-def keys(pos, lo, L):
+def keys(pos, lo, L, curve: str = "morton"):
+    """Space-filling-curve keys of bodies in the root cube (lo, L): the
+    Morton key (default) or the Peano-Hilbert index, 21 bits per axis."""
     lib = _load()
     p = _pos64(pos)
     k = np.zeros(p.shape[0], dtype=np.uint64)
-    lib.orc_keys(p.shape[0], p.ravel(), np.ascontiguousarray(lo, dtype=np.float64), float(L), k)
+    f = {"morton": lib.orc_keys, "hilbert": lib.orc_keys_hilbert}[curve]
+    f(p.shape[0], p.ravel(), np.ascontiguousarray(lo, dtype=np.float64), float(L), k)
     return k
+
+
+def hilbert(q, bits: int) -> int:
+    """Peano-Hilbert index of the integer point q (any dimension, axis 0
+    first) on a grid of 2^bits per axis."""
+    a = (C.c_uint32 * len(q))(*[int(v) for v in q])
+    return int(_load().orc_hilbert(len(q), int(bits), a))
 
 
 def sort(k):
@@ -123,12 +138,20 @@ def sort(k):
     return perm
 
 
-def build_tree(sorted_keys, leaf_size: int) -> dict:
-    """Pre-order node arrays of the canonical octree over key-sorted bodies."""
+def build_tree(sorted_keys, leaf_size: int, cell_keys=None) -> dict:
+    """Pre-order node arrays of the canonical octree over key-sorted bodies.
+    With ``cell_keys`` (the Morton keys of the same sorted bodies, when they
+    were sorted by another curve) cells are ordered by the curve and named
+    by their Morton hashed keys."""
     lib = _load()
     k = np.ascontiguousarray(sorted_keys, dtype=np.uint64)
     n = k.shape[0]
-    m = lib.orc_build(n, k, int(leaf_size), None, None, None, None, None, None, None)
+    if cell_keys is not None:
+        ck = np.ascontiguousarray(cell_keys, dtype=np.uint64)
+        build = lambda *a: lib.orc_build_curve(n, k, ck, int(leaf_size), *a)  # noqa: E731
+    else:
+        build = lambda *a: lib.orc_build(n, k, int(leaf_size), *a)  # noqa: E731
+    m = build(None, None, None, None, None, None, None)
     t = {
         "hkey": np.zeros(m, dtype=np.uint64),
         "level": np.zeros(m, dtype=np.int32),
@@ -138,8 +161,8 @@ def build_tree(sorted_keys, leaf_size: int) -> dict:
         "parent": np.zeros(m, dtype=np.int32),
         "cmask": np.zeros(m, dtype=np.int32),
     }
-    m2 = lib.orc_build(n, k, int(leaf_size), *(t[f].ctypes.data for f in
-                       ("hkey", "level", "begin", "count", "next", "parent", "cmask")))
+    m2 = build(*(t[f].ctypes.data for f in
+                 ("hkey", "level", "begin", "count", "next", "parent", "cmask")))
     assert m2 == m
     return t
 
@@ -224,15 +247,16 @@ def walk(tree, mom, spos, smass, L, theta, eps, order=2, targets=None, guard_lo=
     return WalkResult(acc, phi, npp, npc, ncov, flag)
 
 
-def build_all(pos, mass, leaf_size: int):
-    """Root cube, keys, stable sort, tree and moments for bodies in any order."""
+def build_all(pos, mass, leaf_size: int, curve: str = "morton"):
+    """Root cube, keys, stable sort, tree and moments for bodies in any order
+    (bodies ordered along the Morton or the Peano-Hilbert curve)."""
     p = _pos64(pos)
     m = np.ascontiguousarray(mass, dtype=np.float64)
     lo, L = root_cube(p)
-    k = keys(p, lo, L)
+    k = keys(p, lo, L, curve)
     perm = sort(k)
     sk = k[perm]
-    tree = build_tree(sk, leaf_size)
+    tree = build_tree(sk, leaf_size, None if curve == "morton" else keys(p, lo, L)[perm])
     spos = p[perm]
     smass = m[perm]
     mom = moments(tree, spos, smass, lo, L)

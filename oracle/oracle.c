@@ -151,6 +151,96 @@ void orc_keys(int64_t n, const double *pos, const double *lo, double L, uint64_t
 }
 
 /* ------------------------------------------------------------------------
+ * Peano-Hilbert key (Sec. 4.4 names the Peano-Hilbert order as the remedy
+ * for the jumps of the Morton order; a method variant).  The index is
+ * built one level at a time from the top, following Butz's construction as
+ * Hamilton states it (Compact Hilbert Indices, 2006): at every level the
+ * point's bits, one per axis (bit j of l is axis j), name the sub-cube it
+ * lies in; the current cube's curve is carried onto the standard one by
+ * reflecting through its entry corner e and rotating right by d + 1 bits,
+ * after which the sub-cubes are visited in Gray-code order, so the
+ * sub-cube's rank w is the inverse Gray code of the transformed bits; w is
+ * the next n bits of the index; the sub-cube's own curve enters at corner
+ * e(w) (the Gray code of the largest even number below w, 0 for w = 0) and
+ * leaves along axis g(w) (the trailing set bits of w - 1 for even w, of w
+ * for odd w, modulo n), which update e and d.  Axis 0 is x.  In two
+ * dimensions this draws Hilbert's own curve; in three, one of the Hilbert
+ * curves (the nesting of sub-cubes, the face-adjacency of consecutive
+ * cells and the start at the origin are what the tests check).
+ * ---------------------------------------------------------------------- */
+static unsigned hb_rotr(unsigned x, int r, int n)
+{
+    r %= n;
+    const unsigned mask = (1u << n) - 1u;
+    return r == 0 ? x & mask : ((x >> r) | (x << (n - r))) & mask;
+}
+
+static unsigned hb_rotl(unsigned x, int r, int n)
+{
+    r %= n;
+    const unsigned mask = (1u << n) - 1u;
+    return r == 0 ? x & mask : ((x << r) | (x >> (n - r))) & mask;
+}
+
+static unsigned hb_gray(unsigned i) { return i ^ (i >> 1); }
+
+static unsigned hb_gray_inverse(unsigned g)
+{
+    unsigned i = g;
+    for (unsigned s = g >> 1; s; s >>= 1)
+        i ^= s;
+    return i;
+}
+
+static int hb_trailing_ones(unsigned i)
+{
+    int c = 0;
+    while (i & 1u) {
+        ++c;
+        i >>= 1;
+    }
+    return c;
+}
+
+static unsigned hb_entry(unsigned w) { return w == 0 ? 0u : hb_gray(2u * ((w - 1u) / 2u)); }
+
+static int hb_axis(unsigned w, int n)
+{
+    if (w == 0)
+        return 0;
+    return (w & 1u ? hb_trailing_ones(w) : hb_trailing_ones(w - 1u)) % n;
+}
+
+uint64_t orc_hilbert(int n, int bits, const uint32_t *q)
+{
+    unsigned e = 0;
+    int d = 0;
+    uint64_t h = 0;
+    for (int i = bits - 1; i >= 0; --i) {
+        unsigned l = 0;
+        for (int j = 0; j < n; ++j)
+            l |= ((q[j] >> i) & 1u) << j;
+        const unsigned w = hb_gray_inverse(hb_rotr(l ^ e, d + 1, n));
+        e ^= hb_rotl(hb_entry(w), d + 1, n);
+        d = (d + hb_axis(w, n) + 1) % n;
+        h = (h << n) | w;
+    }
+    return h;
+}
+
+void orc_keys_hilbert(int64_t n, const double *pos, const double *lo, double L,
+                      uint64_t *keys)
+{
+    const double scale = ldexp(1.0, ORC_LEVELS) / L;
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t q[3] = {quantise(pos[3 * i + 0], lo[0], scale),
+                               quantise(pos[3 * i + 1], lo[1], scale),
+                               quantise(pos[3 * i + 2], lo[2], scale)};
+        keys[i] = orc_hilbert(3, ORC_LEVELS, q);
+    }
+}
+
+/* ------------------------------------------------------------------------
  * Sort bodies by key (Sec. 4.4); ties keep the original index order.
  * perm[r] = original index of the body at sorted rank r.
  * ---------------------------------------------------------------------- */
@@ -194,8 +284,8 @@ typedef struct {
     int32_t *level, *begin, *count, *next, *parent, *cmask;
 } tree_out;
 
-static void split_cell(tree_out *t, const uint64_t *keys, int B, int k,
-                       uint64_t prefix, int64_t b, int64_t e, int64_t parent)
+static void split_cell(tree_out *t, const uint64_t *keys, const uint64_t *ckeys, int B,
+                       int k, uint64_t prefix, int64_t b, int64_t e, int64_t parent)
 {
     const int64_t id = t->m++;
     const int w = t->hkey != NULL;
@@ -215,9 +305,11 @@ static void split_cell(tree_out *t, const uint64_t *keys, int B, int k,
             int64_t f = s;
             while (f < e && (unsigned)((keys[f] >> shift) & 7u) == d)
                 ++f;
+            /* the child's octant: its digit of the Morton cell key */
+            const unsigned o = (unsigned)((ckeys[s] >> shift) & 7u);
             if (w)
-                t->cmask[id] |= 1 << d;
-            split_cell(t, keys, B, k + 1, (prefix << 3) | d, s, f, id);
+                t->cmask[id] |= 1 << o;
+            split_cell(t, keys, ckeys, B, k + 1, (prefix << 3) | o, s, f, id);
             s = f;
         }
     }
@@ -230,7 +322,23 @@ int64_t orc_build(int64_t n, const uint64_t *sorted_keys, int leaf_size, uint64_
                   int32_t *parent, int32_t *cmask)
 {
     tree_out t = {0, hkey, level, begin, count, next, parent, cmask};
-    split_cell(&t, sorted_keys, leaf_size, 0, 0, 0, n, -1);
+    split_cell(&t, sorted_keys, sorted_keys, leaf_size, 0, 0, 0, n, -1);
+    return t.m;
+}
+
+/* The same tree over bodies sorted by another space-filling curve's keys
+ * (the Peano-Hilbert keys): cells are split and ordered by the curve's
+ * digits (a curve prefix of k digits names a level-k cube, as a Morton
+ * prefix does), and named, as before, by their Morton hashed keys taken
+ * from cell_keys (the Morton keys of the same sorted bodies), so that the
+ * hashed key, the child mask (by octant) and the cell centre keep their
+ * geometric meaning. */
+int64_t orc_build_curve(int64_t n, const uint64_t *sorted_keys, const uint64_t *cell_keys,
+                        int leaf_size, uint64_t *hkey, int32_t *level, int32_t *begin,
+                        int32_t *count, int32_t *next, int32_t *parent, int32_t *cmask)
+{
+    tree_out t = {0, hkey, level, begin, count, next, parent, cmask};
+    split_cell(&t, sorted_keys, cell_keys, leaf_size, 0, 0, 0, n, -1);
     return t.m;
 }
 

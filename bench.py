@@ -23,7 +23,10 @@ over a seeded 4096-body subsample:
                 trained first on the library's own FP64 simulations of
                 Plummer spheres;
   body-theta-o3, group-theta-o3  the two opening-angle walks with the
-                octopole term added to each particle-cell interaction.
+                octopole term added to each particle-cell interaction;
+  body-theta-hilbert, group-theta-hilbert, group-budget-hilbert  three of
+                the walks over bodies sorted along the Peano-Hilbert curve
+                (a group is 64 consecutive bodies of that curve).
 Each is swept over its parameter grid from accurate to cheap; the cheapest
 grid value with rms <= 1e-3 is kept, and the method with the fastest walk
 at that value is the one timed.  After the timed steps the rms error is
@@ -90,14 +93,29 @@ METHODS = {
     "body-theta-o3": [round(0.5 + 0.005 * k, 3) for k in range(81)],
     "group-theta-o3": [round(0.6 + 0.00625 * k, 5) for k in range(73)],
 }
+# the same methods over bodies sorted along the Peano-Hilbert curve
+for _m in ("body-theta", "group-theta", "group-budget"):
+    METHODS[_m + "-hilbert"] = METHODS[_m]
 PARAM_NAME = {"body-theta": "theta", "body-theta-guard": "theta", "group-theta": "theta",
               "group-budget": "log10_tau",
               "group-learned": "log10_tau", "body-theta-o3": "theta", "group-theta-o3": "theta"}
+for _m in ("body-theta", "group-theta", "group-budget"):
+    PARAM_NAME[_m + "-hilbert"] = PARAM_NAME[_m]
 
 
 def order_of(method):
     """Expansion order of a method: octopole for the -o3 variants."""
     return 3 if method.endswith("-o3") else 2
+
+
+def hilbert(method):
+    """Whether a method sorts the bodies along the Peano-Hilbert curve."""
+    return method.endswith("-hilbert")
+
+
+def base_of(method):
+    """The method without its curve suffix."""
+    return method[:-len("-hilbert")] if hilbert(method) else method
 BUDGET_THETA_MAX = 1.5
 # |a_i| in the budget tests is max(|a_i|, ACC_FLOOR <|a|>)
 ACC_FLOOR = 0.5
@@ -211,6 +229,7 @@ def main():
     def opts_of(method, p, counters=False, for_sim=False):
         kw = dict(order=order_of(method), n_pp=npp if counters else None,
                   n_pc=npc if counters else None)
+        method = base_of(method)
         if method == "body-theta-guard":
             kw.update(mac=B.BH_MAC_THETA_GUARD)
         elif method in ("group-theta", "group-theta-o3"):
@@ -224,7 +243,8 @@ def main():
 
     def walk(method, p, counters=False):
         theta = p if PARAM_NAME[method] == "theta" else 0.5
-        B.bh_forces(tree, theta, eps, acc, opts_of(method, p, counters))
+        B.bh_forces(tree_h if hilbert(method) else tree, theta, eps, acc,
+                    opts_of(method, p, counters))
 
     def rms_at(method, p):
         walk(method, p)
@@ -244,9 +264,15 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    names = list(METHODS) if args.method is None else [args.method]
+    # the same bodies sorted along the Peano-Hilbert curve
+    tree_h = None
+    if any(hilbert(k) for k in names):
+        B.bh_ctx_set_curve(ctx, B.BH_CURVE_HILBERT)
+        tree_h = B.bh_build(ctx, pos, mass, leaf)
+        B.bh_ctx_set_curve(ctx, B.BH_CURVE_MORTON)
     # ---- the learned criterion: train the network on the library's own FP64
     # simulations of small Plummer spheres (bf16 MFMA inference afterwards)
-    names = list(METHODS) if args.method is None else [args.method]
     learned_info = None
     if "group-learned" in names:
         from paper_2203_08966_amd import learned as LM
@@ -319,12 +345,15 @@ def main():
             log(f"body-theta interpolated to rms {args.target_err}: theta {th_t:.4f} "
                 f"walk {wm:.3f} ms")
     B.bh_tree_free(tree)
+    if tree_h is not None:
+        B.bh_tree_free(tree_h)
     chosen = min(methods, key=lambda k: methods[k]["walk_ms"])
     cp = methods[chosen]["param"]
     log(f"timed method: {chosen} ({PARAM_NAME[chosen]} = {cp})")
 
     # ---- timed simulation steps
     sim_theta = cp if PARAM_NAME[chosen] == "theta" else 0.5
+    B.bh_ctx_set_curve(ctx, B.BH_CURVE_HILBERT if hilbert(chosen) else B.BH_CURVE_MORTON)
     B.bh_sim_init(ctx, pos, vel, mass, leaf, sim_theta, eps, opts_of(chosen, cp, for_sim=True))
     for _ in range(args.warmup):
         B.bh_leapfrog_step(ctx, dt)
@@ -371,6 +400,7 @@ def main():
     log(f"step {ms_step:.3f} ms  phases {phases}  rms at the final state {rms_final:.3e}")
 
     kernel = "k_walk" if chosen.startswith("body-") else "k_gwalk"
+    B.bh_ctx_set_curve(ctx, B.BH_CURVE_MORTON)
     result = {
         "metric": METRIC,
         "value": value,
@@ -387,6 +417,7 @@ def main():
         "config": {
             "workload": result_workload(cfg, n),
             "n": n, "eps": eps, "leaf": leaf, "order": order_of(chosen), "dt": dt,
+            "curve": "hilbert" if hilbert(chosen) else "morton",
             "method": chosen, PARAM_NAME[chosen]: cp,
             **({"theta_max": BUDGET_THETA_MAX, "acc_floor": ACC_FLOOR}
                if PARAM_NAME[chosen] == "log10_tau" else {}),

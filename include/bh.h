@@ -79,6 +79,13 @@ enum {
                               1/sqrt(3) it equals BH_MAC_THETA. */
 };
 
+/* Space-filling curve the bodies are sorted along (bh_ctx_set_curve). */
+enum {
+    BH_CURVE_MORTON = 0,  /* Morton (Z) order, Sec. 4.4 (default) */
+    BH_CURVE_HILBERT = 1  /* Peano-Hilbert order, the remedy Sec. 4.4 names
+                             for the Morton order's jumps (a variant) */
+};
+
 /* Arithmetic of the network's inference (MFMA operands; FP32 accumulate). */
 enum {
     BH_MLP_BF16 = 0,
@@ -163,6 +170,17 @@ void bh_force_opts_default(bh_force_opts *opts);
 int bh_ctx_create(int device, void *stream, bh_ctx **out);
 int bh_ctx_set_stream(bh_ctx *ctx, void *stream);
 
+/* The curve that later builds of this context (bh_build, bh_sim_init and
+ * every simulation step) sort the bodies along.  BH_CURVE_HILBERT: the
+ * 63-bit key is the Peano-Hilbert index of the same 21-bit integer point
+ * (Butz's construction: axis x in bit 0 of each level's three bits; the
+ * curve starts at the cube's corner lo).  A prefix of k octal digits of
+ * either key names the same level-k cube, so the tree has the same cells:
+ * only the order of bodies, of a cell's children and of the nodes (still
+ * pre-order) changes.  Cells keep their Morton hashed keys and child masks
+ * by octant.  BH_E_INVALID for another value. */
+int bh_ctx_set_curve(bh_ctx *ctx, int curve);
+
 /* Device memory from the caller's allocator (e.g. a framework's caching
  * allocator) instead of hipMalloc.  alloc(bytes, device, stream, user)
  * returns device memory of at least `bytes` on `device`, usable in the
@@ -228,19 +246,20 @@ int bh_tree_free(bh_tree *tree);
 int bh_forces(bh_tree *tree, double theta, double eps, void *acc, const bh_force_opts *opts);
 
 /* Tree shape: n bodies, m nodes, depth, root cube (lo, side), dtype, leaf
- * size, and the criterion (BH_MAC_*) the tree's last walk used, -1 before
+ * size, curve, and the criterion (BH_MAC_*) the tree's last walk used, -1 before
  * the first: BH_MAC_THETA after a BH_MAC_MLP request with no network
  * loaded (the fallback to the plain opening angle). */
 typedef struct {
     int64_t n, m;
     int32_t depth, dtype, leaf_size, last_mac;
+    int32_t curve, reserved; /* BH_CURVE_* the bodies are sorted along */
     double lo[3], side;
 } bh_tree_info;
 int bh_tree_info_get(const bh_tree *tree, bh_tree_info *info);
 
 /* Copies the tree to host buffers (any may be NULL): sorted keys[n],
  * perm[n] (caller index of each sorted rank), and per node in pre-order:
- * hkey[m] (1 << 3k | key prefix), level[m], begin[m] (first sorted rank),
+ * hkey[m] (1 << 3k | Morton key prefix, whatever the curve), level[m], begin[m] (first sorted rank),
  * count[m], next[m] (first node after the subtree), parent[m] (-1 root),
  * cmask[m] (bit d set iff child octant d exists), mass[m], com[m x 3]
  * (absolute), quad[m x 6] (xx xy xz yy yz zz, sum m(3 y_a y_b - |y|^2 d_ab)

@@ -21,6 +21,7 @@ BH_MAC_THETA, BH_MAC_MLP, BH_MAC_BUDGET, BH_MAC_THETA_GUARD = 0, 1, 2, 3
 BH_MLP_BF16, BH_MLP_FP16 = 0, 1
 BH_WALK_BODY, BH_WALK_GROUP, BH_WALK_DIRECT = 0, 1, 2
 BH_GROUP_BODIES = 64  # bodies per group of BH_WALK_GROUP
+BH_CURVE_MORTON, BH_CURVE_HILBERT = 0, 1
 
 EXPORTED = [
     "bh_version", "bh_last_error", "bh_force_opts_default", "bh_ctx_create", "bh_ctx_set_stream",
@@ -29,7 +30,7 @@ EXPORTED = [
     "bh_sim_tree", "bh_direct", "bh_direct_static", "bh_sim_timing", "bh_sim_timing_get", "bh_sim_counts_get",
     "bh_mlp_set",
     "bh_mlp_get", "bh_mlp_samples", "bh_mlp_train", "bh_mlp_grad", "bh_mlp_infer",
-    "bh_standard_units", "bh_ctx_set_allocator",
+    "bh_standard_units", "bh_ctx_set_allocator", "bh_ctx_set_curve",
 ]
 BH_MLP_PARAMS = 1441
 
@@ -68,8 +69,8 @@ class MlpTrainCfg(C.Structure):
 class TreeInfo(C.Structure):
     _fields_ = [
         ("n", C.c_int64), ("m", C.c_int64), ("depth", C.c_int32), ("dtype", C.c_int32),
-        ("leaf_size", C.c_int32), ("last_mac", C.c_int32), ("lo", C.c_double * 3),
-        ("side", C.c_double),
+        ("leaf_size", C.c_int32), ("last_mac", C.c_int32), ("curve", C.c_int32),
+        ("reserved", C.c_int32), ("lo", C.c_double * 3), ("side", C.c_double),
     ]
 
 
@@ -93,6 +94,7 @@ def load(path: str = LIB_PATH):
         "bh_force_opts_default": ([C.POINTER(ForceOpts)], None),
         "bh_ctx_create": ([i32, vp, pp], i32),
         "bh_ctx_set_stream": ([vp, vp], i32),
+        "bh_ctx_set_curve": ([vp, i32], i32),
         "bh_ctx_destroy": ([vp], i32),
         "bh_sync": ([vp], i32),
         "bh_build": ([vp, vp, vp, i32, i64, i32, pp], i32),
@@ -229,6 +231,10 @@ def bh_ctx_set_stream(ctx, stream=None):
     _check(load().bh_ctx_set_stream(ctx, _stream() if stream is None else C.c_void_p(stream)))
 
 
+def bh_ctx_set_curve(ctx, curve: int):
+    _check(load().bh_ctx_set_curve(ctx, int(curve)))
+
+
 def bh_ctx_destroy(ctx):
     _check(load().bh_ctx_destroy(ctx))
     _ALLOCATORS.pop(ctx.value, None)
@@ -303,8 +309,8 @@ def bh_tree_info_get(tree) -> dict:
     info = TreeInfo()
     _check(load().bh_tree_info_get(tree, C.byref(info)))
     return dict(n=info.n, m=info.m, depth=info.depth, dtype=info.dtype,
-                leaf_size=info.leaf_size, last_mac=info.last_mac, lo=np.array(info.lo[:]),
-                side=info.side)
+                leaf_size=info.leaf_size, last_mac=info.last_mac, curve=info.curve,
+                lo=np.array(info.lo[:]), side=info.side)
 
 
 def bh_tree_export(tree) -> dict:

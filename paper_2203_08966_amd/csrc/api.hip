@@ -209,6 +209,14 @@ int bh_ctx_set_stream(bh_ctx *c, void *stream) {
     return BH_OK;
 }
 
+int bh_ctx_set_curve(bh_ctx *c, int curve) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if (curve != BH_CURVE_MORTON && curve != BH_CURVE_HILBERT)
+        return set_error(BH_E_INVALID, "curve must be BH_CURVE_MORTON or BH_CURVE_HILBERT");
+    c->curve = curve;
+    return BH_OK;
+}
+
 int bh_ctx_set_allocator(bh_ctx *c, bh_alloc_fn alloc, bh_free_fn free_fn, void *user) {
     if (!c) return set_error(BH_E_INVALID, "null ctx");
     if ((alloc == nullptr) != (free_fn == nullptr))
@@ -325,6 +333,7 @@ int bh_tree_info_get(const bh_tree *t, bh_tree_info *info) {
     info->dtype = t->dtype;
     info->leaf_size = t->leaf;
     info->last_mac = t->last_mac;
+    info->curve = t->curve;
     for (int d = 0; d < 3; ++d) info->lo[d] = t->lo[d];
     info->side = t->L;
     return BH_OK;

@@ -96,6 +96,7 @@ struct bh_ctx {
     bh::SimState *sim = nullptr;
     bh_tree *sim_tree = nullptr;
     int live_trees = 0;
+    int curve = BH_CURVE_MORTON;     // space-filling curve of later builds
     // learned acceptance criterion
     bh::DevBuf mlp_w;                // packed inference weights (MlpPacked)
     bh::DevBuf mlp_master;           // FP32 parameters, Adam m, Adam v
@@ -123,6 +124,7 @@ struct bh_tree {
     int depth = 0;
     int32_t lvl_cnt[22] = {}, lvl_base[22] = {};  // cells per level, first slot in lvl_list
     int last_mac = -1;  // criterion the last walk of this tree used (-1: none yet)
+    int curve = BH_CURVE_MORTON;  // the curve the bodies are sorted along
     double lo[3] = {0, 0, 0}, L = 1.0;
     // body-indexed
     bh::DevBuf keys_a, keys_b, idx_a, idx_b;  // radix-sort ping-pong

@@ -185,6 +185,63 @@ __device__ __forceinline__ uint32_t compact3(uint64_t x) {
     x = (x ^ (x >> 32)) & 0x00000000001fffffull;
     return (uint32_t)x;
 }
+// Peano-Hilbert index of the integer point (qx, qy, qz), 21 bits per axis
+// (Sec. 4.4 names the curve as the remedy for the Morton order's jumps).
+// Butz's construction, level by level from the top: the point's three bits
+// at the level (x in bit 0) are reflected through the current cube's entry
+// corner e and rotated right by d + 1 places, which carries the cube's curve
+// onto the standard one; the sub-cube's rank w is then their inverse Gray
+// code and the next octal digit of the index; the sub-cube's curve enters
+// at corner E(w) (rotated left by d + 1 into the cube's frame, then added to
+// e) and d grows by D(w) + 1 modulo 3.  E(w) is the Gray code of the largest
+// even number below w (0 for w = 0): 0 0 0 3 3 6 6 5; D(w) counts the
+// trailing ones of w - 1 (w even) or of w (w odd), modulo 3: 0 1 1 2 2 1 1 0.
+// Both are packed in one word each, 3 and 2 bits per entry.
+constexpr uint32_t kHbEntry = (0u << 0) | (0u << 3) | (0u << 6) | (3u << 9) | (3u << 12) |
+                              (6u << 15) | (6u << 18) | (5u << 21);
+constexpr uint32_t kHbAxis = (0u << 0) | (1u << 2) | (1u << 4) | (2u << 6) | (2u << 8) |
+                             (1u << 10) | (1u << 12) | (0u << 14);
+__device__ __forceinline__ uint32_t rot3r(uint32_t x, uint32_t r) {  // r in 0..2
+    return ((x >> r) | (x << (3u - r))) & 7u;
+}
+__device__ __forceinline__ uint32_t rot3l(uint32_t x, uint32_t r) {
+    return ((x << r) | (x >> (3u - r))) & 7u;
+}
+__device__ __forceinline__ uint64_t hilbert3(uint32_t qx, uint32_t qy, uint32_t qz) {
+    uint32_t e = 0, d = 0;
+    uint64_t h = 0;
+#pragma unroll
+    for (int i = kLevels - 1; i >= 0; --i) {
+        const uint32_t l = ((qx >> i) & 1u) | (((qy >> i) & 1u) << 1) | (((qz >> i) & 1u) << 2);
+        const uint32_t t = rot3r(l ^ e, d == 2 ? 0u : d + 1u);
+        const uint32_t w = t ^ (t >> 1) ^ (t >> 2);
+        e ^= rot3l((kHbEntry >> (3u * w)) & 7u, d == 2 ? 0u : d + 1u);
+        d += ((kHbAxis >> (2u * w)) & 3u) + 1u;
+        d = d >= 3u ? d - 3u : d;
+        d = d >= 3u ? d - 3u : d;
+        h = (h << 3) | w;
+    }
+    return h;
+}
+// The inverse: the integer point of a 63-bit Peano-Hilbert index.
+__device__ __forceinline__ void hilbert3_point(uint64_t h, uint32_t &qx, uint32_t &qy,
+                                               uint32_t &qz) {
+    uint32_t e = 0, d = 0;
+    qx = qy = qz = 0;
+#pragma unroll
+    for (int i = kLevels - 1; i >= 0; --i) {
+        const uint32_t w = (uint32_t)(h >> (3 * i)) & 7u;
+        const uint32_t l = rot3l(w ^ (w >> 1), d == 2 ? 0u : d + 1u) ^ e;
+        qx |= (l & 1u) << i;
+        qy |= ((l >> 1) & 1u) << i;
+        qz |= ((l >> 2) & 1u) << i;
+        e ^= rot3l((kHbEntry >> (3u * w)) & 7u, d == 2 ? 0u : d + 1u);
+        d += ((kHbAxis >> (2u * w)) & 3u) + 1u;
+        d = d >= 3u ? d - 3u : d;
+        d = d >= 3u ? d - 3u : d;
+    }
+}
+
 __device__ __forceinline__ uint32_t quantise(double x, double lo, double scale) {
     double t = __dmul_rn(__dsub_rn(x, lo), scale);
     double f = floor(t);
@@ -202,7 +259,7 @@ template <typename T>
 __global__ __launch_bounds__(kKeyThreads) void k_keys(const T *__restrict__ pos, int n,
                                                       const Cube *__restrict__ cube,
                                                       uint64_t *__restrict__ keys,
-                                                      uint32_t *__restrict__ hist) {
+                                                      uint32_t *__restrict__ hist, int curve) {
     __shared__ uint32_t h[8][256];
     for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
     __syncthreads();
@@ -217,9 +274,11 @@ __global__ __launch_bounds__(kKeyThreads) void k_keys(const T *__restrict__ pos,
         uint64_t k = 0;
         if (valid) {
             const int64_t b = 3 * (int64_t)i;
-            k = (spread3(quantise((double)pos[b + 0], lx, scale)) << 2) |
-                (spread3(quantise((double)pos[b + 1], ly, scale)) << 1) |
-                spread3(quantise((double)pos[b + 2], lz, scale));
+            const uint32_t qx = quantise((double)pos[b + 0], lx, scale),
+                           qy = quantise((double)pos[b + 1], ly, scale),
+                           qz = quantise((double)pos[b + 2], lz, scale);
+            k = curve == BH_CURVE_HILBERT ? hilbert3(qx, qy, qz)
+                                          : (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
             keys[i] = k;
         }
         const uint64_t live = ballot(valid);
@@ -620,7 +679,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(
     int32_t *__restrict__ level, int32_t *__restrict__ begin, int32_t *__restrict__ count,
     int32_t *__restrict__ next, int32_t *__restrict__ parent, int32_t *__restrict__ cx,
     int32_t *__restrict__ cy, int32_t *__restrict__ cz, int32_t *__restrict__ lvl_list,
-    uint32_t *__restrict__ ucnt, int32_t *__restrict__ kids) {
+    uint32_t *__restrict__ ucnt, int32_t *__restrict__ kids, int curve) {
     __shared__ uint32_t lcnt[kLevels + 1];
     // the upward pass's list counters start at zero
     if (blockIdx.x == 0 && threadIdx.x < 3) ucnt[threadIdx.x] = 0u;
@@ -664,15 +723,28 @@ __global__ __launch_bounds__(kThreads) void k_emit(
             const int a = ds > 0 ? seg_begin(keys, s, shp, prep) : 0;
             par = offs[a] + (ds - (delta[a] + 1));
         }
-        const uint32_t qx = compact3(key >> 2), qy = compact3(key >> 1), qz = compact3(key);
-        hkey[node] = (1ull << (3 * k)) | pre;
+        // the cell is named by its Morton hashed key whatever the curve the
+        // bodies follow (a curve prefix and a Morton prefix of k digits name
+        // the same cube); its centre from the integer point of body s
+        uint32_t qx, qy, qz;
+        if (curve == BH_CURVE_HILBERT) {
+            hilbert3_point(key, qx, qy, qz);
+        } else {
+            qx = compact3(key >> 2);
+            qy = compact3(key >> 1);
+            qz = compact3(key);
+        }
+        const uint64_t mkey =
+            curve == BH_CURVE_HILBERT ? (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz) : key;
+        hkey[node] = (1ull << (3 * k)) | (k > 0 ? mkey >> sh : 0ull);
         level[node] = k;
         begin[node] = s;
         count[node] = e - s;
         next[node] = offs[e];
         parent[node] = par < m ? par : -1;
-        // the parent's child table, one slot per key digit (all -1 before
-        // this launch); the upward pass compacts it
+        // the parent's child table, one slot per digit of the sort key (all
+        // -1 before this launch): the slots follow the pre-order; the upward
+        // pass compacts them
         if (par >= 0 && par < m) kids[8 * (int64_t)par + (int)(pre & 7u)] = node;
         const int cs = kLevels - k;
         cx[node] = (int32_t)(((qx >> cs) * 2u + 1u) << cs);
@@ -1262,7 +1334,8 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     k_bbox<T><<<nbbox, kThreads, 0, st>>>(pos, n, (double *)t->part.p);
     k_cube<<<1, kThreads, 0, st>>>((const double *)t->part.p, nbbox, cube, (Cube *)(misc + 40),
                                    flags);
-    k_keys<T><<<nkeys, kKeyThreads, 0, st>>>(pos, n, cube, (uint64_t *)t->keys_a.p, hist);
+    k_keys<T><<<nkeys, kKeyThreads, 0, st>>>(pos, n, cube, (uint64_t *)t->keys_a.p, hist,
+                                             ctx->curve);
     k_hist_scan<<<8, 256, 0, st>>>(hist, doff, tile_ctr);
     uint64_t *ka = (uint64_t *)t->keys_a.p, *kb = (uint64_t *)t->keys_b.p;
     uint32_t *va = nullptr, *vb = (uint32_t *)t->idx_b.p, *vspare = (uint32_t *)t->idx_a.p;
@@ -1340,7 +1413,7 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
                                     (int32_t *)t->count.p, (int32_t *)t->next.p,
                                     (int32_t *)t->parent.p, (int32_t *)t->cx.p,
                                     (int32_t *)t->cy.p, (int32_t *)t->cz.p, lvl_list, ucnt,
-                                    (int32_t *)t->kids.p);
+                                    (int32_t *)t->kids.p, ctx->curve);
     UpArgs ua;
     ua.m = m;
     ua.kids = (const int4 *)t->kids.p;
@@ -1417,6 +1490,7 @@ int build_tree(bh_ctx *ctx, bh_tree *t, const void *pos, const void *mass, int d
     t->dtype = dtype;
     t->n = n;
     t->leaf = leaf;
+    t->curve = ctx->curve;
     t->build_id++;
     int rc;
     if (dtype == BH_F32)

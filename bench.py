@@ -278,13 +278,18 @@ def main():
         from paper_2203_08966_amd import learned as LM
         t0 = time.perf_counter()
         feat, label = LM.training_set(ctx)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         loss = LM.train(ctx, feat, label)
         torch.cuda.synchronize()
+        t2 = time.perf_counter()
         learned_info = {"pairs": int(feat.shape[0]), "epochs": len(loss),
                         "loss_first_last": [float(loss[0]), float(loss[-1])],
                         "label_var": float(label.double().var().item()),
-                        "seconds": time.perf_counter() - t0,
+                        "seconds": t2 - t0, "train_seconds": t2 - t1,
                         "inference": "fp16" if mlp_precision == B.BH_MLP_FP16 else "bf16"}
+        learned_info["roofline"] = mlp_roofline(B, ctx, feat, len(loss), t2 - t1, mlp_precision)
+        log(f"network roofline: {learned_info['roofline']}")
         del feat, label
         log(f"learned criterion: {learned_info}")
 
@@ -534,6 +539,47 @@ def result_workload(cfg, n):
             "two_spheres": "radii 1 and 0.3, lognormal masses, approaching",
             "clumpy": "4096 Plummer clumps + 10% background, equal masses"}[cfg["workload"]]
     return f"{cfg['workload']} N={n} ({what}, seed {cfg['seed']})"
+
+
+# the network 10 -> 32 -> 32 -> 1: FLOPs of one evaluation (two per
+# multiply-add), and of one training sample (forward and backward, about
+# three evaluations)
+MLP_FLOP = 2 * (10 * 32 + 32 * 32 + 32)
+MLP_TRAIN_FLOP = 3 * MLP_FLOP
+PEAK_MFMA_16BIT_TFLOPS = 2500.0
+
+
+def mlp_roofline(B, ctx, feat, epochs, train_s, precision):
+    """The network's roofline figures: the batched MFMA inference kernel over
+    the training features (10 FP32 features read per row: HBM-bound at
+    2752 / 40 flop per byte, below the MFMA ridge), and the training pass
+    (FP32 vector arithmetic, whole bh_mlp_train call)."""
+    import torch
+    n = int(feat.shape[0])
+    B.bh_mlp_infer(ctx, feat, precision)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        B.bh_mlp_infer(ctx, feat, precision)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    inf_tf = n * MLP_FLOP / (ms * 1e-3) / 1e12
+    gbs = n * 44 / (ms * 1e-3) / 1e9  # 40 B of features in, 4 B out per row
+    tr_tf = n * epochs * MLP_TRAIN_FLOP / train_s / 1e12
+    return {
+        "infer": {"kernel": "k_mlp_infer (" + ("fp16" if precision else "bf16") + " MFMA)",
+                  "rows": n, "ms": ms, "flop_per_row": MLP_FLOP, "achieved": inf_tf,
+                  "peak": PEAK_MFMA_16BIT_TFLOPS, "unit": "TFLOP/s",
+                  "frac": inf_tf / PEAK_MFMA_16BIT_TFLOPS, "bound": "hbm",
+                  "hbm_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS},
+        "train": {"kernel": "k_mlp_grad + k_mlp_adam (FP32 vector)", "samples": n,
+                  "epochs": epochs, "seconds": train_s, "flop_per_sample": MLP_TRAIN_FLOP,
+                  "achieved": tr_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                  "frac": tr_tf / PEAK_FP32_TFLOPS},
+    }
 
 
 def traffic_for(kernel, workload):

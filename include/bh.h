@@ -86,6 +86,17 @@ enum {
                              for the Morton order's jumps (a variant) */
 };
 
+/* How a simulation step's rebuild sorts its bodies (bh_ctx_set_sort). */
+enum {
+    BH_SORT_ADAPTIVE = 0, /* default: the bodies arrive in the previous
+                             build's order, nearly sorted after a short step
+                             (Sec. 4.4); only the bodies that left their
+                             leaf's key range (and the leaves whose bodies
+                             fell out of order) are radix-sorted, then merged
+                             with the rest.  Same result as BH_SORT_FULL. */
+    BH_SORT_FULL = 1      /* always the full 8-pass radix sort */
+};
+
 /* Arithmetic of the network's inference (MFMA operands; FP32 accumulate). */
 enum {
     BH_MLP_BF16 = 0,
@@ -181,6 +192,14 @@ int bh_ctx_set_stream(bh_ctx *ctx, void *stream);
  * by octant.  BH_E_INVALID for another value. */
 int bh_ctx_set_curve(bh_ctx *ctx, int curve);
 
+/* The sort of later simulation rebuilds on this context: BH_SORT_ADAPTIVE
+ * (default) or BH_SORT_FULL.  Both give the stable sort of the keys (ties in
+ * input order), bit for bit; the adaptive one falls back to the full sort
+ * when more than a quarter of the bodies move.  bh_build always sorts in
+ * full.  An adaptive rebuild waits for the device once more (to size the
+ * movers' sort).  BH_E_INVALID for another value. */
+int bh_ctx_set_sort(bh_ctx *ctx, int mode);
+
 /* Device memory from the caller's allocator (e.g. a framework's caching
  * allocator) instead of hipMalloc.  alloc(bytes, device, stream, user)
  * returns device memory of at least `bytes` on `device`, usable in the
@@ -254,6 +273,8 @@ typedef struct {
     int32_t depth, dtype, leaf_size, last_mac;
     int32_t curve, reserved; /* BH_CURVE_* the bodies are sorted along */
     double lo[3], side;
+    int64_t movers;          /* bodies the last build's adaptive re-sort moved;
+                                -1 when it sorted in full */
 } bh_tree_info;
 int bh_tree_info_get(const bh_tree *tree, bh_tree_info *info);
 

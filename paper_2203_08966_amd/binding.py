@@ -22,6 +22,7 @@ BH_MLP_BF16, BH_MLP_FP16 = 0, 1
 BH_WALK_BODY, BH_WALK_GROUP, BH_WALK_DIRECT = 0, 1, 2
 BH_GROUP_BODIES = 64  # bodies per group of BH_WALK_GROUP
 BH_CURVE_MORTON, BH_CURVE_HILBERT = 0, 1
+BH_SORT_ADAPTIVE, BH_SORT_FULL = 0, 1
 
 EXPORTED = [
     "bh_version", "bh_last_error", "bh_force_opts_default", "bh_ctx_create", "bh_ctx_set_stream",
@@ -30,7 +31,7 @@ EXPORTED = [
     "bh_sim_tree", "bh_direct", "bh_direct_static", "bh_sim_timing", "bh_sim_timing_get", "bh_sim_counts_get",
     "bh_mlp_set",
     "bh_mlp_get", "bh_mlp_samples", "bh_mlp_train", "bh_mlp_grad", "bh_mlp_infer",
-    "bh_standard_units", "bh_ctx_set_allocator", "bh_ctx_set_curve",
+    "bh_standard_units", "bh_ctx_set_allocator", "bh_ctx_set_curve", "bh_ctx_set_sort",
 ]
 BH_MLP_PARAMS = 1441
 
@@ -71,6 +72,7 @@ class TreeInfo(C.Structure):
         ("n", C.c_int64), ("m", C.c_int64), ("depth", C.c_int32), ("dtype", C.c_int32),
         ("leaf_size", C.c_int32), ("last_mac", C.c_int32), ("curve", C.c_int32),
         ("reserved", C.c_int32), ("lo", C.c_double * 3), ("side", C.c_double),
+        ("movers", C.c_int64),
     ]
 
 
@@ -95,6 +97,7 @@ def load(path: str = LIB_PATH):
         "bh_ctx_create": ([i32, vp, pp], i32),
         "bh_ctx_set_stream": ([vp, vp], i32),
         "bh_ctx_set_curve": ([vp, i32], i32),
+        "bh_ctx_set_sort": ([vp, i32], i32),
         "bh_ctx_destroy": ([vp], i32),
         "bh_sync": ([vp], i32),
         "bh_build": ([vp, vp, vp, i32, i64, i32, pp], i32),
@@ -235,6 +238,10 @@ def bh_ctx_set_curve(ctx, curve: int):
     _check(load().bh_ctx_set_curve(ctx, int(curve)))
 
 
+def bh_ctx_set_sort(ctx, mode: int):
+    _check(load().bh_ctx_set_sort(ctx, int(mode)))
+
+
 def bh_ctx_destroy(ctx):
     _check(load().bh_ctx_destroy(ctx))
     _ALLOCATORS.pop(ctx.value, None)
@@ -310,7 +317,7 @@ def bh_tree_info_get(tree) -> dict:
     _check(load().bh_tree_info_get(tree, C.byref(info)))
     return dict(n=info.n, m=info.m, depth=info.depth, dtype=info.dtype,
                 leaf_size=info.leaf_size, last_mac=info.last_mac, curve=info.curve,
-                lo=np.array(info.lo[:]), side=info.side)
+                lo=np.array(info.lo[:]), side=info.side, movers=info.movers)
 
 
 def bh_tree_export(tree) -> dict:

@@ -79,7 +79,7 @@ static void free_tree_bufs(bh_tree *t) {
                      &t->level, &t->begin, &t->count, &t->next, &t->parent, &t->cmask,
                      &t->lvl_list, &t->cx, &t->cy, &t->cz, &t->mom, &t->recs,
                      &t->cube, &t->part, &t->hist, &t->status, &t->misc, &t->cnt_scratch,
-                     &t->kc, &t->anorm, &t->est_acc, &t->kids, &t->ulist, &t->s3, &t->oct, &t->wq, &t->gorder,
+                     &t->kc, &t->anorm, &t->est_acc, &t->kids, &t->ulist, &t->mv, &t->s3, &t->oct, &t->wq, &t->gorder,
                      &t->gfb};
     for (DevBuf *b : all) free_buf(*b);
 }
@@ -217,6 +217,14 @@ int bh_ctx_set_curve(bh_ctx *c, int curve) {
     return BH_OK;
 }
 
+int bh_ctx_set_sort(bh_ctx *c, int mode) {
+    if (!c) return set_error(BH_E_INVALID, "null ctx");
+    if (mode != BH_SORT_ADAPTIVE && mode != BH_SORT_FULL)
+        return set_error(BH_E_INVALID, "sort mode must be BH_SORT_ADAPTIVE or BH_SORT_FULL");
+    c->sort_mode = mode;
+    return BH_OK;
+}
+
 int bh_ctx_set_allocator(bh_ctx *c, bh_alloc_fn alloc, bh_free_fn free_fn, void *user) {
     if (!c) return set_error(BH_E_INVALID, "null ctx");
     if ((alloc == nullptr) != (free_fn == nullptr))
@@ -276,7 +284,7 @@ int bh_build(bh_ctx *c, const void *pos, const void *mass, int dtype, int64_t n,
         t->ctx = c;
     }
     rc = build_tree(c, t, pos, mass, dtype, n, leaf, nullptr, nullptr, nullptr, nullptr,
-                    nullptr, nullptr);
+                    nullptr, nullptr, false);
     if (rc) {
         if (fresh) {
             free_tree_bufs(t);
@@ -334,6 +342,7 @@ int bh_tree_info_get(const bh_tree *t, bh_tree_info *info) {
     info->leaf_size = t->leaf;
     info->last_mac = t->last_mac;
     info->curve = t->curve;
+    info->movers = t->movers;
     for (int d = 0; d < 3; ++d) info->lo[d] = t->lo[d];
     info->side = t->L;
     return BH_OK;
@@ -423,10 +432,10 @@ static int sim_forces(bh_ctx *c, bool want_phi) {
 }
 
 static int sim_rebuild(bh_ctx *c, const void *pos, const void *vel, const void *mass,
-                       const uint32_t *id) {
+                       const uint32_t *id, bool presorted) {
     SimState *s = c->sim;
     int rc = build_tree(c, c->sim_tree, pos, mass, s->dtype, s->n, s->leaf, vel, id, s->pos2.p,
-                        s->vel2.p, s->mass2.p, (uint32_t *)s->id2.p);
+                        s->vel2.p, s->mass2.p, (uint32_t *)s->id2.p, presorted);
     if (rc) return rc;
     std::swap(s->pos, s->pos2);
     std::swap(s->vel, s->vel2);
@@ -458,6 +467,9 @@ int bh_sim_init(bh_ctx *c, const void *pos, const void *vel, const void *mass, i
         c->sim_tree = new bh_tree;
         c->sim_tree->ctx = c;
     }
+    // a new simulation starts without the previous one's group-walk
+    // fallback predictions (its walks then depend on its inputs alone)
+    c->sim_tree->gfb_ng = -1;
     SimState *s = c->sim;
     s->dtype = dtype;
     s->n = n;
@@ -475,7 +487,7 @@ int bh_sim_init(bh_ctx *c, const void *pos, const void *vel, const void *mass, i
         (rc = grow(s->red, 8ull * (2 * 1024 + 8))))
         return rc;
     // first build gathers straight from the caller's arrays
-    if ((rc = sim_rebuild(c, pos, vel, mass, nullptr))) return rc;
+    if ((rc = sim_rebuild(c, pos, vel, mass, nullptr, false))) return rc;
     if ((rc = sim_forces(c, true))) return rc;
     s->have_acc = true;
     return BH_OK;
@@ -514,7 +526,7 @@ int bh_leapfrog_step(bh_ctx *c, double dt) {
     // new tree and accelerations at the drifted positions (the direct method
     // keeps the bodies in the order of the first build and needs no tree)
     if (s->opts.walk != BH_WALK_DIRECT &&
-        (rc = sim_rebuild(c, s->pos.p, s->vel.p, s->mass.p, (const uint32_t *)s->id.p)))
+        (rc = sim_rebuild(c, s->pos.p, s->vel.p, s->mass.p, (const uint32_t *)s->id.p, true)))
         return rc;
     mark(2);
     c->walk_ev = ev ? ev + 5 : nullptr;  // the walk kernel alone: events 5, 6

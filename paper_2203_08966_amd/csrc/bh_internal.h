@@ -97,6 +97,7 @@ struct bh_ctx {
     bh_tree *sim_tree = nullptr;
     int live_trees = 0;
     int curve = BH_CURVE_MORTON;     // space-filling curve of later builds
+    int sort_mode = BH_SORT_ADAPTIVE;  // re-sort of a simulation's rebuilds
     // learned acceptance criterion
     bh::DevBuf mlp_w;                // packed inference weights (MlpPacked)
     bh::DevBuf mlp_master;           // FP32 parameters, Adam m, Adam v
@@ -125,6 +126,8 @@ struct bh_tree {
     int32_t lvl_cnt[22] = {}, lvl_base[22] = {};  // cells per level, first slot in lvl_list
     int last_mac = -1;  // criterion the last walk of this tree used (-1: none yet)
     int curve = BH_CURVE_MORTON;  // the curve the bodies are sorted along
+    bool resort_ok = false;       // the last build completed (its keys and leaves are valid)
+    int64_t movers = -1;          // bodies the last build's re-sort moved (-1: full sort)
     double lo[3] = {0, 0, 0}, L = 1.0;
     // body-indexed
     bh::DevBuf keys_a, keys_b, idx_a, idx_b;  // radix-sort ping-pong
@@ -142,6 +145,7 @@ struct bh_tree {
     bh::DevBuf kc, anorm, est_acc;
     bh::DevBuf kids;                           // group walk: children per node
     bh::DevBuf ulist;                          // upward pass: subtree roots, upper cells
+    bh::DevBuf mv;                             // re-sort: the movers' keys and positions
     bh::DevBuf s3, oct;                        // order 3: raw third moments, octopole records
     int64_t oct_tree_id = -1;
     bh::DevBuf wq;                             // group walk: queue counters
@@ -182,9 +186,11 @@ int check_launch(const char *what);
 // ---- tree construction (build.hip)
 // Builds the tree from device pos/mass of `dtype`.  If `vel`/`id` are given
 // (simulation), they are permuted alongside into vel_out/id_out.
+// presorted: the bodies come in the order of this tree's previous build (a
+// simulation step), which allows the nearly sorted re-sort
 int build_tree(bh_ctx *ctx, bh_tree *t, const void *pos, const void *mass, int dtype,
                int64_t n, int leaf, const void *vel, const uint32_t *id, void *pos_out,
-               void *vel_out, void *mass_out, uint32_t *id_out);
+               void *vel_out, void *mass_out, uint32_t *id_out, bool presorted);
 
 // Octopole records of the tree (order-3 walks), computed on first use per
 // build: 8 values of the tree's dtype per node (see build.hip).

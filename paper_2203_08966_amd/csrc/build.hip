@@ -457,6 +457,204 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
     }
 }
 
+// ------------------------------------------------------------------ 3b. nearly sorted input
+// A simulation rebuilds its tree from the bodies in the order of its previous
+// build, and after a short step that order is still nearly sorted (Sec. 4.4
+// makes the same observation and re-sorts by insertion).  Here a body whose
+// new key keeps the key prefix of the leaf it sat in "stays": the leaves of
+// the previous tree are disjoint key ranges in rank order, so staying bodies
+// of different leaves are already in order; a leaf whose staying bodies are
+// out of key order among themselves has all its bodies moved.  The movers
+// (about 1 % of the bodies per step of the 2^22-body Plummer sphere) are
+// radix-sorted, then merged with the stayers by rank.  Keys are compared
+// with the input position as tie-break, so the result is exactly the stable
+// sort of the new keys whatever the previous tree was (its leaves only
+// decide how much moves).
+
+// Per leaf of the previous tree (thread per node): mover flags of its bodies.
+__global__ __launch_bounds__(kThreads) void k_ns_mark(int m_old, const int32_t *__restrict__ next,
+                                                      const int32_t *__restrict__ level,
+                                                      const int32_t *__restrict__ begin,
+                                                      const int32_t *__restrict__ count,
+                                                      const uint64_t *__restrict__ old_keys,
+                                                      const uint64_t *__restrict__ new_keys,
+                                                      int n, uint8_t *__restrict__ mover) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m_old || next[c] != c + 1) return;
+    const int b = begin[c];
+    const int e = min(b + count[c], n);  // guard
+    if (b < 0 || b >= e) return;
+    const int sh = 3 * (kLevels - level[c]);  // 63 for a root leaf: every key stays
+    const uint64_t pre = old_keys[b] >> sh;
+    bool in_order = true, have = false;
+    uint64_t prev = 0;
+    for (int i = b; i < e; ++i) {
+        const uint64_t k = new_keys[i];
+        const bool stay = (k >> sh) == pre;
+        mover[i] = stay ? 0 : 1;
+        if (stay) {
+            if (have && k < prev) in_order = false;  // equal keys: input order is the tie-break
+            prev = k;
+            have = true;
+        }
+    }
+    if (!in_order)
+        for (int i = b; i < e; ++i) mover[i] = 1;
+}
+
+// Movers per chunk of kThreads bodies, and the 8 digit histograms of the
+// movers' keys (for their radix sort).  Few large blocks stride over the
+// chunks, so that the histogram reaches global memory in few adds.
+constexpr int kNsCountBlocks = 256;
+__global__ __launch_bounds__(1024) void k_ns_count(int n, const uint8_t *__restrict__ mover,
+                                                   const uint64_t *__restrict__ keys,
+                                                   uint32_t *__restrict__ bcnt,
+                                                   uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[8][256];
+    __shared__ uint32_t ws[16];
+    for (int j = threadIdx.x; j < 8 * 256; j += 1024) (&h[0][0])[j] = 0u;
+    __syncthreads();
+    const int nchunk = (n + kThreads - 1) / kThreads;
+    // four chunks of kThreads bodies per iteration of the block
+    for (int c0 = 4 * blockIdx.x; c0 < nchunk; c0 += 4 * gridDim.x) {
+        const int i = c0 * kThreads + threadIdx.x;
+        const bool mv = i < n && mover[i];
+        if (mv) {
+            const uint64_t k = keys[i];
+#pragma unroll
+            for (int p = 0; p < 8; ++p) atomicAdd(&h[p][(uint32_t)(k >> (8 * p)) & 255u], 1u);
+        }
+        const uint64_t bal = ballot(mv);
+        if (lane_id() == 0) ws[threadIdx.x / 64] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        if (threadIdx.x < 4 && c0 + (int)threadIdx.x < nchunk) {
+            const int q = threadIdx.x;
+            bcnt[c0 + q] = ws[4 * q] + ws[4 * q + 1] + ws[4 * q + 2] + ws[4 * q + 3];
+        }
+        __syncthreads();
+    }
+    for (int j = threadIdx.x; j < 8 * 256; j += 1024) {
+        const uint32_t v = (&h[0][0])[j];
+        if (v) atomicAdd(&hist[j], v);
+    }
+}
+
+// Stayers to (skeys, sidx) in input order, movers to (mkeys, midx) in input
+// order; boff: the exclusive scan of the block counts.  Every kNsSample-th
+// stayer is also copied to (tkeys, tidx), a sample small enough to stay in
+// cache for the movers' searches.
+constexpr int kNsSample = 64;
+__global__ __launch_bounds__(kThreads) void k_ns_split(int n, const uint8_t *__restrict__ mover,
+                                                       const uint64_t *__restrict__ keys,
+                                                       const uint32_t *__restrict__ boff,
+                                                       uint64_t *__restrict__ skeys,
+                                                       uint32_t *__restrict__ sidx,
+                                                       uint64_t *__restrict__ mkeys,
+                                                       uint32_t *__restrict__ midx,
+                                                       uint64_t *__restrict__ tkeys,
+                                                       uint32_t *__restrict__ tidx) {
+    __shared__ uint32_t ws[kThreads / 64];
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const bool mv = i < n && mover[i];
+    const uint64_t bal = ballot(mv);
+    const int w = threadIdx.x / 64;
+    if (lane_id() == 0) ws[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t before = boff[blockIdx.x] + rank_in(bal);
+    for (int q = 0; q < w; ++q) before += ws[q];
+    if (i < n) {
+        const uint64_t k = keys[i];
+        if (mv) {
+            mkeys[before] = k;
+            midx[before] = (uint32_t)i;
+        } else {
+            const int si = i - (int)before;
+            skeys[si] = k;
+            sidx[si] = (uint32_t)i;
+            if (si % kNsSample == 0) {
+                tkeys[si / kNsSample] = k;
+                tidx[si / kNsSample] = (uint32_t)i;
+            }
+        }
+    }
+}
+
+// (key, position) order: the stable order of keys
+__device__ __forceinline__ bool ns_less(uint64_t ka, uint32_t ia, uint64_t kb, uint32_t ib) {
+    return ka < kb || (ka == kb && ia < ib);
+}
+// how many of the sorted pairs (k, v)[lo, hi) come before (key, id), plus lo
+__device__ __forceinline__ int ns_rank_in(const uint64_t *__restrict__ k,
+                                          const uint32_t *__restrict__ v, int lo, int hi,
+                                          uint64_t key, uint32_t id) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ns_less(k[mid], v[mid], key, id)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Merge by rank: stayer j goes to j + (movers before it), mover q to q +
+// (stayers before it).  A wavefront takes kNsPerLane * 64 consecutive
+// stayers (sorted): one full search each for its first and last stayer
+// bounds the movers' range that the others search (usually a few movers
+// wide), so the chains of dependent loads are few.
+constexpr int kNsPerLane = 4;
+__global__ __launch_bounds__(kThreads) void k_ns_merge_stay(int ns, int nm,
+                                                            const uint64_t *__restrict__ skeys,
+                                                            const uint32_t *__restrict__ sidx,
+                                                            const uint64_t *__restrict__ mkeys,
+                                                            const uint32_t *__restrict__ midx,
+                                                            uint64_t *__restrict__ okeys,
+                                                            uint32_t *__restrict__ oidx) {
+    constexpr int kSpan = 64 * kNsPerLane;
+    const int lane = (int)lane_id();
+    const int w0 = (blockIdx.x * (kThreads / 64) + (int)(threadIdx.x >> 6)) * kSpan;
+    if (w0 >= ns) return;  // whole wavefront
+    const int last = min(w0 + kSpan - 1, ns - 1);
+    int r = 0;
+    if (lane == 0) r = ns_rank_in(mkeys, midx, 0, nm, skeys[w0], sidx[w0]);
+    if (lane == 63) r = ns_rank_in(mkeys, midx, 0, nm, skeys[last], sidx[last]);
+    const int lo = __builtin_amdgcn_readfirstlane(r);
+    const int hi = __builtin_amdgcn_readlane(r, 63);
+#pragma unroll
+    for (int e = 0; e < kNsPerLane; ++e) {
+        const int j = w0 + 64 * e + lane;
+        if (j < ns) {
+            const uint64_t k = skeys[j];
+            const uint32_t v = sidx[j];
+            const int o = j + ns_rank_in(mkeys, midx, lo, hi, k, v);
+            okeys[o] = k;
+            oidx[o] = v;
+        }
+    }
+}
+
+// The movers' side: c samples (every kNsSample-th stayer) come before the
+// mover, so do the stayers up to kNsSample (c - 1), and none from
+// kNsSample c on.
+__global__ __launch_bounds__(kThreads) void k_ns_merge_move(int ns, int nm,
+                                                            const uint64_t *__restrict__ skeys,
+                                                            const uint32_t *__restrict__ sidx,
+                                                            const uint64_t *__restrict__ mkeys,
+                                                            const uint32_t *__restrict__ midx,
+                                                            const uint64_t *__restrict__ tkeys,
+                                                            const uint32_t *__restrict__ tidx,
+                                                            uint64_t *__restrict__ okeys,
+                                                            uint32_t *__restrict__ oidx) {
+    const int q = blockIdx.x * kThreads + threadIdx.x;
+    if (q >= nm) return;
+    const uint64_t k = mkeys[q];
+    const uint32_t v = midx[q];
+    const int c = ns_rank_in(tkeys, tidx, 0, (ns + kNsSample - 1) / kNsSample, k, v);
+    const int lo = c > 0 ? kNsSample * (c - 1) + 1 : 0;
+    const int hi = min(kNsSample * c, ns);
+    const int o = q + ns_rank_in(skeys, sidx, lo, hi, k, v);
+    okeys[o] = k;
+    oidx[o] = v;
+}
+
 // ------------------------------------------------------------------ 4. gather
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gather(int n, uint32_t *__restrict__ flags,
@@ -1285,7 +1483,7 @@ __global__ __launch_bounds__(kThreads) void k_oct_pack(int m, const double *__re
 template <typename T>
 int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int B,
                 const T *vel, const uint32_t *id, T *pos_out, T *vel_out, T *mass_out,
-                uint32_t *id_out) {
+                uint32_t *id_out, bool resort) {
     hipStream_t st = ctx->stream;
     const int ntiles = div_up(n, kSortTile);
     const int nb = div_up(n, kThreads);
@@ -1298,7 +1496,7 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
         (rc = grow(t->idx_a, 4ull * n)) || (rc = grow(t->idx_b, 4ull * n)) ||
         (rc = grow(t->delta, (size_t)n + 1)) || (rc = grow(t->nstart, (size_t)n)) ||
         (rc = grow(t->offs, 4ull * (n + 1))) || (rc = grow(t->cube, sizeof(Cube))) ||
-        (rc = grow(t->part, 7ull * 8 * nbbox)) || (rc = grow(t->hist, 4ull * 256 * 8 * 2)) ||
+        (rc = grow(t->part, 7ull * 8 * nbbox)) || (rc = grow(t->hist, 4ull * 256 * 8 * 4)) ||
         (rc = grow(t->misc, 256 + 4ull * (kLevels + 2) * (nb + 1))) ||
         (rc = grow(t->status, 8ull * 256 * ntiles)) ||
         (rc = grow(t->bodies, sizeof(BodyRec<T>) * (size_t)n)) ||
@@ -1320,11 +1518,17 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     uint32_t *flags = misc, *tile_ctr = misc + 8, *seg_tot = misc + 16;
     uint32_t *bsum = misc + 64;
     uint32_t *ucnt = misc + 48;  // upward pass: roots, upper cells, hand-out
+    // digit histograms and their scans: all keys, then the movers of a
+    // nearly sorted input
     uint32_t *hist = (uint32_t *)t->hist.p, *doff = hist + 2048;
+    uint32_t *mhist = hist + 4096, *mdoff = hist + 6144;
 
-    // the digit histogram is left zeroed by the previous build's scan;
+    // the digit histograms are left zeroed by the previous build's scans;
     // only fresh memory needs clearing
-    if (t->hist.cap != hist_cap0) k_fill_u32<<<8, 256, 0, st>>>(hist, 2048, 0u);
+    if (t->hist.cap != hist_cap0) {
+        k_fill_u32<<<8, 256, 0, st>>>(hist, 2048, 0u);
+        k_fill_u32<<<8, 256, 0, st>>>(mhist, 2048, 0u);
+    }
     if (t->status.cap != status_cap0) {
         // fresh look-back status memory: clear it, or leftover words of
         // whatever used the memory before could carry the current epoch
@@ -1334,25 +1538,89 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     k_bbox<T><<<nbbox, kThreads, 0, st>>>(pos, n, (double *)t->part.p);
     k_cube<<<1, kThreads, 0, st>>>((const double *)t->part.p, nbbox, cube, (Cube *)(misc + 40),
                                    flags);
-    k_keys<T><<<nkeys, kKeyThreads, 0, st>>>(pos, n, cube, (uint64_t *)t->keys_a.p, hist,
-                                             ctx->curve);
+    // the new keys go to the buffer that does not hold the previous build's
+    // sorted keys (a nearly sorted rebuild reads those)
+    uint64_t *kold = t->sorted_keys;
+    uint64_t *knew = kold == (uint64_t *)t->keys_a.p ? (uint64_t *)t->keys_b.p
+                                                     : (uint64_t *)t->keys_a.p;
+    uint64_t *kother = knew == (uint64_t *)t->keys_a.p ? (uint64_t *)t->keys_b.p
+                                                       : (uint64_t *)t->keys_a.p;
+    k_keys<T><<<nkeys, kKeyThreads, 0, st>>>(pos, n, cube, knew, hist, ctx->curve);
     k_hist_scan<<<8, 256, 0, st>>>(hist, doff, tile_ctr);
-    uint64_t *ka = (uint64_t *)t->keys_a.p, *kb = (uint64_t *)t->keys_b.p;
-    uint32_t *va = nullptr, *vb = (uint32_t *)t->idx_b.p, *vspare = (uint32_t *)t->idx_a.p;
-    for (int p = 0; p < 8; ++p) {
-        const uint32_t ep = ++ctx->epoch;
-        k_sort_pass<<<ntiles, kSortThreads, 0, st>>>(ka, va, kb, vb, n, 8 * p, doff + 256 * p,
-                                                     (unsigned long long *)t->status.p,
-                                                     tile_ctr + p, ep & 0x3fffffffu);
-        uint64_t *tk = ka;
-        ka = kb;
-        kb = tk;
-        uint32_t *tv = va ? va : vspare;
-        va = vb;
-        vb = tv;
+    // one radix sort of n (key, index) pairs, 8 passes of 8 bits: from (ka,
+    // va) (va NULL: the input positions), through (kb, vb), ending in (ka,
+    // va) again (an even number of passes)
+    auto radix = [&](uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, uint32_t *vspare,
+                     int cnt, const uint32_t *offs8) -> uint32_t * {
+        const int tiles = div_up(cnt, kSortTile);
+        for (int p = 0; p < 8; ++p) {
+            const uint32_t ep = ++ctx->epoch;
+            k_sort_pass<<<tiles, kSortThreads, 0, st>>>(ka, va, kb, vb, cnt, 8 * p,
+                                                        offs8 + 256 * p,
+                                                        (unsigned long long *)t->status.p,
+                                                        tile_ctr + p, ep & 0x3fffffffu);
+            uint64_t *tk = ka;
+            ka = kb;
+            kb = tk;
+            uint32_t *tv = va ? va : vspare;
+            va = vb;
+            vb = tv;
+        }
+        return va;
+    };
+    bool sorted = false;
+    t->movers = -1;
+    if (resort && kold) {
+        // nearly sorted input: stayers, movers, merge (see k_ns_mark)
+        const int64_t cap = n / 4 + 1, tcap = n / kNsSample + 1;
+        if ((rc = grow(t->mv, 24ull * cap + 12ull * tcap))) return rc;
+        uint64_t *mk0 = (uint64_t *)t->mv.p, *mk1 = mk0 + cap, *tk = mk1 + cap;
+        uint32_t *mi0 = (uint32_t *)(tk + tcap), *mi1 = mi0 + cap, *ti = mi1 + cap;
+        uint8_t *mover = (uint8_t *)t->nstart.p;  // free until the topology
+        const int m_old = (int)t->m;
+        k_ns_mark<<<div_up(m_old, kThreads), kThreads, 0, st>>>(
+            m_old, (const int32_t *)t->next.p, (const int32_t *)t->level.p,
+            (const int32_t *)t->begin.p, (const int32_t *)t->count.p, kold, knew, n, mover);
+        k_ns_count<<<std::min(kNsCountBlocks, div_up(nb, 4)), 1024, 0, st>>>(n, mover, knew,
+                                                                             bsum, mhist);
+        k_scan_sums<<<1, 1024, 0, st>>>(bsum, nb, misc + 51);
+        // the mover histograms are scanned (and so cleared) on every path
+        k_hist_scan<<<8, 256, 0, st>>>(mhist, mdoff, tile_ctr);
+        uint32_t *hp = (uint32_t *)ctx->pinned + 56;
+        if ((rc = check_launch("resort")) ||
+            hipMemcpyAsync(hp, misc + 51, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return rc ? rc : set_error(BH_E_DEVICE, "build: device failure while re-sorting");
+        const int nm = (int)hp[0];
+        if (nm >= 0 && nm < cap) {
+            k_ns_split<<<nb, kThreads, 0, st>>>(n, mover, knew, bsum, kother,
+                                                (uint32_t *)t->idx_a.p, mk0, mi0, tk, ti);
+            if (nm > 1) radix(mk0, mi0, mk1, mi1, nullptr, nm, mdoff);
+            const int ns = n - nm;
+            const uint32_t *si = (const uint32_t *)t->idx_a.p;
+            uint32_t *oi = (uint32_t *)t->idx_b.p;
+            if (ns > 0)
+                k_ns_merge_stay<<<div_up(ns, kThreads * kNsPerLane), kThreads, 0, st>>>(
+                    ns, nm, kother, si, mk0, mi0, knew, oi);
+            if (nm > 0)
+                k_ns_merge_move<<<div_up(nm, kThreads), kThreads, 0, st>>>(ns, nm, kother, si,
+                                                                           mk0, mi0, tk, ti,
+                                                                           knew, oi);
+            t->sorted_keys = knew;
+            t->perm = (uint32_t *)t->idx_b.p;
+            t->movers = nm;
+            sorted = true;
+        }
+        // else: too many movers for the merge to pay; the full sort below
+        // uses the all-key histograms scanned above
     }
-    t->sorted_keys = ka;
-    t->perm = va;
+    if (!sorted) {
+        t->perm = radix(knew, nullptr, kother, (uint32_t *)t->idx_b.p, (uint32_t *)t->idx_a.p, n,
+                        doff);
+        t->sorted_keys = knew;
+    }
+    uint64_t *ka = t->sorted_keys;
+    uint32_t *va = t->perm;
     if ((rc = check_launch("sort"))) return rc;
     k_gather<T><<<nb, kThreads, 0, st>>>(n, flags, va, pos, mass, vel, id, pos_out, mass_out, vel_out,
                                          id_out);
@@ -1486,7 +1754,12 @@ int ensure_octopole(bh_tree *t) {
 
 int build_tree(bh_ctx *ctx, bh_tree *t, const void *pos, const void *mass, int dtype,
                int64_t n, int leaf, const void *vel, const uint32_t *id, void *pos_out,
-               void *vel_out, void *mass_out, uint32_t *id_out) {
+               void *vel_out, void *mass_out, uint32_t *id_out, bool presorted) {
+    // the nearly sorted re-sort needs this tree's previous build (same n)
+    // complete: its sorted keys and its leaves
+    const bool resort = presorted && ctx->sort_mode == BH_SORT_ADAPTIVE && t->resort_ok &&
+                        t->n == n && t->m > 0 && t->sorted_keys != nullptr;
+    t->resort_ok = false;
     t->dtype = dtype;
     t->n = n;
     t->leaf = leaf;
@@ -1496,11 +1769,12 @@ int build_tree(bh_ctx *ctx, bh_tree *t, const void *pos, const void *mass, int d
     if (dtype == BH_F32)
         rc = build_typed<float>(ctx, t, (const float *)pos, (const float *)mass, (int)n, leaf,
                                 (const float *)vel, id, (float *)pos_out, (float *)vel_out,
-                                (float *)mass_out, id_out);
+                                (float *)mass_out, id_out, resort);
     else
         rc = build_typed<double>(ctx, t, (const double *)pos, (const double *)mass, (int)n,
                                  leaf, (const double *)vel, id, (double *)pos_out,
-                                 (double *)vel_out, (double *)mass_out, id_out);
+                                 (double *)vel_out, (double *)mass_out, id_out, resort);
+    t->resort_ok = rc == BH_OK;
     return rc;
 }
 

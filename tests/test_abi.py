@@ -52,6 +52,7 @@ def test_null_handles_rejected():
     assert lib.bh_standard_units(None, None, None, None, 0, 10, None) == B.BH_E_INVALID
     assert lib.bh_ctx_set_allocator(None, B.ALLOC_FN(), B.FREE_FN(), None) == B.BH_E_INVALID
     assert lib.bh_ctx_set_curve(None, B.BH_CURVE_HILBERT) == B.BH_E_INVALID
+    assert lib.bh_ctx_set_sort(None, B.BH_SORT_FULL) == B.BH_E_INVALID
     assert lib.bh_tree_free(None) == B.BH_E_INVALID
     assert lib.bh_ctx_destroy(None) == B.BH_E_INVALID
     assert lib.bh_sync(None) == B.BH_E_INVALID

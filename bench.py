@@ -553,7 +553,7 @@ def mlp_roofline(B, ctx, feat, epochs, train_s, precision):
     """The network's roofline figures: the batched MFMA inference kernel over
     the training features (10 FP32 features read per row: HBM-bound at
     2752 / 40 flop per byte, below the MFMA ridge), and the training pass
-    (FP32 vector arithmetic, whole bh_mlp_train call)."""
+    (FP32 MFMA, whole bh_mlp_train call, against the FP32 peak)."""
     import torch
     n = int(feat.shape[0])
     B.bh_mlp_infer(ctx, feat, precision)
@@ -575,7 +575,7 @@ def mlp_roofline(B, ctx, feat, epochs, train_s, precision):
                   "peak": PEAK_MFMA_16BIT_TFLOPS, "unit": "TFLOP/s",
                   "frac": inf_tf / PEAK_MFMA_16BIT_TFLOPS, "bound": "hbm",
                   "hbm_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS},
-        "train": {"kernel": "k_mlp_grad + k_mlp_adam (FP32 vector)", "samples": n,
+        "train": {"kernel": "k_mlp_grad (FP32 MFMA) + k_mlp_adam", "samples": n,
                   "epochs": epochs, "seconds": train_s, "flop_per_sample": MLP_TRAIN_FLOP,
                   "achieved": tr_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                   "frac": tr_tf / PEAK_FP32_TFLOPS},

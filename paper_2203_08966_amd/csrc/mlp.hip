@@ -256,102 +256,162 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const int32_t *__restrict_
 }
 
 // ------------------------------------------------------------------ training
+// One wavefront per block of kTrainBlock samples, in tiles of 32, with FP32
+// MFMA (v_mfma_f32_32x32x2_f32: A 32x2, one value per lane at row l%32 and
+// k l/32; B 2x32 at k l/32 and column l%32; D 32x32, register v of lane l
+// at row 8(v/4) + 4(l/32) + v%4 and column l%32).  Products take hidden
+// units down the rows and the tile's samples across the columns, the layout
+// of the inference; an accumulator then feeds the next product as its B
+// operand register by register, if the product's K runs over the units in
+// the order its rows hold them (kappa below).
 constexpr int kTrainBlock = 128;  // samples per block
+constexpr int kTrainTile = 32;    // samples per MFMA column block
+
+__device__ __forceinline__ f32x16 mfma_f32(float a, float b, const f32x16 &c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+// the row (hidden unit) of accumulator register v on a lane of half-wave h
+__device__ __forceinline__ int acc_row(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
 
 // Gradient of the loss over one minibatch: mean-squared error (quantile 0)
 // or the pinball loss of quantile q (derivative 1 - q where the prediction
 // exceeds the label, else -q).  Sample j of the batch is sample
 // (a * (base + j) + c) mod ns of the set (a permutation of the set per
-// epoch).  Each block writes its partial gradient and loss.
-__global__ __launch_bounds__(kTrainBlock) void k_mlp_grad(
+// epoch).  Each block writes its partial gradient and loss; sums run in a
+// fixed order (tiles, then the MFMA's own), so the result is deterministic.
+__global__ __launch_bounds__(64) void k_mlp_grad(
     const float *__restrict__ w, const float *__restrict__ X, const float *__restrict__ y,
     int64_t ns, int64_t base, int bs, uint64_t a, uint64_t c, float quantile,
     float *__restrict__ gpart) {
     __shared__ float sw[kMlpParams];
-    __shared__ float sx[kTrainBlock][kMlpIn];
-    __shared__ float sh1[kTrainBlock][kMlpHidden];
-    __shared__ float sd1[kTrainBlock][kMlpHidden];
-    __shared__ float sh2[kTrainBlock][kMlpHidden];
-    __shared__ float sd2[kTrainBlock][kMlpHidden];
-    __shared__ float sdo[kTrainBlock];
-    __shared__ float sl[kTrainBlock];
-    const int t = threadIdx.x;
-    for (int k = t; k < kMlpParams; k += kTrainBlock) sw[k] = w[k];
+    __shared__ float sa[kMlpHidden][kTrainTile + 1];  // transposes: unit x sample
+    __shared__ float sb[kMlpHidden][kTrainTile + 1];
+    __shared__ float sx[kTrainTile][16];              // features, 1 (bias slot), 0
+    const int l = (int)threadIdx.x;
+    const int h = l >> 5, r = l & 31;
+    for (int k = l; k < kMlpParams; k += 64) sw[k] = w[k];
     __syncthreads();
     const float *W1 = sw, *b1 = sw + 320, *W2 = sw + 352, *b2 = sw + 1376, *w3 = sw + 1408;
     const float b3 = sw[1440];
-    const int j = blockIdx.x * kTrainBlock + t;
-    const bool live = j < bs;
-    float x[kMlpIn], z1[kMlpHidden], z2[kMlpHidden];
-    float yy = 0;
-    if (live) {
-        const uint64_t g = base + (uint64_t)j;
-        const int64_t sidx = (int64_t)((a * (g % (uint64_t)ns) + c) % (uint64_t)ns);
-        for (int q = 0; q < kMlpIn; ++q) x[q] = X[kMlpIn * sidx + q];
-        yy = y[sidx];
-    } else {
-        for (int q = 0; q < kMlpIn; ++q) x[q] = 0.f;
+    // operands that stay over the tiles
+    float A1[8], A2[16], AT[16], b2v[16], w3v[16];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = 2 * i + h;  // feature slot: 0..9 weights, 10 bias, 11..15 zero
+        A1[i] = k < kMlpIn ? W1[r * kMlpIn + k] : (k == kMlpIn ? b1[r] : 0.f);
     }
-    for (int u = 0; u < kMlpHidden; ++u) {
-        float s = b1[u];
-        for (int q = 0; q < kMlpIn; ++q) s += W1[u * kMlpIn + q] * x[q];
-        z1[u] = s;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int kap = acc_row(i, h);
+        A2[i] = W2[r * kMlpHidden + kap];  // row r of W2, K in row order
+        AT[i] = W2[kap * kMlpHidden + r];  // row r of W2^T
+        b2v[i] = b2[acc_row(i, h)];
+        w3v[i] = w3[acc_row(i, h)];
     }
-    for (int u = 0; u < kMlpHidden; ++u) {
-        float s = b2[u];
-        for (int q = 0; q < kMlpHidden; ++q) s += W2[u * kMlpHidden + q] * fmaxf(z1[q], 0.f);
-        z2[u] = s;
-    }
-    float out = b3;
-    for (int u = 0; u < kMlpHidden; ++u) out += w3[u] * fmaxf(z2[u], 0.f);
-    float dout, lv;
-    if (quantile > 0.f) {
-        const bool over = out > yy;
-        dout = (over ? 1.f - quantile : -quantile) / (float)bs;
-        lv = over ? (1.f - quantile) * (out - yy) : quantile * (yy - out);
-    } else {
-        dout = 2.f * (out - yy) / (float)bs;
-        lv = (out - yy) * (out - yy);
-    }
-    if (!live) dout = lv = 0.f;
-    sl[t] = lv;
-    sdo[t] = dout;
-    for (int q = 0; q < kMlpIn; ++q) sx[t][q] = x[q];
-    float d2v[kMlpHidden];
-    for (int u = 0; u < kMlpHidden; ++u) {
-        d2v[u] = z2[u] > 0.f ? dout * w3[u] : 0.f;
-        sd2[t][u] = d2v[u];
-        sh2[t][u] = fmaxf(z2[u], 0.f);
-        sh1[t][u] = fmaxf(z1[u], 0.f);
-    }
-    for (int q = 0; q < kMlpHidden; ++q) {
-        float s = 0.f;
-        for (int u = 0; u < kMlpHidden; ++u) s += W2[u * kMlpHidden + q] * d2v[u];
-        sd1[t][q] = z1[q] > 0.f ? s : 0.f;
-    }
-    __syncthreads();
-    // reduce over the block's samples, in sample order
-    float *gp = gpart + (size_t)blockIdx.x * (kMlpParams + 1);
-    for (int k = t; k < kMlpParams + 1; k += kTrainBlock) {
-        float s = 0.f;
-        if (k < 320) {  // W1[u][q] = sum d1[u] x[q]
-            const int u = k / kMlpIn, q = k % kMlpIn;
-            for (int r = 0; r < kTrainBlock; ++r) s += sd1[r][u] * sx[r][q];
-        } else if (k < 352) {
-            for (int r = 0; r < kTrainBlock; ++r) s += sd1[r][k - 320];
-        } else if (k < 1376) {  // W2[u][q] = sum d2[u] h1[q]
-            const int u = (k - 352) / kMlpHidden, q = (k - 352) % kMlpHidden;
-            for (int r = 0; r < kTrainBlock; ++r) s += sd2[r][u] * sh1[r][q];
-        } else if (k < 1408) {
-            for (int r = 0; r < kTrainBlock; ++r) s += sd2[r][k - 1376];
-        } else if (k < 1440) {
-            for (int r = 0; r < kTrainBlock; ++r) s += sdo[r] * sh2[r][k - 1408];
-        } else if (k == 1440) {
-            for (int r = 0; r < kTrainBlock; ++r) s += sdo[r];
-        } else {  // loss sum
-            for (int r = 0; r < kTrainBlock; ++r) s += sl[r];
+    f32x16 gW1 = {}, gW2 = {};
+    float gb2 = 0.f, gw3 = 0.f, gb3 = 0.f, lsum = 0.f;
+    for (int t = 0; t < kTrainBlock / kTrainTile; ++t) {
+        const int j = blockIdx.x * kTrainBlock + t * kTrainTile + r;  // this lane's sample
+        const bool live = j < bs;
+        float yy = 0.f;
+        if (h == 0) {
+            float x[kMlpIn] = {};
+            if (live) {
+                const uint64_t g = base + (uint64_t)j;
+                const int64_t sidx = (int64_t)((a * (g % (uint64_t)ns) + c) % (uint64_t)ns);
+                for (int q = 0; q < kMlpIn; ++q) x[q] = X[kMlpIn * sidx + q];
+            }
+            for (int q = 0; q < 16; ++q) sx[r][q] = q < kMlpIn ? x[q] : (q == kMlpIn ? 1.f : 0.f);
         }
-        gp[k] = s;
+        if (live) {
+            const uint64_t g = base + (uint64_t)j;
+            yy = y[(int64_t)((a * (g % (uint64_t)ns) + c) % (uint64_t)ns)];
+        }
+        __syncthreads();
+        // forward: z1 = W1e xe, z2 = W2 relu(z1) + b2 (rows: units, columns: samples)
+        f32x16 z1 = {};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) z1 = mfma_f32(A1[i], sx[r][2 * i + h], z1);
+        f32x16 z2;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) z2[v] = b2v[v];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) z2 = mfma_f32(A2[i], fmaxf(z1[i], 0.f), z2);
+        float p = 0.f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) p += w3v[v] * fmaxf(z2[v], 0.f);
+        const float out = p + __shfl_xor(p, 32) + b3;  // sample r, on both halves
+        float dout, lv;
+        if (quantile > 0.f) {
+            const bool over = out > yy;
+            dout = (over ? 1.f - quantile : -quantile) / (float)bs;
+            lv = over ? (1.f - quantile) * (out - yy) : quantile * (yy - out);
+        } else {
+            dout = 2.f * (out - yy) / (float)bs;
+            lv = (out - yy) * (out - yy);
+        }
+        if (!live) dout = lv = 0.f;
+        // backward: d2 = dout w3 relu'(z2); d1 = (W2^T d2) relu'(z1)
+        f32x16 d2, e1 = {};
+#pragma unroll
+        for (int v = 0; v < 16; ++v) d2[v] = z2[v] > 0.f ? dout * w3v[v] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) e1 = mfma_f32(AT[i], d2[i], e1);
+        // dW2 = sum over samples of d2 h1^T: both operands transposed
+        // through LDS (row u = r, k = sample)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            sa[acc_row(v, h)][r] = d2[v];
+            sb[acc_row(v, h)][r] = fmaxf(z1[v], 0.f);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) gW2 = mfma_f32(sa[r][2 * i + h], sb[r][2 * i + h], gW2);
+        if (h == 0)  // b2: the row sums of d2
+            for (int q = 0; q < kTrainTile; ++q) gb2 += sa[r][q];
+        __syncthreads();
+        // w3: the row sums of dout h2; then dW1 = sum of d1 xe^T (its bias
+        // column is b1's gradient)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            sa[acc_row(v, h)][r] = dout * fmaxf(z2[v], 0.f);
+            sb[acc_row(v, h)][r] = z1[v] > 0.f ? e1[v] : 0.f;
+        }
+        __syncthreads();
+        if (h == 0)
+            for (int q = 0; q < kTrainTile; ++q) gw3 += sa[r][q];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            gW1 = mfma_f32(sb[r][2 * i + h], r < 16 ? sx[2 * i + h][r] : 0.f, gW1);
+        __syncthreads();
+        // b3 and the loss: sums over the tile's samples in sample order
+        if (h == 0) sa[0][r] = dout;
+        __syncthreads();
+        if (l == 0) {
+            for (int q = 0; q < kTrainTile; ++q) gb3 += sa[0][q];
+        }
+        __syncthreads();
+        if (h == 0) sa[0][r] = lv;
+        __syncthreads();
+        if (l == 0)
+            for (int q = 0; q < kTrainTile; ++q) lsum += sa[0][q];
+        __syncthreads();
+    }
+    float *gp = gpart + (size_t)blockIdx.x * (kMlpParams + 1);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int u = acc_row(v, h);
+        if (r < kMlpIn) gp[u * kMlpIn + r] = gW1[v];
+        else if (r == kMlpIn) gp[320 + u] = gW1[v];
+        gp[352 + u * kMlpHidden + r] = gW2[v];
+    }
+    if (h == 0) {
+        gp[1376 + r] = gb2;
+        gp[1408 + r] = gw3;
+    }
+    if (l == 0) {
+        gp[1440] = gb3;
+        gp[1441] = lsum;
     }
 }
 
@@ -537,7 +597,7 @@ int mlp_grad_step(bh_ctx *c, const float *X, const float *y, int64_t ns, int64_t
     const int nblk = div_up(bs, kTrainBlock);
     int rc = grow(c->mlp_gpart, 4ull * (kMlpParams + 1) * nblk);
     if (rc) return rc;
-    k_mlp_grad<<<nblk, kTrainBlock, 0, c->stream>>>((const float *)c->mlp_master.p, X, y, ns, base,
+    k_mlp_grad<<<nblk, 64, 0, c->stream>>>((const float *)c->mlp_master.p, X, y, ns, base,
                                                     bs, a, cc, cfg.quantile,
                                                     (float *)c->mlp_gpart.p);
     const float c1 = 1.f - powf(cfg.beta1, (float)step), c2 = 1.f - powf(cfg.beta2, (float)step);

@@ -24,9 +24,10 @@ over a seeded 4096-body subsample:
                 Plummer spheres;
   body-theta-o3, group-theta-o3  the two opening-angle walks with the
                 octopole term added to each particle-cell interaction;
-  body-theta-hilbert, group-theta-hilbert, group-budget-hilbert  three of
-                the walks over bodies sorted along the Peano-Hilbert curve
-                (a group is 64 consecutive bodies of that curve).
+  body-theta-hilbert, group-theta-hilbert, group-budget-hilbert,
+  group-learned-hilbert  four of the walks over bodies sorted along the
+                Peano-Hilbert curve (a group is 64 consecutive bodies of
+                that curve).
 Each is swept over its parameter grid from accurate to cheap; the cheapest
 grid value with rms <= 1e-3 is kept, and the method with the fastest walk
 at that value is the one timed.  After the timed steps the rms error is
@@ -94,12 +95,12 @@ METHODS = {
     "group-theta-o3": [round(0.6 + 0.00625 * k, 5) for k in range(73)],
 }
 # the same methods over bodies sorted along the Peano-Hilbert curve
-for _m in ("body-theta", "group-theta", "group-budget"):
+for _m in ("body-theta", "group-theta", "group-budget", "group-learned"):
     METHODS[_m + "-hilbert"] = METHODS[_m]
 PARAM_NAME = {"body-theta": "theta", "body-theta-guard": "theta", "group-theta": "theta",
               "group-budget": "log10_tau",
               "group-learned": "log10_tau", "body-theta-o3": "theta", "group-theta-o3": "theta"}
-for _m in ("body-theta", "group-theta", "group-budget"):
+for _m in ("body-theta", "group-theta", "group-budget", "group-learned"):
     PARAM_NAME[_m + "-hilbert"] = PARAM_NAME[_m]
 
 
@@ -274,7 +275,7 @@ def main():
     # ---- the learned criterion: train the network on the library's own FP64
     # simulations of small Plummer spheres (bf16 MFMA inference afterwards)
     learned_info = None
-    if "group-learned" in names:
+    if "group-learned" in names or "group-learned-hilbert" in names:
         from paper_2203_08966_amd import learned as LM
         t0 = time.perf_counter()
         feat, label = LM.training_set(ctx)
@@ -427,7 +428,7 @@ def main():
             **({"theta_max": BUDGET_THETA_MAX, "acc_floor": ACC_FLOOR}
                if PARAM_NAME[chosen] == "log10_tau" else {}),
             **({"mlp": "fp16" if mlp_precision == B.BH_MLP_FP16 else "bf16"}
-               if chosen == "group-learned" else {}),
+               if base_of(chosen) == "group-learned" else {}),
             "step": "KDK leapfrog step: kick+drift, rebuild, walk (accelerations), kick; "
                     "energy before and after the timed steps",
         },

@@ -207,19 +207,43 @@ __device__ __forceinline__ uint32_t rot3r(uint32_t x, uint32_t r) {  // r in 0..
 __device__ __forceinline__ uint32_t rot3l(uint32_t x, uint32_t r) {
     return ((x << r) | (x >> (3u - r))) & 7u;
 }
-__device__ __forceinline__ uint64_t hilbert3(uint32_t qx, uint32_t qy, uint32_t qz) {
-    uint32_t e = 0, d = 0;
-    uint64_t h = 0;
+// One level: state s = 3 e + d, the level's three bits l; returns the next
+// state and the digit w.
+__device__ __forceinline__ uint32_t hb_step(uint32_t s, uint32_t l, uint32_t &w) {
+    uint32_t e = s / 3u, d = s - 3u * (s / 3u);
+    const uint32_t t = rot3r(l ^ e, d == 2 ? 0u : d + 1u);
+    w = t ^ (t >> 1) ^ (t >> 2);
+    e ^= rot3l((kHbEntry >> (3u * w)) & 7u, d == 2 ? 0u : d + 1u);
+    d += ((kHbAxis >> (2u * w)) & 3u) + 1u;
+    d = d >= 3u ? d - 3u : d;
+    d = d >= 3u ? d - 3u : d;
+    return 3u * e + d;
+}
+__device__ __forceinline__ uint32_t hb_bits(uint32_t qx, uint32_t qy, uint32_t qz, int i) {
+    return ((qx >> i) & 1u) | (((qy >> i) & 1u) << 1) | (((qz >> i) & 1u) << 2);
+}
+// Two levels per lookup: entry 64 s + (l_hi << 3 | l_lo) of this table
+// holds the two digits (6 bits) and the state after them (bits 6..10), for
+// the 24 states; filled by the threads of a workgroup from hb_step.
+constexpr int kHbTable = 24 * 64;
+__device__ __forceinline__ void hb_table_fill(uint16_t *tab, int t, int nt) {
+    for (int idx = t; idx < kHbTable; idx += nt) {
+        uint32_t w1, w2;
+        const uint32_t s1 = hb_step((uint32_t)idx >> 6, ((uint32_t)idx >> 3) & 7u, w1);
+        const uint32_t s2 = hb_step(s1, (uint32_t)idx & 7u, w2);
+        tab[idx] = (uint16_t)((w1 << 3) | w2 | (s2 << 6));
+    }
+}
+__device__ __forceinline__ uint64_t hilbert3_tab(uint32_t qx, uint32_t qy, uint32_t qz,
+                                                 const uint16_t *tab) {
+    uint32_t w;
+    uint32_t s = hb_step(0u, hb_bits(qx, qy, qz, kLevels - 1), w);  // the top level alone
+    uint64_t h = w;
 #pragma unroll
-    for (int i = kLevels - 1; i >= 0; --i) {
-        const uint32_t l = ((qx >> i) & 1u) | (((qy >> i) & 1u) << 1) | (((qz >> i) & 1u) << 2);
-        const uint32_t t = rot3r(l ^ e, d == 2 ? 0u : d + 1u);
-        const uint32_t w = t ^ (t >> 1) ^ (t >> 2);
-        e ^= rot3l((kHbEntry >> (3u * w)) & 7u, d == 2 ? 0u : d + 1u);
-        d += ((kHbAxis >> (2u * w)) & 3u) + 1u;
-        d = d >= 3u ? d - 3u : d;
-        d = d >= 3u ? d - 3u : d;
-        h = (h << 3) | w;
+    for (int i = kLevels - 2; i > 0; i -= 2) {  // levels i and i - 1
+        const uint32_t v = tab[64u * s + ((hb_bits(qx, qy, qz, i) << 3) | hb_bits(qx, qy, qz, i - 1))];
+        h = (h << 6) | (v & 63u);
+        s = v >> 6;
     }
     return h;
 }
@@ -261,7 +285,9 @@ __global__ __launch_bounds__(kKeyThreads) void k_keys(const T *__restrict__ pos,
                                                       uint64_t *__restrict__ keys,
                                                       uint32_t *__restrict__ hist, int curve) {
     __shared__ uint32_t h[8][256];
+    __shared__ uint16_t hb_tab[kHbTable];
     for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
+    if (curve == BH_CURVE_HILBERT) hb_table_fill(hb_tab, threadIdx.x, blockDim.x);
     __syncthreads();
     const double lx = cube->lo[0], ly = cube->lo[1], lz = cube->lo[2];
     const double scale = ldexp(1.0, kLevels) / cube->L;
@@ -277,7 +303,7 @@ __global__ __launch_bounds__(kKeyThreads) void k_keys(const T *__restrict__ pos,
             const uint32_t qx = quantise((double)pos[b + 0], lx, scale),
                            qy = quantise((double)pos[b + 1], ly, scale),
                            qz = quantise((double)pos[b + 2], lz, scale);
-            k = curve == BH_CURVE_HILBERT ? hilbert3(qx, qy, qz)
+            k = curve == BH_CURVE_HILBERT ? hilbert3_tab(qx, qy, qz, hb_tab)
                                           : (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
             keys[i] = k;
         }

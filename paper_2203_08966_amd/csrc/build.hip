@@ -1106,58 +1106,102 @@ __global__ __launch_bounds__(kThreads) void k_leaves(UpArgs ua, const T *__restr
         }
     }
     __syncthreads();
-    if (!leaf) return;
-    // body j's position component d and mass, from LDS or memory
-    auto P = [&](int j, int d) -> double {
-        return (double)(staged ? stg[w][d][j - lo] : spos[3 * (int64_t)j + d]);
-    };
-    auto Mj = [&](int j) -> T { return staged ? stg[w][3][j - lo] : smass[j]; };
     const double h = ldexp(cube->L, -(kLevels + 1));
-    const double c0 = cube->lo[0] + gn.cx * h, c1 = cube->lo[1] + gn.cy * h,
-                 c2 = cube->lo[2] + gn.cz * h;
-    Anchor<R> an;
-    an.x = (R)(gn.cx * h);  // exact
-    an.y = (R)(gn.cy * h);
-    an.z = (R)(gn.cz * h);
-    an.leaf = i;
-    double mt = 0, s0 = 0, s1 = 0, s2 = 0;
-    for (int j = b; j < e; ++j) {
-        const T mm = Mj(j);
-        const double mj = (double)mm;
-        const double y0 = P(j, 0) - c0;
-        const double y1 = P(j, 1) - c1;
-        const double y2 = P(j, 2) - c2;
-        mt += mj;
-        s0 += mj * y0;
-        s1 += mj * y1;
-        s2 += mj * y2;
-        BodyRec<R> br;
-        br.x = (R)y0;
-        br.y = (R)y1;
-        br.z = (R)y2;
-        br.m = (R)mm;
-        bodies[j] = br;
-        anchors[j] = an;
+    if (leaf) {
+        // body j's position component d and mass, from LDS or memory
+        auto P = [&](int j, int d) -> double {
+            return (double)(staged ? stg[w][d][j - lo] : spos[3 * (int64_t)j + d]);
+        };
+        auto Mj = [&](int j) -> T { return staged ? stg[w][3][j - lo] : smass[j]; };
+        const double c0 = cube->lo[0] + gn.cx * h, c1 = cube->lo[1] + gn.cy * h,
+                     c2 = cube->lo[2] + gn.cz * h;
+        Anchor<R> an;
+        an.x = (R)(gn.cx * h);  // exact
+        an.y = (R)(gn.cy * h);
+        an.z = (R)(gn.cz * h);
+        an.leaf = i;
+        double mt = 0, s0 = 0, s1 = 0, s2 = 0;
+        for (int j = b; j < e; ++j) {
+            const T mm = Mj(j);
+            const double mj = (double)mm;
+            const double y0 = P(j, 0) - c0;
+            const double y1 = P(j, 1) - c1;
+            const double y2 = P(j, 2) - c2;
+            mt += mj;
+            s0 += mj * y0;
+            s1 += mj * y1;
+            s2 += mj * y2;
+            if (!staged) {  // (a staged wavefront writes its records below)
+                BodyRec<R> br;
+                br.x = (R)y0;
+                br.y = (R)y1;
+                br.z = (R)y2;
+                br.m = (R)mm;
+                bodies[j] = br;
+                anchors[j] = an;
+            }
+        }
+        Moments r;
+        r.m = mt;
+        r.c[0] = mt > 0 ? s0 / mt : 0.0;
+        r.c[1] = mt > 0 ? s1 / mt : 0.0;
+        r.c[2] = mt > 0 ? s2 / mt : 0.0;
+        for (int a = 0; a < 6; ++a) r.t[a] = 0.0;
+        for (int j = b; j < e; ++j) {
+            const double mj = (double)Mj(j);
+            const double y0 = P(j, 0) - c0 - r.c[0];
+            const double y1 = P(j, 1) - c1 - r.c[1];
+            const double y2 = P(j, 2) - c2 - r.c[2];
+            r.t[0] += mj * y0 * y0;
+            r.t[1] += mj * y0 * y1;
+            r.t[2] += mj * y0 * y2;
+            r.t[3] += mj * y1 * y1;
+            r.t[4] += mj * y1 * y2;
+            r.t[5] += mj * y2 * y2;
+        }
+        finish_node<R>(ua, i, gn, r, 0u, h);
     }
-    Moments r;
-    r.m = mt;
-    r.c[0] = mt > 0 ? s0 / mt : 0.0;
-    r.c[1] = mt > 0 ? s1 / mt : 0.0;
-    r.c[2] = mt > 0 ? s2 / mt : 0.0;
-    for (int a = 0; a < 6; ++a) r.t[a] = 0.0;
-    for (int j = b; j < e; ++j) {
-        const double mj = (double)Mj(j);
-        const double y0 = P(j, 0) - c0 - r.c[0];
-        const double y1 = P(j, 1) - c1 - r.c[1];
-        const double y2 = P(j, 2) - c2 - r.c[2];
-        r.t[0] += mj * y0 * y0;
-        r.t[1] += mj * y0 * y1;
-        r.t[2] += mj * y0 * y2;
-        r.t[3] += mj * y1 * y1;
-        r.t[4] += mj * y1 * y2;
-        r.t[5] += mj * y2 * y2;
+    // A staged wavefront writes the body and anchor records of its whole
+    // body range with coalesced stores: its leaves, in body order (pre-order
+    // leaves hold consecutive ranges), are listed in LDS, and each body finds
+    // its leaf by a binary search of their first bodies.
+    __shared__ int32_t lb[kThreads / 64][64], lnode[kThreads / 64][64];
+    __shared__ int32_t lcx[kThreads / 64][64], lcy[kThreads / 64][64], lcz[kThreads / 64][64];
+    const uint64_t lm = ballot(leaf);
+    if (staged && leaf) {
+        const int slot = (int)rank_in(lm);
+        lb[w][slot] = b;
+        lnode[w][slot] = i;
+        lcx[w][slot] = gn.cx;
+        lcy[w][slot] = gn.cy;
+        lcz[w][slot] = gn.cz;
     }
-    finish_node<R>(ua, i, gn, r, 0u, h);
+    __syncthreads();
+    if (staged) {
+        const int nl = __popcll(lm);
+        for (int j = lo + (int)lane_id(); j < hi; j += 64) {
+            int s0 = 0, s1 = nl;  // lb[w][s0] <= j < lb[w][s1]
+            while (s1 - s0 > 1) {
+                const int mid = (s0 + s1) >> 1;
+                if (lb[w][mid] <= j) s0 = mid;
+                else s1 = mid;
+            }
+            const int cx = lcx[w][s0], cy = lcy[w][s0], cz = lcz[w][s0];
+            const T mm = stg[w][3][j - lo];
+            BodyRec<R> br;
+            br.x = (R)((double)stg[w][0][j - lo] - (cube->lo[0] + cx * h));
+            br.y = (R)((double)stg[w][1][j - lo] - (cube->lo[1] + cy * h));
+            br.z = (R)((double)stg[w][2][j - lo] - (cube->lo[2] + cz * h));
+            br.m = (R)mm;
+            bodies[j] = br;
+            Anchor<R> an;
+            an.x = (R)(cx * h);  // exact
+            an.y = (R)(cy * h);
+            an.z = (R)(cz * h);
+            an.leaf = lnode[w][s0];
+            anchors[j] = an;
+        }
+    }
 }
 
 // One internal cell: combine its children (already done, one level deeper)

@@ -145,6 +145,10 @@ def parse():
                     default=None, help="time only this method (default: the fastest at the "
                     "target error)")
     ap.add_argument("--target-err", type=float, default=1e-3)
+    ap.add_argument("--acc-floor", type=float, default=ACC_FLOOR,
+                    help="budget criteria: |a_i| floored at this fraction of the mean |a|")
+    ap.add_argument("--theta-max", type=float, default=BUDGET_THETA_MAX,
+                    help="budget criteria: cells above this opening angle are opened")
     ap.add_argument("--walk-cap", type=int, default=0,
                     help="group walk work cap (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -238,8 +242,8 @@ def main():
         elif method in ("group-budget", "group-learned"):
             kw.update(walk=B.BH_WALK_GROUP, walk_cap=args.walk_cap, mlp_precision=mlp_precision,
                       mac=B.BH_MAC_BUDGET if method == "group-budget" else B.BH_MAC_MLP,
-                      mlp_log10_tau=p, mlp_theta_max=BUDGET_THETA_MAX,
-                      mlp_acc_norm=None if for_sim else anorm, mlp_acc_floor=ACC_FLOOR)
+                      mlp_log10_tau=p, mlp_theta_max=args.theta_max,
+                      mlp_acc_norm=None if for_sim else anorm, mlp_acc_floor=args.acc_floor)
         return B.force_opts(**kw)
 
     def walk(method, p, counters=False):
@@ -377,6 +381,8 @@ def main():
         B.bh_leapfrog_step(ctx, dt)
     phase_ms, nsteps = B.bh_sim_timing_get(ctx)
     sim_pp, sim_pc = B.bh_sim_counts_get(ctx)
+    # bodies the last rebuild's adaptive re-sort moved (-1: it sorted in full)
+    movers = int(B.bh_tree_info_get(B.bh_sim_tree(ctx))["movers"])
     B.bh_sim_timing(ctx, False)
     ek, ep = B.bh_energy(ctx)
     ms_step = (t1 - t0) * 1e3 / args.steps
@@ -425,7 +431,8 @@ def main():
             "n": n, "eps": eps, "leaf": leaf, "order": order_of(chosen), "dt": dt,
             "curve": "hilbert" if hilbert(chosen) else "morton",
             "method": chosen, PARAM_NAME[chosen]: cp,
-            **({"theta_max": BUDGET_THETA_MAX, "acc_floor": ACC_FLOOR}
+            **({"theta_max": args.theta_max, "acc_floor": args.acc_floor,
+                "walk_cap": args.walk_cap or "library default"}
                if PARAM_NAME[chosen] == "log10_tau" else {}),
             **({"mlp": "fp16" if mlp_precision == B.BH_MLP_FP16 else "bf16"}
                if base_of(chosen) == "group-learned" else {}),
@@ -444,6 +451,7 @@ def main():
         "body_theta_points": theta_points,
         "phases_ms": phases,
         "phase_steps": int(nsteps),
+        "resort_movers_last_step": movers,
         "energy_rel_change": abs((ek + ep) - (ek0 + ep0)) / abs(ek0 + ep0),
         "methods": methods,
         "learned_training": learned_info,

@@ -626,12 +626,41 @@ __device__ __forceinline__ int ns_rank_in(const uint64_t *__restrict__ k,
 // stayers (sorted): one full search each for its first and last stayer
 // bounds the movers' range that the others search (usually a few movers
 // wide), so the chains of dependent loads are few.
-constexpr int kNsPerLane = 4;
+// stayers per lane of k_ns_merge_stay: more for a large sort (fewer chains
+// of dependent loads), fewer for a small one (more wavefronts to hide them)
+constexpr int kNsPerLaneSmall = 4, kNsPerLaneLarge = 16, kNsLargeStayers = 1 << 24;
+// the movers' rank of (key, id): first among every kNsSample-th mover
+// (tkeys, tidx: cached), then within one block of kNsSample movers
+__device__ __forceinline__ int ns_rank_sampled(const uint64_t *__restrict__ k,
+                                               const uint32_t *__restrict__ v, int len,
+                                               const uint64_t *__restrict__ tk,
+                                               const uint32_t *__restrict__ tv, uint64_t key,
+                                               uint32_t id) {
+    const int c = ns_rank_in(tk, tv, 0, (len + kNsSample - 1) / kNsSample, key, id);
+    const int lo = c > 0 ? kNsSample * (c - 1) + 1 : 0;
+    return ns_rank_in(k, v, lo, min(kNsSample * c, len), key, id);
+}
+
+// every kNsSample-th mover (sorted), for ns_rank_sampled
+__global__ __launch_bounds__(kThreads) void k_ns_sample(int nm, const uint64_t *__restrict__ mkeys,
+                                                        const uint32_t *__restrict__ midx,
+                                                        uint64_t *__restrict__ tkeys,
+                                                        uint32_t *__restrict__ tidx) {
+    const int q = blockIdx.x * kThreads + threadIdx.x;
+    if (q * kNsSample < nm) {
+        tkeys[q] = mkeys[q * kNsSample];
+        tidx[q] = midx[q * kNsSample];
+    }
+}
+
+template <int kNsPerLane>
 __global__ __launch_bounds__(kThreads) void k_ns_merge_stay(int ns, int nm,
                                                             const uint64_t *__restrict__ skeys,
                                                             const uint32_t *__restrict__ sidx,
                                                             const uint64_t *__restrict__ mkeys,
                                                             const uint32_t *__restrict__ midx,
+                                                            const uint64_t *__restrict__ mtk,
+                                                            const uint32_t *__restrict__ mti,
                                                             uint64_t *__restrict__ okeys,
                                                             uint32_t *__restrict__ oidx) {
     constexpr int kSpan = 64 * kNsPerLane;
@@ -640,8 +669,8 @@ __global__ __launch_bounds__(kThreads) void k_ns_merge_stay(int ns, int nm,
     if (w0 >= ns) return;  // whole wavefront
     const int last = min(w0 + kSpan - 1, ns - 1);
     int r = 0;
-    if (lane == 0) r = ns_rank_in(mkeys, midx, 0, nm, skeys[w0], sidx[w0]);
-    if (lane == 63) r = ns_rank_in(mkeys, midx, 0, nm, skeys[last], sidx[last]);
+    if (lane == 0) r = ns_rank_sampled(mkeys, midx, nm, mtk, mti, skeys[w0], sidx[w0]);
+    if (lane == 63) r = ns_rank_sampled(mkeys, midx, nm, mtk, mti, skeys[last], sidx[last]);
     const int lo = __builtin_amdgcn_readfirstlane(r);
     const int hi = __builtin_amdgcn_readlane(r, 63);
 #pragma unroll
@@ -1643,9 +1672,10 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     if (resort && kold) {
         // nearly sorted input: stayers, movers, merge (see k_ns_mark)
         const int64_t cap = n / 4 + 1, tcap = n / kNsSample + 1;
-        if ((rc = grow(t->mv, 24ull * cap + 12ull * tcap))) return rc;
-        uint64_t *mk0 = (uint64_t *)t->mv.p, *mk1 = mk0 + cap, *tk = mk1 + cap;
-        uint32_t *mi0 = (uint32_t *)(tk + tcap), *mi1 = mi0 + cap, *ti = mi1 + cap;
+        if ((rc = grow(t->mv, 24ull * cap + 24ull * tcap))) return rc;
+        uint64_t *mk0 = (uint64_t *)t->mv.p, *mk1 = mk0 + cap, *tk = mk1 + cap, *mtk = tk + tcap;
+        uint32_t *mi0 = (uint32_t *)(mtk + tcap), *mi1 = mi0 + cap, *ti = mi1 + cap,
+                 *mti = ti + tcap;
         uint8_t *mover = (uint8_t *)t->nstart.p;  // free until the topology
         const int m_old = (int)t->m;
         k_ns_mark<<<div_up(m_old, kThreads), kThreads, 0, st>>>(
@@ -1669,9 +1699,17 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
             const int ns = n - nm;
             const uint32_t *si = (const uint32_t *)t->idx_a.p;
             uint32_t *oi = (uint32_t *)t->idx_b.p;
-            if (ns > 0)
-                k_ns_merge_stay<<<div_up(ns, kThreads * kNsPerLane), kThreads, 0, st>>>(
-                    ns, nm, kother, si, mk0, mi0, knew, oi);
+            if (nm > 0)
+                k_ns_sample<<<div_up(div_up(nm, kNsSample), kThreads), kThreads, 0, st>>>(
+                    nm, mk0, mi0, mtk, mti);
+            if (ns >= kNsLargeStayers)
+                k_ns_merge_stay<kNsPerLaneLarge>
+                    <<<div_up(ns, kThreads * kNsPerLaneLarge), kThreads, 0, st>>>(
+                        ns, nm, kother, si, mk0, mi0, mtk, mti, knew, oi);
+            else if (ns > 0)
+                k_ns_merge_stay<kNsPerLaneSmall>
+                    <<<div_up(ns, kThreads * kNsPerLaneSmall), kThreads, 0, st>>>(
+                        ns, nm, kother, si, mk0, mi0, mtk, mti, knew, oi);
             if (nm > 0)
                 k_ns_merge_move<<<div_up(nm, kThreads), kThreads, 0, st>>>(ns, nm, kother, si,
                                                                            mk0, mi0, tk, ti,

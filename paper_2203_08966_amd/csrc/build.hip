@@ -497,16 +497,26 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(
 // sort of the new keys whatever the previous tree was (its leaves only
 // decide how much moves).
 
-// Per leaf of the previous tree (thread per node): mover flags of its bodies.
+// Per leaf of the previous tree (thread per node): each body's byte in
+// mover[] is kNsMover for a mover, else kNsStay + (its rank among the leaf's
+// stayers sorted by (key, position)) - (its rank among them in input
+// order), the offset that puts the leaf's stayers in order.  A leaf whose
+// stayers are out of order gets oflag 1 (k_ns_reorder then sets those
+// offsets); one with more than 64 bodies moves whole instead.  Every node
+// writes its oflag.
+constexpr uint8_t kNsMover = 255, kNsStay = 64;
 __global__ __launch_bounds__(kThreads) void k_ns_mark(int m_old, const int32_t *__restrict__ next,
                                                       const int32_t *__restrict__ level,
                                                       const int32_t *__restrict__ begin,
                                                       const int32_t *__restrict__ count,
                                                       const uint64_t *__restrict__ old_keys,
                                                       const uint64_t *__restrict__ new_keys,
-                                                      int n, uint8_t *__restrict__ mover) {
+                                                      int n, uint8_t *__restrict__ mover,
+                                                      uint8_t *__restrict__ oflag) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= m_old || next[c] != c + 1) return;
+    if (c >= m_old) return;
+    oflag[c] = 0;
+    if (next[c] != c + 1) return;
     const int b = begin[c];
     const int e = min(b + count[c], n);  // guard
     if (b < 0 || b >= e) return;
@@ -517,15 +527,52 @@ __global__ __launch_bounds__(kThreads) void k_ns_mark(int m_old, const int32_t *
     for (int i = b; i < e; ++i) {
         const uint64_t k = new_keys[i];
         const bool stay = (k >> sh) == pre;
-        mover[i] = stay ? 0 : 1;
+        mover[i] = stay ? kNsStay : kNsMover;
         if (stay) {
             if (have && k < prev) in_order = false;  // equal keys: input order is the tie-break
             prev = k;
             have = true;
         }
     }
-    if (!in_order)
-        for (int i = b; i < e; ++i) mover[i] = 1;
+    if (in_order) return;
+    if (e - b > 64) {
+        for (int i = b; i < e; ++i) mover[i] = kNsMover;
+        return;
+    }
+    oflag[c] = 1;
+}
+
+// The flagged leaves: a wavefront takes 64 consecutive nodes and reorders
+// its flagged leaves one after the other (lane j: body begin + j): a
+// stayer's rank by (key, position) among the stayers against its rank by
+// position.
+__global__ __launch_bounds__(kThreads) void k_ns_reorder(int m_old,
+                                                         const int32_t *__restrict__ begin,
+                                                         const int32_t *__restrict__ count,
+                                                         const uint64_t *__restrict__ new_keys,
+                                                         int n, uint8_t *__restrict__ mover,
+                                                         const uint8_t *__restrict__ oflag) {
+    const int lane = (int)lane_id();
+    const int c0 = (blockIdx.x * (kThreads / 64) + (int)(threadIdx.x >> 6)) * 64;
+    if (c0 >= m_old) return;  // whole wavefront
+    uint64_t fl = ballot(c0 + lane < m_old && oflag[c0 + lane]);
+    while (fl) {
+        const int c = c0 + __builtin_ctzll(fl);
+        fl &= fl - 1;
+        const int b = begin[c];
+        const int cnt = min(count[c], n - b);  // at most 64 (k_ns_mark)
+        const bool live = lane < cnt;
+        const uint64_t k = live ? new_keys[b + lane] : 0ull;
+        const bool stay = live && mover[b + lane] != kNsMover;
+        const uint64_t smask = ballot(stay);
+        int rs = 0;
+        for (int t = 0; t < cnt; ++t) {
+            const uint64_t kt = __shfl(k, t);
+            if ((smask >> t) & 1ull) rs += kt < k || (kt == k && t < lane) ? 1 : 0;
+        }
+        const int rin = (int)rank_in(smask);
+        if (stay) mover[b + lane] = (uint8_t)(kNsStay + rs - rin);
+    }
 }
 
 // Movers per chunk of kThreads bodies, and the 8 digit histograms of the
@@ -544,7 +591,7 @@ __global__ __launch_bounds__(1024) void k_ns_count(int n, const uint8_t *__restr
     // four chunks of kThreads bodies per iteration of the block
     for (int c0 = 4 * blockIdx.x; c0 < nchunk; c0 += 4 * gridDim.x) {
         const int i = c0 * kThreads + threadIdx.x;
-        const bool mv = i < n && mover[i];
+        const bool mv = i < n && mover[i] == kNsMover;
         if (mv) {
             const uint64_t k = keys[i];
 #pragma unroll
@@ -581,7 +628,8 @@ __global__ __launch_bounds__(kThreads) void k_ns_split(int n, const uint8_t *__r
                                                        uint32_t *__restrict__ tidx) {
     __shared__ uint32_t ws[kThreads / 64];
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    const bool mv = i < n && mover[i];
+    const uint8_t code = i < n ? mover[i] : kNsMover;
+    const bool mv = i < n && code == kNsMover;
     const uint64_t bal = ballot(mv);
     const int w = threadIdx.x / 64;
     if (lane_id() == 0) ws[w] = (uint32_t)__popcll(bal);
@@ -593,8 +641,8 @@ __global__ __launch_bounds__(kThreads) void k_ns_split(int n, const uint8_t *__r
         if (mv) {
             mkeys[before] = k;
             midx[before] = (uint32_t)i;
-        } else {
-            const int si = i - (int)before;
+        } else {  // the stayer's place, reordered within its leaf
+            const int si = i - (int)before + ((int)code - (int)kNsStay);
             skeys[si] = k;
             sidx[si] = (uint32_t)i;
             if (si % kNsSample == 0) {
@@ -1678,9 +1726,15 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
                  *mti = ti + tcap;
         uint8_t *mover = (uint8_t *)t->nstart.p;  // free until the topology
         const int m_old = (int)t->m;
+        // the previous build's upward-pass lists (8 m_old bytes) are free
+        // until this build's k_leaves: the leaves' out-of-order flags go there
+        uint8_t *oflag = (uint8_t *)t->ulist.p;
         k_ns_mark<<<div_up(m_old, kThreads), kThreads, 0, st>>>(
             m_old, (const int32_t *)t->next.p, (const int32_t *)t->level.p,
-            (const int32_t *)t->begin.p, (const int32_t *)t->count.p, kold, knew, n, mover);
+            (const int32_t *)t->begin.p, (const int32_t *)t->count.p, kold, knew, n, mover, oflag);
+        k_ns_reorder<<<div_up(m_old, kThreads), kThreads, 0, st>>>(
+            m_old, (const int32_t *)t->begin.p, (const int32_t *)t->count.p, knew, n, mover,
+            oflag);
         k_ns_count<<<std::min(kNsCountBlocks, div_up(nb, 4)), 1024, 0, st>>>(n, mover, knew,
                                                                              bsum, mhist);
         k_scan_sums<<<1, 1024, 0, st>>>(bsum, nb, misc + 51);

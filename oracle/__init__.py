@@ -346,7 +346,7 @@ def _mac_sigs(lib):
     lib.orc_cell_kc.argtypes = [C.c_int64, _i32, _f64, C.c_double, _f64]
     lib.orc_walk_kc.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64, _f64,
                                 C.c_double, C.c_double, C.c_double, C.c_double, _f64, _f64,
-                                C.c_int64, _i64, _f64, _f64, _i64, _i64, _i64, _i32]
+                                C.c_int64, _i64, _f64, _f64, _i64, _i64, _i64, _i32, C.c_int]
     lib.orc_walk_group.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
                                    _f64, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
                                    C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -414,9 +414,10 @@ def floored_norms(anorm, floor):
     return np.maximum(a, floor * a.mean())
 
 
-def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None, floor=0.0):
+def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None, floor=0.0, order=2):
     """Walk with the error budget (kc from ``cell_kc``); anorm is |a_i| per
-    sorted rank, floored by ``floored_norms``."""
+    sorted rank, floored by ``floored_norms``.  order 0: monopole terms, the
+    budget charging each cell the bound on its dropped quadrupole term too."""
     anorm = floored_norms(anorm, floor)
     lib = _mlib()
     t = b["tree"]
@@ -435,7 +436,7 @@ def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None, floor=0.0):
                     float(b["L"]), float(eps), float(theta_max),
                     float(tau), np.ascontiguousarray(kc, dtype=np.float64),
                     np.ascontiguousarray(anorm, dtype=np.float64), nt, tg, acc.ravel(), phi, npp,
-                    npc, ncov, flag)
+                    npc, ncov, flag, int(order))
     return WalkResult(acc, phi, npp, npc, ncov, flag)
 
 

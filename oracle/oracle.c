@@ -790,6 +790,20 @@ typedef struct {
     double tau, anorm; /* tau and |a_i| of the current body */
 } mac_ctx;
 
+/* The quadrupole term a particle-cell term drops when it keeps the monopole
+ * only (order 0): a_Q = Q x / s^5 - (5/2) (x.Q.x) x / s^7 (Sec. 2.2, R10).
+ * With |Q y| <= |Q|_2 |y| <= |Q|_F |y| and |x| <= s,
+ *   |a_Q| <= |Q|_F |x| / s^5 + (5/2) |Q|_F |x|^3 / s^7 <= (7/2) |Q|_F / s^4.
+ * The error budget with monopole terms charges a cell this bound at the
+ * (group) distance d plus the next order's estimate M l^3 / d^5:
+ *   M l^3 + (7/2) |Q|_F d < tau a d^5. */
+#define ORC_QUAD_BOUND 3.5
+static double q_frobenius(const double *q)
+{
+    return sqrt(q[0] * q[0] + q[3] * q[3] + q[5] * q[5] +
+                2.0 * (q[1] * q[1] + q[2] * q[2] + q[4] * q[4]));
+}
+
 /* Per cell: M l^3, the error budget's k_C M l^3 with k_C = 1. */
 void orc_cell_kc(int64_t m, const int32_t *level, const double *M, double L, double *kc)
 {
@@ -820,7 +834,11 @@ static void cell_force_kc(mac_ctx *m, int64_t node, int64_t i, walk_acc *r)
             x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
         const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
         const double s2 = side * side;
-        const double lhs = m->kc[c], rhs = m->tau * m->anorm * d2 * d2 * sqrt(d2);
+        /* monopole terms (order 0): the dropped quadrupole's bound as well */
+        const double lhs = m->kc[c] + (w->order == 0 ? ORC_QUAD_BOUND *
+                                                           q_frobenius(&w->Q[6 * c]) * sqrt(d2)
+                                                     : 0.0);
+        const double rhs = m->tau * m->anorm * d2 * d2 * sqrt(d2);
         double centre[3];
         cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
         int out = -1; /* three-valued "the body lies outside the cube" */
@@ -848,13 +866,14 @@ void orc_walk_kc(const int32_t *level, const uint64_t *hkey, const int32_t *begi
                  double L, double eps, double theta_max,
                  double tau, const double *kc, const double *anorm, int64_t nt,
                  const int64_t *targets, double *acc, double *phi, int64_t *npp, int64_t *npc,
-                 int64_t *ncov, int32_t *flag)
+                 int64_t *ncov, int32_t *flag, int order)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nt; ++t) {
         mac_ctx m;
         memset(&m, 0, sizeof(m));
-        m.w = (walk_ctx){level, begin, count, next, M, com, Q, spos, smass, L, 0.0, eps * eps, 2};
+        m.w = (walk_ctx){level, begin, count, next, M, com, Q, spos, smass, L, 0.0, eps * eps,
+                         order};
         m.hkey = hkey;
         m.lo = lo;
         m.tmax2 = theta_max * theta_max;
@@ -971,9 +990,13 @@ static void group_cell(group_ctx *g, int64_t node)
         int accept = !overlap && s2 < lim2;
         int terms[3] = {sep, cmp3(s2, lim2, g->tol, s2), 1};
         if (g->mode == 1) {
+            /* monopole terms (order 0): the dropped quadrupole's bound as well */
+            const double lhs = g->kc[c] + (w->order == 0 ? ORC_QUAD_BOUND *
+                                                               q_frobenius(&w->Q[6 * c]) * sqrt(dg2)
+                                                         : 0.0);
             const double rhs = g->tau * g->amin * dg2 * dg2 * sqrt(dg2);
-            terms[2] = cmp3(g->kc[c], rhs, g->tol, g->kc[c]);
-            accept = accept && g->kc[c] < rhs;
+            terms[2] = cmp3(lhs, rhs, g->tol, lhs);
+            accept = accept && lhs < rhs;
         } else if (g->mode == 2 && sep >= 0 && terms[1] >= 0) {
             int acc_l = 0;
             terms[2] = learned_term(g, c, side, dg2, &acc_l);

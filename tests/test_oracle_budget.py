@@ -140,3 +140,85 @@ def test_group_angle_limit_uses_the_box_distance():
             r = oracle.walk_group(tb, 0.0, group=2, mode=mode, kc=kc, anorm=an,
                                   target_range=(r0, r0 + 2), cap=1 << 40, split=False, **kw2)
             assert np.all(r.npc == (1 if accepted else 0)), (mode, f)
+
+
+# ---- monopole terms (order 0): the budget also charges each cell the bound
+# on the quadrupole term it drops, (7/2) |Q|_F / d^4
+
+def _quad_frobenius_by_hand():
+    """|Q|_F of C from its two masses: Q = sum m (3 y y^T - |y|^2 I), y
+    about the COM (the convention of Sec. 2.2)."""
+    Qm = np.zeros((3, 3))
+    for p, m in ((C1, MC1), (C2, MC2)):
+        y = np.array(p) - _com()
+        Qm += m * (3.0 * np.outer(y, y) - (y @ y) * np.eye(3))
+    return np.sqrt(np.sum(Qm * Qm))
+
+
+def test_dropped_quadrupole_within_its_bound():
+    """Far from C the monopole's error is its quadrupole term (the next
+    terms fall off faster): in every direction it stays within
+    (7/2) |Q|_F / d^4, and in the worst direction reaches a third of it (the
+    bound of a cell whose Q has two equal eigenvalues is 3/sqrt(6) of |Q|_F
+    along the axis, i.e. 0.35 of the bound)."""
+    qf = _quad_frobenius_by_hand()
+    rng = np.random.default_rng(3)
+    ratios = []
+    for _ in range(400):
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        d = 40.0
+        x = _com() + d * u
+        exact = np.zeros(3)
+        for p, m in ((C1, MC1), (C2, MC2)):
+            r = np.array(p) - x
+            exact += m * r / np.linalg.norm(r) ** 3
+        mono = (MC1 + MC2) * (_com() - x) / d ** 3
+        ratios.append(np.linalg.norm(exact - mono) / (3.5 * qf / d ** 4))
+    assert max(ratios) <= 1.0 + 1e-3
+    assert max(ratios) > 0.3
+
+
+def test_per_body_monopole_budget_flips_at_hand_threshold():
+    """Body A alone, monopole terms: accept C iff
+    M l^3 + (7/2) |Q|_F d < tau |a_A| d^5."""
+    tb, rank, c = _system()
+    M, com, Q = tb["mom"]
+    qf = _quad_frobenius_by_hand()
+    q = Q[c]
+    np.testing.assert_allclose(np.sqrt(q[0] ** 2 + q[3] ** 2 + q[5] ** 2
+                                       + 2 * (q[1] ** 2 + q[2] ** 2 + q[4] ** 2)), qf, rtol=1e-12)
+    kc = oracle.cell_kc(tb)
+    a_A = 0.7
+    an = _norms(rank, {1: a_A, 2: 5.0})
+    d = np.linalg.norm(np.array(A) - _com())
+    tau_star = ((MC1 + MC2) * SIDE ** 3 + 3.5 * qf * d) / (a_A * d ** 5)
+    # the quadrupole budget alone would accept well below this tau
+    assert (MC1 + MC2) * SIDE ** 3 / (a_A * d ** 5) < 0.9 * tau_star
+    for f, accepted in ((1 + 1e-3, True), (1 - 1e-3, False)):
+        r = oracle.walk_kc(tb, 0.0, 10.0, tau_star * f, kc, an, targets=[rank[1]], order=0)
+        assert r.npc[0] == (1 if accepted else 0), f
+        assert r.npp[0] == (3 if accepted else 5), f
+        assert r.flag[0] == 0
+
+
+def test_group_monopole_budget_flips_at_hand_threshold():
+    """Group {A, B}, monopole terms: accept C for both iff
+    M l^3 + (7/2) |Q|_F d_g < tau min |a| d_g^5."""
+    tb, rank, c = _system()
+    r0 = min(rank[1], rank[2])
+    kc = oracle.cell_kc(tb)
+    a_A, a_B = 1.3, 0.7
+    an = _norms(rank, {1: a_A, 2: a_B})
+    lo = np.minimum(A, B)
+    hi = np.maximum(A, B)
+    dg = np.linalg.norm(np.maximum(0.0, np.maximum(lo - _com(), _com() - hi)))
+    qf = _quad_frobenius_by_hand()
+    tau_star = ((MC1 + MC2) * SIDE ** 3 + 3.5 * qf * dg) / (min(a_A, a_B) * dg ** 5)
+    for f, accepted in ((1 + 1e-3, True), (1 - 1e-3, False)):
+        r = oracle.walk_group(tb, 0.0, group=2, mode=1, theta_max=10.0, tau=tau_star * f,
+                              kc=kc, anorm=an, target_range=(r0, r0 + 2), cap=1 << 40,
+                              split=False, order=0)
+        assert np.all(r.npc == (1 if accepted else 0)), f
+        assert np.all(r.npp == (3 if accepted else 5)), f
+        assert np.all(r.flag == 0)

@@ -24,10 +24,13 @@ over a seeded 4096-body subsample:
                 Plummer spheres;
   body-theta-o3, group-theta-o3  the two opening-angle walks with the
                 octopole term added to each particle-cell interaction;
+  group-budget-mono  the group error budget with monopole terms: a cell is
+                also charged the bound (7/2) |Q|_F / d_g^4 of the
+                quadrupole term it drops;
   body-theta-hilbert, group-theta-hilbert, group-budget-hilbert,
-  group-learned-hilbert  four of the walks over bodies sorted along the
-                Peano-Hilbert curve (a group is 64 consecutive bodies of
-                that curve).
+  group-budget-mono-hilbert, group-learned-hilbert  five of the walks over
+                bodies sorted along the Peano-Hilbert curve (a group is 64
+                consecutive bodies of that curve).
 Each is swept over its parameter grid from accurate to cheap; the cheapest
 grid value with rms <= 1e-3 is kept, and the method with the fastest walk
 at that value is the one timed.  After the timed steps the rms error is
@@ -93,20 +96,25 @@ METHODS = {
     # the opening angle with the octopole term (l = 3 of the expansion)
     "body-theta-o3": [round(0.5 + 0.005 * k, 3) for k in range(81)],
     "group-theta-o3": [round(0.6 + 0.00625 * k, 5) for k in range(73)],
+    # the budget with monopole terms (the dropped quadrupole's bound charged)
+    "group-budget-mono": [round(-3.0 + 0.03125 * k, 5) for k in range(57)],  # log10 tau
 }
 # the same methods over bodies sorted along the Peano-Hilbert curve
-for _m in ("body-theta", "group-theta", "group-budget", "group-learned"):
+for _m in ("body-theta", "group-theta", "group-budget", "group-budget-mono", "group-learned"):
     METHODS[_m + "-hilbert"] = METHODS[_m]
 PARAM_NAME = {"body-theta": "theta", "body-theta-guard": "theta", "group-theta": "theta",
-              "group-budget": "log10_tau",
+              "group-budget": "log10_tau", "group-budget-mono": "log10_tau",
               "group-learned": "log10_tau", "body-theta-o3": "theta", "group-theta-o3": "theta"}
-for _m in ("body-theta", "group-theta", "group-budget", "group-learned"):
+for _m in ("body-theta", "group-theta", "group-budget", "group-budget-mono", "group-learned"):
     PARAM_NAME[_m + "-hilbert"] = PARAM_NAME[_m]
 
 
 def order_of(method):
-    """Expansion order of a method: octopole for the -o3 variants."""
-    return 3 if method.endswith("-o3") else 2
+    """Expansion order of a method: octopole for the -o3 variants,
+    monopole for the -mono ones."""
+    if method.endswith("-o3"):
+        return 3
+    return 0 if "-mono" in method else 2
 
 
 def hilbert(method):
@@ -239,9 +247,9 @@ def main():
             kw.update(mac=B.BH_MAC_THETA_GUARD)
         elif method in ("group-theta", "group-theta-o3"):
             kw.update(walk=B.BH_WALK_GROUP, walk_cap=args.walk_cap)
-        elif method in ("group-budget", "group-learned"):
+        elif method in ("group-budget", "group-budget-mono", "group-learned"):
             kw.update(walk=B.BH_WALK_GROUP, walk_cap=args.walk_cap, mlp_precision=mlp_precision,
-                      mac=B.BH_MAC_BUDGET if method == "group-budget" else B.BH_MAC_MLP,
+                      mac=B.BH_MAC_MLP if method == "group-learned" else B.BH_MAC_BUDGET,
                       mlp_log10_tau=p, mlp_theta_max=args.theta_max,
                       mlp_acc_norm=None if for_sim else anorm, mlp_acc_floor=args.acc_floor)
         return B.force_opts(**kw)
@@ -457,7 +465,8 @@ def main():
         "learned_training": learned_info,
         "roofline": {
             "bound": "alu",
-            "kernel": f"{kernel} (FP32, {'octopole' if order_of(chosen) == 3 else 'quadrupole'})",
+            "kernel": f"{kernel} (FP32, "
+                      f"{ {0: 'monopole', 2: 'quadrupole', 3: 'octopole'}[order_of(chosen)]})",
             "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved_tf / PEAK_FP32_TFLOPS,
             "traffic": traffic_for(kernel, result_workload(cfg, n)),

@@ -121,10 +121,13 @@ typedef struct {
     int64_t target_begin; /* walk only bodies of sorted rank [begin, end); */
     int64_t target_end;   /* end <= 0 means all.  Outputs of other bodies are
                              left untouched. */
-    /* BH_MAC_BUDGET (FP32 quadrupole walk only): accept a multi-body cell
+    /* BH_MAC_BUDGET (FP32 walk of order 2 or 0): accept a multi-body cell
      * iff side/d < mlp_theta_max, the body is outside it, and
      * M side^3 < 10^mlp_log10_tau |a_i| d^5 (per group: d_g and the
-     * smallest |a_i|).  BH_MAC_MLP: the learned decision described with
+     * smallest |a_i|); with order 0 (monopole terms) the left side also
+     * holds (7/2) |Q|_F d, d^-4 times which bounds the quadrupole term the
+     * cell drops (Sec. 2.2), Q its traceless quadrupole.  BH_MAC_MLP (FP32
+     * quadrupole walk only): the learned decision described with
      * bh_mlp_set, with tau = 10^mlp_log10_tau; with no network loaded the
      * walk takes the opening-angle test at theta instead.  |a_i| comes from
      * mlp_acc_norm (device, n norms in the tree's dtype, caller order) or,

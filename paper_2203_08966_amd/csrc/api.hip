@@ -99,6 +99,8 @@ static int check_opts(const bh_force_opts &o, int64_t n) {
     if (o.order == 3 && o.mac != BH_MAC_THETA)
         return set_error(BH_E_INVALID, "opts.order 3 (octopole) runs with the opening angle "
                                        "BH_MAC_THETA only");
+    if (o.mac == BH_MAC_MLP && o.order != 2)
+        return set_error(BH_E_INVALID, "BH_MAC_MLP runs in the quadrupole walk (opts.order 2)");
     if (o.mac != BH_MAC_THETA && o.mac != BH_MAC_MLP && o.mac != BH_MAC_BUDGET &&
         o.mac != BH_MAC_THETA_GUARD)
         return set_error(BH_E_INVALID, "opts.mac must be BH_MAC_THETA, BH_MAC_MLP, BH_MAC_BUDGET "

@@ -100,6 +100,19 @@ struct MlpMac {
 
 template <int MAC> struct NetVec { using type = bf16x8; };
 
+// The error budget with monopole terms charges a cell the bound on the
+// quadrupole term it drops (Sec. 2.2): |Q x / s^5 - (5/2) (x.Q.x) x / s^7|
+// <= (7/2) |Q|_F / s^4, so the cell is accepted iff
+// M l^3 + (7/2) |Q|_F d < tau |a| d^5.  This returns (7/2) |Q|_F of the
+// record's traceless quadrupole.
+template <typename Rec> __device__ __forceinline__ float quad_bound(const Rec &nd) {
+    const float qxx = (float)nd.qxx, qyy = (float)nd.qyy, qzz = -qxx - qyy;
+    const float qxy = (float)nd.qxy, qxz = (float)nd.qxz, qyz = (float)nd.qyz;
+    const float diag = qxx * qxx + qyy * qyy + qzz * qzz;
+    const float off = qxy * qxy + qxz * qxz + qyz * qyz;
+    return 3.5f * sqrtf(2.f * off + diag);
+}
+
 // The octopole term of a particle-cell interaction (order 3; Sec. 2.2, the
 // l = 3 term): from o = (xxx xxy xxz xyy xyz yyy yyz), the traceless
 // octopole's independent components, and x = body - COM, adds
@@ -179,11 +192,14 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
             if (MAC == 1) {
                 // error budget: M l^3 / d^5 below tau |a_i|, l/d below
                 // theta_max, and the body outside the cell
-                const float kcv = mac.kc[idx];
+                // (monopole terms: plus the dropped quadrupole's bound)
+                float kcv = mac.kc[idx];
                 const R hs = (R)0.5 * sqrt(nd.l2);
                 const bool inside = fabs(X) <= hs && fabs(Y) <= hs && fabs(Z) <= hs;
+                const R d = sqrt(d2);
+                if (!ORDER2) kcv = quad_bound(nd) * d + kcv;
                 accept = act && nd.l2 < (R)mac.tmax2 * d2 && !inside &&
-                         kcv < tau_a * (d2 * d2 * sqrt(d2));
+                         kcv < tau_a * (d2 * d2 * d);
             } else if (MAC >= 2) {
                 // learned, the body as its own group: the network's error
                 // for (body, cell) below tau |a_i|, l/d below theta_max, the
@@ -522,7 +538,11 @@ __device__ __forceinline__ auto group_walk(
             const R tz = fmax(fabs(uz + nd.mz) - bhz, (R)0);
             const R dg2 = tx * tx + ty * ty + tz * tz;
             bool accept = !overlap && nd.l2 < theta2 * dg2;
-            if (MAC == 1) accept = accept && kcv < tau_amin * (float)(dg2 * dg2 * sqrt(dg2));
+            if (MAC == 1) {  // (monopole terms: plus the dropped quadrupole's bound)
+                const float dg = sqrtf((float)dg2);
+                if (!ORDER2) kcv = quad_bound(nd) * dg + kcv;
+                accept = accept && kcv < tau_amin * (float)(dg2 * dg2 * dg);
+            }
             if (MAC >= 2 && accept && nd.m > (R)0) return kGCand;  // the network decides
             if (MAC >= 2) accept = false;
             if (accept) return kGPC;
@@ -1204,9 +1224,12 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
         sig |= 1ull << 63;  // never the unset value 0
     }
     if (o.mac == BH_MAC_MLP || o.mac == BH_MAC_BUDGET) {
-        if (t->dtype != BH_F32 || o.order != 2)
-            return set_error(BH_E_INVALID, "the learned criterion runs in the FP32 quadrupole walk");
         const bool learned = o.mac == BH_MAC_MLP;
+        if (t->dtype != BH_F32 || (o.order != 2 && (learned || o.order != 0)))
+            return set_error(BH_E_INVALID, learned
+                                               ? "the learned criterion runs in the FP32 quadrupole walk"
+                                               : "the error budget runs in the FP32 walk of order 0 or 2");
+        const bool mono = o.order == 0;
         int rc = learned ? BH_OK : mlp_cells(t);
         if (rc) return rc;
         if (o.mlp_acc_norm) {
@@ -1246,13 +1269,15 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
             gm.net = mac.net;
             gm.eps = mac.eps;
 #define BH_GM(k) gdispatch<float, true, k>(t, t0, t1, o.mlp_theta_max, eps, acc, phi, npp, npc, sorted_out, gm, sig)
-            if (!learned) BH_GM(1);
+            if (!learned && mono) gdispatch<float, false, 1>(t, t0, t1, o.mlp_theta_max, eps, acc, phi, npp, npc, sorted_out, gm, sig);
+            else if (!learned) BH_GM(1);
             else if (f16) BH_GM(3);
             else BH_GM(2);
 #undef BH_GM
         } else {
 #define BH_BM(k) dispatch2<float, true, k>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac)
-            if (!learned) BH_BM(1);
+            if (!learned && mono) dispatch2<float, false, 1>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+            else if (!learned) BH_BM(1);
             else if (f16) BH_BM(3);
             else BH_BM(2);
 #undef BH_BM

@@ -683,18 +683,17 @@ __device__ __forceinline__ auto group_walk(
                 top -= k;
                 __builtin_amdgcn_wave_barrier();
                 const bool has = lane < k;
+                // lanes without a node load and classify the root (valid,
+                // cached) and take no part
                 const int c = has ? stk[top + lane] : 0;
-                int cls = kGNone;
                 int4 k0 = make_int4(-1, -1, -1, -1), k1 = k0;
-                Rec nd{};
-                if (has) {
-                    if (MAC < 2) {
-                        k0 = kids[2 * (int64_t)c];  // loaded with the record, used if opened
-                        k1 = kids[2 * (int64_t)c + 1];
-                    }
-                    nd = nodes[c];
-                    cls = classify(nd, c, MAC == 1 ? gm.kc[c] : 0.f);
+                if (MAC < 2) {
+                    k0 = kids[2 * (int64_t)c];  // loaded with the record, used if opened
+                    k1 = kids[2 * (int64_t)c + 1];
                 }
+                const Rec nd = nodes[c];
+                int cls = classify(nd, c, MAC == 1 ? gm.kc[c] : 0.f);
+                if (!has) cls = kGNone;
                 if (MAC >= 2) {
                     // the children after the network (fewer registers live
                     // across its evaluation)
@@ -715,12 +714,14 @@ __device__ __forceinline__ auto group_walk(
                     st[1] = (nd.cy - gy) + nd.my;
                     st[2] = (nd.cz - gz) + nd.mz;
                     st[3] = nd.m;
-                    st[4] = nd.qxx;
-                    st[5] = nd.qxy;
-                    st[6] = nd.qxz;
-                    st[7] = nd.qyy;
-                    st[8] = nd.qyz;
-                    st[9] = -nd.qxx - nd.qyy;
+                    if (ORDER2) {
+                        st[4] = nd.qxx;
+                        st[5] = nd.qxy;
+                        st[6] = nd.qxz;
+                        st[7] = nd.qyy;
+                        st[8] = nd.qyz;
+                        st[9] = -nd.qxx - nd.qyy;
+                    }
                     if (OCT) {
                         const R *o = (const R *)gm.oct + 8 * (int64_t)c;
                         for (int q = 0; q < 7; ++q) st[10 + q] = o[q];
@@ -728,10 +729,15 @@ __device__ __forceinline__ auto group_walk(
                 }
                 if (m_op) {
                     const int kid[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+                    // the child table lists a cell's children first (then -1):
+                    // their count by bisection
                     int nk = 0;
                     if (cls == kGOpen) {
-    #pragma unroll
-                        for (int q = 0; q < 8; ++q) nk += kid[q] >= 0 ? 1 : 0;
+                        if (k0.w >= 0)
+                            nk = k1.y >= 0 ? (k1.w >= 0 ? 8 : k1.z >= 0 ? 7 : 6)
+                                           : (k1.x >= 0 ? 5 : 4);
+                        else
+                            nk = k0.y >= 0 ? (k0.z >= 0 ? 3 : 2) : (k0.x >= 0 ? 1 : 0);
                     }
                     // exclusive prefix sum of nk (0..8) over the lanes, bit by bit
                     int excl = 0, total = 0;
@@ -745,7 +751,9 @@ __device__ __forceinline__ auto group_walk(
                     }
                     if (top + total <= gm.cap) {
                         const int off = top + excl;
-                        for (int q = 0; q < nk; ++q) stk[off + q] = kid[q];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)  // constant offsets, no indexed registers
+                            if (q < nk) stk[off + q] = kid[q];
                         top += total;
                     } else {
                         uint64_t mm = m_op;
@@ -805,13 +813,23 @@ __device__ __forceinline__ auto group_walk(
                     if (fits) {
                         const R lx = nd.cx - gx, ly = nd.cy - gy, lz = nd.cz - gz;  // exact
                         R *d = stage + 4 * (incl - nb);
-                        for (int q = 0; q < nb; ++q) {
-                            const BodyRec<R> sb = bodies[jb_l + q];
+                        const BodyRec<R> *src = bodies + jb_l;
+                        auto put_body = [&](int q, const BodyRec<R> &sb) {
                             d[4 * q + 0] = lx + sb.x;
                             d[4 * q + 1] = ly + sb.y;
                             d[4 * q + 2] = lz + sb.z;
                             d[4 * q + 3] = sb.m;
+                        };
+                        int q = 0;
+                        for (; q + 4 <= nb; q += 4) {  // four loads in flight
+                            const BodyRec<R> b0 = src[q], b1 = src[q + 1], b2 = src[q + 2],
+                                             b3 = src[q + 3];
+                            put_body(q, b0);
+                            put_body(q + 1, b1);
+                            put_body(q + 2, b2);
+                            put_body(q + 3, b3);
                         }
+                        for (; q < nb; ++q) put_body(q, src[q]);
                     }
                     const int total =
                         __builtin_amdgcn_readlane(incl, 63 - __builtin_clzll(put));

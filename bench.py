@@ -147,6 +147,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c4")
     ap.add_argument("--n", type=int, default=None, help="override N")
+    ap.add_argument("--leaf", type=int, default=None, help="override the leaf capacity")
     ap.add_argument("--theta", type=float, default=None,
                     help="per-body walk: skip the sweep and use this theta")
     ap.add_argument("--method", choices=list(METHODS),
@@ -208,6 +209,8 @@ def main():
         energy_table(args)
         return
     bodies, cfg = W.config(args.config, n=args.n)
+    if args.leaf is not None:
+        cfg = dict(cfg, leaf=args.leaf)
     n = bodies.n
     eps, leaf, dt, order = cfg["eps"], cfg["leaf"], cfg["dt"], 2
     dtype = torch.float32 if cfg["dtype"] == "f32" else torch.float64

@@ -1068,6 +1068,7 @@ struct UpArgs {
     Moments *mom;
     uint32_t *cmask;
     void *recs;  // NodeRecT<R>::type[m]
+    float *kc;   // M l^3 per node (the error budget's per-cell term)
 };
 
 __device__ __forceinline__ void set_level(NodeRec32 &, int) {}
@@ -1090,6 +1091,10 @@ __device__ __forceinline__ void finish_node(const UpArgs &a, int i, const NodeGe
                                             const Moments &q, uint32_t mask, double h) {
     a.mom[i] = q;
     a.cmask[i] = mask;
+    {
+        const double side = ldexp(h, kLevels + 1 - gn.level);
+        a.kc[i] = (float)(q.m * side * side * side);
+    }
     const double tr = q.t[0] + q.t[3] + q.t[5];
     typename NodeRecT<R>::type r{};
     r.cx = (R)(gn.cx * h);  // exact
@@ -1832,7 +1837,8 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
         (rc = grow(t->cy, 4ull * m)) || (rc = grow(t->cz, 4ull * m)) ||
         (rc = grow(t->mom, sizeof(Moments) * (size_t)m)) ||
         (rc = grow(t->kids, 32ull * m)) || (rc = grow(t->ulist, 8ull * m)) ||
-        (rc = grow(t->recs, sizeof(typename NodeRecT<T>::type) * (size_t)m)))
+        (rc = grow(t->recs, sizeof(typename NodeRecT<T>::type) * (size_t)m)) ||
+        (rc = grow(t->kc, 4ull * m)))
         return rc;
     const int nbm = div_up(m, kThreads);
     int32_t *lvl_list = (int32_t *)t->lvl_list.p;
@@ -1861,6 +1867,7 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     ua.mom = (Moments *)t->mom.p;
     ua.cmask = (uint32_t *)t->cmask.p;
     ua.recs = t->recs.p;
+    ua.kc = (float *)t->kc.p;
     int32_t *ulist = (int32_t *)t->ulist.p;
     k_leaves<T, T><<<nbm, kThreads, 0, st>>>(ua, pos_out, mass_out,
                                              (BodyRec<T> *)t->bodies.p,
@@ -1871,6 +1878,7 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     k_up_sub<T><<<nsub, kSubThreads, 0, st>>>(ua, ulist, ucnt);
     k_up_upper<T><<<1, kUpThreads, 0, st>>>(ua, ulist + m, ucnt);
     t->kids_tree_id = t->build_id;
+    t->kc_tree_id = t->build_id;
     return check_launch("tree");
 }
 

@@ -62,10 +62,12 @@ __global__ __launch_bounds__(256) void k_anorm(int n, const R *__restrict__ acc,
                                                const uint32_t *__restrict__ perm,
                                                float *__restrict__ out,
                                                double *__restrict__ part) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    float v = 0.f;
-    if (i < n) {
+    // grid-stride over the ranks (a fixed grid: the sum's order is fixed)
+    double sum = 0.0;
+    const int stride = (int)(gridDim.x * blockDim.x);
+    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n; i += stride) {
         const int64_t j = perm ? (int64_t)perm[i] : i;
+        float v;
         if (norm) {
             v = (float)norm[j];
         } else {
@@ -73,16 +75,15 @@ __global__ __launch_bounds__(256) void k_anorm(int n, const R *__restrict__ acc,
             v = (float)sqrt(x * x + y * y + z * z);
         }
         out[i] = v;
+        sum += (double)v;
     }
-    // block sum of the stored norms, FP64, fixed order
-    __shared__ double s[256];
-    s[threadIdx.x] = (double)v;
+    // block sum of the stored norms, FP64: a butterfly within each
+    // wavefront (lane 0's result is used), then the four wavefronts in order
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    __shared__ double ws[4];
+    if (lane_id() == 0) ws[threadIdx.x >> 6] = sum;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+    if (threadIdx.x == 0) part[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
 }
 
 // floor = f * (sum of the block sums) / n, one block, fixed order.
@@ -518,6 +519,8 @@ int mlp_infer(bh_ctx *c, const float *X, int64_t n, int precision, float *pred) 
     return check_launch("mlp infer");
 }
 
+// (every build writes M l^3 with its upward pass: this recomputes it only
+// for a tree whose build did not)
 int mlp_cells(bh_tree *t) {
     if (t->kc_tree_id == t->build_id) return BH_OK;
     const int m = (int)t->m;
@@ -531,12 +534,15 @@ int mlp_cells(bh_tree *t) {
     return BH_OK;
 }
 
+// blocks of k_anorm (at most; its block sums sit in a fixed-size slot)
+constexpr int kAnormBlocks = 1024;
+
 int mlp_anorm(bh_tree *t, const void *acc, const void *norm, bool caller_order,
               double floor_frac) {
     const int n = (int)t->n;
-    const int nblk = div_up(n, 256);
+    const int nblk = min(kAnormBlocks, div_up(n, 256));
     const size_t npad = 4ull * (size_t)div_up(n, 64) * 64;  // norms, then block sums, floor
-    int rc = grow(t->anorm, npad + 8ull * nblk + 8);
+    int rc = grow(t->anorm, npad + 8ull * kAnormBlocks + 8);
     if (rc) return rc;
     const uint32_t *perm = caller_order ? t->perm : nullptr;
     double *part = (double *)((char *)t->anorm.p + npad);
@@ -547,13 +553,13 @@ int mlp_anorm(bh_tree *t, const void *acc, const void *norm, bool caller_order,
         k_anorm<double><<<nblk, 256, 0, t->ctx->stream>>>(
             n, (const double *)acc, (const double *)norm, perm, (float *)t->anorm.p, part);
     k_anorm_floor<<<1, 1024, 0, t->ctx->stream>>>(part, nblk, n, floor_frac,
-                                                  (float *)(part + nblk));
+                                                  (float *)(part + kAnormBlocks));
     return check_launch("anorm");
 }
 
 const float *mlp_anorm_floor(const bh_tree *t) {
     const size_t npad = 4ull * (size_t)div_up((int)t->n, 64) * 64;
-    return (const float *)((const char *)t->anorm.p + npad + 8ull * div_up((int)t->n, 256));
+    return (const float *)((const char *)t->anorm.p + npad + 8ull * kAnormBlocks);
 }
 
 int mlp_samples(bh_tree *t, double eps, double theta_lo, double theta_max, double keep,

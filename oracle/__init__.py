@@ -184,8 +184,10 @@ def moments(tree: dict, spos, smass, lo, L):
 
 
 class WalkResult(tuple):
-    """(acc, phi, npp, npc, ncov, flag) of a tree walk; fields by name too."""
-    _fields = ("acc", "phi", "npp", "npc", "ncov", "flag")
+    """(acc, phi, npp, npc, ncov, flag) of a tree walk; fields by name too.
+    The budget walks add npq: of the npc particle-cell terms, those that
+    carry the quadrupole."""
+    _fields = ("acc", "phi", "npp", "npc", "ncov", "flag", "npq")
 
     def __new__(cls, *vals):
         return super().__new__(cls, vals)
@@ -346,13 +348,14 @@ def _mac_sigs(lib):
     lib.orc_cell_kc.argtypes = [C.c_int64, _i32, _f64, C.c_double, _f64]
     lib.orc_walk_kc.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64, _f64,
                                 C.c_double, C.c_double, C.c_double, C.c_double, _f64, _f64,
-                                C.c_int64, _i64, _f64, _f64, _i64, _i64, _i64, _i32, C.c_int]
+                                C.c_int64, _i64, _f64, _f64, _i64, _i64, _i64, _i32, C.c_int, _i64]
     lib.orc_walk_group.argtypes = [_i32, _u64, _i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64,
                                    _f64, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
                                    C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
                                    C.c_double, _u64,
-                                   _i32, C.c_int, _f64, _f64, _i64, _i64, _i64, _i32, C.c_void_p]
+                                   _i32, C.c_int, _f64, _f64, _i64, _i64, _i64, _i32, C.c_void_p,
+                                   _i64]
     lib.orc_gfeatures.argtypes = [_f64, _f64, _f64, C.c_double, _f64, C.c_double, _f64, C.c_int,
                                   C.c_int, C.c_double, _f64]
     lib.orc_gnet_bound.argtypes = [_f64, _f64, C.POINTER(C.c_double), C.c_int]
@@ -414,10 +417,17 @@ def floored_norms(anorm, floor):
     return np.maximum(a, floor * a.mean())
 
 
+# mixed expansion order of the budget walks: per cell the monopole where the
+# budget charged with the dropped quadrupole's bound holds, else the
+# quadrupole where the plain budget holds, else the cell is opened
+ORDER_MIXED = 1
+
+
 def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None, floor=0.0, order=2):
     """Walk with the error budget (kc from ``cell_kc``); anorm is |a_i| per
     sorted rank, floored by ``floored_norms``.  order 0: monopole terms, the
-    budget charging each cell the bound on its dropped quadrupole term too."""
+    budget charging each cell the bound on its dropped quadrupole term too;
+    ORDER_MIXED: the cheaper of the two orders that meets the budget."""
     anorm = floored_norms(anorm, floor)
     lib = _mlib()
     t = b["tree"]
@@ -431,13 +441,14 @@ def walk_kc(b, eps, theta_max, tau, kc, anorm, targets=None, floor=0.0, order=2)
     npc = np.zeros(nt, dtype=np.int64)
     ncov = np.zeros(nt, dtype=np.int64)
     flag = np.zeros(nt, dtype=np.int32)
+    npq = np.zeros(nt, dtype=np.int64)
     lib.orc_walk_kc(t["level"], t["hkey"], t["begin"], t["count"], t["next"], M, com.ravel(),
                     Q.ravel(), b["spos"].ravel(), b["smass"], np.ascontiguousarray(b["lo"]),
                     float(b["L"]), float(eps), float(theta_max),
                     float(tau), np.ascontiguousarray(kc, dtype=np.float64),
                     np.ascontiguousarray(anorm, dtype=np.float64), nt, tg, acc.ravel(), phi, npp,
-                    npc, ncov, flag, int(order))
-    return WalkResult(acc, phi, npp, npc, ncov, flag)
+                    npc, ncov, flag, int(order), npq)
+    return WalkResult(acc, phi, npp, npc, ncov, flag, npq)
 
 
 # ------------------------------------------------------------------ group walk
@@ -482,6 +493,7 @@ def walk_group(b, eps, *, cap, split, group=64, mode=0, theta=0.5, theta_max=1.0
     npc = np.zeros(nt, dtype=np.int64)
     ncov = np.zeros(nt, dtype=np.int64)
     flag = np.zeros(nt, dtype=np.int32)
+    npq = np.zeros(nt, dtype=np.int64)
     kcv = None if kc is None else np.ascontiguousarray(kc, dtype=np.float64)
     anv = None if anorm is None else np.ascontiguousarray(floored_norms(anorm, floor))
     if mode == 1 and (kcv is None or anv is None):
@@ -500,8 +512,8 @@ def walk_group(b, eps, *, cap, split, group=64, mode=0, theta=0.5, theta_max=1.0
                            t0, t1,
                            int(cap), float(tol), np.ascontiguousarray(b["keys"], dtype=np.uint64),
                            leaf_levels(b), 1 if split else 0, acc.ravel(), phi, npp, npc, ncov,
-                           flag, octopole(b).ctypes.data if order >= 3 else None)
-    return WalkResult(acc, phi, npp, npc, ncov, flag)
+                           flag, octopole(b).ctypes.data if order >= 3 else None, npq)
+    return WalkResult(acc, phi, npp, npc, ncov, flag, npq)
 
 
 # ------------------------------------------------------------------ learned group criterion

@@ -529,6 +529,7 @@ static int and_uncertain(const int *t, int n)
 typedef struct {
     double a[3], phi;
     int64_t npp, npc, ncov;
+    int64_t npq; /* particle-cell terms that carry the quadrupole */
     int flag;
 } walk_acc;
 
@@ -548,7 +549,10 @@ static void pp(const walk_ctx *w, int64_t i, int64_t j, walk_acc *r)
     r->ncov += 1;
 }
 
-static void pc(const walk_ctx *w, int64_t i, int64_t c, const double x[3], double d2, walk_acc *r)
+/* The particle-cell term of cell c for body i up to expansion order `order`
+ * (0, 2 or 3). */
+static void pc_ord(const walk_ctx *w, int64_t i, int64_t c, const double x[3], double d2,
+                   walk_acc *r, int order)
 {
     const double Mc = w->M[c];
     const double s2 = d2 + w->e2;
@@ -560,7 +564,7 @@ static void pc(const walk_ctx *w, int64_t i, int64_t c, const double x[3], doubl
     r->a[1] -= Mc * x[1] * inv3;
     r->a[2] -= Mc * x[2] * inv3;
     r->phi -= Mc * inv;
-    if (w->order >= 2) {
+    if (order >= 2) {
         const double *q = &w->Q[6 * c];
         const double qx = q[0] * x[0] + q[1] * x[1] + q[2] * x[2];
         const double qy = q[1] * x[0] + q[3] * x[1] + q[4] * x[2];
@@ -572,8 +576,9 @@ static void pc(const walk_ctx *w, int64_t i, int64_t c, const double x[3], doubl
         r->a[1] += qy * inv5 - 2.5 * xqx * x[1] * inv7;
         r->a[2] += qz * inv5 - 2.5 * xqx * x[2] * inv7;
         r->phi -= 0.5 * xqx * inv5;
+        r->npq += 1;
     }
-    if (w->order >= 3) {
+    if (order >= 3) {
         /* a = (O:xx) / (2 s^7) - 7 (O:xxx) x / (6 s^9), the gradient of
          * O:xxx / (6 s^7) */
         const double *o = &w->O[10 * c];
@@ -593,6 +598,11 @@ static void pc(const walk_ctx *w, int64_t i, int64_t c, const double x[3], doubl
     (void)i;
     r->npc += 1;
     r->ncov += w->count[c];
+}
+
+static void pc(const walk_ctx *w, int64_t i, int64_t c, const double x[3], double d2, walk_acc *r)
+{
+    pc_ord(w, i, c, x, d2, r, w->order);
 }
 
 static void leaf_pp(const walk_ctx *w, int64_t i, int64_t c, walk_acc *r)
@@ -804,6 +814,46 @@ static double q_frobenius(const double *q)
                 2.0 * (q[1] * q[1] + q[2] * q[2] + q[4] * q[4]));
 }
 
+/* Mixed order (order 1 in the budget walks): a cell accepted with its
+ * monopole where the budget charged with the dropped quadrupole's bound
+ * holds, else with the quadrupole where the plain budget holds, else
+ * opened.  Both kinds of term meet the same budget; the quadrupole costs
+ * more arithmetic than the monopole and less than opening the cell. */
+#define ORC_ORDER_MIXED 1
+
+/* The budget decision for one cell: 0 open, else the order of the term
+ * (0 or 2) it is accepted with.  geo: the geometric terms (angle, outside)
+ * as three-valued tests, n_geo of them, and their conjunction ok; kc the
+ * cell's M l^3, qb its (7/2) |Q|_F, d the distance, rhs tau a d^5.  Sets
+ * *unc if a near-threshold test could change the decision or the order. */
+static int budget_choice(int order, const int *geo, int n_geo, int ok, double kc, double qb,
+                         double d, double rhs, double tol, int *unc)
+{
+    int t[4];
+    for (int k = 0; k < n_geo; ++k)
+        t[k] = geo[k];
+    const double lhs_m = kc + qb * d; /* monopole: the quadrupole's bound charged */
+    const int mono = order == 0 || order == ORC_ORDER_MIXED; /* monopole terms allowed */
+    const int high = order != 0; /* terms with the quadrupole (and above) allowed */
+    if (high) {
+        t[n_geo] = cmp3(kc, rhs, tol, kc);
+        if (and_uncertain(t, n_geo + 1))
+            *unc = 1;
+    }
+    if (mono) {
+        t[n_geo] = cmp3(lhs_m, rhs, tol, lhs_m);
+        if (and_uncertain(t, n_geo + 1))
+            *unc = 1;
+    }
+    if (!ok)
+        return -1;
+    if (mono && lhs_m < rhs)
+        return 0;
+    if (high && kc < rhs)
+        return order == ORC_ORDER_MIXED ? 2 : order;
+    return -1;
+}
+
 /* Per cell: M l^3, the error budget's k_C M l^3 with k_C = 1. */
 void orc_cell_kc(int64_t m, const int32_t *level, const double *M, double L, double *kc)
 {
@@ -834,10 +884,6 @@ static void cell_force_kc(mac_ctx *m, int64_t node, int64_t i, walk_acc *r)
             x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
         const double d2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
         const double s2 = side * side;
-        /* monopole terms (order 0): the dropped quadrupole's bound as well */
-        const double lhs = m->kc[c] + (w->order == 0 ? ORC_QUAD_BOUND *
-                                                           q_frobenius(&w->Q[6 * c]) * sqrt(d2)
-                                                     : 0.0);
         const double rhs = m->tau * m->anorm * d2 * d2 * sqrt(d2);
         double centre[3];
         cell_centre(m->hkey[c], w->level[c], m->lo, w->L, centre);
@@ -847,12 +893,15 @@ static void cell_force_kc(mac_ctx *m, int64_t node, int64_t i, walk_acc *r)
             if (o3 > out)
                 out = o3;
         }
-        const int terms[3] = {cmp3(s2, m->tmax2 * d2, 1e-5, s2), out, cmp3(lhs, rhs, 1e-5, lhs)};
-        if (and_uncertain(terms, 3))
-            r->flag = 1;
+        const int geo[2] = {cmp3(s2, m->tmax2 * d2, 1e-5, s2), out};
         const int in = inside_cell(&w->spos[3 * i], centre, side);
-        if (s2 < m->tmax2 * d2 && !in && lhs < rhs)
-            pc(w, i, c, x, d2, r);
+        /* monopole terms (order 0, or mixed): the dropped quadrupole's
+         * bound charged as well */
+        const int ord = budget_choice(w->order, geo, 2, s2 < m->tmax2 * d2 && !in, m->kc[c],
+                                      ORC_QUAD_BOUND * q_frobenius(&w->Q[6 * c]), sqrt(d2), rhs,
+                                      1e-5, &r->flag);
+        if (ord >= 0)
+            pc_ord(w, i, c, x, d2, r, ord);
         else if (w->next[c] == c + 1)
             leaf_pp(w, i, c, r);
         else
@@ -866,7 +915,7 @@ void orc_walk_kc(const int32_t *level, const uint64_t *hkey, const int32_t *begi
                  double L, double eps, double theta_max,
                  double tau, const double *kc, const double *anorm, int64_t nt,
                  const int64_t *targets, double *acc, double *phi, int64_t *npp, int64_t *npc,
-                 int64_t *ncov, int32_t *flag, int order)
+                 int64_t *ncov, int32_t *flag, int order, int64_t *npq)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nt; ++t) {
@@ -892,6 +941,7 @@ void orc_walk_kc(const int32_t *level, const uint64_t *hkey, const int32_t *begi
         if (phi) phi[t] = r.phi;
         if (npp) npp[t] = r.npp;
         if (npc) npc[t] = r.npc;
+        if (npq) npq[t] = r.npq;
         if (ncov) ncov[t] = r.ncov;
         if (flag) flag[t] = r.flag;
     }
@@ -989,27 +1039,29 @@ static void group_cell(group_ctx *g, int64_t node)
         const double lim2 = (g->mode == 0 ? g->th2 : g->tmax2) * dg2;
         int accept = !overlap && s2 < lim2;
         int terms[3] = {sep, cmp3(s2, lim2, g->tol, s2), 1};
+        int ord = w->order;
         if (g->mode == 1) {
-            /* monopole terms (order 0): the dropped quadrupole's bound as well */
-            const double lhs = g->kc[c] + (w->order == 0 ? ORC_QUAD_BOUND *
-                                                               q_frobenius(&w->Q[6 * c]) * sqrt(dg2)
-                                                         : 0.0);
+            /* monopole terms (order 0, or mixed): the dropped quadrupole's
+             * bound charged as well */
             const double rhs = g->tau * g->amin * dg2 * dg2 * sqrt(dg2);
-            terms[2] = cmp3(lhs, rhs, g->tol, lhs);
-            accept = accept && lhs < rhs;
+            ord = budget_choice(w->order, terms, 2, accept, g->kc[c],
+                                ORC_QUAD_BOUND * q_frobenius(&w->Q[6 * c]), sqrt(dg2), rhs,
+                                g->tol, &g->flag);
+            accept = ord >= 0;
         } else if (g->mode == 2 && sep >= 0 && terms[1] >= 0) {
             int acc_l = 0;
             terms[2] = learned_term(g, c, side, dg2, &acc_l);
             accept = accept && acc_l;
         }
-        if (and_uncertain(terms, 3))
+        if (g->mode != 1 && and_uncertain(terms, 3))
             g->flag = 1;
         if (accept) {
             for (int64_t i = g->g0; i < g->g1; ++i) {
                 double x[3];
                 for (int d = 0; d < 3; ++d)
                     x[d] = w->spos[3 * i + d] - w->com[3 * c + d];
-                pc(w, i, c, x, x[0] * x[0] + x[1] * x[1] + x[2] * x[2], &g->r[i - g->g0]);
+                pc_ord(w, i, c, x, x[0] * x[0] + x[1] * x[1] + x[2] * x[2], &g->r[i - g->g0],
+                       ord);
             }
             g->work += 1;
         } else if (w->next[c] == c + 1) {
@@ -1031,7 +1083,7 @@ static void walk_one_group(const int32_t *level, const uint64_t *hkey, const int
                            const double *kc, const double *anorm, const double *params,
                            int f16, int64_t r0, int64_t r1, int64_t t0, int64_t cap, double tol,
                            double *acc, double *phi, int64_t *npp, int64_t *npc, int64_t *ncov,
-                           int32_t *flag, const double *O);
+                           int32_t *flag, const double *O, int64_t *npq);
 
 static void group_run(group_ctx *g, int64_t r0, int64_t r1, const double *anorm, walk_acc *r);
 
@@ -1056,7 +1108,7 @@ void orc_walk_group(const int32_t *level, const uint64_t *hkey, const int32_t *b
                     int64_t cap, double tol,
                     const uint64_t *skeys, const int32_t *leaf_level, int split, double *acc,
                     double *phi, int64_t *npp, int64_t *npc, int64_t *ncov, int32_t *flag,
-                    const double *O)
+                    const double *O, int64_t *npq)
 {
     const int64_t ng = (t1 - t0 + G - 1) / G;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -1084,7 +1136,7 @@ void orc_walk_group(const int32_t *level, const uint64_t *hkey, const int32_t *b
             }
             walk_one_group(level, hkey, begin, count, next, M, com, Q, spos, smass, lo, L, eps,
                            order, mode, theta, theta_max, tau, kc, anorm, params, f16, a, b, t0,
-                           cap, tol, acc, phi, npp, npc, ncov, flag, O);
+                           cap, tol, acc, phi, npp, npc, ncov, flag, O, npq);
             a = b;
         }
     }
@@ -1099,7 +1151,7 @@ static void walk_one_group(const int32_t *level, const uint64_t *hkey, const int
                            const double *kc, const double *anorm, const double *params,
                            int f16, int64_t r0, int64_t r1, int64_t t0, int64_t cap, double tol,
                            double *acc, double *phi, int64_t *npp, int64_t *npc, int64_t *ncov,
-                           int32_t *flag, const double *O)
+                           int32_t *flag, const double *O, int64_t *npq)
 {
     {
         group_ctx g;
@@ -1167,6 +1219,7 @@ static void walk_one_group(const int32_t *level, const uint64_t *hkey, const int
             if (phi) phi[o] = r->phi;
             if (npp) npp[o] = r->npp;
             if (npc) npc[o] = r->npc;
+            if (npq) npq[o] = r->npq;
             if (ncov) ncov[o] = r->ncov;
             if (flag) flag[o] = gflag || (per_body && r->flag);
         }

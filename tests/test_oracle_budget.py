@@ -222,3 +222,89 @@ def test_group_monopole_budget_flips_at_hand_threshold():
         assert np.all(r.npc == (1 if accepted else 0)), f
         assert np.all(r.npp == (3 if accepted else 5)), f
         assert np.all(r.flag == 0)
+
+
+# ---- mixed order: per cell the monopole where M l^3 + (7/2) |Q|_F d <
+# tau a d^5, else the quadrupole where M l^3 < tau a d^5, else open
+
+def _mixed_thresholds(a, d):
+    qf = _quad_frobenius_by_hand()
+    kc = (MC1 + MC2) * SIDE ** 3
+    return kc / (a * d ** 5), (kc + 3.5 * qf * d) / (a * d ** 5)
+
+
+def test_per_body_mixed_order_picks_the_cheaper_term():
+    """Body A: above the monopole threshold C gives a monopole term, between
+    the two thresholds a quadrupole term, below both it is opened; each
+    accepted term is the one the walk of that single order computes."""
+    tb, rank, c = _system()
+    kc = oracle.cell_kc(tb)
+    a_A = 0.7
+    an = _norms(rank, {1: a_A, 2: 5.0})
+    d = np.linalg.norm(np.array(A) - _com())
+    tau_q, tau_m = _mixed_thresholds(a_A, d)
+    assert tau_q < 0.9 * tau_m
+    tau_mid = np.sqrt(tau_q * tau_m)
+    args = (tb, 0.0, 10.0)
+    cases = ((tau_m * (1 + 1e-3), 1, 0, 0), (tau_m * (1 - 1e-3), 1, 1, 2),
+             (tau_mid, 1, 1, 2), (tau_q * (1 + 1e-3), 1, 1, 2), (tau_q * (1 - 1e-3), 0, 0, None))
+    for tau, npc, npq, same_as in cases:
+        r = oracle.walk_kc(*args, tau, kc, an, targets=[rank[1]], order=oracle.ORDER_MIXED)
+        assert (r.npc[0], r.npq[0], r.flag[0]) == (npc, npq, 0), tau
+        if same_as is not None:  # (the pins O and Z, of mass 1e-9, may be taken apart)
+            ref = oracle.walk_kc(*args, tau, kc, an, targets=[rank[1]], order=same_as)
+            assert ref.npc[0] == 1
+            np.testing.assert_allclose(r.acc, ref.acc, rtol=1e-8)
+
+
+def test_group_mixed_order_picks_the_cheaper_term():
+    tb, rank, c = _system()
+    r0 = min(rank[1], rank[2])
+    kc = oracle.cell_kc(tb)
+    a_A, a_B = 1.3, 0.7
+    an = _norms(rank, {1: a_A, 2: a_B})
+    lo = np.minimum(A, B)
+    hi = np.maximum(A, B)
+    dg = np.linalg.norm(np.maximum(0.0, np.maximum(lo - _com(), _com() - hi)))
+    tau_q, tau_m = _mixed_thresholds(min(a_A, a_B), dg)
+    kw = dict(group=2, mode=1, theta_max=10.0, kc=kc, anorm=an, target_range=(r0, r0 + 2),
+              cap=1 << 40, split=False)
+    for tau, npc, npq in ((tau_m * (1 + 1e-3), 1, 0), (tau_m * (1 - 1e-3), 1, 1),
+                          (tau_q * (1 + 1e-3), 1, 1), (tau_q * (1 - 1e-3), 0, 0)):
+        r = oracle.walk_group(tb, 0.0, tau=tau, order=oracle.ORDER_MIXED, **kw)
+        assert np.all(r.npc == npc) and np.all(r.npq == npq) and np.all(r.flag == 0), tau
+
+
+def test_mixed_order_accepts_what_the_quadrupole_budget_accepts():
+    """The mixed walk opens exactly the cells the quadrupole budget opens (a
+    monopole acceptance implies the quadrupole one): the same interaction
+    counts for every body, with part of the terms monopoles; at a tau where
+    no cell's quadrupole bound is small enough every term is a quadrupole,
+    and the forces equal the quadrupole walk's."""
+    from tests.conftest import case_bodies
+    pos, _, mass = case_bodies("plummer", 3000, 31, np.float64)
+    tb = oracle.build_all(pos, mass, 8)
+    w = oracle.walk(tb["tree"], tb["mom"], tb["spos"], tb["smass"], tb["L"], 0.5, 0.01)
+    an = np.linalg.norm(w.acc, axis=1)
+    kc = oracle.cell_kc(tb)
+    for tau in (1e-3, 1e-2):
+        r2 = oracle.walk_kc(tb, 0.01, 1.2, tau, kc, an, order=2)
+        rm = oracle.walk_kc(tb, 0.01, 1.2, tau, kc, an, order=oracle.ORDER_MIXED)
+        np.testing.assert_array_equal(rm.npc, r2.npc)
+        np.testing.assert_array_equal(rm.npp, r2.npp)
+        assert np.all(r2.npq == r2.npc) and np.all(rm.npq <= rm.npc)
+        assert 0.05 < 1 - rm.npq.sum() / rm.npc.sum() < 0.999
+        g2 = oracle.walk_group(tb, 0.01, group=64, mode=1, theta_max=1.2, tau=tau, kc=kc,
+                               anorm=an, cap=4096, split=True, order=2)
+        gm = oracle.walk_group(tb, 0.01, group=64, mode=1, theta_max=1.2, tau=tau, kc=kc,
+                               anorm=an, cap=4096, split=True, order=oracle.ORDER_MIXED)
+        np.testing.assert_array_equal(gm.npc, g2.npc)
+        np.testing.assert_array_equal(gm.npp, g2.npp)
+    # tau so small that nearly every accepted cell fails its monopole
+    # budget: where all of a body's terms are quadrupoles its force is the
+    # quadrupole walk's, bit for bit
+    rq = oracle.walk_kc(tb, 0.01, 1.2, 1e-9, kc, an, order=oracle.ORDER_MIXED)
+    r2 = oracle.walk_kc(tb, 0.01, 1.2, 1e-9, kc, an, order=2)
+    allq = rq.npq == rq.npc
+    assert allq.mean() > 0.99
+    np.testing.assert_array_equal(rq.acc[allq], r2.acc[allq])

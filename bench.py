@@ -27,10 +27,14 @@ over a seeded 4096-body subsample:
   group-budget-mono  the group error budget with monopole terms: a cell is
                 also charged the bound (7/2) |Q|_F / d_g^4 of the
                 quadrupole term it drops;
+  group-budget-mixed the group error budget with the mixed order: per cell
+                the monopole term where that charged budget holds, else the
+                quadrupole term where the plain budget holds, else open;
   body-theta-hilbert, group-theta-hilbert, group-budget-hilbert,
-  group-budget-mono-hilbert, group-learned-hilbert  five of the walks over
-                bodies sorted along the Peano-Hilbert curve (a group is 64
-                consecutive bodies of that curve).
+  group-budget-mono-hilbert, group-budget-mixed-hilbert,
+  group-learned-hilbert  six of the walks over bodies sorted along the
+                Peano-Hilbert curve (a group is 64 consecutive bodies of
+                that curve).
 Each is swept over its parameter grid from accurate to cheap; the cheapest
 grid value with rms <= 1e-3 is kept, and the method with the fastest walk
 at that value is the one timed.  After the timed steps the rms error is
@@ -98,22 +102,29 @@ METHODS = {
     "group-theta-o3": [round(0.6 + 0.00625 * k, 5) for k in range(73)],
     # the budget with monopole terms (the dropped quadrupole's bound charged)
     "group-budget-mono": [round(-3.0 + 0.03125 * k, 5) for k in range(57)],  # log10 tau
+    # the mixed order (monopole or quadrupole per cell)
+    "group-budget-mixed": [round(-3.0 + 0.03125 * k, 5) for k in range(57)],  # log10 tau
 }
 # the same methods over bodies sorted along the Peano-Hilbert curve
-for _m in ("body-theta", "group-theta", "group-budget", "group-budget-mono", "group-learned"):
+for _m in ("body-theta", "group-theta", "group-budget", "group-budget-mono",
+           "group-budget-mixed", "group-learned"):
     METHODS[_m + "-hilbert"] = METHODS[_m]
 PARAM_NAME = {"body-theta": "theta", "body-theta-guard": "theta", "group-theta": "theta",
               "group-budget": "log10_tau", "group-budget-mono": "log10_tau",
+              "group-budget-mixed": "log10_tau",
               "group-learned": "log10_tau", "body-theta-o3": "theta", "group-theta-o3": "theta"}
-for _m in ("body-theta", "group-theta", "group-budget", "group-budget-mono", "group-learned"):
+for _m in ("body-theta", "group-theta", "group-budget", "group-budget-mono",
+           "group-budget-mixed", "group-learned"):
     PARAM_NAME[_m + "-hilbert"] = PARAM_NAME[_m]
 
 
 def order_of(method):
     """Expansion order of a method: octopole for the -o3 variants,
-    monopole for the -mono ones."""
+    monopole for the -mono ones, the mixed order (1) for the -mixed ones."""
     if method.endswith("-o3"):
         return 3
+    if "-mixed" in method:
+        return 1
     return 0 if "-mono" in method else 2
 
 
@@ -250,7 +261,8 @@ def main():
             kw.update(mac=B.BH_MAC_THETA_GUARD)
         elif method in ("group-theta", "group-theta-o3"):
             kw.update(walk=B.BH_WALK_GROUP, walk_cap=args.walk_cap)
-        elif method in ("group-budget", "group-budget-mono", "group-learned"):
+        elif method in ("group-budget", "group-budget-mono", "group-budget-mixed",
+                        "group-learned"):
             kw.update(walk=B.BH_WALK_GROUP, walk_cap=args.walk_cap, mlp_precision=mlp_precision,
                       mac=B.BH_MAC_MLP if method == "group-learned" else B.BH_MAC_BUDGET,
                       mlp_log10_tau=p, mlp_theta_max=args.theta_max,
@@ -392,6 +404,7 @@ def main():
         B.bh_leapfrog_step(ctx, dt)
     phase_ms, nsteps = B.bh_sim_timing_get(ctx)
     sim_pp, sim_pc = B.bh_sim_counts_get(ctx)
+    sim_pq = B.bh_sim_counts_pq_get(ctx)  # cell terms with the quadrupole
     # bodies the last rebuild's adaptive re-sort moved (-1: it sorted in full)
     movers = int(B.bh_tree_info_get(B.bh_sim_tree(ctx))["movers"])
     B.bh_sim_timing(ctx, False)
@@ -417,8 +430,12 @@ def main():
     # walk kernel's event time is taken over)
     s_pp = sim_pp / max(nsteps, 1)
     s_pc = sim_pc / max(nsteps, 1)
+    s_pq = sim_pq / max(nsteps, 1)
     inter = s_pp + s_pc
-    flops = FLOP_PP * s_pp + FLOP_PC[order_of(chosen)] * s_pc
+    if order_of(chosen) == 1:  # monopole and quadrupole cell terms
+        flops = FLOP_PP * s_pp + FLOP_PC[0] * (s_pc - s_pq) + FLOP_PC[2] * s_pq
+    else:
+        flops = FLOP_PP * s_pp + FLOP_PC[order_of(chosen)] * s_pc
     achieved_tf = flops / (walk_kernel_ms * 1e-3) / 1e12
     log(f"step {ms_step:.3f} ms  phases {phases}  rms at the final state {rms_final:.3e}")
 
@@ -456,7 +473,7 @@ def main():
         "interactions_per_s": inter / (walk_step_ms * 1e-3),
         # particle-cell terms weighted 2 (the paper's cost weights, Sec. 4.5)
         "weighted_interactions_per_s": (s_pp + 2 * s_pc) / (walk_step_ms * 1e-3),
-        "interactions_per_eval": {"pp": s_pp, "pc": s_pc,
+        "interactions_per_eval": {"pp": s_pp, "pc": s_pc, "pc_quadrupole": s_pq,
                                   "source": f"mean over the {nsteps} recorded simulation steps"},
         "walk_bodies_per_s": n / (walk_step_ms * 1e-3),
         "body_theta_points": theta_points,
@@ -469,7 +486,7 @@ def main():
         "roofline": {
             "bound": "alu",
             "kernel": f"{kernel} (FP32, "
-                      f"{ {0: 'monopole', 2: 'quadrupole', 3: 'octopole'}[order_of(chosen)]})",
+                      f"{ {0: 'monopole', 1: 'mixed monopole/quadrupole', 2: 'quadrupole', 3: 'octopole'}[order_of(chosen)]})",
             "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved_tf / PEAK_FP32_TFLOPS,
             "traffic": traffic_for(kernel, result_workload(cfg, n)),

@@ -106,12 +106,20 @@ enum {
 typedef struct bh_ctx bh_ctx;
 typedef struct bh_tree bh_tree;
 
+/* Mixed expansion order of the error budget (opts.order with BH_MAC_BUDGET):
+ * per cell the monopole term where M side^3 + (7/2) |Q|_F d < tau |a| d^5,
+ * else the quadrupole term where M side^3 < tau |a| d^5, else the cell is
+ * opened (both kinds of term meet the budget; a quadrupole term costs less
+ * than opening the cell). */
+enum { BH_ORDER_MIXED = 1 };
+
 /* Options of a force evaluation.  Fill with bh_force_opts_default first. */
 typedef struct {
     int order;        /* 0: monopole only; 2: monopole + quadrupole (default);
                          3: and the octopole, the l = 3 term of Sec. 2.2
                          (BH_MAC_THETA only; its moments are computed from
-                         the tree on the first order-3 walk of a build) */
+                         the tree on the first order-3 walk of a build);
+                         BH_ORDER_MIXED (1): BH_MAC_BUDGET only */
     int mac;          /* BH_MAC_THETA (default), BH_MAC_MLP, BH_MAC_BUDGET or
                          BH_MAC_THETA_GUARD */
     void *phi;        /* optional device out, N values in caller order: the
@@ -168,6 +176,9 @@ typedef struct {
                                  acceleration.  Default 0 (none). */
     int mlp_precision;        /* BH_MAC_MLP: BH_MLP_BF16 (default) or
                                  BH_MLP_FP16 operands of the network */
+    uint32_t *n_pq;           /* optional device out, N: of the particle-cell
+                                 terms, those with the quadrupole (all of
+                                 them at order 2 or 3, none at order 0) */
 } bh_force_opts;
 
 /* Library version string. */
@@ -334,6 +345,9 @@ int bh_sim_tree(bh_ctx *ctx, bh_tree **tree);
 int bh_sim_timing(bh_ctx *ctx, int enable);
 int bh_sim_timing_get(bh_ctx *ctx, double *ms, int64_t *steps);
 int bh_sim_counts_get(bh_ctx *ctx, int64_t *n_pp, int64_t *n_pc);
+/* Of the recorded steps' particle-cell terms, those with the quadrupole (as
+ * opts.n_pq counts them). */
+int bh_sim_counts_pq_get(bh_ctx *ctx, int64_t *n_pq);
 
 /* ---------------------------------------------------------------------
  * bh_direct -- FP64 direct summation (Sec. 2.1) for a subset of targets,

@@ -23,12 +23,14 @@ BH_WALK_BODY, BH_WALK_GROUP, BH_WALK_DIRECT = 0, 1, 2
 BH_GROUP_BODIES = 64  # bodies per group of BH_WALK_GROUP
 BH_CURVE_MORTON, BH_CURVE_HILBERT = 0, 1
 BH_SORT_ADAPTIVE, BH_SORT_FULL = 0, 1
+BH_ORDER_MIXED = 1  # opts.order of the error budget: monopole or quadrupole per cell
 
 EXPORTED = [
     "bh_version", "bh_last_error", "bh_force_opts_default", "bh_ctx_create", "bh_ctx_set_stream",
     "bh_ctx_destroy", "bh_sync", "bh_build", "bh_tree_free", "bh_forces", "bh_tree_info_get",
     "bh_tree_export", "bh_sim_init", "bh_leapfrog_step", "bh_sim_get", "bh_energy",
     "bh_sim_tree", "bh_direct", "bh_direct_static", "bh_sim_timing", "bh_sim_timing_get", "bh_sim_counts_get",
+    "bh_sim_counts_pq_get",
     "bh_mlp_set",
     "bh_mlp_get", "bh_mlp_samples", "bh_mlp_train", "bh_mlp_grad", "bh_mlp_infer",
     "bh_standard_units", "bh_ctx_set_allocator", "bh_ctx_set_curve", "bh_ctx_set_sort",
@@ -57,7 +59,7 @@ class ForceOpts(C.Structure):
         ("mlp_theta_max", C.c_double), ("mlp_log10_tau", C.c_double),
         ("mlp_acc_norm", C.c_void_p), ("mlp_theta_est", C.c_double),
         ("walk", C.c_int), ("walk_stack", C.c_int), ("walk_cap", C.c_int),
-        ("mlp_acc_floor", C.c_double), ("mlp_precision", C.c_int),
+        ("mlp_acc_floor", C.c_double), ("mlp_precision", C.c_int), ("n_pq", C.c_void_p),
     ]
 
 
@@ -117,6 +119,7 @@ def load(path: str = LIB_PATH):
         "bh_sim_timing": ([vp, i32], i32),
         "bh_sim_timing_get": ([vp, C.POINTER(dbl), C.POINTER(i64)], i32),
         "bh_sim_counts_get": ([vp, C.POINTER(i64), C.POINTER(i64)], i32),
+        "bh_sim_counts_pq_get": ([vp, C.POINTER(i64)], i32),
         "bh_mlp_set": ([vp, vp], i32),
         "bh_mlp_get": ([vp, vp], i32),
         "bh_mlp_samples": ([vp, dbl, dbl, dbl, dbl, C.c_uint64, i64, vp, vp, vp, vp,
@@ -178,7 +181,7 @@ def _stream():
 def force_opts(order=2, mac=BH_MAC_THETA, phi=None, n_pp=None, n_pc=None, target_range=None,
                mlp_theta_max=None, mlp_log10_tau=None, mlp_acc_norm=None,
                mlp_theta_est=None, walk=BH_WALK_BODY, walk_stack=0, walk_cap=0,
-               mlp_acc_floor=None, mlp_precision=None) -> ForceOpts:
+               mlp_acc_floor=None, mlp_precision=None, n_pq=None) -> ForceOpts:
     """Walk options.  mlp_acc_norm: device tensor of |a_i| in caller order
     and the tree's dtype (kept alive by the caller until the walk ran);
     mlp_acc_floor: f in max(|a_i|, f <|a|>)."""
@@ -205,6 +208,7 @@ def force_opts(order=2, mac=BH_MAC_THETA, phi=None, n_pp=None, n_pc=None, target
         o.mlp_acc_floor = mlp_acc_floor
     if mlp_precision is not None:
         o.mlp_precision = mlp_precision
+    o.n_pq = _dev(n_pq, "n_pq")
     return o
 
 
@@ -421,6 +425,13 @@ def bh_sim_counts_get(ctx) -> tuple[int, int]:
     pp, pc = C.c_int64(), C.c_int64()
     _check(load().bh_sim_counts_get(ctx, C.byref(pp), C.byref(pc)))
     return pp.value, pc.value
+
+
+def bh_sim_counts_pq_get(ctx) -> int:
+    """Of the recorded steps' particle-cell terms, those with the quadrupole."""
+    pq = C.c_int64()
+    _check(load().bh_sim_counts_pq_get(ctx, C.byref(pq)))
+    return pq.value
 
 
 # ----------------------------------------------------------------- learned criterion

@@ -86,7 +86,8 @@ static void free_tree_bufs(bh_tree *t) {
 
 static void free_sim(SimState *s) {
     DevBuf *all[] = {&s->pos, &s->vel, &s->mass, &s->acc, &s->phi, &s->id,
-                     &s->pos2, &s->vel2, &s->mass2, &s->id2, &s->red, &s->acc_tmp};
+                     &s->pos2, &s->vel2, &s->mass2, &s->id2, &s->red, &s->acc_tmp,
+                     &s->cnt_pp, &s->cnt_pc, &s->cnt_pq, &s->cnt_sum};
     for (DevBuf *b : all) free_buf(*b);
 }
 
@@ -94,8 +95,10 @@ static bool bad_dtype(int d) { return d != BH_F32 && d != BH_F64; }
 static size_t dsize(int d) { return d == BH_F32 ? 4 : 8; }
 
 static int check_opts(const bh_force_opts &o, int64_t n) {
-    if (o.order != 0 && o.order != 2 && o.order != 3)
-        return set_error(BH_E_INVALID, "opts.order must be 0, 2 or 3");
+    if (o.order != 0 && o.order != BH_ORDER_MIXED && o.order != 2 && o.order != 3)
+        return set_error(BH_E_INVALID, "opts.order must be 0, 1 (BH_ORDER_MIXED), 2 or 3");
+    if (o.order == BH_ORDER_MIXED && o.mac != BH_MAC_BUDGET)
+        return set_error(BH_E_INVALID, "opts.order BH_ORDER_MIXED runs with BH_MAC_BUDGET only");
     if (o.order == 3 && o.mac != BH_MAC_THETA)
         return set_error(BH_E_INVALID, "opts.order 3 (octopole) runs with the opening angle "
                                        "BH_MAC_THETA only");
@@ -426,8 +429,10 @@ static int sim_forces(bh_ctx *c, bool want_phi) {
     const bool count = c->walk_ev != nullptr && s->cnt_sum.p != nullptr;
     uint32_t *npp = count ? (uint32_t *)s->cnt_pp.p : nullptr;
     uint32_t *npc = count ? (uint32_t *)s->cnt_pc.p : nullptr;
+    bh_force_opts wo = s->opts;
+    wo.n_pq = count ? (uint32_t *)s->cnt_pq.p : nullptr;
     rc = run_walk(c->sim_tree, s->theta, s->eps, s->acc.p, want_phi ? s->phi.p : nullptr,
-                  npp, npc, s->opts, true, s->have_acc ? s->acc.p : nullptr);
+                  npp, npc, wo, true, s->have_acc ? s->acc.p : nullptr);
     s->phi_valid = want_phi && rc == BH_OK;
     s->counted = rc == BH_OK && count;
     return rc;
@@ -479,6 +484,7 @@ int bh_sim_init(bh_ctx *c, const void *pos, const void *vel, const void *mass, i
     s->theta = theta;
     s->eps = eps;
     s->opts = o;
+    s->opts.n_pq = nullptr;  // a recorded step counts into the state's own buffers
     s->have_acc = false;
     const size_t e = dsize(dtype);
     if ((rc = grow(s->pos, 3 * e * n)) || (rc = grow(s->vel, 3 * e * n)) ||
@@ -543,7 +549,8 @@ int bh_leapfrog_step(bh_ctx *c, double dt) {
     if (rc == BH_OK && s->counted) {  // after the step's last event: not in its phases
         s->counted = false;
         rc = launch_count_sum(c->stream, s->n, (const uint32_t *)s->cnt_pp.p,
-                              (const uint32_t *)s->cnt_pc.p, (unsigned long long *)s->cnt_sum.p);
+                              (const uint32_t *)s->cnt_pc.p, (const uint32_t *)s->cnt_pq.p,
+                              (unsigned long long *)s->cnt_sum.p);
     }
     return rc;
 }
@@ -556,9 +563,9 @@ int bh_sim_timing(bh_ctx *c, int enable) {
         if (use_device(c)) return BH_E_DEVICE;
         int rc;
         if ((rc = grow(s->cnt_pp, 4ull * s->n)) || (rc = grow(s->cnt_pc, 4ull * s->n)) ||
-            (rc = grow(s->cnt_sum, 16)))
+            (rc = grow(s->cnt_pq, 4ull * s->n)) || (rc = grow(s->cnt_sum, 24)))
             return rc;
-        if (hipMemsetAsync(s->cnt_sum.p, 0, 16, c->stream) != hipSuccess)
+        if (hipMemsetAsync(s->cnt_sum.p, 0, 24, c->stream) != hipSuccess)
             return set_error(BH_E_DEVICE, "clearing the interaction counters failed");
     }
     c->timing = enable != 0;
@@ -579,6 +586,22 @@ int bh_sim_counts_get(bh_ctx *c, int64_t *pp, int64_t *pc) {
         return set_error(BH_E_DEVICE, "reading the interaction counters failed");
     *pp = (int64_t)h[0];
     *pc = (int64_t)h[1];
+    return BH_OK;
+}
+
+int bh_sim_counts_pq_get(bh_ctx *c, int64_t *pq) {
+    if (!c || !pq) return set_error(BH_E_INVALID, "null argument");
+    if (!c->sim || !c->sim->have_acc) return set_error(BH_E_STATE, "bh_sim_init has not run");
+    SimState *s = c->sim;
+    *pq = 0;
+    if (!s->cnt_sum.p) return BH_OK;  // nothing recorded (or the direct method)
+    if (use_device(c)) return BH_E_DEVICE;
+    unsigned long long h = 0;
+    if (hipMemcpyAsync(&h, (const char *)s->cnt_sum.p + 16, 8, hipMemcpyDeviceToHost,
+                       c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return set_error(BH_E_DEVICE, "reading the interaction counters failed");
+    *pq = (int64_t)h;
     return BH_OK;
 }
 

@@ -171,7 +171,7 @@ struct SimState {
     DevBuf pos2, vel2, mass2, id2;             // gather targets
     DevBuf red;                                // energy reduction scratch
     DevBuf acc_tmp;                            // accelerations of an energy walk
-    DevBuf cnt_pp, cnt_pc, cnt_sum;            // interaction counts of recorded steps
+    DevBuf cnt_pp, cnt_pc, cnt_pq, cnt_sum;    // interaction counts of recorded steps
     bool have_acc = false;
     bool phi_valid = false;                    // phi belongs to the current state
     bool counted = false;                      // cnt_pp/cnt_pc hold this step's counts
@@ -211,9 +211,9 @@ int launch_energy(hipStream_t s, int dtype, int64_t n, const void *vel, const vo
                   const void *phi, double *red, double *host_out2);
 int launch_unpermute(hipStream_t s, int dtype, int64_t n, const uint32_t *id, const void *src,
                      void *dst);
-// out[0] += sum a, out[1] += sum b (n values each)
+// out[0] += sum a, out[1] += sum b, out[2] += sum c (n values each)
 int launch_count_sum(hipStream_t s, int64_t n, const uint32_t *a, const uint32_t *b,
-                     unsigned long long *out);
+                     const uint32_t *c, unsigned long long *out);
 int launch_direct(hipStream_t s, int dtype, int64_t n, const void *pos, const void *mass,
                   const int64_t *targets, int64_t nt, double eps, double *acc, double *phi,
                   DevBuf &scratch);

@@ -37,24 +37,36 @@ __global__ __launch_bounds__(kThreads) void k_kick_drift(int64_t n3, T *__restri
     }
 }
 
-// Adds sum(a) and sum(b) (per-body interaction counts) into out[0], out[1]:
-// per-thread 64-bit sums, a wavefront reduction, one atomic per wavefront.
+// Adds sum(a), sum(b) and sum(c) (per-body interaction counts) into out[0],
+// out[1], out[2]: per-thread 64-bit sums, a wavefront reduction, the block's
+// wavefronts in LDS, one atomic per block and sum.
 __global__ __launch_bounds__(kThreads) void k_count_sum(int64_t n, const uint32_t *__restrict__ a,
                                                         const uint32_t *__restrict__ b,
+                                                        const uint32_t *__restrict__ c,
                                                         unsigned long long *__restrict__ out) {
-    unsigned long long sa = 0, sb = 0;
+    unsigned long long sa = 0, sb = 0, sc = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         sa += a[i];
         sb += b[i];
+        sc += c[i];
     }
     for (int off = 32; off > 0; off >>= 1) {
         sa += __shfl_down(sa, off);
         sb += __shfl_down(sb, off);
+        sc += __shfl_down(sc, off);
     }
+    __shared__ unsigned long long ws[kThreads / 64][3];
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&out[0], sa);
-        atomicAdd(&out[1], sb);
+        ws[threadIdx.x >> 6][0] = sa;
+        ws[threadIdx.x >> 6][1] = sb;
+        ws[threadIdx.x >> 6][2] = sc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long v = 0;
+        for (int w = 0; w < kThreads / 64; ++w) v += ws[w][threadIdx.x];
+        atomicAdd(&out[threadIdx.x], v);
     }
 }
 
@@ -322,8 +334,8 @@ int grid_for(int64_t n) {
 }  // namespace
 
 int launch_count_sum(hipStream_t s, int64_t n, const uint32_t *a, const uint32_t *b,
-                     unsigned long long *out) {
-    k_count_sum<<<std::min(grid_for(n), 1024), kThreads, 0, s>>>(n, a, b, out);
+                     const uint32_t *c, unsigned long long *out) {
+    k_count_sum<<<std::min(grid_for(n), 1024), kThreads, 0, s>>>(n, a, b, c, out);
     return check_launch("count_sum");
 }
 

@@ -24,6 +24,7 @@
 // below 2^23) times h, so the difference of the body's leaf centre and any
 // cell centre is exact in FP32; adding the offset is the only rounding.
 #include <algorithm>
+#include <type_traits>
 
 #include "bh_internal.h"
 #include "mlp.h"
@@ -102,7 +103,15 @@ struct MlpMac {
     const MlpPacked *net;
     float eps;
     const void *oct;  // order 3: octopole records, 8 values per node
+    uint32_t *npq;    // optional: particle-cell terms with the quadrupole
 };
+
+// Criterion codes of the walk kernels: 0 opening angle, 1 error budget,
+// 2 / 3 learned (bf16 / fp16 network), 4 error budget with the mixed order
+// (per cell the monopole where its budget charged with the dropped
+// quadrupole's bound holds, else the quadrupole, else open).
+template <int MAC> constexpr bool kBudget = MAC == 1 || MAC == 4;
+template <int MAC> constexpr bool kLearned = MAC == 2 || MAC == 3;
 
 template <int MAC> struct NetVec { using type = bf16x8; };
 
@@ -159,11 +168,11 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
                                            int nbodies, int i, bool live, R ox, R oy, R oz,
                                            R ax, R ay, R az, int myleaf, R theta2, R eps2,
                                            const MlpMac &mac, R &sx, R &sy, R &sz, R &sp,
-                                           uint32_t &cpp, uint32_t &cpc) {
+                                           uint32_t &cpp, uint32_t &cpc, uint32_t &cpq) {
     using Rec = typename NodeRecT<R>::type;
     float tau_a = 0.f;  // tau |a_i|
     if (MAC >= 1 && live) tau_a = mac.tau * fmaxf(mac.anorm[i], *mac.afloor);
-    const float lt = MAC >= 2 && live ? lg10(tau_a) : 0.f;
+    const float lt = kLearned<MAC> && live ? lg10(tau_a) : 0.f;
     const int lane = (int)lane_id();
 
     const bool root_leaf = nodes[0].next == 1;
@@ -195,7 +204,8 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
             const R x = X - nd.mx, y = Y - nd.my, z = Z - nd.mz;
             const R d2 = x * x + y * y + z * z;
             bool accept;
-            if (MAC == 1) {
+            bool mono = !ORDER2;  // the term without the quadrupole
+            if (kBudget<MAC>) {
                 // error budget: M l^3 / d^5 below tau |a_i|, l/d below
                 // theta_max, and the body outside the cell
                 // (monopole terms: plus the dropped quadrupole's bound)
@@ -203,10 +213,16 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
                 const R hs = (R)0.5 * tsqrt(nd.l2);
                 const bool inside = fabs(X) <= hs && fabs(Y) <= hs && fabs(Z) <= hs;
                 const R d = tsqrt(d2);
-                if (!ORDER2) kcv = quad_bound(nd) * d + kcv;
-                accept = act && nd.l2 < (R)mac.tmax2 * d2 && !inside &&
-                         kcv < tau_a * (d2 * d2 * d);
-            } else if (MAC >= 2) {
+                const R rhs = tau_a * (d2 * d2 * d);
+                const bool geo = act && nd.l2 < (R)mac.tmax2 * d2 && !inside;
+                if (MAC == 4) {  // mixed: the monopole where it meets the budget
+                    mono = geo && quad_bound(nd) * d + kcv < rhs;
+                    accept = geo && kcv < rhs;
+                } else {
+                    if (!ORDER2) kcv = quad_bound(nd) * d + kcv;
+                    accept = geo && kcv < rhs;
+                }
+            } else if (kLearned<MAC>) {
                 // learned, the body as its own group: the network's error
                 // for (body, cell) below tau |a_i|, l/d below theta_max, the
                 // body outside the cell; one 64-row batch per node
@@ -240,10 +256,15 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
                 const R inv2 = inv * inv;
                 const R inv3 = inv * inv2;
                 if (ORDER2) {
-                    const R qzz = -nd.qxx - nd.qyy;
-                    const R qx = nd.qxx * x + nd.qxy * y + nd.qxz * z;
-                    const R qy = nd.qxy * x + nd.qyy * y + nd.qyz * z;
-                    const R qz = nd.qxz * x + nd.qyz * y + qzz * z;
+                    // (mixed order: a monopole lane takes Q = 0, which gives
+                    // the monopole term exactly)
+                    const R qs = MAC == 4 && mono ? (R)0 : (R)1;
+                    const R qxx = nd.qxx * qs, qxy = nd.qxy * qs, qxz = nd.qxz * qs,
+                            qyy = nd.qyy * qs, qyz = nd.qyz * qs;
+                    const R qzz = -qxx - qyy;
+                    const R qx = qxx * x + qxy * y + qxz * z;
+                    const R qy = qxy * x + qyy * y + qyz * z;
+                    const R qz = qxz * x + qyz * y + qzz * z;
                     const R xqx = x * qx + y * qy + z * qz;
                     const R inv5 = inv3 * inv2;
                     const R t5 = xqx * inv5;
@@ -265,7 +286,10 @@ __device__ __forceinline__ void body_sweep(const typename NodeRecT<R>::type *__r
                     sz = -g * z + sz;
                     if (PHI) sp = sp - nd.m * inv;
                 }
-                if (CNT) ++cpc;
+                if (CNT) {
+                    ++cpc;
+                    if (!mono) ++cpq;
+                }
             }
             if (nxt == idx + 1) pp = act && !accept;  // leaf
             else open = act && !accept;
@@ -323,10 +347,10 @@ __global__ __launch_bounds__(256) void k_walk(
         myleaf = an.leaf;
     }
     R sx = 0, sy = 0, sz = 0, sp = 0;
-    uint32_t cpp = 0, cpc = 0;
+    uint32_t cpp = 0, cpc = 0, cpq = 0;
     body_sweep<R, ORDER2, PHI, CNT, MAC, false, GUARD, OCT>(nodes, m, bodies, nbodies, i, live, ox,
                                                        oy, oz, ax, ay, az, myleaf, theta2, eps2,
-                                                       mac, sx, sy, sz, sp, cpp, cpc);
+                                                       mac, sx, sy, sz, sp, cpp, cpc, cpq);
     if (live) {
         const int o = SORTED_OUT ? i : (int)perm[i];
         acc[3 * (int64_t)o + 0] = sx;
@@ -336,6 +360,7 @@ __global__ __launch_bounds__(256) void k_walk(
         if (CNT) {
             npp_out[o] = cpp;
             npc_out[o] = cpc;
+            if (mac.npq) mac.npq[o] = cpq;
         }
     }
 }
@@ -426,6 +451,7 @@ struct GroupMac {
     const MlpPacked *net;  // learned criterion: the packed network
     float eps;             // and the softening (a feature)
     const void *oct;       // order 3: octopole records, 8 values per node
+    uint32_t *npq;         // optional: particle-cell terms with the quadrupole
 };
 
 // A group that exceeded the work cap is walked per body straight away (in
@@ -466,7 +492,9 @@ __device__ __forceinline__ int wave_min_i(int v) {
 }
 
 // kGCand: a candidate of the learned criterion, decided by the network
-enum : int { kGNone = 0, kGPC = 1, kGPP = 2, kGOpen = 3, kGCand = 4 };
+// kGPQ: accepted with the quadrupole (the mixed order; kGPC is then the
+// monopole)
+enum : int { kGNone = 0, kGPC = 1, kGPP = 2, kGOpen = 3, kGCand = 4, kGPQ = 5 };
 
 // One group: the 64 bodies of sorted rank [base, min(base + 64, t1)).
 template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, int MAC, bool OCT>
@@ -526,10 +554,10 @@ __device__ __forceinline__ auto group_walk(
         float tau_amin = 0.f;
         if (MAC >= 1)
             tau_amin = gm.tau * fmaxf(wave_min(live_run ? gm.anorm[i] : 3.0e38f), *gm.afloor);
-        const float lt = MAC >= 2 ? lg10(tau_amin) : 0.f;  // log10(tau a_min)
+        const float lt = kLearned<MAC> ? lg10(tau_amin) : 0.f;  // log10(tau a_min)
 
         R sx = 0, sy = 0, sz = 0, sp = 0;
-        uint32_t cpp = 0, cpc = 0;
+        uint32_t cpp = 0, cpc = 0, cpq = 0;
         int work = 0;  // wave-uniform
 
         // decision for node c (any lane; wave-uniform when the node is)
@@ -544,14 +572,21 @@ __device__ __forceinline__ auto group_walk(
             const R tz = fmax(fabs(uz + nd.mz) - bhz, (R)0);
             const R dg2 = tx * tx + ty * ty + tz * tz;
             bool accept = !overlap && nd.l2 < theta2 * dg2;
-            if (MAC == 1) {  // (monopole terms: plus the dropped quadrupole's bound)
+            if (kBudget<MAC>) {  // (monopole terms: plus the dropped quadrupole's bound)
                 const float dg = tsqrt((float)dg2);
-                if (!ORDER2) kcv = quad_bound(nd) * dg + kcv;
-                accept = accept && kcv < tau_amin * (float)(dg2 * dg2 * dg);
+                const float rhs = tau_amin * (float)(dg2 * dg2 * dg);
+                if (MAC == 4) {  // mixed order: the monopole where it meets the budget
+                    if (accept && quad_bound(nd) * dg + kcv < rhs) return kGPC;
+                    if (accept && kcv < rhs) return kGPQ;
+                    accept = false;
+                } else {
+                    if (!ORDER2) kcv = quad_bound(nd) * dg + kcv;
+                    accept = accept && kcv < rhs;
+                }
             }
-            if (MAC >= 2 && accept && nd.m > (R)0) return kGCand;  // the network decides
-            if (MAC >= 2) accept = false;
-            if (accept) return kGPC;
+            if (kLearned<MAC> && accept && nd.m > (R)0) return kGCand;  // the network decides
+            if (kLearned<MAC>) accept = false;
+            if (accept) return MAC == 4 ? kGPQ : kGPC;
             return nd.next == c + 1 ? kGPP : kGOpen;
         };
         // the learned decision for the candidates among the lanes' nodes:
@@ -575,14 +610,15 @@ __device__ __forceinline__ auto group_walk(
                           : (nd.next == c + 1 ? kGPP : kGOpen);
         };
         // particle-cell term of node nd for this lane's body
-        auto cell_term = [&](const Rec &nd, int c) {
+        // (quad: with the quadrupole, in a walk of order 2 or more)
+        auto cell_term = [&](const Rec &nd, int c, bool quad) {
             const R X = (ax - nd.cx) + ox, Y = (ay - nd.cy) + oy, Z = (az - nd.cz) + oz;
             const R x = X - nd.mx, y = Y - nd.my, z = Z - nd.mz;
             const R d2 = x * x + y * y + z * z;
             const R inv = rsq(d2 + eps2);
             const R inv2 = inv * inv;
             const R inv3 = inv * inv2;
-            if (ORDER2) {
+            if (ORDER2 && quad) {
                 const R qzz = -nd.qxx - nd.qyy;
                 const R qx = nd.qxx * x + nd.qxy * y + nd.qxz * z;
                 const R qy = nd.qxy * x + nd.qyy * y + nd.qyz * z;
@@ -608,18 +644,22 @@ __device__ __forceinline__ auto group_walk(
                 sz = -g * z + sz;
                 if (PHI) sp = sp - nd.m * inv;
             }
-            if (CNT) ++cpc;
+            if (CNT) {
+                ++cpc;
+                if (ORDER2 && quad) ++cpq;
+            }
             ++work;
         };
         // particle-cell term of a staged cell: COM relative to the group origin
         // g, mass, quadrupole (xx xy xz yy yz zz)
-        auto staged_term = [&](const R *st) {
+        // (Quad: an integral constant, with the quadrupole)
+        auto staged_term = [&](const R *st, auto Quad) {
             const R x = px - st[0], y = py - st[1], z = pz - st[2];
             const R s2 = z * z + (y * y + (x * x + eps2));
             const R inv = rsq(s2);
             const R inv2 = inv * inv;
             const R m = st[3];
-            if (ORDER2) {
+            if constexpr (decltype(Quad)::value) {
                 // a = inv^5 (Q x - (m s^2 + 5/2 (x.Q.x)/s^2) x)
                 const R qx = st[4] * x + st[5] * y + st[6] * z;
                 const R qy = st[5] * x + st[7] * y + st[8] * z;
@@ -640,7 +680,10 @@ __device__ __forceinline__ auto group_walk(
                 sz = -g * z + sz;
                 if (PHI) sp = sp - m * inv;
             }
-            if (CNT) ++cpc;
+            if (CNT) {
+                ++cpc;
+                if (decltype(Quad)::value) ++cpq;
+            }
         };
         // particle-particle terms with the bodies of leaf (or one-body cell) nd
         auto leaf_terms = [&](const Rec &nd) {
@@ -660,12 +703,13 @@ __device__ __forceinline__ auto group_walk(
             while (idx < end && work <= gm.work_cap) {
                 idx = uniform(idx);
                 const Rec nd = nodes[idx];
-                int cls = uniform(classify(nd, idx, MAC == 1 ? gm.kc[idx] : 0.f));
-                if (MAC >= 2 && cls == kGCand) {
+                int cls = uniform(classify(nd, idx, kBudget<MAC> ? gm.kc[idx] : 0.f));
+                if (kLearned<MAC> && cls == kGCand) {
                     learn(nd, idx, cls);
                     cls = uniform(cls);
                 }
-                if (cls == kGPC) cell_term(nd, idx);
+                if (cls == kGPC) cell_term(nd, idx, ORDER2 && MAC != 4);
+                else if (cls == kGPQ) cell_term(nd, idx, true);
                 else if (cls == kGPP) leaf_terms(nd);
                 const int nx = uniform(nd.next);
                 idx = cls == kGOpen || nx <= idx ? idx + 1 : nx;  // always moves forward
@@ -687,14 +731,14 @@ __device__ __forceinline__ auto group_walk(
                 // cached) and take no part
                 const int c = has ? stk[top + lane] : 0;
                 int4 k0 = make_int4(-1, -1, -1, -1), k1 = k0;
-                if (MAC < 2) {
+                if (!kLearned<MAC>) {
                     k0 = kids[2 * (int64_t)c];  // loaded with the record, used if opened
                     k1 = kids[2 * (int64_t)c + 1];
                 }
                 const Rec nd = nodes[c];
-                int cls = classify(nd, c, MAC == 1 ? gm.kc[c] : 0.f);
+                int cls = classify(nd, c, kBudget<MAC> ? gm.kc[c] : 0.f);
                 if (!has) cls = kGNone;
-                if (MAC >= 2) {
+                if (kLearned<MAC>) {
                     // the children after the network (fewer registers live
                     // across its evaluation)
                     if (__ballot(cls == kGCand)) learn(nd, c, cls);
@@ -703,18 +747,24 @@ __device__ __forceinline__ auto group_walk(
                         k1 = kids[2 * (int64_t)c + 1];
                     }
                 }
-                const uint64_t m_pc = __ballot(cls == kGPC);
+                const uint64_t m_pc = __ballot(cls == kGPC);  // (mixed order: monopoles)
+                const uint64_t m_pq = MAC == 4 ? __ballot(cls == kGPQ) : 0ull;
                 const uint64_t m_pp = __ballot(cls == kGPP);
                 const uint64_t m_op = __ballot(cls == kGOpen);
-                if (cls == kGPC) {  // stage the accepted cell for every lane
-                    const int slot = (int)__builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(m_pc >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m_pc, 0u));
-                    R *st = stage + SW * slot;
+                // stage the accepted cell for every lane; in the mixed order
+                // the quadrupole terms from slot 0 up, the monopoles from slot
+                // 63 down (at most 64 cells a round)
+                const bool quad_st = MAC == 4 ? cls == kGPQ : ORDER2;
+                if (cls == kGPC || (MAC == 4 && cls == kGPQ)) {
+                    const uint64_t mm = MAC == 4 && cls == kGPQ ? m_pq : m_pc;
+                    const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
+                    R *st = stage + SW * (MAC == 4 && cls == kGPC ? 63 - rank : rank);
                     st[0] = (nd.cx - gx) + nd.mx;
                     st[1] = (nd.cy - gy) + nd.my;
                     st[2] = (nd.cz - gz) + nd.mz;
                     st[3] = nd.m;
-                    if (ORDER2) {
+                    if (ORDER2 && quad_st) {
                         st[4] = nd.qxx;
                         st[5] = nd.qxy;
                         st[6] = nd.qxz;
@@ -766,16 +816,31 @@ __device__ __forceinline__ auto group_walk(
                 }
                 // accepted cells from LDS (same address on every lane: broadcast)
                 const int npc_round = __builtin_popcountll(m_pc);
+                const int npq_round = MAC == 4 ? __builtin_popcountll(m_pq) : 0;
                 __builtin_amdgcn_wave_barrier();
                 // two cells per iteration (immediate LDS offsets, two
                 // independent chains; the sums still follow q)
-                int q = 0;
-                for (; q + 1 < npc_round; q += 2) {
-                    staged_term(stage + SW * q);
-                    staged_term(stage + SW * (q + 1));
+                using QuadT = std::integral_constant<bool, ORDER2 && MAC != 4>;
+                if (MAC == 4) {
+                    const std::true_type yes;
+                    int q = 0;
+                    for (; q + 1 < npq_round; q += 2) {
+                        staged_term(stage + SW * q, yes);
+                        staged_term(stage + SW * (q + 1), yes);
+                    }
+                    if (q < npq_round) staged_term(stage + SW * q, yes);
                 }
-                if (q < npc_round) staged_term(stage + SW * q);
-                work += npc_round;
+                {
+                    const QuadT quad;
+                    const int top_slot = MAC == 4 ? 63 : 0, dir = MAC == 4 ? -1 : 1;
+                    int q = 0;
+                    for (; q + 1 < npc_round; q += 2) {
+                        staged_term(stage + SW * (top_slot + dir * q), quad);
+                        staged_term(stage + SW * (top_slot + dir * (q + 1)), quad);
+                    }
+                    if (q < npc_round) staged_term(stage + SW * (top_slot + dir * q), quad);
+                }
+                work += npc_round + npq_round;
                 // particle-particle leaves (and one-body cells) of the round.
                 // The bodies of those that hold none of the group's bodies are
                 // written to LDS in the group's frame, each leaf by its own
@@ -873,11 +938,11 @@ __device__ __forceinline__ auto group_walk(
         over += per_body ? 1 : 0;
         if (per_body) {  // too spread out for one decision: walk per body
             sx = sy = sz = sp = 0;
-            cpp = cpc = 0;
-            const MlpMac pm{gm.kc, gm.anorm, gm.afloor, (float)theta2, gm.tau, gm.net, gm.eps, gm.oct};
-            body_sweep<R, ORDER2, PHI, CNT, MAC, (MAC < 2), false, OCT>(nodes, m, bodies, nbodies, i, live_run, ox, oy, oz,
+            cpp = cpc = cpq = 0;
+            const MlpMac pm{gm.kc, gm.anorm, gm.afloor, (float)theta2, gm.tau, gm.net, gm.eps, gm.oct, nullptr};
+            body_sweep<R, ORDER2, PHI, CNT, MAC, !kLearned<MAC>, false, OCT>(nodes, m, bodies, nbodies, i, live_run, ox, oy, oz,
                                                     ax, ay, az, myleaf, theta2, eps2, pm, sx, sy, sz,
-                                                    sp, cpp, cpc);
+                                                    sp, cpp, cpc, cpq);
         }
         if (live_run) {
             const int o = SORTED_OUT ? i : (int)perm[i];
@@ -888,6 +953,7 @@ __device__ __forceinline__ auto group_walk(
             if (CNT) {
                 npp_out[o] = cpp;
                 npc_out[o] = cpc;
+                if (gm.npq) gm.npq[o] = cpq;
             }
         }
     };
@@ -936,11 +1002,11 @@ __device__ __forceinline__ void part_walk(
         myleaf = an.leaf;
     }
     R sx = 0, sy = 0, sz = 0, sp = 0;
-    uint32_t cpp = 0, cpc = 0;
-    const MlpMac pm{gm.kc, gm.anorm, gm.afloor, (float)theta2, gm.tau, gm.net, gm.eps, gm.oct};
-    body_sweep<R, ORDER2, PHI, CNT, MAC, (MAC < 2), false, OCT>(nodes, m, bodies, nbodies, i, live, ox, oy, oz,
+    uint32_t cpp = 0, cpc = 0, cpq = 0;
+    const MlpMac pm{gm.kc, gm.anorm, gm.afloor, (float)theta2, gm.tau, gm.net, gm.eps, gm.oct, nullptr};
+    body_sweep<R, ORDER2, PHI, CNT, MAC, !kLearned<MAC>, false, OCT>(nodes, m, bodies, nbodies, i, live, ox, oy, oz,
                                                   ax, ay, az, myleaf, theta2, eps2, pm, sx, sy, sz,
-                                                  sp, cpp, cpc);
+                                                  sp, cpp, cpc, cpq);
     if (live) {
         const int o = SORTED_OUT ? i : (int)perm[i];
         acc[3 * (int64_t)o + 0] = sx;
@@ -950,6 +1016,7 @@ __device__ __forceinline__ void part_walk(
         if (CNT) {
             npp_out[o] = cpp;
             npc_out[o] = cpc;
+            if (gm.npq) gm.npq[o] = cpq;
         }
     }
 }
@@ -961,7 +1028,7 @@ __device__ __forceinline__ void part_walk(
 // atomic counter until the chunk is done.  A heavy group then delays only
 // the wavefront that drew it.
 template <typename R, bool ORDER2, bool PHI, bool CNT, bool SORTED_OUT, int MAC, bool OCT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAC >= 2 ? 4 : 1))) void k_gwalk(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kLearned<MAC> ? 4 : 1))) void k_gwalk(
     const typename NodeRecT<R>::type *__restrict__ nodes, int m,
     const BodyRec<R> *__restrict__ bodies, const Anchor<R> *__restrict__ anchors,
     const int4 *__restrict__ kids, const uint32_t *__restrict__ perm, int nbodies, int t0,
@@ -971,10 +1038,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAC >= 2 ? 
     __shared__ int stack_all[4][kGroupStack];
     __shared__ R stage_all[4][64 * StageW<OCT>::value];
     // the learned criterion's network, staged once per workgroup
-    __shared__ u32x4 net_lds[MAC >= 2 ? sizeof(MlpPacked) / 16 : 1];
+    __shared__ u32x4 net_lds[kLearned<MAC> ? sizeof(MlpPacked) / 16 : 1];
     int *stk = stack_all[threadIdx.x >> 6];
     R *stage = stage_all[threadIdx.x >> 6];
-    if (MAC >= 2) {
+    if (kLearned<MAC>) {
         const u32x4 *src = (const u32x4 *)gm.net;
         for (int k = threadIdx.x; k < (int)(sizeof(MlpPacked) / 16); k += 256) net_lds[k] = src[k];
         __syncthreads();
@@ -1212,13 +1279,19 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
     }
     if (t1 <= t0) return BH_OK;
     t->last_mac = o.mac;
-    if ((npp != nullptr) != (npc != nullptr)) {  // the kernel writes both or neither
+    if (o.n_pq && !npp && !npc) {  // the quadrupole terms are counted with the others
+        int rc = grow(t->cnt_scratch, 8ull * t->n);
+        if (rc) return rc;
+        npp = (uint32_t *)t->cnt_scratch.p;
+        npc = npp + t->n;
+    } else if ((npp != nullptr) != (npc != nullptr)) {  // the kernel writes both or neither
         int rc = grow(t->cnt_scratch, 4ull * t->n);
         if (rc) return rc;
         if (!npp) npp = (uint32_t *)t->cnt_scratch.p;
         else npc = (uint32_t *)t->cnt_scratch.p;
     }
     MlpMac mac{nullptr, nullptr, nullptr, 0.f, 0.f};
+    mac.npq = o.n_pq;
     const bool group = o.walk == BH_WALK_GROUP;
     if (group) {
         int rc = ensure_kids(t);
@@ -1229,6 +1302,7 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
                 : o.mac == BH_MAC_BUDGET       ? kGroupWorkCapBudget
                                                : kGroupWorkCap,
                 nullptr, nullptr, kPredictWalks};
+    gm.npq = o.n_pq;
     // the parameters that decide which groups exceed the work cap (FNV-1a)
     uint64_t sig = 1469598103934665603ull;
     auto mixin = [&](const void *p, size_t len) {
@@ -1249,11 +1323,11 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
     }
     if (o.mac == BH_MAC_MLP || o.mac == BH_MAC_BUDGET) {
         const bool learned = o.mac == BH_MAC_MLP;
-        if (t->dtype != BH_F32 || (o.order != 2 && (learned || o.order != 0)))
+        if (t->dtype != BH_F32 || (o.order != 2 && (learned || o.order > 2)))
             return set_error(BH_E_INVALID, learned
                                                ? "the learned criterion runs in the FP32 quadrupole walk"
-                                               : "the error budget runs in the FP32 walk of order 0 or 2");
-        const bool mono = o.order == 0;
+                                               : "the error budget runs in the FP32 walk of order 0, 1 (mixed) or 2");
+        const bool mono = o.order == 0, mixed = o.order == BH_ORDER_MIXED;
         int rc = learned ? BH_OK : mlp_cells(t);
         if (rc) return rc;
         if (o.mlp_acc_norm) {
@@ -1294,6 +1368,7 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
             gm.eps = mac.eps;
 #define BH_GM(k) gdispatch<float, true, k>(t, t0, t1, o.mlp_theta_max, eps, acc, phi, npp, npc, sorted_out, gm, sig)
             if (!learned && mono) gdispatch<float, false, 1>(t, t0, t1, o.mlp_theta_max, eps, acc, phi, npp, npc, sorted_out, gm, sig);
+            else if (!learned && mixed) BH_GM(4);
             else if (!learned) BH_GM(1);
             else if (f16) BH_GM(3);
             else BH_GM(2);
@@ -1301,6 +1376,7 @@ int run_walk(bh_tree *t, double theta, double eps, void *acc, void *phi, uint32_
         } else {
 #define BH_BM(k) dispatch2<float, true, k>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac)
             if (!learned && mono) dispatch2<float, false, 1>(t, t0, t1, theta, eps, acc, phi, npp, npc, sorted_out, mac);
+            else if (!learned && mixed) BH_BM(4);
             else if (!learned) BH_BM(1);
             else if (f16) BH_BM(3);
             else BH_BM(2);

@@ -2,7 +2,9 @@
 oracle: a cell is accepted iff M l^3 + (7/2) |Q|_F d < tau |a| d^5 (the
 dropped quadrupole term of Sec. 2.2 bounded by (7/2) |Q|_F / d^4, added to
 the budget of Sec. 3.2), per body and per group, over Morton and Hilbert
-groups, with the per-body fallback of runs over the work cap."""
+groups, with the per-body fallback of runs over the work cap; and the mixed
+order (the monopole where that holds, else the quadrupole where
+M l^3 < tau |a| d^5, else open), with its count of quadrupole terms."""
 import numpy as np
 import pytest
 import torch
@@ -10,7 +12,7 @@ import torch
 import oracle
 from paper_2203_08966_amd import binding as B
 from tests.conftest import case_bodies, say
-from tests.test_gpu_group import CAP_BUDGET, FLAG_TOL, _check, _run
+from tests.test_gpu_group import CAP_BUDGET, FLAG_TOL, MAX_FLAGGED, _check, _run
 from tests.test_gpu_mlp import _compare, _gpu_walk, _oracle_anorm
 
 pytestmark = pytest.mark.gpu
@@ -103,5 +105,100 @@ def test_budget_orders_accepted_and_refused(ctx):
         with pytest.raises(B.BHError):
             B.bh_forces(t, 0.5, 0.005, torch.empty_like(p64),
                         B.force_opts(mac=B.BH_MAC_BUDGET, order=0))
+    finally:
+        B.bh_tree_free(t)
+
+
+def _run_q(ctx, pos, mass, eps, curve=B.BH_CURVE_MORTON, **kw):
+    """A walk with all four outputs and the quadrupole-term count."""
+    B.bh_ctx_set_curve(ctx, curve)
+    try:
+        P, M = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
+        t = B.bh_build(ctx, P, M, 16)
+    finally:
+        B.bh_ctx_set_curve(ctx, B.BH_CURVE_MORTON)
+    n = len(mass)
+    acc = torch.empty_like(P)
+    phi = torch.empty_like(M)
+    cnt = [torch.zeros(n, dtype=torch.int32, device="cuda") for _ in range(3)]
+    an = kw.pop("acc_norm", None)
+    an_t = None if an is None else torch.from_numpy(an.astype(np.float32)).cuda()
+    o = B.force_opts(phi=phi, n_pp=cnt[0], n_pc=cnt[1], n_pq=cnt[2], mlp_acc_norm=an_t, **kw)
+    B.bh_forces(t, 0.5, eps, acc, o)
+    torch.cuda.synchronize()
+    B.bh_tree_free(t)
+    return (acc.cpu().numpy().astype(np.float64), phi.cpu().numpy().astype(np.float64),
+            *(c.cpu().numpy() for c in cnt))
+
+
+def _check_q(ref, r, out, eps, max_flagged):
+    """Unflagged bodies: identical counts (quadrupole terms included) and
+    forces within the FP32 bounds; flagged bodies within the method's error."""
+    from tests.conftest import check_flagged
+    a, phi, cp, cc, cq = (x[ref["perm"]] for x in out)
+    ok = r.flag == 0
+    same = (cp == r.npp) & (cc == r.npc) & (cq == r.npq)
+    say(f"  unflagged {ok.mean():.4f}, identical counts there {same[ok].mean():.4f}; "
+        f"quadrupole terms {r.npq.sum() / max(r.npc.sum(), 1):.3f} of the cell terms")
+    assert np.all(same[ok])
+    e = np.linalg.norm(a - r.acc, axis=1) / np.linalg.norm(r.acc, axis=1)
+    assert np.sqrt(np.mean(e[ok] ** 2)) <= 1e-5 and e[ok].max() <= 1e-4
+    check_flagged(ref, r.acc, a, r.flag, eps, max_flagged)
+
+
+@pytest.mark.parametrize("kind,tau,tmax,fl", [
+    ("plummer", 1e-2, 1.0, 0.0),
+    ("clumpy", 10 ** -1.5, 1.5, 0.5),
+])
+def test_body_budget_mixed_matches_oracle(ctx, kind, tau, tmax, fl):
+    eps = 0.005
+    pos, mass, ref, an = _setup(kind, 20000, 25)
+    say(f"per-body mixed-order budget: {kind}, tau {tau:.3g}, theta_max {tmax}, floor {fl}")
+    out = _run_q(ctx, pos, mass, eps, mac=B.BH_MAC_BUDGET, order=B.BH_ORDER_MIXED,
+                 mlp_theta_max=tmax, mlp_log10_tau=np.log10(tau), acc_norm=an, mlp_acc_floor=fl)
+    r = oracle.walk_kc(ref, eps, tmax, tau, oracle.cell_kc(ref), an.astype(np.float64)[ref["perm"]],
+                       floor=fl, order=oracle.ORDER_MIXED)
+    assert 0.01 < r.npq.sum() / r.npc.sum() < 0.99  # both kinds of term present
+    _check_q(ref, r, out, eps, 0.01)
+
+
+@pytest.mark.parametrize("curve,cap", [("morton", CAP_BUDGET), ("hilbert", CAP_BUDGET),
+                                       ("morton", 1200)])
+def test_group_budget_mixed_matches_oracle(ctx, curve, cap):
+    eps, tau, tmax, fl = 0.005, 10 ** -2.0, 1.5, 0.5
+    pos, mass, ref, an = _setup("plummer" if cap == CAP_BUDGET else "clumpy", 20000, 26, curve)
+    say(f"group mixed-order budget ({curve}, work cap {cap}): tau {tau:.3g}, floor {fl}")
+    out = _run_q(ctx, pos, mass, eps,
+                 curve=B.BH_CURVE_HILBERT if curve == "hilbert" else B.BH_CURVE_MORTON,
+                 walk=B.BH_WALK_GROUP, mac=B.BH_MAC_BUDGET, order=B.BH_ORDER_MIXED,
+                 mlp_theta_max=tmax, mlp_log10_tau=np.log10(tau), acc_norm=an,
+                 mlp_acc_floor=fl, walk_cap=cap)
+    kw = dict(group=B.BH_GROUP_BODIES, mode=1, order=oracle.ORDER_MIXED, theta_max=tmax, tau=tau,
+              kc=oracle.cell_kc(ref), anorm=an.astype(np.float64)[ref["perm"]],
+              tol=FLAG_TOL[np.float32], split=True, floor=fl)
+    r = oracle.walk_group(ref, eps, cap=cap, **kw)
+    if cap != CAP_BUDGET:  # part of the runs walked per body
+        r0 = oracle.walk_group(ref, eps, cap=1 << 40, **kw)
+        assert 0.1 < np.mean((r.npp != r0.npp) | (r.npc != r0.npc)) < 0.9
+    assert 0.01 < r.npq.sum() / r.npc.sum() < 0.99
+    _check_q(ref, r, out, eps, MAX_FLAGGED)
+
+
+def test_quadrupole_count_by_order(ctx):
+    """n_pq: every particle-cell term at order 2, none at order 0; the mixed
+    order runs with the error budget only."""
+    pos, _, mass = case_bodies("plummer", 3000, 27, np.float32)
+    for walk in (B.BH_WALK_BODY, B.BH_WALK_GROUP):
+        for order, mac in ((2, B.BH_MAC_THETA), (0, B.BH_MAC_THETA), (2, B.BH_MAC_BUDGET),
+                           (0, B.BH_MAC_BUDGET)):
+            _, _, cp, cc, cq = _run_q(ctx, pos, mass, 0.01, walk=walk, mac=mac, order=order)
+            assert cc.sum() > 0
+            np.testing.assert_array_equal(cq, cc if order == 2 else 0)
+    t = B.bh_build(ctx, torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda(), 16)
+    acc = torch.empty(3000, 3, device="cuda")
+    try:
+        for mac in (B.BH_MAC_THETA, B.BH_MAC_MLP, B.BH_MAC_THETA_GUARD):
+            with pytest.raises(B.BHError):
+                B.bh_forces(t, 0.5, 0.01, acc, B.force_opts(mac=mac, order=B.BH_ORDER_MIXED))
     finally:
         B.bh_tree_free(t)

@@ -489,7 +489,7 @@ def main():
                       f"{ {0: 'monopole', 1: 'mixed monopole/quadrupole', 2: 'quadrupole', 3: 'octopole'}[order_of(chosen)]})",
             "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved_tf / PEAK_FP32_TFLOPS,
-            "traffic": traffic_for(kernel, result_workload(cfg, n)),
+            "traffic": traffic_for(kernel, result_workload(cfg, n), chosen),
             "flop_per_launch": flops, "launch_ms": walk_kernel_ms,
         },
     }
@@ -620,10 +620,10 @@ def mlp_roofline(B, ctx, feat, epochs, train_s, precision):
     }
 
 
-def traffic_for(kernel, workload):
+def traffic_for(kernel, workload, method):
     """HBM bytes per launch of the timed walk kernel from the committed
-    rocprofv3 counter summary, if it was taken on this workload with the
-    current walk source; else None."""
+    rocprofv3 counter summary, if it was taken on this workload and method
+    with the current walk source; else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "walk_traffic.json")
     src = os.path.join(ROOT, "paper_2203_08966_amd", "csrc", "walk.hip")
@@ -633,7 +633,8 @@ def traffic_for(kernel, workload):
     except (OSError, ValueError):
         return None
     k = rec.get("kernels", {}).get(kernel)
-    if not k or rec.get("walk_hip_sha256") != sha or rec.get("workload") != workload:
+    if (not k or rec.get("walk_hip_sha256") != sha or rec.get("workload") != workload
+            or k.get("method") != method):
         return None
     return k["hbm_bytes_per_launch"]
 

@@ -972,8 +972,11 @@ struct LevelBase {
 // one thread per cell (a chain's cells are independent: each finds its own
 // segment end), so a long chain of shallow cells is spread over threads.
 // Block b places its level-k cells after those of blocks < b (scanned
-// per-block level counts in lvl_pre[(1 + k) * nb + b]).
-__global__ __launch_bounds__(kThreads) void k_emit(
+// per-block level counts in lvl_pre[(1 + k) * nb + b]).  A block is one
+// wavefront: 256 ranks hold about 60 cells (one per 4 to 5 bodies at
+// leaf capacity 16), which then keep its lanes busy.
+constexpr int kEmitThreads = 64;
+__global__ __launch_bounds__(kEmitThreads) void k_emit(
     const uint64_t *__restrict__ keys, const int8_t *__restrict__ delta,
     const int32_t *__restrict__ offs, int n, int m,
     const uint32_t *__restrict__ lvl_pre, LevelBase lb, uint64_t *__restrict__ hkey,
@@ -992,14 +995,13 @@ __global__ __launch_bounds__(kThreads) void k_emit(
                              (int32_t)lvl_pre[(size_t)(1 + threadIdx.x) * gridDim.x + blockIdx.x];
     }
     const int b0 = blockIdx.x * kThreads;
-    {
-        const int r = b0 + threadIdx.x;
-        so[threadIdx.x] = offs[r < n ? r : n];
-        if (threadIdx.x == 0) so[kThreads] = offs[b0 + kThreads < n ? b0 + kThreads : n];
+    for (int j = threadIdx.x; j <= kThreads; j += kEmitThreads) {
+        const int r = b0 + j;
+        so[j] = offs[r < n ? r : n];
     }
     __syncthreads();
     const int c1 = so[kThreads] < m ? so[kThreads] : m;
-    for (int node = so[0] + threadIdx.x; node < c1; node += kThreads) {
+    for (int node = so[0] + threadIdx.x; node < c1; node += kEmitThreads) {
         // the rank whose chain holds node: the last local r with so[r] <= node
         int lo = 0, hi = kThreads;  // so[lo] <= node < so[hi]
         while (hi - lo > 1) {
@@ -1844,7 +1846,7 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     int32_t *lvl_list = (int32_t *)t->lvl_list.p;
     k_fill_u32<<<div_up(8 * (int64_t)m, kThreads), kThreads, 0, st>>>((uint32_t *)t->kids.p,
                                                                       8 * (int64_t)m, ~0u);
-    k_emit<<<nb, kThreads, 0, st>>>(ka, delta, offs, n, m, bsum, lb, (uint64_t *)t->hkey.p,
+    k_emit<<<nb, kEmitThreads, 0, st>>>(ka, delta, offs, n, m, bsum, lb, (uint64_t *)t->hkey.p,
                                     (int32_t *)t->level.p, (int32_t *)t->begin.p,
                                     (int32_t *)t->count.p, (int32_t *)t->next.p,
                                     (int32_t *)t->parent.p, (int32_t *)t->cx.p,

@@ -101,9 +101,9 @@ METHODS = {
     "body-theta-o3": [round(0.5 + 0.005 * k, 3) for k in range(81)],
     "group-theta-o3": [round(0.6 + 0.00625 * k, 5) for k in range(73)],
     # the budget with monopole terms (the dropped quadrupole's bound charged)
-    "group-budget-mono": [round(-3.0 + 0.03125 * k, 5) for k in range(57)],  # log10 tau
+    "group-budget-mono": [round(-4.0 + 0.03125 * k, 5) for k in range(89)],  # log10 tau
     # the mixed order (monopole or quadrupole per cell)
-    "group-budget-mixed": [round(-3.0 + 0.03125 * k, 5) for k in range(57)],  # log10 tau
+    "group-budget-mixed": [round(-4.0 + 0.03125 * k, 5) for k in range(89)],  # log10 tau
 }
 # the same methods over bodies sorted along the Peano-Hilbert curve
 for _m in ("body-theta", "group-theta", "group-budget", "group-budget-mono",
@@ -161,9 +161,9 @@ def parse():
     ap.add_argument("--leaf", type=int, default=None, help="override the leaf capacity")
     ap.add_argument("--theta", type=float, default=None,
                     help="per-body walk: skip the sweep and use this theta")
-    ap.add_argument("--method", choices=list(METHODS),
-                    default=None, help="time only this method (default: the fastest at the "
-                    "target error)")
+    ap.add_argument("--method", default=None,
+                    help="calibrate only this method, or a comma-separated list of them, and "
+                    "time the fastest (default: all of " + ", ".join(METHODS) + ")")
     ap.add_argument("--target-err", type=float, default=1e-3)
     ap.add_argument("--acc-floor", type=float, default=ACC_FLOOR,
                     help="budget criteria: |a_i| floored at this fraction of the mean |a|")
@@ -292,7 +292,10 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    names = list(METHODS) if args.method is None else [args.method]
+    names = list(METHODS) if args.method is None else args.method.split(",")
+    for k in names:
+        if k not in METHODS:
+            raise SystemExit(f"unknown method {k!r}; choose from {', '.join(METHODS)}")
     # the same bodies sorted along the Peano-Hilbert curve
     tree_h = None
     if any(hilbert(k) for k in names):

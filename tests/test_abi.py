@@ -35,6 +35,7 @@ def test_version_and_defaults():
     assert o.mlp_theta_max == 1.0 and o.mlp_log10_tau == -3.0 and o.mlp_theta_est == 0.8
     assert o.mlp_acc_norm is None and o.mlp_acc_floor == 0.0
     assert o.mlp_precision == B.BH_MLP_BF16
+    assert o.n_pq is None
 
 
 def test_null_handles_rejected():
@@ -69,6 +70,8 @@ def test_null_handles_rejected():
     assert lib.bh_mlp_grad(None, None, None, 1, 0.0, None, None) == B.BH_E_INVALID
     assert lib.bh_mlp_infer(None, None, 1, B.BH_MLP_BF16, None) == B.BH_E_INVALID
     assert lib.bh_sim_timing_get(None, None, None) == B.BH_E_INVALID
+    assert lib.bh_sim_counts_get(None, None, None) == B.BH_E_INVALID
+    assert lib.bh_sim_counts_pq_get(None, None) == B.BH_E_INVALID
 
 
 def test_build_argument_checks_precede_device_use():
@@ -111,6 +114,12 @@ def test_force_parameter_checks_precede_device_use():
         assert "learned-criterion" in B.bh_last_error()
     o = B.force_opts(mac=B.BH_MAC_MLP, mlp_precision=2)
     assert lib.bh_forces(t, 0.5, 0.0, acc, C.byref(o)) == B.BH_E_INVALID
+    # the mixed order runs with the error budget only; order 4 does not exist
+    for mac, order in ((B.BH_MAC_THETA, B.BH_ORDER_MIXED), (B.BH_MAC_MLP, B.BH_ORDER_MIXED),
+                       (B.BH_MAC_BUDGET, 4)):
+        o = B.force_opts(mac=mac, order=order)
+        assert lib.bh_forces(t, 0.5, 0.0, acc, C.byref(o)) == B.BH_E_INVALID
+        assert "order" in B.bh_last_error()
     ctx = C.c_void_p(C.addressof(dummy))
     assert lib.bh_mlp_infer(ctx, acc, 1, 2, acc) == B.BH_E_INVALID
     assert "precision" in B.bh_last_error()

@@ -82,6 +82,9 @@ sys.path.insert(0, ROOT)
 METRIC = "body-cell interactions/s and bodies/s force eval at rms rel force err 1e-3"
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# VALU issue: 256 CUs x 4 SIMDs, a wavefront instruction every four cycles
+# on a SIMD (16 lanes), 2.4 GHz
+VALU_SIMDS, VALU_CYCLES_PER_INSTR, CLOCK_HZ = 1024, 4, 2.4e9
 # algorithmic FLOPs per interaction: particle-particle 20; particle-cell 20
 # (monopole), 60 (monopole + quadrupole) or 125 (and octopole: its contraction
 # with x x costs 39, the rest of the term 26)
@@ -494,6 +497,7 @@ def main():
             "frac": achieved_tf / PEAK_FP32_TFLOPS,
             "traffic": traffic_for(kernel, result_workload(cfg, n), chosen),
             "flop_per_launch": flops, "launch_ms": walk_kernel_ms,
+            "valu_issue": valu_issue_for(kernel, result_workload(cfg, n), chosen, walk_kernel_ms),
         },
     }
 
@@ -640,6 +644,29 @@ def traffic_for(kernel, workload, method):
             or k.get("method") != method):
         return None
     return k["hbm_bytes_per_launch"]
+
+
+def valu_issue_for(kernel, workload, method, launch_ms):
+    """The walk kernel's wavefront VALU instructions per launch from the
+    committed rocprofv3 counter summary (same workload, method and walk
+    source, else None), and the time they take at one instruction per four
+    cycles on every SIMD, against the launch's measured time."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "walk_valu.json")
+    src = os.path.join(ROOT, "paper_2203_08966_amd", "csrc", "walk.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if (not k or rec.get("walk_hip_sha256") != sha or rec.get("workload") != workload
+            or k.get("method") != method):
+        return None
+    v = k["valu_instr_per_launch"]
+    ms = v * VALU_CYCLES_PER_INSTR / VALU_SIMDS / CLOCK_HZ * 1e3
+    return {"valu_instr_per_launch": v, "ms_at_4_cycles_per_instr": ms,
+            "launch_ms": launch_ms, "issue_frac": ms / launch_ms}
 
 
 def cpu_model() -> str:

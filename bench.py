@@ -16,8 +16,8 @@ over a seeded 4096-body subsample:
   group-theta   one opening-angle decision per wavefront of 64 bodies;
   group-budget  one error-budget decision per wavefront (error model
                 M l^3 / d_g^5 against tau times the group's smallest |a|,
-                each |a_i| floored at half the mean |a|, 0.3 of it with
-                monopole terms);
+                each |a_i| floored at half the mean |a|, 0.3 of it for
+                the monopole terms over Hilbert groups);
   group-learned one learned decision per wavefront and cell: the network's
                 predicted error of the particle-cell term on the group
                 against the same budget (bf16 MFMA inside the walk),
@@ -142,17 +142,17 @@ def base_of(method):
     return method[:-len("-hilbert")] if hilbert(method) else method
 BUDGET_THETA_MAX = 1.5
 # |a_i| in the budget tests is max(|a_i|, f <|a|>): f = 0.3 for the budget
-# with monopole terms, 0.5 for the others (each the faster at rms 1e-3 on
-# the 2^22 Plummer sphere)
+# with monopole terms over Hilbert groups, 0.5 for the others (each the
+# faster at rms 1e-3 on the 2^22 Plummer sphere)
 ACC_FLOOR = 0.5
-ACC_FLOOR_MONO = 0.3
+ACC_FLOOR_MONO_HILBERT = 0.3
 
 
 def acc_floor_of(method, override=None):
     """The |a| floor of a budget method (``override`` if given)."""
     if override is not None:
         return override
-    return ACC_FLOOR_MONO if "-mono" in method else ACC_FLOOR
+    return ACC_FLOOR_MONO_HILBERT if method == "group-budget-mono-hilbert" else ACC_FLOOR
 # steps after the timed ones that record the per-phase HIP events
 PHASE_STEPS = 20
 # fixed opening angles the per-body walk is also reported at
@@ -181,7 +181,8 @@ def parse():
     ap.add_argument("--target-err", type=float, default=1e-3)
     ap.add_argument("--acc-floor", type=float, default=None,
                     help="budget criteria: |a_i| floored at this fraction of the mean |a| "
-                    f"(default {ACC_FLOOR_MONO} with monopole terms, else {ACC_FLOOR})")
+                    f"(default {ACC_FLOOR_MONO_HILBERT} for group-budget-mono-hilbert, else "
+                    f"{ACC_FLOOR})")
     ap.add_argument("--theta-max", type=float, default=BUDGET_THETA_MAX,
                     help="budget criteria: cells above this opening angle are opened")
     ap.add_argument("--walk-cap", type=int, default=0,
@@ -271,6 +272,7 @@ def main():
     def opts_of(method, p, counters=False, for_sim=False):
         kw = dict(order=order_of(method), n_pp=npp if counters else None,
                   n_pc=npc if counters else None)
+        floor = acc_floor_of(method, args.acc_floor)
         method = base_of(method)
         if method == "body-theta-guard":
             kw.update(mac=B.BH_MAC_THETA_GUARD)
@@ -281,8 +283,7 @@ def main():
             kw.update(walk=B.BH_WALK_GROUP, walk_cap=args.walk_cap, mlp_precision=mlp_precision,
                       mac=B.BH_MAC_MLP if method == "group-learned" else B.BH_MAC_BUDGET,
                       mlp_log10_tau=p, mlp_theta_max=args.theta_max,
-                      mlp_acc_norm=None if for_sim else anorm,
-                      mlp_acc_floor=acc_floor_of(method, args.acc_floor))
+                      mlp_acc_norm=None if for_sim else anorm, mlp_acc_floor=floor)
         return B.force_opts(**kw)
 
     def walk(method, p, counters=False):

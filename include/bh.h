@@ -195,8 +195,9 @@ void bh_force_opts_default(bh_force_opts *opts);
 int bh_ctx_create(int device, void *stream, bh_ctx **out);
 int bh_ctx_set_stream(bh_ctx *ctx, void *stream);
 
-/* The curve that later builds of this context (bh_build, bh_sim_init and
- * every simulation step) sort the bodies along.  BH_CURVE_HILBERT: the
+/* The curve that later builds of this context (bh_build, bh_sim_init) sort
+ * the bodies along.  A simulation keeps the curve of its bh_sim_init for
+ * every rebuild of its steps, whatever this is set to later.  BH_CURVE_HILBERT: the
  * 63-bit key is the Peano-Hilbert index of the same 21-bit integer point
  * (Butz's construction: axis x in bit 0 of each level's three bits; the
  * curve starts at the cube's corner lo).  A prefix of k octal digits of

@@ -288,7 +288,7 @@ int bh_build(bh_ctx *c, const void *pos, const void *mass, int dtype, int64_t n,
         t = new bh_tree;
         t->ctx = c;
     }
-    rc = build_tree(c, t, pos, mass, dtype, n, leaf, nullptr, nullptr, nullptr, nullptr,
+    rc = build_tree(c, t, c->curve, pos, mass, dtype, n, leaf, nullptr, nullptr, nullptr, nullptr,
                     nullptr, nullptr, false);
     if (rc) {
         if (fresh) {
@@ -441,8 +441,8 @@ static int sim_forces(bh_ctx *c, bool want_phi) {
 static int sim_rebuild(bh_ctx *c, const void *pos, const void *vel, const void *mass,
                        const uint32_t *id, bool presorted) {
     SimState *s = c->sim;
-    int rc = build_tree(c, c->sim_tree, pos, mass, s->dtype, s->n, s->leaf, vel, id, s->pos2.p,
-                        s->vel2.p, s->mass2.p, (uint32_t *)s->id2.p, presorted);
+    int rc = build_tree(c, c->sim_tree, s->curve, pos, mass, s->dtype, s->n, s->leaf, vel, id,
+                        s->pos2.p, s->vel2.p, s->mass2.p, (uint32_t *)s->id2.p, presorted);
     if (rc) return rc;
     std::swap(s->pos, s->pos2);
     std::swap(s->vel, s->vel2);
@@ -481,6 +481,7 @@ int bh_sim_init(bh_ctx *c, const void *pos, const void *vel, const void *mass, i
     s->dtype = dtype;
     s->n = n;
     s->leaf = leaf;
+    s->curve = c->curve;
     s->theta = theta;
     s->eps = eps;
     s->opts = o;

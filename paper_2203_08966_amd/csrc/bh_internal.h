@@ -165,6 +165,7 @@ struct SimState {
     int dtype = BH_F32;
     int64_t n = 0;
     int leaf = 16;
+    int curve = BH_CURVE_MORTON;               // every rebuild's curve, fixed at init
     double theta = 0.5, eps = 0.0;
     bh_force_opts opts{};
     DevBuf pos, vel, mass, acc, phi, id;       // key order (current)
@@ -188,9 +189,9 @@ int check_launch(const char *what);
 // (simulation), they are permuted alongside into vel_out/id_out.
 // presorted: the bodies come in the order of this tree's previous build (a
 // simulation step), which allows the nearly sorted re-sort
-int build_tree(bh_ctx *ctx, bh_tree *t, const void *pos, const void *mass, int dtype,
-               int64_t n, int leaf, const void *vel, const uint32_t *id, void *pos_out,
-               void *vel_out, void *mass_out, uint32_t *id_out, bool presorted);
+int build_tree(bh_ctx *ctx, bh_tree *t, int curve, const void *pos, const void *mass,
+               int dtype, int64_t n, int leaf, const void *vel, const uint32_t *id,
+               void *pos_out, void *vel_out, void *mass_out, uint32_t *id_out, bool presorted);
 
 // Octopole records of the tree (order-3 walks), computed on first use per
 // build: 8 values of the tree's dtype per node (see build.hip).

@@ -1699,7 +1699,7 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
                                                      : (uint64_t *)t->keys_a.p;
     uint64_t *kother = knew == (uint64_t *)t->keys_a.p ? (uint64_t *)t->keys_b.p
                                                        : (uint64_t *)t->keys_a.p;
-    k_keys<T><<<nkeys, kKeyThreads, 0, st>>>(pos, n, cube, knew, hist, ctx->curve);
+    k_keys<T><<<nkeys, kKeyThreads, 0, st>>>(pos, n, cube, knew, hist, t->curve);
     k_hist_scan<<<8, 256, 0, st>>>(hist, doff, tile_ctr);
     // one radix sort of n (key, index) pairs, 8 passes of 8 bits: from (ka,
     // va) (va NULL: the input positions), through (kb, vb), ending in (ka,
@@ -1851,7 +1851,7 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
                                     (int32_t *)t->count.p, (int32_t *)t->next.p,
                                     (int32_t *)t->parent.p, (int32_t *)t->cx.p,
                                     (int32_t *)t->cy.p, (int32_t *)t->cz.p, lvl_list, ucnt,
-                                    (int32_t *)t->kids.p, ctx->curve);
+                                    (int32_t *)t->kids.p, t->curve);
     UpArgs ua;
     ua.m = m;
     ua.kids = (const int4 *)t->kids.p;
@@ -1924,18 +1924,19 @@ int ensure_octopole(bh_tree *t) {
     return BH_OK;
 }
 
-int build_tree(bh_ctx *ctx, bh_tree *t, const void *pos, const void *mass, int dtype,
-               int64_t n, int leaf, const void *vel, const uint32_t *id, void *pos_out,
-               void *vel_out, void *mass_out, uint32_t *id_out, bool presorted) {
-    // the nearly sorted re-sort needs this tree's previous build (same n)
-    // complete: its sorted keys and its leaves
+int build_tree(bh_ctx *ctx, bh_tree *t, int curve, const void *pos, const void *mass,
+               int dtype, int64_t n, int leaf, const void *vel, const uint32_t *id,
+               void *pos_out, void *vel_out, void *mass_out, uint32_t *id_out, bool presorted) {
+    // the nearly sorted re-sort needs this tree's previous build (same n,
+    // same curve) complete: its sorted keys and its leaves
     const bool resort = presorted && ctx->sort_mode == BH_SORT_ADAPTIVE && t->resort_ok &&
-                        t->n == n && t->m > 0 && t->sorted_keys != nullptr;
+                        t->n == n && t->curve == curve && t->m > 0 &&
+                        t->sorted_keys != nullptr;
     t->resort_ok = false;
     t->dtype = dtype;
     t->n = n;
     t->leaf = leaf;
-    t->curve = ctx->curve;
+    t->curve = curve;
     t->build_id++;
     int rc;
     if (dtype == BH_F32)

@@ -118,6 +118,26 @@ def test_hilbert_simulation_follows_morton(ctx):
     assert np.sqrt(np.mean(ea ** 2)) < 1e-5
 
 
+def test_simulation_keeps_its_curve(ctx):
+    """The curve set when the simulation starts sorts every later rebuild
+    of its steps, whatever the context's curve is set to afterwards."""
+    pos, vel, mass = case_bodies("plummer", 5000, 6, np.float32)
+    P, V, M = (torch.from_numpy(x).cuda() for x in (pos, vel, mass))
+    for curve, other in ((B.BH_CURVE_HILBERT, B.BH_CURVE_MORTON),
+                         (B.BH_CURVE_MORTON, B.BH_CURVE_HILBERT)):
+        B.bh_ctx_set_curve(ctx, curve)
+        B.bh_sim_init(ctx, P, V, M, 16, 0.5, 0.005, B.force_opts())
+        B.bh_ctx_set_curve(ctx, other)
+        try:
+            for _ in range(2):
+                B.bh_leapfrog_step(ctx, 1e-3)
+            info = B.bh_tree_info_get(B.bh_sim_tree(ctx))
+            torch.cuda.synchronize()
+        finally:
+            B.bh_ctx_set_curve(ctx, B.BH_CURVE_MORTON)
+        assert int(info["curve"]) == curve
+
+
 def test_curve_is_checked(ctx):
     with pytest.raises(B.BHError) as e:
         B.bh_ctx_set_curve(ctx, 2)

@@ -358,11 +358,16 @@ def test_default_work_cap_by_criterion(ctx):
     B.bh_tree_free(t)
 
 
-def test_timed_path_budget_steps_match_oracle(ctx):
+@pytest.mark.parametrize("curve,order,fl,log_tau", [
+    ("morton", 2, 0.5, -1.75),
+    ("hilbert", 0, 0.3, -2.0),   # the budget with monopole terms over Hilbert groups
+])
+def test_timed_path_budget_steps_match_oracle(ctx, curve, order, fl, log_tau):
     """The path the benchmark times: leapfrog steps with the group
-    error-budget walk, |a_i| floored at half the mean and taken from the
-    previous step, a work cap, and the per-body predictions the steps carry
-    from walk to walk.  Steps of dt = 0 keep the bodies in place (so every
+    error-budget walk (quadrupole terms over Morton groups, or monopole
+    terms over Hilbert groups), |a_i| floored at a fraction of the mean and
+    taken from the previous step, a work cap, and the per-body predictions
+    the steps carry from walk to walk.  Steps of dt = 0 keep the bodies in place (so every
     input of the oracle is the host's), while each step still rebuilds the
     tree in place, walks with the previous accelerations and kicks.  The
     oracle runs the same chain with its own accelerations: an estimate by a
@@ -374,15 +379,20 @@ def test_timed_path_budget_steps_match_oracle(ctx):
     one (a flipped decision changes that body's |a_i|, and with it its
     group's next decisions)."""
     n, eps, leaf, cap, steps = 20000, 0.005, 16, 2000, 4
-    tau, tmax, fl, test = 10 ** -1.75, 1.5, 0.5, 0.8
+    tau, tmax, test = 10 ** log_tau, 1.5, 0.8
     pos, vel, mass = case_bodies("plummer", n, 19, np.float32)
     P, V, M = (torch.from_numpy(a).cuda() for a in (pos, vel, mass))
-    o = B.force_opts(walk=B.BH_WALK_GROUP, mac=B.BH_MAC_BUDGET, walk_cap=cap,
+    o = B.force_opts(walk=B.BH_WALK_GROUP, mac=B.BH_MAC_BUDGET, order=order, walk_cap=cap,
                      mlp_log10_tau=np.log10(tau), mlp_theta_max=tmax, mlp_acc_floor=fl,
                      mlp_theta_est=test)
-    say(f"timed path: {n} bodies, group budget walk, cap {cap}, {steps} steps of dt 0")
-    B.bh_sim_init(ctx, P, V, M, leaf, 0.5, eps, o)
-    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), leaf)
+    say(f"timed path: {n} bodies, group budget walk of order {order} over {curve} groups, "
+        f"cap {cap}, {steps} steps of dt 0")
+    B.bh_ctx_set_curve(ctx, B.BH_CURVE_HILBERT if curve == "hilbert" else B.BH_CURVE_MORTON)
+    try:
+        B.bh_sim_init(ctx, P, V, M, leaf, 0.5, eps, o)
+    finally:
+        B.bh_ctx_set_curve(ctx, B.BH_CURVE_MORTON)
+    ref = oracle.build_all(pos.astype(np.float64), mass.astype(np.float64), leaf, curve=curve)
     p = ref["perm"]
     kc = oracle.cell_kc(ref)
     G = B.BH_GROUP_BODIES
@@ -391,7 +401,7 @@ def test_timed_path_budget_steps_match_oracle(ctx):
     anorm = np.linalg.norm(est.acc, axis=1)
     exempt = est.flag != 0  # sorted order: bodies whose |a_i| may differ
     budget = dict(group=G, mode=1, theta_max=tmax, tau=tau, kc=kc, floor=fl, cap=cap,
-                  split=True, tol=FLAG_TOL[np.float32])
+                  split=True, tol=FLAG_TOL[np.float32], order=order)
     # groups over the cap (walked per body at once, then predicted for the
     # next steps) are part of this workload
     free = oracle.walk_group(ref, eps, anorm=anorm, **dict(budget, cap=NO_CAP))
@@ -407,7 +417,7 @@ def test_timed_path_budget_steps_match_oracle(ctx):
         torch.cuda.synchronize()
         a = a.cpu().numpy().astype(np.float64)[p]
         rg = oracle.walk_group(ref, eps, anorm=anorm, **budget)
-        rb = oracle.walk_kc(ref, eps, tmax, tau, kc, anorm, floor=fl)
+        rb = oracle.walk_kc(ref, eps, tmax, tau, kc, anorm, floor=fl, order=order)
 
         def close(r):
             e = np.linalg.norm(a - r.acc, axis=1) / np.linalg.norm(r.acc, axis=1)

@@ -362,10 +362,12 @@ def test_learned_walk_state_and_args(ctx):
     B.bh_tree_free(t)
 
 
-def test_budget_leapfrog_matches_oracle(ctx):
-    """KDK with the error-budget criterion: the initial forces take |a_i| from
-    a monopole walk at theta_est, every later step from the previous step's
-    accelerations.  The oracle runs the same recipe in FP64."""
+@pytest.mark.parametrize("order", [2, 0, B.BH_ORDER_MIXED])
+def test_budget_leapfrog_matches_oracle(ctx, order):
+    """KDK with the error-budget criterion (quadrupole terms, monopole terms
+    or the mixed order): the initial forces take |a_i| from a monopole walk
+    at theta_est, every later step from the previous step's accelerations.
+    The oracle runs the same recipe in FP64."""
     pos, vel, mass = case_bodies("plummer", 8192, 7, np.float32)
     eps, tau, test, dt, steps, leaf = 0.005, 1e-3, 0.8, 5e-4, 4, 16
     p64, v64, m64 = (a.astype(np.float64) for a in (pos, vel, mass))
@@ -379,17 +381,17 @@ def test_budget_leapfrog_matches_oracle(ctx):
             an = np.linalg.norm(w0.acc, axis=1)
         else:
             an = np.linalg.norm(state["prev"], axis=1)[ref["perm"]]
-        r = oracle.walk_kc(ref, eps, 1.0, tau, oracle.cell_kc(ref), an)
+        r = oracle.walk_kc(ref, eps, 1.0, tau, oracle.cell_kc(ref), an, order=order)
         acc = np.empty_like(r.acc)
         acc[ref["perm"]] = r.acc
         state["prev"] = acc
         return acc
 
-    say(f"budget leapfrog: 8192 bodies, {steps} steps, vs FP64 oracle")
+    say(f"budget leapfrog, order {order}: 8192 bodies, {steps} steps, vs FP64 oracle")
     xo, vo, ao = oracle.kdk(p64, v64, m64, dt, steps, force)
     P, V, M = (torch.from_numpy(a).cuda() for a in (pos, vel, mass))
     B.bh_sim_init(ctx, P, V, M, leaf, 0.5, eps,
-                  B.force_opts(mac=B.BH_MAC_BUDGET, mlp_log10_tau=np.log10(tau),
+                  B.force_opts(mac=B.BH_MAC_BUDGET, order=order, mlp_log10_tau=np.log10(tau),
                                mlp_theta_est=test))
     for _ in range(steps):
         B.bh_leapfrog_step(ctx, dt)

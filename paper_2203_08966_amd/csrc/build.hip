@@ -247,25 +247,6 @@ __device__ __forceinline__ uint64_t hilbert3_tab(uint32_t qx, uint32_t qy, uint3
     }
     return h;
 }
-// The inverse: the integer point of a 63-bit Peano-Hilbert index.
-__device__ __forceinline__ void hilbert3_point(uint64_t h, uint32_t &qx, uint32_t &qy,
-                                               uint32_t &qz) {
-    uint32_t e = 0, d = 0;
-    qx = qy = qz = 0;
-#pragma unroll
-    for (int i = kLevels - 1; i >= 0; --i) {
-        const uint32_t w = (uint32_t)(h >> (3 * i)) & 7u;
-        const uint32_t l = rot3l(w ^ (w >> 1), d == 2 ? 0u : d + 1u) ^ e;
-        qx |= (l & 1u) << i;
-        qy |= ((l >> 1) & 1u) << i;
-        qz |= ((l >> 2) & 1u) << i;
-        e ^= rot3l((kHbEntry >> (3u * w)) & 7u, d == 2 ? 0u : d + 1u);
-        d += ((kHbAxis >> (2u * w)) & 3u) + 1u;
-        d = d >= 3u ? d - 3u : d;
-        d = d >= 3u ? d - 3u : d;
-    }
-}
-
 __device__ __forceinline__ uint32_t quantise(double x, double lo, double scale) {
     double t = __dmul_rn(__dsub_rn(x, lo), scale);
     double f = floor(t);
@@ -809,46 +790,63 @@ __global__ __launch_bounds__(kThreads) void k_chain(const uint64_t *__restrict__
                                                     int B, int8_t *__restrict__ delta,
                                                     uint8_t *__restrict__ ns,
                                                     uint32_t *__restrict__ bsum) {
-    __shared__ int8_t sd[kThreads + 2 * (kMaxLeaf + 1) + 1];
+    constexpr int kSd = kThreads + 2 * (kMaxLeaf + 1) + 1;
+    __shared__ int8_t sd[kSd], ta[kSd], tb[kSd];
     __shared__ uint32_t ws[kThreads / 64];
     __shared__ uint32_t lh[kLevels + 1];
     const int H = B + 1;
+    const int NS = kThreads + 2 * H + 1;  // sd entries in use
     if (threadIdx.x <= kLevels) lh[threadIdx.x] = 0;
     const int b0 = blockIdx.x * kThreads;
-    // sd[k] = delta[b0 - H + k]
-    for (int k = threadIdx.x; k < kThreads + 2 * H + 1; k += kThreads)
+    // sd[k] = delta[b0 - H + k] (-1 outside [1, n))
+    for (int k = threadIdx.x; k < NS; k += kThreads)
         sd[k] = (int8_t)key_delta(keys, n, b0 - H + k);
     __syncthreads();
+    // The level-ds cell around s (ds = delta[s]) holds more than B bodies iff
+    // some B + 1 consecutive ranks around s all lie in it, i.e. iff the
+    // largest over p in [s - B, s] of W(p) = min(delta[p+1 .. p+B]) is at
+    // least ds; and the chain of s ends at level max(ds, W(s)) + 1.  Both
+    // windows by doubling tables in LDS (ta, tb alternate; sd is kept).
+    const int8_t *src = sd;
+    int8_t *dst = ta;
+    int w = 1;
+    for (; 2 * w <= B; w *= 2) {  // src[i] = min(sd[i .. i + 2w - 1])
+        for (int i = threadIdx.x; i + 2 * w <= NS; i += kThreads) {
+            const int8_t x = src[i], y = src[i + w];
+            dst[i] = x < y ? x : y;
+        }
+        __syncthreads();
+        src = dst;
+        dst = dst == ta ? tb : ta;
+    }
+    for (int q = threadIdx.x; q + B < NS; q += kThreads) {  // dst[q] = W at local q
+        const int8_t x = src[q + 1], y = src[q + 1 + B - w];
+        dst[q] = x < y ? x : y;
+    }
+    __syncthreads();
     const int s = b0 + threadIdx.x;
-    if (s < n) delta[s] = sd[threadIdx.x + H];
+    const int L = threadIdx.x + H;  // local index of s
+    const int ds = sd[L];
+    const int mu = dst[L];  // min(delta[s+1 .. s+B]), -1 past the last rank
+    src = dst;
+    dst = dst == ta ? tb : ta;
+    for (w = 1; 2 * w <= B + 1; w *= 2) {  // src[i] = max(W over [i, i + 2w - 1])
+        for (int i = threadIdx.x; i + 2 * w <= NS; i += kThreads) {
+            const int8_t x = src[i], y = src[i + w];
+            dst[i] = x > y ? x : y;
+        }
+        __syncthreads();
+        src = dst;
+        dst = dst == ta ? tb : ta;
+    }
+    if (s < n) delta[s] = (int8_t)ds;
     if (s == n - 1) delta[n] = -1;
     uint32_t cnt_s = 0;
     if (s < n) {
-        const int L = threadIdx.x + H;  // local index of s
-        const int ds = sd[L];
         if (ds < kLevels) {
-            bool exists = (s == 0);
-            if (!exists) {
-                int cnt = 1;
-                int j = L;
-                while (cnt <= B && sd[j] >= ds) {  // delta[j] >= ds: rank j-1 inside
-                    ++cnt;
-                    --j;
-                }
-                j = L + 1;
-                while (cnt <= B && sd[j] >= ds) {  // delta[j] >= ds: rank j inside
-                    ++cnt;
-                    ++j;
-                }
-                exists = cnt > B;
-            }
+            const int e0 = src[L - B], e1 = src[L + 1 - w];
+            const bool exists = s == 0 || (e0 > e1 ? e0 : e1) >= ds;
             if (exists) {
-                int mu = kLevels;
-                for (int j = 1; j <= B; ++j) {
-                    const int v = sd[L + j];
-                    mu = v < mu ? v : mu;
-                    if (s + j >= n) break;
-                }
                 int kl = ds + 1 > mu + 1 ? ds + 1 : mu + 1;
                 kl = kl > kLevels ? kLevels : kl;
                 cnt_s = (uint32_t)(kl - ds);
@@ -870,34 +868,60 @@ __global__ __launch_bounds__(kThreads) void k_chain(const uint64_t *__restrict__
 }
 
 // Exclusive scan, in place, of each of gridDim.x segments of nb per-block
-// sums (one block per segment); the segment total goes to tot[segment].
+// sums (one block of 1024 threads per segment); the segment total goes to
+// tot[segment].  Chunks of 8192 sums: loaded coalesced into LDS, eight
+// consecutive sums scanned per thread, the thread totals across the block,
+// then stored coalesced (one chunk covers 2^21 bodies' block sums, so the
+// block's chain of dependent steps stays short).
+constexpr int kScanPer = 8;
+constexpr int kScanChunk = 1024 * kScanPer;
 __global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *__restrict__ sums, int nb,
                                                     uint32_t *__restrict__ tot) {
-    __shared__ uint32_t carry;
+    __shared__ uint32_t buf[kScanChunk];
     __shared__ uint32_t ws[16];
     uint32_t *s = sums + (size_t)blockIdx.x * nb;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int c0 = 0; c0 < nb; c0 += 1024) {
-        const int i = c0 + threadIdx.x;
-        const uint32_t x = i < nb ? s[i] : 0u;
-        uint32_t incl = x;
-        const unsigned lane = lane_id();
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t v = __shfl_up(incl, o);
-            if ((int)lane >= o) incl += v;
+    const int t = threadIdx.x;
+    const unsigned lane = lane_id();
+    const int w = t / 64;
+    uint32_t carry = 0;  // the same in every thread: the previous chunks' total
+    for (int c0 = 0; c0 < nb; c0 += kScanChunk) {
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const int i = c0 + k * 1024 + t;
+            buf[k * 1024 + t] = i < nb ? s[i] : 0u;
         }
-        const int w = threadIdx.x / 64;
+        __syncthreads();
+        uint32_t v[kScanPer];
+        uint32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            v[k] = run;
+            run += buf[t * kScanPer + k];
+        }
+        uint32_t incl = run;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t x = __shfl_up(incl, o);
+            if ((int)lane >= o) incl += x;
+        }
         if (lane == 63) ws[w] = incl;
         __syncthreads();
-        uint32_t pre = carry;
-        for (int k = 0; k < w; ++k) pre += ws[k];
-        if (i < nb) s[i] = pre + incl - x;
+        uint32_t pre = carry + incl - run, ctot = 0;
+        for (int k = 0; k < 16; ++k) {
+            pre += k < w ? ws[k] : 0u;
+            ctot += ws[k];
+        }
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) buf[t * kScanPer + k] = pre + v[k];
         __syncthreads();
-        if (threadIdx.x == 1023) carry = pre + incl;
-        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const int i = c0 + k * 1024 + t;
+            if (i < nb) s[i] = buf[k * 1024 + t];
+        }
+        carry += ctot;
+        __syncthreads();  // buf and ws are refilled by the next chunk
     }
-    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+    if (t == 0) tot[blockIdx.x] = carry;
 }
 
 // offs[s] = exclusive prefix of ns over ranks; offs[n] = node count.
@@ -974,10 +998,16 @@ struct LevelBase {
 // Block b places its level-k cells after those of blocks < b (scanned
 // per-block level counts in lvl_pre[(1 + k) * nb + b]).  A block is one
 // wavefront: 256 ranks hold about 60 cells (one per 4 to 5 bodies at
-// leaf capacity 16), which then keep its lanes busy.
+// leaf capacity 16), which then keep its lanes busy.  A cell's integer
+// centre comes from the integer point of its first body: under the Morton
+// curve the key's bits, under the Peano-Hilbert curve the body's sorted
+// position quantised as its key was (the same bits as inverting the key,
+// at a fraction of the cost).
 constexpr int kEmitThreads = 64;
+template <typename T>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
-    const uint64_t *__restrict__ keys, const int8_t *__restrict__ delta,
+    const uint64_t *__restrict__ keys, const T *__restrict__ spos,
+    const Cube *__restrict__ cube, const int8_t *__restrict__ delta,
     const int32_t *__restrict__ offs, int n, int m,
     const uint32_t *__restrict__ lvl_pre, LevelBase lb, uint64_t *__restrict__ hkey,
     int32_t *__restrict__ level, int32_t *__restrict__ begin, int32_t *__restrict__ count,
@@ -1001,6 +1031,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     }
     __syncthreads();
     const int c1 = so[kThreads] < m ? so[kThreads] : m;
+    const double lx = cube->lo[0], ly = cube->lo[1], lz = cube->lo[2];
+    const double scale = ldexp(1.0, kLevels) / cube->L;
     for (int node = so[0] + threadIdx.x; node < c1; node += kEmitThreads) {
         // the rank whose chain holds node: the last local r with so[r] <= node
         int lo = 0, hi = kThreads;  // so[lo] <= node < so[hi]
@@ -1031,7 +1063,10 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
         // the same cube); its centre from the integer point of body s
         uint32_t qx, qy, qz;
         if (curve == BH_CURVE_HILBERT) {
-            hilbert3_point(key, qx, qy, qz);
+            const int64_t b = 3 * (int64_t)s;
+            qx = quantise((double)spos[b + 0], lx, scale);
+            qy = quantise((double)spos[b + 1], ly, scale);
+            qz = quantise((double)spos[b + 2], lz, scale);
         } else {
             qx = compact3(key >> 2);
             qy = compact3(key >> 1);
@@ -1846,7 +1881,8 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     int32_t *lvl_list = (int32_t *)t->lvl_list.p;
     k_fill_u32<<<div_up(8 * (int64_t)m, kThreads), kThreads, 0, st>>>((uint32_t *)t->kids.p,
                                                                       8 * (int64_t)m, ~0u);
-    k_emit<<<nb, kEmitThreads, 0, st>>>(ka, delta, offs, n, m, bsum, lb, (uint64_t *)t->hkey.p,
+    k_emit<T><<<nb, kEmitThreads, 0, st>>>(ka, pos_out, cube, delta, offs, n, m, bsum, lb,
+                                           (uint64_t *)t->hkey.p,
                                     (int32_t *)t->level.p, (int32_t *)t->begin.p,
                                     (int32_t *)t->count.p, (int32_t *)t->next.p,
                                     (int32_t *)t->parent.p, (int32_t *)t->cx.p,

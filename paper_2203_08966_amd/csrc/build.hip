@@ -219,9 +219,6 @@ __device__ __forceinline__ uint32_t hb_step(uint32_t s, uint32_t l, uint32_t &w)
     d = d >= 3u ? d - 3u : d;
     return 3u * e + d;
 }
-__device__ __forceinline__ uint32_t hb_bits(uint32_t qx, uint32_t qy, uint32_t qz, int i) {
-    return ((qx >> i) & 1u) | (((qy >> i) & 1u) << 1) | (((qz >> i) & 1u) << 2);
-}
 // Two levels per lookup: entry 64 s + (l_hi << 3 | l_lo) of this table
 // holds the two digits (6 bits) and the state after them (bits 6..10), for
 // the 24 states; filled by the threads of a workgroup from hb_step.
@@ -236,12 +233,15 @@ __device__ __forceinline__ void hb_table_fill(uint16_t *tab, int t, int nt) {
 }
 __device__ __forceinline__ uint64_t hilbert3_tab(uint32_t qx, uint32_t qy, uint32_t qz,
                                                  const uint16_t *tab) {
+    // the point's three bits of every level i in bits 3i .. 3i + 2 (x in the
+    // lowest), so that two levels' bits are one 6-bit field
+    const uint64_t b = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
     uint32_t w;
-    uint32_t s = hb_step(0u, hb_bits(qx, qy, qz, kLevels - 1), w);  // the top level alone
+    uint32_t s = hb_step(0u, (uint32_t)(b >> (3 * (kLevels - 1))) & 7u, w);  // the top level alone
     uint64_t h = w;
 #pragma unroll
     for (int i = kLevels - 2; i > 0; i -= 2) {  // levels i and i - 1
-        const uint32_t v = tab[64u * s + ((hb_bits(qx, qy, qz, i) << 3) | hb_bits(qx, qy, qz, i - 1))];
+        const uint32_t v = tab[64u * s + ((uint32_t)(b >> (3 * (i - 1))) & 63u)];
         h = (h << 6) | (v & 63u);
         s = v >> 6;
     }
@@ -255,9 +255,10 @@ __device__ __forceinline__ uint32_t quantise(double x, double lo, double scale) 
     return (uint32_t)f;
 }
 
-// Keys, and the counts of every 8-bit digit of every key (8 x 256 bins):
-// a block histogram in LDS, added to the global one bin by bin.  Few large
-// blocks keep the global adds few.
+// Keys (pos not NULL: computed and stored; NULL: read), and (hist not
+// NULL) the counts of every 8-bit digit of every key (8 x 256 bins) that
+// the full radix sort takes: a block histogram in LDS, added to the global
+// one bin by bin.  Few large blocks keep the global adds few.
 constexpr int kKeyThreads = 1024;
 constexpr int kKeyBlocks = 256;
 template <typename T>
@@ -267,8 +268,9 @@ __global__ __launch_bounds__(kKeyThreads) void k_keys(const T *__restrict__ pos,
                                                       uint32_t *__restrict__ hist, int curve) {
     __shared__ uint32_t h[8][256];
     __shared__ uint16_t hb_tab[kHbTable];
-    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
-    if (curve == BH_CURVE_HILBERT) hb_table_fill(hb_tab, threadIdx.x, blockDim.x);
+    if (hist)
+        for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
+    if (pos && curve == BH_CURVE_HILBERT) hb_table_fill(hb_tab, threadIdx.x, blockDim.x);
     __syncthreads();
     const double lx = cube->lo[0], ly = cube->lo[1], lz = cube->lo[2];
     const double scale = ldexp(1.0, kLevels) / cube->L;
@@ -279,7 +281,9 @@ __global__ __launch_bounds__(kKeyThreads) void k_keys(const T *__restrict__ pos,
         const int i = it * stride + blockIdx.x * blockDim.x + threadIdx.x;
         const bool valid = i < n;
         uint64_t k = 0;
-        if (valid) {
+        if (valid && !pos) {
+            k = keys[i];
+        } else if (valid) {
             const int64_t b = 3 * (int64_t)i;
             const uint32_t qx = quantise((double)pos[b + 0], lx, scale),
                            qy = quantise((double)pos[b + 1], ly, scale),
@@ -288,6 +292,7 @@ __global__ __launch_bounds__(kKeyThreads) void k_keys(const T *__restrict__ pos,
                                           : (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
             keys[i] = k;
         }
+        if (!hist) continue;
         const uint64_t live = ballot(valid);
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
@@ -305,6 +310,7 @@ __global__ __launch_bounds__(kKeyThreads) void k_keys(const T *__restrict__ pos,
             if ((rem >> lane) & 1ull) atomicAdd(&h[p][d], 1u);
         }
     }
+    if (!hist) return;
     __syncthreads();
     for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) {
         const uint32_t v = (&h[0][0])[i];
@@ -1734,8 +1740,11 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
                                                      : (uint64_t *)t->keys_a.p;
     uint64_t *kother = knew == (uint64_t *)t->keys_a.p ? (uint64_t *)t->keys_b.p
                                                        : (uint64_t *)t->keys_a.p;
-    k_keys<T><<<nkeys, kKeyThreads, 0, st>>>(pos, n, cube, knew, hist, t->curve);
-    k_hist_scan<<<8, 256, 0, st>>>(hist, doff, tile_ctr);
+    // the all-key digit counts only for the full sort: a rebuild that tries
+    // the nearly sorted re-sort counts them only if it falls back
+    k_keys<T><<<nkeys, kKeyThreads, 0, st>>>(pos, n, cube, knew, resort ? nullptr : hist,
+                                             t->curve);
+    if (!resort) k_hist_scan<<<8, 256, 0, st>>>(hist, doff, tile_ctr);
     // one radix sort of n (key, index) pairs, 8 passes of 8 bits: from (ka,
     // va) (va NULL: the input positions), through (kb, vb), ending in (ka,
     // va) again (an even number of passes)
@@ -1816,9 +1825,13 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
             sorted = true;
         }
         // else: too many movers for the merge to pay; the full sort below
-        // uses the all-key histograms scanned above
+        // counts the all-key digit histograms first
     }
     if (!sorted) {
+        if (resort) {
+            k_keys<T><<<nkeys, kKeyThreads, 0, st>>>(nullptr, n, cube, knew, hist, t->curve);
+            k_hist_scan<<<8, 256, 0, st>>>(hist, doff, tile_ctr);
+        }
         t->perm = radix(knew, nullptr, kother, (uint32_t *)t->idx_b.p, (uint32_t *)t->idx_a.p, n,
                         doff);
         t->sorted_keys = knew;

@@ -218,7 +218,8 @@ int bh_ctx_set_sort(bh_ctx *ctx, int mode);
 /* Device memory from the caller's allocator (e.g. a framework's caching
  * allocator) instead of hipMalloc.  alloc(bytes, device, stream, user)
  * returns device memory of at least `bytes` on `device`, usable in the
- * order of `stream` (the context's stream at the time), or NULL (the call
+ * order of `stream` (the context's stream at the time), aligned to at
+ * least 16 bytes (the kernels use 16-byte vector accesses), or NULL (the call
  * then fails with BH_E_NOMEM); free_fn(ptr, bytes, device, stream, user)
  * takes back a block with the arguments of its allocation.  Both or
  * neither (NULL, NULL: hipMalloc again).  Buffers allocated earlier keep

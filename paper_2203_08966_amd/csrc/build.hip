@@ -930,15 +930,29 @@ __global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *__restrict__ sums,
     if (t == 0) tot[blockIdx.x] = carry;
 }
 
-// offs[s] = exclusive prefix of ns over ranks; offs[n] = node count.
+// offs[s] = exclusive prefix of ns over ranks; offs[n] = node count.  Four
+// ranks per thread (one 4-byte load, one 16-byte store), 1024 per block:
+// the block's prefix is the scanned sum of its first 256-rank block of
+// k_chain.
+constexpr int kDownPer = 4;
+constexpr int kDownRanks = kThreads * kDownPer;
 __global__ __launch_bounds__(kThreads) void k_scan_down(const uint8_t *__restrict__ ns, int n,
                                                         const uint32_t *__restrict__ bpre,
                                                         int32_t *__restrict__ offs,
                                                         uint32_t *__restrict__ total) {
+    static_assert(kDownRanks % kThreads == 0, "a block covers whole k_chain blocks");
     __shared__ uint32_t ws[kThreads / 64];
-    const int s = blockIdx.x * kThreads + threadIdx.x;
-    const uint32_t x = s < n ? ns[s] : 0u;
-    uint32_t incl = x;
+    const int s0 = (int)(blockIdx.x * kThreads + threadIdx.x) * kDownPer;
+    uint32_t x[kDownPer];
+    if (s0 + kDownPer <= n) {
+        const uchar4 v = *(const uchar4 *)(ns + s0);
+        x[0] = v.x, x[1] = v.y, x[2] = v.z, x[3] = v.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kDownPer; ++k) x[k] = s0 + k < n ? ns[s0 + k] : 0u;
+    }
+    const uint32_t run = x[0] + x[1] + x[2] + x[3];
+    uint32_t incl = run;
     const unsigned lane = lane_id();
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t v = __shfl_up(incl, o);
@@ -947,12 +961,20 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint8_t *__restric
     const int w = threadIdx.x / 64;
     if (lane == 63) ws[w] = incl;
     __syncthreads();
-    uint32_t pre = bpre[blockIdx.x];
+    uint32_t pre = bpre[blockIdx.x * (kDownRanks / kThreads)] + incl - run;
     for (int k = 0; k < w; ++k) pre += ws[k];
-    if (s < n) offs[s] = (int32_t)(pre + incl - x);
-    if (s == n - 1) {
-        offs[n] = (int32_t)(pre + incl);
-        *total = pre + incl;
+    const int4 o4 = make_int4((int)pre, (int)(pre + x[0]), (int)(pre + x[0] + x[1]),
+                              (int)(pre + x[0] + x[1] + x[2]));
+    if (s0 + kDownPer <= n) {
+        *(int4 *)(offs + s0) = o4;
+    } else if (s0 < n) {
+        offs[s0] = o4.x;
+        if (s0 + 1 < n) offs[s0 + 1] = o4.y;
+        if (s0 + 2 < n) offs[s0 + 2] = o4.z;
+    }
+    if (s0 < n && n <= s0 + kDownPer) {  // the thread holding rank n - 1
+        offs[n] = (int32_t)(pre + run);
+        *total = pre + run;
     }
 }
 
@@ -1847,7 +1869,7 @@ int build_typed(bh_ctx *ctx, bh_tree *t, const T *pos, const T *mass, int n, int
     int32_t *offs = (int32_t *)t->offs.p;
     k_chain<<<nb, kThreads, 0, st>>>(ka, n, B, delta, ns, bsum);
     k_scan_sums<<<kLevels + 2, 1024, 0, st>>>(bsum, nb, seg_tot);
-    k_scan_down<<<nb, kThreads, 0, st>>>(ns, n, bsum, offs, misc + 1);
+    k_scan_down<<<div_up(n, kDownRanks), kThreads, 0, st>>>(ns, n, bsum, offs, misc + 1);
     if ((rc = check_launch("topology"))) return rc;
     uint32_t *hp = (uint32_t *)ctx->pinned;
     if (hipMemcpyAsync(hp, misc, 4 * 48, hipMemcpyDeviceToHost, st) != hipSuccess ||

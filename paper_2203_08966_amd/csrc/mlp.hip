@@ -56,24 +56,43 @@ __global__ __launch_bounds__(256) void k_cell_kc_plain(int m, const Moments *__r
 
 // |a| per sorted rank i from element j of an acceleration array (or of an
 // array of norms), j = perm[i] for arrays in caller order, else j = i.
-template <typename R>
+// PERM: perm is given; NORM: norms are read (else accelerations).
+constexpr int kAnormUnroll = 8;
+template <typename R, bool PERM, bool NORM>
 __global__ __launch_bounds__(256) void k_anorm(int n, const R *__restrict__ acc,
                                                const R *__restrict__ norm,
                                                const uint32_t *__restrict__ perm,
                                                float *__restrict__ out,
                                                double *__restrict__ part) {
-    // grid-stride over the ranks (a fixed grid: the sum's order is fixed)
+    // grid-stride over the ranks (a fixed grid: the sum's order is fixed);
+    // kAnormUnroll strides at a time, every load issued before the first
+    // use, so that a thread's dependent loads (perm, then the element) do
+    // not wait one stride after another; the sum keeps the stride order
     double sum = 0.0;
     const int stride = (int)(gridDim.x * blockDim.x);
-    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n; i += stride) {
-        const int64_t j = perm ? (int64_t)perm[i] : i;
-        float v;
-        if (norm) {
-            v = (float)norm[j];
+    auto norm_at = [&](int64_t i) -> float {
+        int64_t j = i;
+        if constexpr (PERM) j = (int64_t)perm[i];
+        if constexpr (NORM) {
+            return (float)norm[j];
         } else {
             const R x = acc[3 * j], y = acc[3 * j + 1], z = acc[3 * j + 2];
-            v = (float)sqrt(x * x + y * y + z * z);
+            return (float)sqrt(x * x + y * y + z * z);
         }
+    };
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (int64_t)(kAnormUnroll - 1) * stride < n; i += (int64_t)kAnormUnroll * stride) {
+        float v[kAnormUnroll];
+#pragma unroll
+        for (int u = 0; u < kAnormUnroll; ++u) v[u] = norm_at(i + (int64_t)u * stride);
+#pragma unroll
+        for (int u = 0; u < kAnormUnroll; ++u) {
+            out[i + (int64_t)u * stride] = v[u];
+            sum += (double)v[u];
+        }
+    }
+    for (; i < n; i += stride) {
+        const float v = norm_at(i);
         out[i] = v;
         sum += (double)v;
     }
@@ -546,12 +565,24 @@ int mlp_anorm(bh_tree *t, const void *acc, const void *norm, bool caller_order,
     if (rc) return rc;
     const uint32_t *perm = caller_order ? t->perm : nullptr;
     double *part = (double *)((char *)t->anorm.p + npad);
+    auto launch = [&](auto zero) {
+        using R = decltype(zero);
+        const R *a = (const R *)acc, *nm = (const R *)norm;
+        float *out = (float *)t->anorm.p;
+        hipStream_t st = t->ctx->stream;
+        if (perm && norm)
+            k_anorm<R, true, true><<<nblk, 256, 0, st>>>(n, a, nm, perm, out, part);
+        else if (perm)
+            k_anorm<R, true, false><<<nblk, 256, 0, st>>>(n, a, nm, perm, out, part);
+        else if (norm)
+            k_anorm<R, false, true><<<nblk, 256, 0, st>>>(n, a, nm, perm, out, part);
+        else
+            k_anorm<R, false, false><<<nblk, 256, 0, st>>>(n, a, nm, perm, out, part);
+    };
     if (t->dtype == BH_F32)
-        k_anorm<float><<<nblk, 256, 0, t->ctx->stream>>>(
-            n, (const float *)acc, (const float *)norm, perm, (float *)t->anorm.p, part);
+        launch(0.0f);
     else
-        k_anorm<double><<<nblk, 256, 0, t->ctx->stream>>>(
-            n, (const double *)acc, (const double *)norm, perm, (float *)t->anorm.p, part);
+        launch(0.0);
     k_anorm_floor<<<1, 1024, 0, t->ctx->stream>>>(part, nblk, n, floor_frac,
                                                   (float *)(part + kAnormBlocks));
     return check_launch("anorm");

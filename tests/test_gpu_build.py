@@ -58,6 +58,11 @@ CASES = [
     ("plummer", 2, 1, 1, np.float64),
     ("plummer", 63, 2, 8, np.float32),
     ("plummer", 8191, 3, 16, np.float32),
+    # leaf capacities that are not powers of two (the chain test's window
+    # tables then overlap two power-of-two windows)
+    ("plummer", 20000, 13, 5, np.float32),
+    ("clumpy", 30000, 14, 12, np.float32),
+    ("plummer", 10000, 15, 100, np.float64),
 ]
 
 

@@ -17,20 +17,61 @@
 namespace bh {
 namespace {
 
+// The kicks and drifts stream the 3n components as 16-byte vectors (the
+// simulation's buffers are 16-byte aligned), then the last components one
+// by one; each component's arithmetic is the same either way.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+    using type = float4;
+    static constexpr int N = 4;
+};
+template <> struct Vec16<double> {
+    using type = double2;
+    static constexpr int N = 2;
+};
+template <typename T> __device__ __forceinline__ T &comp(typename Vec16<T>::type &v, int k) {
+    return reinterpret_cast<T *>(&v)[k];
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_kick(int64_t n3, T *__restrict__ v,
                                                    const T *__restrict__ a, T h) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n3;
-         i += (int64_t)gridDim.x * blockDim.x)
-        v[i] += a[i] * h;
+    using V = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::N;
+    const int64_t nv = n3 / W, stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t i = t; i < nv; i += stride) {
+        V vv = reinterpret_cast<V *>(v)[i];
+        V av = reinterpret_cast<const V *>(a)[i];
+#pragma unroll
+        for (int k = 0; k < W; ++k) comp<T>(vv, k) += comp<T>(av, k) * h;
+        reinterpret_cast<V *>(v)[i] = vv;
+    }
+    for (int64_t i = nv * W + t; i < n3; i += stride) v[i] += a[i] * h;
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_kick_drift(int64_t n3, T *__restrict__ x,
                                                          T *__restrict__ v,
                                                          const T *__restrict__ a, T h, T dt) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n3;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    using V = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::N;
+    const int64_t nv = n3 / W, stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t i = t; i < nv; i += stride) {
+        V vv = reinterpret_cast<V *>(v)[i];
+        V av = reinterpret_cast<const V *>(a)[i];
+        V xv = reinterpret_cast<V *>(x)[i];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const T vi = comp<T>(vv, k) + comp<T>(av, k) * h;
+            comp<T>(vv, k) = vi;
+            comp<T>(xv, k) += vi * dt;
+        }
+        reinterpret_cast<V *>(v)[i] = vv;
+        reinterpret_cast<V *>(x)[i] = xv;
+    }
+    for (int64_t i = nv * W + t; i < n3; i += stride) {
         const T vi = v[i] + a[i] * h;
         v[i] = vi;
         x[i] += vi * dt;
@@ -341,19 +382,19 @@ int launch_count_sum(hipStream_t s, int64_t n, const uint32_t *a, const uint32_t
 
 int launch_kick(hipStream_t s, int dtype, int64_t n, void *vel, const void *acc, double h) {
     if (dtype == BH_F32)
-        k_kick<float><<<grid_for(3 * n), kThreads, 0, s>>>(3 * n, (float *)vel, (const float *)acc, (float)h);
+        k_kick<float><<<grid_for(3 * n / 4 + 1), kThreads, 0, s>>>(3 * n, (float *)vel, (const float *)acc, (float)h);
     else
-        k_kick<double><<<grid_for(3 * n), kThreads, 0, s>>>(3 * n, (double *)vel, (const double *)acc, h);
+        k_kick<double><<<grid_for(3 * n / 2 + 1), kThreads, 0, s>>>(3 * n, (double *)vel, (const double *)acc, h);
     return check_launch("kick");
 }
 
 int launch_kick_drift(hipStream_t s, int dtype, int64_t n, void *pos, void *vel,
                       const void *acc, double h, double dt) {
     if (dtype == BH_F32)
-        k_kick_drift<float><<<grid_for(3 * n), kThreads, 0, s>>>(
+        k_kick_drift<float><<<grid_for(3 * n / 4 + 1), kThreads, 0, s>>>(
             3 * n, (float *)pos, (float *)vel, (const float *)acc, (float)h, (float)dt);
     else
-        k_kick_drift<double><<<grid_for(3 * n), kThreads, 0, s>>>(
+        k_kick_drift<double><<<grid_for(3 * n / 2 + 1), kThreads, 0, s>>>(
             3 * n, (double *)pos, (double *)vel, (const double *)acc, h, dt);
     return check_launch("kick_drift");
 }

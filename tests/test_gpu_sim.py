@@ -15,13 +15,15 @@ def _bh_force(mass, theta, eps, leaf):
     return lambda x: oracle.barnes_hut(x, mass, theta, eps, leaf).acc
 
 
-def test_leapfrog_fp64_matches_oracle(ctx):
-    """N=4096 Plummer, theta 0.5, eps 0.01, leaf 8, FP64: one force evaluation
-    plus 10 KDK steps of dt 1e-3, against the oracle's KDK with its own tree
-    rebuilt every step."""
-    pos, vel, mass = case_bodies("plummer", 4096, 1, np.float64)
+# 4099: 3n odd, so the kicks' last component is outside their 16-byte vectors
+@pytest.mark.parametrize("n", [4096, 4099])
+def test_leapfrog_fp64_matches_oracle(ctx, n):
+    """N=4096 (or 4099) Plummer, theta 0.5, eps 0.01, leaf 8, FP64: one force
+    evaluation plus 10 KDK steps of dt 1e-3, against the oracle's KDK with
+    its own tree rebuilt every step."""
+    pos, vel, mass = case_bodies("plummer", n, 1, np.float64)
     theta, eps, leaf, dt, steps = 0.5, 0.01, 8, 1e-3, 10
-    say("leapfrog FP64: 4096 bodies, 10 steps")
+    say(f"leapfrog FP64: {n} bodies, 10 steps")
     xo, vo, ao = oracle.kdk(pos, vel, mass, dt, steps, _bh_force(mass, theta, eps, leaf))
     P, V, M = (torch.from_numpy(a).cuda() for a in (pos, vel, mass))
     B.bh_sim_init(ctx, P, V, M, leaf, theta, eps)
@@ -46,10 +48,12 @@ def test_leapfrog_fp64_matches_oracle(ctx):
     assert abs(ep - ep_ref) <= 1e-9 * abs(ep_ref)
 
 
-def test_leapfrog_fp32_short_run(ctx):
-    pos, vel, mass = case_bodies("plummer", 20000, 2, np.float32)
+# 20001: 3n = 60003, three components after the kicks' last 16-byte vector
+@pytest.mark.parametrize("n", [20000, 20001])
+def test_leapfrog_fp32_short_run(ctx, n):
+    pos, vel, mass = case_bodies("plummer", n, 2, np.float32)
     theta, eps, leaf, dt = 0.5, 0.005, 16, 5e-4
-    say("leapfrog FP32: 20000 bodies, 5 steps, vs FP64 oracle KDK")
+    say(f"leapfrog FP32: {n} bodies, 5 steps, vs FP64 oracle KDK")
     p64, v64, m64 = (a.astype(np.float64) for a in (pos, vel, mass))
     xo, vo, _ = oracle.kdk(p64, v64, m64, dt, 5, _bh_force(m64, theta, eps, leaf))
     P, V, M = (torch.from_numpy(a).cuda() for a in (pos, vel, mass))
